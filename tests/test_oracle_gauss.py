@@ -1,0 +1,286 @@
+"""Pins of the CPU reference's Gaussian path against facts fixed by the
+mathematics: eigenvalues of the baked covariance, SH orthonormality, the
+closed-form projection of isotropic and image-plane-rotated Gaussians, a
+finite-difference Jacobian, brute-force blending, single/two-Gaussian closed
+forms, the A + T = 1 invariant, permutation and tile-size invariance."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_17932_amd import synth
+
+
+def _scene(seed=0, **kw):
+    sc = synth.small_scene(seed, **kw)
+    g = sc["gaussians"]
+    cov, op = oracle.bake(g["logscale"], g["quat"], g["logit"])
+    V = synth.views_array(sc["views"])
+    D = synth.views_dims(sc["views"])
+    return sc, g, cov.astype(np.float32), op.astype(np.float32), V, D
+
+
+# ---------------------------------------------------------------- bake
+def test_bake_eigenvalues_and_opacity():
+    rng = np.random.default_rng(3)
+    g = synth.gaussians(rng, 200, 0)
+    cov, op = oracle.bake(g["logscale"], g["quat"], g["logit"])
+    for i in range(200):
+        S = np.array([[cov[0, i], cov[1, i], cov[2, i]],
+                      [cov[1, i], cov[3, i], cov[4, i]],
+                      [cov[2, i], cov[4, i], cov[5, i]]])
+        ev = np.linalg.eigvalsh(S)
+        want = np.sort(np.exp(2.0 * g["logscale"][:, i].astype(np.float64)))
+        np.testing.assert_allclose(ev, want, rtol=1e-9)
+    np.testing.assert_allclose(op, 1 / (1 + np.exp(-g["logit"].astype(np.float64))), rtol=1e-14)
+
+
+def test_bake_rotation_axes():
+    # quaternion of a rotation by 90 deg about z maps the x-scale onto y
+    q = np.array([[math.cos(math.pi / 4)], [0], [0], [math.sin(math.pi / 4)]], np.float32)
+    ls = np.array([[math.log(2.0)], [math.log(0.5)], [0.0]], np.float32)
+    cov, _ = oracle.bake(ls, q, np.zeros(1, np.float32))
+    np.testing.assert_allclose(cov[:, 0], [0.25, 0, 0, 4.0, 0, 1.0], atol=1e-6)
+
+
+# ------------------------------------------------------------------- SH
+def test_sh_orthonormal():
+    # Gauss-Legendre in cos(theta) x uniform phi integrates products of
+    # degree <= 6 polynomials on the sphere exactly.
+    xs, ws = np.polynomial.legendre.leggauss(16)
+    phis = np.arange(32) * 2 * np.pi / 32
+    ct, ph = np.meshgrid(xs, phis, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    w = (ws[:, None] * np.full(32, 2 * np.pi / 32)[None, :]).ravel()
+    Y = oracle.sh_basis(3, dirs)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_degree1_is_linear_in_direction():
+    d = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0]])
+    Y = oracle.sh_basis(1, d)
+    c1 = math.sqrt(3 / (4 * math.pi))
+    np.testing.assert_allclose(np.abs(Y[:, 1:]), c1 * np.abs(d[:, [1, 2, 0]]), atol=1e-15)
+
+
+# ----------------------------------------------------------- projection
+def _one(mean, cov6, opac=0.5, rgb=(0.25, 0.5, 0.75)):
+    mean = np.asarray(mean, np.float32).reshape(3, 1)
+    cov = np.asarray(cov6, np.float32).reshape(6, 1)
+    sh = ((np.asarray(rgb, np.float32) - 0.5) * 2 * math.sqrt(math.pi)).reshape(1, 3, 1)
+    return mean, cov, np.array([opac], np.float32), sh.astype(np.float32)
+
+
+def test_isotropic_on_axis_closed_form():
+    f, z, s = 128.0, 3.0, 0.05
+    V = synth.views_array([synth.pinhole(128, 128, f)])
+    D = synth.views_dims([synth.pinhole(128, 128, f)])
+    mean, cov, op, sh = _one([0, 0, z], [s * s, 0, 0, s * s, 0, s * s])
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)[0, 0]
+    var = (f * s / z) ** 2 + 0.3
+    np.testing.assert_allclose(rec[:5], [64, 64, 1 / var, 0, 1 / var], rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(rec[6:9], [0.25, 0.5, 0.75], rtol=1e-6)
+    assert rec[9] == pytest.approx(z)
+
+
+def test_image_plane_rotated_anisotropic_closed_form():
+    # Gaussian on the optical axis with principal axes rotated by theta about
+    # z: the projected covariance is the rotated diagonal scaled by (f/z)^2.
+    f, z, th = 200.0, 4.0, 0.4
+    sa, sb, sc = 0.08, 0.02, 0.05
+    R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    S = R @ np.diag([sa ** 2, sb ** 2, sc ** 2]) @ R.T
+    cam = synth.pinhole(256, 256, f)
+    V, D = synth.views_array([cam]), synth.views_dims([cam])
+    mean, cov, op, sh = _one([0, 0, z], [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]])
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)[0, 0]
+    c2 = (f / z) ** 2 * S[:2, :2] + 0.3 * np.eye(2)
+    inv = np.linalg.inv(c2)
+    np.testing.assert_allclose(rec[2:5], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=1e-5)
+
+
+def test_projection_matches_finite_difference_jacobian():
+    # off-axis Gaussian seen by a rotated, translated camera: the 2D
+    # covariance is J R Sigma R^T J^T + 0.3 I with J the derivative of the
+    # pixel-projection map, here taken by central differences.
+    cam = synth.pinhole(320, 240, 300.0, eye=(0.1, -0.2, -0.5), rot=synth.yaw_pitch(7, -5))
+    V, D = synth.views_array([cam]), synth.views_dims([cam])
+    rng = np.random.default_rng(1)
+    A = rng.normal(size=(3, 3)) * 0.05
+    S = A @ A.T + 1e-4 * np.eye(3)
+    m = np.array([0.3, 0.1, 3.0])
+    mean, cov, op, sh = _one(m, [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]])
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)[0, 0]
+    Rw = np.asarray(cam.rot, np.float64)
+    tw = np.asarray(cam.trans, np.float64)
+    m = mean[:, 0].astype(np.float64)
+
+    def proj(x):
+        c = Rw @ x + tw
+        return np.array([cam.fx * c[0] / c[2] + cam.cx, cam.fy * c[1] / c[2] + cam.cy])
+
+    h = 1e-6
+    J = np.stack([(proj(m + h * e) - proj(m - h * e)) / (2 * h) for e in np.eye(3)], 1)
+    c2 = J @ cov[:, 0].astype(np.float64)[[0, 1, 2, 1, 3, 4, 2, 4, 5]].reshape(3, 3) @ J.T
+    c2 += 0.3 * np.eye(2)
+    inv = np.linalg.inv(c2)
+    np.testing.assert_allclose(rec[:2], proj(m), rtol=1e-12)
+    np.testing.assert_allclose(rec[2:5], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=1e-6)
+    assert rec[9] == pytest.approx((Rw @ m + tw)[2], rel=1e-12)
+
+
+def test_rect_holds_three_sigma_ellipse_and_depth_key():
+    sc, g, cov, op, V, D = _scene(5, n_gauss=300)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
+    W, H = D[0]
+    xs, ys = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    for i in range(300):
+        r = rect[0, i]
+        if r[0] < 0:
+            continue
+        px, py, A, B, C = rec[0, i, :5]
+        dx, dy = px - xs, py - ys
+        q = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+        inside = q > -4.5 + 1e-6
+        yy, xx = np.nonzero(inside)
+        assert xx.min() >= r[0] and xx.max() <= r[2] and yy.min() >= r[1] and yy.max() <= r[3]
+        # depth key is the single-precision depth
+        tz = np.float32(rec[0, i, 9])
+        assert abs(np.uint32(zb[0, i]).view(np.float32) - tz) <= 2e-7 * tz
+
+
+# --------------------------------------------------------------- blend
+def _brute_pixels(rect, zb, rec, D, opts=(0.99, 1 / 255, 1e-4)):
+    """Independent formulation: per pixel gather every Gaussian (no tiles),
+    order with lexsort, apply the skip rule, then take the transmittances
+    as a cumulative product and cut at the first one below t_min."""
+    aclamp, amin, tmin = opts
+    W, H = D[0]
+    n = zb.shape[1]
+    rgb = np.zeros((3, H, W))
+    T = np.ones((H, W))
+    for y in range(H):
+        for x in range(W):
+            r = rect[0]
+            m = (r[:, 0] >= 0) & (r[:, 0] <= x) & (x <= r[:, 2]) & (r[:, 1] <= y) & (y <= r[:, 3])
+            idx = np.nonzero(m)[0]
+            idx = idx[np.lexsort((idx, zb[0, idx]))]
+            g = rec[0, idx]
+            dx, dy = g[:, 0] - (x + 0.5), g[:, 1] - (y + 0.5)
+            q = -0.5 * (g[:, 2] * dx * dx + g[:, 4] * dy * dy) - g[:, 3] * dx * dy
+            a = np.minimum(aclamp, g[:, 5] * np.exp(q))
+            keep = (q <= 0) & (a >= amin)
+            a, g = a[keep], g[keep]
+            Tn = np.cumprod(1 - a)
+            stop = np.nonzero(Tn < tmin)[0]
+            k = stop[0] if len(stop) else len(a)
+            Tb = np.concatenate([[1.0], Tn[:-1]])[:k]
+            rgb[:, y, x] = (g[:k, 6:9] * (a[:k] * Tb)[:, None]).sum(0)
+            T[y, x] = Tn[k - 1] if k > 0 else 1.0
+    return rgb, T
+
+
+def test_blend_equals_brute_force():
+    sc, g, cov, op, V, D = _scene(7, n_gauss=150, width=40, height=24, f=40.0)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
+    out = oracle.render(rect, zb, rec, D, tile=16)
+    rgb, T = _brute_pixels(rect, zb, rec, D)
+    np.testing.assert_allclose(out["rgb"][0], rgb, atol=1e-12)
+    np.testing.assert_allclose(out["tfinal"][0], T, atol=1e-12)
+    assert out["ncontrib"].max() > 3
+
+
+def test_single_gaussian_closed_form():
+    f, z, s, a0 = 64.0, 2.5, 0.04, 0.8
+    cam = synth.pinhole(64, 64, f)
+    V, D = synth.views_array([cam]), synth.views_dims([cam])
+    mean, cov, op, sh = _one([0, 0, z], [s * s, 0, 0, s * s, 0, s * s], opac=a0)
+    rect, zb = oracle.gauss_geom32(mean, cov, V, D)
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)
+    out = oracle.render(rect, zb, rec, D)
+    var = (f * s / z) ** 2 + 0.3
+    xs, ys = np.meshgrid(np.arange(64) + 0.5, np.arange(64) + 0.5)
+    a = np.minimum(0.99, a0 * np.exp(-((xs - 32) ** 2 + (ys - 32) ** 2) / (2 * var)))
+    r = rect[0, 0]
+    inrect = (xs - 0.5 >= r[0]) & (xs - 0.5 <= r[2]) & (ys - 0.5 >= r[1]) & (ys - 0.5 <= r[3])
+    a = np.where(inrect & (a >= 1 / 255), a, 0)
+    np.testing.assert_allclose(out["rgb"][0], np.array([0.25, 0.5, 0.75])[:, None, None] * a, atol=1e-7)
+    np.testing.assert_allclose(out["depth"][0], z * a, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(out["tfinal"][0], 1 - a, atol=1e-7)
+    # 3 sigma extent: radius = ceil(3 sqrt(var))
+    rad = math.ceil(3 * math.sqrt(var))
+    assert r[0] == math.ceil(32 - rad - 0.5) and r[2] == math.floor(32 + rad - 0.5)
+
+
+def test_two_gaussians_front_to_back():
+    cam = synth.pinhole(32, 32, 32.0)
+    V, D = synth.views_array([cam]), synth.views_dims([cam])
+    s = 0.02
+    mean = np.array([[0, 0], [0, 0], [3.0, 2.0]], np.float32)   # second is nearer
+    cov = np.array([[s * s] * 2, [0, 0], [0, 0], [s * s] * 2, [0, 0], [s * s] * 2], np.float32)
+    op = np.array([0.6, 0.7], np.float32)
+    rgb = np.array([[1.0, 0, 0], [0, 1.0, 0]], np.float32)
+    sh = ((rgb.T - 0.5) * 2 * math.sqrt(math.pi))[None].astype(np.float32)
+    rect, zb = oracle.gauss_geom32(mean, cov, V, D)
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)
+    px = oracle.render(rect, zb, rec, D, pix=np.array([[0, 16, 16]]))
+    # pixel centre (16.5, 16.5) is half a pixel from both means in x and y
+    var = [(32.0 * s / z) ** 2 + 0.3 for z in (3.0, 2.0)]
+    a0 = 0.6 * math.exp(-0.5 * 0.5 / var[0])
+    a1 = 0.7 * math.exp(-0.5 * 0.5 / var[1])
+    np.testing.assert_allclose(px["rgb"][0], [a0 * (1 - a1), a1, 0], rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(px["depth"][0], 2.0 * a1 + 3.0 * a0 * (1 - a1), rtol=1e-6)
+
+
+def test_white_scene_alpha_plus_transmittance_is_one():
+    sc, g, cov, op, V, D = _scene(11, n_gauss=400)
+    sh = np.zeros_like(g["sh"])
+    sh[0] = 0.5 * 2 * math.sqrt(math.pi)     # colour 1 in every channel
+    mean = g["mean"].copy()
+    rect, zb = oracle.gauss_geom32(mean, cov, V, D)
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)
+    rec[..., 9] = 4.0   # constant depth value: D = z0 (1 - T)
+    out = oracle.render(rect, zb, rec, D)
+    for ch in range(3):
+        np.testing.assert_allclose(out["rgb"][0, ch], 1 - out["tfinal"][0], atol=1e-12)
+    np.testing.assert_allclose(out["depth"][0], 4.0 * (1 - out["tfinal"][0]), atol=1e-11)
+    assert (out["tfinal"] >= 1e-4 * 0.01).all() and (out["tfinal"] <= 1).all()
+
+
+def test_permutation_and_tile_size_invariance():
+    sc, g, cov, op, V, D = _scene(13, n_gauss=500, width=100, height=76)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
+    base = oracle.render(rect, zb, rec, D, tile=16)
+    for t in (8, 32):
+        o = oracle.render(rect, zb, rec, D, tile=t)
+        assert np.array_equal(o["rgb"], base["rgb"]) and np.array_equal(o["ncontrib"], base["ncontrib"])
+    perm = np.random.default_rng(0).permutation(500)
+    rect2, zb2 = oracle.gauss_geom32(g["mean"][:, perm], cov[:, perm], V, D)
+    rec2 = oracle.gauss_project64(g["mean"][:, perm], cov[:, perm], op[perm], g["sh"][..., perm], 0, V, D)
+    o = oracle.render(rect2, zb2, rec2, D, tile=16)
+    live = zb[0][zb[0] != 0xFFFFFFFF]
+    assert len(np.unique(live)) == len(live)   # no depth ties: order fully fixed by depth
+    assert np.array_equal(o["rgb"], base["rgb"])
+
+
+def test_tile_lists_sorted_and_cover_contributors():
+    sc, g, cov, op, V, D = _scene(17, n_gauss=300, width=72, height=56, n_views=2)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    tiles_x, tiles_y = (72 + 15) // 16, (56 + 15) // 16
+    sel = np.array([[v, t] for v in range(2) for t in range(tiles_x * tiles_y)], np.int32)
+    off, ids = oracle.tile_lists(rect, zb, D, 16, sel)
+    for s, (v, t) in enumerate(sel):
+        lst = ids[off[s]:off[s + 1]]
+        keys = [(int(zb[v, i]), int(i)) for i in lst]
+        assert keys == sorted(keys)
+        tx, ty = t % tiles_x, t // tiles_x
+        for i in range(300):
+            r = rect[v, i]
+            hit = r[0] >= 0 and r[0] // 16 <= tx <= r[2] // 16 and r[1] // 16 <= ty <= r[3] // 16
+            assert hit == (i in set(lst.tolist()))
