@@ -1,0 +1,301 @@
+/*
+ * vrsplat -- C-ABI of an MI355X (gfx950) foveated hybrid radiance-field
+ * renderer after VR-Splatting (Franke, Fink & Stamminger, PACMCGIT 8(1),
+ * 2025): a peripheral 3D Gaussian splatting pass over the full image
+ * (Sec. 3.2, Eq. 1), a foveal neural-point splat into an image pyramid with
+ * depth-occlusion culling (Sec. 3.3, Sec. 4 "Inference"), a small gated
+ * convolutional decoder with the periphery crop injected (Sec. 3.3), and the
+ * edge-aware combination (Sec. 3.4, Eqs. 2-5), each with a backward entry
+ * for end-to-end fitting (Sec. 3.5).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer owned by the caller; the
+ *    library never allocates or frees device memory.  Scratch memory is a
+ *    caller-provided workspace whose size a *_workspace_size query returns.
+ *  - Small descriptors (vrs_view, vrs_crop, option structs) are HOST
+ *    pointers, read during the call; they are copied into kernel arguments.
+ *  - All work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *    the default stream).  Nothing synchronises the host, so a sequence of
+ *    calls can be captured into a HIP graph.
+ *  - Argument errors are detected on the host and returned as VRS_EINVAL
+ *    before anything is launched.  Launch failures return VRS_EHIP.
+ *  - Data-dependent overflow (more tile pairs or point fragments than the
+ *    workspace was sized for) is detected on the device: the kernels write
+ *    VRS_ECAPACITY into *dev_status (an int32 in device memory that the
+ *    caller zeroes) and the outputs of that call are undefined.
+ *  - Backward entries ACCUMULATE (+=) into gradient arrays; the caller zeroes
+ *    them.  A backward call needs the workspace of its forward call intact.
+ *  - Layouts: primitives are structure-of-arrays planes ([attr][n]); full
+ *    frames are planar [view][channel][H][W]; pyramids are NHWC float32
+ *    packed [crop][layer][y][x][C]; foveal images are planar
+ *    [crop][3][S][S] packed back to back.  Pixel (i, j) has its centre at
+ *    (i + 0.5, j + 0.5).  All views of one call share width and height.
+ *  - Numerics: rasterisation runs in float32.  The integer decisions
+ *    (culling, pixel and tile rectangles, depth keys, pyramid layer and
+ *    target pixels) follow the single-precision operation order documented
+ *    at each entry, with IEEE-rounded + - * / sqrt and no contraction.
+ */
+#ifndef VRSPLAT_H
+#define VRSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VRS_OK = 0,
+  VRS_EINVAL = 1,        /* bad argument (host-side check, nothing launched) */
+  VRS_ECAPACITY = 2,     /* workspace capacity exceeded (device-side, in dev_status) */
+  VRS_EHIP = 3,          /* HIP runtime error */
+  VRS_EUNSUPPORTED = 4,  /* valid but unsupported configuration */
+  VRS_ETIMEOUT = 5       /* a device-side bounded wait expired (dev_status) */
+} vrs_status;
+
+enum { VRS_MAX_VIEWS = 8, VRS_MAX_CROPS = 32, VRS_MAX_LEVELS = 8 };
+enum { VRS_F32 = 0, VRS_BF16 = 1 };                   /* decoder arithmetic */
+enum { VRS_BLEND_LINEAR = 0, VRS_BLEND_PAPER = 1 };   /* combination mask   */
+
+/* Pinhole view.  rot is the world-to-camera rotation (row-major), trans the
+ * world-to-camera translation: x_cam = rot * x_world + trans.  The camera
+ * looks along +z; pixel = (fx x/z + cx, fy y/z + cy).  Geometry closer than
+ * znear is culled. */
+typedef struct {
+  float fx, fy, cx, cy;
+  float rot[9];
+  float trans[3];
+  float znear;
+  int32_t width, height;
+} vrs_view;
+
+/* Foveal crop: the sub-frustum of view `view` (Sec. 3.3, Fig. 5) covering
+ * pixels [x0, x0+size) x [y0, y0+size) of that view, i.e. the same focal
+ * lengths with the principal point shifted by (-x0, -y0).  (gaze_x, gaze_y)
+ * is the fixation point e in view pixels, the centre of the blend (Eq. 2).
+ * size must be a multiple of 2^(levels-1). */
+typedef struct {
+  int32_t view, x0, y0, size;
+  float gaze_x, gaze_y;
+} vrs_crop;
+
+/* Rasteriser options.  Defaults: tile 16, alpha_clamp 0.99,
+ * alpha_min 1/255, t_min 1e-4, lowpass 0.3, extent 3, bg 0. */
+typedef struct {
+  int32_t tile;          /* screen tile edge: 8, 16 or 32 */
+  float alpha_clamp;     /* alpha = min(alpha_clamp, opacity e^q) */
+  float alpha_min;       /* contributions with alpha < alpha_min are skipped */
+  float t_min;           /* a pixel stops before T would fall below t_min */
+  float lowpass;         /* dilation added to the 2D covariance diagonal (px^2) */
+  float extent;          /* splat half-extent in standard deviations */
+  float bg[3];           /* background colour added as T_final * bg */
+} vrs_raster_opts;
+
+/* Decoder description: n_levels gated 3x3 conv levels, level 0 finest;
+ * width[l] output channels of level l; in_ch pyramid channels (4).
+ * dtype: VRS_F32 (float32 arithmetic) or VRS_BF16 (bfloat16 MFMA operands,
+ * float32 accumulation).  The packed float32 weight buffer holds, for
+ * l = 0..n_levels-1, W_l [2*width[l]][3][3][Cin_l] then b_l [2*width[l]],
+ * then the RGB head W_o [3][width[0]] and b_o [3], with
+ * Cin_l = in_ch + (l+1 < n_levels ? width[l+1] : 0) + (l == 0 ? 3 : 0).
+ * Output channels 0..width-1 are the feature half f, width..2width-1 the
+ * gate half g. */
+typedef struct {
+  int32_t n_levels;
+  int32_t width[VRS_MAX_LEVELS];
+  int32_t in_ch;
+  int32_t dtype;
+} vrs_decoder_desc;
+
+const char* vrs_status_string(vrs_status s);
+/* Library version string. */
+const char* vrs_version(void);
+
+/* ---------------------------------------------------------------- bake
+ * Attribute baking (Sec. 4 "Inference": opacities and covariances are baked
+ * into the primitives before rendering).  logscale [3][n], quat [4][n]
+ * (w, x, y, z; normalised inside), logit [n] -> cov [6][n] =
+ * (xx, xy, xz, yy, yz, zz) of R(q) diag(exp(2 logscale)) R(q)^T and
+ * opacity [n] = sigmoid(logit). */
+vrs_status vrs_bake_gaussians(const float* logscale, const float* quat, const float* logit,
+                              int64_t n, float* cov, float* opacity, void* stream);
+/* Adjoint of vrs_bake_gaussians: accumulates d_logscale [3][n], d_quat [4][n]
+ * (with respect to the unnormalised input quaternion), d_logit [n] from
+ * d_cov [6][n] and d_opacity [n] (d_opacity may be NULL). */
+vrs_status vrs_bake_gaussians_backward(const float* logscale, const float* quat,
+                                       const float* logit, int64_t n, const float* d_cov,
+                                       const float* d_opacity, float* d_logscale, float* d_quat,
+                                       float* d_logit, void* stream);
+
+/* ------------------------------------------------------------ periphery
+ * Peripheral 3D Gaussian splatting of n_views full images (Sec. 3.2).
+ * Inputs: mean [3][n], cov [6][n] (baked), opacity [n], sh [K][3][n] with
+ * K = (sh_degree+1)^2, sh_degree in 0..3.
+ * Per view and Gaussian, in float32 (EWA projection):
+ *   t = rot*mean + trans, evaluated ((r0 x + r1 y) + r2 z) + t; cull unless
+ *   t.z > znear; Jacobian J of the pixel projection with x/z, y/z clamped
+ *   to +-1.3 (W/2)/fx, +-1.3 (H/2)/fy; Sigma2D = (J R) Sigma (J R)^T +
+ *   lowpass*I; cull unless det > 0; conic = Sigma2D^-1;
+ *   r = ceil(extent * sqrt(lambda_max)); pixel rectangle
+ *   [ceil(px - r - 0.5), floor(px + r - 0.5)] clipped to the image (cull if
+ *   empty); colour = max(0, 0.5 + sum_k Y_k(dir) sh_k) with dir the unit
+ *   vector from the camera centre to the mean (real SH, degree <= 3).
+ * Binning: every Gaussian is listed in each tile its rectangle touches;
+ * each tile list is ordered by (float32 bits of t.z, Gaussian index).
+ * Blending per pixel (front to back, Eq. 1 for depth): a Gaussian
+ * contributes only if the pixel lies in its rectangle;
+ *   alpha = min(alpha_clamp, opacity exp(-0.5 d^T conic d)), skipped below
+ *   alpha_min; the pixel stops before T(1 - alpha) < t_min;
+ *   C += rgb alpha T, D += t.z alpha T, T *= 1 - alpha.
+ * Outputs: rgb [V][3][H][W] = C + T bg, depth [V][H][W] = D (Eq. 1),
+ * t_final [V][H][W] = T, n_contrib [V][H][W] = number of Gaussians blended.
+ * Workspace: vrs_render_workspace_size(); max_pairs bounds the number of
+ * (Gaussian, tile) pairs.  The workspace keeps the projected records, the
+ * sorted tile lists and per-pixel stop positions for the backward call. */
+size_t vrs_render_workspace_size(int64_t n, int n_views, const vrs_view* views,
+                                 const vrs_raster_opts* opts, int64_t max_pairs);
+vrs_status vrs_render_gaussians(const float* mean, const float* cov, const float* opacity,
+                                const float* sh, int sh_degree, int64_t n,
+                                const vrs_view* views, int n_views, const vrs_raster_opts* opts,
+                                float* rgb, float* depth, float* t_final, int32_t* n_contrib,
+                                void* ws, size_t ws_bytes, int64_t max_pairs,
+                                int32_t* dev_status, void* stream);
+/* Offsets (bytes into the workspace) of the render's intermediate results:
+ * pair_count (uint32, device), tile lists as sorted Gaussian indices
+ * (uint32 [max_pairs]), tile ranges (uint32 pairs [tiles][2] = begin, end
+ * for tile index v*tiles_per_view + ty*tiles_x + tx).  For inspection and
+ * tests. */
+typedef struct {
+  size_t pair_count, sorted_ids, tile_ranges;
+  int64_t tiles_x, tiles_y, tiles_total;
+} vrs_render_layout;
+vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const vrs_view* views,
+                                       const vrs_raster_opts* opts, int64_t max_pairs,
+                                       vrs_render_layout* out);
+/* Adjoint of vrs_render_gaussians, replaying each pixel back to front from
+ * its stored final transmittance.  d_rgb [V][3][H][W]; d_depth [V][H][W] or
+ * NULL.  Accumulates d_mean [3][n], d_cov [6][n], d_opacity [n],
+ * d_sh [K][3][n].  Forward inputs and outputs and the workspace must be
+ * those of the matching forward call. */
+vrs_status vrs_render_gaussians_backward(const float* mean, const float* cov,
+                                         const float* opacity, const float* sh, int sh_degree,
+                                         int64_t n, const vrs_view* views, int n_views,
+                                         const vrs_raster_opts* opts, const float* t_final,
+                                         const float* d_rgb, const float* d_depth, float* d_mean,
+                                         float* d_cov, float* d_opacity, float* d_sh, void* ws,
+                                         size_t ws_bytes, int64_t max_pairs, void* stream);
+
+/* ---------------------------------------------------------------- fovea
+ * Neural-point splat into a multi-resolution pyramid for every crop
+ * (Sec. 3.3 sub-frustum and depth culling; Sec. 4 "Inference": one count,
+ * one scan and one fill over all layers and crops).  Inputs: pos [3][np],
+ * radius [np] (world units), feat [np][channels] IEEE half bits, opacity
+ * [np] or NULL (all ones).  Per point and view, in float32:
+ *   t = rot*pos + trans; cull unless t.z > znear;
+ *   p = (fx (t.x/t.z) + cx, fy (t.y/t.z) + cy);
+ *   depth cull when depth/t_final are given ([V][H][W], the periphery's
+ *   Eq. 1 depth and final transmittance): at pixel floor(p) inside the view,
+ *   A = 1 - T_final; cull if A >= cov_min and t.z > slack * (D / A);
+ *   s = ((2 fx) radius)/t.z; s <= 1: layer 0 only; else s = m 2^e (frexp),
+ *   l0 = e - 1 (clamped to levels-1, single layer), second layer l0+1
+ *   unless m == 0.5; layer weights 1 - f and f with f = log2(s) - l0;
+ *   per crop and layer l: xl = ((p.x - x0) * 2^-l) - 0.5 (y likewise),
+ *   bilinear weights to the four pixels around (xl, yl) inside the layer.
+ * Per layer pixel the fragments are blended front to back in (float32 bits
+ * of t.z, point index) order: alpha = w * opacity, F += feat alpha T,
+ * T *= 1 - alpha.  Output pyramid: packed [crop][layer][y][x][channels]
+ * float32.  channels must be 4; levels 1..8. */
+size_t vrs_splat_workspace_size(int64_t np, int n_views, const vrs_view* views,
+                                const vrs_crop* crops, int n_crops, int levels,
+                                int64_t max_frags);
+vrs_status vrs_splat_points(const float* pos, const float* radius, const uint16_t* feat,
+                            const float* opacity, int64_t np, int channels, int levels,
+                            const vrs_view* views, int n_views, const vrs_crop* crops,
+                            int n_crops, const float* depth, const float* t_final,
+                            float cov_min, float slack, float* pyramid, void* ws,
+                            size_t ws_bytes, int64_t max_frags, int32_t* dev_status,
+                            void* stream);
+/* Offsets of the splat's intermediate results: frag_count (uint32),
+ * sorted layer-pixel keys (uint32 [max_frags]) and sorted point indices
+ * (uint32 [max_frags]); layer pixel index = position in the packed pyramid. */
+typedef struct {
+  size_t frag_count, sorted_keys, sorted_ids;
+  int64_t pyramid_pixels;
+} vrs_splat_layout;
+vrs_status vrs_splat_workspace_layout(int64_t np, int n_views, const vrs_view* views,
+                                      const vrs_crop* crops, int n_crops, int levels,
+                                      int64_t max_frags, vrs_splat_layout* out);
+/* Adjoint of vrs_splat_points given d_pyramid (same layout as pyramid).
+ * Accumulates d_feat [np][channels] (float32), d_pos [3][np], d_radius [np]
+ * and d_opacity [np] (each may be NULL).  Culling is a non-differentiable
+ * mask. */
+vrs_status vrs_splat_points_backward(const float* pos, const float* radius,
+                                     const uint16_t* feat, const float* opacity, int64_t np,
+                                     int channels, int levels, const vrs_view* views,
+                                     int n_views, const vrs_crop* crops, int n_crops,
+                                     const float* d_pyramid, float* d_feat, float* d_pos,
+                                     float* d_radius, float* d_opacity, void* ws,
+                                     size_t ws_bytes, int64_t max_frags, void* stream);
+
+/* -------------------------------------------------------------- decoder
+ * Small gated CNN turning each crop's pyramid into its foveal image F
+ * (Sec. 3.3): h_top = G(X_top); h_l = G_l([X_l, up2(h_{l+1}), Pcrop if l=0]);
+ * F = W_o h_0 + b_o, with G(x) = ELU(W_f*x + b_f) * sigmoid(W_g*x + b_g),
+ * 3x3 kernels with zero padding, up2 = bilinear x2 (half-pixel centres,
+ * edge clamp), Pcrop = the periphery rgb under the crop.  pyramid as written
+ * by vrs_splat_points with `levels` layers (levels >= n_levels);
+ * rgb_periphery [V][3][H][W]; weights packed float32 as described at
+ * vrs_decoder_desc.  Output fovea_rgb packed [crop][3][S][S] float32.
+ * The workspace holds the activations the backward call needs. */
+size_t vrs_decoder_workspace_size(const vrs_decoder_desc* dd, const vrs_crop* crops,
+                                  int n_crops);
+vrs_status vrs_decode_fovea(const float* pyramid, int levels, const float* rgb_periphery,
+                            const vrs_view* views, int n_views, const vrs_crop* crops,
+                            int n_crops, const float* weights, const vrs_decoder_desc* dd,
+                            float* fovea_rgb, void* ws, size_t ws_bytes, void* stream);
+/* Adjoint of vrs_decode_fovea: from d_fovea accumulates d_pyramid (may be
+ * NULL), d_rgb_periphery (may be NULL) and d_weights (packed like weights,
+ * may be NULL). */
+vrs_status vrs_decode_fovea_backward(const float* pyramid, int levels,
+                                     const float* rgb_periphery, const vrs_view* views,
+                                     int n_views, const vrs_crop* crops, int n_crops,
+                                     const float* weights, const vrs_decoder_desc* dd,
+                                     const float* d_fovea, float* d_pyramid,
+                                     float* d_rgb_periphery, float* d_weights, void* ws,
+                                     size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ combine
+ * Combination of periphery P [V][3][H][W] and foveal crops F (Sec. 3.4).
+ * For each crop in index order and each of its pixels, with r the distance
+ * of the pixel centre to the crop's gaze point and d_f = size/2:
+ *   VRS_BLEND_LINEAR: c = clamp((d_f - r)/ring, 0, 1);
+ *   VRS_BLEND_PAPER:  r_n = clamp(r/d_f, 0, 1) (Eq. 2),
+ *     f_p = (r_n - m)/(1 - m) (Eq. 3), f_e = |Sobel(mean_rgb(F))|/4 with
+ *     replicated crop borders (Eq. 4), c = 1 - S2(clamp(f_p + gamma f_e, 0,
+ *     1)), S2(x) = 6x^5 - 15x^4 + 10x^3 (Eq. 5);
+ *   out = (1 - c) out + c F.  Elsewhere out = P. */
+vrs_status vrs_composite_frame(const float* rgb_periphery, int n_views, int width, int height,
+                               const float* fovea_rgb, const vrs_crop* crops, int n_crops,
+                               int mode, float ring, float m, float gamma, float* out,
+                               void* stream);
+/* Adjoint: from d_out accumulates d_rgb_periphery and d_fovea (either may be
+ * NULL).  In VRS_BLEND_PAPER mode the edge term's dependence on F is
+ * differentiated too. */
+vrs_status vrs_composite_frame_backward(const float* rgb_periphery, int n_views, int width,
+                                        int height, const float* fovea_rgb,
+                                        const vrs_crop* crops, int n_crops, int mode,
+                                        float ring, float m, float gamma, const float* d_out,
+                                        float* d_rgb_periphery, float* d_fovea, void* stream);
+
+/* --------------------------------------------------------------- loss
+ * L1 photometric term of the fitting loss (Sec. 3.5, Eq. 6):
+ * loss[0] = sum |pred - target| / n (written, float32 device scalar);
+ * d_pred (may be NULL) accumulates scale * sign(pred - target) / n. */
+vrs_status vrs_l1_loss(const float* pred, const float* target, int64_t n, float* loss,
+                       float* d_pred, float scale, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VRSPLAT_H */

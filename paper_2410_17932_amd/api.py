@@ -1,0 +1,407 @@
+"""Thin ctypes binding of libvrsplat.so (include/vrsplat.h).
+
+Argument marshalling only: every step of the renderer runs in the HIP
+library.  torch provides device memory and the current stream.  If the
+library is missing, every call raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvrsplat.so")
+_lib = None
+
+VRS_OK, VRS_EINVAL, VRS_ECAPACITY, VRS_EHIP, VRS_EUNSUPPORTED, VRS_ETIMEOUT = range(6)
+VRS_F32, VRS_BF16 = 0, 1
+BLEND_LINEAR, BLEND_PAPER = 0, 1
+MAX_VIEWS, MAX_CROPS, MAX_LEVELS = 8, 32, 8
+
+
+class VrsError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+        self.code = code
+
+
+class View(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("rot", ctypes.c_float * 9),
+                ("trans", ctypes.c_float * 3), ("znear", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Crop(ctypes.Structure):
+    _fields_ = [("view", ctypes.c_int32), ("x0", ctypes.c_int32), ("y0", ctypes.c_int32),
+                ("size", ctypes.c_int32), ("gaze_x", ctypes.c_float), ("gaze_y", ctypes.c_float)]
+
+
+class RasterOpts(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("alpha_clamp", ctypes.c_float),
+                ("alpha_min", ctypes.c_float), ("t_min", ctypes.c_float),
+                ("lowpass", ctypes.c_float), ("extent", ctypes.c_float),
+                ("bg", ctypes.c_float * 3)]
+
+
+class DecoderDesc(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("width", ctypes.c_int32 * MAX_LEVELS),
+                ("in_ch", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+class RenderLayout(ctypes.Structure):
+    _fields_ = [("pair_count", ctypes.c_size_t), ("sorted_ids", ctypes.c_size_t),
+                ("tile_ranges", ctypes.c_size_t), ("tiles_x", ctypes.c_int64),
+                ("tiles_y", ctypes.c_int64), ("tiles_total", ctypes.c_int64)]
+
+
+class SplatLayout(ctypes.Structure):
+    _fields_ = [("frag_count", ctypes.c_size_t), ("sorted_keys", ctypes.c_size_t),
+                ("sorted_ids", ctypes.c_size_t), ("pyramid_pixels", ctypes.c_int64)]
+
+
+_vp, _i64, _int, _flt, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+_P = ctypes.POINTER
+
+# (name, restype, argtypes) of every exported entry point
+SIGNATURES = {
+    "vrs_status_string": (ctypes.c_char_p, [_int]),
+    "vrs_version": (ctypes.c_char_p, []),
+    "vrs_bake_gaussians": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "vrs_bake_gaussians_backward": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vrs_render_workspace_size": (_sz, [_i64, _int, _P(View), _P(RasterOpts), _i64]),
+    "vrs_render_workspace_layout": (_int, [_i64, _int, _P(View), _P(RasterOpts), _i64,
+                                           _P(RenderLayout)]),
+    "vrs_render_gaussians": (_int, [_vp, _vp, _vp, _vp, _int, _i64, _P(View), _int,
+                                    _P(RasterOpts), _vp, _vp, _vp, _vp, _vp, _sz, _i64, _vp,
+                                    _vp]),
+    "vrs_render_gaussians_backward": (_int, [_vp, _vp, _vp, _vp, _int, _i64, _P(View), _int,
+                                             _P(RasterOpts), _vp, _vp, _vp, _vp, _vp, _vp,
+                                             _vp, _vp, _sz, _i64, _vp]),
+    "vrs_splat_workspace_size": (_sz, [_i64, _int, _P(View), _P(Crop), _int, _int, _i64]),
+    "vrs_splat_workspace_layout": (_int, [_i64, _int, _P(View), _P(Crop), _int, _int, _i64,
+                                          _P(SplatLayout)]),
+    "vrs_splat_points": (_int, [_vp, _vp, _vp, _vp, _i64, _int, _int, _P(View), _int,
+                                _P(Crop), _int, _vp, _vp, _flt, _flt, _vp, _vp, _sz, _i64,
+                                _vp, _vp]),
+    "vrs_splat_points_backward": (_int, [_vp, _vp, _vp, _vp, _i64, _int, _int, _P(View), _int,
+                                         _P(Crop), _int, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                                         _i64, _vp]),
+    "vrs_decoder_workspace_size": (_sz, [_P(DecoderDesc), _P(Crop), _int]),
+    "vrs_decode_fovea": (_int, [_vp, _int, _vp, _P(View), _int, _P(Crop), _int, _vp,
+                                _P(DecoderDesc), _vp, _vp, _sz, _vp]),
+    "vrs_decode_fovea_backward": (_int, [_vp, _int, _vp, _P(View), _int, _P(Crop), _int, _vp,
+                                         _P(DecoderDesc), _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "vrs_composite_frame": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _int, _flt,
+                                   _flt, _flt, _vp, _vp]),
+    "vrs_composite_frame_backward": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _int,
+                                            _flt, _flt, _flt, _vp, _vp, _vp, _vp]),
+    "vrs_l1_loss": (_int, [_vp, _vp, _i64, _vp, _vp, _flt, _vp]),
+}
+
+
+def lib():
+    """Load the HIP library (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: build it with paper_2410_17932_amd/build.py")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            if hasattr(l, name):
+                fn = getattr(l, name)
+                fn.restype = res
+                fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return lib().vrs_status_string(code).decode()
+    except Exception:  # pragma: no cover - only for messages
+        return str(code)
+
+
+def _check(code, where):
+    if code != VRS_OK:
+        raise VrsError(code, where)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def ptr(t, dtype=None):
+    """Device pointer of a contiguous GPU tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------ descriptors
+def make_views(views) -> ctypes.Array:
+    """views: list of objects with fx, fy, cx, cy, width, height, rot, trans,
+    znear (see synth.View)."""
+    arr = (View * len(views))()
+    for i, v in enumerate(views):
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = v.fx, v.fy, v.cx, v.cy
+        for k, x in enumerate(np.asarray(v.rot, np.float32).ravel()):
+            arr[i].rot[k] = float(x)
+        for k, x in enumerate(np.asarray(v.trans, np.float32).ravel()):
+            arr[i].trans[k] = float(x)
+        arr[i].znear = v.znear
+        arr[i].width, arr[i].height = v.width, v.height
+    return arr
+
+
+def make_crops(crops) -> ctypes.Array:
+    arr = (Crop * max(len(crops), 1))()
+    for i, c in enumerate(crops):
+        arr[i].view, arr[i].x0, arr[i].y0, arr[i].size = c.view, c.x0, c.y0, c.size
+        arr[i].gaze_x, arr[i].gaze_y = c.gaze_x, c.gaze_y
+    return arr
+
+
+def make_opts(tile=16, alpha_clamp=0.99, alpha_min=1 / 255, t_min=1e-4, lowpass=0.3, extent=3.0,
+              bg=(0.0, 0.0, 0.0), **_) -> RasterOpts:
+    o = RasterOpts()
+    o.tile, o.alpha_clamp, o.alpha_min, o.t_min = tile, alpha_clamp, alpha_min, t_min
+    o.lowpass, o.extent = lowpass, extent
+    for k in range(3):
+        o.bg[k] = bg[k]
+    return o
+
+
+def make_decoder_desc(widths, in_ch=4, dtype=VRS_F32) -> DecoderDesc:
+    d = DecoderDesc()
+    d.n_levels = len(widths)
+    for k, w in enumerate(widths):
+        d.width[k] = w
+    d.in_ch, d.dtype = in_ch, dtype
+    return d
+
+
+# ------------------------------------------------------------------ bake
+def bake_gaussians(logscale, quat, logit):
+    n = logit.shape[0]
+    cov = torch.empty((6, n), device=logit.device, dtype=torch.float32)
+    op = torch.empty(n, device=logit.device, dtype=torch.float32)
+    _check(lib().vrs_bake_gaussians(ptr(logscale, torch.float32), ptr(quat, torch.float32),
+                                    ptr(logit, torch.float32), n, ptr(cov), ptr(op), _stream()),
+           "vrs_bake_gaussians")
+    return cov, op
+
+
+def bake_gaussians_backward(logscale, quat, logit, d_cov, d_opacity, d_logscale, d_quat, d_logit):
+    _check(lib().vrs_bake_gaussians_backward(
+        ptr(logscale, torch.float32), ptr(quat, torch.float32), ptr(logit, torch.float32),
+        logit.shape[0], ptr(d_cov, torch.float32), ptr(d_opacity, torch.float32),
+        ptr(d_logscale, torch.float32), ptr(d_quat, torch.float32), ptr(d_logit, torch.float32),
+        _stream()), "vrs_bake_gaussians_backward")
+
+
+# ------------------------------------------------------------- periphery
+class RenderWorkspace:
+    """Caller-owned workspace of one render call (kept for its backward)."""
+
+    def __init__(self, n, views, opts, max_pairs, device="cuda"):
+        self.n, self.views, self.opts, self.max_pairs = n, views, opts, int(max_pairs)
+        self.cviews = make_views(views)
+        size = lib().vrs_render_workspace_size(n, len(views), self.cviews, ctypes.byref(opts),
+                                               self.max_pairs)
+        if size == 0:
+            raise VrsError(VRS_EINVAL, "vrs_render_workspace_size")
+        self.buf = torch.empty(size, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        lay = RenderLayout()
+        _check(lib().vrs_render_workspace_layout(n, len(views), self.cviews, ctypes.byref(opts),
+                                                 self.max_pairs, ctypes.byref(lay)),
+               "vrs_render_workspace_layout")
+        self.layout = lay
+
+    def u32(self, off, count):
+        return self.buf[off:off + 4 * count].view(torch.int32)
+
+    def pair_count(self) -> int:
+        return int(self.u32(self.layout.pair_count, 1).item())
+
+    def tile_lists(self):
+        """(ranges [tiles][2] int64, sorted ids int64) on the host."""
+        ranges = self.u32(self.layout.tile_ranges, 2 * self.layout.tiles_total)
+        ranges = ranges.view(-1, 2).cpu().numpy().astype(np.int64)
+        cnt = min(self.pair_count(), self.max_pairs)
+        ids = self.u32(self.layout.sorted_ids, max(cnt, 1))[:cnt].cpu().numpy().astype(np.int64)
+        return ranges, ids
+
+
+def render_gaussians(mean, cov, opacity, sh, sh_degree, views, opts, ws: RenderWorkspace,
+                     outputs=None):
+    nv = len(views)
+    W, H = views[0].width, views[0].height
+    dev = mean.device
+    if outputs is None:
+        outputs = dict(rgb=torch.empty((nv, 3, H, W), device=dev),
+                       depth=torch.empty((nv, H, W), device=dev),
+                       tfinal=torch.empty((nv, H, W), device=dev),
+                       ncontrib=torch.empty((nv, H, W), device=dev, dtype=torch.int32))
+    n = mean.shape[1]
+    code = lib().vrs_render_gaussians(
+        ptr(mean, torch.float32), ptr(cov, torch.float32), ptr(opacity, torch.float32),
+        ptr(sh, torch.float32), sh_degree, n, ws.cviews, nv, ctypes.byref(opts),
+        ptr(outputs["rgb"]), ptr(outputs["depth"]), ptr(outputs["tfinal"]),
+        ptr(outputs["ncontrib"]), ptr(ws.buf), ws.buf.numel(), ws.max_pairs, ptr(ws.status),
+        _stream())
+    _check(code, "vrs_render_gaussians")
+    return outputs
+
+
+def render_gaussians_backward(mean, cov, opacity, sh, sh_degree, views, opts, ws, tfinal, d_rgb,
+                              d_depth, d_mean, d_cov, d_opacity, d_sh):
+    n = mean.shape[1]
+    code = lib().vrs_render_gaussians_backward(
+        ptr(mean, torch.float32), ptr(cov, torch.float32), ptr(opacity, torch.float32),
+        ptr(sh, torch.float32), sh_degree, n, ws.cviews, len(views), ctypes.byref(opts),
+        ptr(tfinal, torch.float32), ptr(d_rgb, torch.float32), ptr(d_depth, torch.float32),
+        ptr(d_mean, torch.float32), ptr(d_cov, torch.float32), ptr(d_opacity, torch.float32),
+        ptr(d_sh, torch.float32), ptr(ws.buf), ws.buf.numel(), ws.max_pairs, _stream())
+    _check(code, "vrs_render_gaussians_backward")
+
+
+# ----------------------------------------------------------------- fovea
+def pyramid_pixels(crops, levels) -> int:
+    return int(sum(sum((c.size >> l) ** 2 for l in range(levels)) for c in crops))
+
+
+class SplatWorkspace:
+    def __init__(self, np_, views, crops, levels, max_frags, device="cuda"):
+        self.np, self.views, self.crops, self.levels = np_, views, crops, levels
+        self.max_frags = int(max_frags)
+        self.cviews, self.ccrops = make_views(views), make_crops(crops)
+        size = lib().vrs_splat_workspace_size(np_, len(views), self.cviews, self.ccrops,
+                                              len(crops), levels, self.max_frags)
+        if size == 0:
+            raise VrsError(VRS_EINVAL, "vrs_splat_workspace_size")
+        self.buf = torch.empty(size, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        lay = SplatLayout()
+        _check(lib().vrs_splat_workspace_layout(np_, len(views), self.cviews, self.ccrops,
+                                                len(crops), levels, self.max_frags,
+                                                ctypes.byref(lay)), "vrs_splat_workspace_layout")
+        self.layout = lay
+
+    def u32(self, off, count):
+        return self.buf[off:off + 4 * count].view(torch.int32)
+
+    def frag_count(self) -> int:
+        return int(self.u32(self.layout.frag_count, 1).item())
+
+    def lists(self):
+        cnt = min(self.frag_count(), self.max_frags)
+        keys = self.u32(self.layout.sorted_keys, max(cnt, 1))[:cnt].cpu().numpy().astype(np.int64)
+        ids = self.u32(self.layout.sorted_ids, max(cnt, 1))[:cnt].cpu().numpy().astype(np.int64)
+        return keys, ids
+
+
+def splat_points(pos, radius, feat, opacity, views, crops, levels, depth, tfinal, ws,
+                 cov_min=0.5, slack=1.05, pyramid=None):
+    P = pyramid_pixels(crops, levels)
+    C = feat.shape[1]
+    if pyramid is None:
+        pyramid = torch.empty((P, C), device=pos.device, dtype=torch.float32)
+    code = lib().vrs_splat_points(
+        ptr(pos, torch.float32), ptr(radius, torch.float32), ptr(feat), ptr(opacity),
+        pos.shape[1], C, levels, ws.cviews, len(views), ws.ccrops, len(crops), ptr(depth),
+        ptr(tfinal), cov_min, slack, ptr(pyramid), ptr(ws.buf), ws.buf.numel(), ws.max_frags,
+        ptr(ws.status), _stream())
+    _check(code, "vrs_splat_points")
+    return pyramid
+
+
+def splat_points_backward(pos, radius, feat, opacity, views, crops, levels, d_pyramid, ws,
+                          d_feat=None, d_pos=None, d_radius=None, d_opacity=None):
+    code = lib().vrs_splat_points_backward(
+        ptr(pos, torch.float32), ptr(radius, torch.float32), ptr(feat), ptr(opacity),
+        pos.shape[1], feat.shape[1], levels, ws.cviews, len(views), ws.ccrops, len(crops),
+        ptr(d_pyramid, torch.float32), ptr(d_feat), ptr(d_pos), ptr(d_radius), ptr(d_opacity),
+        ptr(ws.buf), ws.buf.numel(), ws.max_frags, _stream())
+    _check(code, "vrs_splat_points_backward")
+
+
+# --------------------------------------------------------------- decoder
+class DecoderWorkspace:
+    def __init__(self, widths, crops, dtype=VRS_F32, in_ch=4, device="cuda"):
+        self.desc = make_decoder_desc(widths, in_ch, dtype)
+        self.crops = crops
+        self.ccrops = make_crops(crops)
+        size = lib().vrs_decoder_workspace_size(ctypes.byref(self.desc), self.ccrops, len(crops))
+        if size == 0:
+            raise VrsError(VRS_EINVAL, "vrs_decoder_workspace_size")
+        self.buf = torch.empty(size, dtype=torch.uint8, device=device)
+
+
+def fovea_elements(crops) -> int:
+    return int(sum(3 * c.size * c.size for c in crops))
+
+
+def decode_fovea(pyramid, levels, periphery, views, crops, weights, ws: DecoderWorkspace,
+                 out=None):
+    if out is None:
+        out = torch.empty(fovea_elements(crops), device=pyramid.device, dtype=torch.float32)
+    cviews = make_views(views)
+    code = lib().vrs_decode_fovea(ptr(pyramid, torch.float32), levels,
+                                  ptr(periphery, torch.float32), cviews, len(views), ws.ccrops,
+                                  len(crops), ptr(weights, torch.float32), ctypes.byref(ws.desc),
+                                  ptr(out), ptr(ws.buf), ws.buf.numel(), _stream())
+    _check(code, "vrs_decode_fovea")
+    return out
+
+
+def decode_fovea_backward(pyramid, levels, periphery, views, crops, weights, ws, d_fovea,
+                          d_pyramid=None, d_periphery=None, d_weights=None):
+    cviews = make_views(views)
+    code = lib().vrs_decode_fovea_backward(
+        ptr(pyramid, torch.float32), levels, ptr(periphery, torch.float32), cviews, len(views),
+        ws.ccrops, len(crops), ptr(weights, torch.float32), ctypes.byref(ws.desc),
+        ptr(d_fovea, torch.float32), ptr(d_pyramid), ptr(d_periphery), ptr(d_weights),
+        ptr(ws.buf), ws.buf.numel(), _stream())
+    _check(code, "vrs_decode_fovea_backward")
+
+
+# ------------------------------------------------------------- combine
+def composite_frame(periphery, fovea, crops, mode=BLEND_LINEAR, ring=64.0, m=0.75, gamma=0.2,
+                    out=None):
+    V, _, H, W = periphery.shape
+    if out is None:
+        out = torch.empty_like(periphery)
+    code = lib().vrs_composite_frame(ptr(periphery, torch.float32), V, W, H,
+                                     ptr(fovea, torch.float32), make_crops(crops), len(crops),
+                                     mode, ring, m, gamma, ptr(out), _stream())
+    _check(code, "vrs_composite_frame")
+    return out
+
+
+def composite_frame_backward(periphery, fovea, crops, d_out, d_periphery=None, d_fovea=None,
+                             mode=BLEND_LINEAR, ring=64.0, m=0.75, gamma=0.2):
+    V, _, H, W = periphery.shape
+    code = lib().vrs_composite_frame_backward(
+        ptr(periphery, torch.float32), V, W, H, ptr(fovea, torch.float32), make_crops(crops),
+        len(crops), mode, ring, m, gamma, ptr(d_out, torch.float32), ptr(d_periphery),
+        ptr(d_fovea), _stream())
+    _check(code, "vrs_composite_frame_backward")
+
+
+def l1_loss(pred, target, d_pred=None, scale=1.0):
+    loss = torch.empty(1, device=pred.device, dtype=torch.float32)
+    _check(lib().vrs_l1_loss(ptr(pred, torch.float32), ptr(target, torch.float32), pred.numel(),
+                             ptr(loss), ptr(d_pred), scale, _stream()), "vrs_l1_loss")
+    return loss

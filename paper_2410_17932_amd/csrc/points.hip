@@ -1,0 +1,381 @@
+// Foveal neural-point splat, forward (Sec. 3.3 sub-frustum + depth cull;
+// Sec. 4 "Inference": one count, one scan and one fill over all pyramid
+// layers and all crops).
+//
+// Instead of per-pixel fragment lists sorted in place, the pass orders all
+// surviving (view, point) entries by depth once, emits every fragment in
+// that order, and sorts the fragments stably by layer pixel -- the same
+// onesweep sort the periphery uses -- so each pixel's list comes out in
+// (depth, point index) order with no atomics and no per-pixel sort.
+//   k_pt_project   one thread per point, points read once for all crops:
+//                  projection, depth cull, layer, fragment count per view
+//   scan + k_pt_compact  keep (depth key, entry) of surviving entries in
+//                  index order
+//   radix sort     by depth key (stable)
+//   scan           fragment counts in depth order -> offsets
+//   k_pt_emit      one thread per surviving entry writes its fragments
+//                  (layer pixel key, weight | point index)
+//   radix sort     by layer pixel key (stable)
+//   k_pt_blend     segment heads walk their pixel's list front to back
+#include <hip/hip_fp16.h>
+
+#include "pt_device.h"
+
+namespace vrs {
+
+struct SplatWs {
+  size_t nfrag, zkey, scan, ckey0, cval0, ckey1, cval1, live, foffs, frag_count, fkey0, fval0,
+      fkey1, fval1, sort_tmp, scan_tmp, total;
+  int64_t vn, pix_total;
+  int key_bits;
+  bool frags_in_1;
+};
+
+static int bits_for_p(int64_t n) {
+  int b = 1;
+  while (b < 32 && (int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+static int64_t pyramid_pixels(const vrs_crop* crops, int n_crops, int levels) {
+  int64_t s = 0;
+  for (int k = 0; k < n_crops; ++k)
+    for (int l = 0; l < levels; ++l) {
+      int64_t e = crops[k].size >> l;
+      s += e * e;
+    }
+  return s;
+}
+
+static bool splat_layout(int64_t np, int nv, const vrs_crop* crops, int n_crops, int levels,
+                         int64_t max_frags, SplatWs* L) {
+  if (np < 0 || nv < 1 || nv > VRS_MAX_VIEWS || n_crops < 0 || n_crops > VRS_MAX_CROPS ||
+      levels < 1 || levels > VRS_MAX_LEVELS || max_frags < 0 || (n_crops > 0 && !crops))
+    return false;
+  L->vn = np * nv;
+  L->pix_total = pyramid_pixels(crops, n_crops, levels);
+  L->key_bits = bits_for_p(std::max<int64_t>(L->pix_total, 2));
+  L->frags_in_1 = (((L->key_bits + 7) / 8) & 1) != 0;
+  const int64_t vn = std::max<int64_t>(L->vn, 1), mf = std::max<int64_t>(max_frags, 1);
+  Carver c;
+  L->nfrag = c.take(vn * 4);
+  L->zkey = c.take(vn * 4);
+  L->scan = c.take(vn * 4);
+  L->ckey0 = c.take(vn * 4);
+  L->cval0 = c.take(vn * 4);
+  L->ckey1 = c.take(vn * 4);
+  L->cval1 = c.take(vn * 4);
+  L->live = c.take(4);
+  L->foffs = c.take(vn * 4);
+  L->frag_count = c.take(4);
+  L->fkey0 = c.take(mf * 4);
+  L->fval0 = c.take(mf * 8);
+  L->fkey1 = c.take(mf * 4);
+  L->fval1 = c.take(mf * 8);
+  L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mf, L->key_bits)));
+  L->scan_tmp = c.take(scan_tmp_bytes(vn));
+  L->total = c.off;
+  return true;
+}
+
+// host: crop table with packed-pyramid and packed-output bases
+bool make_crops(const vrs_crop* crops, int n_crops, int levels, const KViews& kv, KCrops* out) {
+  if (n_crops < 0 || n_crops > VRS_MAX_CROPS) return false;
+  out->n = n_crops;
+  int64_t pb = 0, ob = 0;
+  const int unit = 1 << (levels - 1);
+  for (int k = 0; k < n_crops; ++k) {
+    const vrs_crop& c = crops[k];
+    if (c.view < 0 || c.view >= kv.n) return false;
+    if (c.size < unit || c.size % unit != 0) return false;
+    const KView& v = kv.v[c.view];
+    if (c.x0 < 0 || c.y0 < 0 || c.x0 + c.size > v.W || c.y0 + c.size > v.H) return false;
+    KCrop& d = out->c[k];
+    d.view = c.view; d.x0 = c.x0; d.y0 = c.y0; d.size = c.size;
+    d.gx = c.gaze_x; d.gy = c.gaze_y;
+    d.pix_base = (int)pb;
+    d.out_base = (int)ob;
+    for (int l = 0; l < levels; ++l) pb += (int64_t)(c.size >> l) * (c.size >> l);
+    ob += (int64_t)3 * c.size * c.size;
+    if (pb > (int64_t(1) << 30) || ob > (int64_t(1) << 30)) return false;
+  }
+  return true;
+}
+
+bool splat_layout_public(int64_t np, int nv, const vrs_crop* crops, int n_crops, int levels,
+                         int64_t max_frags, size_t* frag_count, size_t* keys, size_t* vals,
+                         size_t* total, int64_t* pix_total, bool* in1, size_t* vals_alt) {
+  SplatWs L;
+  if (!splat_layout(np, nv, crops, n_crops, levels, max_frags, &L)) return false;
+  *frag_count = L.frag_count;
+  *keys = L.frags_in_1 ? L.fkey1 : L.fkey0;
+  *vals = L.frags_in_1 ? L.fval1 : L.fval0;
+  *vals_alt = L.frags_in_1 ? L.fval0 : L.fval1;
+  *total = L.total;
+  *pix_total = L.pix_total;
+  *in1 = L.frags_in_1;
+  return true;
+}
+
+struct PtArgs {
+  float cov_min, slack;
+  int levels;
+  uint32_t view_mask;  // views that own at least one crop
+};
+
+// --------------------------------------------------------------- project
+__global__ __launch_bounds__(256) void k_pt_project(
+    const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
+    KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
+    uint32_t* __restrict__ nfrag, uint32_t* __restrict__ zkey) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const float x = pos[i], y = pos[np + i], z = pos[2 * np + i], r = radius[i];
+  for (int v = 0; v < views.n; ++v) {
+    const int64_t e = (int64_t)v * np + i;
+    uint32_t cnt = 0;
+    PtGeom g;
+    if ((a.view_mask >> v) & 1u) {
+      const KView& cv = views.v[v];
+      const int64_t plane = (int64_t)cv.W * cv.H;
+      if (pt_geom32(cv, x, y, z, r, depth ? depth + v * plane : nullptr,
+                    tfinal ? tfinal + v * plane : nullptr, a.cov_min, a.slack, a.levels, g)) {
+        for (int k = 0; k < crops.n; ++k) {
+          const KCrop& c = crops.c[k];
+          if (c.view != v) continue;
+          for (int li = 0; li < (g.two ? 2 : 1); ++li) {
+            const int l = g.l0 + li, Sl = c.size >> l;
+            float xl, yl;
+            int ix, iy;
+            if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) cnt += pt_targets(ix, iy, Sl);
+          }
+        }
+      }
+    }
+    nfrag[e] = cnt;
+    zkey[e] = cnt ? __float_as_uint(g.t[2]) : 0xffffffffu;
+  }
+}
+
+__global__ void k_pt_compact(const uint32_t* __restrict__ nfrag, const uint32_t* __restrict__ zkey,
+                             const uint32_t* __restrict__ scan, int64_t vn,
+                             uint32_t* __restrict__ ckey, uint32_t* __restrict__ cval) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < vn;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (nfrag[i]) {
+      const uint32_t p = scan[i];
+      ckey[p] = zkey[i];
+      cval[p] = (uint32_t)i;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ emit
+__global__ __launch_bounds__(256) void k_pt_emit(
+    const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
+    KCrops crops, PtArgs a, const uint32_t* __restrict__ sorted_e,
+    const uint32_t* __restrict__ live_p, const uint32_t* __restrict__ foffs,
+    const uint32_t* __restrict__ total_p, int64_t max_frags, uint32_t* __restrict__ fkey,
+    uint64_t* __restrict__ fval, int32_t* status) {
+  const int64_t live = *live_p;
+  const int64_t total = *total_p;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = sorted_e[j];
+    const int v = (int)(e / np);
+    const int64_t i = e - (int64_t)v * np;
+    const KView& cv = views.v[v];
+    PtGeom g;
+    // the depth test already passed in k_pt_project; recomputing the same
+    // single-precision sequence without it gives identical geometry
+    if (!pt_geom32(cv, pos[i], pos[np + i], pos[2 * np + i], radius[i], nullptr, nullptr,
+                   a.cov_min, a.slack, a.levels, g))
+      continue;
+    float f = 0.0f;
+    if (g.two) f = log2f(g.s) - (float)g.l0;
+    int64_t o = foffs[j];
+    for (int k = 0; k < crops.n; ++k) {
+      const KCrop& c = crops.c[k];
+      if (c.view != v) continue;
+      int lb = c.pix_base;
+      int l = 0;
+      for (; l < g.l0; ++l) lb += (c.size >> l) * (c.size >> l);
+      for (int li = 0; li < (g.two ? 2 : 1); ++li, ++l) {
+        const int Sl = c.size >> l;
+        const float wl = g.two ? (li == 0 ? 1.0f - f : f) : 1.0f;
+        float xl, yl;
+        int ix, iy;
+        if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) {
+          const float bx = xl - (float)ix, by = yl - (float)iy;
+          for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+              const int xx = ix + dx, yy = iy + dy;
+              if (xx < 0 || xx >= Sl || yy < 0 || yy >= Sl) continue;
+              const float w = wl * (dx ? bx : 1.0f - bx) * (dy ? by : 1.0f - by);
+              if (o < max_frags) {
+                fkey[o] = (uint32_t)(lb + yy * Sl + xx);
+                fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
+              }
+              ++o;
+            }
+        }
+        lb += Sl * Sl;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- blend
+__global__ __launch_bounds__(256) void k_pt_blend(const uint32_t* __restrict__ fkey,
+                                                  const uint64_t* __restrict__ fval,
+                                                  const uint32_t* __restrict__ total_p,
+                                                  int64_t max_frags,
+                                                  const uint16_t* __restrict__ feat,
+                                                  const float* __restrict__ opacity, int64_t np,
+                                                  int64_t pix_total, float4* __restrict__ pyr) {
+  const int64_t cnt = std::min<int64_t>(*total_p, max_frags);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = fkey[i];
+    if (i > 0 && fkey[i - 1] == k) continue;
+    if (k >= (uint64_t)pix_total) continue;
+    float T = 1.0f;
+    float4 F = make_float4(0, 0, 0, 0);
+    for (int64_t j = i; j < cnt && fkey[j] == k; ++j) {
+      const uint64_t vv = fval[j];
+      const uint32_t id = (uint32_t)vv;
+      if (id >= (uint64_t)np) continue;
+      const float w = __uint_as_float((uint32_t)(vv >> 32));
+      const float al = opacity ? w * opacity[id] : w;
+      const uint2 hb = *reinterpret_cast<const uint2*>(feat + (int64_t)id * 4);
+      const float aT = al * T;
+      F.x += h2f((uint16_t)(hb.x & 0xffffu)) * aT;
+      F.y += h2f((uint16_t)(hb.x >> 16)) * aT;
+      F.z += h2f((uint16_t)(hb.y & 0xffffu)) * aT;
+      F.w += h2f((uint16_t)(hb.y >> 16)) * aT;
+      T = T * (1.0f - al);
+    }
+    pyr[k] = F;
+  }
+}
+
+__global__ void k_zero4(float4* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_float4(0, 0, 0, 0);
+}
+
+}  // namespace vrs
+
+using namespace vrs;
+
+static bool check_views(const vrs_view* views, int nv, KViews* kv) {
+  if (!make_views(views, nv, kv)) return false;
+  for (int i = 1; i < nv; ++i)
+    if (views[i].width != views[0].width || views[i].height != views[0].height) return false;
+  return true;
+}
+
+extern "C" size_t vrs_splat_workspace_size(int64_t np, int n_views, const vrs_view* views,
+                                           const vrs_crop* crops, int n_crops, int levels,
+                                           int64_t max_frags) {
+  SplatWs L;
+  KViews kv;
+  KCrops kc;
+  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc)) return 0;
+  if (!splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L)) return 0;
+  return L.total;
+}
+
+extern "C" vrs_status vrs_splat_workspace_layout(int64_t np, int n_views, const vrs_view* views,
+                                                 const vrs_crop* crops, int n_crops, int levels,
+                                                 int64_t max_frags, vrs_splat_layout* out) {
+  SplatWs L;
+  if (!out || !splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L))
+    return VRS_EINVAL;
+  out->frag_count = L.frag_count;
+  out->sorted_keys = L.frags_in_1 ? L.fkey1 : L.fkey0;
+  out->sorted_ids = L.frags_in_1 ? L.fval1 : L.fval0;   // low 32 bits of each 64-bit value
+  out->pyramid_pixels = L.pix_total;
+  return VRS_OK;
+}
+
+extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
+                                       const uint16_t* feat, const float* opacity, int64_t np,
+                                       int channels, int levels, const vrs_view* views,
+                                       int n_views, const vrs_crop* crops, int n_crops,
+                                       const float* depth, const float* t_final, float cov_min,
+                                       float slack, float* pyramid, void* ws, size_t ws_bytes,
+                                       int64_t max_frags, int32_t* dev_status, void* stream) {
+  KViews kv;
+  KCrops kc;
+  SplatWs L;
+  if (channels != 4) return channels > 0 ? VRS_EUNSUPPORTED : VRS_EINVAL;
+  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc))
+    return VRS_EINVAL;
+  if (np < 0 || np > (int64_t(1) << 31) / std::max(n_views, 1) ||
+      (np > 0 && (!pos || !radius || !feat)))
+    return VRS_EINVAL;
+  if ((depth == nullptr) != (t_final == nullptr)) return VRS_EINVAL;
+  if (!pyramid || !ws || max_frags < 0 || max_frags >= (int64_t(1) << 32)) return VRS_EINVAL;
+  if (!splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L) || ws_bytes < L.total)
+    return VRS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PtArgs a;
+  a.cov_min = cov_min;
+  a.slack = slack;
+  a.levels = levels;
+  a.view_mask = 0;
+  for (int k = 0; k < n_crops; ++k) a.view_mask |= 1u << crops[k].view;
+  const int64_t vn = L.vn;
+  uint32_t* frag_count = at<uint32_t>(ws, L.frag_count);
+  if (L.pix_total > 0) {
+    const int blocks = (int)std::min<int64_t>(4096, div_up(L.pix_total, 256));
+    hipLaunchKernelGGL(k_zero4, dim3(blocks), dim3(256), 0, st,
+                       reinterpret_cast<float4*>(pyramid), L.pix_total);
+    VRS_LAUNCH_CHECK();
+  }
+  if (vn == 0 || n_crops == 0) {
+    VRS_HIP_CHECK(fill_u32(frag_count, 0, 1, st));
+    return VRS_OK;
+  }
+  uint32_t* nfrag = at<uint32_t>(ws, L.nfrag);
+  uint32_t* zkey = at<uint32_t>(ws, L.zkey);
+  uint32_t* scan = at<uint32_t>(ws, L.scan);
+  uint32_t* live = at<uint32_t>(ws, L.live);
+  hipLaunchKernelGGL(k_pt_project, dim3(div_up(np, 256)), dim3(256), 0, st, pos, radius, np, kv,
+                     kc, a, depth, t_final, nfrag, zkey);
+  VRS_LAUNCH_CHECK();
+  // surviving entries, kept in index order
+  VRS_HIP_CHECK(exclusive_scan_flags_u32(nfrag, scan, live, vn, at<void>(ws, L.scan_tmp),
+                                         dev_status, st));
+  hipLaunchKernelGGL(k_pt_compact, dim3((unsigned)std::min<int64_t>(8192, div_up(vn, 256))),
+                     dim3(256), 0, st, nfrag, zkey, scan, vn, at<uint32_t>(ws, L.ckey0),
+                     at<uint32_t>(ws, L.cval0));
+  VRS_LAUNCH_CHECK();
+  bool c1 = false;
+  VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.ckey0), at<uint32_t>(ws, L.cval0),
+                               at<uint32_t>(ws, L.ckey1), at<uint32_t>(ws, L.cval1), live, vn, 32,
+                               at<void>(ws, L.sort_tmp), dev_status, st, &c1));
+  const uint32_t* sorted_e = at<uint32_t>(ws, c1 ? L.cval1 : L.cval0);
+  VRS_HIP_CHECK(exclusive_scan_u32(nfrag, sorted_e, at<uint32_t>(ws, L.foffs), frag_count, live,
+                                   vn, at<void>(ws, L.scan_tmp), dev_status, st));
+  hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)std::min<int64_t>(8192, div_up(vn, 256))),
+                     dim3(256), 0, st, pos, radius, np, kv, kc, a, sorted_e, live,
+                     at<uint32_t>(ws, L.foffs), frag_count, max_frags, at<uint32_t>(ws, L.fkey0),
+                     at<uint64_t>(ws, L.fval0), dev_status);
+  VRS_LAUNCH_CHECK();
+  bool f1 = false;
+  VRS_HIP_CHECK(radix_sort_u64(at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
+                               at<uint32_t>(ws, L.fkey1), at<uint64_t>(ws, L.fval1), frag_count,
+                               std::max<int64_t>(max_frags, 1), L.key_bits,
+                               at<void>(ws, L.sort_tmp), dev_status, st, &f1));
+  const int bb = (int)std::min<int64_t>(8192, std::max(1, div_up(max_frags, 256)));
+  hipLaunchKernelGGL(k_pt_blend, dim3(bb), dim3(256), 0, st,
+                     at<uint32_t>(ws, f1 ? L.fkey1 : L.fkey0), at<uint64_t>(ws, f1 ? L.fval1 : L.fval0),
+                     frag_count, max_frags, feat, opacity, np, L.pix_total,
+                     reinterpret_cast<float4*>(pyramid));
+  VRS_LAUNCH_CHECK();
+  return VRS_OK;
+}

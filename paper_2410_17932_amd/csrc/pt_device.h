@@ -1,0 +1,92 @@
+// Device-side pieces of the foveal neural-point splat shared by the forward
+// and backward kernels.
+#pragma once
+#include <hip/hip_fp16.h>
+
+#include "vrs_common.h"
+
+namespace vrs {
+
+struct PtGeom {
+  float t[3];
+  float ux, uy, px, py, s;
+  int l0;
+  bool two;
+};
+
+// Projection, depth-occlusion cull and pyramid layer of one point in view
+// cv (Sec. 3.3), single precision in the documented operation order.
+// depth/tfinal point at the view's planes (or are null: no depth cull).
+// Returns false if the point is culled.
+__device__ inline bool pt_geom32(const KView& cv, float x, float y, float z, float radius,
+                                 const float* depth, const float* tfinal, float cov_min,
+                                 float slack, int levels, PtGeom& g) {
+#pragma clang fp contract(off)
+  for (int i = 0; i < 3; ++i) {
+    float a = cv.R[3 * i + 0] * x;
+    float b = cv.R[3 * i + 1] * y;
+    float s = a + b;
+    float e = cv.R[3 * i + 2] * z;
+    s = s + e;
+    g.t[i] = s + cv.t[i];
+  }
+  if (!(g.t[2] > cv.znear)) return false;
+  g.ux = g.t[0] / g.t[2];
+  g.uy = g.t[1] / g.t[2];
+  const float fxu = cv.fx * g.ux, fyu = cv.fy * g.uy;
+  g.px = fxu + cv.cx;
+  g.py = fyu + cv.cy;
+  if (!(isfinite(g.px) && isfinite(g.py))) return false;
+  if (tfinal && g.px >= 0.0f && g.px < (float)cv.W && g.py >= 0.0f && g.py < (float)cv.H) {
+    const int X = (int)floorf(g.px), Y = (int)floorf(g.py);
+    const int64_t pi = (int64_t)Y * cv.W + X;
+    const float A = 1.0f - tfinal[pi];
+    if (A >= cov_min) {
+      const float q = depth[pi] / A;
+      const float lim = slack * q;
+      if (g.t[2] > lim) return false;
+    }
+  }
+  const float f2 = 2.0f * cv.fx;
+  const float num = f2 * radius;
+  g.s = num / g.t[2];
+  if (!isfinite(g.s)) return false;
+  g.l0 = 0;
+  g.two = false;
+  if (g.s > 1.0f) {
+    int e;
+    const float m = frexpf(g.s, &e);
+    g.l0 = e - 1;
+    if (g.l0 >= levels - 1) g.l0 = levels - 1;
+    else g.two = m > 0.5f;
+  }
+  return true;
+}
+
+// Layer-l coordinates of the point in a crop with origin (x0, y0) and the
+// integer corner of its bilinear footprint.  Returns false if no target of
+// the footprint lies inside the S_l x S_l layer.
+__device__ inline bool pt_layer32(const PtGeom& g, int x0, int y0, int l, int Sl, float& xl,
+                                  float& yl, int& ix, int& iy) {
+#pragma clang fp contract(off)
+  const float sc = ldexpf(1.0f, -l);
+  const float ax = g.px - (float)x0, ay = g.py - (float)y0;
+  const float bx = ax * sc, by = ay * sc;
+  xl = bx - 0.5f;
+  yl = by - 0.5f;
+  if (!(xl >= -1.0f && xl < (float)Sl && yl >= -1.0f && yl < (float)Sl)) return false;
+  ix = (int)floorf(xl);
+  iy = (int)floorf(yl);
+  return true;
+}
+
+__device__ inline int pt_targets(int ix, int iy, int Sl) {
+  const int nx = (ix >= 0 ? 1 : 0) + (ix + 1 <= Sl - 1 ? 1 : 0);
+  const int ny = (iy >= 0 ? 1 : 0) + (iy + 1 <= Sl - 1 ? 1 : 0);
+  return nx * ny;
+}
+
+// Half precision bits -> float.
+__device__ inline float h2f(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+
+}  // namespace vrs

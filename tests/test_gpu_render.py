@@ -1,0 +1,81 @@
+"""GPU parity of the periphery (vrs_render_gaussians) against the CPU
+reference: images within 1e-4, tile lists bit-exact, contributor counts
+exact, on the tiny forward case, a ragged multi-view case and every tile
+size; plus capacity overflow and the empty scene."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_17932_amd import api, synth
+
+from gpu_helpers import baked, check_render, gpu_render, oracle_render, pair_total
+
+pytestmark = pytest.mark.gpu
+
+
+def _lists_equal(ws, rect, zb, views, tile):
+    ranges, ids = ws.tile_lists()
+    D = synth.views_dims(views)
+    tx, ty = ws.layout.tiles_x, ws.layout.tiles_y
+    sel = np.array([[v, t] for v in range(len(views)) for t in range(tx * ty)], np.int32)
+    off, oids = oracle.tile_lists(rect, zb, D, tile, sel)
+    for s in range(len(sel)):
+        b, e = ranges[s]
+        assert np.array_equal(ids[b:e], oids[off[s]:off[s + 1]]), f"tile list {s} differs"
+    assert ws.pair_count() == off[-1]
+
+
+@pytest.mark.parametrize("case", ["tiny", "ragged_stereo", "sh3"])
+def test_render_parity(case):
+    if case == "tiny":
+        sc = synth.config(0)
+    elif case == "ragged_stereo":
+        sc = synth.small_scene(21, n_gauss=3000, width=200, height=136, f=150.0, n_views=2)
+    else:
+        sc = synth.small_scene(22, n_gauss=2500, width=176, height=120, f=140.0, sh_degree=3,
+                               n_views=2)
+    g, views, raster = sc["gaussians"], sc["views"], sc["raster"]
+    cov, op = baked(g)
+    o, rect, zb = oracle_render(g, cov, op, views, raster)
+    total = pair_total(rect, synth.views_dims(views), raster["tile"])
+    gpu, ws = gpu_render(g, cov, op, views, raster, max_pairs=total + 1000)
+    assert int(ws.status.item()) == 0
+    print(case, "ambiguous pixels:", check_render(o, gpu))
+    _lists_equal(ws, rect, zb, views, raster["tile"])
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_tile_size_invariance(tile):
+    sc = synth.small_scene(23, n_gauss=2000, width=150, height=100, f=120.0)
+    g, views, raster = sc["gaussians"], sc["views"], dict(sc["raster"])
+    cov, op = baked(g)
+    raster["tile"] = tile
+    o, rect, zb = oracle_render(g, cov, op, views, raster)
+    total = pair_total(rect, synth.views_dims(views), tile)
+    gpu, ws = gpu_render(g, cov, op, views, raster, max_pairs=total)
+    check_render(o, gpu)
+    _lists_equal(ws, rect, zb, views, tile)
+    raster16 = dict(raster, tile=16)
+    gpu16, _ = gpu_render(g, cov, op, views, raster16, max_pairs=4 * total)
+    assert np.array_equal(gpu16["ncontrib"], gpu["ncontrib"])
+    np.testing.assert_allclose(gpu16["rgb"], gpu["rgb"], atol=1e-6)
+
+
+def test_capacity_overflow_flagged():
+    sc = synth.config(0)
+    g, views, raster = sc["gaussians"], sc["views"], sc["raster"]
+    cov, op = baked(g)
+    gpu, ws = gpu_render(g, cov, op, views, raster, max_pairs=100)
+    assert int(ws.status.item()) == api.VRS_ECAPACITY
+
+
+def test_empty_scene_is_background():
+    sc = synth.small_scene(0, n_gauss=0)
+    g, views = sc["gaussians"], sc["views"]
+    raster = dict(sc["raster"], bg=(0.1, 0.2, 0.3))
+    cov = np.zeros((6, 0), np.float32)
+    op = np.zeros(0, np.float32)
+    gpu, ws = gpu_render(g, cov, op, views, raster, max_pairs=16)
+    for ch, b in enumerate((0.1, 0.2, 0.3)):
+        assert np.allclose(gpu["rgb"][:, ch], b)
+    assert (gpu["tfinal"] == 1).all() and (gpu["ncontrib"] == 0).all()
