@@ -306,10 +306,11 @@ class SplatWorkspace:
         return int(self.u32(self.layout.frag_count, 1).item())
 
     def lists(self):
+        """(layer-pixel keys, point ids) of every fragment in blend order."""
         cnt = min(self.frag_count(), self.max_frags)
         keys = self.u32(self.layout.sorted_keys, max(cnt, 1))[:cnt].cpu().numpy().astype(np.int64)
-        ids = self.u32(self.layout.sorted_ids, max(cnt, 1))[:cnt].cpu().numpy().astype(np.int64)
-        return keys, ids
+        vals = self.u32(self.layout.sorted_ids, 2 * max(cnt, 1))[:2 * cnt].cpu().numpy()
+        return keys, vals[0::2].astype(np.int64)   # low word of each 64-bit value
 
 
 def splat_points(pos, radius, feat, opacity, views, crops, levels, depth, tfinal, ws,

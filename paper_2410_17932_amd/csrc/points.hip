@@ -314,11 +314,11 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   if (channels != 4) return channels > 0 ? VRS_EUNSUPPORTED : VRS_EINVAL;
   if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc))
     return VRS_EINVAL;
-  if (np < 0 || np > (int64_t(1) << 31) / std::max(n_views, 1) ||
+  if (np < 0 || np * n_views >= (int64_t(1) << 30) ||
       (np > 0 && (!pos || !radius || !feat)))
     return VRS_EINVAL;
   if ((depth == nullptr) != (t_final == nullptr)) return VRS_EINVAL;
-  if (!pyramid || !ws || max_frags < 0 || max_frags >= (int64_t(1) << 32)) return VRS_EINVAL;
+  if (!pyramid || !ws || max_frags < 0 || max_frags >= (int64_t(1) << 30)) return VRS_EINVAL;
   if (!splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L) || ws_bytes < L.total)
     return VRS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
