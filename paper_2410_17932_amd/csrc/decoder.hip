@@ -1,0 +1,476 @@
+// Foveal decoder, forward: the small gated CNN that resolves each crop's
+// neural-point pyramid into the foveal image F, with the periphery crop
+// injected at the finest level (Sec. 3.3).
+//
+// Each level is one implicit-GEMM 3x3 convolution on the matrix cores:
+//   M = output pixels (a tile of TH rows x 16 columns per workgroup, one
+//       16-pixel row segment per MFMA row block),
+//   N = 2 * Kp pre-activations, ordered so N-tile 2t holds the feature half
+//       and N-tile 2t+1 the gate half of channels [16t, 16t+16): the gated
+//       epilogue ELU(f) * sigmoid(g) pairs values held by the same lane,
+//   K = 9 taps x Cin8 input channels (Cin padded to 8), padded to the MFMA
+//       depth.
+// The loader builds the zero-padded (TH+2) x 18 halo tile of the level's
+// input in LDS directly from its sources -- pyramid layer, bilinear x2
+// upsample of the coarser level's output, periphery crop -- so the
+// concatenated input never exists in HBM.  One launch per level covers all
+// crops (crops of uneven size are packed back to back in the grid).
+// Arithmetic: float operands with v_mfma_f32_16x16x4_f32 (VRS_F32), or
+// bfloat16 operands with v_mfma_f32_16x16x32_bf16 and float accumulation
+// (VRS_BF16); biases, activations and the RGB head in float.
+#include "vrs_common.h"
+
+namespace vrs {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kDecMaxNT = 8;  // widths up to 64 channels
+
+struct DecLevel {
+  int C, cin, cin8, kpad, kp, nout, kn, kpn, has_p, n_crops, W, H, width;
+  int tile_base[VRS_MAX_CROPS + 1];
+  int tiles_x[VRS_MAX_CROPS];
+  int S[VRS_MAX_CROPS];
+  int view[VRS_MAX_CROPS], x0[VRS_MAX_CROPS], y0[VRS_MAX_CROPS];
+  long long pyr_off[VRS_MAX_CROPS];  // float offset of this layer in the pyramid
+  long long h_off[VRS_MAX_CROPS];    // element offset of h_l
+  long long hn_off[VRS_MAX_CROPS];   // element offset of h_{l+1}
+  long long pre_off[VRS_MAX_CROPS];  // float offset of the pre-activations
+};
+
+template <typename T>
+struct DecTraits;
+template <>
+struct DecTraits<float> {
+  static constexpr int KSTEP = 4;
+  static constexpr int TH = 8;
+};
+template <>
+struct DecTraits<__bf16> {
+  static constexpr int KSTEP = 32;
+  static constexpr int TH = 16;
+};
+
+__device__ inline float to_f(float x) { return x; }
+__device__ inline float to_f(__bf16 x) { return (float)x; }
+
+__device__ inline float elu_f(float x) { return x > 0.0f ? x : expm1f(x); }
+__device__ inline float sigmoid_f(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// value of input channel c of level l at pixel (y, x) of crop k (inside the
+// S x S layer)
+template <typename T>
+__device__ inline float dec_input(const DecLevel& d, int k, int S, int y, int x, int c,
+                                  const float* __restrict__ pyr, const float* __restrict__ periph,
+                                  const T* __restrict__ hnext) {
+  if (c < d.C) return pyr[d.pyr_off[k] + ((long long)y * S + x) * d.C + c];
+  c -= d.C;
+  if (c < d.kn) {
+    const int Sn = S >> 1;
+    const float sx = 0.5f * (float)x - 0.25f, sy = 0.5f * (float)y - 0.25f;
+    const float fx0 = floorf(sx), fy0 = floorf(sy);
+    const float fx = sx - fx0, fy = sy - fy0;
+    int xa = (int)fx0, ya = (int)fy0, xb = xa + 1, yb = ya + 1;
+    xa = xa < 0 ? 0 : (xa > Sn - 1 ? Sn - 1 : xa);
+    xb = xb < 0 ? 0 : (xb > Sn - 1 ? Sn - 1 : xb);
+    ya = ya < 0 ? 0 : (ya > Sn - 1 ? Sn - 1 : ya);
+    yb = yb < 0 ? 0 : (yb > Sn - 1 ? Sn - 1 : yb);
+    const T* h = hnext + d.hn_off[k];
+    const float v00 = to_f(h[((long long)ya * Sn + xa) * d.kpn + c]);
+    const float v01 = to_f(h[((long long)ya * Sn + xb) * d.kpn + c]);
+    const float v10 = to_f(h[((long long)yb * Sn + xa) * d.kpn + c]);
+    const float v11 = to_f(h[((long long)yb * Sn + xb) * d.kpn + c]);
+    return (1.0f - fy) * ((1.0f - fx) * v00 + fx * v01) + fy * ((1.0f - fx) * v10 + fx * v11);
+  }
+  c -= d.kn;
+  if (d.has_p && c < 3) {
+    const long long plane = (long long)d.W * d.H;
+    return periph[(long long)d.view[k] * 3 * plane + c * plane +
+                  (long long)(d.y0[k] + y) * d.W + (d.x0[k] + x)];
+  }
+  return 0.0f;
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
+                                                  const float* __restrict__ periph,
+                                                  const T* __restrict__ hnext,
+                                                  const T* __restrict__ wp,
+                                                  const float* __restrict__ bp,
+                                                  T* __restrict__ hout, float* __restrict__ pre) {
+  constexpr int TH = DecTraits<T>::TH, RPW = TH / 4, KSTEP = DecTraits<T>::KSTEP;
+  extern __shared__ __align__(16) char smem[];
+  T* tile = reinterpret_cast<T*>(smem);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int k = 0;
+  while (k + 1 < d.n_crops && (int)blockIdx.x >= d.tile_base[k + 1]) ++k;
+  const int tl = blockIdx.x - d.tile_base[k];
+  const int S = d.S[k];
+  const int oy = (tl / d.tiles_x[k]) * TH, ox = (tl % d.tiles_x[k]) * 16;
+  const int cin8 = d.cin8;
+  // ---- halo tile fill (zero padding outside the layer and past Cin)
+  const int total = (TH + 2) * 18 * cin8;
+  for (int e = tid; e < total; e += 256) {
+    const int pix = e / cin8, c = e - pix * cin8;
+    const int hy = pix / 18, hx = pix - hy * 18;
+    const int y = oy + hy - 1, x = ox + hx - 1;
+    float v = 0.0f;
+    if (c < d.cin && y >= 0 && y < S && x >= 0 && x < S)
+      v = dec_input<T>(d, k, S, y, x, c, pyr, periph, hnext);
+    tile[e] = (T)v;
+  }
+  __syncthreads();
+  // ---- MFMA main loop
+  v4f acc[RPW][NT];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[r][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  const int r0 = wave * RPW;
+  const int col = lane & 15, kq = lane >> 4;
+  const int nsteps = d.kpad / KSTEP;
+  if constexpr (sizeof(T) == 2) {
+    const int g8 = cin8 >> 3;
+    for (int ks = 0; ks < nsteps; ++ks) {
+      const int gi = ks * 4 + kq;
+      const int tap = gi / g8, cg = gi - tap * g8;
+      const int dy = tap / 3, dx = tap - dy * 3;
+      v8bf a[RPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        if (tap < 9)
+          a[r] = *reinterpret_cast<const v8bf*>(&tile[((r0 + r + dy) * 18 + col + dx) * cin8 + cg * 8]);
+        else
+          a[r] = v8bf{0, 0, 0, 0, 0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const v8bf b = *reinterpret_cast<const v8bf*>(&wp[(long long)(j * 16 + col) * d.kpad + ks * 32 + kq * 8]);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b, acc[r][j], 0, 0, 0);
+      }
+    }
+  } else {
+    for (int ks = 0; ks < nsteps; ++ks) {
+      const int kk = ks * 4 + kq;
+      const int tap = kk / cin8, c = kk - tap * cin8;
+      const int dy = tap / 3, dx = tap - dy * 3;
+      float a[RPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+        a[r] = tap < 9 ? to_f(tile[((r0 + r + dy) * 18 + col + dx) * cin8 + c]) : 0.0f;
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const float b = to_f(wp[(long long)(j * 16 + col) * d.kpad + ks * 4 + kq]);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b, acc[r][j], 0, 0, 0);
+      }
+    }
+  }
+  // ---- gated epilogue: lane holds pixels kq*4 + i of the row, channel col
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int y = oy + r0 + r;
+    if (y >= S) continue;
+#pragma unroll
+    for (int t = 0; t < NT / 2; ++t) {
+      const int ch = t * 16 + col;
+      const float bf = bp[2 * t * 16 + col], bg = bp[(2 * t + 1) * 16 + col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = ox + kq * 4 + i;
+        if (x >= S) continue;
+        const float f = acc[r][2 * t][i] + bf, g = acc[r][2 * t + 1][i] + bg;
+        const long long p = (long long)y * S + x;
+        hout[d.h_off[k] + p * d.kp + ch] = (T)(elu_f(f) * sigmoid_f(g));
+        if (pre) {
+          pre[d.pre_off[k] + p * d.nout + 2 * t * 16 + col] = f;
+          pre[d.pre_off[k] + p * d.nout + (2 * t + 1) * 16 + col] = g;
+        }
+      }
+    }
+  }
+}
+
+// Re-order one level's float weights [2K][3][3][Cin] into the GEMM operand
+// [nout][kpad] (N-tile pairs of feature/gate halves, k = tap*Cin8 + c,
+// zero padding) and its bias.
+template <typename T>
+__global__ void k_dec_pack(const float* __restrict__ w, const float* __restrict__ b, int K,
+                           int cin, int cin8, int kp, int kpad, T* __restrict__ wp,
+                           float* __restrict__ bp) {
+  const int nout = 2 * kp;
+  const long long total = (long long)nout * kpad;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int n = (int)(e / kpad), kk = (int)(e - (long long)n * kpad);
+    const int t = n / 32, half = (n % 32) / 16, ch = t * 16 + (n % 16);
+    const int tap = kk / cin8, c = kk - tap * cin8;
+    float v = 0.0f;
+    if (ch < K && tap < 9 && c < cin) {
+      const int row = half ? K + ch : ch;
+      v = w[((long long)row * 9 + tap) * cin + c];
+    }
+    wp[e] = (T)v;
+    if (kk == 0) bp[n] = ch < K ? b[half ? K + ch : ch] : 0.0f;
+  }
+}
+
+// RGB head: F = W_o h_0 + b_o, one thread per output pixel of any crop.
+struct HeadArgs {
+  int n_crops, kp, K0;
+  int S[VRS_MAX_CROPS];
+  long long pix_base[VRS_MAX_CROPS + 1];
+  long long out_base[VRS_MAX_CROPS];
+  long long h_off[VRS_MAX_CROPS];
+};
+
+template <typename T>
+__global__ void k_dec_head(HeadArgs a, const T* __restrict__ h0, const float* __restrict__ wo,
+                           const float* __restrict__ bo, float* __restrict__ out) {
+  const long long npix = a.pix_base[a.n_crops];
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < npix;
+       p += (long long)gridDim.x * blockDim.x) {
+    int k = 0;
+    while (k + 1 < a.n_crops && p >= a.pix_base[k + 1]) ++k;
+    const long long q = p - a.pix_base[k];
+    const int S = a.S[k];
+    const T* h = h0 + a.h_off[k] + q * a.kp;
+    float a0 = bo[0], a1 = bo[1], a2 = bo[2];
+    for (int c = 0; c < a.K0; ++c) {
+      const float v = to_f(h[c]);
+      a0 += wo[c] * v;
+      a1 += wo[a.K0 + c] * v;
+      a2 += wo[2 * a.K0 + c] * v;
+    }
+    const long long plane = (long long)S * S;
+    out[a.out_base[k] + q] = a0;
+    out[a.out_base[k] + plane + q] = a1;
+    out[a.out_base[k] + 2 * plane + q] = a2;
+  }
+}
+
+// ------------------------------------------------------------ host side
+struct DecPlan {
+  int nd, C, dtype;
+  int K[VRS_MAX_LEVELS], kp[VRS_MAX_LEVELS], cin[VRS_MAX_LEVELS], cin8[VRS_MAX_LEVELS],
+      kpad[VRS_MAX_LEVELS];
+  size_t w_off[VRS_MAX_LEVELS], b_off[VRS_MAX_LEVELS];   // offsets into the float weights
+  size_t head_w, head_b;
+  // workspace (bytes)
+  size_t wp[VRS_MAX_LEVELS], bp[VRS_MAX_LEVELS], h[VRS_MAX_LEVELS], pre[VRS_MAX_LEVELS], total;
+  long long h_elems[VRS_MAX_LEVELS], pre_elems[VRS_MAX_LEVELS];
+  int n_crops;
+  long long head_pix;
+};
+
+static int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+static bool dec_plan(const vrs_decoder_desc* dd, const vrs_crop* crops, int n_crops, DecPlan* P) {
+  if (!dd || dd->n_levels < 1 || dd->n_levels > VRS_MAX_LEVELS || dd->in_ch < 1) return false;
+  if (dd->dtype != VRS_F32 && dd->dtype != VRS_BF16) return false;
+  if (n_crops < 1 || n_crops > VRS_MAX_CROPS || !crops) return false;
+  P->nd = dd->n_levels;
+  P->C = dd->in_ch;
+  P->dtype = dd->dtype;
+  P->n_crops = n_crops;
+  const int kstep = dd->dtype == VRS_BF16 ? 32 : 4;
+  const size_t esz = dd->dtype == VRS_BF16 ? 2 : 4;
+  size_t wo = 0;
+  for (int l = 0; l < P->nd; ++l) {
+    const int K = dd->width[l];
+    if (K < 1 || K > 16 * kDecMaxNT / 2) return false;
+    P->K[l] = K;
+    P->kp[l] = round_up(K, 16);
+  }
+  for (int l = 0; l < P->nd; ++l) {
+    P->cin[l] = P->C + (l + 1 < P->nd ? P->K[l + 1] : 0) + (l == 0 ? 3 : 0);
+    P->cin8[l] = round_up(P->cin[l], 8);
+    P->kpad[l] = round_up(9 * P->cin8[l], kstep);
+    P->w_off[l] = wo;
+    wo += (size_t)2 * P->K[l] * 9 * P->cin[l];
+    P->b_off[l] = wo;
+    wo += 2 * P->K[l];
+  }
+  P->head_w = wo;
+  P->head_b = wo + 3 * P->K[0];
+  const int unit = 1 << (P->nd - 1);
+  Carver c;
+  for (int l = 0; l < P->nd; ++l) {
+    long long he = 0;
+    for (int k = 0; k < n_crops; ++k) {
+      if (crops[k].size < unit || crops[k].size % unit) return false;
+      const long long s = crops[k].size >> l;
+      he += s * s;
+    }
+    P->h_elems[l] = he * P->kp[l];
+    P->pre_elems[l] = he * 2 * P->kp[l];
+    P->wp[l] = c.take((size_t)2 * P->kp[l] * P->kpad[l] * esz);
+    P->bp[l] = c.take((size_t)2 * P->kp[l] * 4);
+    P->h[l] = c.take((size_t)P->h_elems[l] * esz);
+    P->pre[l] = c.take((size_t)P->pre_elems[l] * 4);
+    // halo tile must fit the LDS a workgroup may use
+    const int th = dd->dtype == VRS_BF16 ? 16 : 8;
+    if ((size_t)(th + 2) * 18 * P->cin8[l] * esz > 64 * 1024) return false;
+  }
+  P->total = c.off;
+  return true;
+}
+
+static void level_args(const DecPlan& P, int l, const vrs_crop* crops, int n_crops,
+                       const KViews& kv, int levels, DecLevel* d, int* blocks) {
+  const int TH = P.dtype == VRS_BF16 ? 16 : 8;
+  d->C = P.C;
+  d->cin = P.cin[l];
+  d->cin8 = P.cin8[l];
+  d->kpad = P.kpad[l];
+  d->kp = P.kp[l];
+  d->nout = 2 * P.kp[l];
+  d->kn = l + 1 < P.nd ? P.K[l + 1] : 0;
+  d->kpn = l + 1 < P.nd ? P.kp[l + 1] : 0;
+  d->has_p = l == 0;
+  d->n_crops = n_crops;
+  d->W = kv.v[0].W;
+  d->H = kv.v[0].H;
+  d->width = P.K[l];
+  long long pyr = 0, h = 0, hn = 0, pre = 0;
+  int tb = 0;
+  for (int k = 0; k < n_crops; ++k) {
+    const int S = crops[k].size >> l;
+    const int tx = (S + 15) / 16, ty = (S + TH - 1) / TH;
+    d->tile_base[k] = tb;
+    d->tiles_x[k] = tx;
+    tb += tx * ty;
+    d->S[k] = S;
+    d->view[k] = crops[k].view;
+    d->x0[k] = crops[k].x0;
+    d->y0[k] = crops[k].y0;
+    long long lay = pyr;
+    for (int q = 0; q < l; ++q) lay += (long long)(crops[k].size >> q) * (crops[k].size >> q);
+    d->pyr_off[k] = lay * P.C;
+    for (int q = 0; q < levels; ++q) pyr += (long long)(crops[k].size >> q) * (crops[k].size >> q);
+    d->h_off[k] = h;
+    h += (long long)S * S * P.kp[l];
+    d->pre_off[k] = pre;
+    pre += (long long)S * S * 2 * P.kp[l];
+    if (l + 1 < P.nd) {
+      d->hn_off[k] = hn;
+      hn += (long long)(S / 2) * (S / 2) * P.kp[l + 1];
+    } else {
+      d->hn_off[k] = 0;
+    }
+  }
+  d->tile_base[n_crops] = tb;
+  *blocks = tb;
+}
+
+template <typename T>
+static hipError_t launch_conv(const DecLevel& d, int NT, int blocks, const float* pyr,
+                              const float* periph, const T* hn, const T* wp, const float* bp, T* h,
+                              float* pre, hipStream_t st) {
+  const int TH = DecTraits<T>::TH;
+  const size_t smem = (size_t)(TH + 2) * 18 * d.cin8 * sizeof(T);
+  switch (NT) {
+    case 2: hipLaunchKernelGGL((k_dec_conv<T, 2>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
+    case 4: hipLaunchKernelGGL((k_dec_conv<T, 4>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
+    case 6: hipLaunchKernelGGL((k_dec_conv<T, 6>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
+    default: hipLaunchKernelGGL((k_dec_conv<T, 8>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static vrs_status decode_impl(const DecPlan& P, const float* pyramid, int levels,
+                              const float* periph, const KViews& kv, const vrs_crop* crops,
+                              int n_crops, const float* weights, float* out, void* ws,
+                              bool keep_pre, hipStream_t st) {
+  for (int l = 0; l < P.nd; ++l) {
+    const long long total = (long long)2 * P.kp[l] * P.kpad[l];
+    const int blocks = (int)std::min<long long>(1024, (total + 255) / 256);
+    hipLaunchKernelGGL(k_dec_pack<T>, dim3(blocks), dim3(256), 0, st, weights + P.w_off[l],
+                       weights + P.b_off[l], P.K[l], P.cin[l], P.cin8[l], P.kp[l], P.kpad[l],
+                       at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]));
+    VRS_LAUNCH_CHECK();
+  }
+  DecLevel d;
+  for (int l = P.nd - 1; l >= 0; --l) {
+    int blocks = 0;
+    level_args(P, l, crops, n_crops, kv, levels, &d, &blocks);
+    const T* hn = l + 1 < P.nd ? at<T>(ws, P.h[l + 1]) : nullptr;
+    VRS_HIP_CHECK(launch_conv<T>(d, 2 * P.kp[l] / 16, blocks, pyramid, periph, hn,
+                                 at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]), at<T>(ws, P.h[l]),
+                                 keep_pre ? at<float>(ws, P.pre[l]) : nullptr, st));
+    if (l == 0) {
+      HeadArgs ha;
+      ha.n_crops = n_crops;
+      ha.kp = P.kp[0];
+      ha.K0 = P.K[0];
+      long long p = 0, o = 0;
+      for (int k = 0; k < n_crops; ++k) {
+        ha.S[k] = crops[k].size;
+        ha.pix_base[k] = p;
+        ha.out_base[k] = o;
+        ha.h_off[k] = d.h_off[k];
+        p += (long long)crops[k].size * crops[k].size;
+        o += 3LL * crops[k].size * crops[k].size;
+      }
+      ha.pix_base[n_crops] = p;
+      const int hb = (int)std::min<long long>(8192, (p + 255) / 256);
+      hipLaunchKernelGGL(k_dec_head<T>, dim3(hb), dim3(256), 0, st, ha, at<T>(ws, P.h[0]),
+                         weights + P.head_w, weights + P.head_b, out);
+      VRS_LAUNCH_CHECK();
+    }
+  }
+  return VRS_OK;
+}
+
+bool dec_plan_public(const vrs_decoder_desc* dd, const vrs_crop* crops, int n_crops, size_t* total) {
+  DecPlan P;
+  if (!dec_plan(dd, crops, n_crops, &P)) return false;
+  *total = P.total;
+  return true;
+}
+
+}  // namespace vrs
+
+using namespace vrs;
+
+extern "C" size_t vrs_decoder_workspace_size(const vrs_decoder_desc* dd, const vrs_crop* crops,
+                                             int n_crops) {
+  DecPlan P;
+  if (!dec_plan(dd, crops, n_crops, &P)) return 0;
+  return P.total;
+}
+
+extern "C" vrs_status vrs_decode_fovea(const float* pyramid, int levels,
+                                       const float* rgb_periphery, const vrs_view* views,
+                                       int n_views, const vrs_crop* crops, int n_crops,
+                                       const float* weights, const vrs_decoder_desc* dd,
+                                       float* fovea_rgb, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  DecPlan P;
+  KViews kv;
+  if (!make_views(views, n_views, &kv) || !dec_plan(dd, crops, n_crops, &P)) return VRS_EINVAL;
+  if (levels < P.nd || levels > VRS_MAX_LEVELS) return VRS_EINVAL;
+  if (!pyramid || !rgb_periphery || !weights || !fovea_rgb || !ws || ws_bytes < P.total)
+    return VRS_EINVAL;
+  if (dd->in_ch != 4) return VRS_EUNSUPPORTED;
+  for (int k = 0; k < n_crops; ++k) {
+    const vrs_crop& c = crops[k];
+    if (c.view < 0 || c.view >= n_views || c.x0 < 0 || c.y0 < 0 ||
+        c.x0 + c.size > views[c.view].width || c.y0 + c.size > views[c.view].height ||
+        c.size % (1 << (levels - 1)))
+      return VRS_EINVAL;
+  }
+  for (int i = 1; i < n_views; ++i)
+    if (views[i].width != views[0].width || views[i].height != views[0].height) return VRS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (P.dtype == VRS_BF16)
+    return decode_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
+                               fovea_rgb, ws, false, st);
+  return decode_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
+                            fovea_rgb, ws, false, st);
+}
