@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark: stereo foveated frames/s at 2016x2240 per eye on one MI355X.
+
+Workload (the full hybrid stereo frame): 500,000 Gaussians with SH degree 3
+for the periphery of both eyes (f = 1100, 64 mm IPD), 5,000,000 neural
+points, eight gaze crops per eye of uneven size (256..640 px, 4-layer
+pyramids, depth culled against the periphery), a 16/32/64/64 gated decoder
+in BF16 on the matrix cores, and the 64 px linear blend ring.  One step =
+one whole frame (periphery, splat, decoder, combination) of both eyes,
+replayed from a HIP graph with all inputs resident in HBM.
+
+Prints ONE JSON line (rank 0) with the frame rate, the roofline of the
+dominant kernel measured live with HIP events, the plain FP32 eager form of
+the same frame and the CPU reference timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, published
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense bf16, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_ms(frame, stage, steps):
+    """Average duration of one stage's kernels over `steps` eager frames,
+    from HIP events recorded by the library around the stage."""
+    import torch
+    from paper_2410_17932_amd import api
+    evs = []
+    tot = 0.0
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        api.trace_set(stage, a, b)
+        frame.run()
+        evs.append((a, b))
+    api.trace_set("off")
+    torch.cuda.synchronize()
+    for a, b in evs:
+        tot += a.elapsed_time(b)
+    return tot / steps
+
+
+def cpu_baseline(scene, budget_s=20.0):
+    """The CPU reference on a bounded sample of the frame, scaled to
+    frames/s: periphery of a random sample of tiles of both eyes, and the
+    whole foveal path (splat, decoder, combination) of one crop, each scaled
+    by its share of the frame."""
+    import numpy as np
+    import oracle
+    from paper_2410_17932_amd import synth
+    oracle.build(force=False)
+    g, p = scene["gaussians"], scene["points"]
+    views, crops, L = scene["views"], scene["crops"], scene["levels"]
+    V, D = synth.views_array(views), synth.views_dims(views)
+    t0 = time.perf_counter()
+    cov, op = oracle.bake(g["logscale"], g["quat"], g["logit"])
+    cov, op = cov.astype(np.float32), op.astype(np.float32)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 3, V, D)
+    t_proj = time.perf_counter() - t0
+    W, H = views[0].width, views[0].height
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    rng = np.random.default_rng(0)
+    n_tiles = 2 * tx * ty
+    sample = rng.choice(n_tiles, size=48, replace=False)
+    pix = []
+    for s in sample:
+        v, t = divmod(int(s), tx * ty)
+        x0, y0 = (t % tx) * 16, (t // tx) * 16
+        for yy in range(y0, min(y0 + 16, H)):
+            for xx in range(x0, min(x0 + 16, W)):
+                pix.append((v, xx, yy))
+    pix = np.array(pix, np.int32)
+    t0 = time.perf_counter()
+    oracle.render(rect, zb, rec, D, 16, pix=pix)
+    t_tiles = time.perf_counter() - t0
+    t_periph = t_proj + t_tiles * n_tiles / len(sample)
+    # one crop of the fovea, culled against depth from the reference itself
+    c = crops[0]
+    ci, cf = synth.crops_array([c])
+    cpix = np.array([(c.view, x, y) for y in range(c.y0, c.y0 + c.size)
+                     for x in range(c.x0, c.x0 + c.size)], np.int32)
+    pr = oracle.render(rect, zb, rec, D, 16, pix=cpix)
+    depth = np.zeros((len(views), H, W), np.float32)
+    tf = np.ones((len(views), H, W), np.float32)
+    depth[c.view, c.y0:c.y0 + c.size, c.x0:c.x0 + c.size] = pr["depth"].reshape(c.size, c.size)
+    tf[c.view, c.y0:c.y0 + c.size, c.x0:c.x0 + c.size] = pr["tfinal"].reshape(c.size, c.size)
+    t0 = time.perf_counter()
+    pyr = oracle.splat_points(p["pos"], p["radius"], p["feat"], V, D, ci, L, depth, tf)
+    periph = np.zeros((len(views), 3, H, W))
+    Fo = oracle.decode(ci, L, 4, pyr, periph, D, scene["decoder"]["widths"],
+                       synth.pack_decoder(scene["decoder"]).astype(np.float64))
+    t_crop = time.perf_counter() - t0
+    crop_px = sum(cc.size ** 2 for cc in crops)
+    t_fovea = t_crop * crop_px / (c.size ** 2)
+    t_frame = t_periph + t_fovea
+    return dict(value=1.0 / t_frame, unit="frames/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"periphery: projection of all Gaussians + {len(sample)} of {n_tiles} "
+                        f"16x16 tiles ({t_tiles:.1f} s); fovea: splat + FP64 decoder of crop 0 "
+                        f"({c.size}^2, {t_crop:.1f} s), scaled by tile and crop-pixel shares"),
+                seconds_per_frame=t_frame)
+
+
+def blend_work(frame):
+    """Algorithmic floating-point work of the last periphery blend: every
+    evaluation of a Gaussian at a pixel inside its rectangle costs 14 flops
+    (offset, quadratic form, exp, opacity, clamp, transmittance product) and
+    each blended contribution 11 more (colour and depth accumulation)."""
+    import torch
+    npix = frame.depth.numel()
+    evals = frame.rws.pixel_evals(npix).to(torch.int64).sum().item()
+    contrib = frame.ncontrib.to(torch.int64).sum().item()
+    return 14 * evals + 11 * contrib, evals, contrib
+
+
+def profile_pass(args):
+    """A short eager run for hardware-counter passes: two frames, then a
+    plain device copy of known size for the HBM byte-counter calibration."""
+    import torch
+    from paper_2410_17932_amd import api, synth
+    from paper_2410_17932_amd.frame import Frame
+    scene = synth.config(args.config)
+    fr = Frame(scene, decoder_dtype=api.VRS_BF16, tile=args.tile or 32)
+    for _ in range(2):
+        fr.run()
+    torch.cuda.synchronize()
+    x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log("profile pass done: frames 2, calibration copy 256 MiB")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--profile-pass", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2410_17932_amd import api, synth
+    from paper_2410_17932_amd.frame import Frame, PlainFrame
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    api.lib()
+    if args.profile_pass:
+        profile_pass(args)
+        return
+    t0 = time.perf_counter()
+    scene = synth.config(args.config)
+    log(f"scene generated in {time.perf_counter() - t0:.1f} s")
+    fr = Frame(scene, decoder_dtype=api.VRS_BF16)
+    tune = fr.autotune() if args.tile == 0 else (fr._plan(args.tile) or dict(tile=args.tile))
+    log(f"autotune: {tune}; pairs {fr.pairs}, fragments {fr.frags}")
+    fr.capture()
+    for _ in range(args.warmup):
+        fr.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fr.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    fps = args.steps / dt
+    assert fr.status() == 0, f"device status {fr.status()}"
+    log(f"graph replay: {ms:.3f} ms/frame, {fps:.1f} frames/s")
+    # per-stage kernel time over K eager frames (library-recorded HIP events
+    # on the frame's stream)
+    stages = {}
+    for st in ("gs_preprocess", "gs_depth_sort", "gs_emit", "gs_sort", "gs_blend", "splat",
+               "decoder", "composite"):
+        stages[st] = stage_ms(fr, st, args.steps)
+    log("stages ms:", json.dumps({k: round(v, 4) for k, v in stages.items()}))
+    flops, evals, contrib = blend_work(fr)
+    blend_s = stages["gs_blend"] * 1e-3
+    achieved = flops / blend_s / 1e12
+    roofline = dict(kernel="k_gs_blend (periphery front-to-back blend)", bound="alu",
+                    achieved=round(achieved, 3), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4), traffic=None,
+                    work=dict(flops=flops, evaluations=evals, contributions=contrib,
+                              ms=round(stages["gs_blend"], 4)))
+    # rasterizer HBM rate: the tile-pair sort (the periphery's HBM-bound
+    # stage): per pair and pass 16 B (key+id read and written), + 4 B/pair
+    # for the histogram read
+    sort_bytes = fr.pairs * (2 * 16 + 4)
+    sort_gbs = sort_bytes / (stages["gs_sort"] * 1e-3) / 1e9
+    result = dict(metric="stereo foveated frames/s @2016x2240/eye; rasterizer HBM GB/s vs peak",
+                  value=round(fps, 3), unit="frames/s", n_gpus=1, steps=args.steps,
+                  warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True,
+                  scaling="weak", vs_baseline=None, dtype="f32+bf16", data="synthetic",
+                  config=dict(workload=f"config {args.config}: stereo 2016x2240/eye, 500k "
+                              "Gaussians SH3, 5M neural points, 8 crops/eye 256..640 px, "
+                              "decoder 16/32/64/64 BF16, hipGraph replay",
+                              tile=tune["tile"], pairs=fr.pairs, fragments=fr.frags),
+                  roofline=roofline,
+                  rasterizer_hbm=dict(stage="periphery tile-pair sort", achieved=round(sort_gbs, 1),
+                                      peak=HBM_PEAK_GBS, unit="GB/s",
+                                      frac=round(sort_gbs / HBM_PEAK_GBS, 4)),
+                  stages_ms={k: round(v, 4) for k, v in stages.items()})
+    if not args.no_plain:
+        pf = PlainFrame(fr)
+        for _ in range(2):
+            pf.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = max(3, args.steps // 3)
+        for _ in range(k):
+            pf.run()
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) / k * 1e3
+        result["plain_fp32_eager"] = dict(ms_per_frame=round(pms, 4), frames_per_s=round(1e3 / pms, 3))
+        log(f"plain FP32 eager: {pms:.3f} ms/frame")
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(scene)
+        result["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb['seconds_per_frame']:.1f} s/frame on {cb['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

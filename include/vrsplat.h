@@ -164,10 +164,12 @@ vrs_status vrs_render_gaussians(const float* mean, const float* cov, const float
 /* Offsets (bytes into the workspace) of the render's intermediate results:
  * pair_count (uint32, device), tile lists as sorted Gaussian indices
  * (uint32 [max_pairs]), tile ranges (uint32 pairs [tiles][2] = begin, end
- * for tile index v*tiles_per_view + ty*tiles_x + tx).  For inspection and
- * tests. */
+ * for tile index v*tiles_per_view + ty*tiles_x + tx), and per pixel the
+ * number of Gaussians whose rectangle held the pixel and that the pixel
+ * evaluated before it stopped (uint32 [V][H][W]: the blend's work count).
+ * For inspection, tests and throughput accounting. */
 typedef struct {
-  size_t pair_count, sorted_ids, tile_ranges;
+  size_t pair_count, sorted_ids, tile_ranges, pixel_evals;
   int64_t tiles_x, tiles_y, tiles_total;
 } vrs_render_layout;
 vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const vrs_view* views,
@@ -294,6 +296,22 @@ vrs_status vrs_composite_frame_backward(const float* rgb_periphery, int n_views,
  * d_pred (may be NULL) accumulates scale * sign(pred - target) / n. */
 vrs_status vrs_l1_loss(const float* pred, const float* target, int64_t n, float* loss,
                        float* d_pred, float scale, void* stream);
+
+/* ------------------------------------------------------------- tracing
+ * Stage timing hook: while set, every call that runs `stage` records the
+ * caller's HIP event `start_event` on its stream right before the stage's
+ * first kernel and `stop_event` right after its last one (the events may be
+ * recorded many times; the caller reads the last pair).  stage 0 turns the
+ * hook off.  Process-wide setting, not thread-safe; meant for benchmarks
+ * and profilers.  Stages: 1 periphery blend, 2 periphery tile-pair sort,
+ * 3 periphery preprocess, 4 periphery pair emission, 5 whole point splat,
+ * 6 whole decoder, 7 composite, 8 periphery depth sort + scan. */
+enum {
+  VRS_TRACE_OFF = 0, VRS_TRACE_GS_BLEND = 1, VRS_TRACE_GS_SORT = 2, VRS_TRACE_GS_PREPROCESS = 3,
+  VRS_TRACE_GS_EMIT = 4, VRS_TRACE_SPLAT = 5, VRS_TRACE_DECODER = 6, VRS_TRACE_COMPOSITE = 7,
+  VRS_TRACE_GS_DEPTH_SORT = 8
+};
+vrs_status vrs_trace_set(int stage, void* start_event, void* stop_event);
 
 #ifdef __cplusplus
 }

@@ -56,7 +56,7 @@ def lib():
         l.orc_tile_lists.argtypes = [_i64, _int, _I, _int, _I, _U, _i64, _I, _L, _vp]
         l.orc_tile_lists.restype = _i64
         l.orc_render.argtypes = [_i64, _int, _I, _int, _I, _U, _D, _D, _i64, _vp,
-                                 _D, _D, _D, _I, _D]
+                                 _D, _D, _D, _I, _D, _I]
         l.orc_pyramid_pixels.argtypes = [_int, _I, _int]
         l.orc_pyramid_pixels.restype = _i64
         l.orc_point_lists.argtypes = [_i64, _F, _F, _int, _F, _I, _int, _I, _int, _vp, _vp,
@@ -159,16 +159,18 @@ def render(rect, zbits, rec, dims, tile=16, alpha_clamp=0.99, alpha_min=1 / 255,
     tf = np.zeros(npix)
     nc = np.zeros(npix, np.int32)
     mg = np.zeros(npix)
+    ev = np.zeros(npix, np.int32)
     lib().orc_render(n, nv, dims, tile, _c(rect, np.int32), _c(zbits, np.uint32),
-                     _c(rec, np.float64), opts, npix, _ptr(pp), rgb, depth, tf, nc, mg)
+                     _c(rec, np.float64), opts, npix, _ptr(pp), rgb, depth, tf, nc, mg, ev)
     if pix is not None:
-        return dict(rgb=rgb, depth=depth, tfinal=tf, ncontrib=nc, margin=mg)
-    out = dict(rgb=[], depth=[], tfinal=[], ncontrib=[], margin=[])
+        return dict(rgb=rgb, depth=depth, tfinal=tf, ncontrib=nc, margin=mg, evals=ev)
+    out = dict(rgb=[], depth=[], tfinal=[], ncontrib=[], margin=[], evals=[])
     o = 0
     for w, h in dims:
         k = int(w) * int(h)
         out["rgb"].append(rgb[o:o + k].reshape(h, w, 3).transpose(2, 0, 1))
-        for name, arr in (("depth", depth), ("tfinal", tf), ("ncontrib", nc), ("margin", mg)):
+        for name, arr in (("depth", depth), ("tfinal", tf), ("ncontrib", nc), ("margin", mg),
+                          ("evals", ev)):
             out[name].append(arr[o:o + k].reshape(h, w))
         o += k
     return {k: np.stack(v) for k, v in out.items()}

@@ -369,7 +369,9 @@ int64_t orc_tile_lists(int64_t n, int nv, const int* dims, int tile, const int32
 //   alpha < alpha_min;  T' = T (1 - alpha);  stop (without this Gaussian)
 //   if T' < t_min;  else C += rgb alpha T, D += tz alpha T, T = T'.
 // Outputs rgb = C + T bg, depth = D (Eq. 1 as printed), T_final = T,
-// ncontrib = number of Gaussians blended.  margin = smallest relative
+// ncontrib = number of Gaussians blended, evals = number of Gaussians whose
+// rectangle holds the pixel that it evaluated up to and including the one
+// that stopped it.  margin = smallest relative
 // distance of any threshold decision taken (alpha vs alpha_min, T' vs t_min)
 // to its threshold: the pixels where single-precision arithmetic may take
 // the other branch.
@@ -379,7 +381,7 @@ int64_t orc_tile_lists(int64_t n, int nv, const int* dims, int tile, const int32
 void orc_render(int64_t n, int nv, const int* dims, int tile, const int32_t* rect,
                 const uint32_t* zbits, const double* rec, const double* opts, int64_t npix,
                 const int32_t* pix, double* rgb, double* depth, double* tfinal,
-                int32_t* ncontrib, double* margin) {
+                int32_t* ncontrib, double* margin, int32_t* evals) {
   // enumerate requested pixels
   std::vector<int32_t> all;
   if (!pix) {
@@ -429,11 +431,12 @@ void orc_render(int64_t n, int nv, const int* dims, int tile, const int32_t* rec
     int tx_n = (dims[2 * v] + tile - 1) / tile;
     const auto& L = lists[tile_base[v] + (y / tile) * tx_n + x / tile];
     double T = 1, C[3] = {0, 0, 0}, D = 0, mg = INFINITY;
-    int cnt = 0;
+    int cnt = 0, ev = 0;
     for (const auto& e : L) {
       int64_t i = e.second;
       const int32_t* r = rect + ((int64_t)v * n + i) * 4;
       if (x < r[0] || x > r[2] || y < r[1] || y > r[3]) continue;
+      ++ev;
       const double* g = rec + ((int64_t)v * n + i) * 10;
       double dx = g[0] - (x + 0.5), dy = g[1] - (y + 0.5);
       double q = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
@@ -454,6 +457,7 @@ void orc_render(int64_t n, int nv, const int* dims, int tile, const int32_t* rec
     tfinal[k] = T;
     ncontrib[k] = cnt;
     margin[k] = mg;
+    if (evals) evals[k] = ev;
   }
 }
 

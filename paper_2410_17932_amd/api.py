@@ -54,7 +54,8 @@ class DecoderDesc(ctypes.Structure):
 
 class RenderLayout(ctypes.Structure):
     _fields_ = [("pair_count", ctypes.c_size_t), ("sorted_ids", ctypes.c_size_t),
-                ("tile_ranges", ctypes.c_size_t), ("tiles_x", ctypes.c_int64),
+                ("tile_ranges", ctypes.c_size_t), ("pixel_evals", ctypes.c_size_t),
+                ("tiles_x", ctypes.c_int64),
                 ("tiles_y", ctypes.c_int64), ("tiles_total", ctypes.c_int64)]
 
 
@@ -100,7 +101,11 @@ SIGNATURES = {
     "vrs_composite_frame_backward": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _int,
                                             _flt, _flt, _flt, _vp, _vp, _vp, _vp]),
     "vrs_l1_loss": (_int, [_vp, _vp, _i64, _vp, _vp, _flt, _vp]),
+    "vrs_trace_set": (_int, [_int, _vp, _vp]),
 }
+
+TRACE = dict(off=0, gs_blend=1, gs_sort=2, gs_preprocess=3, gs_emit=4, splat=5, decoder=6,
+             composite=7, gs_depth_sort=8)
 
 
 def lib():
@@ -234,6 +239,10 @@ class RenderWorkspace:
 
     def pair_count(self) -> int:
         return int(self.u32(self.layout.pair_count, 1).item())
+
+    def pixel_evals(self, npix):
+        """Per-pixel evaluation counts of the last blend (device tensor)."""
+        return self.u32(self.layout.pixel_evals, npix)
 
     def tile_lists(self):
         """(ranges [tiles][2] int64, sorted ids int64) on the host."""
@@ -399,6 +408,17 @@ def composite_frame_backward(periphery, fovea, crops, d_out, d_periphery=None, d
         len(crops), mode, ring, m, gamma, ptr(d_out, torch.float32), ptr(d_periphery),
         ptr(d_fovea), _stream())
     _check(code, "vrs_composite_frame_backward")
+
+
+def trace_set(stage: str, start=None, stop=None):
+    """Record torch.cuda.Event `start`/`stop` around a stage's kernels."""
+    code = TRACE[stage]
+    for e in (start, stop):
+        if e is not None and e.cuda_event == 0:
+            e.record()   # torch creates the HIP event on first record
+    a = ctypes.c_void_p(start.cuda_event) if start is not None else None
+    b = ctypes.c_void_p(stop.cuda_event) if stop is not None else None
+    _check(lib().vrs_trace_set(code, a, b), "vrs_trace_set")
 
 
 def l1_loss(pred, target, d_pred=None, scale=1.0):

@@ -262,9 +262,11 @@ extern "C" vrs_status vrs_composite_frame(const float* rgb_periphery, int n_view
   if (!rgb_periphery || !out || (n_crops > 0 && !fovea_rgb)) return VRS_EINVAL;
   const long long total = (long long)width * height * n_views;
   const int blocks = (int)std::min<long long>(16384, (total + 255) / 256);
+  trace_begin(VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
   hipLaunchKernelGGL(k_composite, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), a,
                      rgb_periphery, fovea_rgb, out);
   VRS_LAUNCH_CHECK();
+  trace_end(VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
   return VRS_OK;
 }
 

@@ -468,9 +468,14 @@ extern "C" vrs_status vrs_decode_fovea(const float* pyramid, int levels,
   for (int i = 1; i < n_views; ++i)
     if (views[i].width != views[0].width || views[i].height != views[0].height) return VRS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  trace_begin(VRS_TRACE_DECODER, st);
+  vrs_status r;
   if (P.dtype == VRS_BF16)
-    return decode_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
-                               fovea_rgb, ws, false, st);
-  return decode_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
+    r = decode_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
                             fovea_rgb, ws, false, st);
+  else
+    r = decode_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
+                           fovea_rgb, ws, false, st);
+  trace_end(VRS_TRACE_DECODER, st);
+  return r;
 }

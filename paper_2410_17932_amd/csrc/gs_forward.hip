@@ -20,7 +20,7 @@ namespace vrs {
 // ---------------------------------------------------------------- layout
 struct RenderWs {
   size_t rec, dkey0, dval0, dkey1, dval1, ntiles, offs, pair_count, pkey0, pval0, pkey1, pval1,
-      ranges, last, sort_tmp, scan_tmp, total;
+      ranges, last, evals, sort_tmp, scan_tmp, total;
   int64_t vn, tiles_x, tiles_y, tiles_total, npix;
   int tile_bits;
   bool pairs_in_1;
@@ -62,6 +62,7 @@ static bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->pval1 = c.take(mp * 4);
   L->ranges = c.take((size_t)L->tiles_total * 8);
   L->last = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
+  L->evals = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->tile_bits)));
   L->scan_tmp = c.take(scan_tmp_bytes(vn));
   L->total = c.off;
@@ -231,7 +232,8 @@ __global__ __launch_bounds__(BlendCfg<TILE>::BLOCK) void k_gs_blend(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
     const float4* __restrict__ rec, int64_t n, KViews views, GsOpt o, int64_t tiles_x,
     int64_t tiles_per_view, float* __restrict__ out_rgb, float* __restrict__ out_depth,
-    float* __restrict__ out_t, int32_t* __restrict__ out_n, uint32_t* __restrict__ out_last) {
+    float* __restrict__ out_t, int32_t* __restrict__ out_n, uint32_t* __restrict__ out_last,
+    uint32_t* __restrict__ out_evals) {
   using Cfg = BlendCfg<TILE>;
   constexpr int BLOCK = Cfg::BLOCK, PPT = Cfg::PPT;
   __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK];
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(BlendCfg<TILE>::BLOCK) void k_gs_blend(
   int px[PPT], py[PPT];
   float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
   int cnt[PPT];
-  uint32_t last[PPT];
+  uint32_t last[PPT], evals[PPT];
   bool done[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -255,6 +257,7 @@ __global__ __launch_bounds__(BlendCfg<TILE>::BLOCK) void k_gs_blend(
     T[q] = 1.0f; C0[q] = C1[q] = C2[q] = D[q] = 0.0f;
     cnt[q] = 0;
     last[q] = 0;
+    evals[q] = 0;
     done[q] = px[q] >= W || py[q] >= H;
   }
   const uint2 rg = ranges[tglob];
@@ -286,6 +289,7 @@ __global__ __launch_bounds__(BlendCfg<TILE>::BLOCK) void k_gs_blend(
         const uint32_t lo = __float_as_uint(c.z), hi = __float_as_uint(c.w);
         if (pxl < (lo & 0xffffu) || pxl > (hi & 0xffffu) || pyl < (lo >> 16) || pyl > (hi >> 16))
           continue;
+        ++evals[q];
         const float4 a = s_a[k];
         const float4 bq = s_b[k];
         const float dx = a.x - xc, dy = a.y - yc;
@@ -321,6 +325,7 @@ __global__ __launch_bounds__(BlendCfg<TILE>::BLOCK) void k_gs_blend(
     out_t[pix] = T[q];
     out_n[pix] = cnt[q];
     out_last[pix] = last[q];
+    out_evals[pix] = evals[q];
   }
 }
 
@@ -365,6 +370,7 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
   out->tiles_x = L.tiles_x;
   out->tiles_y = L.tiles_y;
   out->tiles_total = L.tiles_total;
+  out->pixel_evals = L.evals;
   return VRS_OK;
 }
 
@@ -375,7 +381,8 @@ static void launch_blend(const RenderWs& L, void* ws, int64_t n, const KViews& k
   const uint32_t* ids = at<uint32_t>(ws, L.pairs_in_1 ? L.pval1 : L.pval0);
   hipLaunchKernelGGL(k_gs_blend<TILE>, dim3((unsigned)L.tiles_total), dim3(BlendCfg<TILE>::BLOCK),
                      0, st, ranges, ids, at<float4>(ws, L.rec), n, kv, o, L.tiles_x,
-                     L.tiles_x * L.tiles_y, rgb, depth, tf, nc, at<uint32_t>(ws, L.last));
+                     L.tiles_x * L.tiles_y, rgb, depth, tf, nc, at<uint32_t>(ws, L.last),
+                     at<uint32_t>(ws, L.evals));
 }
 
 extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
@@ -401,11 +408,14 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   const int64_t vn = L.vn;
   uint32_t* pair_count = at<uint32_t>(ws, L.pair_count);
   if (vn > 0) {
+    trace_begin(VRS_TRACE_GS_PREPROCESS, st);
     hipLaunchKernelGGL(k_gs_preprocess, dim3(div_up(n, 256)), dim3(256), 0, st, mean, cov,
                        opacity, sh, sh_degree, n, kv, o, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
                        at<uint32_t>(ws, L.ntiles));
     VRS_LAUNCH_CHECK();
+    trace_end(VRS_TRACE_GS_PREPROCESS, st);
+    trace_begin(VRS_TRACE_GS_DEPTH_SORT, st);
     bool d1 = false;
     VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
                                  at<uint32_t>(ws, L.dkey1), at<uint32_t>(ws, L.dval1), nullptr, vn,
@@ -414,6 +424,8 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.ntiles), sorted_e, at<uint32_t>(ws, L.offs),
                                      pair_count, nullptr, vn, at<void>(ws, L.scan_tmp), dev_status,
                                      st));
+    trace_end(VRS_TRACE_GS_DEPTH_SORT, st);
+    trace_begin(VRS_TRACE_GS_EMIT, st);
     {
       const int blocks = std::max(1, div_up(max_pairs, 256 * kEmitPerThread));
       hipLaunchKernelGGL(k_gs_emit, dim3(blocks), dim3(256), 0, st, at<uint32_t>(ws, L.offs),
@@ -422,11 +434,14 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                          at<uint32_t>(ws, L.pval0), dev_status);
       VRS_LAUNCH_CHECK();
     }
+    trace_end(VRS_TRACE_GS_EMIT, st);
+    trace_begin(VRS_TRACE_GS_SORT, st);
     bool p1 = false;
     VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.pkey0), at<uint32_t>(ws, L.pval0),
                                  at<uint32_t>(ws, L.pkey1), at<uint32_t>(ws, L.pval1), pair_count,
                                  max_pairs, L.tile_bits, at<void>(ws, L.sort_tmp), dev_status, st,
                                  &p1));
+    trace_end(VRS_TRACE_GS_SORT, st);
   } else {
     VRS_HIP_CHECK(fill_u32(pair_count, 0, 1, st));
   }
@@ -438,11 +453,13 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                        L.tiles_total, at<uint2>(ws, L.ranges));
     VRS_LAUNCH_CHECK();
   }
+  trace_begin(VRS_TRACE_GS_BLEND, st);
   switch (o.tile) {
     case 8: launch_blend<8>(L, ws, n, kv, o, rgb, depth, t_final, n_contrib, st); break;
     case 16: launch_blend<16>(L, ws, n, kv, o, rgb, depth, t_final, n_contrib, st); break;
     default: launch_blend<32>(L, ws, n, kv, o, rgb, depth, t_final, n_contrib, st); break;
   }
   VRS_LAUNCH_CHECK();
+  trace_end(VRS_TRACE_GS_BLEND, st);
   return VRS_OK;
 }

@@ -330,6 +330,7 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   for (int k = 0; k < n_crops; ++k) a.view_mask |= 1u << crops[k].view;
   const int64_t vn = L.vn;
   uint32_t* frag_count = at<uint32_t>(ws, L.frag_count);
+  trace_begin(VRS_TRACE_SPLAT, st);
   if (L.pix_total > 0) {
     const int blocks = (int)std::min<int64_t>(4096, div_up(L.pix_total, 256));
     hipLaunchKernelGGL(k_zero4, dim3(blocks), dim3(256), 0, st,
@@ -338,6 +339,7 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   }
   if (vn == 0 || n_crops == 0) {
     VRS_HIP_CHECK(fill_u32(frag_count, 0, 1, st));
+    trace_end(VRS_TRACE_SPLAT, st);
     return VRS_OK;
   }
   uint32_t* nfrag = at<uint32_t>(ws, L.nfrag);
@@ -377,5 +379,6 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
                      frag_count, max_frags, feat, opacity, np, L.pix_total,
                      reinterpret_cast<float4*>(pyramid));
   VRS_LAUNCH_CHECK();
+  trace_end(VRS_TRACE_SPLAT, st);
   return VRS_OK;
 }

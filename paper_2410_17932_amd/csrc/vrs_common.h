@@ -99,6 +99,10 @@ hipError_t radix_sort_u64(uint32_t* k0, uint64_t* v0, uint32_t* k1, uint64_t* v1
                           const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
                           int32_t* status, hipStream_t st, bool* result_in_1);
 
+// Stage timing hook (vrs_trace_set).
+void trace_begin(int stage, hipStream_t st);
+void trace_end(int stage, hipStream_t st);
+
 // Fill n words with a value (graph-safe replacement for memset).
 hipError_t fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st);
 

@@ -1,0 +1,196 @@
+"""Per-frame runtime of the foveated hybrid renderer (Fig. 5 of the paper):
+periphery P and depth (Sec. 3.2) -> gaze crops -> neural-point pyramid with
+depth culling (Sec. 3.3) -> decoder -> combination (Sec. 3.4).
+
+Two forms of the same frame:
+  * batched: both eyes in one periphery call, every crop of both eyes in one
+    splat call and one decoder launch per level, BF16 decoder; the whole
+    frame is captured once into a HIP graph and replayed;
+  * plain: eager, one periphery call per eye, one splat and one FP32 decoder
+    call per crop.
+Workspaces are sized once by a counting pass (no host read-back inside a
+frame); device-side overflow is reported through the status words.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import api
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t.to(dtype) if dtype is not None else t).cuda()
+
+
+class Frame:
+    def __init__(self, scene: dict, decoder_dtype: int = api.VRS_BF16, tile: int = 16,
+                 mode: int = api.BLEND_LINEAR, ring: float = 64.0, m: float = 0.75,
+                 gamma: float = 0.2, cull: bool = True, pair_margin: float = 1.10,
+                 frag_margin: float = 1.25):
+        g, p = scene["gaussians"], scene["points"]
+        self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
+        self.sh_degree = g["sh_degree"]
+        self.mode, self.ring, self.m, self.gamma, self.cull = mode, ring, m, gamma, cull
+        self.decoder_dtype = decoder_dtype
+        self.widths = scene["decoder"]["widths"]
+        self.raster = dict(scene["raster"], tile=tile)
+        # primitives resident in HBM; attributes baked once (Sec. 4 "Inference")
+        self.mean = _dev(g["mean"])
+        self.sh = _dev(g["sh"])
+        self.cov, self.opacity = api.bake_gaussians(_dev(g["logscale"]), _dev(g["quat"]),
+                                                    _dev(g["logit"]))
+        self.pos, self.radius = _dev(p["pos"]), _dev(p["radius"])
+        self.feat = _dev(p["feat"].view(np.int16))
+        from .synth import pack_decoder
+        self.weights = _dev(pack_decoder(scene["decoder"]))
+        self.n, self.np = g["n"], p["n"]
+        self.pair_margin, self.frag_margin = pair_margin, frag_margin
+        self._plan(tile)
+
+    # ------------------------------------------------------------ planning
+    def _plan(self, tile):
+        self.raster["tile"] = tile
+        self.opts = api.make_opts(**self.raster)
+        V, H, W = len(self.views), self.views[0].height, self.views[0].width
+        dev = self.mean.device
+        self.rgb = torch.empty((V, 3, H, W), device=dev)
+        self.depth = torch.empty((V, H, W), device=dev)
+        self.tfinal = torch.empty((V, H, W), device=dev)
+        self.ncontrib = torch.empty((V, H, W), device=dev, dtype=torch.int32)
+        self.out = torch.empty((V, 3, H, W), device=dev)
+        self.r_out = dict(rgb=self.rgb, depth=self.depth, tfinal=self.tfinal, ncontrib=self.ncontrib)
+        # counting pass: capacity 1 computes the totals on the device
+        ws = api.RenderWorkspace(self.n, self.views, self.opts, 1)
+        api.render_gaussians(self.mean, self.cov, self.opacity, self.sh, self.sh_degree,
+                             self.views, self.opts, ws, self.r_out)
+        self.pairs = ws.pair_count()
+        self.rws = api.RenderWorkspace(self.n, self.views, self.opts,
+                                       int(self.pairs * self.pair_margin) + 4096)
+        del ws
+        api.render_gaussians(self.mean, self.cov, self.opacity, self.sh, self.sh_degree,
+                             self.views, self.opts, self.rws, self.r_out)
+        P = api.pyramid_pixels(self.crops, self.levels)
+        self.pyramid = torch.empty((P, 4), device=dev)
+        sws = api.SplatWorkspace(self.np, self.views, self.crops, self.levels, 1)
+        self._splat(sws)
+        self.frags = sws.frag_count()
+        del sws
+        self.sws = api.SplatWorkspace(self.np, self.views, self.crops, self.levels,
+                                      int(self.frags * self.frag_margin) + 4096)
+        self.dws = api.DecoderWorkspace(self.widths, self.crops, self.decoder_dtype)
+        self.fovea = torch.empty(api.fovea_elements(self.crops), device=dev)
+        torch.cuda.synchronize()
+        self.graph = None
+
+    def _splat(self, sws):
+        api.splat_points(self.pos, self.radius, self.feat, None, self.views, self.crops,
+                         self.levels, self.depth if self.cull else None,
+                         self.tfinal if self.cull else None, sws, pyramid=self.pyramid)
+
+    # --------------------------------------------------------------- frame
+    def run(self):
+        """Enqueue one batched frame on the current stream."""
+        api.render_gaussians(self.mean, self.cov, self.opacity, self.sh, self.sh_degree,
+                             self.views, self.opts, self.rws, self.r_out)
+        self._splat(self.sws)
+        api.decode_fovea(self.pyramid, self.levels, self.rgb, self.views, self.crops,
+                         self.weights, self.dws, out=self.fovea)
+        api.composite_frame(self.rgb, self.fovea, self.crops, self.mode, self.ring, self.m,
+                            self.gamma, out=self.out)
+        return self.out
+
+    def capture(self):
+        """Capture run() into a HIP graph (warm-up on a side stream first)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        torch.cuda.synchronize()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+        return self.out
+
+    def status(self) -> int:
+        return max(int(self.rws.status.item()), int(self.sws.status.item()))
+
+    # ----------------------------------------------------------- autotune
+    def autotune(self, tiles=(8, 16, 32), reps: int = 5) -> dict:
+        """Time the periphery for each tile size on the live scene and keep
+        the fastest (results are tile-size invariant)."""
+        times = {}
+        for t in tiles:
+            self._plan(t)
+            for _ in range(2):
+                self.run()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                self.run()
+            b.record()
+            torch.cuda.synchronize()
+            times[t] = a.elapsed_time(b) / reps
+        best = min(times, key=times.get)
+        self._plan(best)
+        return dict(tile=best, ms=times)
+
+
+class PlainFrame:
+    """The plain FP32 form of the same frame: eager, one periphery call per
+    eye, one splat and one FP32 decoder call per crop, one combination."""
+
+    def __init__(self, batched: Frame):
+        b = batched
+        self.b = b
+        dev = b.mean.device
+        self.opts = b.opts
+        self.rws, self.sws, self.dws, self.pyr, self.fov = [], [], [], [], []
+        H, W = b.views[0].height, b.views[0].width
+        self.rgb = torch.empty_like(b.rgb)
+        self.depth = torch.empty_like(b.depth)
+        self.tfinal = torch.empty_like(b.tfinal)
+        self.nc = torch.empty_like(b.ncontrib)
+        for v in range(len(b.views)):
+            ws = api.RenderWorkspace(b.n, [b.views[v]], self.opts, 1)
+            o = dict(rgb=self.rgb[v:v + 1], depth=self.depth[v:v + 1],
+                     tfinal=self.tfinal[v:v + 1], ncontrib=self.nc[v:v + 1])
+            api.render_gaussians(b.mean, b.cov, b.opacity, b.sh, b.sh_degree, [b.views[v]],
+                                 self.opts, ws, o)
+            self.rws.append(api.RenderWorkspace(b.n, [b.views[v]], self.opts,
+                                                int(ws.pair_count() * 1.1) + 4096))
+        for c in b.crops:
+            self.pyr.append(torch.empty((api.pyramid_pixels([c], b.levels), 4), device=dev))
+            self.sws.append(api.SplatWorkspace(b.np, b.views, [c], b.levels,
+                                               int(b.frags * 1.25) + 4096))
+            self.dws.append(api.DecoderWorkspace(b.widths, [c], api.VRS_F32))
+            self.fov.append(torch.empty(3 * c.size * c.size, device=dev))
+        self.fovea = torch.empty_like(b.fovea)
+        self.out = torch.empty_like(b.out)
+
+    def run(self):
+        b = self.b
+        for v in range(len(b.views)):
+            o = dict(rgb=self.rgb[v:v + 1], depth=self.depth[v:v + 1],
+                     tfinal=self.tfinal[v:v + 1], ncontrib=self.nc[v:v + 1])
+            api.render_gaussians(b.mean, b.cov, b.opacity, b.sh, b.sh_degree, [b.views[v]],
+                                 self.opts, self.rws[v], o)
+        off = 0
+        for k, c in enumerate(b.crops):
+            api.splat_points(b.pos, b.radius, b.feat, None, b.views, [c], b.levels,
+                             self.depth if b.cull else None, self.tfinal if b.cull else None,
+                             self.sws[k], pyramid=self.pyr[k])
+            api.decode_fovea(self.pyr[k], b.levels, self.rgb, b.views, [c], b.weights,
+                             self.dws[k], out=self.fovea[off:off + 3 * c.size * c.size])
+            off += 3 * c.size * c.size
+        api.composite_frame(self.rgb, self.fovea, b.crops, b.mode, b.ring, b.m, b.gamma,
+                            out=self.out)
+        return self.out

@@ -42,6 +42,10 @@ def test_render_parity(case):
     assert int(ws.status.item()) == 0
     print(case, "ambiguous pixels:", check_render(o, gpu))
     _lists_equal(ws, rect, zb, views, raster["tile"])
+    # the blend's work count is the definition's: evaluations up to the stop
+    ev = ws.pixel_evals(o["evals"].size).cpu().numpy().reshape(o["evals"].shape)
+    ok = o["margin"] >= 1e-4
+    assert np.array_equal(ev[ok], o["evals"][ok])
 
 
 @pytest.mark.parametrize("tile", [8, 32])
@@ -79,3 +83,17 @@ def test_empty_scene_is_background():
     for ch, b in enumerate((0.1, 0.2, 0.3)):
         assert np.allclose(gpu["rgb"][:, ch], b)
     assert (gpu["tfinal"] == 1).all() and (gpu["ncontrib"] == 0).all()
+
+
+def test_bake_parity():
+    import torch
+    from gpu_helpers import dev
+    rng = np.random.default_rng(9)
+    g = synth.gaussians(rng, 5000, 0)
+    cov_o, op_o = oracle.bake(g["logscale"], g["quat"], g["logit"])
+    cov, op = api.bake_gaussians(dev(g["logscale"]), dev(g["quat"]), dev(g["logit"]))
+    torch.cuda.synchronize()
+    # single precision: error relative to the Gaussian's largest variance
+    scale = cov_o[[0, 3, 5]].max(0)
+    assert (np.abs(cov.cpu().numpy() - cov_o) <= 1e-5 * scale[None]).all()
+    np.testing.assert_allclose(op.cpu().numpy(), op_o, rtol=1e-6, atol=1e-7)
