@@ -62,6 +62,9 @@ def lib():
         l.orc_point_lists.argtypes = [_i64, _F, _F, _int, _F, _I, _int, _I, _int, _vp, _vp,
                                       _flt, _flt, _L, _vp]
         l.orc_point_lists.restype = _i64
+        l.orc_point_frags.argtypes = [_i64, _F, _F, _int, _F, _I, _int, _I, _int, _vp, _vp,
+                                      _flt, _flt, _vp]
+        l.orc_point_frags.restype = _i64
         l.orc_splat_points.argtypes = [_i64, _F, _F, _H, _vp, _int, _int, _F, _I, _int, _I,
                                        _int, _vp, _vp, _flt, _flt, _D]
         l.orc_decode.argtypes = [_int, _I, _int, _int, _D, _D, _I, _int, _I, _D, _D]
@@ -197,6 +200,23 @@ def point_lists(pos, radius, views, dims, crops_i, levels, depth=None, tfinal=No
     ids = np.zeros(max(cnt, 1), np.int32)
     l.orc_point_lists(*args, _ptr(ids))
     return off, ids[:cnt]
+
+
+def point_frags(pos, radius, views, dims, crops_i, levels, depth=None, tfinal=None,
+                cov_min=0.5, slack=1.05):
+    """Fragments in blend order with their integer decisions:
+    int64 [nfrag][8] = key, point id, crop, layer, ix, iy, l0, two."""
+    crops_i = _c(crops_i, np.int32)
+    d = None if depth is None else _c(depth, np.float32)
+    t = None if tfinal is None else _c(tfinal, np.float32)
+    args = (pos.shape[1], _c(pos, np.float32), _c(radius, np.float32), views.shape[0],
+            _c(views, np.float32), _c(dims, np.int32), crops_i.shape[0], crops_i, levels,
+            _ptr(d), _ptr(t), cov_min, slack)
+    l = lib()
+    cnt = l.orc_point_frags(*args, None)
+    out = np.zeros((max(cnt, 1), 8), np.int64)
+    l.orc_point_frags(*args, _ptr(out))
+    return out[:cnt]
 
 
 def splat_points(pos, radius, feat, views, dims, crops_i, levels, depth=None, tfinal=None,

@@ -491,6 +491,7 @@ struct Frag {
   uint32_t zb;
   int32_t id;
   double w;
+  int32_t crop, layer, ix, iy, l0, two;  // the integer decisions behind w
 };
 
 static void point_fragments(int64_t np, const float* pos, const float* radius, int nv,
@@ -580,6 +581,7 @@ static void point_fragments(int64_t np, const float* pos, const float* radius, i
                 fr.zb = zb;
                 fr.id = (int32_t)i;
                 fr.w = wl * wb;
+                fr.crop = k; fr.layer = l; fr.ix = ix; fr.iy = iy; fr.l0 = l0; fr.two = two;
                 part[tid].push_back(fr);
               }
           }
@@ -623,6 +625,26 @@ int64_t orc_point_lists(int64_t np, const float* pos, const float* radius, int n
   for (int64_t p = 0; p < P; ++p) offsets[p + 1] += offsets[p];
   if (ids)
     for (size_t k = 0; k < fr.size(); ++k) ids[k] = fr[k].id;
+  return (int64_t)fr.size();
+}
+
+// Fragments in blend order with their integer decisions:
+// out [nfrag][8] = key, point id, crop, layer, ix, iy, l0, two.
+// Returns the count; out may be null (count only).
+int64_t orc_point_frags(int64_t np, const float* pos, const float* radius, int nv,
+                        const float* views, const int* dims, int ncrops, const int32_t* crops,
+                        int L, const float* depth, const float* tfinal, float cov_min,
+                        float slack, int64_t* out) {
+  std::vector<Frag> fr;
+  std::vector<int64_t> base;
+  point_fragments(np, pos, radius, nv, views, dims, ncrops, crops, L, depth, tfinal, cov_min,
+                  slack, fr, base);
+  if (out)
+    for (size_t k = 0; k < fr.size(); ++k) {
+      int64_t* o = out + 8 * k;
+      o[0] = fr[k].key; o[1] = fr[k].id; o[2] = fr[k].crop; o[3] = fr[k].layer;
+      o[4] = fr[k].ix; o[5] = fr[k].iy; o[6] = fr[k].l0; o[7] = fr[k].two;
+    }
   return (int64_t)fr.size();
 }
 
