@@ -261,7 +261,8 @@ struct DecPlan {
   size_t w_off[VRS_MAX_LEVELS], b_off[VRS_MAX_LEVELS];   // offsets into the float weights
   size_t head_w, head_b;
   // workspace (bytes)
-  size_t wp[VRS_MAX_LEVELS], bp[VRS_MAX_LEVELS], h[VRS_MAX_LEVELS], pre[VRS_MAX_LEVELS], total;
+  size_t wp[VRS_MAX_LEVELS], bp[VRS_MAX_LEVELS], h[VRS_MAX_LEVELS], pre[VRS_MAX_LEVELS],
+      dh[VRS_MAX_LEVELS], total;
   long long h_elems[VRS_MAX_LEVELS], pre_elems[VRS_MAX_LEVELS];
   int n_crops;
   long long head_pix;
@@ -312,6 +313,7 @@ static bool dec_plan(const vrs_decoder_desc* dd, const vrs_crop* crops, int n_cr
     P->bp[l] = c.take((size_t)2 * P->kp[l] * 4);
     P->h[l] = c.take((size_t)P->h_elems[l] * esz);
     P->pre[l] = c.take((size_t)P->pre_elems[l] * 4);
+    P->dh[l] = c.take((size_t)P->h_elems[l] * 4);
     // halo tile must fit the LDS a workgroup may use
     const int th = dd->dtype == VRS_BF16 ? 16 : 8;
     if ((size_t)(th + 2) * 18 * P->cin8[l] * esz > 64 * 1024) return false;
@@ -478,4 +480,288 @@ extern "C" vrs_status vrs_decode_fovea(const float* pyramid, int levels,
                            fovea_rgb, ws, false, st);
   trace_end(VRS_TRACE_DECODER, st);
   return r;
+}
+
+// ------------------------------------------------------------- backward
+namespace vrs {
+
+// head: dh0 = W_o^T dF, dW_o += dF h0^T, db_o += sum dF (block sums, atomics)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dec_head_bwd(HeadArgs a, const T* __restrict__ h0,
+                                                      const float* __restrict__ wo,
+                                                      const float* __restrict__ dF,
+                                                      float* __restrict__ dh0,
+                                                      float* __restrict__ dwo,
+                                                      float* __restrict__ dbo) {
+  __shared__ float s_acc[3 * 64 + 3];
+  for (int e = threadIdx.x; e < 3 * a.K0 + 3; e += blockDim.x) s_acc[e] = 0.0f;
+  __syncthreads();
+  const long long npix = a.pix_base[a.n_crops];
+  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (p < npix) {
+    int k = 0;
+    while (k + 1 < a.n_crops && p >= a.pix_base[k + 1]) ++k;
+    const long long q = p - a.pix_base[k];
+    const long long plane = (long long)a.S[k] * a.S[k];
+    const float g[3] = {dF[a.out_base[k] + q], dF[a.out_base[k] + plane + q],
+                        dF[a.out_base[k] + 2 * plane + q]};
+    const T* h = h0 + a.h_off[k] + q * a.kp;
+    float* dh = dh0 + a.h_off[k] + q * a.kp;
+    for (int c = 0; c < a.K0; ++c) {
+      const float hv = to_f(h[c]);
+      dh[c] += wo[c] * g[0] + wo[a.K0 + c] * g[1] + wo[2 * a.K0 + c] * g[2];
+      if (dwo) {
+        atomicAdd(&s_acc[c], g[0] * hv);
+        atomicAdd(&s_acc[a.K0 + c], g[1] * hv);
+        atomicAdd(&s_acc[2 * a.K0 + c], g[2] * hv);
+      }
+    }
+    if (dbo)
+      for (int ch = 0; ch < 3; ++ch) atomicAdd(&s_acc[3 * a.K0 + ch], g[ch]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * a.K0 + 3; e += blockDim.x) {
+    if (e < 3 * a.K0 && dwo) atomicAdd(&dwo[e], s_acc[e]);
+    if (e >= 3 * a.K0 && dbo) atomicAdd(&dbo[e - 3 * a.K0], s_acc[e]);
+  }
+}
+
+// gate: h = ELU(f) sigmoid(g); pre-activations overwritten by their grads
+__global__ void k_dec_gate_bwd(float* __restrict__ pre, const float* __restrict__ dh,
+                               long long npix, int kp, int K) {
+  const long long total = npix * kp;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long p = e / kp;
+    const int ch = (int)(e - p * kp);
+    const int t = ch / 16, j = ch % 16;
+    float* pf = pre + p * 2 * kp + t * 32 + j;
+    float* pg = pf + 16;
+    if (ch >= K) { *pf = 0.0f; *pg = 0.0f; continue; }
+    const float f = *pf, g = *pg, d = dh[p * kp + ch];
+    const float sg = 1.0f / (1.0f + expf(-g));
+    const float el = f > 0.0f ? f : expm1f(f);
+    const float del = f > 0.0f ? 1.0f : el + 1.0f;
+    *pf = d * sg * del;
+    *pg = d * el * sg * (1.0f - sg);
+  }
+}
+
+// transposed convolution: gradient of level l's input, routed to its
+// sources (pyramid layer, upsampled coarser output, periphery crop)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dec_dgrad(DecLevel d, const float* __restrict__ dpre,
+                                                   const float* __restrict__ w, float* __restrict__ dpyr,
+                                                   float* __restrict__ dhn, float* __restrict__ dper) {
+  const int cin = d.cin;
+  // global pixel index over all crops of this level
+  long long pbase[VRS_MAX_CROPS + 1];
+  pbase[0] = 0;
+  for (int k = 0; k < d.n_crops; ++k) pbase[k + 1] = pbase[k] + (long long)d.S[k] * d.S[k];
+  const long long n_elem = pbase[d.n_crops] * cin;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n_elem;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long p = e / cin;
+    const int c = (int)(e - p * cin);
+    int k = 0;
+    while (k + 1 < d.n_crops && p >= pbase[k + 1]) ++k;
+    const int S = d.S[k];
+    const long long q = p - pbase[k];
+    const int y = (int)(q / S), x = (int)(q - (long long)y * S);
+    const float* dp = dpre + d.pre_off[k];
+    float acc = 0.0f;
+    for (int ky = 0; ky < 3; ++ky) {
+      const int oy = y - ky + 1;
+      if (oy < 0 || oy >= S) continue;
+      for (int kx = 0; kx < 3; ++kx) {
+        const int ox = x - kx + 1;
+        if (ox < 0 || ox >= S) continue;
+        const float* g = dp + ((long long)oy * S + ox) * d.nout;
+        const int tap = ky * 3 + kx;
+        for (int ch = 0; ch < d.width; ++ch) {
+          const int t = ch / 16, j = ch % 16;
+          acc += g[t * 32 + j] * w[((long long)ch * 9 + tap) * cin + c];
+          acc += g[t * 32 + 16 + j] * w[((long long)(d.width + ch) * 9 + tap) * cin + c];
+        }
+      }
+    }
+    if (c < d.C) {
+      if (dpyr) dpyr[d.pyr_off[k] + q * d.C + c] += acc;
+    } else if (c < d.C + d.kn) {
+      const int cc = c - d.C;
+      const int Sn = S >> 1;
+      const float sx = 0.5f * (float)x - 0.25f, sy = 0.5f * (float)y - 0.25f;
+      const float fx0 = floorf(sx), fy0 = floorf(sy);
+      const float fx = sx - fx0, fy = sy - fy0;
+      int xa = (int)fx0, ya = (int)fy0, xb = xa + 1, yb = ya + 1;
+      xa = xa < 0 ? 0 : (xa > Sn - 1 ? Sn - 1 : xa);
+      xb = xb < 0 ? 0 : (xb > Sn - 1 ? Sn - 1 : xb);
+      ya = ya < 0 ? 0 : (ya > Sn - 1 ? Sn - 1 : ya);
+      yb = yb < 0 ? 0 : (yb > Sn - 1 ? Sn - 1 : yb);
+      float* h = dhn + d.hn_off[k];
+      atomicAdd(&h[((long long)ya * Sn + xa) * d.kpn + cc], acc * (1.0f - fy) * (1.0f - fx));
+      atomicAdd(&h[((long long)ya * Sn + xb) * d.kpn + cc], acc * (1.0f - fy) * fx);
+      atomicAdd(&h[((long long)yb * Sn + xa) * d.kpn + cc], acc * fy * (1.0f - fx));
+      atomicAdd(&h[((long long)yb * Sn + xb) * d.kpn + cc], acc * fy * fx);
+    } else if (d.has_p && dper) {
+      const int cc = c - d.C - d.kn;
+      const long long plane = (long long)d.W * d.H;
+      atomicAdd(&dper[(long long)d.view[k] * 3 * plane + cc * plane +
+                      (long long)(d.y0[k] + y) * d.W + (d.x0[k] + x)],
+                acc);
+    }
+  }
+}
+
+// weight gradient over 8x8 output tiles: dW[row][tap][c] += sum_p dpre[p][row] x[p+tap][c]
+template <typename T>
+__global__ __launch_bounds__(256) void k_dec_wgrad(DecLevel d, const float* __restrict__ pyr,
+                                                   const float* __restrict__ periph,
+                                                   const T* __restrict__ hnext,
+                                                   const float* __restrict__ dpre,
+                                                   float* __restrict__ dw, float* __restrict__ db) {
+  extern __shared__ __align__(16) char smem[];
+  const int cin = d.cin, K = d.width;
+  float* sx = reinterpret_cast<float*>(smem);          // [10*10][cin]
+  float* sg = sx + 100 * cin;                          // [64][2K]
+  int b = blockIdx.x, k = 0;
+  while (k + 1 < d.n_crops && b >= d.tile_base[k + 1]) ++k;
+  const int S = d.S[k];
+  const int tl = b - d.tile_base[k], tpr = (S + 7) / 8;
+  const int oy = (tl / tpr) * 8, ox = (tl % tpr) * 8;
+  for (int e = threadIdx.x; e < 100 * cin; e += blockDim.x) {
+    const int pix = e / cin, c = e - pix * cin;
+    const int y = oy + pix / 10 - 1, x = ox + pix % 10 - 1;
+    float v = 0.0f;
+    if (y >= 0 && y < S && x >= 0 && x < S) v = dec_input<T>(d, k, S, y, x, c, pyr, periph, hnext);
+    sx[e] = v;
+  }
+  for (int e = threadIdx.x; e < 64 * 2 * K; e += blockDim.x) {
+    const int pix = e / (2 * K), r = e - pix * 2 * K;
+    const int y = oy + pix / 8, x = ox + pix % 8;
+    float v = 0.0f;
+    if (y < S && x < S) {
+      const int ch = r < K ? r : r - K, half = r < K ? 0 : 1;
+      v = dpre[d.pre_off[k] + ((long long)y * S + x) * d.nout + (ch / 16) * 32 + half * 16 + ch % 16];
+    }
+    sg[e] = v;
+  }
+  __syncthreads();
+  const int nw = 2 * K * 9 * cin;
+  for (int e = threadIdx.x; e < nw; e += blockDim.x) {
+    const int row = e / (9 * cin), rem = e - row * 9 * cin;
+    const int tap = rem / cin, c = rem - tap * cin;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    float acc = 0.0f;
+    for (int pix = 0; pix < 64; ++pix) {
+      const int py = pix / 8, px = pix % 8;
+      acc += sg[pix * 2 * K + row] * sx[((py + ky) * 10 + px + kx) * cin + c];
+    }
+    if (acc != 0.0f) atomicAdd(&dw[e], acc);
+  }
+  for (int r = threadIdx.x; r < 2 * K; r += blockDim.x) {
+    float acc = 0.0f;
+    for (int pix = 0; pix < 64; ++pix) acc += sg[pix * 2 * K + r];
+    if (acc != 0.0f) atomicAdd(&db[r], acc);
+  }
+}
+
+template <typename T>
+static vrs_status decode_bwd_impl(const DecPlan& P, const float* pyramid, int levels,
+                                  const float* periph, const KViews& kv, const vrs_crop* crops,
+                                  int n_crops, const float* weights, const float* d_fovea,
+                                  float* d_pyr, float* d_per, float* d_w, void* ws,
+                                  hipStream_t st) {
+  // recompute every level's pre-activations (the forward's h_l stay valid)
+  for (int l = P.nd - 1; l >= 0; --l) {
+    DecLevel d;
+    int blocks = 0;
+    level_args(P, l, crops, n_crops, kv, levels, &d, &blocks);
+    const T* hn = l + 1 < P.nd ? at<T>(ws, P.h[l + 1]) : nullptr;
+    VRS_HIP_CHECK(launch_conv<T>(d, 2 * P.kp[l] / 16, blocks, pyramid, periph, hn,
+                                 at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]), at<T>(ws, P.h[l]),
+                                 at<float>(ws, P.pre[l]), st));
+    VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, P.dh[l]), 0u, P.h_elems[l], st));
+  }
+  // head
+  {
+    HeadArgs ha;
+    ha.n_crops = n_crops;
+    ha.kp = P.kp[0];
+    ha.K0 = P.K[0];
+    long long p = 0, o = 0;
+    DecLevel d0;
+    int b0 = 0;
+    level_args(P, 0, crops, n_crops, kv, levels, &d0, &b0);
+    for (int k = 0; k < n_crops; ++k) {
+      ha.S[k] = crops[k].size;
+      ha.pix_base[k] = p;
+      ha.out_base[k] = o;
+      ha.h_off[k] = d0.h_off[k];
+      p += (long long)crops[k].size * crops[k].size;
+      o += 3LL * crops[k].size * crops[k].size;
+    }
+    ha.pix_base[n_crops] = p;
+    hipLaunchKernelGGL(k_dec_head_bwd<T>, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, ha,
+                       at<T>(ws, P.h[0]), weights + P.head_w, d_fovea, at<float>(ws, P.dh[0]),
+                       d_w ? d_w + P.head_w : nullptr, d_w ? d_w + P.head_b : nullptr);
+    VRS_LAUNCH_CHECK();
+  }
+  for (int l = 0; l < P.nd; ++l) {
+    DecLevel d;
+    int blocks = 0;
+    level_args(P, l, crops, n_crops, kv, levels, &d, &blocks);
+    long long npix = 0;
+    for (int k = 0; k < n_crops; ++k) npix += (long long)d.S[k] * d.S[k];
+    const int gb = (int)std::min<long long>(16384, (npix * P.kp[l] + 255) / 256);
+    hipLaunchKernelGGL(k_dec_gate_bwd, dim3(gb), dim3(256), 0, st, at<float>(ws, P.pre[l]),
+                       at<float>(ws, P.dh[l]), npix, P.kp[l], P.K[l]);
+    VRS_LAUNCH_CHECK();
+    const int dbk = (int)std::min<long long>(16384, (npix * P.cin[l] + 255) / 256);
+    hipLaunchKernelGGL(k_dec_dgrad<T>, dim3(dbk), dim3(256), 0, st, d, at<float>(ws, P.pre[l]),
+                       weights + P.w_off[l], d_pyr,
+                       l + 1 < P.nd ? at<float>(ws, P.dh[l + 1]) : nullptr, d_per);
+    VRS_LAUNCH_CHECK();
+    if (d_w) {
+      DecLevel dw8 = d;
+      int tb = 0;
+      for (int k = 0; k < n_crops; ++k) {
+        dw8.tile_base[k] = tb;
+        const int t = (d.S[k] + 7) / 8;
+        tb += t * t;
+      }
+      dw8.tile_base[n_crops] = tb;
+      const size_t smem = (size_t)(100 * P.cin[l] + 64 * 2 * P.K[l]) * 4;
+      if (smem > 64 * 1024) return VRS_EUNSUPPORTED;
+      const T* hn = l + 1 < P.nd ? at<T>(ws, P.h[l + 1]) : nullptr;
+      hipLaunchKernelGGL(k_dec_wgrad<T>, dim3(tb), dim3(256), smem, st, dw8, pyramid, periph, hn,
+                         at<float>(ws, P.pre[l]), d_w + P.w_off[l], d_w + P.b_off[l]);
+      VRS_LAUNCH_CHECK();
+    }
+  }
+  return VRS_OK;
+}
+
+}  // namespace vrs
+
+extern "C" vrs_status vrs_decode_fovea_backward(const float* pyramid, int levels,
+                                                const float* rgb_periphery, const vrs_view* views,
+                                                int n_views, const vrs_crop* crops, int n_crops,
+                                                const float* weights, const vrs_decoder_desc* dd,
+                                                const float* d_fovea, float* d_pyramid,
+                                                float* d_rgb_periphery, float* d_weights,
+                                                void* ws, size_t ws_bytes, void* stream) {
+  DecPlan P;
+  KViews kv;
+  if (!make_views(views, n_views, &kv) || !dec_plan(dd, crops, n_crops, &P)) return VRS_EINVAL;
+  if (levels < P.nd || levels > VRS_MAX_LEVELS || !pyramid || !rgb_periphery || !weights ||
+      !d_fovea || !ws || ws_bytes < P.total)
+    return VRS_EINVAL;
+  if (dd->in_ch != 4) return VRS_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (P.dtype == VRS_BF16)
+    return decode_bwd_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
+                                   d_fovea, d_pyramid, d_rgb_periphery, d_weights, ws, st);
+  return decode_bwd_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
+                                d_fovea, d_pyramid, d_rgb_periphery, d_weights, ws, st);
 }

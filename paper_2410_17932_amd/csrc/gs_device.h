@@ -150,6 +150,21 @@ __device__ inline void sh_eval(int deg, float x, float y, float z, float* Y) {
   Y[15] = -ShC::c3a * x * (xx - 3.0f * yy);
 }
 
+// Opacity of a projected Gaussian at a pixel centre: record fields
+// a = (px, py, A, B), b = (C, opacity, r, g).  Returns false where the
+// quadratic form is positive (no contribution).  Shared by the forward and
+// backward blends so both take the same threshold decisions.
+__device__ inline bool gs_alpha(const float4& a, const float4& b, float xc, float yc,
+                                float aclamp, float& dx, float& dy, float& eq, float& al) {
+  dx = a.x - xc;
+  dy = a.y - yc;
+  const float qv = -0.5f * (a.z * dx * dx + b.x * dy * dy) - a.w * dx * dy;
+  if (qv > 0.0f) return false;
+  eq = __expf(qv);
+  al = fminf(aclamp, b.y * eq);
+  return true;
+}
+
 // Packed rectangle: low 16 bits x, high 16 bits y.
 __device__ inline uint32_t pack_xy(int x, int y) { return (uint32_t)x | ((uint32_t)y << 16); }
 

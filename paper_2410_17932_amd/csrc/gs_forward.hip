@@ -13,61 +13,9 @@
 //   k_gs_ranges       [begin, end) per tile from the sorted keys
 //   k_gs_blend        one workgroup per tile, batches of records staged in
 //                     LDS, front-to-back blend with a block-wide early exit
-#include "gs_device.h"
+#include "gs_layout.h"
 
 namespace vrs {
-
-// ---------------------------------------------------------------- layout
-struct RenderWs {
-  size_t rec, dkey0, dval0, dkey1, dval1, ntiles, offs, pair_count, pkey0, pval0, pkey1, pval1,
-      ranges, last, evals, sort_tmp, scan_tmp, total;
-  int64_t vn, tiles_x, tiles_y, tiles_total, npix;
-  int tile_bits;
-  bool pairs_in_1;
-};
-
-static int bits_for(int64_t n) {
-  int b = 1;
-  while (b < 32 && (int64_t(1) << b) < n) ++b;
-  return b;
-}
-
-static bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, int64_t max_pairs,
-                          RenderWs* L) {
-  if (n < 0 || nv < 1 || nv > VRS_MAX_VIEWS || !views || max_pairs < 0) return false;
-  if (tile != 8 && tile != 16 && tile != 32) return false;
-  const int W = views[0].width, H = views[0].height;
-  L->vn = n * nv;
-  L->tiles_x = (W + tile - 1) / tile;
-  L->tiles_y = (H + tile - 1) / tile;
-  L->tiles_total = L->tiles_x * L->tiles_y * nv;
-  L->npix = (int64_t)W * H * nv;
-  L->tile_bits = bits_for(L->tiles_total);
-  const int tile_passes = (L->tile_bits + 7) / 8;
-  L->pairs_in_1 = (tile_passes & 1) != 0;
-  const int64_t vn = std::max<int64_t>(L->vn, 1);
-  const int64_t mp = std::max<int64_t>(max_pairs, 1);
-  Carver c;
-  L->rec = c.take((size_t)vn * 48);
-  L->dkey0 = c.take(vn * 4);
-  L->dval0 = c.take(vn * 4);
-  L->dkey1 = c.take(vn * 4);
-  L->dval1 = c.take(vn * 4);
-  L->ntiles = c.take(vn * 4);
-  L->offs = c.take(vn * 4);
-  L->pair_count = c.take(4);
-  L->pkey0 = c.take(mp * 4);
-  L->pval0 = c.take(mp * 4);
-  L->pkey1 = c.take(mp * 4);
-  L->pval1 = c.take(mp * 4);
-  L->ranges = c.take((size_t)L->tiles_total * 8);
-  L->last = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
-  L->evals = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
-  L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->tile_bits)));
-  L->scan_tmp = c.take(scan_tmp_bytes(vn));
-  L->total = c.off;
-  return true;
-}
 
 bool gs_render_layout(int64_t n, int nv, const vrs_view* views, int tile, int64_t max_pairs,
                       size_t* rec, size_t* ranges, size_t* sorted_ids, size_t* last,
@@ -292,10 +240,8 @@ __global__ __launch_bounds__(BlendCfg<TILE>::BLOCK) void k_gs_blend(
         ++evals[q];
         const float4 a = s_a[k];
         const float4 bq = s_b[k];
-        const float dx = a.x - xc, dy = a.y - yc;
-        const float qv = -0.5f * (a.z * dx * dx + bq.x * dy * dy) - a.w * dx * dy;
-        if (qv > 0.0f) continue;
-        const float al = fminf(aclamp, bq.y * __expf(qv));
+        float dx, dy, eq, al;
+        if (!gs_alpha(a, bq, xc, yc, aclamp, dx, dy, eq, al)) continue;
         if (al < amin) continue;
         const float Tn = T[q] * (1.0f - al);
         if (Tn < tmin) {

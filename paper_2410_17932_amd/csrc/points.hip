@@ -382,3 +382,165 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   trace_end(VRS_TRACE_SPLAT, st);
   return VRS_OK;
 }
+
+// ------------------------------------------------------------- backward
+namespace vrs {
+
+// Segment heads replay their pixel's list: a forward walk finds the final
+// transmittance (and the first fully opaque fragment, after which nothing is
+// visible), then a backward walk recovers T before each fragment as
+// T / (1 - alpha) and accumulates
+//   dfeat = alpha T dF,  dalpha = T (feat - acc) . dF,  acc = feat alpha + (1 - alpha) acc
+// Fragment weights are recomputed from the point to carry dalpha into the
+// position and radius (trilinear weight = layer weight x bilinear weight).
+__global__ __launch_bounds__(256) void k_pt_blend_bwd(
+    const uint32_t* __restrict__ fkey, const uint64_t* __restrict__ fval,
+    const uint32_t* __restrict__ total_p, int64_t max_frags, const float* __restrict__ pos,
+    const float* __restrict__ radius, const uint16_t* __restrict__ feat,
+    const float* __restrict__ opacity, int64_t np, KViews views, KCrops crops, PtArgs a,
+    int64_t pix_total, const float4* __restrict__ dpyr, float* __restrict__ d_feat,
+    float* __restrict__ d_pos, float* __restrict__ d_radius, float* __restrict__ d_opacity) {
+  const int64_t cnt = std::min<int64_t>(*total_p, max_frags);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = fkey[i];
+    if (i > 0 && fkey[i - 1] == key) continue;
+    if (key >= (uint64_t)pix_total) continue;
+    const float4 g = dpyr[key];
+    // locate crop, layer and pixel of this key
+    int k = 0;
+    while (k + 1 < crops.n && (int)key >= crops.c[k + 1].pix_base) ++k;
+    const KCrop& c = crops.c[k];
+    int l = 0, lb = c.pix_base;
+    while (l + 1 < a.levels && (int)key >= lb + (c.size >> l) * (c.size >> l)) {
+      lb += (c.size >> l) * (c.size >> l);
+      ++l;
+    }
+    const int Sl = c.size >> l;
+    const int xx = ((int)key - lb) % Sl, yy = ((int)key - lb) / Sl;
+    // forward walk
+    int64_t j = i, jend = i;
+    float T = 1.0f;
+    while (jend < cnt && fkey[jend] == key) {
+      const uint64_t vv = fval[jend];
+      const uint32_t id = (uint32_t)vv;
+      const float w = __uint_as_float((uint32_t)(vv >> 32));
+      const float al = opacity && id < (uint64_t)np ? w * opacity[id] : w;
+      ++jend;
+      if (al >= 1.0f) { T = 0.0f; break; }   // fully opaque: nothing behind is visible
+      T = T * (1.0f - al);
+    }
+    // backward walk over [i, jend)
+    float acc[4] = {0, 0, 0, 0};
+    bool opaque_end = T == 0.0f;
+    for (j = jend - 1; j >= i; --j) {
+      const uint64_t vv = fval[j];
+      const uint32_t id = (uint32_t)vv;
+      if (id >= (uint64_t)np) continue;
+      const float w = __uint_as_float((uint32_t)(vv >> 32));
+      const float o = opacity ? opacity[id] : 1.0f;
+      const float al = w * o;
+      float Tb;
+      if (opaque_end && j == jend - 1) {
+        // T before the opaque fragment: product of the ones in front
+        Tb = 1.0f;
+        for (int64_t q = i; q < j; ++q) {
+          const uint64_t u = fval[q];
+          const uint32_t iq = (uint32_t)u;
+          const float wq = __uint_as_float((uint32_t)(u >> 32));
+          Tb *= 1.0f - (opacity && iq < (uint64_t)np ? wq * opacity[iq] : wq);
+        }
+      } else {
+        Tb = T / (1.0f - al);
+      }
+      const uint2 hb = *reinterpret_cast<const uint2*>(feat + (int64_t)id * 4);
+      const float f[4] = {h2f((uint16_t)(hb.x & 0xffffu)), h2f((uint16_t)(hb.x >> 16)),
+                          h2f((uint16_t)(hb.y & 0xffffu)), h2f((uint16_t)(hb.y >> 16))};
+      const float gg[4] = {g.x, g.y, g.z, g.w};
+      float dal = 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        if (d_feat) atomicAdd(&d_feat[(int64_t)id * 4 + ch], al * Tb * gg[ch]);
+        dal += Tb * (f[ch] - acc[ch]) * gg[ch];
+        acc[ch] = f[ch] * al + (1.0f - al) * acc[ch];
+      }
+      T = Tb;
+      if (d_opacity && opacity) atomicAdd(&d_opacity[id], dal * w);
+      const float dw = dal * o;
+      if ((d_pos || d_radius) && dw != 0.0f) {
+        const KView& cv = views.v[c.view];
+        PtGeom pg;
+        if (!pt_geom32(cv, pos[id], pos[np + id], pos[2 * np + id], radius[id], nullptr,
+                       nullptr, a.cov_min, a.slack, a.levels, pg))
+          continue;
+        float xl, yl;
+        int ix, iy;
+        if (!pt_layer32(pg, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) continue;
+        const float bx = xl - (float)ix, by = yl - (float)iy;
+        const int dx = xx - ix, dy = yy - iy;
+        const float wx = dx ? bx : 1.0f - bx, wy = dy ? by : 1.0f - by;
+        float f2 = 0.0f, wl = 1.0f;
+        if (pg.two) {
+          f2 = log2f(pg.s) - (float)pg.l0;
+          wl = l == pg.l0 ? 1.0f - f2 : f2;
+        }
+        const float dwl = dw * wx * wy;
+        const float sc = ldexpf(1.0f, -l);
+        const float dpx = dw * wl * wy * (dx ? 1.0f : -1.0f) * sc;
+        const float dpy = dw * wl * wx * (dy ? 1.0f : -1.0f) * sc;
+        float ds = 0.0f;
+        if (pg.two) ds = (l == pg.l0 ? -dwl : dwl) / (pg.s * 0.69314718055994531f);
+        const float tz = pg.t[2];
+        const float dr = ds * 2.0f * cv.fx / tz;
+        float dt0 = dpx * cv.fx / tz, dt1 = dpy * cv.fy / tz;
+        float dt2 = -dpx * cv.fx * pg.t[0] / (tz * tz) - dpy * cv.fy * pg.t[1] / (tz * tz) -
+                    ds * pg.s / tz;
+        if (d_radius) atomicAdd(&d_radius[id], dr);
+        if (d_pos)
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            atomicAdd(&d_pos[q * np + id], cv.R[q] * dt0 + cv.R[3 + q] * dt1 + cv.R[6 + q] * dt2);
+      }
+    }
+  }
+}
+
+}  // namespace vrs
+
+extern "C" vrs_status vrs_splat_points_backward(const float* pos, const float* radius,
+                                                const uint16_t* feat, const float* opacity,
+                                                int64_t np, int channels, int levels,
+                                                const vrs_view* views, int n_views,
+                                                const vrs_crop* crops, int n_crops,
+                                                const float* d_pyramid, float* d_feat,
+                                                float* d_pos, float* d_radius, float* d_opacity,
+                                                void* ws, size_t ws_bytes, int64_t max_frags,
+                                                void* stream) {
+  KViews kv;
+  KCrops kc;
+  SplatWs L;
+  if (channels != 4) return channels > 0 ? VRS_EUNSUPPORTED : VRS_EINVAL;
+  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc))
+    return VRS_EINVAL;
+  if (!splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L) || !ws ||
+      ws_bytes < L.total || !d_pyramid)
+    return VRS_EINVAL;
+  if (np > 0 && (!pos || !radius || !feat)) return VRS_EINVAL;
+  if (np == 0 || n_crops == 0) return VRS_OK;
+  PtArgs a;
+  a.cov_min = 0.5f;
+  a.slack = 1.05f;
+  a.levels = levels;
+  a.view_mask = 0;
+  for (int k = 0; k < n_crops; ++k) a.view_mask |= 1u << crops[k].view;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int bb = (int)std::min<int64_t>(8192, std::max(1, div_up(max_frags, 256)));
+  hipLaunchKernelGGL(k_pt_blend_bwd, dim3(bb), dim3(256), 0, st,
+                     at<uint32_t>(ws, L.frags_in_1 ? L.fkey1 : L.fkey0),
+                     at<uint64_t>(ws, L.frags_in_1 ? L.fval1 : L.fval0),
+                     at<uint32_t>(ws, L.frag_count), max_frags, pos, radius, feat, opacity, np, kv,
+                     kc, a, L.pix_total, reinterpret_cast<const float4*>(d_pyramid), d_feat, d_pos,
+                     d_radius, d_opacity);
+  VRS_LAUNCH_CHECK();
+  return VRS_OK;
+}
