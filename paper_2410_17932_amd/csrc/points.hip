@@ -441,8 +441,9 @@ __global__ __launch_bounds__(256) void k_pt_blend_bwd(
       const float o = opacity ? opacity[id] : 1.0f;
       const float al = w * o;
       float Tb;
-      if (opaque_end && j == jend - 1) {
-        // T before the opaque fragment: product of the ones in front
+      if ((opaque_end && j == jend - 1) || !(1.0f - al >= 0.5f)) {
+        // T before an opaque or nearly opaque fragment: the product of the
+        // ones in front (dividing by a small 1 - alpha would amplify error)
         Tb = 1.0f;
         for (int64_t q = i; q < j; ++q) {
           const uint64_t u = fval[q];

@@ -194,3 +194,85 @@ class PlainFrame:
         api.composite_frame(self.rgb, self.fovea, b.crops, b.mode, b.ring, b.m, b.gamma,
                             out=self.out)
         return self.out
+
+
+class FitStep:
+    """One differentiable fitting step (Sec. 3.5): bake -> periphery ->
+    depth-culled point splat -> decoder -> combination -> L1 against a
+    target, then the hand-written adjoints of every stage through
+    torch.autograd.  Parameters live in HBM as leaf tensors with .grad."""
+
+    def __init__(self, scene: dict, target, decoder_dtype: int = api.VRS_BF16, tile: int = 16,
+                 ring: float = 64.0, cull: bool = True, pair_margin: float = 1.5,
+                 frag_margin: float = 2.0, mask=None):
+        self.mask = None if mask is None else (mask if torch.is_tensor(mask) else _dev(mask))
+        g, p = scene["gaussians"], scene["points"]
+        self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
+        self.deg, self.ring, self.cull = g["sh_degree"], ring, cull
+        self.opts = api.make_opts(**dict(scene["raster"], tile=tile))
+        from .synth import pack_decoder
+        self.params = dict(
+            mean=_dev(g["mean"]), logscale=_dev(g["logscale"]), quat=_dev(g["quat"]),
+            logit=_dev(g["logit"]), sh=_dev(g["sh"]), pos=_dev(p["pos"]),
+            radius=_dev(p["radius"]),
+            feat=_dev(p["feat"].view(np.float16).astype(np.float32)),
+            weights=_dev(pack_decoder(scene["decoder"])))
+        for t in self.params.values():
+            t.requires_grad_(True)
+        self.target = None if target is None else (target if torch.is_tensor(target) else _dev(target))
+        if self.target is not None:
+            V, H, W = len(self.views), self.views[0].height, self.views[0].width
+            if tuple(self.target.shape) != (V, 3, H, W):
+                raise ValueError(f"target must be [{V}][3][{H}][{W}]")
+        self.widths = scene["decoder"]["widths"]
+        self.n, self.np = g["n"], p["n"]
+        # size the workspaces with counting passes at the initial parameters
+        with torch.no_grad():
+            cov, op = api.bake_gaussians(self.params["logscale"], self.params["quat"],
+                                         self.params["logit"])
+            ws = api.RenderWorkspace(self.n, self.views, self.opts, 1)
+            r = api.render_gaussians(self.params["mean"], cov, op, self.params["sh"], self.deg,
+                                     self.views, self.opts, ws)
+            self.rws = api.RenderWorkspace(self.n, self.views, self.opts,
+                                           int(ws.pair_count() * pair_margin) + 4096)
+            sws = api.SplatWorkspace(self.np, self.views, self.crops, self.levels, 1)
+            feat_h = self.params["feat"].to(torch.float16).view(torch.int16)
+            api.splat_points(self.params["pos"], self.params["radius"], feat_h, None, self.views,
+                             self.crops, self.levels, r["depth"] if cull else None,
+                             r["tfinal"] if cull else None, sws)
+            self.sws = api.SplatWorkspace(self.np, self.views, self.crops, self.levels,
+                                          int(sws.frag_count() * frag_margin) + 4096)
+        self.dws = api.DecoderWorkspace(self.widths, self.crops, decoder_dtype)
+
+    def forward(self):
+        from .autograd import (BakeGaussians, CompositeFrame, DecodeFovea, L1Loss,
+                               RenderGaussians, SplatPoints)
+        P = self.params
+        cov, op = BakeGaussians.apply(P["logscale"], P["quat"], P["logit"])
+        rgb, depth, tfinal = RenderGaussians.apply(P["mean"], cov, op, P["sh"], self.deg,
+                                                   self.views, self.opts, self.rws)
+        pyr = SplatPoints.apply(P["pos"], P["radius"], P["feat"], None, self.views, self.crops,
+                                self.levels, depth.detach() if self.cull else None,
+                                tfinal if self.cull else None, self.sws)
+        fovea = DecodeFovea.apply(pyr, rgb, P["weights"], self.levels, self.views, self.crops,
+                                  self.dws)
+        out = CompositeFrame.apply(rgb, fovea, self.crops, api.BLEND_LINEAR, self.ring, 0.75, 0.2)
+        if self.target is None:
+            return out, None
+        if self.mask is not None:
+            return out, L1Loss.apply(out * self.mask, self.target * self.mask)
+        return out, L1Loss.apply(out, self.target)
+
+    def step(self, lr: float = 0.0):
+        for t in self.params.values():
+            t.grad = None
+        out, loss = self.forward()
+        loss.backward()
+        if lr:
+            with torch.no_grad():
+                for t in self.params.values():
+                    t -= lr * t.grad
+        return loss
+
+    def status(self) -> int:
+        return max(int(self.rws.status.item()), int(self.sws.status.item()))

@@ -1,0 +1,63 @@
+"""The batched frame: HIP-graph replays equal the eager frame bit for bit
+(several replays, with eager work and synchronisation in between), the
+autotuned tile size does not change the image, and the plain FP32 form
+agrees with the batched BF16 form within the decoder tolerance."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_17932_amd import api, synth
+from paper_2410_17932_amd.frame import Frame, PlainFrame
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene():
+    crops = ((60.0, 50.0, 64), (150.0, 120.0, 96), (30.0, 180.0, 32), (200.0, 90.0, 128),
+             (120.0, 100.0, 48))
+    sc = synth.small_scene(61, n_gauss=6000, n_points=40000, width=256, height=224, f=220.0,
+                           sh_degree=3, n_views=2, crops=crops, crop_views=[0, 0, 1, 1, 0],
+                           widths=(16, 32, 64, 64), radius="lognormal")
+    sc["points"]["radius"] *= 3.0
+    return sc
+
+
+def test_graph_replay_equals_eager():
+    fr = Frame(_scene(), decoder_dtype=api.VRS_BF16, tile=16)
+    eager = fr.run().clone()
+    torch.cuda.synchronize()
+    fr.capture()
+    for i in range(3):
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()                      # unrelated eager work in between
+        out = fr.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {i} differs"
+    assert fr.status() == 0
+
+
+def test_autotune_keeps_image():
+    sc = _scene()
+    fr = Frame(sc, decoder_dtype=api.VRS_F32, tile=16)
+    ref = fr.run().clone()
+    res = fr.autotune(reps=2)
+    out = fr.run()
+    torch.cuda.synchronize()
+    assert res["tile"] in (8, 16, 32)
+    np.testing.assert_allclose(out.cpu().numpy(), ref.cpu().numpy(), atol=1e-5)
+
+
+def test_plain_form_matches_batched():
+    sc = _scene()
+    fb = Frame(sc, decoder_dtype=api.VRS_BF16, tile=16)
+    ob = fb.run().clone()
+    ff = Frame(sc, decoder_dtype=api.VRS_F32, tile=16)
+    pf = PlainFrame(ff)
+    op = pf.run()
+    of = ff.run()
+    torch.cuda.synchronize()
+    # plain (per eye / per crop, FP32) == batched FP32
+    np.testing.assert_allclose(op.cpu().numpy(), of.cpu().numpy(), atol=1e-5)
+    # batched BF16 vs FP32: decoder tolerance
+    err = float((ob - of).abs().max()) / max(1.0, float(of.abs().max()))
+    assert err <= 2e-2, err

@@ -1,0 +1,121 @@
+"""Parity at the benchmark's full size and launch configuration (the full
+stereo frame: 2 x 2016x2240, 500k Gaussians SH3, 5M points, 16 crops of
+256..640 px, tile 32, BF16 decoder), each entry point fed the same inputs
+as the CPU reference: periphery on sampled pixels and sampled tile lists,
+point splat over every layer pixel (lists bit-exact), decoder and
+combination over every crop pixel."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2410_17932_amd import api, synth
+
+from gpu_helpers import baked, check_render, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full():
+    sc = synth.config(3)
+    g, p = sc["gaussians"], sc["points"]
+    views, crops = sc["views"], sc["crops"]
+    V, D = synth.views_array(views), synth.views_dims(views)
+    cov, op = baked(g)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 3, V, D)
+    return dict(sc=sc, cov=cov, op=op, rect=rect, zb=zb, rec=rec, V=V, D=D)
+
+
+def test_fullsize_periphery_sampled(full):
+    sc, g = full["sc"], full["sc"]["gaussians"]
+    views, raster = sc["views"], dict(sc["raster"], tile=32)
+    r = full["rect"][full["rect"][..., 0] >= 0]
+    pairs = int(((r[:, 2] // 32 - r[:, 0] // 32 + 1) * (r[:, 3] // 32 - r[:, 1] // 32 + 1)).sum())
+    opts = api.make_opts(**raster)
+    ws = api.RenderWorkspace(g["n"], views, opts, pairs + 1024)
+    out = api.render_gaussians(dev(g["mean"]), dev(full["cov"]), dev(full["op"]), dev(g["sh"]), 3,
+                               views, opts, ws)
+    torch.cuda.synchronize()
+    assert int(ws.status.item()) == 0 and ws.pair_count() == pairs
+    rng = np.random.default_rng(0)
+    W, H = 2016, 2240
+    pix = np.stack([rng.integers(0, 2, 6000), rng.integers(0, W, 6000), rng.integers(0, H, 6000)], 1)
+    o = oracle.render(full["rect"], full["zb"], full["rec"], full["D"], 32, pix=pix.astype(np.int32))
+    v, x, y = pix[:, 0], pix[:, 1], pix[:, 2]
+    g_rgb = out["rgb"].cpu().numpy()[v, :, y, x]            # [n][3]
+    g_depth = out["depth"].cpu().numpy()[v, y, x]
+    g_t = out["tfinal"].cpu().numpy()[v, y, x]
+    g_n = out["ncontrib"].cpu().numpy()[v, y, x]
+    ok = o["margin"] >= 1e-4                               # unambiguous pixels
+    assert (~ok).mean() < 0.005
+    assert np.abs(g_rgb[ok] - o["rgb"][ok]).max() <= 1e-4
+    assert np.abs(g_t[ok] - o["tfinal"][ok]).max() <= 1e-4
+    assert np.abs(g_depth[ok] - o["depth"][ok]).max() <= 1e-4 * 6   # depth up to ~6
+    assert np.array_equal(g_n[ok], o["ncontrib"][ok])
+    # sampled tile lists, bit-exact
+    ranges, ids = ws.tile_lists()
+    tiles = rng.choice(ws.layout.tiles_total, 24, replace=False)
+    tpv = ws.layout.tiles_x * ws.layout.tiles_y
+    sel_t = np.array([[t // tpv, t % tpv] for t in tiles], np.int32)
+    off, oids = oracle.tile_lists(full["rect"], full["zb"], full["D"], 32, sel_t)
+    for s, t in enumerate(tiles):
+        b, e = ranges[t]
+        assert np.array_equal(ids[b:e], oids[off[s]:off[s + 1]])
+
+
+def test_fullsize_splat_decoder_composite(full):
+    sc = full["sc"]
+    p, views, crops, L = sc["points"], sc["views"], sc["crops"], sc["levels"]
+    V, D = full["V"], full["D"]
+    ci, cf = synth.crops_array(crops)
+    W, H = 2016, 2240
+    # the reference's periphery under every crop (depth cull input and the
+    # decoder's injected crop)
+    cover = np.zeros((2, H, W), bool)
+    for c in crops:
+        cover[c.view, c.y0:c.y0 + c.size, c.x0:c.x0 + c.size] = True
+    vv, yy, xx = np.nonzero(cover)
+    pix = np.stack([vv, xx, yy], 1).astype(np.int32)
+    o = oracle.render(full["rect"], full["zb"], full["rec"], D, 32, pix=pix)
+    depth = np.zeros((2, H, W), np.float32)
+    tf = np.ones((2, H, W), np.float32)
+    rgb = np.zeros((2, 3, H, W), np.float32)
+    depth[vv, yy, xx] = o["depth"]
+    tf[vv, yy, xx] = o["tfinal"]
+    rgb[vv, :, yy, xx] = o["rgb"]
+    # splat: lists and pyramid
+    off, oids = oracle.point_lists(p["pos"], p["radius"], V, D, ci, L, depth, tf)
+    pyr_o = oracle.splat_points(p["pos"], p["radius"], p["feat"], V, D, ci, L, depth, tf)
+    ws = api.SplatWorkspace(p["n"], views, crops, L, len(oids) + 1024)
+    pyr = api.splat_points(dev(p["pos"]), dev(p["radius"]), dev(p["feat"].view(np.int16)), None,
+                           views, crops, L, dev(depth), dev(tf), ws)
+    torch.cuda.synchronize()
+    assert int(ws.status.item()) == 0
+    keys, ids = ws.lists()
+    assert np.array_equal(np.bincount(keys, minlength=len(off) - 1), np.diff(off))
+    assert np.array_equal(ids, oids)
+    # features within 1e-4 of the largest feature magnitude: single-precision
+    # view pixel coordinates near x = 2000 carry ~6e-5 px of rounding, which
+    # the bilinear weights pass on to features of size up to ~4.5
+    fmax = float(np.abs(p["feat"].view(np.float16).astype(np.float64)).max())
+    err = float(np.abs(pyr.cpu().numpy() - pyr_o).max())
+    print(f"full-size pyramid max err {err:.2e} (features up to {fmax:.2f})")
+    assert err <= 1e-4 * max(1.0, fmax)
+    # decoder on the reference pyramid and periphery, BF16 as benchmarked
+    dw = sc["decoder"]
+    packed = synth.pack_decoder(dw)
+    F_o = oracle.decode(ci, L, 4, pyr_o, rgb.astype(np.float64), D, dw["widths"],
+                        packed.astype(np.float64))
+    dws = api.DecoderWorkspace(dw["widths"], crops, api.VRS_BF16)
+    F = api.decode_fovea(dev(pyr_o.astype(np.float32)), L, dev(rgb), views, crops, dev(packed), dws)
+    torch.cuda.synchronize()
+    err = float(np.abs(F.cpu().numpy() - F_o).max()) / max(1.0, float(np.abs(F_o).max()))
+    print("full-size decoder BF16 rel err", err)
+    assert err <= 2e-2
+    # combination
+    out_o = oracle.composite(rgb.astype(np.float64), D, ci, cf, F_o, mode=0, ring=64.0)
+    out = api.composite_frame(dev(rgb), dev(F_o.astype(np.float32)), crops, api.BLEND_LINEAR, 64.0)
+    torch.cuda.synchronize()
+    assert float(np.abs(out.cpu().numpy() - out_o).max()) <= 1e-5
