@@ -252,7 +252,7 @@ def decode(crops_i, levels, channels, pyramid, periph, dims, widths, weights):
 def composite(P, dims, crops_i, gaze, F, mode=0, ring=64.0, m=0.75, gamma=0.2):
     """Combined frame [v][3][H][W] float64 (mode 0 linear ring, 1 Eqs. 2-5)."""
     crops_i = _c(crops_i, np.int32)
-    out = np.zeros_like(np.asarray(P, np.float64))
+    out = np.zeros(np.shape(P), np.float64)
     lib().orc_composite(len(dims), _c(dims, np.int32), _c(P, np.float64), crops_i.shape[0],
                         crops_i, _c(gaze, np.float32).reshape(-1, 2), _c(F, np.float64), mode,
                         ring, m, gamma, out)
