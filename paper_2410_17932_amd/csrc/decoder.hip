@@ -92,14 +92,68 @@ __device__ inline float dec_input(const DecLevel& d, int k, int S, int y, int x,
   return 0.0f;
 }
 
+// Channel order of the halo tile in LDS (and of the packed weights' K
+// dimension): [upsampled coarser output (kn) | pyramid layer (C) | periphery
+// crop (3, finest level only) | zero padding], so the upsampled channels form
+// aligned 8-channel groups.  Returns the original input channel, or -1 for
+// padding.
+__device__ __host__ inline int lds_to_orig(int c, int C, int kn, int has_p) {
+  if (c < kn) return C + c;
+  c -= kn;
+  if (c < C) return c;
+  c -= C;
+  if (has_p && c < 3) return C + kn + c;
+  return -1;
+}
+
+template <typename T>
+__device__ inline void load8(const T* p, float* v);
+template <>
+__device__ inline void load8<__bf16>(const __bf16* p, float* v) {
+  const v8bf a = *reinterpret_cast<const v8bf*>(p);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (float)a[j];
+}
+template <>
+__device__ inline void load8<float>(const float* p, float* v) {
+  const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+template <typename T>
+__device__ inline void store8(T* p, const float* v);
+template <>
+__device__ inline void store8<__bf16>(__bf16* p, const float* v) {
+  v8bf a;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = (__bf16)v[j];
+  *reinterpret_cast<v8bf*>(p) = a;
+}
+template <>
+__device__ inline void store8<float>(float* p, const float* v) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  *reinterpret_cast<float4*>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+// head: optional fused RGB head at the finest level (fovea != null):
+// F = W_o h_0 + b_o written straight to the packed foveal image; h_0 is
+// then only written when pre-activations are requested (backward).
+struct HeadFuse {
+  const float* wo;
+  const float* bo;
+  float* fovea;
+  long long out_base[VRS_MAX_CROPS];
+};
+
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
                                                   const float* __restrict__ periph,
                                                   const T* __restrict__ hnext,
                                                   const T* __restrict__ wp,
                                                   const float* __restrict__ bp,
-                                                  T* __restrict__ hout, float* __restrict__ pre) {
+                                                  T* __restrict__ hout, float* __restrict__ pre,
+                                                  HeadFuse hf) {
   constexpr int TH = DecTraits<T>::TH, RPW = TH / 4, KSTEP = DecTraits<T>::KSTEP;
+  constexpr int NPIX = (TH + 2) * 18;
   extern __shared__ __align__(16) char smem[];
   T* tile = reinterpret_cast<T*>(smem);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -109,16 +163,48 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
   const int S = d.S[k];
   const int oy = (tl / d.tiles_x[k]) * TH, ox = (tl % d.tiles_x[k]) * 16;
   const int cin8 = d.cin8;
-  // ---- halo tile fill (zero padding outside the layer and past Cin)
-  const int total = (TH + 2) * 18 * cin8;
-  for (int e = tid; e < total; e += 256) {
-    const int pix = e / cin8, c = e - pix * cin8;
+  // ---- halo tile fill, one (pixel, 8-channel group) per work item, zero
+  // padding outside the layer and past Cin
+  const int G = cin8 >> 3;
+  for (int e = tid; e < NPIX * G; e += 256) {
+    const int g = e / NPIX, pix = e - g * NPIX;
     const int hy = pix / 18, hx = pix - hy * 18;
     const int y = oy + hy - 1, x = ox + hx - 1;
-    float v = 0.0f;
-    if (c < d.cin && y >= 0 && y < S && x >= 0 && x < S)
-      v = dec_input<T>(d, k, S, y, x, c, pyr, periph, hnext);
-    tile[e] = (T)v;
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = 0.0f;
+    if (y >= 0 && y < S && x >= 0 && x < S) {
+      const int c0 = g * 8;
+      if (c0 + 8 <= d.kn) {
+        // bilinear x2 upsample of 8 consecutive channels of the coarser output
+        const int Sn = S >> 1;
+        const float sx = 0.5f * (float)x - 0.25f, sy = 0.5f * (float)y - 0.25f;
+        const float fx0 = floorf(sx), fy0 = floorf(sy);
+        const float fx = sx - fx0, fy = sy - fy0;
+        int xa = (int)fx0, ya = (int)fy0, xb = xa + 1, yb = ya + 1;
+        xa = xa < 0 ? 0 : (xa > Sn - 1 ? Sn - 1 : xa);
+        xb = xb < 0 ? 0 : (xb > Sn - 1 ? Sn - 1 : xb);
+        ya = ya < 0 ? 0 : (ya > Sn - 1 ? Sn - 1 : ya);
+        yb = yb < 0 ? 0 : (yb > Sn - 1 ? Sn - 1 : yb);
+        const T* h = hnext + d.hn_off[k] + c0;
+        float a00[8], a01[8], a10[8], a11[8];
+        load8<T>(h + ((long long)ya * Sn + xa) * d.kpn, a00);
+        load8<T>(h + ((long long)ya * Sn + xb) * d.kpn, a01);
+        load8<T>(h + ((long long)yb * Sn + xa) * d.kpn, a10);
+        load8<T>(h + ((long long)yb * Sn + xb) * d.kpn, a11);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          v[j] = (1.0f - fy) * ((1.0f - fx) * a00[j] + fx * a01[j]) +
+                 fy * ((1.0f - fx) * a10[j] + fx * a11[j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int oc = lds_to_orig(c0 + j, d.C, d.kn, d.has_p);
+          if (oc >= 0) v[j] = dec_input<T>(d, k, S, y, x, oc, pyr, periph, hnext);
+        }
+      }
+    }
+    store8<T>(&tile[pix * cin8 + g * 8], v);
   }
   __syncthreads();
   // ---- MFMA main loop
@@ -171,10 +257,14 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
     }
   }
   // ---- gated epilogue: lane holds pixels kq*4 + i of the row, channel col
+  const bool write_h = hf.fovea == nullptr || pre != nullptr;
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const int y = oy + r0 + r;
-    if (y >= S) continue;
+    if (y >= S) continue;   // uniform over the wave
+    float part[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[i][0] = part[i][1] = part[i][2] = 0.0f;
 #pragma unroll
     for (int t = 0; t < NT / 2; ++t) {
       const int ch = t * 16 + col;
@@ -182,13 +272,39 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int x = ox + kq * 4 + i;
-        if (x >= S) continue;
         const float f = acc[r][2 * t][i] + bf, g = acc[r][2 * t + 1][i] + bg;
+        const float hv = elu_f(f) * sigmoid_f(g);
+        if (hf.fovea && ch < d.width) {
+          part[i][0] += hf.wo[ch] * hv;
+          part[i][1] += hf.wo[d.width + ch] * hv;
+          part[i][2] += hf.wo[2 * d.width + ch] * hv;
+        }
+        if (x >= S) continue;
         const long long p = (long long)y * S + x;
-        hout[d.h_off[k] + p * d.kp + ch] = (T)(elu_f(f) * sigmoid_f(g));
+        if (write_h) hout[d.h_off[k] + p * d.kp + ch] = (T)hv;
         if (pre) {
           pre[d.pre_off[k] + p * d.nout + 2 * t * 16 + col] = f;
           pre[d.pre_off[k] + p * d.nout + (2 * t + 1) * 16 + col] = g;
+        }
+      }
+    }
+    if (hf.fovea) {
+      // sum the head's partial products over the 16 channel lanes
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int o = 8; o > 0; o >>= 1) part[i][c] += __shfl_xor(part[i][c], o, 64);
+      if (col == 0) {
+        const long long plane = (long long)S * S;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int x = ox + kq * 4 + i;
+          if (x >= S) continue;
+          const long long p = (long long)y * S + x;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) hf.fovea[hf.out_base[k] + c * plane + p] = part[i][c] + hf.bo[c];
         }
       }
     }
@@ -196,12 +312,12 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
 }
 
 // Re-order one level's float weights [2K][3][3][Cin] into the GEMM operand
-// [nout][kpad] (N-tile pairs of feature/gate halves, k = tap*Cin8 + c,
-// zero padding) and its bias.
+// [nout][kpad] (N-tile pairs of feature/gate halves, k = tap*Cin8 + c with c
+// in the LDS channel order, zero padding) and its bias.
 template <typename T>
 __global__ void k_dec_pack(const float* __restrict__ w, const float* __restrict__ b, int K,
-                           int cin, int cin8, int kp, int kpad, T* __restrict__ wp,
-                           float* __restrict__ bp) {
+                           int cin, int cin8, int kp, int kpad, int C, int kn, int has_p,
+                           T* __restrict__ wp, float* __restrict__ bp) {
   const int nout = 2 * kp;
   const long long total = (long long)nout * kpad;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -209,10 +325,11 @@ __global__ void k_dec_pack(const float* __restrict__ w, const float* __restrict_
     const int n = (int)(e / kpad), kk = (int)(e - (long long)n * kpad);
     const int t = n / 32, half = (n % 32) / 16, ch = t * 16 + (n % 16);
     const int tap = kk / cin8, c = kk - tap * cin8;
+    const int oc = lds_to_orig(c, C, kn, has_p);
     float v = 0.0f;
-    if (ch < K && tap < 9 && c < cin) {
+    if (ch < K && tap < 9 && oc >= 0 && oc < cin) {
       const int row = half ? K + ch : ch;
-      v = w[((long long)row * 9 + tap) * cin + c];
+      v = w[((long long)row * 9 + tap) * cin + oc];
     }
     wp[e] = (T)v;
     if (kk == 0) bp[n] = ch < K ? b[half ? K + ch : ch] : 0.0f;
@@ -372,14 +489,14 @@ static void level_args(const DecPlan& P, int l, const vrs_crop* crops, int n_cro
 template <typename T>
 static hipError_t launch_conv(const DecLevel& d, int NT, int blocks, const float* pyr,
                               const float* periph, const T* hn, const T* wp, const float* bp, T* h,
-                              float* pre, hipStream_t st) {
+                              float* pre, const HeadFuse& hf, hipStream_t st) {
   const int TH = DecTraits<T>::TH;
   const size_t smem = (size_t)(TH + 2) * 18 * d.cin8 * sizeof(T);
   switch (NT) {
-    case 2: hipLaunchKernelGGL((k_dec_conv<T, 2>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
-    case 4: hipLaunchKernelGGL((k_dec_conv<T, 4>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
-    case 6: hipLaunchKernelGGL((k_dec_conv<T, 6>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
-    default: hipLaunchKernelGGL((k_dec_conv<T, 8>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre); break;
+    case 2: hipLaunchKernelGGL((k_dec_conv<T, 2>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    case 4: hipLaunchKernelGGL((k_dec_conv<T, 4>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    case 6: hipLaunchKernelGGL((k_dec_conv<T, 6>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    default: hipLaunchKernelGGL((k_dec_conv<T, 8>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
   }
   return hipGetLastError();
 }
@@ -394,7 +511,8 @@ static vrs_status decode_impl(const DecPlan& P, const float* pyramid, int levels
     const int blocks = (int)std::min<long long>(1024, (total + 255) / 256);
     hipLaunchKernelGGL(k_dec_pack<T>, dim3(blocks), dim3(256), 0, st, weights + P.w_off[l],
                        weights + P.b_off[l], P.K[l], P.cin[l], P.cin8[l], P.kp[l], P.kpad[l],
-                       at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]));
+                       P.C, l + 1 < P.nd ? P.K[l + 1] : 0, l == 0 ? 1 : 0, at<T>(ws, P.wp[l]),
+                       at<float>(ws, P.bp[l]));
     VRS_LAUNCH_CHECK();
   }
   DecLevel d;
@@ -402,29 +520,21 @@ static vrs_status decode_impl(const DecPlan& P, const float* pyramid, int levels
     int blocks = 0;
     level_args(P, l, crops, n_crops, kv, levels, &d, &blocks);
     const T* hn = l + 1 < P.nd ? at<T>(ws, P.h[l + 1]) : nullptr;
-    VRS_HIP_CHECK(launch_conv<T>(d, 2 * P.kp[l] / 16, blocks, pyramid, periph, hn,
-                                 at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]), at<T>(ws, P.h[l]),
-                                 keep_pre ? at<float>(ws, P.pre[l]) : nullptr, st));
+    HeadFuse hf{};
     if (l == 0) {
-      HeadArgs ha;
-      ha.n_crops = n_crops;
-      ha.kp = P.kp[0];
-      ha.K0 = P.K[0];
-      long long p = 0, o = 0;
+      // the RGB head runs in the finest level's epilogue
+      hf.wo = weights + P.head_w;
+      hf.bo = weights + P.head_b;
+      hf.fovea = out;
+      long long o = 0;
       for (int k = 0; k < n_crops; ++k) {
-        ha.S[k] = crops[k].size;
-        ha.pix_base[k] = p;
-        ha.out_base[k] = o;
-        ha.h_off[k] = d.h_off[k];
-        p += (long long)crops[k].size * crops[k].size;
+        hf.out_base[k] = o;
         o += 3LL * crops[k].size * crops[k].size;
       }
-      ha.pix_base[n_crops] = p;
-      const int hb = (int)std::min<long long>(8192, (p + 255) / 256);
-      hipLaunchKernelGGL(k_dec_head<T>, dim3(hb), dim3(256), 0, st, ha, at<T>(ws, P.h[0]),
-                         weights + P.head_w, weights + P.head_b, out);
-      VRS_LAUNCH_CHECK();
     }
+    VRS_HIP_CHECK(launch_conv<T>(d, 2 * P.kp[l] / 16, blocks, pyramid, periph, hn,
+                                 at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]), at<T>(ws, P.h[l]),
+                                 keep_pre ? at<float>(ws, P.pre[l]) : nullptr, hf, st));
   }
   return VRS_OK;
 }
@@ -680,7 +790,7 @@ static vrs_status decode_bwd_impl(const DecPlan& P, const float* pyramid, int le
     const T* hn = l + 1 < P.nd ? at<T>(ws, P.h[l + 1]) : nullptr;
     VRS_HIP_CHECK(launch_conv<T>(d, 2 * P.kp[l] / 16, blocks, pyramid, periph, hn,
                                  at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]), at<T>(ws, P.h[l]),
-                                 at<float>(ws, P.pre[l]), st));
+                                 at<float>(ws, P.pre[l]), HeadFuse{}, st));
     VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, P.dh[l]), 0u, P.h_elems[l], st));
   }
   // head

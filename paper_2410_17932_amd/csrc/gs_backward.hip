@@ -17,6 +17,7 @@
 namespace vrs {
 
 constexpr int kG2d = 10;  // px, py, A, B, C, opacity, r, g, b, z
+constexpr float kLn2 = 0.69314718055994531f;
 
 __device__ inline float wave_sum(float v) {
 #pragma unroll
@@ -92,16 +93,18 @@ __global__ __launch_bounds__(BwdCfg<TILE>::BLOCK) void k_gs_blend_bwd(
       const uint32_t id = ids[b0 + tid];
       const uint32_t idc = id < (uint64_t)n ? id : 0;
       const int64_t e = (int64_t)v * n + idc;
-      s_a[tid] = rec[3 * e + 0];
-      s_b[tid] = rec[3 * e + 1];
-      s_c[tid] = rec[3 * e + 2];
+      float4 a, b, c;
+      gs_stage(rec, e, a, b, c);
+      s_a[tid] = a;
+      s_b[tid] = b;
+      s_c[tid] = c;
       s_id[tid] = idc;
     }
     __syncthreads();
     for (int k = cnt - 1; k >= 0; --k) {
       const uint32_t pos = (uint32_t)(b0 - begin) + k;  // position in the tile list
       const float4 a = s_a[k], bq = s_b[k], c = s_c[k];
-      const uint32_t lo = __float_as_uint(c.z), hi = __float_as_uint(c.w);
+      const uint32_t lo = __float_as_uint(bq.z), hi = __float_as_uint(bq.w);
       float dpx = 0, dpy = 0, dA = 0, dB = 0, dC = 0, dop = 0, dr = 0, dg = 0, db = 0, dz = 0;
       bool any = false;
 #pragma unroll
@@ -109,10 +112,9 @@ __global__ __launch_bounds__(BwdCfg<TILE>::BLOCK) void k_gs_blend_bwd(
         if (pos >= last[q]) continue;
         const uint32_t x = (uint32_t)px[q], y = (uint32_t)py[q];
         if (x < (lo & 0xffffu) || x > (hi & 0xffffu) || y < (lo >> 16) || y > (hi >> 16)) continue;
-        float dx, dy, eq, al;
-        if (!gs_alpha(a, bq, (float)px[q] + 0.5f, (float)py[q] + 0.5f, aclamp, dx, dy, eq, al))
-          continue;
-        if (al < amin) continue;
+        float dx, dy, eq;
+        const float al = gs_alpha(a, bq, (float)px[q] + 0.5f, (float)py[q] + 0.5f, aclamp, dx, dy, eq);
+        if (!(al >= amin)) continue;
         any = true;
         const float Tb = T[q] / (1.0f - al);
         const float w = al * Tb;
@@ -120,21 +122,23 @@ __global__ __launch_bounds__(BwdCfg<TILE>::BLOCK) void k_gs_blend_bwd(
         dg += w * g1[q];
         db += w * g2[q];
         dz += w * gd[q];
-        const float dal = Tb * (g0[q] * (bq.z - acc0[q]) + g1[q] * (bq.w - acc1[q]) +
-                                g2[q] * (c.x - acc2[q]) + gd[q] * (c.y - accd[q]));
-        acc0[q] = bq.z * al + (1.0f - al) * acc0[q];
-        acc1[q] = bq.w * al + (1.0f - al) * acc1[q];
-        acc2[q] = c.x * al + (1.0f - al) * acc2[q];
-        accd[q] = c.y * al + (1.0f - al) * accd[q];
+        const float dal = Tb * (g0[q] * (c.x - acc0[q]) + g1[q] * (c.y - acc1[q]) +
+                                g2[q] * (c.z - acc2[q]) + gd[q] * (c.w - accd[q]));
+        acc0[q] = c.x * al + (1.0f - al) * acc0[q];
+        acc1[q] = c.y * al + (1.0f - al) * acc1[q];
+        acc2[q] = c.z * al + (1.0f - al) * acc2[q];
+        accd[q] = c.w * al + (1.0f - al) * accd[q];
         T[q] = Tb;
-        if (bq.y * eq < aclamp) {   // alpha not clamped: flows to opacity and q
+        if (bq.y * eq < aclamp) {   // alpha not clamped: flows to opacity and the exponent
           dop += dal * eq;
-          const float dq = dal * al;
-          dA += -0.5f * dq * dx * dx;
-          dC += -0.5f * dq * dy * dy;
-          dB += -dq * dx * dy;
-          dpx += -dq * (a.z * dx + a.w * dy);
-          dpy += -dq * (bq.x * dy + a.w * dx);
+          // exponent s = -(A dx^2 + C dy^2)/2 - B dx dy; the staged form holds
+          // A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2
+          const float ds = dal * al;
+          dA += -0.5f * ds * dx * dx;
+          dC += -0.5f * ds * dy * dy;
+          dB += -ds * dx * dy;
+          dpx += ds * kLn2 * (2.0f * a.z * dx + a.w * dy);
+          dpy += ds * kLn2 * (2.0f * bq.x * dy + a.w * dx);
         }
       }
       // wave-level reduction, one atomic per value per wave

@@ -150,19 +150,36 @@ __device__ inline void sh_eval(int deg, float x, float y, float z, float* Y) {
   Y[15] = -ShC::c3a * x * (xx - 3.0f * yy);
 }
 
-// Opacity of a projected Gaussian at a pixel centre: record fields
-// a = (px, py, A, B), b = (C, opacity, r, g).  Returns false where the
-// quadratic form is positive (no contribution).  Shared by the forward and
-// backward blends so both take the same threshold decisions.
-__device__ inline bool gs_alpha(const float4& a, const float4& b, float xc, float yc,
-                                float aclamp, float& dx, float& dy, float& eq, float& al) {
+// Blend-time form of a projected Gaussian, staged in LDS once per tile
+// batch: a = (px, py, A', B'), b = (C', opacity, rect_lo, rect_hi),
+// c = (r, g, b, z), with the conic pre-scaled for a base-2 exponential:
+// A' = -log2(e)/2 A, B' = -log2(e) B, C' = -log2(e)/2 C, so that
+// alpha = min(alpha_clamp, opacity 2^(A' dx^2 + B' dx dy + C' dy^2)).
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ inline void gs_stage(const float4* __restrict__ rec, int64_t e, float4& a, float4& b,
+                                float4& c) {
+  const float4 r0 = rec[3 * e + 0], r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
+  a = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+  b = make_float4(-0.5f * kLog2e * r1.x, r1.y, r2.z, r2.w);
+  c = make_float4(r1.z, r1.w, r2.x, r2.y);
+}
+
+// Opacity at a pixel centre, negative where the exponent is positive (no
+// contribution for any alpha_min >= 0).  The forward blend evaluates the same
+// operations inline and the backward calls this, so both take the same
+// threshold decisions; e = 2^q is returned for the adjoint.
+__device__ inline float gs_alpha(const float4& a, const float4& b, float xc, float yc,
+                                 float aclamp, float& dx, float& dy, float& e) {
   dx = a.x - xc;
   dy = a.y - yc;
-  const float qv = -0.5f * (a.z * dx * dx + b.x * dy * dy) - a.w * dx * dy;
-  if (qv > 0.0f) return false;
-  eq = __expf(qv);
-  al = fminf(aclamp, b.y * eq);
-  return true;
+  float u = a.z * dx;
+  u = fmaf(a.w, dy, u);
+  float q = dx * u;
+  q = fmaf(b.x * dy, dy, q);
+  e = __builtin_amdgcn_exp2f(q);
+  const float al = fminf(aclamp, b.y * e);
+  return q > 0.0f ? -1.0f : al;
 }
 
 // Packed rectangle: low 16 bits x, high 16 bits y.

@@ -7,12 +7,13 @@
 //                     depth key and tile count per (view, Gaussian)
 //   radix sort        (depth bits) of all (view, Gaussian) entries
 //   scan              tile counts in depth order -> pair offsets (device)
-//   k_gs_emit         output-parallel: each thread writes one (tile, id)
-//                     pair, so stores are fully coalesced
+//   k_gs_emit         output-parallel: each thread writes pairs found by a
+//                     search over offsets staged in LDS; stores coalesce
 //   radix sort        (tile id) of the pairs, stable: keeps depth order
-//   k_gs_ranges       [begin, end) per tile from the sorted keys
-//   k_gs_blend        one workgroup per tile, batches of records staged in
-//                     LDS, front-to-back blend with a block-wide early exit
+//   k_gs_blend        one workgroup per tile, one wave per sub-tile; finds
+//                     the tile's range in the sorted keys, stages records in
+//                     LDS in batches, front-to-back blend with per-wave and
+//                     block-wide early exit
 #include "gs_layout.h"
 
 namespace vrs {
@@ -96,177 +97,256 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
 }
 
 // ------------------------------------------------------------------ emit
-// Output-parallel pair emission: pair p belongs to the depth-ordered entry
-// j with offs[j] <= p < offs[j] + ntiles[j] (last such j, found by binary
-// search within the block's window).  key = view*tiles_per_view + tile,
-// value = Gaussian index.
-constexpr int kEmitPerThread = 4;
-__global__ __launch_bounds__(256) void k_gs_emit(
+// Output-parallel pair emission.  A block owns 256 consecutive depth-ordered
+// entries; their pair offsets and tile rectangles are staged in LDS, and each
+// thread writes pairs p = first + tid, first + tid + 256, ... of the block's
+// range, finding the owning entry (last i with off[i] <= p) by binary search
+// in LDS.  Stores of consecutive p are consecutive, so they coalesce.
+// key = view * tiles_per_view + tile, value = Gaussian index.
+constexpr int kEmitBlock = 256;
+__global__ __launch_bounds__(kEmitBlock) void k_gs_emit(
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ sorted_e,
     const float4* __restrict__ rec, const uint32_t* __restrict__ total_p, int64_t vn,
     int64_t n, int64_t max_pairs, int tile, int64_t tiles_x, int64_t tiles_per_view,
     uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, int32_t* status) {
-  __shared__ int64_t s_lo, s_hi;
+  __shared__ uint32_t s_off[kEmitBlock + 1];
+  __shared__ uint32_t s_base[kEmitBlock];   // key of the entry's first tile
+  __shared__ uint32_t s_w[kEmitBlock];      // tiles per rectangle row
+  __shared__ uint32_t s_id[kEmitBlock];
+  const int tid = threadIdx.x;
   const int64_t total = *total_p;
   const int64_t cap = std::min<int64_t>(total, max_pairs);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_pairs) set_status(status, VRS_ECAPACITY);
-  const int64_t p0 = blockIdx.x * (int64_t)blockDim.x * kEmitPerThread;
-  if (p0 >= cap) return;
-  const int64_t p1 = std::min<int64_t>(p0 + (int64_t)blockDim.x * kEmitPerThread, cap) - 1;
-  if (threadIdx.x < 2) {
-    // last j with offs[j] <= target
-    const int64_t target = threadIdx.x == 0 ? p0 : p1;
-    int64_t lo = 0, hi = vn - 1;
-    while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if ((int64_t)offs[mid] <= target) lo = mid;
-      else hi = mid - 1;
-    }
-    if (threadIdx.x == 0) s_lo = lo;
-    else s_hi = lo;
-  }
-  __syncthreads();
-  const int64_t wlo = s_lo, whi = s_hi;
-  for (int r = 0; r < kEmitPerThread; ++r) {
-    const int64_t p = p0 + r * (int64_t)blockDim.x + threadIdx.x;
-    if (p > p1) break;
-    int64_t lo = wlo, hi = whi;
-    while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if ((int64_t)offs[mid] <= p) lo = mid;
-      else hi = mid - 1;
-    }
-    const uint32_t e = sorted_e[lo];
+  if (blockIdx.x == 0 && tid == 0 && total > max_pairs) set_status(status, VRS_ECAPACITY);
+  const int64_t j0 = (int64_t)blockIdx.x * kEmitBlock;
+  const int64_t j = j0 + tid;
+  if (j < vn) {
+    s_off[tid] = offs[j];
+    const uint32_t e = sorted_e[j];
     const int64_t v = e / n, gi = e - v * n;
     const float4 r2 = rec[3 * (int64_t)e + 2];
     const uint32_t lo_xy = __float_as_uint(r2.z), hi_xy = __float_as_uint(r2.w);
     const int tx0 = (int)(lo_xy & 0xffffu) / tile, ty0 = (int)(lo_xy >> 16) / tile;
     const int tx1 = (int)(hi_xy & 0xffffu) / tile;
-    const int w = tx1 - tx0 + 1;
-    const int k = (int)(p - (int64_t)offs[lo]);
-    const int ty = ty0 + k / w, tx = tx0 + k % w;
-    pkey[p] = (uint32_t)(v * tiles_per_view + (int64_t)ty * tiles_x + tx);
-    pval[p] = (uint32_t)gi;
+    s_base[tid] = (uint32_t)(v * tiles_per_view + (int64_t)ty0 * tiles_x + tx0);
+    s_w[tid] = (uint32_t)(tx1 - tx0 + 1);
+    s_id[tid] = (uint32_t)gi;
+  } else {
+    s_off[tid] = (uint32_t)total;
   }
-}
-
-// ---------------------------------------------------------------- ranges
-__global__ void k_gs_ranges(const uint32_t* __restrict__ key, const uint32_t* total_p,
-                            int64_t max_pairs, int64_t tiles_total, uint2* __restrict__ ranges) {
-  const int64_t cnt = std::min<int64_t>(*total_p, max_pairs);
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < cnt;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = key[p];
-    if (k >= (uint64_t)tiles_total) continue;   // never for a well-formed list
-    if (p == 0 || key[p - 1] != k) ranges[k].x = (uint32_t)p;
-    if (p == cnt - 1 || key[p + 1] != k) ranges[k].y = (uint32_t)(p + 1);
+  if (tid == 0) s_off[kEmitBlock] = j0 + kEmitBlock < vn ? offs[j0 + kEmitBlock] : (uint32_t)total;
+  __syncthreads();
+  const int64_t first = s_off[0];
+  const int64_t last = std::min<int64_t>((int64_t)s_off[kEmitBlock], cap);
+  int lo = 0;
+  for (int64_t p = first + tid; p < last; p += kEmitBlock) {
+    // s_off[lo] <= p holds on entry (p only grows); find the last such index
+    int hi = kEmitBlock - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)s_off[mid] <= p) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t k = (uint32_t)(p - (int64_t)s_off[lo]);
+    const uint32_t w = s_w[lo];
+    const uint32_t row = k / w, col = k - row * w;
+    pkey[p] = s_base[lo] + row * (uint32_t)tiles_x + col;
+    pval[p] = s_id[lo];
   }
 }
 
 // ----------------------------------------------------------------- blend
-// One workgroup per (view, tile).  BLOCK threads, PPT pixels per thread.
-// Records of the tile list are staged in LDS in batches of BLOCK; every
-// pixel evaluates the batch in list order; the block leaves the list as
-// soon as all its pixels have stopped (block-wide vote).
-template <int TILE>
+// First index in [0, cnt) whose key is >= target (cnt if none).  The 32
+// lanes of one half-wave search together: each round probes 32 evenly spaced
+// keys and keeps the gap in which the comparison flips, so a list of 2^25
+// pairs takes five dependent loads.
+__device__ inline uint32_t halfwave_lower_bound(const uint32_t* __restrict__ keys, uint32_t cnt,
+                                                uint32_t target) {
+  const int lane = threadIdx.x & 63, j = lane & 31;
+  const bool upper = lane >= 32;
+  uint32_t lo = 0, hi = cnt;
+  while (lo < hi) {
+    const uint32_t step = (hi - lo + 31) / 32;
+    const uint32_t p = lo + (uint32_t)j * step;
+    const bool less = p < hi && keys[p] < target;
+    const uint64_t b = __ballot(less);
+    const uint32_t c = (uint32_t)__popc(upper ? (uint32_t)(b >> 32) : (uint32_t)b);
+    if (c == 0) {
+      hi = lo;
+    } else {
+      const uint32_t nhi = lo + c * step;
+      lo = lo + (c - 1) * step + 1;
+      hi = nhi < hi ? nhi : hi;
+    }
+  }
+  return lo;
+}
+
+// One workgroup per (view, tile).  The tile is cut into SUB x SUB sub-tiles,
+// one wave each; a lane holds PPT pixels of its sub-tile (a column, rows
+// 64/SUB apart).  Records of the tile list are staged in LDS in batches of
+// BLOCK (one per thread, conic pre-scaled for exp2); while staging, each wave
+// ballots which of the batch's records reach each sub-tile, so a wave walks
+// only the records that touch its sub-tile, in list order, with scalar bit
+// scans.  The per-pixel step is branch-free: every lane evaluates, and
+// selects decide.  A wave stops evaluating once all its pixels have
+// stopped; the block leaves the list when every wave has.  The tile's
+// [begin, end) in the sorted pair list is found by a half-wave search and
+// stored for the backward pass.
+template <int TILE, int SUB>
 struct BlendCfg {
-  static constexpr int PIX = TILE * TILE;
-  static constexpr int BLOCK = PIX < 256 ? PIX : 256;
-  static constexpr int PPT = PIX / BLOCK;
+  static constexpr int NQ = TILE / SUB;          // sub-tiles per side
+  static constexpr int NW = NQ * NQ;             // waves per block
+  static constexpr int BLOCK = 64 * NW;
+  static constexpr int PPT = SUB * SUB / 64;     // pixels per lane
+  static constexpr int ROWS = 64 / SUB;          // rows between a lane's pixels
 };
 
-template <int TILE>
-__global__ __launch_bounds__(BlendCfg<TILE>::BLOCK) void k_gs_blend(
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ rec, int64_t n, KViews views, GsOpt o, int64_t tiles_x,
-    int64_t tiles_per_view, float* __restrict__ out_rgb, float* __restrict__ out_depth,
+template <int TILE, int SUB>
+__global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK)) void k_gs_blend(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ids,
+    const uint32_t* __restrict__ total_p, int64_t max_pairs, const float4* __restrict__ rec,
+    int64_t n, KViews views, GsOpt o, int64_t tiles_x, int64_t tiles_per_view,
+    uint2* __restrict__ ranges, float* __restrict__ out_rgb, float* __restrict__ out_depth,
     float* __restrict__ out_t, int32_t* __restrict__ out_n, uint32_t* __restrict__ out_last,
     uint32_t* __restrict__ out_evals) {
-  using Cfg = BlendCfg<TILE>;
-  constexpr int BLOCK = Cfg::BLOCK, PPT = Cfg::PPT;
+  using Cfg = BlendCfg<TILE, SUB>;
+  constexpr int BLOCK = Cfg::BLOCK, PPT = Cfg::PPT, NW = Cfg::NW, NQ = Cfg::NQ;
   __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK];
+  __shared__ uint64_t s_mask[NW][NW];   // [sub-tile][group of 64 records]
+  __shared__ uint32_t s_range[2];
   const int64_t tglob = blockIdx.x;
   const int v = (int)(tglob / tiles_per_view);
   const int64_t tl = tglob - (int64_t)v * tiles_per_view;
   const int ty = (int)(tl / tiles_x), tx = (int)(tl - (int64_t)ty * tiles_x);
   const KView& cv = views.v[v];
   const int W = cv.W, H = cv.H;
-  const int tid = threadIdx.x;
-  int px[PPT], py[PPT];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // sub-tile of this wave and the lane's pixels
+  const int sx0 = tx * TILE + (wave % NQ) * SUB, sy0 = ty * TILE + (wave / NQ) * SUB;
+  const int px = sx0 + lane % SUB;
+  // ry[q] is the pixel row tested against record rectangles; a pixel that has
+  // stopped (or lies outside the image) gets kStopped, which fails every test
+  constexpr int kStopped = 1 << 30;
+  int py[PPT], ry[PPT];
   float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
   int cnt[PPT];
   uint32_t last[PPT], evals[PPT];
-  bool done[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
-    const int l = tid + q * BLOCK;
-    px[q] = tx * TILE + (l % TILE);
-    py[q] = ty * TILE + (l / TILE);
-    T[q] = 1.0f; C0[q] = C1[q] = C2[q] = D[q] = 0.0f;
+    py[q] = sy0 + lane / SUB + q * Cfg::ROWS;
+    ry[q] = px >= W || py[q] >= H ? kStopped : py[q];
+    T[q] = 1.0f;
+    C0[q] = C1[q] = C2[q] = D[q] = 0.0f;
     cnt[q] = 0;
     last[q] = 0;
     evals[q] = 0;
-    done[q] = px[q] >= W || py[q] >= H;
   }
-  const uint2 rg = ranges[tglob];
-  const uint32_t begin = rg.x, end = rg.y > rg.x ? rg.y : rg.x;
+  if (wave == 0) {
+    const uint32_t cntp = (uint32_t)std::min<int64_t>(*total_p, max_pairs);
+    const uint32_t r = halfwave_lower_bound(keys, cntp, (uint32_t)tglob + (lane >= 32 ? 1u : 0u));
+    if (lane == 0) s_range[0] = r;
+    if (lane == 32) s_range[1] = r;
+  }
+  __syncthreads();
+  const uint32_t begin = s_range[0], end = s_range[1] > begin ? s_range[1] : begin;
+  if (tid == 0) ranges[tglob] = make_uint2(begin, end);
   const float aclamp = o.aclamp, amin = o.amin, tmin = o.tmin;
-  for (uint32_t b0 = begin; b0 < end; b0 += BLOCK) {
-    bool mine_done = true;
+  const float xc = (float)px + 0.5f;
+  float yc[PPT];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) mine_done &= done[q];
-    if (__syncthreads_count(mine_done) == BLOCK) break;
-    const uint32_t j = b0 + tid;
-    if (j < end) {
-      const uint32_t id = ids[j];
+  for (int q = 0; q < PPT; ++q) yc[q] = (float)py[q] + 0.5f;
+  int all_ry = kStopped;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) all_ry &= ry[q];
+  bool alive = __ballot(all_ry != kStopped) != 0;   // wave-uniform
+  for (uint32_t b0 = begin; b0 < end; b0 += BLOCK) {
+    if (__syncthreads_count(alive) == 0) break;
+    const uint32_t jr = b0 + tid;
+    bool has = jr < end;
+    int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
+    if (has) {
+      const uint32_t id = ids[jr];
       const int64_t e = (int64_t)v * n + (id < (uint64_t)n ? id : 0);
-      s_a[tid] = rec[3 * e + 0];
-      s_b[tid] = rec[3 * e + 1];
-      s_c[tid] = rec[3 * e + 2];
+      float4 a, b, c;
+      gs_stage(rec, e, a, b, c);
+      s_a[tid] = a;
+      s_b[tid] = b;
+      s_c[tid] = c;
+      const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
+      x0 = (int)(lo & 0xffffu); y0 = (int)(lo >> 16);
+      x1 = (int)(hi & 0xffffu); y1 = (int)(hi >> 16);
+    }
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int qx0 = tx * TILE + (w % NQ) * SUB, qy0 = ty * TILE + (w / NQ) * SUB;
+      const bool hit = has && x0 <= qx0 + SUB - 1 && x1 >= qx0 && y0 <= qy0 + SUB - 1 && y1 >= qy0;
+      const uint64_t m = __ballot(hit);
+      if (lane == 0) s_mask[w][wave] = m;
     }
     __syncthreads();
-    const int cntb = (int)min((uint32_t)BLOCK, end - b0);
+    if (!alive) continue;
+    for (int g = 0; g < NW && alive; ++g) {
+      const uint64_t mv = s_mask[wave][g];
+      uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)mv);
+      uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32));
+      uint64_t m = ((uint64_t)mhi << 32) | mlo;
+      while (m) {
+        const int k = g * 64 + __builtin_ctzll(m);
+        m &= m - 1;
+        const float4 a = s_a[k], b = s_b[k], c = s_c[k];
+        const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
+        const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
+        const int rx1 = (int)(hi & 0xffffu), ry1 = (int)(hi >> 16);
+        // rectangle tests as unsigned range checks, combined with bitwise
+        // operators so that nothing branches
+        const bool inx = (uint32_t)(px - rx0) <= (uint32_t)(rx1 - rx0);
+        const uint32_t ry_span = (uint32_t)(ry1 - ry0);
+        const uint32_t pos = b0 + (uint32_t)k + 1u - begin;
+        const float dx = a.x - xc;
+        const float adx = a.z * dx;
+        all_ry = kStopped;
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      if (done[q]) continue;
-      const float xc = (float)px[q] + 0.5f, yc = (float)py[q] + 0.5f;
-      const uint32_t pxy = pack_xy(px[q], py[q]);
-      const uint32_t pxl = pxy & 0xffffu, pyl = pxy >> 16;
-      for (int k = 0; k < cntb; ++k) {
-        const float4 c = s_c[k];
-        const uint32_t lo = __float_as_uint(c.z), hi = __float_as_uint(c.w);
-        if (pxl < (lo & 0xffffu) || pxl > (hi & 0xffffu) || pyl < (lo >> 16) || pyl > (hi >> 16))
-          continue;
-        ++evals[q];
-        const float4 a = s_a[k];
-        const float4 bq = s_b[k];
-        float dx, dy, eq, al;
-        if (!gs_alpha(a, bq, xc, yc, aclamp, dx, dy, eq, al)) continue;
-        if (al < amin) continue;
-        const float Tn = T[q] * (1.0f - al);
-        if (Tn < tmin) {
-          done[q] = true;
+        for (int q = 0; q < PPT; ++q) {
+          const float dy = a.y - yc[q];
+          const float u = fmaf(a.w, dy, adx);
+          const float qq = fmaf(b.x * dy, dy, dx * u);
+          const float e = __builtin_amdgcn_exp2f(qq);
+          const float al0 = b.y * e;
+          const float al = al0 < aclamp ? al0 : aclamp;
+          const bool inr = inx & ((uint32_t)(ry[q] - ry0) <= ry_span);
+          const float Tn = T[q] * (1.0f - al);
+          const bool ok0 = inr & !(qq > 0.0f) & (al >= amin);
+          const bool stop = ok0 & (Tn < tmin);
+          const bool ok = ok0 & !stop;
+          ry[q] = stop ? kStopped : ry[q];
+          const float wgt = ok ? al * T[q] : 0.0f;
+          C0[q] = fmaf(c.x, wgt, C0[q]);
+          C1[q] = fmaf(c.y, wgt, C1[q]);
+          C2[q] = fmaf(c.z, wgt, C2[q]);
+          D[q] = fmaf(c.w, wgt, D[q]);
+          T[q] = ok ? Tn : T[q];
+          cnt[q] += ok ? 1 : 0;
+          last[q] = ok ? pos : last[q];
+          evals[q] += inr ? 1u : 0u;
+          all_ry &= ry[q];
+        }
+        if (__ballot(all_ry != kStopped) == 0) {
+          alive = false;
           break;
         }
-        const float wgt = al * T[q];
-        C0[q] += bq.z * wgt;
-        C1[q] += bq.w * wgt;
-        C2[q] += c.x * wgt;
-        D[q] += c.y * wgt;
-        T[q] = Tn;
-        ++cnt[q];
-        last[q] = b0 + k + 1 - begin;
       }
     }
   }
+  const int64_t plane = (int64_t)W * H;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
-    if (px[q] >= W || py[q] >= H) continue;
-    const int64_t pix = (int64_t)v * W * H + (int64_t)py[q] * W + px[q];
-    const int64_t plane = (int64_t)W * H;
-    out_rgb[(int64_t)v * 3 * plane + 0 * plane + (int64_t)py[q] * W + px[q]] = C0[q] + T[q] * o.bg[0];
-    out_rgb[(int64_t)v * 3 * plane + 1 * plane + (int64_t)py[q] * W + px[q]] = C1[q] + T[q] * o.bg[1];
-    out_rgb[(int64_t)v * 3 * plane + 2 * plane + (int64_t)py[q] * W + px[q]] = C2[q] + T[q] * o.bg[2];
+    if (px >= W || py[q] >= H) continue;
+    const int64_t off = (int64_t)py[q] * W + px;
+    const int64_t pix = (int64_t)v * plane + off;
+    float* rgb = out_rgb + (int64_t)v * 3 * plane + off;
+    rgb[0] = C0[q] + T[q] * o.bg[0];
+    rgb[plane] = C1[q] + T[q] * o.bg[1];
+    rgb[2 * plane] = C2[q] + T[q] * o.bg[2];
     out_depth[pix] = D[q];
     out_t[pix] = T[q];
     out_n[pix] = cnt[q];
@@ -288,7 +368,8 @@ static bool read_opts(const vrs_raster_opts* ro, GsOpt* o) {
   o->lowpass = ro->lowpass;
   o->extent = ro->extent;
   for (int k = 0; k < 3; ++k) o->bg[k] = ro->bg[k];
-  return (o->tile == 8 || o->tile == 16 || o->tile == 32) && o->extent > 0 && o->lowpass >= 0;
+  return (o->tile == 8 || o->tile == 16 || o->tile == 32) && o->extent > 0 && o->lowpass >= 0 &&
+         o->amin >= 0;
 }
 
 static bool same_dims(const vrs_view* views, int nv) {
@@ -320,15 +401,20 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
   return VRS_OK;
 }
 
+// Sub-tile edge per tile size: 16x16 sub-tiles (4 pixels per lane) for
+// 32-pixel tiles, 8x8 (one pixel per lane) below.
 template <int TILE>
-static void launch_blend(const RenderWs& L, void* ws, int64_t n, const KViews& kv, const GsOpt& o,
-                         float* rgb, float* depth, float* tf, int32_t* nc, hipStream_t st) {
-  const uint2* ranges = at<uint2>(ws, L.ranges);
+static void launch_blend(const RenderWs& L, void* ws, int64_t n, int64_t max_pairs,
+                         const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
+                         int32_t* nc, hipStream_t st) {
+  constexpr int SUB = TILE == 32 ? 16 : 8;
+  const uint32_t* keys = at<uint32_t>(ws, L.pairs_in_1 ? L.pkey1 : L.pkey0);
   const uint32_t* ids = at<uint32_t>(ws, L.pairs_in_1 ? L.pval1 : L.pval0);
-  hipLaunchKernelGGL(k_gs_blend<TILE>, dim3((unsigned)L.tiles_total), dim3(BlendCfg<TILE>::BLOCK),
-                     0, st, ranges, ids, at<float4>(ws, L.rec), n, kv, o, L.tiles_x,
-                     L.tiles_x * L.tiles_y, rgb, depth, tf, nc, at<uint32_t>(ws, L.last),
-                     at<uint32_t>(ws, L.evals));
+  hipLaunchKernelGGL((k_gs_blend<TILE, SUB>), dim3((unsigned)L.tiles_total),
+                     dim3(BlendCfg<TILE, SUB>::BLOCK), 0, st, keys, ids,
+                     at<uint32_t>(ws, L.pair_count), max_pairs, at<float4>(ws, L.rec), n, kv, o,
+                     L.tiles_x, L.tiles_x * L.tiles_y, at<uint2>(ws, L.ranges), rgb, depth, tf, nc,
+                     at<uint32_t>(ws, L.last), at<uint32_t>(ws, L.evals));
 }
 
 extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
@@ -373,11 +459,10 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     trace_end(VRS_TRACE_GS_DEPTH_SORT, st);
     trace_begin(VRS_TRACE_GS_EMIT, st);
     {
-      const int blocks = std::max(1, div_up(max_pairs, 256 * kEmitPerThread));
-      hipLaunchKernelGGL(k_gs_emit, dim3(blocks), dim3(256), 0, st, at<uint32_t>(ws, L.offs),
-                         sorted_e, at<float4>(ws, L.rec), pair_count, vn, n, max_pairs, o.tile,
-                         L.tiles_x, L.tiles_x * L.tiles_y, at<uint32_t>(ws, L.pkey0),
-                         at<uint32_t>(ws, L.pval0), dev_status);
+      hipLaunchKernelGGL(k_gs_emit, dim3(div_up(vn, kEmitBlock)), dim3(kEmitBlock), 0, st,
+                         at<uint32_t>(ws, L.offs), sorted_e, at<float4>(ws, L.rec), pair_count, vn,
+                         n, max_pairs, o.tile, L.tiles_x, L.tiles_x * L.tiles_y,
+                         at<uint32_t>(ws, L.pkey0), at<uint32_t>(ws, L.pval0), dev_status);
       VRS_LAUNCH_CHECK();
     }
     trace_end(VRS_TRACE_GS_EMIT, st);
@@ -391,19 +476,11 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   } else {
     VRS_HIP_CHECK(fill_u32(pair_count, 0, 1, st));
   }
-  VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, L.ranges), 0, L.tiles_total * 2, st));
-  if (max_pairs > 0) {
-    const int blocks = (int)std::min<int64_t>(8192, std::max(1, div_up(max_pairs, 256)));
-    hipLaunchKernelGGL(k_gs_ranges, dim3(blocks), dim3(256), 0, st,
-                       at<uint32_t>(ws, L.pairs_in_1 ? L.pkey1 : L.pkey0), pair_count, max_pairs,
-                       L.tiles_total, at<uint2>(ws, L.ranges));
-    VRS_LAUNCH_CHECK();
-  }
   trace_begin(VRS_TRACE_GS_BLEND, st);
   switch (o.tile) {
-    case 8: launch_blend<8>(L, ws, n, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    case 16: launch_blend<16>(L, ws, n, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    default: launch_blend<32>(L, ws, n, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    case 8: launch_blend<8>(L, ws, n, max_pairs, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    case 16: launch_blend<16>(L, ws, n, max_pairs, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    default: launch_blend<32>(L, ws, n, max_pairs, kv, o, rgb, depth, t_final, n_contrib, st); break;
   }
   VRS_LAUNCH_CHECK();
   trace_end(VRS_TRACE_GS_BLEND, st);
