@@ -55,8 +55,14 @@ struct DecTraits<__bf16> {
 __device__ inline float to_f(float x) { return x; }
 __device__ inline float to_f(__bf16 x) { return (float)x; }
 
-__device__ inline float elu_f(float x) { return x > 0.0f ? x : expm1f(x); }
-__device__ inline float sigmoid_f(float x) { return 1.0f / (1.0f + __expf(-x)); }
+// Activations of the gated convolution, on the hardware exp2 and reciprocal
+// (a few ulp; the reference and the gradients use the library functions).
+__device__ inline float elu_f(float x) {
+  return x > 0.0f ? x : __builtin_amdgcn_exp2f(x * 1.4426950408889634f) - 1.0f;
+}
+__device__ inline float sigmoid_f(float x) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-x * 1.4426950408889634f));
+}
 
 // value of input channel c of level l at pixel (y, x) of crop k (inside the
 // S x S layer)
@@ -144,6 +150,44 @@ struct HeadFuse {
   long long out_base[VRS_MAX_CROPS];
 };
 
+// 16-byte copies of 8 channels (one uint4 for bfloat16, two for float)
+template <typename T>
+__device__ inline void copy8(T* dst, const T* src) {
+  if constexpr (sizeof(T) == 2) {
+    *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+  } else {
+    reinterpret_cast<uint4*>(dst)[0] = reinterpret_cast<const uint4*>(src)[0];
+    reinterpret_cast<uint4*>(dst)[1] = reinterpret_cast<const uint4*>(src)[1];
+  }
+}
+
+// Geometry of one workgroup's LDS: halo tile, the coarser level's footprint
+// and two weight chunks of CHS k-steps (8 KB each).
+template <typename T, int NT>
+struct ConvCfg {
+  static constexpr int TH = DecTraits<T>::TH, KSTEP = DecTraits<T>::KSTEP;
+  static constexpr int NPIX = (TH + 2) * 18;
+  static constexpr int CR = TH / 2 + 2, CC = 10;       // coarse rows / columns staged
+  static constexpr int NOUT = NT * 16;
+  static constexpr int CHS = 8192 / (NOUT * KSTEP * (int)sizeof(T)) > 0
+                                 ? 8192 / (NOUT * KSTEP * (int)sizeof(T)) : 1;
+  static constexpr int CK = CHS * KSTEP;                // k per chunk
+  static constexpr int BROW = CK + 16 / (int)sizeof(T); // padded LDS row (elements)
+  static constexpr int PPR = CK * (int)sizeof(T) / 16;  // 16-byte pieces per row
+  static constexpr int PIECES = NOUT * PPR;
+  static constexpr int PPT = (PIECES + 255) / 256;
+};
+
+// The weight chunks reuse the coarse footprint's LDS once the halo tile is
+// filled.
+template <typename T, int NT>
+__host__ __device__ inline size_t conv_smem_bytes(int cin8, int kn) {
+  using Cfg = ConvCfg<T, NT>;
+  const size_t kn8 = (size_t)((kn + 7) & ~7);
+  const size_t coarse = (size_t)Cfg::CR * Cfg::CC * kn8, wchunks = (size_t)2 * Cfg::NOUT * Cfg::BROW;
+  return ((size_t)Cfg::NPIX * cin8 + (coarse > wchunks ? coarse : wchunks)) * sizeof(T);
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
                                                   const float* __restrict__ periph,
@@ -152,62 +196,146 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
                                                   const float* __restrict__ bp,
                                                   T* __restrict__ hout, float* __restrict__ pre,
                                                   HeadFuse hf) {
-  constexpr int TH = DecTraits<T>::TH, RPW = TH / 4, KSTEP = DecTraits<T>::KSTEP;
-  constexpr int NPIX = (TH + 2) * 18;
+  using Cfg = ConvCfg<T, NT>;
+  constexpr int TH = Cfg::TH, RPW = TH / 4, KSTEP = Cfg::KSTEP, NPIX = Cfg::NPIX;
+  constexpr int CR = Cfg::CR, CC = Cfg::CC, NOUT = Cfg::NOUT, CHS = Cfg::CHS, CK = Cfg::CK;
+  constexpr int BROW = Cfg::BROW;
   extern __shared__ __align__(16) char smem[];
+  const int cin8 = d.cin8, kn8 = (d.kn + 7) & ~7;
   T* tile = reinterpret_cast<T*>(smem);
+  T* ctile = tile + NPIX * cin8;
+  T* sB = ctile;   // after the fill
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int k = 0;
   while (k + 1 < d.n_crops && (int)blockIdx.x >= d.tile_base[k + 1]) ++k;
   const int tl = blockIdx.x - d.tile_base[k];
   const int S = d.S[k];
   const int oy = (tl / d.tiles_x[k]) * TH, ox = (tl % d.tiles_x[k]) * 16;
-  const int cin8 = d.cin8;
-  // ---- halo tile fill, one (pixel, 8-channel group) per work item, zero
-  // padding outside the layer and past Cin
-  const int G = cin8 >> 3;
-  for (int e = tid; e < NPIX * G; e += 256) {
-    const int g = e / NPIX, pix = e - g * NPIX;
-    const int hy = pix / 18, hx = pix - hy * 18;
-    const int y = oy + hy - 1, x = ox + hx - 1;
-    float v[8];
+  const int nsteps = d.kpad / KSTEP;
+  const int nchunks = (nsteps + CHS - 1) / CHS;
+  // ---- weight chunks: global -> registers -> LDS, one chunk ahead
+  uint4 breg[Cfg::PPT];
+  auto load_chunk = [&](int c) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = 0.0f;
-    if (y >= 0 && y < S && x >= 0 && x < S) {
-      const int c0 = g * 8;
-      if (c0 + 8 <= d.kn) {
-        // bilinear x2 upsample of 8 consecutive channels of the coarser output
-        const int Sn = S >> 1;
-        const float sx = 0.5f * (float)x - 0.25f, sy = 0.5f * (float)y - 0.25f;
-        const float fx0 = floorf(sx), fy0 = floorf(sy);
-        const float fx = sx - fx0, fy = sy - fy0;
-        int xa = (int)fx0, ya = (int)fy0, xb = xa + 1, yb = ya + 1;
-        xa = xa < 0 ? 0 : (xa > Sn - 1 ? Sn - 1 : xa);
-        xb = xb < 0 ? 0 : (xb > Sn - 1 ? Sn - 1 : xb);
-        ya = ya < 0 ? 0 : (ya > Sn - 1 ? Sn - 1 : ya);
-        yb = yb < 0 ? 0 : (yb > Sn - 1 ? Sn - 1 : yb);
-        const T* h = hnext + d.hn_off[k] + c0;
-        float a00[8], a01[8], a10[8], a11[8];
-        load8<T>(h + ((long long)ya * Sn + xa) * d.kpn, a00);
-        load8<T>(h + ((long long)ya * Sn + xb) * d.kpn, a01);
-        load8<T>(h + ((long long)yb * Sn + xa) * d.kpn, a10);
-        load8<T>(h + ((long long)yb * Sn + xb) * d.kpn, a11);
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          v[j] = (1.0f - fy) * ((1.0f - fx) * a00[j] + fx * a01[j]) +
-                 fy * ((1.0f - fx) * a10[j] + fx * a11[j]);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int oc = lds_to_orig(c0 + j, d.C, d.kn, d.has_p);
-          if (oc >= 0) v[j] = dec_input<T>(d, k, S, y, x, oc, pyr, periph, hnext);
-        }
+    for (int q = 0; q < Cfg::PPT; ++q) {
+      const int pc = tid + q * 256;
+      breg[q] = make_uint4(0, 0, 0, 0);
+      if (pc < Cfg::PIECES) {
+        const int n = pc / Cfg::PPR, kk = (pc - n * Cfg::PPR) * (16 / (int)sizeof(T));
+        const int gk = c * CK + kk;
+        if (gk < d.kpad) breg[q] = *reinterpret_cast<const uint4*>(wp + (long long)n * d.kpad + gk);
       }
     }
-    store8<T>(&tile[pix * cin8 + g * 8], v);
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < Cfg::PPT; ++q) {
+      const int pc = tid + q * 256;
+      if (pc < Cfg::PIECES) {
+        const int n = pc / Cfg::PPR, kk = (pc - n * Cfg::PPR) * (16 / (int)sizeof(T));
+        *reinterpret_cast<uint4*>(&sB[(buf * NOUT + n) * BROW + kk]) = breg[q];
+      }
+    }
+  };
+  load_chunk(0);
+  // ---- the coarser level's output under this tile, clamped at the layer
+  // edge, staged once (each coarse pixel feeds up to 16 fine pixels)
+  const int Sn = S >> 1;
+  const int cy0 = (oy >> 1) - 1, cx0 = (ox >> 1) - 1;
+  if (d.kn > 0) {
+    const int kg = kn8 >> 3;
+    for (int e = tid; e < CR * CC * kg; e += 256) {
+      const int cp = e / kg, g = e - cp * kg;
+      const int cyi = cp / CC, cxi = cp - cyi * CC;
+      int yy = cy0 + cyi, xx = cx0 + cxi;
+      yy = yy < 0 ? 0 : (yy > Sn - 1 ? Sn - 1 : yy);
+      xx = xx < 0 ? 0 : (xx > Sn - 1 ? Sn - 1 : xx);
+      copy8<T>(&ctile[cp * kn8 + g * 8], hnext + d.hn_off[k] + ((long long)yy * Sn + xx) * d.kpn + g * 8);
+    }
+    __syncthreads();
   }
+  // ---- halo tile fill.  Upsampled channels: one work item per 2x2 block of
+  // fine pixels and 8-channel group -- fine rows 2m+1, 2m+2 (and columns
+  // likewise) interpolate the same two coarse rows with weights 3/4, 1/4 and
+  // 1/4, 3/4, so four coarse reads serve four pixels.  Other channels
+  // (pyramid layer, periphery crop, padding): one item per pixel and group.
+  // Pixels outside the layer are zero.
+  const int G = cin8 >> 3;
+  const int kgf = d.kn >> 3;   // full 8-channel groups of upsampled channels
+  constexpr int NB = (TH + 2) / 2 * 9;   // 2x2 blocks of the halo tile
+  const bool fast_py = d.C == 4 && (d.kn & 7) == 0 && (reinterpret_cast<uintptr_t>(pyr) & 15) == 0;
+  const long long plane = (long long)d.W * d.H;
+  const int n_up = NB * kgf, n_items = n_up + NPIX * (G - kgf);
+  for (int e = tid; e < n_items; e += 256) {
+    if (e < n_up) {
+      const int g = e / NB, blk = e - g * NB;
+      const int bi = blk / 9, bj = blk - bi * 9;
+      const T* c00 = &ctile[(bi * CC + bj) * kn8 + g * 8];
+      float a00[8], a01[8], a10[8], a11[8];
+      load8<T>(c00, a00);
+      load8<T>(c00 + kn8, a01);
+      load8<T>(c00 + CC * kn8, a10);
+      load8<T>(c00 + (CC + 1) * kn8, a11);
+      // horizontal: left fine column (3/4 a_0 + 1/4 a_1), right (1/4, 3/4)
+      float tl[8], tr[8], bl[8], br[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        tl[j] = fmaf(0.25f, a01[j], 0.75f * a00[j]);
+        tr[j] = fmaf(0.75f, a01[j], 0.25f * a00[j]);
+        bl[j] = fmaf(0.25f, a11[j], 0.75f * a10[j]);
+        br[j] = fmaf(0.75f, a11[j], 0.25f * a10[j]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int dy = q >> 1, dx = q & 1;
+        const int hy = 2 * bi + dy, hx = 2 * bj + dx;
+        const int y = oy + hy - 1, x = ox + hx - 1;
+        float v[8];
+        const bool in = y >= 0 && y < S && x >= 0 && x < S;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float top = dx ? tr[j] : tl[j], bot = dx ? br[j] : bl[j];
+          const float val = dy ? fmaf(0.75f, bot, 0.25f * top) : fmaf(0.25f, bot, 0.75f * top);
+          v[j] = in ? val : 0.0f;
+        }
+        store8<T>(&tile[(hy * 18 + hx) * cin8 + g * 8], v);
+      }
+    } else {
+      const int e2 = e - n_up;
+      const int g = kgf + e2 / NPIX, pix = e2 - (g - kgf) * NPIX;
+      const int hy = pix / 18, hx = pix - hy * 18;
+      const int y = oy + hy - 1, x = ox + hx - 1;
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = 0.0f;
+      if (y >= 0 && y < S && x >= 0 && x < S) {
+        const int c0 = g * 8;
+        if (fast_py && c0 == d.kn) {
+          // pyramid layer (4 channels, one 16-byte load) and periphery crop
+          const float4 pv = *reinterpret_cast<const float4*>(pyr + d.pyr_off[k] + ((long long)y * S + x) * 4);
+          v[0] = pv.x; v[1] = pv.y; v[2] = pv.z; v[3] = pv.w;
+          if (d.has_p) {
+            const float* pp = periph + (long long)d.view[k] * 3 * plane +
+                              (long long)(d.y0[k] + y) * d.W + (d.x0[k] + x);
+            v[4] = pp[0];
+            v[5] = pp[plane];
+            v[6] = pp[2 * plane];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int oc = lds_to_orig(c0 + j, d.C, d.kn, d.has_p);
+            if (oc >= 0) v[j] = dec_input<T>(d, k, S, y, x, oc, pyr, periph, hnext);
+          }
+        }
+      }
+      store8<T>(&tile[pix * cin8 + g * 8], v);
+    }
+  }
+  __syncthreads();   // the coarse footprint is dead from here
+  store_chunk(0);
   __syncthreads();
-  // ---- MFMA main loop
+  // ---- MFMA main loop over weight chunks
   v4f acc[RPW][NT];
 #pragma unroll
   for (int r = 0; r < RPW; ++r)
@@ -215,124 +343,155 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
     for (int j = 0; j < NT; ++j) acc[r][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   const int r0 = wave * RPW;
   const int col = lane & 15, kq = lane >> 4;
-  const int nsteps = d.kpad / KSTEP;
-  if constexpr (sizeof(T) == 2) {
-    const int g8 = cin8 >> 3;
-    for (int ks = 0; ks < nsteps; ++ks) {
-      const int gi = ks * 4 + kq;
-      const int tap = gi / g8, cg = gi - tap * g8;
-      const int dy = tap / 3, dx = tap - dy * 3;
-      v8bf a[RPW];
+  for (int c = 0; c < nchunks; ++c) {
+    if (c + 1 < nchunks) load_chunk(c + 1);
+    const T* B = sB + (c & 1) * NOUT * BROW;
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        if (tap < 9)
-          a[r] = *reinterpret_cast<const v8bf*>(&tile[((r0 + r + dy) * 18 + col + dx) * cin8 + cg * 8]);
-        else
-          a[r] = v8bf{0, 0, 0, 0, 0, 0, 0, 0};
-      }
+    for (int s = 0; s < CHS; ++s) {
+      const int ks = c * CHS + s;
+      if (ks >= nsteps) break;
+      if constexpr (sizeof(T) == 2) {
+        const int g8 = cin8 >> 3;
+        const int gi = ks * 4 + kq;
+        const int tap = gi / g8, cg = gi - tap * g8;
+        const int dy = tap / 3, dx = tap - dy * 3;
+        v8bf a[RPW];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const v8bf b = *reinterpret_cast<const v8bf*>(&wp[(long long)(j * 16 + col) * d.kpad + ks * 32 + kq * 8]);
+        for (int r = 0; r < RPW; ++r) {
+          if (tap < 9)
+            a[r] = *reinterpret_cast<const v8bf*>(&tile[((r0 + r + dy) * 18 + col + dx) * cin8 + cg * 8]);
+          else
+            a[r] = v8bf{0, 0, 0, 0, 0, 0, 0, 0};
+        }
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
-          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b, acc[r][j], 0, 0, 0);
-      }
-    }
-  } else {
-    for (int ks = 0; ks < nsteps; ++ks) {
-      const int kk = ks * 4 + kq;
-      const int tap = kk / cin8, c = kk - tap * cin8;
-      const int dy = tap / 3, dx = tap - dy * 3;
-      float a[RPW];
+        for (int j = 0; j < NT; ++j) {
+          const v8bf b = *reinterpret_cast<const v8bf*>(&B[(j * 16 + col) * BROW + s * KSTEP + kq * 8]);
 #pragma unroll
-      for (int r = 0; r < RPW; ++r)
-        a[r] = tap < 9 ? to_f(tile[((r0 + r + dy) * 18 + col + dx) * cin8 + c]) : 0.0f;
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const float b = to_f(wp[(long long)(j * 16 + col) * d.kpad + ks * 4 + kq]);
+          for (int r = 0; r < RPW; ++r)
+            acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[r], acc[r][j], 0, 0, 0);
+        }
+      } else {
+        const int kk = ks * 4 + kq;
+        const int tap = kk / cin8, cc = kk - tap * cin8;
+        const int dy = tap / 3, dx = tap - dy * 3;
+        float a[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r)
-          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b, acc[r][j], 0, 0, 0);
+          a[r] = tap < 9 ? to_f(tile[((r0 + r + dy) * 18 + col + dx) * cin8 + cc]) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const float b = to_f(B[(j * 16 + col) * BROW + s * KSTEP + kq]);
+#pragma unroll
+          for (int r = 0; r < RPW; ++r)
+            acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a[r], acc[r][j], 0, 0, 0);
+        }
       }
     }
+    if (c + 1 < nchunks) store_chunk((c + 1) & 1);
+    __syncthreads();
   }
-  // ---- gated epilogue: lane holds pixels kq*4 + i of the row, channel col
+  // ---- gated epilogue.  The weights are the MFMA's A operand, so lane
+  // (col, kq) holds channels 4 kq + i (i < 4) of N-tile j for the pixel in
+  // column col: feature and gate of a channel sit in the same lane, and the
+  // lane's four channels are contiguous in h and in the pre-activations.
   const bool write_h = hf.fovea == nullptr || pre != nullptr;
+  const int x = ox + col;
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const int y = oy + r0 + r;
     if (y >= S) continue;   // uniform over the wave
-    float part[4][3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) part[i][0] = part[i][1] = part[i][2] = 0.0f;
+    const long long p = (long long)y * S + x;
+    float part[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int t = 0; t < NT / 2; ++t) {
-      const int ch = t * 16 + col;
-      const float bf = bp[2 * t * 16 + col], bg = bp[(2 * t + 1) * 16 + col];
+      const float4 bf = *reinterpret_cast<const float4*>(&bp[2 * t * 16 + 4 * kq]);
+      const float4 bg = *reinterpret_cast<const float4*>(&bp[(2 * t + 1) * 16 + 4 * kq]);
+      const float f[4] = {acc[r][2 * t][0] + bf.x, acc[r][2 * t][1] + bf.y,
+                          acc[r][2 * t][2] + bf.z, acc[r][2 * t][3] + bf.w};
+      const float g[4] = {acc[r][2 * t + 1][0] + bg.x, acc[r][2 * t + 1][1] + bg.y,
+                          acc[r][2 * t + 1][2] + bg.z, acc[r][2 * t + 1][3] + bg.w};
+      float hv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int x = ox + kq * 4 + i;
-        const float f = acc[r][2 * t][i] + bf, g = acc[r][2 * t + 1][i] + bg;
-        const float hv = elu_f(f) * sigmoid_f(g);
-        if (hf.fovea && ch < d.width) {
-          part[i][0] += hf.wo[ch] * hv;
-          part[i][1] += hf.wo[d.width + ch] * hv;
-          part[i][2] += hf.wo[2 * d.width + ch] * hv;
+      for (int i = 0; i < 4; ++i) hv[i] = elu_f(f[i]) * sigmoid_f(g[i]);
+      if (hf.fovea) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int ch = t * 16 + 4 * kq + i;
+          if (ch < d.width)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[c] = fmaf(hf.wo[c * d.width + ch], hv[i], part[c]);
         }
-        if (x >= S) continue;
-        const long long p = (long long)y * S + x;
-        if (write_h) hout[d.h_off[k] + p * d.kp + ch] = (T)hv;
+      }
+      if (x < S) {
+        if (write_h) {
+          T* hp = hout + d.h_off[k] + p * d.kp + t * 16 + 4 * kq;
+          if constexpr (sizeof(T) == 2) {
+            typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+            *reinterpret_cast<v4bf*>(hp) = v4bf{(__bf16)hv[0], (__bf16)hv[1], (__bf16)hv[2], (__bf16)hv[3]};
+          } else {
+            *reinterpret_cast<float4*>(hp) = make_float4(hv[0], hv[1], hv[2], hv[3]);
+          }
+        }
         if (pre) {
-          pre[d.pre_off[k] + p * d.nout + 2 * t * 16 + col] = f;
-          pre[d.pre_off[k] + p * d.nout + (2 * t + 1) * 16 + col] = g;
+          float* pp = pre + d.pre_off[k] + p * d.nout;
+          *reinterpret_cast<float4*>(pp + 2 * t * 16 + 4 * kq) = make_float4(f[0], f[1], f[2], f[3]);
+          *reinterpret_cast<float4*>(pp + (2 * t + 1) * 16 + 4 * kq) = make_float4(g[0], g[1], g[2], g[3]);
         }
       }
     }
     if (hf.fovea) {
-      // sum the head's partial products over the 16 channel lanes
+      // sum the head's partial products over the four lanes of the pixel
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int c = 0; c < 3; ++c) {
+        part[c] += __shfl_xor(part[c], 16, 64);
+        part[c] += __shfl_xor(part[c], 32, 64);
+      }
+      if (kq == 0 && x < S) {
+        const long long opl = (long long)S * S;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int o = 8; o > 0; o >>= 1) part[i][c] += __shfl_xor(part[i][c], o, 64);
-      if (col == 0) {
-        const long long plane = (long long)S * S;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int x = ox + kq * 4 + i;
-          if (x >= S) continue;
-          const long long p = (long long)y * S + x;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) hf.fovea[hf.out_base[k] + c * plane + p] = part[i][c] + hf.bo[c];
-        }
+        for (int c = 0; c < 3; ++c) hf.fovea[hf.out_base[k] + c * opl + p] = part[c] + hf.bo[c];
       }
     }
   }
 }
 
-// Re-order one level's float weights [2K][3][3][Cin] into the GEMM operand
-// [nout][kpad] (N-tile pairs of feature/gate halves, k = tap*Cin8 + c with c
-// in the LDS channel order, zero padding) and its bias.
+// Re-order every level's float weights [2K][3][3][Cin] into its GEMM
+// operand [nout][kpad] (N-tile pairs of feature/gate halves, k = tap*Cin8 + c
+// with c in the LDS channel order, zero padding) and its bias, all levels in
+// one launch.
 template <typename T>
-__global__ void k_dec_pack(const float* __restrict__ w, const float* __restrict__ b, int K,
-                           int cin, int cin8, int kp, int kpad, int C, int kn, int has_p,
-                           T* __restrict__ wp, float* __restrict__ bp) {
-  const int nout = 2 * kp;
-  const long long total = (long long)nout * kpad;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
+struct PackArgs {
+  int n;
+  int K[VRS_MAX_LEVELS], cin[VRS_MAX_LEVELS], cin8[VRS_MAX_LEVELS], kp[VRS_MAX_LEVELS],
+      kpad[VRS_MAX_LEVELS], kn[VRS_MAX_LEVELS];
+  long long start[VRS_MAX_LEVELS + 1];   // first element of each level
+  const float* w[VRS_MAX_LEVELS];
+  const float* b[VRS_MAX_LEVELS];
+  T* wp[VRS_MAX_LEVELS];
+  float* bp[VRS_MAX_LEVELS];
+  int C;
+};
+
+template <typename T>
+__global__ void k_dec_pack(PackArgs<T> a) {
+  const long long total = a.start[a.n];
+  for (long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; e0 < total;
+       e0 += (long long)gridDim.x * blockDim.x) {
+    int l = 0;
+    while (l + 1 < a.n && e0 >= a.start[l + 1]) ++l;
+    const long long e = e0 - a.start[l];
+    const int kpad = a.kpad[l], cin8 = a.cin8[l], K = a.K[l];
     const int n = (int)(e / kpad), kk = (int)(e - (long long)n * kpad);
     const int t = n / 32, half = (n % 32) / 16, ch = t * 16 + (n % 16);
     const int tap = kk / cin8, c = kk - tap * cin8;
-    const int oc = lds_to_orig(c, C, kn, has_p);
+    const int oc = lds_to_orig(c, a.C, a.kn[l], l == 0 ? 1 : 0);
     float v = 0.0f;
-    if (ch < K && tap < 9 && oc >= 0 && oc < cin) {
+    if (ch < K && tap < 9 && oc >= 0 && oc < a.cin[l]) {
       const int row = half ? K + ch : ch;
-      v = w[((long long)row * 9 + tap) * cin + oc];
+      v = a.w[l][((long long)row * 9 + tap) * a.cin[l] + oc];
     }
-    wp[e] = (T)v;
-    if (kk == 0) bp[n] = ch < K ? b[half ? K + ch : ch] : 0.0f;
+    a.wp[l][e] = (T)v;
+    if (kk == 0) a.bp[l][n] = ch < K ? a.b[l][half ? K + ch : ch] : 0.0f;
   }
 }
 
@@ -431,9 +590,6 @@ static bool dec_plan(const vrs_decoder_desc* dd, const vrs_crop* crops, int n_cr
     P->h[l] = c.take((size_t)P->h_elems[l] * esz);
     P->pre[l] = c.take((size_t)P->pre_elems[l] * 4);
     P->dh[l] = c.take((size_t)P->h_elems[l] * 4);
-    // halo tile must fit the LDS a workgroup may use
-    const int th = dd->dtype == VRS_BF16 ? 16 : 8;
-    if ((size_t)(th + 2) * 18 * P->cin8[l] * esz > 64 * 1024) return false;
   }
   P->total = c.off;
   return true;
@@ -486,17 +642,37 @@ static void level_args(const DecPlan& P, int l, const vrs_crop* crops, int n_cro
   *blocks = tb;
 }
 
+// LDS a workgroup may allocate on the current device (queried once).
+static size_t max_lds_bytes() {
+  static size_t cached = 0;
+  if (!cached) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      cached = (size_t)v;
+    else
+      cached = 64 * 1024;
+  }
+  return cached;
+}
+
+template <typename T, int NT>
+static size_t conv_lds(const DecLevel& d) {
+  return conv_smem_bytes<T, NT>(d.cin8, d.kn);
+}
+
 template <typename T>
 static hipError_t launch_conv(const DecLevel& d, int NT, int blocks, const float* pyr,
                               const float* periph, const T* hn, const T* wp, const float* bp, T* h,
                               float* pre, const HeadFuse& hf, hipStream_t st) {
-  const int TH = DecTraits<T>::TH;
-  const size_t smem = (size_t)(TH + 2) * 18 * d.cin8 * sizeof(T);
+  const size_t need = NT == 2 ? conv_lds<T, 2>(d) : NT == 4 ? conv_lds<T, 4>(d)
+                      : NT == 6 ? conv_lds<T, 6>(d) : conv_lds<T, 8>(d);
+  if (need > max_lds_bytes()) return hipErrorInvalidValue;
   switch (NT) {
-    case 2: hipLaunchKernelGGL((k_dec_conv<T, 2>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
-    case 4: hipLaunchKernelGGL((k_dec_conv<T, 4>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
-    case 6: hipLaunchKernelGGL((k_dec_conv<T, 6>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
-    default: hipLaunchKernelGGL((k_dec_conv<T, 8>), dim3(blocks), dim3(256), smem, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    case 2: hipLaunchKernelGGL((k_dec_conv<T, 2>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    case 4: hipLaunchKernelGGL((k_dec_conv<T, 4>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    case 6: hipLaunchKernelGGL((k_dec_conv<T, 6>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    default: hipLaunchKernelGGL((k_dec_conv<T, 8>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
   }
   return hipGetLastError();
 }
@@ -506,13 +682,28 @@ static vrs_status decode_impl(const DecPlan& P, const float* pyramid, int levels
                               const float* periph, const KViews& kv, const vrs_crop* crops,
                               int n_crops, const float* weights, float* out, void* ws,
                               bool keep_pre, hipStream_t st) {
-  for (int l = 0; l < P.nd; ++l) {
-    const long long total = (long long)2 * P.kp[l] * P.kpad[l];
-    const int blocks = (int)std::min<long long>(1024, (total + 255) / 256);
-    hipLaunchKernelGGL(k_dec_pack<T>, dim3(blocks), dim3(256), 0, st, weights + P.w_off[l],
-                       weights + P.b_off[l], P.K[l], P.cin[l], P.cin8[l], P.kp[l], P.kpad[l],
-                       P.C, l + 1 < P.nd ? P.K[l + 1] : 0, l == 0 ? 1 : 0, at<T>(ws, P.wp[l]),
-                       at<float>(ws, P.bp[l]));
+  {
+    PackArgs<T> pa;
+    pa.n = P.nd;
+    pa.C = P.C;
+    long long s = 0;
+    for (int l = 0; l < P.nd; ++l) {
+      pa.K[l] = P.K[l];
+      pa.cin[l] = P.cin[l];
+      pa.cin8[l] = P.cin8[l];
+      pa.kp[l] = P.kp[l];
+      pa.kpad[l] = P.kpad[l];
+      pa.kn[l] = l + 1 < P.nd ? P.K[l + 1] : 0;
+      pa.w[l] = weights + P.w_off[l];
+      pa.b[l] = weights + P.b_off[l];
+      pa.wp[l] = at<T>(ws, P.wp[l]);
+      pa.bp[l] = at<float>(ws, P.bp[l]);
+      pa.start[l] = s;
+      s += (long long)2 * P.kp[l] * P.kpad[l];
+    }
+    pa.start[P.nd] = s;
+    const int blocks = (int)std::min<long long>(1024, (s + 255) / 256);
+    hipLaunchKernelGGL(k_dec_pack<T>, dim3(blocks), dim3(256), 0, st, pa);
     VRS_LAUNCH_CHECK();
   }
   DecLevel d;

@@ -7,29 +7,38 @@
 // that order, and sorts the fragments stably by layer pixel -- the same
 // onesweep sort the periphery uses -- so each pixel's list comes out in
 // (depth, point index) order with no atomics and no per-pixel sort.
-//   k_pt_project   one thread per point, points read once for all crops:
-//                  projection, depth cull, layer, fragment count per view
-//   scan + k_pt_compact  keep (depth key, entry) of surviving entries in
-//                  index order
-//   radix sort     by depth key (stable)
+//   k_pt_select    one thread per point, points read once for all crops:
+//                  projection, layer, crop footprints, then the depth cull
+//                  for points that reach a crop; survivors (depth key, entry,
+//                  fragment count) are compacted in the same pass
+//                  (decoupled look-back), per view in point order
+//   radix sort     of the survivors by depth key (stable)
 //   scan           fragment counts in depth order -> offsets
-//   k_pt_emit      one thread per surviving entry writes its fragments
+//   k_pt_emit      one thread per survivor writes its fragments
 //                  (layer pixel key, weight | point index)
 //   radix sort     by layer pixel key (stable)
 //   k_pt_blend     segment heads walk their pixel's list front to back
 #include <hip/hip_fp16.h>
 
+#include "lookback.h"
 #include "pt_device.h"
 
 namespace vrs {
 
 struct SplatWs {
-  size_t nfrag, zkey, scan, ckey0, cval0, ckey1, cval1, live, foffs, frag_count, fkey0, fval0,
-      fkey1, fval1, sort_tmp, scan_tmp, total;
+  size_t cent, ccnt, ckey0, cval0, ckey1, cval1, live, foffs, frag_count, fkey0, fval0, fkey1,
+      fval1, sel_tmp, sort_tmp, scan_tmp, total;
   int64_t vn, pix_total;
   int key_bits;
   bool frags_in_1;
 };
+
+constexpr int kSelBlock = 256;
+
+// look-back partition counter (256 bytes) + one status word per partition
+static size_t sel_tmp_bytes(int64_t np) {
+  return 256 + (size_t)std::max<int64_t>(1, div_up(np, kSelBlock)) * 8;
+}
 
 static int bits_for_p(int64_t n) {
   int b = 1;
@@ -58,9 +67,8 @@ static bool splat_layout(int64_t np, int nv, const vrs_crop* crops, int n_crops,
   L->frags_in_1 = (((L->key_bits + 7) / 8) & 1) != 0;
   const int64_t vn = std::max<int64_t>(L->vn, 1), mf = std::max<int64_t>(max_frags, 1);
   Carver c;
-  L->nfrag = c.take(vn * 4);
-  L->zkey = c.take(vn * 4);
-  L->scan = c.take(vn * 4);
+  L->cent = c.take(vn * 4);
+  L->ccnt = c.take(vn * 4);
   L->ckey0 = c.take(vn * 4);
   L->cval0 = c.take(vn * 4);
   L->ckey1 = c.take(vn * 4);
@@ -72,6 +80,7 @@ static bool splat_layout(int64_t np, int nv, const vrs_crop* crops, int n_crops,
   L->fval0 = c.take(mf * 8);
   L->fkey1 = c.take(mf * 4);
   L->fval1 = c.take(mf * 8);
+  L->sel_tmp = c.take(sel_tmp_bytes(np));
   L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mf, L->key_bits)));
   L->scan_tmp = c.take(scan_tmp_bytes(vn));
   L->total = c.off;
@@ -123,49 +132,110 @@ struct PtArgs {
   uint32_t view_mask;  // views that own at least one crop
 };
 
-// --------------------------------------------------------------- project
-__global__ __launch_bounds__(256) void k_pt_project(
-    const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
-    KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
-    uint32_t* __restrict__ nfrag, uint32_t* __restrict__ zkey) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const float x = pos[i], y = pos[np + i], z = pos[2 * np + i], r = radius[i];
-  for (int v = 0; v < views.n; ++v) {
-    const int64_t e = (int64_t)v * np + i;
-    uint32_t cnt = 0;
-    PtGeom g;
-    if ((a.view_mask >> v) & 1u) {
-      const KView& cv = views.v[v];
-      const int64_t plane = (int64_t)cv.W * cv.H;
-      if (pt_geom32(cv, x, y, z, r, depth ? depth + v * plane : nullptr,
-                    tfinal ? tfinal + v * plane : nullptr, a.cov_min, a.slack, a.levels, g)) {
-        for (int k = 0; k < crops.n; ++k) {
-          const KCrop& c = crops.c[k];
-          if (c.view != v) continue;
-          for (int li = 0; li < (g.two ? 2 : 1); ++li) {
-            const int l = g.l0 + li, Sl = c.size >> l;
-            float xl, yl;
-            int ix, iy;
-            if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) cnt += pt_targets(ix, iy, Sl);
-          }
-        }
-      }
+// ---------------------------------------------------------------- select
+// Fragment count of one point in view v (0 if culled): footprint targets
+// over the view's crops and the point's one or two layers, then the depth
+// cull for a point that reaches any crop.
+__device__ inline uint32_t pt_count(const KView& cv, int v, const KCrops& crops, const PtArgs& a,
+                                    float x, float y, float z, float r, const float* depth,
+                                    const float* tfinal, float& zkey_depth) {
+  PtGeom g;
+  if (!pt_geom32(cv, x, y, z, r, a.levels, g)) return 0;
+  uint32_t cnt = 0;
+  // a footprint at layer l < levels reaches at most 2^(l-1) + 1 view pixels
+  // beyond the crop, so a point farther out than 2^levels is rejected
+  // without the per-layer tests (same decisions, fewer operations)
+  const float M = (float)(1 << a.levels);
+  for (int k = 0; k < crops.n; ++k) {
+    const KCrop& c = crops.c[k];
+    if (c.view != v) continue;
+    const float ax = g.px - (float)c.x0, ay = g.py - (float)c.y0, lim = (float)c.size + M;
+    if (!(ax >= -M && ax < lim && ay >= -M && ay < lim)) continue;
+    for (int li = 0; li < (g.two ? 2 : 1); ++li) {
+      const int l = g.l0 + li, Sl = c.size >> l;
+      float xl, yl;
+      int ix, iy;
+      if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) cnt += pt_targets(ix, iy, Sl);
     }
-    nfrag[e] = cnt;
-    zkey[e] = cnt ? __float_as_uint(g.t[2]) : 0xffffffffu;
   }
+  if (cnt && tfinal && pt_occluded(cv, g, depth, tfinal, a.cov_min, a.slack)) cnt = 0;
+  zkey_depth = g.t[2];
+  return cnt;
 }
 
-__global__ void k_pt_compact(const uint32_t* __restrict__ nfrag, const uint32_t* __restrict__ zkey,
-                             const uint32_t* __restrict__ scan, int64_t vn,
-                             uint32_t* __restrict__ ckey, uint32_t* __restrict__ cval) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < vn;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (nfrag[i]) {
-      const uint32_t p = scan[i];
-      ckey[p] = zkey[i];
-      cval[p] = (uint32_t)i;
+// Partition p (taken from an atomic counter) holds points [256p, 256p+256).
+// Its survivors go out view by view, each view's in point order, after all
+// survivors of earlier partitions: within one view the compacted list is in
+// point order, which is all the later stable sorts need (fragments of
+// different views never share a pyramid pixel).
+__global__ __launch_bounds__(kSelBlock) void k_pt_select(
+    const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
+    KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
+    uint32_t* counter, uint64_t* flags, uint32_t* __restrict__ ckey, uint32_t* __restrict__ cval,
+    uint32_t* __restrict__ cent, uint32_t* __restrict__ ccnt, uint32_t* __restrict__ live,
+    int32_t* status) {
+  constexpr int NW = kSelBlock / 64;
+  __shared__ uint32_t s_part, s_base;
+  __shared__ uint32_t s_wcnt[VRS_MAX_VIEWS][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_part = atomicAdd(counter, 1u);
+  __syncthreads();
+  const int64_t part = s_part;
+  const int64_t i = part * kSelBlock + tid;
+  const bool in = i < np;
+  float x = 0, y = 0, z = 0, r = 0;
+  if (in) { x = pos[i]; y = pos[np + i]; z = pos[2 * np + i]; r = radius[i]; }
+  uint32_t cnt[VRS_MAX_VIEWS];
+  float zd[VRS_MAX_VIEWS];
+  uint64_t m[VRS_MAX_VIEWS];
+#pragma unroll
+  for (int v = 0; v < VRS_MAX_VIEWS; ++v) {
+    cnt[v] = 0;
+    zd[v] = 0.0f;
+    m[v] = 0;
+    if (v < views.n) {
+      if (in && ((a.view_mask >> v) & 1u)) {
+        const int64_t plane = (int64_t)views.v[v].W * views.v[v].H;
+        cnt[v] = pt_count(views.v[v], v, crops, a, x, y, z, r,
+                          depth ? depth + v * plane : nullptr,
+                          tfinal ? tfinal + v * plane : nullptr, zd[v]);
+      }
+      m[v] = __ballot(cnt[v] != 0);
+      if (lane == 0) s_wcnt[v][wave] = (uint32_t)__popcll(m[v]);
+    }
+  }
+  __syncthreads();
+  uint32_t total = 0;
+  for (int v = 0; v < views.n; ++v)
+#pragma unroll
+    for (int w = 0; w < NW; ++w) total += s_wcnt[v][w];
+  if (wave == 0) {
+    const uint32_t excl = wave_lookback(flags, part, total, status);
+    if (lane == 0) {
+      s_base = excl;
+      if (part == (int64_t)gridDim.x - 1) *live = excl + total;
+    }
+  }
+  __syncthreads();
+  uint32_t off = s_base;
+#pragma unroll
+  for (int v = 0; v < VRS_MAX_VIEWS; ++v) {
+    if (v < views.n) {
+      uint32_t o = off;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        if (w < wave) o += s_wcnt[v][w];
+        off += s_wcnt[v][w];
+      }
+      if (cnt[v]) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m[v] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[v], 0u));
+        const uint32_t p = o + below;
+        ckey[p] = __float_as_uint(zd[v]);
+        cval[p] = p;
+        cent[p] = (uint32_t)(v * np + i);
+        ccnt[p] = cnt[v];
+      }
     }
   }
 }
@@ -173,8 +243,8 @@ __global__ void k_pt_compact(const uint32_t* __restrict__ nfrag, const uint32_t*
 // ------------------------------------------------------------------ emit
 __global__ __launch_bounds__(256) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
-    KCrops crops, PtArgs a, const uint32_t* __restrict__ sorted_e,
-    const uint32_t* __restrict__ live_p, const uint32_t* __restrict__ foffs,
+    KCrops crops, PtArgs a, const uint32_t* __restrict__ sorted_c,
+    const uint32_t* __restrict__ cent, const uint32_t* __restrict__ live_p, const uint32_t* __restrict__ foffs,
     const uint32_t* __restrict__ total_p, int64_t max_frags, uint32_t* __restrict__ fkey,
     uint64_t* __restrict__ fval, int32_t* status) {
   const int64_t live = *live_p;
@@ -182,16 +252,14 @@ __global__ __launch_bounds__(256) void k_pt_emit(
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t e = sorted_e[j];
+    const uint32_t e = cent[sorted_c[j]];
     const int v = (int)(e / np);
     const int64_t i = e - (int64_t)v * np;
     const KView& cv = views.v[v];
     PtGeom g;
-    // the depth test already passed in k_pt_project; recomputing the same
-    // single-precision sequence without it gives identical geometry
-    if (!pt_geom32(cv, pos[i], pos[np + i], pos[2 * np + i], radius[i], nullptr, nullptr,
-                   a.cov_min, a.slack, a.levels, g))
-      continue;
+    // the depth cull already passed in k_pt_select; the same single-precision
+    // sequence gives identical geometry here
+    if (!pt_geom32(cv, pos[i], pos[np + i], pos[2 * np + i], radius[i], a.levels, g)) continue;
     float f = 0.0f;
     if (g.two) f = log2f(g.s) - (float)g.l0;
     int64_t o = foffs[j];
@@ -342,31 +410,27 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
     trace_end(VRS_TRACE_SPLAT, st);
     return VRS_OK;
   }
-  uint32_t* nfrag = at<uint32_t>(ws, L.nfrag);
-  uint32_t* zkey = at<uint32_t>(ws, L.zkey);
-  uint32_t* scan = at<uint32_t>(ws, L.scan);
   uint32_t* live = at<uint32_t>(ws, L.live);
-  hipLaunchKernelGGL(k_pt_project, dim3(div_up(np, 256)), dim3(256), 0, st, pos, radius, np, kv,
-                     kc, a, depth, t_final, nfrag, zkey);
-  VRS_LAUNCH_CHECK();
-  // surviving entries, kept in index order
-  VRS_HIP_CHECK(exclusive_scan_flags_u32(nfrag, scan, live, vn, at<void>(ws, L.scan_tmp),
-                                         dev_status, st));
-  hipLaunchKernelGGL(k_pt_compact, dim3((unsigned)std::min<int64_t>(8192, div_up(vn, 256))),
-                     dim3(256), 0, st, nfrag, zkey, scan, vn, at<uint32_t>(ws, L.ckey0),
-                     at<uint32_t>(ws, L.cval0));
+  uint32_t* sel_counter = at<uint32_t>(ws, L.sel_tmp);
+  uint64_t* sel_flags = at<uint64_t>(ws, L.sel_tmp + 256);
+  const int sel_parts = div_up(np, kSelBlock);
+  VRS_HIP_CHECK(fill_u32(sel_counter, 0, (int64_t)(sel_tmp_bytes(np) / 4), st));
+  hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), 0, st, pos, radius, np, kv,
+                     kc, a, depth, t_final, sel_counter, sel_flags, at<uint32_t>(ws, L.ckey0),
+                     at<uint32_t>(ws, L.cval0), at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt),
+                     live, dev_status);
   VRS_LAUNCH_CHECK();
   bool c1 = false;
   VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.ckey0), at<uint32_t>(ws, L.cval0),
                                at<uint32_t>(ws, L.ckey1), at<uint32_t>(ws, L.cval1), live, vn, 32,
                                at<void>(ws, L.sort_tmp), dev_status, st, &c1));
-  const uint32_t* sorted_e = at<uint32_t>(ws, c1 ? L.cval1 : L.cval0);
-  VRS_HIP_CHECK(exclusive_scan_u32(nfrag, sorted_e, at<uint32_t>(ws, L.foffs), frag_count, live,
-                                   vn, at<void>(ws, L.scan_tmp), dev_status, st));
+  const uint32_t* sorted_c = at<uint32_t>(ws, c1 ? L.cval1 : L.cval0);
+  VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.ccnt), sorted_c, at<uint32_t>(ws, L.foffs),
+                                   frag_count, live, vn, at<void>(ws, L.scan_tmp), dev_status, st));
   hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)std::min<int64_t>(8192, div_up(vn, 256))),
-                     dim3(256), 0, st, pos, radius, np, kv, kc, a, sorted_e, live,
-                     at<uint32_t>(ws, L.foffs), frag_count, max_frags, at<uint32_t>(ws, L.fkey0),
-                     at<uint64_t>(ws, L.fval0), dev_status);
+                     dim3(256), 0, st, pos, radius, np, kv, kc, a, sorted_c,
+                     at<uint32_t>(ws, L.cent), live, at<uint32_t>(ws, L.foffs), frag_count,
+                     max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0), dev_status);
   VRS_LAUNCH_CHECK();
   bool f1 = false;
   VRS_HIP_CHECK(radix_sort_u64(at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
@@ -471,8 +535,7 @@ __global__ __launch_bounds__(256) void k_pt_blend_bwd(
       if ((d_pos || d_radius) && dw != 0.0f) {
         const KView& cv = views.v[c.view];
         PtGeom pg;
-        if (!pt_geom32(cv, pos[id], pos[np + id], pos[2 * np + id], radius[id], nullptr,
-                       nullptr, a.cov_min, a.slack, a.levels, pg))
+        if (!pt_geom32(cv, pos[id], pos[np + id], pos[2 * np + id], radius[id], a.levels, pg))
           continue;
         float xl, yl;
         int ix, iy;

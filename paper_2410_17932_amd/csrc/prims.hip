@@ -7,7 +7,7 @@
 // on has already started.  Every wait is bounded (kSpinLimit polls); on
 // expiry the kernel records VRS_ETIMEOUT in the status word and proceeds, so
 // every wave always exits.
-#include "vrs_common.h"
+#include "lookback.h"
 
 namespace vrs {
 namespace {
@@ -25,12 +25,6 @@ __device__ inline uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void st_agent(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline uint64_t ld_agent64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void st_agent64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -52,7 +46,6 @@ __global__ void k_fill(uint32_t* p, uint32_t v, int64_t n) {
 
 // ------------------------------------------------------------------ scan
 constexpr int kScanBlock = 256, kScanItems = 8, kScanTile = kScanBlock * kScanItems;
-constexpr uint64_t kFlagAgg = 1ull << 32, kFlagPre = 2ull << 32;
 
 __global__ void k_scan_clear(uint32_t* counter, uint64_t* flags, const uint32_t* n_dev,
                              int64_t n_max) {
@@ -63,6 +56,9 @@ __global__ void k_scan_clear(uint32_t* counter, uint64_t* flags, const uint32_t*
   for (; i < parts; i += (int64_t)gridDim.x * blockDim.x) flags[i] = 0;
 }
 
+// Thread t of a partition owns items [8t, 8t + 8) of it; when the input is
+// read directly (no index) and 16-byte aligned, they come in as two 16-byte
+// loads.
 __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict__ in,
                                                       const uint32_t* __restrict__ idx,
                                                       uint32_t* __restrict__ out,
@@ -73,24 +69,37 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
   __shared__ uint32_t s_part, s_prefix;
   __shared__ uint32_t s_wsum[kScanBlock / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the grid is sized for n_max; blocks beyond the partitions n needs leave
+  // before taking a partition id, so exactly those take ids 0..parts-1
+  const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
+  if ((int64_t)blockIdx.x * kScanTile >= n) return;
   if (tid == 0) s_part = atomicAdd(counter, 1u);
   __syncthreads();
   const int64_t part = s_part;
-  const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
   const int64_t base = part * kScanTile;
-  if (base >= n) return;
+  const int64_t i0 = base + (int64_t)tid * kScanItems;
+  uint32_t x[kScanItems];
+  if (!idx && i0 + kScanItems <= n && (reinterpret_cast<uintptr_t>(in) & 15) == 0) {
+    const uint4 a = *reinterpret_cast<const uint4*>(in + i0);
+    const uint4 b = *reinterpret_cast<const uint4*>(in + i0 + 4);
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = i0 + j;
+      x[j] = i < n ? (idx ? in[idx[i]] : in[i]) : 0u;
+    }
+  }
   uint32_t v[kScanItems];
   uint32_t sum = 0;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    int64_t i = base + (int64_t)tid * kScanItems + j;
-    uint32_t x = 0;
-    if (i < n) x = idx ? in[idx[i]] : in[i];
-    if (flags_mode) x = x != 0u;
+    const uint32_t xj = flags_mode ? (x[j] != 0u ? 1u : 0u) : x[j];
     v[j] = sum;
-    sum += x;
+    sum += xj;
   }
-  uint32_t incl = wave_incl_scan(sum);
+  const uint32_t incl = wave_incl_scan(sum);
   if (lane == 63) s_wsum[wave] = incl;
   __syncthreads();
   uint32_t woff = 0, btot = 0;
@@ -99,36 +108,23 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
     if (w < wave) woff += s_wsum[w];
     btot += s_wsum[w];
   }
-  if (tid == 0) {
-    uint32_t excl = 0;
-    if (part == 0) {
-      st_agent64(&flags[0], kFlagPre | btot);
-    } else {
-      st_agent64(&flags[part], kFlagAgg | btot);
-      int64_t p = part - 1;
-      int spins = 0;
-      while (p >= 0) {
-        uint64_t w = ld_agent64(&flags[p]);
-        if ((w >> 32) == 0) {
-          if (++spins > kSpinLimit) { set_status(status, VRS_ETIMEOUT); break; }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += (uint32_t)w;
-        if ((w & kFlagPre) != 0) break;
-        --p;
-      }
-      st_agent64(&flags[part], kFlagPre | (uint64_t)(excl + btot));
+  if (wave == 0) {
+    const uint32_t excl = wave_lookback(flags, part, btot, status);
+    if (lane == 0) {
+      s_prefix = excl;
+      if (total && base + kScanTile >= n) *total = excl + btot;
     }
-    s_prefix = excl;
-    if (total && base + kScanTile >= n) *total = excl + btot;
   }
   __syncthreads();
   const uint32_t off = s_prefix + woff + (incl - sum);
+  if (i0 + kScanItems <= n && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+    *reinterpret_cast<uint4*>(out + i0) = make_uint4(off + v[0], off + v[1], off + v[2], off + v[3]);
+    *reinterpret_cast<uint4*>(out + i0 + 4) =
+        make_uint4(off + v[4], off + v[5], off + v[6], off + v[7]);
+  } else {
 #pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    int64_t i = base + (int64_t)tid * kScanItems + j;
-    if (i < n) out[i] = off + v[j];
+    for (int j = 0; j < kScanItems; ++j)
+      if (i0 + j < n) out[i0 + j] = off + v[j];
   }
 }
 
@@ -149,6 +145,24 @@ __global__ void k_sort_clear(uint32_t* hist, int passes, uint32_t* lookback, int
     for (int64_t i = i0; i < per; i += stride) lookback[p * parts_max * 256 + i] = 0;
 }
 
+// Digit histograms of every pass in one read of the keys.  A thread takes
+// 16 consecutive keys per round (four 16-byte loads in flight).  Keys often
+// come in runs (pairs of one Gaussian, pixels of one point), so where all
+// active lanes of a wave hold the same digit the wave adds once.
+constexpr int kHistItems = 16;
+__device__ inline void hist_add(uint32_t (*s_h)[256], uint32_t k, int passes, uint64_t active,
+                                bool leader) {
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t d = (k >> (8 * p)) & 255u;
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    if (__ballot(d != d0) == 0) {
+      if (leader) atomicAdd(&s_h[p][d0], (uint32_t)__popcll(active));
+    } else {
+      atomicAdd(&s_h[p][d], 1u);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ keys,
                                                     const uint32_t* n_dev, int64_t n_max,
                                                     int passes, uint32_t* hist) {
@@ -157,10 +171,29 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ 
   for (int p = 0; p < 4; ++p) s_h[p][tid] = 0;
   __syncthreads();
   const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + tid; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
+  const bool aligned = (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x * kHistItems;
+  for (int64_t i0 = (blockIdx.x * (int64_t)blockDim.x + tid) * kHistItems; i0 < n; i0 += step) {
+    if (aligned && i0 + kHistItems <= n) {
+      const uint64_t active = __ballot(true);   // lanes on this branch
+      const bool leader = count_below(active) == 0;
+      uint4 q[kHistItems / 4];
+#pragma unroll
+      for (int j = 0; j < kHistItems / 4; ++j) q[j] = *reinterpret_cast<const uint4*>(keys + i0 + 4 * j);
+#pragma unroll
+      for (int j = 0; j < kHistItems / 4; ++j) {
+        hist_add(s_h, q[j].x, passes, active, leader);
+        hist_add(s_h, q[j].y, passes, active, leader);
+        hist_add(s_h, q[j].z, passes, active, leader);
+        hist_add(s_h, q[j].w, passes, active, leader);
+      }
+    } else {
+      for (int j = 0; j < kHistItems; ++j) {
+        if (i0 + j >= n) break;
+        const uint32_t k = keys[i0 + j];
+        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
+      }
+    }
   }
   __syncthreads();
   for (int p = 0; p < passes; ++p)
@@ -179,14 +212,15 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
   __shared__ V s_vals[kSortTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = 8 * pass;
+  // blocks beyond the partitions n needs leave before taking an id
+  const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
+  if ((int64_t)blockIdx.x * kSortTile >= n) return;
   if (tid == 0) s_part = atomicAdd(&counters[pass], 1u);
 #pragma unroll
   for (int w = 0; w < kSortWaves; ++w) s_wh[w][tid] = 0;
   __syncthreads();
   const int64_t part = s_part;
-  const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
   const int64_t base = part * kSortTile;
-  if (base >= n) return;
 
   // load: wave w owns [base + w*960, +960); item j of lane l at j*64 + l
   uint32_t key[kSortItems];
@@ -250,21 +284,42 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
   uint32_t hoff = 0;
   for (int w = 0; w < wave; ++w) hoff += s_scan[w];
   const uint32_t gdig = hoff + hincl - h;
-  // decoupled look-back for digit d
+  // decoupled look-back for digit d: eight predecessors are read per round
+  // (independent loads in flight), consumed in order until an inclusive
+  // prefix is met; a word not yet published ends the round and is re-read
   uint32_t excl = 0;
   if (part > 0) {
+    constexpr int kWin = 8;
     int64_t p = part - 1;
     int spins = 0;
-    while (p >= 0) {
-      uint32_t w = ld_agent(&lb[p * 256 + d]);
-      if ((w & (kLbAgg | kLbPre)) == 0) {
-        if (++spins > kSpinLimit) { set_status(status, VRS_ETIMEOUT); break; }
-        __builtin_amdgcn_s_sleep(1);
-        continue;
+    bool found = false;
+    while (!found) {
+      uint32_t w[kWin];
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) w[k] = p - k >= 0 ? ld_agent(&lb[(p - k) * 256 + d]) : kLbPre;
+      int used = kWin;
+      bool stall = false;
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) {
+        if (!found && !stall) {
+          if ((w[k] & (kLbAgg | kLbPre)) == 0) {
+            stall = true;
+            used = k;
+          } else {
+            excl += w[k] & kLbVal;
+            found = (w[k] & kLbPre) != 0;
+          }
+        }
       }
-      excl += w & kLbVal;
-      if (w & kLbPre) break;
-      --p;
+      if (found) break;
+      p -= used;
+      if (stall) {
+        if (++spins > kSpinLimit) {
+          set_status(status, VRS_ETIMEOUT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
     }
     st_agent(&lb[part * 256 + d], kLbPre | (excl + cnt));
   }
@@ -305,7 +360,7 @@ hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint3
   int clear_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (parts * 256 + 255) / 256));
   hipLaunchKernelGGL(k_sort_clear, dim3(clear_blocks), dim3(256), 0, st, hist, passes, lookback,
                      parts, n_dev, n_max);
-  int hist_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n_max + 4095) / 4096));
+  int hist_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_max + 4095) / 4096));
   hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, st, k0, n_dev, n_max, passes,
                      hist);
   uint32_t* kb[2] = {k0, k1};

@@ -14,13 +14,11 @@ struct PtGeom {
   bool two;
 };
 
-// Projection, depth-occlusion cull and pyramid layer of one point in view
-// cv (Sec. 3.3), single precision in the documented operation order.
-// depth/tfinal point at the view's planes (or are null: no depth cull).
-// Returns false if the point is culled.
+// Projection and pyramid layer of one point in view cv (Sec. 3.3), single
+// precision in the documented operation order.  Returns false if the point
+// is culled by the near plane or projects to a non-finite position or size.
 __device__ inline bool pt_geom32(const KView& cv, float x, float y, float z, float radius,
-                                 const float* depth, const float* tfinal, float cov_min,
-                                 float slack, int levels, PtGeom& g) {
+                                 int levels, PtGeom& g) {
 #pragma clang fp contract(off)
   for (int i = 0; i < 3; ++i) {
     float a = cv.R[3 * i + 0] * x;
@@ -37,16 +35,6 @@ __device__ inline bool pt_geom32(const KView& cv, float x, float y, float z, flo
   g.px = fxu + cv.cx;
   g.py = fyu + cv.cy;
   if (!(isfinite(g.px) && isfinite(g.py))) return false;
-  if (tfinal && g.px >= 0.0f && g.px < (float)cv.W && g.py >= 0.0f && g.py < (float)cv.H) {
-    const int X = (int)floorf(g.px), Y = (int)floorf(g.py);
-    const int64_t pi = (int64_t)Y * cv.W + X;
-    const float A = 1.0f - tfinal[pi];
-    if (A >= cov_min) {
-      const float q = depth[pi] / A;
-      const float lim = slack * q;
-      if (g.t[2] > lim) return false;
-    }
-  }
   const float f2 = 2.0f * cv.fx;
   const float num = f2 * radius;
   g.s = num / g.t[2];
@@ -61,6 +49,25 @@ __device__ inline bool pt_geom32(const KView& cv, float x, float y, float z, flo
     else g.two = m > 0.5f;
   }
   return true;
+}
+
+// Depth-occlusion cull against the periphery's approximate depth (Eq. 1)
+// at the pixel under the point: where the periphery's coverage 1 - T' is at
+// least cov_min, a point farther than slack x (depth / coverage) is hidden.
+// depth/tfinal point at the view's planes.  Every other culling test is
+// independent of this one, so callers run it last, only for points that
+// reach a crop.
+__device__ inline bool pt_occluded(const KView& cv, const PtGeom& g, const float* depth,
+                                   const float* tfinal, float cov_min, float slack) {
+#pragma clang fp contract(off)
+  if (!(g.px >= 0.0f && g.px < (float)cv.W && g.py >= 0.0f && g.py < (float)cv.H)) return false;
+  const int X = (int)floorf(g.px), Y = (int)floorf(g.py);
+  const int64_t pi = (int64_t)Y * cv.W + X;
+  const float A = 1.0f - tfinal[pi];
+  if (!(A >= cov_min)) return false;
+  const float q = depth[pi] / A;
+  const float lim = slack * q;
+  return g.t[2] > lim;
 }
 
 // Layer-l coordinates of the point in a crop with origin (x0, y0) and the
