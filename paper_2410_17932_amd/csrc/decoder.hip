@@ -162,15 +162,19 @@ __device__ inline void copy8(T* dst, const T* src) {
 }
 
 // Geometry of one workgroup's LDS: halo tile, the coarser level's footprint
-// and two weight chunks of CHS k-steps (8 KB each).
-template <typename T, int NT>
+// and the weights.  ONE: the whole weight operand (up to 24 KB) is loaded
+// once, at the start, overlapping the halo fill; otherwise two 8 KB chunks
+// of CHS k-steps are double-buffered.
+template <typename T, int NT, bool ONE>
 struct ConvCfg {
   static constexpr int TH = DecTraits<T>::TH, KSTEP = DecTraits<T>::KSTEP;
   static constexpr int NPIX = (TH + 2) * 18;
   static constexpr int CR = TH / 2 + 2, CC = 10;       // coarse rows / columns staged
   static constexpr int NOUT = NT * 16;
-  static constexpr int CHS = 8192 / (NOUT * KSTEP * (int)sizeof(T)) > 0
-                                 ? 8192 / (NOUT * KSTEP * (int)sizeof(T)) : 1;
+  static constexpr int NBUF = ONE ? 1 : 2;
+  static constexpr int CBYTES = ONE ? 24576 : 8192;
+  static constexpr int CHS = CBYTES / (NOUT * KSTEP * (int)sizeof(T)) > 0
+                                 ? CBYTES / (NOUT * KSTEP * (int)sizeof(T)) : 1;
   static constexpr int CK = CHS * KSTEP;                // k per chunk
   static constexpr int BROW = CK + 16 / (int)sizeof(T); // padded LDS row (elements)
   static constexpr int PPR = CK * (int)sizeof(T) / 16;  // 16-byte pieces per row
@@ -180,15 +184,16 @@ struct ConvCfg {
 
 // The weight chunks reuse the coarse footprint's LDS once the halo tile is
 // filled.
-template <typename T, int NT>
+template <typename T, int NT, bool ONE>
 __host__ __device__ inline size_t conv_smem_bytes(int cin8, int kn) {
-  using Cfg = ConvCfg<T, NT>;
+  using Cfg = ConvCfg<T, NT, ONE>;
   const size_t kn8 = (size_t)((kn + 7) & ~7);
-  const size_t coarse = (size_t)Cfg::CR * Cfg::CC * kn8, wchunks = (size_t)2 * Cfg::NOUT * Cfg::BROW;
+  const size_t coarse = (size_t)Cfg::CR * Cfg::CC * kn8;
+  const size_t wchunks = (size_t)Cfg::NBUF * Cfg::NOUT * Cfg::BROW;
   return ((size_t)Cfg::NPIX * cin8 + (coarse > wchunks ? coarse : wchunks)) * sizeof(T);
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool ONE>
 __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
                                                   const float* __restrict__ periph,
                                                   const T* __restrict__ hnext,
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
                                                   const float* __restrict__ bp,
                                                   T* __restrict__ hout, float* __restrict__ pre,
                                                   HeadFuse hf) {
-  using Cfg = ConvCfg<T, NT>;
+  using Cfg = ConvCfg<T, NT, ONE>;
   constexpr int TH = Cfg::TH, RPW = TH / 4, KSTEP = Cfg::KSTEP, NPIX = Cfg::NPIX;
   constexpr int CR = Cfg::CR, CC = Cfg::CC, NOUT = Cfg::NOUT, CHS = Cfg::CHS, CK = Cfg::CK;
   constexpr int BROW = Cfg::BROW;
@@ -344,8 +349,8 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
   const int r0 = wave * RPW;
   const int col = lane & 15, kq = lane >> 4;
   for (int c = 0; c < nchunks; ++c) {
-    if (c + 1 < nchunks) load_chunk(c + 1);
-    const T* B = sB + (c & 1) * NOUT * BROW;
+    if (!ONE && c + 1 < nchunks) load_chunk(c + 1);
+    const T* B = sB + (ONE ? 0 : (c & 1)) * NOUT * BROW;
 #pragma unroll
     for (int s = 0; s < CHS; ++s) {
       const int ks = c * CHS + s;
@@ -387,8 +392,10 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
         }
       }
     }
-    if (c + 1 < nchunks) store_chunk((c + 1) & 1);
-    __syncthreads();
+    if (!ONE) {
+      if (c + 1 < nchunks) store_chunk((c + 1) & 1);
+      __syncthreads();
+    }
   }
   // ---- gated epilogue.  The weights are the MFMA's A operand, so lane
   // (col, kq) holds channels 4 kq + i (i < 4) of N-tile j for the pixel in
@@ -657,24 +664,34 @@ static size_t max_lds_bytes() {
 }
 
 template <typename T, int NT>
-static size_t conv_lds(const DecLevel& d) {
-  return conv_smem_bytes<T, NT>(d.cin8, d.kn);
+static hipError_t launch_nt(const DecLevel& d, int blocks, const float* pyr, const float* periph,
+                            const T* hn, const T* wp, const float* bp, T* h, float* pre,
+                            const HeadFuse& hf, hipStream_t st) {
+  // the whole weight operand in one LDS chunk when it fits
+  using One = ConvCfg<T, NT, true>;
+  const bool one = d.kpad <= One::CK;
+  const size_t need = one ? conv_smem_bytes<T, NT, true>(d.cin8, d.kn)
+                          : conv_smem_bytes<T, NT, false>(d.cin8, d.kn);
+  if (need > max_lds_bytes()) return hipErrorInvalidValue;
+  if (one)
+    hipLaunchKernelGGL((k_dec_conv<T, NT, true>), dim3(blocks), dim3(256), need, st, d, pyr,
+                       periph, hn, wp, bp, h, pre, hf);
+  else
+    hipLaunchKernelGGL((k_dec_conv<T, NT, false>), dim3(blocks), dim3(256), need, st, d, pyr,
+                       periph, hn, wp, bp, h, pre, hf);
+  return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_conv(const DecLevel& d, int NT, int blocks, const float* pyr,
                               const float* periph, const T* hn, const T* wp, const float* bp, T* h,
                               float* pre, const HeadFuse& hf, hipStream_t st) {
-  const size_t need = NT == 2 ? conv_lds<T, 2>(d) : NT == 4 ? conv_lds<T, 4>(d)
-                      : NT == 6 ? conv_lds<T, 6>(d) : conv_lds<T, 8>(d);
-  if (need > max_lds_bytes()) return hipErrorInvalidValue;
   switch (NT) {
-    case 2: hipLaunchKernelGGL((k_dec_conv<T, 2>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
-    case 4: hipLaunchKernelGGL((k_dec_conv<T, 4>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
-    case 6: hipLaunchKernelGGL((k_dec_conv<T, 6>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
-    default: hipLaunchKernelGGL((k_dec_conv<T, 8>), dim3(blocks), dim3(256), need, st, d, pyr, periph, hn, wp, bp, h, pre, hf); break;
+    case 2: return launch_nt<T, 2>(d, blocks, pyr, periph, hn, wp, bp, h, pre, hf, st);
+    case 4: return launch_nt<T, 4>(d, blocks, pyr, periph, hn, wp, bp, h, pre, hf, st);
+    case 6: return launch_nt<T, 6>(d, blocks, pyr, periph, hn, wp, bp, h, pre, hf, st);
+    default: return launch_nt<T, 8>(d, blocks, pyr, periph, hn, wp, bp, h, pre, hf, st);
   }
-  return hipGetLastError();
 }
 
 template <typename T>
