@@ -192,6 +192,38 @@ __device__ inline uint32_t halfwave_lower_bound(const uint32_t* __restrict__ key
 // stopped; the block leaves the list when every wave has.  The tile's
 // [begin, end) in the sorted pair list is found by a half-wave search and
 // stored for the backward pass.
+// A 64-bit value known to be equal in every lane, moved to scalar registers
+// (the builtin returns a signed 32-bit int: each half goes through uint32_t
+// so that the low half is not sign-extended into the high one).
+__device__ inline uint64_t wave_uniform_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Lower bound of G(d) = ga dx^2 + gb dx dy + gc dy^2 (positive definite)
+// over the box dx in [X0, X1], dy in [Y0, Y1]: 0 if the box holds the
+// origin, else the least of the four edge minima (the minimiser of a convex
+// quadratic over a box lies on its boundary; on an edge it is the clamped
+// stationary point).
+__device__ inline float box_min_quadratic(float ga, float gb, float gc, float X0, float X1,
+                                          float Y0, float Y1) {
+  if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
+  const float ia = 0.5f / ga, ic = 0.5f / gc;
+  float m = 3.0e38f;
+  float Xe[2] = {X0, X1}, Ye[2] = {Y0, Y1};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float X = Xe[i];
+    const float dy = fminf(fmaxf(-gb * X * ic, Y0), Y1);
+    m = fminf(m, ga * X * X + gb * X * dy + gc * dy * dy);
+    const float Y = Ye[i];
+    const float dx = fminf(fmaxf(-gb * Y * ia, X0), X1);
+    m = fminf(m, ga * dx * dx + gb * dx * Y + gc * Y * Y);
+  }
+  return m;
+}
+
 template <int TILE, int SUB>
 struct BlendCfg {
   static constexpr int NQ = TILE / SUB;          // sub-tiles per side
@@ -212,7 +244,8 @@ __global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK)) void k_gs_blend(
   using Cfg = BlendCfg<TILE, SUB>;
   constexpr int BLOCK = Cfg::BLOCK, PPT = Cfg::PPT, NW = Cfg::NW, NQ = Cfg::NQ;
   __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK];
-  __shared__ uint64_t s_mask[NW][NW];   // [sub-tile][group of 64 records]
+  __shared__ uint64_t s_mask[NW][NW];   // [sub-tile][group of 64 records]: rectangle reaches it
+  __shared__ uint64_t s_full[NW][NW];   // ... and the contributing ellipse may too
   __shared__ uint32_t s_range[2];
   const int64_t tglob = blockIdx.x;
   const int v = (int)(tglob / tiles_per_view);
@@ -264,6 +297,11 @@ __global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK)) void k_gs_blend(
     const uint32_t jr = b0 + tid;
     bool has = jr < end;
     int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
+    // contributing region: alpha >= alpha_min <=> G(d) = -q(d) <= log2(op /
+    // alpha_min); thr carries a margin far above the rounding of q so that a
+    // sub-tile is declared out of reach only where every pixel's own test
+    // would fail
+    float cx = 0.0f, cy = 0.0f, ga = 1.0f, gb = 0.0f, gc = 1.0f, thr = -1.0f;
     if (has) {
       const uint32_t id = ids[jr];
       const int64_t e = (int64_t)v * n + (id < (uint64_t)n ? id : 0);
@@ -275,24 +313,53 @@ __global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK)) void k_gs_blend(
       const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
       x0 = (int)(lo & 0xffffu); y0 = (int)(lo >> 16);
       x1 = (int)(hi & 0xffffu); y1 = (int)(hi >> 16);
+      cx = a.x; cy = a.y;
+      ga = -a.z; gb = -a.w; gc = -b.x;
+      thr = b.y >= amin ? log2f(b.y / amin) * 1.001f + 1.0e-3f : -1.0f;
+      if (!(ga > 0.0f && gc > 0.0f)) thr = 3.0e38f;   // never declared out of reach
     }
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       const int qx0 = tx * TILE + (w % NQ) * SUB, qy0 = ty * TILE + (w / NQ) * SUB;
-      const bool hit = has && x0 <= qx0 + SUB - 1 && x1 >= qx0 && y0 <= qy0 + SUB - 1 && y1 >= qy0;
-      const uint64_t m = __ballot(hit);
-      if (lane == 0) s_mask[w][wave] = m;
+      const int xlo = max(x0, qx0), xhi = min(x1, qx0 + SUB - 1);
+      const int ylo = max(y0, qy0), yhi = min(y1, qy0 + SUB - 1);
+      const bool hit = has && xlo <= xhi && ylo <= yhi;
+      bool full = false;
+      if (hit) {
+        // d = centre - pixel centre over the pixel centres of the overlap
+        const float g = box_min_quadratic(ga, gb, gc, cx - ((float)xhi + 0.5f),
+                                          cx - ((float)xlo + 0.5f), cy - ((float)yhi + 0.5f),
+                                          cy - ((float)ylo + 0.5f));
+        full = !(g > thr);
+      }
+      const uint64_t m = __ballot(hit), mf = __ballot(full);
+      if (lane == 0) {
+        s_mask[w][wave] = m;
+        s_full[w][wave] = mf;
+      }
     }
     __syncthreads();
     if (!alive) continue;
     for (int g = 0; g < NW && alive; ++g) {
-      const uint64_t mv = s_mask[wave][g];
-      uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)mv);
-      uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mv >> 32));
-      uint64_t m = ((uint64_t)mhi << 32) | mlo;
+      uint64_t m = wave_uniform_u64(s_mask[wave][g]);
+      const uint64_t mfull = wave_uniform_u64(s_full[wave][g]);
       while (m) {
-        const int k = g * 64 + __builtin_ctzll(m);
+        const int bit = __builtin_ctzll(m);
+        const int k = g * 64 + bit;
         m &= m - 1;
+        if (((mfull >> bit) & 1ull) == 0) {
+          // out of reach of the ellipse: no pixel here can pass alpha_min, so
+          // only the evaluation count of in-rectangle live pixels moves
+          const float4 b = s_b[k];
+          const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
+          const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
+          const bool inx = (uint32_t)(px - rx0) <= (uint32_t)((int)(hi & 0xffffu) - rx0);
+          const uint32_t ry_span = (uint32_t)((int)(hi >> 16) - ry0);
+#pragma unroll
+          for (int q = 0; q < PPT; ++q)
+            evals[q] += (inx & ((uint32_t)(ry[q] - ry0) <= ry_span)) ? 1u : 0u;
+          continue;
+        }
         const float4 a = s_a[k], b = s_b[k], c = s_c[k];
         const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
         const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
