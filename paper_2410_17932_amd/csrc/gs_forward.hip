@@ -233,8 +233,12 @@ struct BlendCfg {
   static constexpr int ROWS = 64 / SUB;          // rows between a lane's pixels
 };
 
+// Register budget for five waves per SIMD (96 VGPRs; no spills): the
+// staging and the per-pixel state compete for registers, and occupancy hides
+// the LDS and gather latency better than the extra registers would help.
 template <int TILE, int SUB>
-__global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK)) void k_gs_blend(
+__global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK))
+__attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ids,
     const uint32_t* __restrict__ total_p, int64_t max_pairs, const float4* __restrict__ rec,
     int64_t n, KViews views, GsOpt o, int64_t tiles_x, int64_t tiles_per_view,
