@@ -348,6 +348,13 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
     for (int j = 0; j < NT; ++j) acc[r][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   const int r0 = wave * RPW;
   const int col = lane & 15, kq = lane >> 4;
+  // this lane's k position as (tap, channel unit): unit = 8-channel group
+  // (BF16, 4 lanes x 8 = one k-step of 32) or channel (FP32, 4 per k-step);
+  // advanced by 4 units per k-step without divisions
+  const int units = sizeof(T) == 2 ? (cin8 >> 3) : cin8;
+  int tap = 0, cu = kq;
+  while (cu >= units) { cu -= units; ++tap; }
+  int dy = tap / 3, dx = tap - 3 * (tap / 3);
   for (int c = 0; c < nchunks; ++c) {
     if (!ONE && c + 1 < nchunks) load_chunk(c + 1);
     const T* B = sB + (ONE ? 0 : (c & 1)) * NOUT * BROW;
@@ -356,15 +363,12 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
       const int ks = c * CHS + s;
       if (ks >= nsteps) break;
       if constexpr (sizeof(T) == 2) {
-        const int g8 = cin8 >> 3;
-        const int gi = ks * 4 + kq;
-        const int tap = gi / g8, cg = gi - tap * g8;
-        const int dy = tap / 3, dx = tap - dy * 3;
+        const int abase = ((r0 + dy) * 18 + col + dx) * cin8 + cu * 8;
         v8bf a[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
           if (tap < 9)
-            a[r] = *reinterpret_cast<const v8bf*>(&tile[((r0 + r + dy) * 18 + col + dx) * cin8 + cg * 8]);
+            a[r] = *reinterpret_cast<const v8bf*>(&tile[abase + r * 18 * cin8]);
           else
             a[r] = v8bf{0, 0, 0, 0, 0, 0, 0, 0};
         }
@@ -376,19 +380,27 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
             acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[r], acc[r][j], 0, 0, 0);
         }
       } else {
-        const int kk = ks * 4 + kq;
-        const int tap = kk / cin8, cc = kk - tap * cin8;
-        const int dy = tap / 3, dx = tap - dy * 3;
+        const int abase = ((r0 + dy) * 18 + col + dx) * cin8 + cu;
         float a[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r)
-          a[r] = tap < 9 ? to_f(tile[((r0 + r + dy) * 18 + col + dx) * cin8 + cc]) : 0.0f;
+          a[r] = tap < 9 ? to_f(tile[abase + r * 18 * cin8]) : 0.0f;
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const float b = to_f(B[(j * 16 + col) * BROW + s * KSTEP + kq]);
 #pragma unroll
           for (int r = 0; r < RPW; ++r)
             acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a[r], acc[r][j], 0, 0, 0);
+        }
+      }
+      // next k-step: four units further
+      cu += 4;
+      while (cu >= units) {
+        cu -= units;
+        ++tap;
+        if (++dx == 3) {
+          dx = 0;
+          ++dy;
         }
       }
     }
