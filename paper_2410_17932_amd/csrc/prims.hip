@@ -1,31 +1,22 @@
 // Device-wide primitives written for gfx950 wave64: fill, single-pass
-// exclusive scan with decoupled look-back, and an onesweep LSD radix sort
-// with wave-level multisplit ranking in LDS.
+// exclusive scan with a wave-parallel decoupled look-back, and a
+// reduce-then-scan LSD radix sort with wave-level multisplit ranking in LDS.
 //
-// Forward progress: scan partitions and sort partitions take their index
-// from an atomic counter in launch order, so every predecessor a block waits
-// on has already started.  Every wait is bounded (kSpinLimit polls); on
-// expiry the kernel records VRS_ETIMEOUT in the status word and proceeds, so
-// every wave always exits.
+// Forward progress: scan partitions take their index from an atomic counter
+// in launch order, so every predecessor a workgroup waits on has already
+// started; every wait is bounded and records VRS_ETIMEOUT on expiry, so every
+// wave always exits.  The sort never waits on another workgroup.
 #include "lookback.h"
 
 namespace vrs {
 namespace {
 
-constexpr int kSpinLimit = 1 << 22;
 
 __device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
 // number of set bits of m at lanes below this lane
 __device__ inline uint32_t count_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ inline uint32_t ld_agent(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void st_agent(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x) {
@@ -129,99 +120,121 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
 }
 
 // ------------------------------------------------------------------ sort
+// LSD radix sort, 8 bits per pass, reduce-then-scan: per pass an upsweep
+// counts each partition's digits, one workgroup per digit scans those
+// counts over partitions, and the downsweep ranks its partition in LDS and
+// writes every item straight to its final position.  No inter-workgroup
+// waiting anywhere; deterministic.
 constexpr int kSortBlock = 256, kSortWaves = kSortBlock / 64, kSortItems = 15;
 constexpr int kWaveChunk = 64 * kSortItems, kSortTile = kSortBlock * kSortItems;  // 3840
-constexpr uint32_t kLbAgg = 1u << 30, kLbPre = 2u << 30, kLbVal = (1u << 30) - 1;
 
-__global__ void k_sort_clear(uint32_t* hist, int passes, uint32_t* lookback, int64_t parts_max,
-                             const uint32_t* n_dev, int64_t n_max) {
-  int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
-  int64_t parts = (n + kSortTile - 1) / kSortTile;
-  int64_t per = parts * 256;
-  int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = i0; i < passes * 256 + passes; i += stride) hist[i] = 0;  // hist + counters
-  for (int p = 0; p < passes; ++p)
-    for (int64_t i = i0; i < per; i += stride) lookback[p * parts_max * 256 + i] = 0;
+__device__ inline int64_t sort_n(const uint32_t* n_dev, int64_t n_max) {
+  return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
 }
 
-// Digit histograms of every pass in one read of the keys.  A thread takes
-// 16 consecutive keys per round (four 16-byte loads in flight).  Keys often
-// come in runs (pairs of one Gaussian, pixels of one point), so where all
-// active lanes of a wave hold the same digit the wave adds once.
-constexpr int kHistItems = 16;
-__device__ inline void hist_add(uint32_t (*s_h)[256], uint32_t k, int passes, uint64_t active,
-                                bool leader) {
-  for (int p = 0; p < passes; ++p) {
-    const uint32_t d = (k >> (8 * p)) & 255u;
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-    if (__ballot(d != d0) == 0) {
-      if (leader) atomicAdd(&s_h[p][d0], (uint32_t)__popcll(active));
-    } else {
-      atomicAdd(&s_h[p][d], 1u);
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_sort_hist(const uint32_t* __restrict__ keys,
-                                                    const uint32_t* n_dev, int64_t n_max,
-                                                    int passes, uint32_t* hist) {
-  __shared__ uint32_t s_h[4][256];
-  const int tid = threadIdx.x;
-  for (int p = 0; p < 4; ++p) s_h[p][tid] = 0;
+// Upsweep: digit counts of partition blockIdx.x, stored digit-major
+// (counts[d * parts + p]).  Keys often come in runs (pairs of one Gaussian,
+// pixels of one point): where all active lanes hold the same digit the wave
+// adds once.
+__global__ __launch_bounds__(kSortBlock) void k_sort_count(const uint32_t* __restrict__ keys,
+                                                            const uint32_t* n_dev, int64_t n_max,
+                                                            int shift, int64_t parts,
+                                                            uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_h[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n = sort_n(n_dev, n_max);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;
+  s_h[tid] = 0;
   __syncthreads();
-  const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
-  const bool aligned = (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
-  const int64_t step = (int64_t)gridDim.x * blockDim.x * kHistItems;
-  for (int64_t i0 = (blockIdx.x * (int64_t)blockDim.x + tid) * kHistItems; i0 < n; i0 += step) {
-    if (aligned && i0 + kHistItems <= n) {
-      const uint64_t active = __ballot(true);   // lanes on this branch
-      const bool leader = count_below(active) == 0;
-      uint4 q[kHistItems / 4];
+  const int64_t wbase = base + (int64_t)wave * kWaveChunk;
+  uint32_t kv[kSortItems];   // every load in flight before the first atomic
 #pragma unroll
-      for (int j = 0; j < kHistItems / 4; ++j) q[j] = *reinterpret_cast<const uint4*>(keys + i0 + 4 * j);
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = wbase + j * 64 + lane;
+    kv[j] = i < n ? keys[i] : 0u;
+  }
 #pragma unroll
-      for (int j = 0; j < kHistItems / 4; ++j) {
-        hist_add(s_h, q[j].x, passes, active, leader);
-        hist_add(s_h, q[j].y, passes, active, leader);
-        hist_add(s_h, q[j].z, passes, active, leader);
-        hist_add(s_h, q[j].w, passes, active, leader);
-      }
-    } else {
-      for (int j = 0; j < kHistItems; ++j) {
-        if (i0 + j >= n) break;
-        const uint32_t k = keys[i0 + j];
-        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t i = wbase + j * 64 + lane;
+    if (i < n) {
+      const uint32_t d = (kv[j] >> shift) & 255u;
+      const uint64_t act = __ballot(true);
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+      if (__ballot(d != d0) == 0) {
+        if (count_below(act) == 0) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
+      } else {
+        atomicAdd(&s_h[d], 1u);
       }
     }
   }
   __syncthreads();
-  for (int p = 0; p < passes; ++p)
-    if (s_h[p][tid]) atomicAdd(&hist[p * 256 + tid], s_h[p][tid]);
+  counts[(int64_t)tid * parts + blockIdx.x] = s_h[tid];
 }
 
+// One workgroup per digit: exclusive scan of the digit's counts over the
+// partitions n needs (in place), the digit total to totals[d].
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* counts, const uint32_t* n_dev,
+                                                   int64_t n_max, int64_t parts,
+                                                   uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_w[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n = sort_n(n_dev, n_max);
+  const int64_t used = (n + kSortTile - 1) / kSortTile;
+  uint32_t* c = counts + (int64_t)blockIdx.x * parts;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < used; b0 += 256 * 4) {
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = b0 + tid * 4 + j;
+      const uint32_t x = i < used ? c[i] : 0u;
+      v[j] = sum;
+      sum += x;
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0, btot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) woff += s_w[w];
+      btot += s_w[w];
+    }
+    const uint32_t off = carry + woff + incl - sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t i = b0 + tid * 4 + j;
+      if (i < used) c[i] = off + v[j];
+    }
+    carry += btot;
+    __syncthreads();   // s_w is rewritten by the next chunk
+  }
+  if (tid == 0) totals[blockIdx.x] = carry;
+}
+
+// Downsweep of partition blockIdx.x: stable rank of every item among the
+// partition's items of the same digit (wave ballots, then waves in order),
+// items regrouped by digit in LDS, then written to
+//   base(digit) + count of the digit in earlier partitions + local rank,
+// with base(digit) the exclusive scan of the digit totals.
 template <typename V>
-__global__ __launch_bounds__(kSortBlock) void k_onesweep(
+__global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
     const uint32_t* __restrict__ kin, const V* __restrict__ vin, uint32_t* __restrict__ kout,
-    V* __restrict__ vout, const uint32_t* n_dev, int64_t n_max, int pass,
-    const uint32_t* __restrict__ hist, uint32_t* counters, uint32_t* lookback, int32_t* status) {
-  __shared__ uint32_t s_part;
+    V* __restrict__ vout, const uint32_t* n_dev, int64_t n_max, int shift, int64_t parts,
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals) {
   __shared__ uint32_t s_wh[kSortWaves][256];
   __shared__ uint32_t s_lstart[256], s_gstart[256], s_scan[kSortWaves];
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ V s_vals[kSortTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int shift = 8 * pass;
-  // blocks beyond the partitions n needs leave before taking an id
-  const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
-  if ((int64_t)blockIdx.x * kSortTile >= n) return;
-  if (tid == 0) s_part = atomicAdd(&counters[pass], 1u);
+  const int64_t n = sort_n(n_dev, n_max);
+  const int64_t part = blockIdx.x;
+  const int64_t base = part * kSortTile;
+  if (base >= n) return;
 #pragma unroll
   for (int w = 0; w < kSortWaves; ++w) s_wh[w][tid] = 0;
   __syncthreads();
-  const int64_t part = s_part;
-  const int64_t base = part * kSortTile;
-
   // load: wave w owns [base + w*960, +960); item j of lane l at j*64 + l
   uint32_t key[kSortItems];
   V val[kSortItems];
@@ -229,8 +242,8 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
   const int64_t wbase = base + (int64_t)wave * kWaveChunk;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    int64_t i = wbase + j * 64 + lane;
-    bool ok = i < n;
+    const int64_t i = wbase + j * 64 + lane;
+    const bool ok = i < n;
     key[j] = ok ? kin[i] : 0xffffffffu;
     val[j] = ok ? vin[i] : V(0);
   }
@@ -255,25 +268,20 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // per digit: exclusive prefix over waves, block count
+  // per digit d = tid: exclusive prefix over waves and the partition's count
   const uint32_t d = tid;
   uint32_t cnt = 0;
 #pragma unroll
   for (int w = 0; w < kSortWaves; ++w) {
-    uint32_t c = s_wh[w][d];
+    const uint32_t c = s_wh[w][d];
     s_wh[w][d] = cnt;
     cnt += c;
   }
-  // publish this partition's aggregate for digit d
-  uint32_t* lb = lookback + (int64_t)pass * ((n_max + kSortTile - 1) / kSortTile) * 256;
-  if (part == 0) st_agent(&lb[d], kLbPre | cnt);
-  else st_agent(&lb[part * 256 + d], kLbAgg | cnt);
-  // block-wide exclusive scan of counts over digits -> local start
-  uint32_t incl = wave_incl_scan(cnt);
+  // local start of each digit (block scan of cnt) and its global base (block
+  // scan of the digit totals)
+  const uint32_t h = totals[d];
+  const uint32_t incl = wave_incl_scan(cnt), hincl = wave_incl_scan(h);
   if (lane == 63) s_scan[wave] = incl;
-  // global digit offsets from the histogram of this pass
-  uint32_t h = hist[pass * 256 + d];
-  uint32_t hincl = wave_incl_scan(h);
   __syncthreads();
   uint32_t woff = 0;
   for (int w = 0; w < wave; ++w) woff += s_scan[w];
@@ -283,49 +291,9 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
   __syncthreads();
   uint32_t hoff = 0;
   for (int w = 0; w < wave; ++w) hoff += s_scan[w];
-  const uint32_t gdig = hoff + hincl - h;
-  // decoupled look-back for digit d: eight predecessors are read per round
-  // (independent loads in flight), consumed in order until an inclusive
-  // prefix is met; a word not yet published ends the round and is re-read
-  uint32_t excl = 0;
-  if (part > 0) {
-    constexpr int kWin = 8;
-    int64_t p = part - 1;
-    int spins = 0;
-    bool found = false;
-    while (!found) {
-      uint32_t w[kWin];
-#pragma unroll
-      for (int k = 0; k < kWin; ++k) w[k] = p - k >= 0 ? ld_agent(&lb[(p - k) * 256 + d]) : kLbPre;
-      int used = kWin;
-      bool stall = false;
-#pragma unroll
-      for (int k = 0; k < kWin; ++k) {
-        if (!found && !stall) {
-          if ((w[k] & (kLbAgg | kLbPre)) == 0) {
-            stall = true;
-            used = k;
-          } else {
-            excl += w[k] & kLbVal;
-            found = (w[k] & kLbPre) != 0;
-          }
-        }
-      }
-      if (found) break;
-      p -= used;
-      if (stall) {
-        if (++spins > kSpinLimit) {
-          set_status(status, VRS_ETIMEOUT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    st_agent(&lb[part * 256 + d], kLbPre | (excl + cnt));
-  }
-  s_gstart[d] = gdig + excl;
+  s_gstart[d] = hoff + hincl - h + counts[(int64_t)d * parts + part];
   __syncthreads();
-  // scatter into LDS in block-sorted order
+  // regroup by digit in LDS, then coalesced runs to the output
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     if (wbase + j * 64 + lane < n) {
@@ -350,25 +318,23 @@ template <typename V>
 hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t* n_dev,
                            int64_t n_max, int key_bits, void* tmp, int32_t* status,
                            hipStream_t st, bool* result_in_1) {
+  (void)status;   // nothing in the sort waits on another workgroup
   const int passes = key_bits <= 0 ? 0 : (key_bits + 7) / 8;
   *result_in_1 = (passes & 1) != 0;
   if (passes == 0 || n_max == 0) return hipSuccess;
   const int64_t parts = (n_max + kSortTile - 1) / kSortTile;
-  uint32_t* hist = static_cast<uint32_t*>(tmp);
-  uint32_t* counters = hist + passes * 256;
-  uint32_t* lookback = hist + ((passes * 256 + passes + 63) / 64) * 64;
-  int clear_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (parts * 256 + 255) / 256));
-  hipLaunchKernelGGL(k_sort_clear, dim3(clear_blocks), dim3(256), 0, st, hist, passes, lookback,
-                     parts, n_dev, n_max);
-  int hist_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_max + 4095) / 4096));
-  hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, st, k0, n_dev, n_max, passes,
-                     hist);
+  uint32_t* totals = static_cast<uint32_t*>(tmp);
+  uint32_t* counts = totals + 256;
   uint32_t* kb[2] = {k0, k1};
   V* vb[2] = {v0, v1};
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_onesweep<V>, dim3((unsigned)parts), dim3(kSortBlock), 0, st, kb[p & 1],
-                       vb[p & 1], kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, n_max, p, hist,
-                       counters, lookback, status);
+    hipLaunchKernelGGL(k_sort_count, dim3((unsigned)parts), dim3(kSortBlock), 0, st, kb[p & 1],
+                       n_dev, n_max, 8 * p, parts, counts);
+    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, st, counts, n_dev, n_max, parts,
+                       totals);
+    hipLaunchKernelGGL(k_sort_scatter<V>, dim3((unsigned)parts), dim3(kSortBlock), 0, st,
+                       kb[p & 1], vb[p & 1], kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, n_max,
+                       8 * p, parts, counts, totals);
   }
   return hipGetLastError();
 }
@@ -420,10 +386,9 @@ hipError_t exclusive_scan_flags_u32(const uint32_t* in, uint32_t* out, uint32_t*
 }
 
 size_t sort_tmp_bytes(int64_t n_max, int key_bits) {
-  const int passes = std::max(1, (key_bits + 7) / 8);
+  (void)key_bits;   // one counts matrix, reused by every pass
   const int64_t parts = std::max<int64_t>(1, (n_max + kSortTile - 1) / kSortTile);
-  size_t head = ((passes * 256 + passes + 63) / 64) * 64 * 4;
-  return head + (size_t)passes * parts * 256 * 4;
+  return (size_t)(256 + 256 * parts) * 4;
 }
 
 hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,

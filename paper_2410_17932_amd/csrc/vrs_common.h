@@ -87,10 +87,11 @@ hipError_t exclusive_scan_flags_u32(const uint32_t* in, uint32_t* out, uint32_t*
                                     int64_t n, void* tmp, int32_t* status, hipStream_t st);
 
 // Stable LSD radix sort of (uint32 key, value) pairs over the low key_bits
-// bits, 8 bits per pass, one onesweep kernel per pass (Adinets & Merrill
-// 2022) after one histogram kernel.  Ping-pongs between (k0, v0) and
-// (k1, v1); returns through *result_in_1 whether the sorted data ended in
-// the second buffer.  n = min(*n_dev, n_max).
+// bits, 8 bits per pass, reduce-then-scan per pass (digit counts per
+// partition, their scan per digit, then a ranking scatter; Merrill &
+// Grimshaw's structure with wave-ballot multisplit ranking).  Ping-pongs
+// between (k0, v0) and (k1, v1); returns through *result_in_1 whether the
+// sorted data ended in the second buffer.  n = min(*n_dev, n_max).
 size_t sort_tmp_bytes(int64_t n_max, int key_bits);
 hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
