@@ -188,6 +188,21 @@ vrs_status vrs_render_gaussians_backward(const float* mean, const float* cov,
                                          float* d_cov, float* d_opacity, float* d_sh, void* ws,
                                          size_t ws_bytes, int64_t max_pairs, void* stream);
 
+/* ------------------------------------------------------- scene layout
+ * Spatial (Morton, Z-order) permutation of a point set, for storing a static
+ * scene so that points adjacent in memory are adjacent in space (a load-time
+ * storage step, not part of the per-frame path, whose results do not depend
+ * on point order except for the order of exactly equal depths).  pos [3][n]
+ * float32 (device); each coordinate is mapped to 10 bits over the set's
+ * finite bounding box (non-finite coordinates to the last cell) and the
+ * 30-bit interleaved x, y, z codes are sorted stably.  perm [n] (device,
+ * caller-owned) receives point indices in that order.  ws: device workspace
+ * of vrs_spatial_order_workspace_size(n) bytes (0 if n < 1 or n >= 2^31).
+ * VRS_EINVAL on null pointers, a bad n or a short workspace. */
+size_t vrs_spatial_order_workspace_size(int64_t n);
+vrs_status vrs_spatial_order(const float* pos, int64_t n, uint32_t* perm, void* ws,
+                             size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- fovea
  * Neural-point splat into a multi-resolution pyramid for every crop
  * (Sec. 3.3 sub-frustum and depth culling; Sec. 4 "Inference": one count,

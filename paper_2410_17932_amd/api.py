@@ -72,6 +72,8 @@ SIGNATURES = {
     "vrs_status_string": (ctypes.c_char_p, [_int]),
     "vrs_version": (ctypes.c_char_p, []),
     "vrs_bake_gaussians": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "vrs_spatial_order_workspace_size": (_sz, [_i64]),
+    "vrs_spatial_order": (_int, [_vp, _i64, _vp, _vp, _sz, _vp]),
     "vrs_bake_gaussians_backward": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vrs_render_workspace_size": (_sz, [_i64, _int, _P(View), _P(RasterOpts), _i64]),
     "vrs_render_workspace_layout": (_int, [_i64, _int, _P(View), _P(RasterOpts), _i64,
@@ -213,6 +215,20 @@ def bake_gaussians_backward(logscale, quat, logit, d_cov, d_opacity, d_logscale,
         logit.shape[0], ptr(d_cov, torch.float32), ptr(d_opacity, torch.float32),
         ptr(d_logscale, torch.float32), ptr(d_quat, torch.float32), ptr(d_logit, torch.float32),
         _stream()), "vrs_bake_gaussians_backward")
+
+
+def spatial_order(pos):
+    """Morton-order permutation of pos [3][n] (device int32 tensor of point
+    indices); a load-time storage step for static scenes."""
+    n = pos.shape[1]
+    size = lib().vrs_spatial_order_workspace_size(n)
+    if size == 0:
+        raise VrsError(VRS_EINVAL, "vrs_spatial_order_workspace_size")
+    ws = torch.empty(size, dtype=torch.uint8, device=pos.device)
+    perm = torch.empty(n, dtype=torch.int32, device=pos.device)
+    _check(lib().vrs_spatial_order(ptr(pos, torch.float32), n, ptr(perm), ptr(ws), size, _stream()),
+           "vrs_spatial_order")
+    return perm
 
 
 # ------------------------------------------------------------- periphery

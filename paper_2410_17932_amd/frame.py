@@ -28,7 +28,7 @@ class Frame:
     def __init__(self, scene: dict, decoder_dtype: int = api.VRS_BF16, tile: int = 16,
                  mode: int = api.BLEND_LINEAR, ring: float = 64.0, m: float = 0.75,
                  gamma: float = 0.2, cull: bool = True, pair_margin: float = 1.10,
-                 frag_margin: float = 1.25):
+                 frag_margin: float = 1.25, spatial_order: bool = True):
         g, p = scene["gaussians"], scene["points"]
         self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
         self.sh_degree = g["sh_degree"]
@@ -43,6 +43,13 @@ class Frame:
                                                     _dev(g["logit"]))
         self.pos, self.radius = _dev(p["pos"]), _dev(p["radius"])
         self.feat = _dev(p["feat"].view(np.int16))
+        if spatial_order:
+            # storage layout of the static point cloud: Morton order, so the
+            # depth cull's per-point reads of depth and T' share cache lines
+            perm = api.spatial_order(self.pos).long()
+            self.pos = self.pos[:, perm].contiguous()
+            self.radius = self.radius[perm].contiguous()
+            self.feat = self.feat[perm].contiguous()
         from .synth import pack_decoder
         self.weights = _dev(pack_decoder(scene["decoder"]))
         self.n, self.np = g["n"], p["n"]

@@ -47,6 +47,16 @@ def test_autotune_keeps_image():
     np.testing.assert_allclose(out.cpu().numpy(), ref.cpu().numpy(), atol=1e-5)
 
 
+def test_spatial_order_keeps_image():
+    """Storing the points in Morton order changes no output (no two points
+    share a depth here, so every pixel's fragment order is the same)."""
+    sc = _scene()
+    a = Frame(sc, decoder_dtype=api.VRS_BF16, tile=16, spatial_order=True).run().clone()
+    b = Frame(sc, decoder_dtype=api.VRS_BF16, tile=16, spatial_order=False).run().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_plain_form_matches_batched():
     sc = _scene()
     fb = Frame(sc, decoder_dtype=api.VRS_BF16, tile=16)

@@ -79,3 +79,35 @@ def test_points_capacity_flag():
                      crops, 4, None, None, ws)
     torch.cuda.synchronize()
     assert int(ws.status.item()) == api.VRS_ECAPACITY
+
+
+def _morton_reference(pos):
+    """30-bit Morton codes from the same float32 quantisation (numpy)."""
+    pos = pos.astype(np.float32)
+    codes = np.zeros(pos.shape[1], np.uint64)
+    for a in range(3):
+        v = pos[a]
+        lo, hi = v.min(), v.max()
+        t = np.zeros_like(v) if not hi > lo else ((v - lo) / np.float32(hi - lo)) * np.float32(1024.0)
+        q = np.clip(t, 0.0, 1023.0).astype(np.uint64)
+        for b in range(10):
+            codes |= ((q >> b) & 1) << (3 * b + a)
+    return codes
+
+
+@pytest.mark.parametrize("n", [1, 1000, 123457])
+def test_spatial_order_is_stable_morton_sort(n):
+    rng = np.random.default_rng(n)
+    pos = np.stack([rng.uniform(-1, 1, n), rng.uniform(-2, 3, n), rng.uniform(2, 6, n)]).astype(np.float32)
+    if n > 10:
+        pos[:, 5] = pos[:, 7]          # exact duplicates keep index order
+    perm = api.spatial_order(dev(pos)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    codes = _morton_reference(pos)
+    assert np.array_equal(perm, np.argsort(codes, kind="stable"))
+
+
+def test_spatial_order_degenerate_box():
+    pos = np.ones((3, 777), np.float32)
+    perm = api.spatial_order(dev(pos)).cpu().numpy()
+    assert np.array_equal(perm, np.arange(777))
