@@ -165,6 +165,13 @@ __device__ inline void gs_stage(const float4* __restrict__ rec, int64_t e, float
   c = make_float4(r1.z, r1.w, r2.x, r2.y);
 }
 
+// Exponent q = P + dy (C' dy + R) with P = (A' dx) dx and R = B' dx: P and R
+// are shared by every pixel of a column.
+__device__ inline float gs_exponent(const float4& a, const float4& b, float dx, float dy) {
+  const float P = (a.z * dx) * dx, R = a.w * dx;
+  return fmaf(dy, fmaf(b.x, dy, R), P);
+}
+
 // Opacity at a pixel centre, negative where the exponent is positive (no
 // contribution for any alpha_min >= 0).  The forward blend evaluates the same
 // operations inline and the backward calls this, so both take the same
@@ -173,10 +180,7 @@ __device__ inline float gs_alpha(const float4& a, const float4& b, float xc, flo
                                  float aclamp, float& dx, float& dy, float& e) {
   dx = a.x - xc;
   dy = a.y - yc;
-  float u = a.z * dx;
-  u = fmaf(a.w, dy, u);
-  float q = dx * u;
-  q = fmaf(b.x * dy, dy, q);
+  const float q = gs_exponent(a, b, dx, dy);
   e = __builtin_amdgcn_exp2f(q);
   const float al = fminf(aclamp, b.y * e);
   return q > 0.0f ? -1.0f : al;

@@ -374,18 +374,18 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
         const uint32_t ry_span = (uint32_t)(ry1 - ry0);
         const uint32_t pos = b0 + (uint32_t)k + 1u - begin;
         const float dx = a.x - xc;
-        const float adx = a.z * dx;
+        // the exponent's per-column part (same operations as gs_exponent)
+        const float P = (a.z * dx) * dx, R = a.w * dx;
         all_ry = kStopped;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
           const float dy = a.y - yc[q];
-          const float u = fmaf(a.w, dy, adx);
-          const float qq = fmaf(b.x * dy, dy, dx * u);
+          const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
           const float e = __builtin_amdgcn_exp2f(qq);
           const float al0 = b.y * e;
           const float al = al0 < aclamp ? al0 : aclamp;
           const bool inr = inx & ((uint32_t)(ry[q] - ry0) <= ry_span);
-          const float Tn = T[q] * (1.0f - al);
+          const float Tn = fmaf(-T[q], al, T[q]);
           const bool ok0 = inr & !(qq > 0.0f) & (al >= amin);
           const bool stop = ok0 & (Tn < tmin);
           const bool ok = ok0 & !stop;
