@@ -2,9 +2,10 @@
 // Eqs. 2-5), its adjoint, and the L1 photometric term of the fitting loss
 // (Sec. 3.5, Eq. 6).
 //
-// One thread per full-frame pixel: the crop table travels as a kernel
-// argument, each pixel walks the crops of its view in index order.  HBM-bound:
-// P is read and out written once; F is read only under the crops.
+// One thread per four full-frame pixels of a row (one per pixel when the
+// width is not a multiple of 4): the crop table travels as a kernel argument,
+// each pixel walks the crops of its view in index order.  HBM-bound: P is
+// read and out written once; F is read only under the crops.
 #include "vrs_common.h"
 
 namespace vrs {
@@ -87,6 +88,53 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* __re
     out[base] = o0;
     out[base + plane] = o1;
     out[base + 2 * plane] = o2;
+  }
+}
+
+// Same per pixel as k_composite, four consecutive pixels of a row per thread
+// (W % 4 == 0): 16-byte loads and stores of P and out, crops rejected once
+// per four pixels.
+__global__ __launch_bounds__(256) void k_composite4(CompArgs a, const float* __restrict__ P,
+                                                    const float* __restrict__ F,
+                                                    float* __restrict__ out) {
+  const long long plane = (long long)a.W * a.H, qplane = plane / 4;
+  const long long total = qplane * a.nv;
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int v = (int)(q / qplane);
+    const long long pi = (q - v * qplane) * 4;
+    const int y = (int)(pi / a.W), x = (int)(pi - (long long)y * a.W);
+    const long long base = (long long)v * 3 * plane + pi;
+    float4 c4[3] = {*reinterpret_cast<const float4*>(P + base),
+                    *reinterpret_cast<const float4*>(P + base + plane),
+                    *reinterpret_cast<const float4*>(P + base + 2 * plane)};
+    float o[3][4];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      o[ch][0] = c4[ch].x; o[ch][1] = c4[ch].y; o[ch][2] = c4[ch].z; o[ch][3] = c4[ch].w;
+    }
+    for (int k = 0; k < a.n_crops; ++k) {
+      if (a.view[k] != v) continue;
+      const int S = a.S[k], ly = y - a.y0[k];
+      if (ly < 0 || ly >= S || x + 3 < a.x0[k] || x >= a.x0[k] + S) continue;
+      const float* Fk = F + a.fbase[k];
+      const long long fp = (long long)S * S;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int lx = x + j - a.x0[k];
+        if (lx < 0 || lx >= S) continue;
+        float u, gx, gy;
+        const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy);
+        const long long fo = (long long)ly * S + lx;
+        o[0][j] = (1.0f - c) * o[0][j] + c * Fk[fo];
+        o[1][j] = (1.0f - c) * o[1][j] + c * Fk[fp + fo];
+        o[2][j] = (1.0f - c) * o[2][j] + c * Fk[2 * fp + fo];
+      }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+      *reinterpret_cast<float4*>(out + base + ch * plane) =
+          make_float4(o[ch][0], o[ch][1], o[ch][2], o[ch][3]);
   }
 }
 
@@ -261,10 +309,18 @@ extern "C" vrs_status vrs_composite_frame(const float* rgb_periphery, int n_view
     return VRS_EINVAL;
   if (!rgb_periphery || !out || (n_crops > 0 && !fovea_rgb)) return VRS_EINVAL;
   const long long total = (long long)width * height * n_views;
-  const int blocks = (int)std::min<long long>(16384, (total + 255) / 256);
   trace_begin(VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
-  hipLaunchKernelGGL(k_composite, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream), a,
-                     rgb_periphery, fovea_rgb, out);
+  const bool vec4 = width % 4 == 0 && (reinterpret_cast<uintptr_t>(rgb_periphery) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+  if (vec4) {
+    const int blocks = (int)std::min<long long>(16384, (total / 4 + 255) / 256);
+    hipLaunchKernelGGL(k_composite4, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       a, rgb_periphery, fovea_rgb, out);
+  } else {
+    const int blocks = (int)std::min<long long>(16384, (total + 255) / 256);
+    hipLaunchKernelGGL(k_composite, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       a, rgb_periphery, fovea_rgb, out);
+  }
   VRS_LAUNCH_CHECK();
   trace_end(VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
   return VRS_OK;

@@ -36,6 +36,7 @@ struct SplatWs {
 constexpr int kSelBlock = 256;
 
 // look-back partition counter (256 bytes) + one status word per partition
+// (partitions of 2048 points; a bound for smaller ones too)
 static size_t sel_tmp_bytes(int64_t np) {
   return 256 + (size_t)std::max<int64_t>(1, div_up(np, kSelBlock)) * 8;
 }
@@ -163,11 +164,18 @@ __device__ inline uint32_t pt_count(const KView& cv, int v, const KCrops& crops,
   return cnt;
 }
 
-// Partition p (taken from an atomic counter) holds points [256p, 256p+256).
-// Its survivors go out view by view, each view's in point order, after all
-// survivors of earlier partitions: within one view the compacted list is in
-// point order, which is all the later stable sorts need (fragments of
-// different views never share a pyramid pixel).
+// Partition p (taken from an atomic counter, launch order) holds points
+// [2048p, 2048p+2048), handled in eight rounds of 256.  Per round and view
+// each lane's fragment count and depth key go to LDS and each wave ballots
+// its survivors; one look-back per partition gives the partition's output
+// base; then the survivors go out view by view, each view's in point order
+// (rounds, then waves, then lanes), after all survivors of earlier
+// partitions.  Within one view the compacted list is in point order, which
+// is all the later stable sorts need (fragments of different views never
+// share a pyramid pixel).  One atomic per 2048 points: a single counter
+// address serialises its atomics, so partitions are kept large.
+constexpr int kSelRounds = 8, kSelPart = kSelBlock * kSelRounds;
+
 __global__ __launch_bounds__(kSelBlock) void k_pt_select(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
@@ -175,67 +183,93 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
     uint32_t* __restrict__ cent, uint32_t* __restrict__ ccnt, uint32_t* __restrict__ live,
     int32_t* status) {
   constexpr int NW = kSelBlock / 64;
+  constexpr int NSLOT = kSelRounds * VRS_MAX_VIEWS * NW;   // (view, round, wave), view-major
   __shared__ uint32_t s_part, s_base;
-  __shared__ uint32_t s_wcnt[VRS_MAX_VIEWS][NW];
+  __shared__ uint64_t s_mask[NSLOT];
+  __shared__ uint32_t s_pre[NSLOT];
+  __shared__ uint32_t s_wsum[NW];
+  extern __shared__ __align__(16) char s_dyn[];
+  const int nv = views.n;
+  float* s_zd = reinterpret_cast<float*>(s_dyn);                               // [round][view][tid]
+  uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_dyn) + kSelRounds * nv * kSelBlock;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n_parts = (np + kSelPart - 1) / kSelPart;
   if (tid == 0) s_part = atomicAdd(counter, 1u);
+  for (int e = tid; e < NSLOT; e += kSelBlock) s_mask[e] = 0;
   __syncthreads();
   const int64_t part = s_part;
-  const int64_t i = part * kSelBlock + tid;
-  const bool in = i < np;
-  float x = 0, y = 0, z = 0, r = 0;
-  if (in) { x = pos[i]; y = pos[np + i]; z = pos[2 * np + i]; r = radius[i]; }
-  uint32_t cnt[VRS_MAX_VIEWS];
-  float zd[VRS_MAX_VIEWS];
-  uint64_t m[VRS_MAX_VIEWS];
-#pragma unroll
-  for (int v = 0; v < VRS_MAX_VIEWS; ++v) {
-    cnt[v] = 0;
-    zd[v] = 0.0f;
-    m[v] = 0;
-    if (v < views.n) {
+  // ---- counts of every (round, view, point)
+  for (int j = 0; j < kSelRounds; ++j) {
+    const int64_t i = part * kSelPart + (int64_t)j * kSelBlock + tid;
+    const bool in = i < np;
+    float x = 0, y = 0, z = 0, r = 0;
+    if (in) { x = pos[i]; y = pos[np + i]; z = pos[2 * np + i]; r = radius[i]; }
+    for (int v = 0; v < nv; ++v) {
+      uint32_t cnt = 0;
+      float zd = 0.0f;
       if (in && ((a.view_mask >> v) & 1u)) {
         const int64_t plane = (int64_t)views.v[v].W * views.v[v].H;
-        cnt[v] = pt_count(views.v[v], v, crops, a, x, y, z, r,
-                          depth ? depth + v * plane : nullptr,
-                          tfinal ? tfinal + v * plane : nullptr, zd[v]);
+        cnt = pt_count(views.v[v], v, crops, a, x, y, z, r, depth ? depth + v * plane : nullptr,
+                       tfinal ? tfinal + v * plane : nullptr, zd);
       }
-      m[v] = __ballot(cnt[v] != 0);
-      if (lane == 0) s_wcnt[v][wave] = (uint32_t)__popcll(m[v]);
+      s_zd[(j * nv + v) * kSelBlock + tid] = zd;
+      s_cnt[(j * nv + v) * kSelBlock + tid] = cnt;
+      const uint64_t m = __ballot(cnt != 0);
+      if (lane == 0) s_mask[(v * kSelRounds + j) * NW + wave] = m;
     }
   }
   __syncthreads();
-  uint32_t total = 0;
-  for (int v = 0; v < views.n; ++v)
+  // ---- exclusive scan of the slot counts in output order
+  {
+    uint32_t c[NSLOT / kSelBlock], sum = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) total += s_wcnt[v][w];
-  if (wave == 0) {
-    const uint32_t excl = wave_lookback(flags, part, total, status);
-    if (lane == 0) {
-      s_base = excl;
-      if (part == (int64_t)gridDim.x - 1) *live = excl + total;
+    for (int q = 0; q < NSLOT / kSelBlock; ++q) {
+      const int e = tid * (NSLOT / kSelBlock) + q;
+      c[q] = sum;
+      sum += (uint32_t)__popcll(s_mask[e]);
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      if (w < wave) woff += s_wsum[w];
+      total += s_wsum[w];
+    }
+#pragma unroll
+    for (int q = 0; q < NSLOT / kSelBlock; ++q)
+      s_pre[tid * (NSLOT / kSelBlock) + q] = woff + incl - sum + c[q];
+    if (wave == 0) {
+      const uint32_t excl = wave_lookback(flags, part, total, status);
+      if (lane == 0) {
+        s_base = excl;
+        if (part == n_parts - 1) *live = excl + total;
+      }
     }
   }
   __syncthreads();
-  uint32_t off = s_base;
-#pragma unroll
-  for (int v = 0; v < VRS_MAX_VIEWS; ++v) {
-    if (v < views.n) {
-      uint32_t o = off;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        if (w < wave) o += s_wcnt[v][w];
-        off += s_wcnt[v][w];
-      }
-      if (cnt[v]) {
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-            (uint32_t)(m[v] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[v], 0u));
-        const uint32_t p = o + below;
-        ckey[p] = __float_as_uint(zd[v]);
-        cval[p] = p;
-        cent[p] = (uint32_t)(v * np + i);
-        ccnt[p] = cnt[v];
-      }
+  // ---- survivors to their positions
+  const uint32_t base = s_base;
+  for (int j = 0; j < kSelRounds; ++j) {
+    const int64_t i = part * kSelPart + (int64_t)j * kSelBlock + tid;
+    for (int v = 0; v < nv; ++v) {
+      const uint32_t cnt = s_cnt[(j * nv + v) * kSelBlock + tid];
+      if (!cnt) continue;
+      const int slot = (v * kSelRounds + j) * NW + wave;
+      const uint64_t m = s_mask[slot];
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      const uint32_t p = base + s_pre[slot] + below;
+      ckey[p] = __float_as_uint(s_zd[(j * nv + v) * kSelBlock + tid]);
+      cval[p] = p;
+      cent[p] = (uint32_t)(v * np + i);
+      ccnt[p] = cnt;
     }
   }
 }
@@ -413,9 +447,10 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   uint32_t* live = at<uint32_t>(ws, L.live);
   uint32_t* sel_counter = at<uint32_t>(ws, L.sel_tmp);
   uint64_t* sel_flags = at<uint64_t>(ws, L.sel_tmp + 256);
-  const int sel_parts = div_up(np, kSelBlock);
+  const int sel_parts = div_up(np, kSelPart);
+  const size_t sel_lds = (size_t)kSelRounds * n_views * kSelBlock * 8;
   VRS_HIP_CHECK(fill_u32(sel_counter, 0, (int64_t)(sel_tmp_bytes(np) / 4), st));
-  hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), 0, st, pos, radius, np, kv,
+  hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), sel_lds, st, pos, radius, np, kv,
                      kc, a, depth, t_final, sel_counter, sel_flags, at<uint32_t>(ws, L.ckey0),
                      at<uint32_t>(ws, L.cval0), at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt),
                      live, dev_status);

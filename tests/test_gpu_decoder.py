@@ -49,9 +49,10 @@ def test_decoder_parity(dtype, tol, widths, L):
 
 
 @pytest.mark.parametrize("mode", [api.BLEND_LINEAR, api.BLEND_PAPER])
-def test_composite_parity(mode):
+@pytest.mark.parametrize("W", [180, 181])   # four pixels per thread, and one
+def test_composite_parity(mode, W):
     rng = np.random.default_rng(5)
-    W, H = 180, 150
+    H = 150
     views = [synth.pinhole(W, H, 150.0), synth.pinhole(W, H, 150.0, (0.06, 0, 0))]
     crops = [synth.crop_at(0, 60.3, 70.7, 64, W, H), synth.crop_at(0, 80.0, 80.0, 96, W, H),
              synth.crop_at(1, 170.0, 10.0, 32, W, H), synth.crop_at(1, 90.0, 75.0, 128, W, H)]
