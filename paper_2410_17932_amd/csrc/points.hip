@@ -27,7 +27,8 @@ namespace vrs {
 
 struct SplatWs {
   size_t cent, ccnt, ckey0, cval0, ckey1, cval1, live, foffs, frag_count, fkey0, fval0, fkey1,
-      fval1, sel_tmp, sort_tmp, scan_tmp, total;
+      fval1, sel_tmp, grid, sort_tmp, scan_tmp, total;
+  int gx, gy;   // crop-lookup grid cells per view row / column
   int64_t vn, pix_total;
   int key_bits;
   bool frags_in_1;
@@ -57,11 +58,17 @@ static int64_t pyramid_pixels(const vrs_crop* crops, int n_crops, int levels) {
   return s;
 }
 
-static bool splat_layout(int64_t np, int nv, const vrs_crop* crops, int n_crops, int levels,
-                         int64_t max_frags, SplatWs* L) {
+// Crop-lookup grid: cells of kGridCell x kGridCell view pixels, per view.
+constexpr int kGridCell = 32;
+
+static bool splat_layout(int64_t np, int nv, int W, int H, const vrs_crop* crops, int n_crops,
+                         int levels, int64_t max_frags, SplatWs* L) {
   if (np < 0 || nv < 1 || nv > VRS_MAX_VIEWS || n_crops < 0 || n_crops > VRS_MAX_CROPS ||
-      levels < 1 || levels > VRS_MAX_LEVELS || max_frags < 0 || (n_crops > 0 && !crops))
+      levels < 1 || levels > VRS_MAX_LEVELS || max_frags < 0 || (n_crops > 0 && !crops) ||
+      W < 1 || H < 1)
     return false;
+  L->gx = (W + kGridCell - 1) / kGridCell;
+  L->gy = (H + kGridCell - 1) / kGridCell;
   L->vn = np * nv;
   L->pix_total = pyramid_pixels(crops, n_crops, levels);
   L->key_bits = bits_for_p(std::max<int64_t>(L->pix_total, 2));
@@ -82,10 +89,18 @@ static bool splat_layout(int64_t np, int nv, const vrs_crop* crops, int n_crops,
   L->fkey1 = c.take(mf * 4);
   L->fval1 = c.take(mf * 8);
   L->sel_tmp = c.take(sel_tmp_bytes(np));
+  L->grid = c.take((size_t)nv * L->gx * L->gy * 4);
   L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mf, L->key_bits)));
   L->scan_tmp = c.take(scan_tmp_bytes(vn));
   L->total = c.off;
   return true;
+}
+
+static bool splat_layout_for(int64_t np, int n_views, const vrs_view* views, const vrs_crop* crops,
+                             int n_crops, int levels, int64_t max_frags, SplatWs* L) {
+  if (!views || n_views < 1) return false;
+  return splat_layout(np, n_views, views[0].width, views[0].height, crops, n_crops, levels,
+                      max_frags, L);
 }
 
 // host: crop table with packed-pyramid and packed-output bases
@@ -112,21 +127,6 @@ bool make_crops(const vrs_crop* crops, int n_crops, int levels, const KViews& kv
   return true;
 }
 
-bool splat_layout_public(int64_t np, int nv, const vrs_crop* crops, int n_crops, int levels,
-                         int64_t max_frags, size_t* frag_count, size_t* keys, size_t* vals,
-                         size_t* total, int64_t* pix_total, bool* in1, size_t* vals_alt) {
-  SplatWs L;
-  if (!splat_layout(np, nv, crops, n_crops, levels, max_frags, &L)) return false;
-  *frag_count = L.frag_count;
-  *keys = L.frags_in_1 ? L.fkey1 : L.fkey0;
-  *vals = L.frags_in_1 ? L.fval1 : L.fval0;
-  *vals_alt = L.frags_in_1 ? L.fval0 : L.fval1;
-  *total = L.total;
-  *pix_total = L.pix_total;
-  *in1 = L.frags_in_1;
-  return true;
-}
-
 struct PtArgs {
   float cov_min, slack;
   int levels;
@@ -134,20 +134,70 @@ struct PtArgs {
 };
 
 // ---------------------------------------------------------------- select
+// Crop-lookup grid: per view and cell, the bit set of crops that a point
+// whose pixel lies in the cell may reach.  A footprint at layer l < levels
+// reaches at most 2^(l-1) + 1 view pixels beyond its crop, so crop k is
+// listed in every cell that meets [x0 - 2^levels - 2, x0 + size + 2^levels + 2)
+// (likewise y); border cells extend to infinity so that lookups of pixels
+// outside the view clamp to them.
+__global__ void k_pt_cropgrid(KCrops crops, int nv, int levels, int gx, int gy,
+                              uint32_t* __restrict__ grid) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nv * gx * gy) return;
+  const int v = (int)(idx / ((int64_t)gx * gy));
+  const int cell = (int)(idx - (int64_t)v * gx * gy);
+  const int cy = cell / gx, cx = cell - cy * gx;
+  const int M = (1 << levels) + 2;
+  const int64_t lo_x = cx == 0 ? INT32_MIN : (int64_t)cx * kGridCell;
+  const int64_t hi_x = cx == gx - 1 ? INT32_MAX : (int64_t)(cx + 1) * kGridCell;
+  const int64_t lo_y = cy == 0 ? INT32_MIN : (int64_t)cy * kGridCell;
+  const int64_t hi_y = cy == gy - 1 ? INT32_MAX : (int64_t)(cy + 1) * kGridCell;
+  uint32_t mask = 0;
+  for (int k = 0; k < crops.n; ++k) {
+    const KCrop& c = crops.c[k];
+    if (c.view != v) continue;
+    const int64_t x0 = (int64_t)c.x0 - M, x1 = (int64_t)c.x0 + c.size + M;
+    const int64_t y0 = (int64_t)c.y0 - M, y1 = (int64_t)c.y0 + c.size + M;
+    if (x0 < hi_x && x1 > lo_x && y0 < hi_y && y1 > lo_y) mask |= 1u << k;
+  }
+  grid[idx] = mask;
+}
+
 // Fragment count of one point in view v (0 if culled): footprint targets
-// over the view's crops and the point's one or two layers, then the depth
-// cull for a point that reaches any crop.
+// over the crops the grid lists for the point's cell and the point's one or
+// two layers, then the depth cull for a point that reaches any crop.  The
+// cell comes from a reciprocal-based pixel estimate (within 1e-2 px of the
+// exact one, well inside the grid's slack), so the exact projection runs
+// only for points near a crop; a non-positive or non-finite estimate falls
+// back to every crop.
 __device__ inline uint32_t pt_count(const KView& cv, int v, const KCrops& crops, const PtArgs& a,
+                                    const uint32_t* __restrict__ grid, int gx, int gy,
                                     float x, float y, float z, float r, const float* depth,
                                     const float* tfinal, float& zkey_depth) {
+  uint32_t cand = crops.n >= 32 ? 0xffffffffu : ((1u << crops.n) - 1u);
+  {
+    const float tx = cv.R[0] * x + cv.R[1] * y + cv.R[2] * z + cv.t[0];
+    const float ty = cv.R[3] * x + cv.R[4] * y + cv.R[5] * z + cv.t[1];
+    const float tz = cv.R[6] * x + cv.R[7] * y + cv.R[8] * z + cv.t[2];
+    if (tz > 0.0f) {
+      const float rz = __builtin_amdgcn_rcpf(tz);
+      const float ex = (cv.fx * (tx * rz) + cv.cx) * (1.0f / kGridCell);
+      const float ey = (cv.fy * (ty * rz) + cv.cy) * (1.0f / kGridCell);
+      if (isfinite(ex) && isfinite(ey)) {
+        const float fx = fminf(fmaxf(floorf(ex), 0.0f), (float)(gx - 1));
+        const float fy = fminf(fmaxf(floorf(ey), 0.0f), (float)(gy - 1));
+        cand = grid[((int64_t)v * gy + (int)fy) * gx + (int)fx];
+        if (!cand) return 0;
+      }
+    }
+  }
   PtGeom g;
   if (!pt_geom32(cv, x, y, z, r, a.levels, g)) return 0;
   uint32_t cnt = 0;
-  // a footprint at layer l < levels reaches at most 2^(l-1) + 1 view pixels
-  // beyond the crop, so a point farther out than 2^levels is rejected
-  // without the per-layer tests (same decisions, fewer operations)
   const float M = (float)(1 << a.levels);
-  for (int k = 0; k < crops.n; ++k) {
+  while (cand) {
+    const int k = __builtin_ctz(cand);
+    cand &= cand - 1;
     const KCrop& c = crops.c[k];
     if (c.view != v) continue;
     const float ax = g.px - (float)c.x0, ay = g.py - (float)c.y0, lim = (float)c.size + M;
@@ -179,9 +229,9 @@ constexpr int kSelRounds = 8, kSelPart = kSelBlock * kSelRounds;
 __global__ __launch_bounds__(kSelBlock) void k_pt_select(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
-    uint32_t* counter, uint64_t* flags, uint32_t* __restrict__ ckey, uint32_t* __restrict__ cval,
-    uint32_t* __restrict__ cent, uint32_t* __restrict__ ccnt, uint32_t* __restrict__ live,
-    int32_t* status) {
+    const uint32_t* __restrict__ grid, int gx, int gy, uint32_t* counter, uint64_t* flags,
+    uint32_t* __restrict__ ckey, uint32_t* __restrict__ cval, uint32_t* __restrict__ cent,
+    uint32_t* __restrict__ ccnt, uint32_t* __restrict__ live, int32_t* status) {
   constexpr int NW = kSelBlock / 64;
   constexpr int NSLOT = kSelRounds * VRS_MAX_VIEWS * NW;   // (view, round, wave), view-major
   __shared__ uint32_t s_part, s_base;
@@ -209,8 +259,9 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
       float zd = 0.0f;
       if (in && ((a.view_mask >> v) & 1u)) {
         const int64_t plane = (int64_t)views.v[v].W * views.v[v].H;
-        cnt = pt_count(views.v[v], v, crops, a, x, y, z, r, depth ? depth + v * plane : nullptr,
-                       tfinal ? tfinal + v * plane : nullptr, zd);
+        cnt = pt_count(views.v[v], v, crops, a, grid, gx, gy, x, y, z, r,
+                       depth ? depth + v * plane : nullptr, tfinal ? tfinal + v * plane : nullptr,
+                       zd);
       }
       s_zd[(j * nv + v) * kSelBlock + tid] = zd;
       s_cnt[(j * nv + v) * kSelBlock + tid] = cnt;
@@ -386,7 +437,7 @@ extern "C" size_t vrs_splat_workspace_size(int64_t np, int n_views, const vrs_vi
   KViews kv;
   KCrops kc;
   if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc)) return 0;
-  if (!splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L)) return 0;
+  if (!splat_layout_for(np, n_views, views, crops, n_crops, levels, max_frags, &L)) return 0;
   return L.total;
 }
 
@@ -394,7 +445,7 @@ extern "C" vrs_status vrs_splat_workspace_layout(int64_t np, int n_views, const 
                                                  const vrs_crop* crops, int n_crops, int levels,
                                                  int64_t max_frags, vrs_splat_layout* out) {
   SplatWs L;
-  if (!out || !splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L))
+  if (!out || !splat_layout_for(np, n_views, views, crops, n_crops, levels, max_frags, &L))
     return VRS_EINVAL;
   out->frag_count = L.frag_count;
   out->sorted_keys = L.frags_in_1 ? L.fkey1 : L.fkey0;
@@ -421,7 +472,7 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
     return VRS_EINVAL;
   if ((depth == nullptr) != (t_final == nullptr)) return VRS_EINVAL;
   if (!pyramid || !ws || max_frags < 0 || max_frags >= (int64_t(1) << 30)) return VRS_EINVAL;
-  if (!splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L) || ws_bytes < L.total)
+  if (!splat_layout_for(np, n_views, views, crops, n_crops, levels, max_frags, &L) || ws_bytes < L.total)
     return VRS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   PtArgs a;
@@ -450,8 +501,13 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   const int sel_parts = div_up(np, kSelPart);
   const size_t sel_lds = (size_t)kSelRounds * n_views * kSelBlock * 8;
   VRS_HIP_CHECK(fill_u32(sel_counter, 0, (int64_t)(sel_tmp_bytes(np) / 4), st));
+  uint32_t* grid = at<uint32_t>(ws, L.grid);
+  const int64_t cells = (int64_t)n_views * L.gx * L.gy;
+  hipLaunchKernelGGL(k_pt_cropgrid, dim3(div_up(cells, 256)), dim3(256), 0, st, kc, n_views, levels,
+                     L.gx, L.gy, grid);
+  VRS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), sel_lds, st, pos, radius, np, kv,
-                     kc, a, depth, t_final, sel_counter, sel_flags, at<uint32_t>(ws, L.ckey0),
+                     kc, a, depth, t_final, grid, L.gx, L.gy, sel_counter, sel_flags, at<uint32_t>(ws, L.ckey0),
                      at<uint32_t>(ws, L.cval0), at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt),
                      live, dev_status);
   VRS_LAUNCH_CHECK();
@@ -621,7 +677,7 @@ extern "C" vrs_status vrs_splat_points_backward(const float* pos, const float* r
   if (channels != 4) return channels > 0 ? VRS_EUNSUPPORTED : VRS_EINVAL;
   if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc))
     return VRS_EINVAL;
-  if (!splat_layout(np, n_views, crops, n_crops, levels, max_frags, &L) || !ws ||
+  if (!splat_layout_for(np, n_views, views, crops, n_crops, levels, max_frags, &L) || !ws ||
       ws_bytes < L.total || !d_pyramid)
     return VRS_EINVAL;
   if (np > 0 && (!pos || !radius || !feat)) return VRS_EINVAL;
