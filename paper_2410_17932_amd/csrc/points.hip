@@ -37,7 +37,7 @@ struct SplatWs {
 constexpr int kSelBlock = 256;
 
 // look-back partition counter (256 bytes) + one status word per partition
-// (partitions of 2048 points; a bound for smaller ones too)
+// (partitions of kSelPart points; one word per 256 points bounds them)
 static size_t sel_tmp_bytes(int64_t np) {
   return 256 + (size_t)std::max<int64_t>(1, div_up(np, kSelBlock)) * 8;
 }
@@ -215,16 +215,16 @@ __device__ inline uint32_t pt_count(const KView& cv, int v, const KCrops& crops,
 }
 
 // Partition p (taken from an atomic counter, launch order) holds points
-// [2048p, 2048p+2048), handled in eight rounds of 256.  Per round and view
+// [1024p, 1024p+1024), handled in four rounds of 256.  Per round and view
 // each lane's fragment count and depth key go to LDS and each wave ballots
 // its survivors; one look-back per partition gives the partition's output
 // base; then the survivors go out view by view, each view's in point order
 // (rounds, then waves, then lanes), after all survivors of earlier
 // partitions.  Within one view the compacted list is in point order, which
 // is all the later stable sorts need (fragments of different views never
-// share a pyramid pixel).  One atomic per 2048 points: a single counter
+// share a pyramid pixel).  One atomic per 1024 points: a single counter
 // address serialises its atomics, so partitions are kept large.
-constexpr int kSelRounds = 8, kSelPart = kSelBlock * kSelRounds;
+constexpr int kSelRounds = 4, kSelPart = kSelBlock * kSelRounds;
 
 __global__ __launch_bounds__(kSelBlock) void k_pt_select(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
@@ -272,12 +272,13 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
   __syncthreads();
   // ---- exclusive scan of the slot counts in output order
   {
-    uint32_t c[NSLOT / kSelBlock], sum = 0;
+    constexpr int Q = NSLOT >= kSelBlock ? NSLOT / kSelBlock : 1;   // slots per thread
+    uint32_t c[Q], sum = 0;
 #pragma unroll
-    for (int q = 0; q < NSLOT / kSelBlock; ++q) {
-      const int e = tid * (NSLOT / kSelBlock) + q;
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid * Q + q;
       c[q] = sum;
-      sum += (uint32_t)__popcll(s_mask[e]);
+      sum += e < NSLOT ? (uint32_t)__popcll(s_mask[e]) : 0u;
     }
     uint32_t incl = sum;
 #pragma unroll
@@ -294,8 +295,8 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
       total += s_wsum[w];
     }
 #pragma unroll
-    for (int q = 0; q < NSLOT / kSelBlock; ++q)
-      s_pre[tid * (NSLOT / kSelBlock) + q] = woff + incl - sum + c[q];
+    for (int q = 0; q < Q; ++q)
+      if (tid * Q + q < NSLOT) s_pre[tid * Q + q] = woff + incl - sum + c[q];
     if (wave == 0) {
       const uint32_t excl = wave_lookback(flags, part, total, status);
       if (lane == 0) {
