@@ -10,10 +10,13 @@
 //   k_gs_emit         output-parallel: each thread writes pairs found by a
 //                     search over offsets staged in LDS; stores coalesce
 //   radix sort        (tile id) of the pairs, stable: keeps depth order
-//   k_gs_blend        one workgroup per tile, one wave per sub-tile; finds
-//                     the tile's range in the sorted keys, stages records in
-//                     LDS in batches, front-to-back blend with per-wave and
-//                     block-wide early exit
+//   k_gs_tile_ranges  [begin, end) per tile by a half-wave search of the
+//                     sorted keys, and a length bucket per tile
+//   radix sort        (one 8-bit pass) of the tiles, longest list first
+//   k_gs_blend        one workgroup per tile in that order, one wave per
+//                     sub-tile; records staged in LDS in batches,
+//                     front-to-back blend with per-wave and block-wide early
+//                     exit
 #include "gs_layout.h"
 
 namespace vrs {
@@ -181,6 +184,33 @@ __device__ inline uint32_t halfwave_lower_bound(const uint32_t* __restrict__ key
   return lo;
 }
 
+// Tile ranges and schedule: one wave per tile finds [begin, end) in the
+// sorted pair keys and files the tile under a length bucket (descending in
+// 16 log2(1 + length)), so that one stable 8-bit sort pass lists the tiles
+// longest first.  Work per tile is very uneven (dense screen regions hold
+// lists orders of magnitude longer than the median); starting the long ones
+// first keeps them off the end of the blend.
+__global__ __launch_bounds__(256) void k_gs_tile_ranges(const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ total_p,
+                                                        int64_t max_pairs, int64_t tiles_total,
+                                                        uint2* __restrict__ ranges,
+                                                        uint32_t* __restrict__ okey,
+                                                        uint32_t* __restrict__ oval) {
+  const int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (t >= tiles_total) return;   // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  const uint32_t cntp = (uint32_t)std::min<int64_t>(*total_p, max_pairs);
+  const uint32_t r = halfwave_lower_bound(keys, cntp, (uint32_t)t + (lane >= 32 ? 1u : 0u));
+  const uint32_t begin = __shfl(r, 0, 64), end_raw = __shfl(r, 32, 64);
+  const uint32_t end = end_raw > begin ? end_raw : begin;
+  if (lane == 0) {
+    ranges[t] = make_uint2(begin, end);
+    const float b = 16.0f * log2f(1.0f + (float)(end - begin));
+    okey[t] = 255u - (uint32_t)fminf(b, 255.0f);
+    oval[t] = (uint32_t)t;
+  }
+}
+
 // One workgroup per (view, tile).  The tile is cut into SUB x SUB sub-tiles,
 // one wave each; a lane holds PPT pixels of its sub-tile (a column, rows
 // 64/SUB apart).  Records of the tile list are staged in LDS in batches of
@@ -189,9 +219,9 @@ __device__ inline uint32_t halfwave_lower_bound(const uint32_t* __restrict__ key
 // only the records that touch its sub-tile, in list order, with scalar bit
 // scans.  The per-pixel step is branch-free: every lane evaluates, and
 // selects decide.  A wave stops evaluating once all its pixels have
-// stopped; the block leaves the list when every wave has.  The tile's
-// [begin, end) in the sorted pair list is found by a half-wave search and
-// stored for the backward pass.
+// stopped; the block leaves the list when every wave has.  Workgroup i
+// takes the i-th tile of the longest-first schedule.
+
 // A 64-bit value known to be equal in every lane, moved to scalar registers
 // (the builtin returns a signed 32-bit int: each half goes through uint32_t
 // so that the low half is not sign-extended into the high one).
@@ -239,10 +269,10 @@ struct BlendCfg {
 template <int TILE, int SUB>
 __global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ids,
-    const uint32_t* __restrict__ total_p, int64_t max_pairs, const float4* __restrict__ rec,
-    int64_t n, KViews views, GsOpt o, int64_t tiles_x, int64_t tiles_per_view,
-    uint2* __restrict__ ranges, float* __restrict__ out_rgb, float* __restrict__ out_depth,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ rec, int64_t n, KViews views, GsOpt o, int64_t tiles_x,
+    int64_t tiles_per_view, const uint2* __restrict__ ranges, float* __restrict__ out_rgb,
+    float* __restrict__ out_depth,
     float* __restrict__ out_t, int32_t* __restrict__ out_n, uint32_t* __restrict__ out_last,
     uint32_t* __restrict__ out_evals) {
   using Cfg = BlendCfg<TILE, SUB>;
@@ -250,8 +280,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK];
   __shared__ uint64_t s_mask[NW][NW];   // [sub-tile][group of 64 records]: rectangle reaches it
   __shared__ uint64_t s_full[NW][NW];   // ... and the contributing ellipse may too
-  __shared__ uint32_t s_range[2];
-  const int64_t tglob = blockIdx.x;
+  const int64_t tglob = order[blockIdx.x];
   const int v = (int)(tglob / tiles_per_view);
   const int64_t tl = tglob - (int64_t)v * tiles_per_view;
   const int ty = (int)(tl / tiles_x), tx = (int)(tl - (int64_t)ty * tiles_x);
@@ -278,15 +307,8 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
     last[q] = 0;
     evals[q] = 0;
   }
-  if (wave == 0) {
-    const uint32_t cntp = (uint32_t)std::min<int64_t>(*total_p, max_pairs);
-    const uint32_t r = halfwave_lower_bound(keys, cntp, (uint32_t)tglob + (lane >= 32 ? 1u : 0u));
-    if (lane == 0) s_range[0] = r;
-    if (lane == 32) s_range[1] = r;
-  }
-  __syncthreads();
-  const uint32_t begin = s_range[0], end = s_range[1] > begin ? s_range[1] : begin;
-  if (tid == 0) ranges[tglob] = make_uint2(begin, end);
+  const uint2 rg = ranges[tglob];
+  const uint32_t begin = rg.x, end = rg.y;
   const float aclamp = o.aclamp, amin = o.amin, tmin = o.tmin;
   const float xc = (float)px + 0.5f;
   float yc[PPT];
@@ -475,17 +497,15 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
 // Sub-tile edge per tile size: 16x16 sub-tiles (4 pixels per lane) for
 // 32-pixel tiles, 8x8 (one pixel per lane) below.
 template <int TILE>
-static void launch_blend(const RenderWs& L, void* ws, int64_t n, int64_t max_pairs,
+static void launch_blend(const RenderWs& L, void* ws, int64_t n, const uint32_t* order,
                          const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
                          int32_t* nc, hipStream_t st) {
   constexpr int SUB = TILE == 32 ? 16 : 8;
-  const uint32_t* keys = at<uint32_t>(ws, L.pairs_in_1 ? L.pkey1 : L.pkey0);
   const uint32_t* ids = at<uint32_t>(ws, L.pairs_in_1 ? L.pval1 : L.pval0);
   hipLaunchKernelGGL((k_gs_blend<TILE, SUB>), dim3((unsigned)L.tiles_total),
-                     dim3(BlendCfg<TILE, SUB>::BLOCK), 0, st, keys, ids,
-                     at<uint32_t>(ws, L.pair_count), max_pairs, at<float4>(ws, L.rec), n, kv, o,
-                     L.tiles_x, L.tiles_x * L.tiles_y, at<uint2>(ws, L.ranges), rgb, depth, tf, nc,
-                     at<uint32_t>(ws, L.last), at<uint32_t>(ws, L.evals));
+                     dim3(BlendCfg<TILE, SUB>::BLOCK), 0, st, order, ids, at<float4>(ws, L.rec), n,
+                     kv, o, L.tiles_x, L.tiles_x * L.tiles_y, at<uint2>(ws, L.ranges), rgb, depth,
+                     tf, nc, at<uint32_t>(ws, L.last), at<uint32_t>(ws, L.evals));
 }
 
 extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
@@ -548,10 +568,21 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     VRS_HIP_CHECK(fill_u32(pair_count, 0, 1, st));
   }
   trace_begin(VRS_TRACE_GS_BLEND, st);
+  // tile ranges, then the tiles longest list first (one stable 8-bit pass)
+  hipLaunchKernelGGL(k_gs_tile_ranges, dim3(div_up(L.tiles_total * 64, 256)), dim3(256), 0, st,
+                     at<uint32_t>(ws, L.pairs_in_1 ? L.pkey1 : L.pkey0), pair_count, max_pairs,
+                     L.tiles_total, at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.okey0),
+                     at<uint32_t>(ws, L.oval0));
+  VRS_LAUNCH_CHECK();
+  bool o1 = false;
+  VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.okey0), at<uint32_t>(ws, L.oval0),
+                               at<uint32_t>(ws, L.okey1), at<uint32_t>(ws, L.oval1), nullptr,
+                               L.tiles_total, 8, at<void>(ws, L.sort_tmp), dev_status, st, &o1));
+  const uint32_t* order = at<uint32_t>(ws, o1 ? L.oval1 : L.oval0);
   switch (o.tile) {
-    case 8: launch_blend<8>(L, ws, n, max_pairs, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    case 16: launch_blend<16>(L, ws, n, max_pairs, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    default: launch_blend<32>(L, ws, n, max_pairs, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    case 8: launch_blend<8>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    case 16: launch_blend<16>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    default: launch_blend<32>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
   }
   VRS_LAUNCH_CHECK();
   trace_end(VRS_TRACE_GS_BLEND, st);

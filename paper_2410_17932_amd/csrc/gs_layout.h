@@ -7,6 +7,7 @@ namespace vrs {
 // ---------------------------------------------------------------- layout
 struct RenderWs {
   size_t rec, dkey0, dval0, dkey1, dval1, ntiles, offs, pair_count, pkey0, pval0, pkey1, pval1,
+      okey0, oval0, okey1, oval1,   // tile schedule (length bucket, tile), sorted once
       ranges, last, evals, g2d, sort_tmp, scan_tmp, total;
   int64_t vn, tiles_x, tiles_y, tiles_total, npix;
   int tile_bits;
@@ -48,10 +49,15 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->pkey1 = c.take(mp * 4);
   L->pval1 = c.take(mp * 4);
   L->ranges = c.take((size_t)L->tiles_total * 8);
+  L->okey0 = c.take((size_t)L->tiles_total * 4);
+  L->oval0 = c.take((size_t)L->tiles_total * 4);
+  L->okey1 = c.take((size_t)L->tiles_total * 4);
+  L->oval1 = c.take((size_t)L->tiles_total * 4);
   L->last = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->evals = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->g2d = c.take((size_t)vn * 10 * 4);   // per (view, Gaussian) screen-space gradients
-  L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->tile_bits)));
+  L->sort_tmp = c.take(std::max(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->tile_bits)),
+                                sort_tmp_bytes(L->tiles_total, 8)));
   L->scan_tmp = c.take(scan_tmp_bytes(vn));
   L->total = c.off;
   return true;
