@@ -250,9 +250,9 @@ def main():
                     work=dict(flops=flops, evaluations=evals, contributions=contrib,
                               ms=round(stages["gs_blend"], 4)))
     # rasterizer HBM rate: the tile-pair sort (the periphery's HBM-bound
-    # stage): per pair and pass 16 B (key+id read and written), + 4 B/pair
-    # for the histogram read
-    sort_bytes = fr.pairs * (2 * 16 + 4)
+    # stage), two 8-bit passes; per pair and pass 4 B read by the digit count
+    # and 16 B (key + id) read and written by the scatter
+    sort_bytes = fr.pairs * 2 * (4 + 16)
     sort_gbs = sort_bytes / (stages["gs_sort"] * 1e-3) / 1e9
     result = dict(metric="stereo foveated frames/s @2016x2240/eye; rasterizer HBM GB/s vs peak",
                   value=round(fps, 3), unit="frames/s", n_gpus=1, steps=args.steps,

@@ -563,12 +563,12 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                                  at<uint32_t>(ws, L.pkey1), at<uint32_t>(ws, L.pval1), pair_count,
                                  max_pairs, L.tile_bits, at<void>(ws, L.sort_tmp), dev_status, st,
                                  &p1));
-    trace_end(VRS_TRACE_GS_SORT, st);
   } else {
+    trace_begin(VRS_TRACE_GS_SORT, st);
     VRS_HIP_CHECK(fill_u32(pair_count, 0, 1, st));
   }
-  trace_begin(VRS_TRACE_GS_BLEND, st);
-  // tile ranges, then the tiles longest list first (one stable 8-bit pass)
+  // tile ranges, then the tiles longest list first (one stable 8-bit pass);
+  // timed with the tile sort (binning), so the blend stage is the blend alone
   hipLaunchKernelGGL(k_gs_tile_ranges, dim3(div_up(L.tiles_total * 64, 256)), dim3(256), 0, st,
                      at<uint32_t>(ws, L.pairs_in_1 ? L.pkey1 : L.pkey0), pair_count, max_pairs,
                      L.tiles_total, at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.okey0),
@@ -579,6 +579,8 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                                at<uint32_t>(ws, L.okey1), at<uint32_t>(ws, L.oval1), nullptr,
                                L.tiles_total, 8, at<void>(ws, L.sort_tmp), dev_status, st, &o1));
   const uint32_t* order = at<uint32_t>(ws, o1 ? L.oval1 : L.oval0);
+  trace_end(VRS_TRACE_GS_SORT, st);
+  trace_begin(VRS_TRACE_GS_BLEND, st);
   switch (o.tile) {
     case 8: launch_blend<8>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
     case 16: launch_blend<16>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;

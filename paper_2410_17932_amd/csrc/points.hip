@@ -5,7 +5,7 @@
 // Instead of per-pixel fragment lists sorted in place, the pass orders all
 // surviving (view, point) entries by depth once, emits every fragment in
 // that order, and sorts the fragments stably by layer pixel -- the same
-// onesweep sort the periphery uses -- so each pixel's list comes out in
+// radix sort the periphery uses -- so each pixel's list comes out in
 // (depth, point index) order with no atomics and no per-pixel sort.
 //   k_pt_select    one thread per point, points read once for all crops:
 //                  projection, layer, crop footprints, then the depth cull
