@@ -166,11 +166,14 @@ vrs_status vrs_render_gaussians(const float* mean, const float* cov, const float
  * (uint32 [max_pairs]), tile ranges (uint32 pairs [tiles][2] = begin, end
  * for tile index v*tiles_per_view + ty*tiles_x + tx), and per pixel the
  * number of Gaussians whose rectangle held the pixel and that the pixel
- * evaluated before it stopped (uint32 [V][H][W]: the blend's work count).
+ * evaluated before it stopped (uint32 [V][H][W]: the blend's work count);
+ * super_pair_count (uint32, device): the number of (super-tile, Gaussian)
+ * pairs the binning sorted, a super-tile being 8 x 8 tiles.
  * For inspection, tests and throughput accounting. */
 typedef struct {
   size_t pair_count, sorted_ids, tile_ranges, pixel_evals;
   int64_t tiles_x, tiles_y, tiles_total;
+  size_t super_pair_count;
 } vrs_render_layout;
 vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const vrs_view* views,
                                        const vrs_raster_opts* opts, int64_t max_pairs,

@@ -56,7 +56,8 @@ class RenderLayout(ctypes.Structure):
     _fields_ = [("pair_count", ctypes.c_size_t), ("sorted_ids", ctypes.c_size_t),
                 ("tile_ranges", ctypes.c_size_t), ("pixel_evals", ctypes.c_size_t),
                 ("tiles_x", ctypes.c_int64),
-                ("tiles_y", ctypes.c_int64), ("tiles_total", ctypes.c_int64)]
+                ("tiles_y", ctypes.c_int64), ("tiles_total", ctypes.c_int64),
+                ("super_pair_count", ctypes.c_size_t)]
 
 
 class SplatLayout(ctypes.Structure):
@@ -255,6 +256,9 @@ class RenderWorkspace:
 
     def pair_count(self) -> int:
         return int(self.u32(self.layout.pair_count, 1).item())
+
+    def super_pair_count(self) -> int:
+        return int(self.u32(self.layout.super_pair_count, 1).item())
 
     def pixel_evals(self, npix):
         """Per-pixel evaluation counts of the last blend (device tensor)."""

@@ -415,16 +415,29 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
   // lane's four channels are contiguous in h and in the pre-activations.
   const bool write_h = hf.fovea == nullptr || pre != nullptr;
   const int x = ox + col;
+  // channel pairs outer, rows inner: biases and head weights are read once
+  // per pair; the head's partial products accumulate per row
+  float part[RPW][3];
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) {
-    const int y = oy + r0 + r;
-    if (y >= S) continue;   // uniform over the wave
-    const long long p = (long long)y * S + x;
-    float part[3] = {0.0f, 0.0f, 0.0f};
+  for (int r = 0; r < RPW; ++r) part[r][0] = part[r][1] = part[r][2] = 0.0f;
 #pragma unroll
-    for (int t = 0; t < NT / 2; ++t) {
-      const float4 bf = *reinterpret_cast<const float4*>(&bp[2 * t * 16 + 4 * kq]);
-      const float4 bg = *reinterpret_cast<const float4*>(&bp[(2 * t + 1) * 16 + 4 * kq]);
+  for (int t = 0; t < NT / 2; ++t) {
+    const float4 bf = *reinterpret_cast<const float4*>(&bp[2 * t * 16 + 4 * kq]);
+    const float4 bg = *reinterpret_cast<const float4*>(&bp[(2 * t + 1) * 16 + 4 * kq]);
+    float w[4][3];
+    if (hf.fovea) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ch = t * 16 + 4 * kq + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[i][c] = ch < d.width ? hf.wo[c * d.width + ch] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int y = oy + r0 + r;
+      if (y >= S) continue;   // uniform over the wave
+      const long long p = (long long)y * S + x;
       const float f[4] = {acc[r][2 * t][0] + bf.x, acc[r][2 * t][1] + bf.y,
                           acc[r][2 * t][2] + bf.z, acc[r][2 * t][3] + bf.w};
       const float g[4] = {acc[r][2 * t + 1][0] + bg.x, acc[r][2 * t + 1][1] + bg.y,
@@ -434,12 +447,9 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
       for (int i = 0; i < 4; ++i) hv[i] = elu_f(f[i]) * sigmoid_f(g[i]);
       if (hf.fovea) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int ch = t * 16 + 4 * kq + i;
-          if (ch < d.width)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) part[c] = fmaf(hf.wo[c * d.width + ch], hv[i], part[c]);
-        }
+          for (int c = 0; c < 3; ++c) part[r][c] = fmaf(w[i][c], hv[i], part[r][c]);
       }
       if (x < S) {
         if (write_h) {
@@ -458,17 +468,25 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
         }
       }
     }
-    if (hf.fovea) {
-      // sum the head's partial products over the four lanes of the pixel
+  }
+  if (hf.fovea) {
+    // sum the head's partial products over the four lanes of each pixel
+    const float b0 = hf.bo[0], b1 = hf.bo[1], b2 = hf.bo[2];
+    const long long opl = (long long)S * S;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int y = oy + r0 + r;
+      if (y >= S) continue;   // uniform over the wave
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        part[c] += __shfl_xor(part[c], 16, 64);
-        part[c] += __shfl_xor(part[c], 32, 64);
+        part[r][c] += __shfl_xor(part[r][c], 16, 64);
+        part[r][c] += __shfl_xor(part[r][c], 32, 64);
       }
       if (kq == 0 && x < S) {
-        const long long opl = (long long)S * S;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) hf.fovea[hf.out_base[k] + c * opl + p] = part[c] + hf.bo[c];
+        const long long p = (long long)y * S + x;
+        hf.fovea[hf.out_base[k] + p] = part[r][0] + b0;
+        hf.fovea[hf.out_base[k] + opl + p] = part[r][1] + b1;
+        hf.fovea[hf.out_base[k] + 2 * opl + p] = part[r][2] + b2;
       }
     }
   }

@@ -343,7 +343,7 @@ static void launch_blend_bwd(const RenderWs& L, void* ws, int64_t n, const KView
                              const float* d_depth, hipStream_t st) {
   hipLaunchKernelGGL(k_gs_blend_bwd<TILE>, dim3((unsigned)L.tiles_total),
                      dim3(BwdCfg<TILE>::BLOCK), 0, st, at<uint2>(ws, L.ranges),
-                     at<uint32_t>(ws, L.pairs_in_1 ? L.pval1 : L.pval0), at<float4>(ws, L.rec), n,
+                     at<uint32_t>(ws, L.ids), at<float4>(ws, L.rec), n,
                      kv, o, L.tiles_x, L.tiles_x * L.tiles_y, at<uint32_t>(ws, L.last), tf, d_rgb,
                      d_depth, at<float>(ws, L.g2d));
 }

@@ -4,14 +4,28 @@
 // Pipeline per call, all views in the same launches:
 //   k_gs_preprocess   one thread per Gaussian, attributes read once for all
 //                     views; EWA projection, SH colour, 48-byte record,
-//                     depth key and tile count per (view, Gaussian)
+//                     depth key and super-tile count per (view, Gaussian);
+//                     per-block totals of tile pairs
 //   radix sort        (depth bits) of all (view, Gaussian) entries
-//   scan              tile counts in depth order -> pair offsets (device)
-//   k_gs_emit         output-parallel: each thread writes pairs found by a
-//                     search over offsets staged in LDS; stores coalesce
-//   radix sort        (tile id) of the pairs, stable: keeps depth order
-//   k_gs_tile_ranges  [begin, end) per tile by a half-wave search of the
-//                     sorted keys, and a length bucket per tile
+//   scan              super-tile counts in depth order -> offsets (device)
+//   k_gs_emit_super   output-parallel: one (super-tile, Gaussian) pair per
+//                     8 x 8-tile super-tile a rectangle reaches, carrying
+//                     the rectangle's part inside it; stores coalesce
+//   radix sort        (super-tile id) of those pairs, stable: keeps depth
+//                     order, and there are few of them (a Gaussian reaches
+//                     far fewer super-tiles than tiles)
+//   k_gs_runs         each super-tile's run [begin, end) in the sorted pairs
+//   k_gs_units        runs cut into work units of 512 pairs (a scan), and
+//                     the exact tile pair total
+//   k_gs_bin_count    one wave per unit: per tile (tile = lane of an 8 x 8
+//                     super-tile) the unit's pairs reaching it, from row
+//                     and column ballots
+//   k_gs_bin_prefix   per super-tile: prefix of those counts over its units
+//                     and the tile totals; scan -> tile list offsets
+//   k_gs_tile_ranges  [begin, end) and a length bucket per tile
+//   k_gs_bin_scatter  one wave per unit: every Gaussian index goes to its
+//                     final place in each tile list it belongs to, its rank
+//                     within a round from one ballot per tile
 //   radix sort        (one 8-bit pass) of the tiles, longest list first
 //   k_gs_blend        one workgroup per tile in that order, one wave per
 //                     sub-tile; records staged in LDS in batches,
@@ -28,7 +42,7 @@ bool gs_render_layout(int64_t n, int nv, const vrs_view* views, int tile, int64_
   if (!render_layout(n, nv, views, tile, max_pairs, &L)) return false;
   *rec = L.rec;
   *ranges = L.ranges;
-  *sorted_ids = L.pairs_in_1 ? L.pval1 : L.pval0;
+  *sorted_ids = L.ids;
   *last = L.last;
   *pair_count = L.pair_count;
   *tiles_x = L.tiles_x;
@@ -42,84 +56,102 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
     const float* __restrict__ mean, const float* __restrict__ cov,
     const float* __restrict__ opacity, const float* __restrict__ sh, int deg, int64_t n,
     KViews views, GsOpt o, float4* __restrict__ rec, uint32_t* __restrict__ dkey,
-    uint32_t* __restrict__ dval, uint32_t* __restrict__ ntiles) {
+    uint32_t* __restrict__ dval, uint32_t* __restrict__ nsup, uint64_t* __restrict__ psum) {
+  __shared__ uint64_t s_p[4];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float mx = mean[i], my = mean[n + i], mz = mean[2 * n + i];
-  float S6[6];
+  uint64_t pairs = 0;   // tiles reached, over the views
+  if (i < n) {
+    const float mx = mean[i], my = mean[n + i], mz = mean[2 * n + i];
+    float S6[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) S6[k] = cov[k * n + i];
-  const float op = opacity[i];
-  const int K = (deg + 1) * (deg + 1);
-  float coef[16][3];
+    for (int k = 0; k < 6; ++k) S6[k] = cov[k * n + i];
+    const float op = opacity[i];
+    const int K = (deg + 1) * (deg + 1);
+    float coef[16][3];
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (k < K)
+    for (int k = 0; k < 16; ++k)
+      if (k < K)
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) coef[k][ch] = sh[(k * 3 + ch) * n + i];
-  for (int v = 0; v < views.n; ++v) {
-    const KView& cv = views.v[v];
-    const int64_t e = v * n + i;
-    Geom g;
-    const bool ok = gs_geom32(cv, mx, my, mz, S6, o.lowpass, o.extent, g);
-    dval[e] = (uint32_t)e;
-    if (!ok) {
-      dkey[e] = 0xffffffffu;
-      ntiles[e] = 0;
-      rec[3 * e + 0] = make_float4(0, 0, 0, 0);
-      rec[3 * e + 1] = make_float4(0, 0, 0, 0);
-      rec[3 * e + 2] = make_float4(0, 0, __uint_as_float(0xffffffffu), 0);
-      continue;
+        for (int ch = 0; ch < 3; ++ch) coef[k][ch] = sh[(k * 3 + ch) * n + i];
+    for (int v = 0; v < views.n; ++v) {
+      const KView& cv = views.v[v];
+      const int64_t e = v * n + i;
+      Geom g;
+      const bool ok = gs_geom32(cv, mx, my, mz, S6, o.lowpass, o.extent, g);
+      dval[e] = (uint32_t)e;
+      if (!ok) {
+        dkey[e] = 0xffffffffu;
+        nsup[e] = 0;
+        rec[3 * e + 0] = make_float4(0, 0, 0, 0);
+        rec[3 * e + 1] = make_float4(0, 0, 0, 0);
+        rec[3 * e + 2] = make_float4(0, 0, __uint_as_float(0xffffffffu), 0);
+        continue;
+      }
+      const float inv = 1.0f / g.det;
+      const float A = g.c * inv, B = -g.b * inv, C = g.a * inv;
+      // view-dependent colour
+      float dx = mx - cv.cam[0], dy = my - cv.cam[1], dz = mz - cv.cam[2];
+      const float rn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+      dx *= rn; dy *= rn; dz *= rn;
+      float Y[16];
+      sh_eval(deg, dx, dy, dz, Y);
+      float col[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < K) acc += Y[k] * coef[k][ch];
+        col[ch] = acc > 0.0f ? acc : 0.0f;
+      }
+      const int tile = o.tile;
+      const int tx0 = g.x0 / tile, tx1 = g.x1 / tile, ty0 = g.y0 / tile, ty1 = g.y1 / tile;
+      dkey[e] = __float_as_uint(g.t[2]);
+      pairs += (uint64_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+      nsup[e] = (uint32_t)(((tx1 / kSuper) - (tx0 / kSuper) + 1) *
+                           ((ty1 / kSuper) - (ty0 / kSuper) + 1));
+      rec[3 * e + 0] = make_float4(g.px, g.py, A, B);
+      rec[3 * e + 1] = make_float4(C, op, col[0], col[1]);
+      rec[3 * e + 2] = make_float4(col[2], g.t[2], __uint_as_float(pack_xy(g.x0, g.y0)),
+                                   __uint_as_float(pack_xy(g.x1, g.y1)));
     }
-    const float inv = 1.0f / g.det;
-    const float A = g.c * inv, B = -g.b * inv, C = g.a * inv;
-    // view-dependent colour
-    float dx = mx - cv.cam[0], dy = my - cv.cam[1], dz = mz - cv.cam[2];
-    const float rn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= rn; dy *= rn; dz *= rn;
-    float Y[16];
-    sh_eval(deg, dx, dy, dz, Y);
-    float col[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float acc = 0.5f;
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k < K) acc += Y[k] * coef[k][ch];
-      col[ch] = acc > 0.0f ? acc : 0.0f;
-    }
-    const int tile = o.tile;
-    const int tx0 = g.x0 / tile, tx1 = g.x1 / tile, ty0 = g.y0 / tile, ty1 = g.y1 / tile;
-    dkey[e] = __float_as_uint(g.t[2]);
-    ntiles[e] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-    rec[3 * e + 0] = make_float4(g.px, g.py, A, B);
-    rec[3 * e + 1] = make_float4(C, op, col[0], col[1]);
-    rec[3 * e + 2] = make_float4(col[2], g.t[2], __uint_as_float(pack_xy(g.x0, g.y0)),
-                                 __uint_as_float(pack_xy(g.x1, g.y1)));
   }
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) pairs += __shfl_xor(pairs, s, 64);
+  if ((threadIdx.x & 63) == 0) s_p[threadIdx.x >> 6] = pairs;
+  __syncthreads();
+  if (threadIdx.x == 0) psum[blockIdx.x] = s_p[0] + s_p[1] + s_p[2] + s_p[3];
 }
 
 // ------------------------------------------------------------------ emit
-// Output-parallel pair emission.  A block owns 256 consecutive depth-ordered
-// entries; their pair offsets and tile rectangles are staged in LDS, and each
-// thread writes pairs p = first + tid, first + tid + 256, ... of the block's
-// range, finding the owning entry (last i with off[i] <= p) by binary search
-// in LDS.  Stores of consecutive p are consecutive, so they coalesce.
-// key = view * tiles_per_view + tile, value = Gaussian index.
+// Output-parallel emission of (super-tile, Gaussian) pairs.  A block owns
+// 256 consecutive depth-ordered entries; their pair offsets and rectangles
+// are staged in LDS, and each thread writes pairs p = first + tid, first +
+// tid + 256, ... of the block's range, finding the owning entry (last i with
+// off[i] <= p) by binary search in LDS.  Stores of consecutive p are
+// consecutive, so they coalesce.  key = view * supers_per_view + super-tile;
+// value = Gaussian index | (tile rectangle inside the super-tile, 3 bits per
+// bound: x0, x1, y0, y1) << 32.
 constexpr int kEmitBlock = 256;
-__global__ __launch_bounds__(kEmitBlock) void k_gs_emit(
+__global__ __launch_bounds__(kEmitBlock) void k_gs_emit_super(
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ sorted_e,
     const float4* __restrict__ rec, const uint32_t* __restrict__ total_p, int64_t vn,
-    int64_t n, int64_t max_pairs, int tile, int64_t tiles_x, int64_t tiles_per_view,
-    uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, int32_t* status) {
+    int64_t n, int64_t max_pairs, int tile, int64_t sxn, int64_t spv,
+    uint32_t* __restrict__ skey, uint64_t* __restrict__ sval, int64_t st_total,
+    uint2* __restrict__ srange, int32_t* status) {
   __shared__ uint32_t s_off[kEmitBlock + 1];
-  __shared__ uint32_t s_base[kEmitBlock];   // key of the entry's first tile
-  __shared__ uint32_t s_w[kEmitBlock];      // tiles per rectangle row
+  __shared__ uint32_t s_base[kEmitBlock];   // key of the entry's first super-tile
+  __shared__ uint32_t s_w[kEmitBlock];      // super-tiles per rectangle row
   __shared__ uint32_t s_id[kEmitBlock];
+  __shared__ uint32_t s_lo[kEmitBlock], s_hi[kEmitBlock];   // tile rectangle (x | y << 16)
   const int tid = threadIdx.x;
   const int64_t total = *total_p;
   const int64_t cap = std::min<int64_t>(total, max_pairs);
   if (blockIdx.x == 0 && tid == 0 && total > max_pairs) set_status(status, VRS_ECAPACITY);
+  // the run ranges are filled in after the sort; absent super-tiles keep (0, 0)
+  for (int64_t i = blockIdx.x * (int64_t)kEmitBlock + tid; i < st_total;
+       i += (int64_t)gridDim.x * kEmitBlock)
+    srange[i] = make_uint2(0u, 0u);
   const int64_t j0 = (int64_t)blockIdx.x * kEmitBlock;
   const int64_t j = j0 + tid;
   if (j < vn) {
@@ -129,10 +161,12 @@ __global__ __launch_bounds__(kEmitBlock) void k_gs_emit(
     const float4 r2 = rec[3 * (int64_t)e + 2];
     const uint32_t lo_xy = __float_as_uint(r2.z), hi_xy = __float_as_uint(r2.w);
     const int tx0 = (int)(lo_xy & 0xffffu) / tile, ty0 = (int)(lo_xy >> 16) / tile;
-    const int tx1 = (int)(hi_xy & 0xffffu) / tile;
-    s_base[tid] = (uint32_t)(v * tiles_per_view + (int64_t)ty0 * tiles_x + tx0);
-    s_w[tid] = (uint32_t)(tx1 - tx0 + 1);
+    const int tx1 = (int)(hi_xy & 0xffffu) / tile, ty1 = (int)(hi_xy >> 16) / tile;
+    s_base[tid] = (uint32_t)(v * spv + (int64_t)(ty0 / kSuper) * sxn + tx0 / kSuper);
+    s_w[tid] = (uint32_t)(tx1 / kSuper - tx0 / kSuper + 1);
     s_id[tid] = (uint32_t)gi;
+    s_lo[tid] = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+    s_hi[tid] = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
   } else {
     s_off[tid] = (uint32_t)total;
   }
@@ -152,8 +186,14 @@ __global__ __launch_bounds__(kEmitBlock) void k_gs_emit(
     const uint32_t k = (uint32_t)(p - (int64_t)s_off[lo]);
     const uint32_t w = s_w[lo];
     const uint32_t row = k / w, col = k - row * w;
-    pkey[p] = s_base[lo] + row * (uint32_t)tiles_x + col;
-    pval[p] = s_id[lo];
+    const int tx0 = (int)(s_lo[lo] & 0xffffu), ty0 = (int)(s_lo[lo] >> 16);
+    const int tx1 = (int)(s_hi[lo] & 0xffffu), ty1 = (int)(s_hi[lo] >> 16);
+    const int sx = tx0 / kSuper + (int)col, sy = ty0 / kSuper + (int)row;
+    const int lx0 = max(tx0 - sx * kSuper, 0), lx1 = min(tx1 - sx * kSuper, kSuper - 1);
+    const int ly0 = max(ty0 - sy * kSuper, 0), ly1 = min(ty1 - sy * kSuper, kSuper - 1);
+    const uint32_t r12 = (uint32_t)(lx0 | (lx1 << 3) | (ly0 << 6) | (ly1 << 9));
+    skey[p] = s_base[lo] + row * (uint32_t)sxn + col;
+    sval[p] = ((uint64_t)r12 << 32) | s_id[lo];
   }
 }
 
@@ -184,30 +224,273 @@ __device__ inline uint32_t halfwave_lower_bound(const uint32_t* __restrict__ key
   return lo;
 }
 
-// Tile ranges and schedule: one wave per tile finds [begin, end) in the
-// sorted pair keys and files the tile under a length bucket (descending in
-// 16 log2(1 + length)), so that one stable 8-bit sort pass lists the tiles
-// longest first.  Work per tile is very uneven (dense screen regions hold
-// lists orders of magnitude longer than the median); starting the long ones
-// first keeps them off the end of the blend.
-__global__ __launch_bounds__(256) void k_gs_tile_ranges(const uint32_t* __restrict__ keys,
+// ------------------------------------------------------------- binning
+// After the stable sort by super-tile, each super-tile's pairs form a run in
+// depth order.  Runs are cut into work units of kBinUnit pairs, one wave
+// each, taken 64 pairs (one per lane) per round.  Lane l stands for tile
+// (l / 8, l % 8) of the super-tile.  The pairs reaching a tile row or column
+// are one ballot each, so the pairs reaching a tile are the AND of two of
+// them: their count per tile, and, when scattering, each pair's rank among
+// them (pairs in lower lanes come first, which is depth order).
+
+// R[r] (X[c]): lanes whose rectangle reaches tile row r (column c); rp, cp:
+// the same per lane
+__device__ inline void bin_masks(uint32_t r12, bool ok, uint64_t* R, uint64_t* X, bool* rp,
+                                 bool* cp) {
+  const int lx0 = (int)(r12 & 7u), lx1 = (int)((r12 >> 3) & 7u);
+  const int ly0 = (int)((r12 >> 6) & 7u), ly1 = (int)((r12 >> 9) & 7u);
+#pragma unroll
+  for (int k = 0; k < kSuper; ++k) {
+    rp[k] = ok && ly0 <= k && k <= ly1;
+    cp[k] = ok && lx0 <= k && k <= lx1;
+    R[k] = __ballot(rp[k]);
+    X[k] = __ballot(cp[k]);
+  }
+}
+
+// pairs of the round that reach lane l's tile
+__device__ inline uint32_t bin_lane_count(const uint64_t* R, const uint64_t* X, int lane) {
+  const int r = lane >> 3, c = lane & 7;
+  uint64_t a = R[0], b = X[0];
+#pragma unroll
+  for (int k = 1; k < kSuper; ++k) {
+    a = r == k ? R[k] : a;
+    b = c == k ? X[k] : b;
+  }
+  return (uint32_t)__popcll(a & b);
+}
+
+// global index of lane l's tile in super-tile s; false where it lies
+// outside the view
+__device__ inline bool bin_tile(int64_t s, int lane, int64_t sxn, int64_t spv, int64_t tiles_x,
+                                int64_t tiles_y, int64_t* t) {
+  const int64_t v = s / spv, sl = s - v * spv;
+  const int64_t sy = sl / sxn, sx = sl - sy * sxn;
+  const int64_t ty = sy * kSuper + (lane >> 3), tx = sx * kSuper + (lane & 7);
+  *t = (v * tiles_y + ty) * tiles_x + tx;
+  return ty < tiles_y && tx < tiles_x;
+}
+
+// Run boundaries: [begin, end) of every super-tile present in the sorted
+// keys (absent ones keep the zeroed range).
+__global__ __launch_bounds__(256) void k_gs_runs(const uint32_t* __restrict__ skeys,
+                                                 const uint32_t* __restrict__ stotal_p,
+                                                 int64_t max_pairs, uint2* __restrict__ srange) {
+  const int64_t cnt = std::min<int64_t>(*stotal_p, max_pairs);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = skeys[i];
+    if (i == 0 || skeys[i - 1] != k) srange[k].x = (uint32_t)i;
+    if (i == cnt - 1 || skeys[i + 1] != k) srange[k].y = (uint32_t)(i + 1);
+  }
+}
+
+// One workgroup: units per run, their exclusive scan (first unit of each
+// super-tile, ubase[st_total] = number of units), and the exact number of
+// tile pairs from the preprocess blocks' partial sums (whatever the
+// capacity).
+constexpr int kUnitsBlock = 1024;
+__global__ __launch_bounds__(kUnitsBlock) void k_gs_units(const uint2* __restrict__ srange,
+                                                          int64_t st_total,
+                                                          const uint64_t* __restrict__ psum,
+                                                          int64_t nps, uint32_t* __restrict__ ubase,
+                                                          uint32_t* __restrict__ nunits,
+                                                          uint32_t* __restrict__ pair_count) {
+  __shared__ uint32_t s_w[kUnitsBlock / 64];
+  __shared__ uint64_t s_p[kUnitsBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t p = 0;
+  for (int64_t k = tid; k < nps; k += kUnitsBlock) p += psum[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+  if (lane == 0) s_p[wave] = p;
+  uint32_t carry = 0;
+  for (int64_t s0 = 0; s0 < st_total; s0 += kUnitsBlock) {
+    const int64_t s = s0 + tid;
+    uint32_t u = 0;
+    if (s < st_total) {
+      const uint2 r = srange[s];
+      u = r.y > r.x ? (r.y - r.x + kBinUnit - 1) / kBinUnit : 0u;
+    }
+    uint32_t incl = u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0, btot = 0;
+#pragma unroll
+    for (int w = 0; w < kUnitsBlock / 64; ++w) {
+      woff += w < wave ? s_w[w] : 0u;
+      btot += s_w[w];
+    }
+    if (s < st_total) ubase[s] = carry + woff + incl - u;
+    carry += btot;
+    __syncthreads();   // s_w is rewritten by the next chunk
+  }
+  if (tid == 0) {
+    ubase[st_total] = carry;
+    *nunits = carry;
+    uint64_t q = 0;
+    for (int w = 0; w < kUnitsBlock / 64; ++w) q += s_p[w];
+    *pair_count = (uint32_t)std::min<uint64_t>(q, 0xffffffffull);
+  }
+}
+
+// Unit u of the scan -> its super-tile (last s with ubase[s] <= u) and pair
+// range [lo, hi).
+__device__ inline int64_t bin_unit(const uint32_t* __restrict__ ubase, int64_t st_total,
+                                   const uint2* __restrict__ srange, uint32_t u, uint32_t* lo,
+                                   uint32_t* hi) {
+  const int64_t s = (int64_t)halfwave_lower_bound(ubase, (uint32_t)st_total, u + 1) - 1;
+  const uint2 r = srange[s];
+  *lo = r.x + (u - ubase[s]) * kBinUnit;
+  *hi = std::min<uint32_t>(r.y, *lo + kBinUnit);
+  return s;
+}
+
+// Per unit and tile: pairs of the unit reaching the tile.  Waves take units
+// in grid-stride order; the grid is sized for the capacity, the count is
+// read on the device.
+__global__ __launch_bounds__(256) void k_gs_bin_count(const uint64_t* __restrict__ svals,
+                                                      const uint2* __restrict__ srange,
+                                                      const uint32_t* __restrict__ ubase,
+                                                      const uint32_t* __restrict__ nunits_p,
+                                                      int64_t st_total,
+                                                      uint32_t* __restrict__ ucnt) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t nunits = *nunits_p;
+  for (uint32_t u = blockIdx.x * 4u + (threadIdx.x >> 6); u < nunits; u += gridDim.x * 4u) {
+    uint32_t lo, hi;
+    bin_unit(ubase, st_total, srange, u, &lo, &hi);
+    uint32_t r12[kBinUnit / 64];   // every load of the unit in flight first
+#pragma unroll
+    for (int k = 0; k < kBinUnit / 64; ++k) {
+      const uint32_t j = lo + 64 * k + lane;
+      r12[k] = j < hi ? (uint32_t)(svals[j] >> 32) : 0u;
+    }
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kBinUnit / 64; ++k) {
+      if (lo + 64 * k >= hi) break;   // uniform over the wave
+      uint64_t R[kSuper], X[kSuper];
+      bool rp[kSuper], cp[kSuper];
+      bin_masks(r12[k], lo + 64 * k + lane < hi, R, X, rp, cp);
+      cnt += bin_lane_count(R, X, lane);
+    }
+    ucnt[(int64_t)u * 64 + lane] = cnt;
+  }
+}
+
+// One workgroup per super-tile: exclusive prefix of its units' counts per
+// tile (in place) and the tile totals.  Wave w takes a contiguous share of
+// the units, loads kPrefixBatch of them at a time.
+constexpr int kPrefixWaves = 16, kPrefixBatch = 8;
+__global__ __launch_bounds__(64 * kPrefixWaves) void k_gs_bin_prefix(
+    const uint32_t* __restrict__ ubase, int64_t sxn, int64_t spv, int64_t tiles_x,
+    int64_t tiles_y, uint32_t* __restrict__ ucnt, uint32_t* __restrict__ tcnt) {
+  __shared__ uint32_t s_c[kPrefixWaves][64];
+  const int64_t s = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t u0 = ubase[s], nu = ubase[s + 1] - u0;
+  const uint32_t a = u0 + (uint32_t)((uint64_t)nu * wave / kPrefixWaves);
+  const uint32_t b = u0 + (uint32_t)((uint64_t)nu * (wave + 1) / kPrefixWaves);
+  uint32_t sum = 0;
+  for (uint32_t u = a; u < b; u += kPrefixBatch) {
+    uint32_t c[kPrefixBatch];
+#pragma unroll
+    for (int k = 0; k < kPrefixBatch; ++k)
+      c[k] = u + k < b ? ucnt[(int64_t)(u + k) * 64 + lane] : 0u;
+#pragma unroll
+    for (int k = 0; k < kPrefixBatch; ++k) sum += c[k];
+  }
+  s_c[wave][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kPrefixWaves; ++w) {
+    run += w < wave ? s_c[w][lane] : 0u;
+    tot += s_c[w][lane];
+  }
+  for (uint32_t u = a; u < b; u += kPrefixBatch) {
+    uint32_t c[kPrefixBatch];
+#pragma unroll
+    for (int k = 0; k < kPrefixBatch; ++k)
+      c[k] = u + k < b ? ucnt[(int64_t)(u + k) * 64 + lane] : 0u;
+#pragma unroll
+    for (int k = 0; k < kPrefixBatch; ++k) {
+      if (u + k < b) ucnt[(int64_t)(u + k) * 64 + lane] = run;
+      run += c[k];
+    }
+  }
+  int64_t t;
+  if (wave == 0 && bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t)) tcnt[t] = tot;
+}
+
+// Tile ranges and the schedule key (descending in 16 log2(1 + length)):
+// work per tile is very uneven, and starting the long lists first keeps them
+// off the end of the blend.  Past the capacity every list is left empty.
+__global__ __launch_bounds__(256) void k_gs_tile_ranges(const uint32_t* __restrict__ toff,
+                                                        const uint32_t* __restrict__ tcnt,
                                                         const uint32_t* __restrict__ total_p,
                                                         int64_t max_pairs, int64_t tiles_total,
                                                         uint2* __restrict__ ranges,
                                                         uint32_t* __restrict__ okey,
-                                                        uint32_t* __restrict__ oval) {
-  const int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  if (t >= tiles_total) return;   // uniform over the wave
+                                                        uint32_t* __restrict__ oval,
+                                                        int32_t* status) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= tiles_total) return;
+  const bool over = (int64_t)*total_p > max_pairs;
+  if (t == 0 && over) set_status(status, VRS_ECAPACITY);
+  const uint32_t b = over ? 0u : toff[t], e = over ? 0u : b + tcnt[t];
+  ranges[t] = make_uint2(b, e);
+  const float lb = 16.0f * log2f(1.0f + (float)(e - b));
+  okey[t] = 255u - (uint32_t)fminf(lb, 255.0f);
+  oval[t] = (uint32_t)t;
+}
+
+// Per unit: tile l's cursor starts at the tile's list offset plus the counts
+// of the run's earlier units; per round and tile the reaching pairs'
+// Gaussian indices go to cursor + rank.  Nothing is written past the
+// capacity (the lists are then left empty).
+__global__ __launch_bounds__(256) void k_gs_bin_scatter(
+    const uint64_t* __restrict__ svals, const uint2* __restrict__ srange,
+    const uint32_t* __restrict__ ubase, const uint32_t* __restrict__ nunits_p, int64_t st_total,
+    const uint32_t* __restrict__ ucnt, const uint32_t* __restrict__ toff,
+    const uint32_t* __restrict__ total_p, int64_t max_pairs, int64_t sxn, int64_t spv,
+    int64_t tiles_x, int64_t tiles_y, uint32_t* __restrict__ ids) {
   const int lane = threadIdx.x & 63;
-  const uint32_t cntp = (uint32_t)std::min<int64_t>(*total_p, max_pairs);
-  const uint32_t r = halfwave_lower_bound(keys, cntp, (uint32_t)t + (lane >= 32 ? 1u : 0u));
-  const uint32_t begin = __shfl(r, 0, 64), end_raw = __shfl(r, 32, 64);
-  const uint32_t end = end_raw > begin ? end_raw : begin;
-  if (lane == 0) {
-    ranges[t] = make_uint2(begin, end);
-    const float b = 16.0f * log2f(1.0f + (float)(end - begin));
-    okey[t] = 255u - (uint32_t)fminf(b, 255.0f);
-    oval[t] = (uint32_t)t;
+  if ((int64_t)*total_p > max_pairs) return;
+  const uint32_t nunits = *nunits_p;
+  for (uint32_t u = blockIdx.x * 4u + (threadIdx.x >> 6); u < nunits; u += gridDim.x * 4u) {
+    uint32_t lo, hi;
+    const int64_t s = bin_unit(ubase, st_total, srange, u, &lo, &hi);
+    int64_t t;
+    uint32_t cursor = 0;
+    if (bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t))
+      cursor = toff[t] + ucnt[(int64_t)u * 64 + lane];
+    uint64_t cur = lo + lane < hi ? svals[lo + lane] : 0ull;
+    for (uint32_t i = lo; i < hi; i += 64) {
+      const uint32_t jn = i + 64 + lane;
+      const uint64_t nxt = jn < hi ? svals[jn] : 0ull;   // one round ahead
+      const uint32_t gi = (uint32_t)cur;
+      uint64_t R[kSuper], X[kSuper];
+      bool rp[kSuper], cp[kSuper];
+      bin_masks((uint32_t)(cur >> 32), i + lane < hi, R, X, rp, cp);
+#pragma unroll
+      for (int l = 0; l < 64; ++l) {
+        // the lanes reaching tile l are those of M: the rank is a bit count
+        const uint64_t M = R[l >> 3] & X[l & 7];
+        const uint32_t at_l = (uint32_t)__builtin_amdgcn_readlane((int)cursor, l);
+        if (rp[l >> 3] && cp[l & 7])
+          ids[at_l + __builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u))] = gi;
+      }
+      cursor += bin_lane_count(R, X, lane);
+      cur = nxt;
+    }
   }
 }
 
@@ -485,12 +768,13 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
   if (!opts || !out || !render_layout(n, n_views, views, opts->tile, max_pairs, &L))
     return VRS_EINVAL;
   out->pair_count = L.pair_count;
-  out->sorted_ids = L.pairs_in_1 ? L.pval1 : L.pval0;
+  out->sorted_ids = L.ids;
   out->tile_ranges = L.ranges;
   out->tiles_x = L.tiles_x;
   out->tiles_y = L.tiles_y;
   out->tiles_total = L.tiles_total;
   out->pixel_evals = L.evals;
+  out->super_pair_count = L.super_count;
   return VRS_OK;
 }
 
@@ -501,7 +785,7 @@ static void launch_blend(const RenderWs& L, void* ws, int64_t n, const uint32_t*
                          const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
                          int32_t* nc, hipStream_t st) {
   constexpr int SUB = TILE == 32 ? 16 : 8;
-  const uint32_t* ids = at<uint32_t>(ws, L.pairs_in_1 ? L.pval1 : L.pval0);
+  const uint32_t* ids = at<uint32_t>(ws, L.ids);
   hipLaunchKernelGGL((k_gs_blend<TILE, SUB>), dim3((unsigned)L.tiles_total),
                      dim3(BlendCfg<TILE, SUB>::BLOCK), 0, st, order, ids, at<float4>(ws, L.rec), n,
                      kv, o, L.tiles_x, L.tiles_x * L.tiles_y, at<uint2>(ws, L.ranges), rgb, depth,
@@ -530,12 +814,15 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t vn = L.vn;
   uint32_t* pair_count = at<uint32_t>(ws, L.pair_count);
+  uint32_t* super_count = at<uint32_t>(ws, L.super_count);
+  const int64_t nps = div_up(n, 256);
+  bool s1 = false;
   if (vn > 0) {
     trace_begin(VRS_TRACE_GS_PREPROCESS, st);
-    hipLaunchKernelGGL(k_gs_preprocess, dim3(div_up(n, 256)), dim3(256), 0, st, mean, cov,
+    hipLaunchKernelGGL(k_gs_preprocess, dim3((unsigned)nps), dim3(256), 0, st, mean, cov,
                        opacity, sh, sh_degree, n, kv, o, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
-                       at<uint32_t>(ws, L.ntiles));
+                       at<uint32_t>(ws, L.nsup), at<uint64_t>(ws, L.psum));
     VRS_LAUNCH_CHECK();
     trace_end(VRS_TRACE_GS_PREPROCESS, st);
     trace_begin(VRS_TRACE_GS_DEPTH_SORT, st);
@@ -544,35 +831,64 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                                  at<uint32_t>(ws, L.dkey1), at<uint32_t>(ws, L.dval1), nullptr, vn,
                                  32, at<void>(ws, L.sort_tmp), dev_status, st, &d1));
     const uint32_t* sorted_e = at<uint32_t>(ws, d1 ? L.dval1 : L.dval0);
-    VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.ntiles), sorted_e, at<uint32_t>(ws, L.offs),
-                                     pair_count, nullptr, vn, at<void>(ws, L.scan_tmp), dev_status,
-                                     st));
+    VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.nsup), sorted_e, at<uint32_t>(ws, L.soffs),
+                                     super_count, nullptr, vn, at<void>(ws, L.scan_tmp),
+                                     dev_status, st));
     trace_end(VRS_TRACE_GS_DEPTH_SORT, st);
     trace_begin(VRS_TRACE_GS_EMIT, st);
-    {
-      hipLaunchKernelGGL(k_gs_emit, dim3(div_up(vn, kEmitBlock)), dim3(kEmitBlock), 0, st,
-                         at<uint32_t>(ws, L.offs), sorted_e, at<float4>(ws, L.rec), pair_count, vn,
-                         n, max_pairs, o.tile, L.tiles_x, L.tiles_x * L.tiles_y,
-                         at<uint32_t>(ws, L.pkey0), at<uint32_t>(ws, L.pval0), dev_status);
-      VRS_LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL(k_gs_emit_super, dim3(div_up(vn, kEmitBlock)), dim3(kEmitBlock), 0, st,
+                       at<uint32_t>(ws, L.soffs), sorted_e, at<float4>(ws, L.rec), super_count,
+                       vn, n, max_pairs, o.tile, L.sxn, L.spv, at<uint32_t>(ws, L.skey0),
+                       at<uint64_t>(ws, L.sval0), L.st_total, at<uint2>(ws, L.srange),
+                       dev_status);
+    VRS_LAUNCH_CHECK();
     trace_end(VRS_TRACE_GS_EMIT, st);
     trace_begin(VRS_TRACE_GS_SORT, st);
-    bool p1 = false;
-    VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.pkey0), at<uint32_t>(ws, L.pval0),
-                                 at<uint32_t>(ws, L.pkey1), at<uint32_t>(ws, L.pval1), pair_count,
-                                 max_pairs, L.tile_bits, at<void>(ws, L.sort_tmp), dev_status, st,
-                                 &p1));
+    VRS_HIP_CHECK(radix_sort_u64(at<uint32_t>(ws, L.skey0), at<uint64_t>(ws, L.sval0),
+                                 at<uint32_t>(ws, L.skey1), at<uint64_t>(ws, L.sval1), super_count,
+                                 max_pairs, L.st_bits, at<void>(ws, L.sort_tmp), dev_status, st,
+                                 &s1));
   } else {
     trace_begin(VRS_TRACE_GS_SORT, st);
-    VRS_HIP_CHECK(fill_u32(pair_count, 0, 1, st));
+    VRS_HIP_CHECK(fill_u32(super_count, 0, 1, st));
+    VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, L.srange), 0, 2 * L.st_total, st));
   }
-  // tile ranges, then the tiles longest list first (one stable 8-bit pass);
-  // timed with the tile sort (binning), so the blend stage is the blend alone
-  hipLaunchKernelGGL(k_gs_tile_ranges, dim3(div_up(L.tiles_total * 64, 256)), dim3(256), 0, st,
-                     at<uint32_t>(ws, L.pairs_in_1 ? L.pkey1 : L.pkey0), pair_count, max_pairs,
+  // binning: runs, units, per unit and tile counts, tile offsets, ranges,
+  // scatter; then the tiles longest list first (one stable 8-bit pass).
+  // Timed with the sorts, so the blend stage is the blend alone.
+  const uint32_t* skeys = at<uint32_t>(ws, s1 ? L.skey1 : L.skey0);
+  const uint64_t* svals = at<uint64_t>(ws, s1 ? L.sval1 : L.sval0);
+  const int64_t mp = std::max<int64_t>(max_pairs, 1);
+  const unsigned unit_blocks =
+      (unsigned)std::min<int64_t>(2048, div_up(bin_units_max(mp, L.st_total), 4));
+  hipLaunchKernelGGL(k_gs_runs, dim3((unsigned)std::min<int64_t>(4096, div_up(mp, 256))),
+                     dim3(256), 0, st, skeys, super_count, max_pairs, at<uint2>(ws, L.srange));
+  VRS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gs_units, dim3(1), dim3(kUnitsBlock), 0, st, at<uint2>(ws, L.srange),
+                     L.st_total, at<uint64_t>(ws, L.psum), vn > 0 ? nps : 0,
+                     at<uint32_t>(ws, L.ubase), at<uint32_t>(ws, L.nunits), pair_count);
+  VRS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gs_bin_count, dim3(unit_blocks), dim3(256), 0, st, svals,
+                     at<uint2>(ws, L.srange), at<uint32_t>(ws, L.ubase),
+                     at<uint32_t>(ws, L.nunits), L.st_total, at<uint32_t>(ws, L.ucnt));
+  VRS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gs_bin_prefix, dim3((unsigned)L.st_total), dim3(64 * kPrefixWaves), 0, st,
+                     at<uint32_t>(ws, L.ubase), L.sxn, L.spv, L.tiles_x, L.tiles_y,
+                     at<uint32_t>(ws, L.ucnt), at<uint32_t>(ws, L.tcnt));
+  VRS_LAUNCH_CHECK();
+  VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.tcnt), nullptr, at<uint32_t>(ws, L.toff),
+                                   nullptr, nullptr, L.tiles_total, at<void>(ws, L.scan_tmp),
+                                   dev_status, st));
+  hipLaunchKernelGGL(k_gs_tile_ranges, dim3(div_up(L.tiles_total, 256)), dim3(256), 0, st,
+                     at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.tcnt), pair_count, max_pairs,
                      L.tiles_total, at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.okey0),
-                     at<uint32_t>(ws, L.oval0));
+                     at<uint32_t>(ws, L.oval0), dev_status);
+  VRS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gs_bin_scatter, dim3(unit_blocks), dim3(256), 0, st, svals,
+                     at<uint2>(ws, L.srange), at<uint32_t>(ws, L.ubase),
+                     at<uint32_t>(ws, L.nunits), L.st_total, at<uint32_t>(ws, L.ucnt),
+                     at<uint32_t>(ws, L.toff), pair_count, max_pairs, L.sxn, L.spv, L.tiles_x,
+                     L.tiles_y, at<uint32_t>(ws, L.ids));
   VRS_LAUNCH_CHECK();
   bool o1 = false;
   VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.okey0), at<uint32_t>(ws, L.oval0),

@@ -5,19 +5,34 @@
 namespace vrs {
 
 // ---------------------------------------------------------------- layout
+// Tiles are grouped in super-tiles of kSuper x kSuper tiles (one tile per
+// lane of a wave) for binning.
+constexpr int kSuper = 8;
+
 struct RenderWs {
-  size_t rec, dkey0, dval0, dkey1, dval1, ntiles, offs, pair_count, pkey0, pval0, pkey1, pval1,
+  size_t rec, dkey0, dval0, dkey1, dval1, nsup, soffs, psum, pair_count, super_count,
+      skey0, sval0, skey1, sval1,   // (super-tile, Gaussian) pairs
+      srange, ubase, nunits,        // per super-tile run and first work unit
+      ucnt, tcnt, toff,             // per (unit, tile) and per tile counts, tile offsets
+      ids,                          // tile lists (Gaussian indices), tile-id order
       okey0, oval0, okey1, oval1,   // tile schedule (length bucket, tile), sorted once
       ranges, last, evals, g2d, sort_tmp, scan_tmp, total;
-  int64_t vn, tiles_x, tiles_y, tiles_total, npix;
-  int tile_bits;
-  bool pairs_in_1;
+  int64_t vn, tiles_x, tiles_y, tiles_total, npix, sxn, syn, spv, st_total;
+  int st_bits;
+  bool super_in_1;
 };
 
 inline int bits_for(int64_t n) {
   int b = 1;
   while (b < 32 && (int64_t(1) << b) < n) ++b;
   return b;
+}
+
+// Binning work unit: up to kBinUnit consecutive pairs of one super-tile's
+// run (one wave, kBinUnit / 64 rounds of one pair per lane).
+constexpr int kBinUnit = 512;
+inline int64_t bin_units_max(int64_t max_pairs, int64_t st_total) {
+  return (std::max<int64_t>(max_pairs, 1) + kBinUnit - 1) / kBinUnit + st_total;
 }
 
 inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, int64_t max_pairs,
@@ -30,9 +45,12 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->tiles_y = (H + tile - 1) / tile;
   L->tiles_total = L->tiles_x * L->tiles_y * nv;
   L->npix = (int64_t)W * H * nv;
-  L->tile_bits = bits_for(L->tiles_total);
-  const int tile_passes = (L->tile_bits + 7) / 8;
-  L->pairs_in_1 = (tile_passes & 1) != 0;
+  L->sxn = (L->tiles_x + kSuper - 1) / kSuper;
+  L->syn = (L->tiles_y + kSuper - 1) / kSuper;
+  L->spv = L->sxn * L->syn;
+  L->st_total = L->spv * nv;
+  L->st_bits = bits_for(L->st_total);
+  L->super_in_1 = (((L->st_bits + 7) / 8) & 1) != 0;
   const int64_t vn = std::max<int64_t>(L->vn, 1);
   const int64_t mp = std::max<int64_t>(max_pairs, 1);
   Carver c;
@@ -41,13 +59,22 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->dval0 = c.take(vn * 4);
   L->dkey1 = c.take(vn * 4);
   L->dval1 = c.take(vn * 4);
-  L->ntiles = c.take(vn * 4);
-  L->offs = c.take(vn * 4);
+  L->nsup = c.take(vn * 4);
+  L->soffs = c.take(vn * 4);
+  L->psum = c.take((size_t)(vn + 255) / 256 * 8);   // per preprocess block: tile pairs
   L->pair_count = c.take(4);
-  L->pkey0 = c.take(mp * 4);
-  L->pval0 = c.take(mp * 4);
-  L->pkey1 = c.take(mp * 4);
-  L->pval1 = c.take(mp * 4);
+  L->super_count = c.take(4);
+  L->skey0 = c.take(mp * 4);
+  L->sval0 = c.take(mp * 8);
+  L->skey1 = c.take(mp * 4);
+  L->sval1 = c.take(mp * 8);
+  L->srange = c.take((size_t)L->st_total * 8);
+  L->ubase = c.take((size_t)(L->st_total + 1) * 4);
+  L->nunits = c.take(4);
+  L->ucnt = c.take((size_t)bin_units_max(mp, L->st_total) * 64 * 4);
+  L->tcnt = c.take((size_t)L->tiles_total * 4);
+  L->toff = c.take((size_t)L->tiles_total * 4);
+  L->ids = c.take(mp * 4);
   L->ranges = c.take((size_t)L->tiles_total * 8);
   L->okey0 = c.take((size_t)L->tiles_total * 4);
   L->oval0 = c.take((size_t)L->tiles_total * 4);
@@ -56,9 +83,9 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->last = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->evals = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->g2d = c.take((size_t)vn * 10 * 4);   // per (view, Gaussian) screen-space gradients
-  L->sort_tmp = c.take(std::max(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->tile_bits)),
+  L->sort_tmp = c.take(std::max(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->st_bits)),
                                 sort_tmp_bytes(L->tiles_total, 8)));
-  L->scan_tmp = c.take(scan_tmp_bytes(vn));
+  L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(L->tiles_total)));
   L->total = c.off;
   return true;
 }

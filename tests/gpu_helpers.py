@@ -40,6 +40,14 @@ def pair_total(rect, dims, tile):
     return int(((r[:, 2] // tile - r[:, 0] // tile + 1) * (r[:, 3] // tile - r[:, 1] // tile + 1)).sum())
 
 
+def super_pair_total(rect, tile, group=8):
+    """(super-tile, Gaussian) pairs of the binning: super-tiles of group x
+    group tiles reached by each rectangle."""
+    r = rect[rect[..., 0] >= 0]
+    s = tile * group
+    return int(((r[:, 2] // s - r[:, 0] // s + 1) * (r[:, 3] // s - r[:, 1] // s + 1)).sum())
+
+
 def gpu_render(g, cov, op, views, raster, max_pairs):
     opts = api.make_opts(**raster)
     ws = api.RenderWorkspace(g["n"], views, opts, max_pairs)

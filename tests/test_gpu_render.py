@@ -9,7 +9,8 @@ import torch
 import oracle
 from paper_2410_17932_amd import api, synth
 
-from gpu_helpers import baked, check_render, dev, gpu_render, oracle_render, pair_total
+from gpu_helpers import (baked, check_render, dev, gpu_render, oracle_render, pair_total,
+                         super_pair_total)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +25,7 @@ def _lists_equal(ws, rect, zb, views, tile):
         b, e = ranges[s]
         assert np.array_equal(ids[b:e], oids[off[s]:off[s + 1]]), f"tile list {s} differs"
     assert ws.pair_count() == off[-1]
+    assert ws.super_pair_count() == super_pair_total(rect, tile)
 
 
 @pytest.mark.parametrize("case", ["tiny", "ragged_stereo", "sh3"])
