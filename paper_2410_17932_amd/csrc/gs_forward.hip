@@ -653,22 +653,30 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
       uint64_t m = wave_uniform_u64(s_mask[wave][g]);
       const uint64_t mfull = wave_uniform_u64(s_full[wave][g]);
       while (m) {
+        // records out of reach of the ellipse before the next one that may
+        // contribute: no pixel can pass alpha_min, so only the evaluation
+        // count of in-rectangle live pixels moves (liveness changes only at
+        // contributing records, so these are counted in a loop of their own
+        // and the blend state flows through the outer loop alone)
+        const uint64_t mf = m & mfull;
+        uint64_t cheap = mf ? (m & ((mf & (~mf + 1ull)) - 1ull)) : m;
+        m &= ~cheap;
+        while (cheap) {
+          const int kc = g * 64 + __builtin_ctzll(cheap);
+          cheap &= cheap - 1;
+          const float4 bc = s_b[kc];
+          const uint32_t clo = __float_as_uint(bc.z), chi = __float_as_uint(bc.w);
+          const int cx0 = (int)(clo & 0xffffu), cy0 = (int)(clo >> 16);
+          const bool cin = (uint32_t)(px - cx0) <= (uint32_t)((int)(chi & 0xffffu) - cx0);
+          const uint32_t cspan = (uint32_t)((int)(chi >> 16) - cy0);
+#pragma unroll
+          for (int q = 0; q < PPT; ++q)
+            evals[q] += (cin & ((uint32_t)(ry[q] - cy0) <= cspan)) ? 1u : 0u;
+        }
+        if (!m) break;
         const int bit = __builtin_ctzll(m);
         const int k = g * 64 + bit;
         m &= m - 1;
-        if (((mfull >> bit) & 1ull) == 0) {
-          // out of reach of the ellipse: no pixel here can pass alpha_min, so
-          // only the evaluation count of in-rectangle live pixels moves
-          const float4 b = s_b[k];
-          const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
-          const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
-          const bool inx = (uint32_t)(px - rx0) <= (uint32_t)((int)(hi & 0xffffu) - rx0);
-          const uint32_t ry_span = (uint32_t)((int)(hi >> 16) - ry0);
-#pragma unroll
-          for (int q = 0; q < PPT; ++q)
-            evals[q] += (inx & ((uint32_t)(ry[q] - ry0) <= ry_span)) ? 1u : 0u;
-          continue;
-        }
         const float4 a = s_a[k], b = s_b[k], c = s_c[k];
         const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
         const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
@@ -684,23 +692,26 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
         all_ry = kStopped;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
+#pragma clang fp contract(off)   // T - w0 rounded once, the same in test and update
           const float dy = a.y - yc[q];
           const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
           const float e = __builtin_amdgcn_exp2f(qq);
-          const float al0 = b.y * e;
-          const float al = al0 < aclamp ? al0 : aclamp;
+          const float al = fminf(b.y * e, aclamp);
           const bool inr = inx & ((uint32_t)(ry[q] - ry0) <= ry_span);
-          const float Tn = fmaf(-T[q], al, T[q]);
+          // w0 = alpha T is the contribution's weight and T - w0 the new
+          // transmittance: every state update below is then in place
+          const float w0 = al * T[q];
+          const float Tn = T[q] - w0;
           const bool ok0 = inr & !(qq > 0.0f) & (al >= amin);
           const bool stop = ok0 & (Tn < tmin);
           const bool ok = ok0 & !stop;
           ry[q] = stop ? kStopped : ry[q];
-          const float wgt = ok ? al * T[q] : 0.0f;
+          const float wgt = ok ? w0 : 0.0f;
           C0[q] = fmaf(c.x, wgt, C0[q]);
           C1[q] = fmaf(c.y, wgt, C1[q]);
           C2[q] = fmaf(c.z, wgt, C2[q]);
           D[q] = fmaf(c.w, wgt, D[q]);
-          T[q] = ok ? Tn : T[q];
+          T[q] -= wgt;
           cnt[q] += ok ? 1 : 0;
           last[q] = ok ? pos : last[q];
           evals[q] += inr ? 1u : 0u;
