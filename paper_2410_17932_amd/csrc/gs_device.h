@@ -172,18 +172,20 @@ __device__ inline float gs_exponent(const float4& a, const float4& b, float dx, 
   return fmaf(dy, fmaf(b.x, dy, R), P);
 }
 
-// Opacity at a pixel centre, negative where the exponent is positive (no
-// contribution for any alpha_min >= 0).  The forward blend evaluates the same
-// operations inline and the backward calls this, so both take the same
-// threshold decisions; e = 2^q is returned for the adjoint.
+// Opacity at a pixel centre.  The conic is positive definite (the dilated
+// covariance has a positive determinant), so the exponent is never positive
+// but for rounding within a few units of the last place of zero, at the
+// centre, where the opacity is the Gaussian's own either way: no guard on its
+// sign is taken.  The forward blend evaluates the same operations inline and
+// the backward calls this, so both take the same threshold decisions; e = 2^q
+// is returned for the adjoint.
 __device__ inline float gs_alpha(const float4& a, const float4& b, float xc, float yc,
                                  float aclamp, float& dx, float& dy, float& e) {
   dx = a.x - xc;
   dy = a.y - yc;
   const float q = gs_exponent(a, b, dx, dy);
   e = __builtin_amdgcn_exp2f(q);
-  const float al = fminf(aclamp, b.y * e);
-  return q > 0.0f ? -1.0f : al;
+  return fminf(b.y * e, aclamp);
 }
 
 // Packed rectangle: low 16 bits x, high 16 bits y.

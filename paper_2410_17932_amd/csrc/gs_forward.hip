@@ -563,6 +563,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK];
   __shared__ uint64_t s_mask[NW][NW];   // [sub-tile][group of 64 records]: rectangle reaches it
   __shared__ uint64_t s_full[NW][NW];   // ... and the contributing ellipse may too
+  __shared__ uint64_t s_cover[NW][NW];  // ... and the rectangle holds its in-image pixels
   const int64_t tglob = order[blockIdx.x];
   const int v = (int)(tglob / tiles_per_view);
   const int64_t tl = tglob - (int64_t)v * tiles_per_view;
@@ -601,6 +602,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
 #pragma unroll
   for (int q = 0; q < PPT; ++q) all_ry &= ry[q];
   bool alive = __ballot(all_ry != kStopped) != 0;   // wave-uniform
+  uint32_t pending = 0;   // out-of-reach records holding the sub-tile, not yet counted
   for (uint32_t b0 = begin; b0 < end; b0 += BLOCK) {
     if (__syncthreads_count(alive) == 0) break;
     const uint32_t jr = b0 + tid;
@@ -633,6 +635,8 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
       const int xlo = max(x0, qx0), xhi = min(x1, qx0 + SUB - 1);
       const int ylo = max(y0, qy0), yhi = min(y1, qy0 + SUB - 1);
       const bool hit = has && xlo <= xhi && ylo <= yhi;
+      const bool cover = hit && x0 <= qx0 && x1 >= min(qx0 + SUB - 1, W - 1) && y0 <= qy0 &&
+                         y1 >= min(qy0 + SUB - 1, H - 1);
       bool full = false;
       if (hit) {
         // d = centre - pixel centre over the pixel centres of the overlap
@@ -641,10 +645,11 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
                                           cy - ((float)ylo + 0.5f));
         full = !(g > thr);
       }
-      const uint64_t m = __ballot(hit), mf = __ballot(full);
+      const uint64_t m = __ballot(hit), mf = __ballot(full), mc = __ballot(cover);
       if (lane == 0) {
         s_mask[w][wave] = m;
         s_full[w][wave] = mf;
+        s_cover[w][wave] = mc;
       }
     }
     __syncthreads();
@@ -652,18 +657,23 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
     for (int g = 0; g < NW && alive; ++g) {
       uint64_t m = wave_uniform_u64(s_mask[wave][g]);
       const uint64_t mfull = wave_uniform_u64(s_full[wave][g]);
+      const uint64_t mcov = wave_uniform_u64(s_cover[wave][g]);
       while (m) {
-        // records out of reach of the ellipse before the next one that may
+        // Records out of reach of the ellipse before the next one that may
         // contribute: no pixel can pass alpha_min, so only the evaluation
-        // count of in-rectangle live pixels moves (liveness changes only at
-        // contributing records, so these are counted in a loop of their own
-        // and the blend state flows through the outer loop alone)
+        // count of in-rectangle live pixels moves.  Liveness changes only at
+        // contributing records, so those whose rectangle holds the whole
+        // sub-tile are only counted (added to every live pixel before the
+        // next record that may contribute), the others tested per pixel, in
+        // a loop of their own: the blend state flows through this loop alone.
         const uint64_t mf = m & mfull;
-        uint64_t cheap = mf ? (m & ((mf & (~mf + 1ull)) - 1ull)) : m;
+        const uint64_t cheap = mf ? (m & ((mf & (~mf + 1ull)) - 1ull)) : m;
         m &= ~cheap;
-        while (cheap) {
-          const int kc = g * 64 + __builtin_ctzll(cheap);
-          cheap &= cheap - 1;
+        pending += (uint32_t)__popcll(cheap & mcov);
+        uint64_t cpart = cheap & ~mcov;
+        while (cpart) {
+          const int kc = g * 64 + __builtin_ctzll(cpart);
+          cpart &= cpart - 1;
           const float4 bc = s_b[kc];
           const uint32_t clo = __float_as_uint(bc.z), chi = __float_as_uint(bc.w);
           const int cx0 = (int)(clo & 0xffffu), cy0 = (int)(clo >> 16);
@@ -674,48 +684,61 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
             evals[q] += (cin & ((uint32_t)(ry[q] - cy0) <= cspan)) ? 1u : 0u;
         }
         if (!m) break;
+        if (pending) {   // uniform over the wave
+#pragma unroll
+          for (int q = 0; q < PPT; ++q) evals[q] += ry[q] != kStopped ? pending : 0u;
+          pending = 0;
+        }
         const int bit = __builtin_ctzll(m);
         const int k = g * 64 + bit;
         m &= m - 1;
         const float4 a = s_a[k], b = s_b[k], c = s_c[k];
-        const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
-        const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
-        const int rx1 = (int)(hi & 0xffffu), ry1 = (int)(hi >> 16);
-        // rectangle tests as unsigned range checks, combined with bitwise
-        // operators so that nothing branches
-        const bool inx = (uint32_t)(px - rx0) <= (uint32_t)(rx1 - rx0);
-        const uint32_t ry_span = (uint32_t)(ry1 - ry0);
         const uint32_t pos = b0 + (uint32_t)k + 1u - begin;
         const float dx = a.x - xc;
         // the exponent's per-column part (same operations as gs_exponent)
         const float P = (a.z * dx) * dx, R = a.w * dx;
-        all_ry = kStopped;
+        // One record over the lane's pixels.  in_rect(q): the pixel is live
+        // and inside the record's rectangle (tested as unsigned range checks,
+        // combined with bitwise operators so that nothing branches; where the
+        // rectangle holds the sub-tile, liveness alone).
+        auto blend_record = [&](auto in_rect) {
+          all_ry = kStopped;
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) {
+          for (int q = 0; q < PPT; ++q) {
 #pragma clang fp contract(off)   // T - w0 rounded once, the same in test and update
-          const float dy = a.y - yc[q];
-          const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
-          const float e = __builtin_amdgcn_exp2f(qq);
-          const float al = fminf(b.y * e, aclamp);
-          const bool inr = inx & ((uint32_t)(ry[q] - ry0) <= ry_span);
-          // w0 = alpha T is the contribution's weight and T - w0 the new
-          // transmittance: every state update below is then in place
-          const float w0 = al * T[q];
-          const float Tn = T[q] - w0;
-          const bool ok0 = inr & !(qq > 0.0f) & (al >= amin);
-          const bool stop = ok0 & (Tn < tmin);
-          const bool ok = ok0 & !stop;
-          ry[q] = stop ? kStopped : ry[q];
-          const float wgt = ok ? w0 : 0.0f;
-          C0[q] = fmaf(c.x, wgt, C0[q]);
-          C1[q] = fmaf(c.y, wgt, C1[q]);
-          C2[q] = fmaf(c.z, wgt, C2[q]);
-          D[q] = fmaf(c.w, wgt, D[q]);
-          T[q] -= wgt;
-          cnt[q] += ok ? 1 : 0;
-          last[q] = ok ? pos : last[q];
-          evals[q] += inr ? 1u : 0u;
-          all_ry &= ry[q];
+            const float dy = a.y - yc[q];
+            const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
+            const float e = __builtin_amdgcn_exp2f(qq);
+            const float al = fminf(b.y * e, aclamp);
+            const bool inr = in_rect(q);
+            // w0 = alpha T is the contribution's weight and T - w0 the new
+            // transmittance: every state update below is then in place
+            const float w0 = al * T[q];
+            const float Tn = T[q] - w0;
+            const bool ok0 = inr & (al >= amin);
+            const bool stop = ok0 & (Tn < tmin);
+            const bool ok = ok0 & !stop;
+            ry[q] = stop ? kStopped : ry[q];
+            const float wgt = ok ? w0 : 0.0f;
+            C0[q] = fmaf(c.x, wgt, C0[q]);
+            C1[q] = fmaf(c.y, wgt, C1[q]);
+            C2[q] = fmaf(c.z, wgt, C2[q]);
+            D[q] = fmaf(c.w, wgt, D[q]);
+            T[q] -= wgt;
+            cnt[q] += ok ? 1 : 0;
+            last[q] = ok ? pos : last[q];
+            evals[q] += inr ? 1u : 0u;
+            all_ry &= ry[q];
+          }
+        };
+        if ((mcov >> bit) & 1ull) {
+          blend_record([&](int q) { return ry[q] != kStopped; });
+        } else {
+          const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
+          const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
+          const bool inx = (uint32_t)(px - rx0) <= (uint32_t)((int)(hi & 0xffffu) - rx0);
+          const uint32_t ry_span = (uint32_t)((int)(hi >> 16) - ry0);
+          blend_record([&](int q) { return inx & ((uint32_t)(ry[q] - ry0) <= ry_span); });
         }
         if (__ballot(all_ry != kStopped) == 0) {
           alive = false;
@@ -724,6 +747,9 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
       }
     }
   }
+  // records counted but not yet added: every pixel still live saw them
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) evals[q] += ry[q] != kStopped ? pending : 0u;
   const int64_t plane = (int64_t)W * H;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
