@@ -127,15 +127,18 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
 // waiting anywhere; deterministic.
 constexpr int kSortBlock = 256, kSortWaves = kSortBlock / 64, kSortItems = 15;
 constexpr int kWaveChunk = 64 * kSortItems, kSortTile = kSortBlock * kSortItems;  // 3840
+constexpr int64_t kSortGrid = 1024;
 
 __device__ inline int64_t sort_n(const uint32_t* n_dev, int64_t n_max) {
   return n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
 }
 
-// Upsweep: digit counts of partition blockIdx.x, stored digit-major
-// (counts[d * parts + p]).  Keys often come in runs (pairs of one Gaussian,
-// pixels of one point): where all active lanes hold the same digit the wave
-// adds once.
+// Upsweep: digit counts of a partition, stored digit-major (counts[d * parts
+// + p]).  Keys often come in runs (pairs of one Gaussian, pixels of one
+// point): where all active lanes hold the same digit the wave adds once.
+// Workgroups take partitions in grid-stride order: the grid is sized for at
+// most kSortGrid workgroups whatever the capacity, the count is read on the
+// device.
 __global__ __launch_bounds__(kSortBlock) void k_sort_count(const uint32_t* __restrict__ keys,
                                                             const uint32_t* n_dev, int64_t n_max,
                                                             int shift, int64_t parts,
@@ -143,33 +146,35 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(const uint32_t* __res
   __shared__ uint32_t s_h[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = sort_n(n_dev, n_max);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  if (base >= n) return;
-  s_h[tid] = 0;
-  __syncthreads();
-  const int64_t wbase = base + (int64_t)wave * kWaveChunk;
-  uint32_t kv[kSortItems];   // every load in flight before the first atomic
+  for (int64_t part = blockIdx.x; part * kSortTile < n; part += gridDim.x) {
+    const int64_t base = part * kSortTile;
+    s_h[tid] = 0;
+    __syncthreads();
+    const int64_t wbase = base + (int64_t)wave * kWaveChunk;
+    uint32_t kv[kSortItems];   // every load in flight before the first atomic
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int64_t i = wbase + j * 64 + lane;
-    kv[j] = i < n ? keys[i] : 0u;
-  }
+    for (int j = 0; j < kSortItems; ++j) {
+      const int64_t i = wbase + j * 64 + lane;
+      kv[j] = i < n ? keys[i] : 0u;
+    }
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int64_t i = wbase + j * 64 + lane;
-    if (i < n) {
-      const uint32_t d = (kv[j] >> shift) & 255u;
-      const uint64_t act = __ballot(true);
-      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-      if (__ballot(d != d0) == 0) {
-        if (count_below(act) == 0) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
-      } else {
-        atomicAdd(&s_h[d], 1u);
+    for (int j = 0; j < kSortItems; ++j) {
+      const int64_t i = wbase + j * 64 + lane;
+      if (i < n) {
+        const uint32_t d = (kv[j] >> shift) & 255u;
+        const uint64_t act = __ballot(true);
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        if (__ballot(d != d0) == 0) {
+          if (count_below(act) == 0) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
+        } else {
+          atomicAdd(&s_h[d], 1u);
+        }
       }
     }
+    __syncthreads();
+    counts[(int64_t)tid * parts + part] = s_h[tid];
+    __syncthreads();   // s_h is cleared for the next partition
   }
-  __syncthreads();
-  counts[(int64_t)tid * parts + blockIdx.x] = s_h[tid];
 }
 
 // One workgroup per digit: exclusive scan of the digit's counts over the
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* counts, const uint3
   if (tid == 0) totals[blockIdx.x] = carry;
 }
 
-// Downsweep of partition blockIdx.x: stable rank of every item among the
+// Downsweep of a partition (grid-stride order, as the upsweep): stable rank of every item among the
 // partition's items of the same digit (wave ballots, then waves in order),
 // items regrouped by digit in LDS, then written to
 //   base(digit) + count of the digit in earlier partitions + local rank,
@@ -229,88 +234,89 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
   __shared__ V s_vals[kSortTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = sort_n(n_dev, n_max);
-  const int64_t part = blockIdx.x;
-  const int64_t base = part * kSortTile;
-  if (base >= n) return;
+  for (int64_t part = blockIdx.x; part * kSortTile < n; part += gridDim.x) {
+    const int64_t base = part * kSortTile;
 #pragma unroll
-  for (int w = 0; w < kSortWaves; ++w) s_wh[w][tid] = 0;
-  __syncthreads();
-  // load: wave w owns [base + w*960, +960); item j of lane l at j*64 + l
-  uint32_t key[kSortItems];
-  V val[kSortItems];
-  uint32_t rank[kSortItems];
-  const int64_t wbase = base + (int64_t)wave * kWaveChunk;
+    for (int w = 0; w < kSortWaves; ++w) s_wh[w][tid] = 0;
+    __syncthreads();
+    // load: wave w owns [base + w*960, +960); item j of lane l at j*64 + l
+    uint32_t key[kSortItems];
+    V val[kSortItems];
+    uint32_t rank[kSortItems];
+    const int64_t wbase = base + (int64_t)wave * kWaveChunk;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int64_t i = wbase + j * 64 + lane;
-    const bool ok = i < n;
-    key[j] = ok ? kin[i] : 0xffffffffu;
-    val[j] = ok ? vin[i] : V(0);
-  }
-  // stable rank within the wave: match lanes with equal digit by ballots
-  volatile uint32_t* wh = s_wh[wave];
-#pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const bool ok = wbase + j * 64 + lane < n;
-    const uint32_t d = (key[j] >> shift) & 255u;
-    uint64_t m = __ballot(ok);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
+    for (int j = 0; j < kSortItems; ++j) {
+      const int64_t i = wbase + j * 64 + lane;
+      const bool ok = i < n;
+      key[j] = ok ? kin[i] : 0xffffffffu;
+      val[j] = ok ? vin[i] : V(0);
     }
-    const uint32_t below = count_below(m);
-    const uint32_t prev = wh[d];
-    rank[j] = prev + below;
-    __builtin_amdgcn_wave_barrier();
-    if (ok && below == 0) wh[d] = prev + (uint32_t)__popcll(m);
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  // per digit d = tid: exclusive prefix over waves and the partition's count
-  const uint32_t d = tid;
-  uint32_t cnt = 0;
+    // stable rank within the wave: match lanes with equal digit by ballots
+    volatile uint32_t* wh = s_wh[wave];
 #pragma unroll
-  for (int w = 0; w < kSortWaves; ++w) {
-    const uint32_t c = s_wh[w][d];
-    s_wh[w][d] = cnt;
-    cnt += c;
-  }
-  // local start of each digit (block scan of cnt) and its global base (block
-  // scan of the digit totals)
-  const uint32_t h = totals[d];
-  const uint32_t incl = wave_incl_scan(cnt), hincl = wave_incl_scan(h);
-  if (lane == 63) s_scan[wave] = incl;
-  __syncthreads();
-  uint32_t woff = 0;
-  for (int w = 0; w < wave; ++w) woff += s_scan[w];
-  s_lstart[d] = woff + incl - cnt;
-  __syncthreads();
-  if (lane == 63) s_scan[wave] = hincl;
-  __syncthreads();
-  uint32_t hoff = 0;
-  for (int w = 0; w < wave; ++w) hoff += s_scan[w];
-  s_gstart[d] = hoff + hincl - h + counts[(int64_t)d * parts + part];
-  __syncthreads();
-  // regroup by digit in LDS, then coalesced runs to the output
+    for (int j = 0; j < kSortItems; ++j) {
+      const bool ok = wbase + j * 64 + lane < n;
+      const uint32_t d = (key[j] >> shift) & 255u;
+      uint64_t m = __ballot(ok);
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    if (wbase + j * 64 + lane < n) {
-      const uint32_t dj = (key[j] >> shift) & 255u;
-      const uint32_t lpos = s_lstart[dj] + s_wh[wave][dj] + rank[j];
-      s_keys[lpos] = key[j];
-      s_vals[lpos] = val[j];
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+      }
+      const uint32_t below = count_below(m);
+      const uint32_t prev = wh[d];
+      rank[j] = prev + below;
+      __builtin_amdgcn_wave_barrier();
+      if (ok && below == 0) wh[d] = prev + (uint32_t)__popcll(m);
+      __builtin_amdgcn_wave_barrier();
     }
-  }
-  __syncthreads();
-  const int cnt_tile = (int)min((int64_t)kSortTile, n - base);
-  for (int i = tid; i < cnt_tile; i += kSortBlock) {
-    const uint32_t k = s_keys[i];
-    const uint32_t dk = (k >> shift) & 255u;
-    const uint32_t g = s_gstart[dk] + (uint32_t)i - s_lstart[dk];
-    kout[g] = k;
-    vout[g] = s_vals[i];
+    __syncthreads();
+    // per digit d = tid: exclusive prefix over waves and the partition's count
+    const uint32_t d = tid;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      const uint32_t c = s_wh[w][d];
+      s_wh[w][d] = cnt;
+      cnt += c;
+    }
+    // local start of each digit (block scan of cnt) and its global base (block
+    // scan of the digit totals)
+    const uint32_t h = totals[d];
+    const uint32_t incl = wave_incl_scan(cnt), hincl = wave_incl_scan(h);
+    if (lane == 63) s_scan[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0;
+    for (int w = 0; w < wave; ++w) woff += s_scan[w];
+    s_lstart[d] = woff + incl - cnt;
+    __syncthreads();
+    if (lane == 63) s_scan[wave] = hincl;
+    __syncthreads();
+    uint32_t hoff = 0;
+    for (int w = 0; w < wave; ++w) hoff += s_scan[w];
+    s_gstart[d] = hoff + hincl - h + counts[(int64_t)d * parts + part];
+    __syncthreads();
+    // regroup by digit in LDS, then coalesced runs to the output
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      if (wbase + j * 64 + lane < n) {
+        const uint32_t dj = (key[j] >> shift) & 255u;
+        const uint32_t lpos = s_lstart[dj] + s_wh[wave][dj] + rank[j];
+        s_keys[lpos] = key[j];
+        s_vals[lpos] = val[j];
+      }
+    }
+    __syncthreads();
+    const int cnt_tile = (int)min((int64_t)kSortTile, n - base);
+    for (int i = tid; i < cnt_tile; i += kSortBlock) {
+      const uint32_t k = s_keys[i];
+      const uint32_t dk = (k >> shift) & 255u;
+      const uint32_t g = s_gstart[dk] + (uint32_t)i - s_lstart[dk];
+      kout[g] = k;
+      vout[g] = s_vals[i];
+    }
+    __syncthreads();   // LDS is rewritten by the next partition
   }
 }
 
@@ -323,16 +329,17 @@ hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint3
   *result_in_1 = (passes & 1) != 0;
   if (passes == 0 || n_max == 0) return hipSuccess;
   const int64_t parts = (n_max + kSortTile - 1) / kSortTile;
+  const unsigned grid = (unsigned)std::min<int64_t>(parts, kSortGrid);
   uint32_t* totals = static_cast<uint32_t*>(tmp);
   uint32_t* counts = totals + 256;
   uint32_t* kb[2] = {k0, k1};
   V* vb[2] = {v0, v1};
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_sort_count, dim3((unsigned)parts), dim3(kSortBlock), 0, st, kb[p & 1],
+    hipLaunchKernelGGL(k_sort_count, dim3(grid), dim3(kSortBlock), 0, st, kb[p & 1],
                        n_dev, n_max, 8 * p, parts, counts);
     hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, st, counts, n_dev, n_max, parts,
                        totals);
-    hipLaunchKernelGGL(k_sort_scatter<V>, dim3((unsigned)parts), dim3(kSortBlock), 0, st,
+    hipLaunchKernelGGL(k_sort_scatter<V>, dim3(grid), dim3(kSortBlock), 0, st,
                        kb[p & 1], vb[p & 1], kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, n_max,
                        8 * p, parts, counts, totals);
   }
