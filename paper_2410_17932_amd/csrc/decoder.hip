@@ -18,6 +18,8 @@
 // Arithmetic: float operands with v_mfma_f32_16x16x4_f32 (VRS_F32), or
 // bfloat16 operands with v_mfma_f32_16x16x32_bf16 and float accumulation
 // (VRS_BF16); biases, activations and the RGB head in float.
+#include <type_traits>
+
 #include "vrs_common.h"
 
 namespace vrs {
@@ -150,17 +152,6 @@ struct HeadFuse {
   long long out_base[VRS_MAX_CROPS];
 };
 
-// 16-byte copies of 8 channels (one uint4 for bfloat16, two for float)
-template <typename T>
-__device__ inline void copy8(T* dst, const T* src) {
-  if constexpr (sizeof(T) == 2) {
-    *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
-  } else {
-    reinterpret_cast<uint4*>(dst)[0] = reinterpret_cast<const uint4*>(src)[0];
-    reinterpret_cast<uint4*>(dst)[1] = reinterpret_cast<const uint4*>(src)[1];
-  }
-}
-
 // Geometry of one workgroup's LDS: halo tile, the coarser level's footprint
 // and the weights.  ONE: the whole weight operand (up to 24 KB) is loaded
 // once, at the start, overlapping the halo fill; otherwise two 8 KB chunks
@@ -182,19 +173,30 @@ struct ConvCfg {
   static constexpr int PPT = (PIECES + 255) / 256;
 };
 
-// The weight chunks reuse the coarse footprint's LDS once the halo tile is
-// filled.
+// The weight chunks reuse the coarse footprint's LDS (float) once the halo
+// tile is filled; the per-k-step A offsets (int [k-steps][4]) follow.
 template <typename T, int NT, bool ONE>
-__host__ __device__ inline size_t conv_smem_bytes(int cin8, int kn) {
+__host__ __device__ inline int conv_region_bytes(int kn) {
   using Cfg = ConvCfg<T, NT, ONE>;
-  const size_t kn8 = (size_t)((kn + 7) & ~7);
-  const size_t coarse = (size_t)Cfg::CR * Cfg::CC * kn8;
-  const size_t wchunks = (size_t)Cfg::NBUF * Cfg::NOUT * Cfg::BROW;
-  return ((size_t)Cfg::NPIX * cin8 + (coarse > wchunks ? coarse : wchunks)) * sizeof(T);
+  const int kn8 = (kn + 7) & ~7;
+  const int coarse = Cfg::CR * Cfg::CC * kn8 * (int)sizeof(float);
+  const int wchunks = Cfg::NBUF * Cfg::NOUT * Cfg::BROW * (int)sizeof(T);
+  return coarse > wchunks ? coarse : wchunks;
+}
+template <typename T, int NT, bool ONE>
+__host__ __device__ inline size_t conv_smem_bytes(int cin8, int kn, int kpad) {
+  using Cfg = ConvCfg<T, NT, ONE>;
+  return (size_t)Cfg::NPIX * cin8 * sizeof(T) + conv_region_bytes<T, NT, ONE>(kn) +
+         (size_t)(kpad / Cfg::KSTEP) * 4 * sizeof(int);
 }
 
+// Register budget per N-tile count: the occupancy the accumulators allow
+// (4, 3, 2, 1 waves per SIMD for 2, 4, 6, 8 N-tiles).
+template <int NT>
+constexpr int conv_waves() { return NT <= 2 ? 4 : (NT <= 4 ? 3 : (NT <= 6 ? 2 : 1)); }
 template <typename T, int NT, bool ONE>
-__global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv_waves<NT>())))
+void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
                                                   const float* __restrict__ periph,
                                                   const T* __restrict__ hnext,
                                                   const T* __restrict__ wp,
@@ -208,8 +210,10 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
   extern __shared__ __align__(16) char smem[];
   const int cin8 = d.cin8, kn8 = (d.kn + 7) & ~7;
   T* tile = reinterpret_cast<T*>(smem);
-  T* ctile = tile + NPIX * cin8;
-  T* sB = ctile;   // after the fill
+  char* region = smem + (size_t)NPIX * cin8 * sizeof(T);
+  float* ctile = reinterpret_cast<float*>(region);
+  T* sB = reinterpret_cast<T*>(region);   // after the fill
+  int* s_aoff = reinterpret_cast<int*>(region + conv_region_bytes<T, NT, ONE>(d.kn));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int k = 0;
   while (k + 1 < d.n_crops && (int)blockIdx.x >= d.tile_base[k + 1]) ++k;
@@ -248,6 +252,7 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
   const int Sn = S >> 1;
   const int cy0 = (oy >> 1) - 1, cx0 = (ox >> 1) - 1;
   if (d.kn > 0) {
+    // converted to float once here: each value then feeds four 2x2 blocks
     const int kg = kn8 >> 3;
     for (int e = tid; e < CR * CC * kg; e += 256) {
       const int cp = e / kg, g = e - cp * kg;
@@ -255,9 +260,27 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
       int yy = cy0 + cyi, xx = cx0 + cxi;
       yy = yy < 0 ? 0 : (yy > Sn - 1 ? Sn - 1 : yy);
       xx = xx < 0 ? 0 : (xx > Sn - 1 ? Sn - 1 : xx);
-      copy8<T>(&ctile[cp * kn8 + g * 8], hnext + d.hn_off[k] + ((long long)yy * Sn + xx) * d.kpn + g * 8);
+      float v[8];
+      load8<T>(hnext + d.hn_off[k] + ((long long)yy * Sn + xx) * d.kpn + g * 8, v);
+      store8<float>(&ctile[cp * kn8 + g * 8], v);
     }
     __syncthreads();
+  }
+  // A-operand offset of each k-step and lane group kq: k = 32 s + 8 kq (BF16,
+  // one 8-channel unit) or 4 s + kq (FP32, one channel) is tap * cin8 +
+  // channel.  Steps past the 9 taps read tap 8 (their weights are zero).
+  {
+    const int units = sizeof(T) == 2 ? (cin8 >> 3) : cin8;
+    for (int i = tid; i < nsteps * 4; i += 256) {
+      const int u = i;   // unit index along K: 4 per k-step
+      int tap = u / units, cu = u - tap * units;
+      if (tap > 8) {
+        tap = 8;
+        cu = 0;
+      }
+      const int ty = tap / 3, tx = tap - 3 * ty;
+      s_aoff[i] = (ty * 18 + tx) * cin8 + cu * (sizeof(T) == 2 ? 8 : 1);
+    }
   }
   // ---- halo tile fill.  Upsampled channels: one work item per 2x2 block of
   // fine pixels and 8-channel group -- fine rows 2m+1, 2m+2 (and columns
@@ -271,16 +294,30 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
   const bool fast_py = d.C == 4 && (d.kn & 7) == 0 && (reinterpret_cast<uintptr_t>(pyr) & 15) == 0;
   const long long plane = (long long)d.W * d.H;
   const int n_up = NB * kgf, n_items = n_up + NPIX * (G - kgf);
+  // every halo pixel inside the layer: no zero selects
+  const bool interior = oy >= 1 && ox >= 1 && oy + TH + 1 <= S && ox + 17 <= S;
+  // upsampled item e = block * kgf + group (groups fastest, so that a wave's
+  // coarse reads and tile writes are runs of consecutive 32- and 16-byte
+  // pieces), advanced by 256 items per round without divisions
+  const int kgf_s = kgf > 0 ? kgf : 1;
+  const int up_sb = 256 / kgf_s, up_sg = 256 - up_sb * kgf_s;
+  int up_blk = tid / kgf_s, up_g = tid - up_blk * kgf_s;
   for (int e = tid; e < n_items; e += 256) {
+    const int blk = up_blk, g = up_g;
+    up_blk += up_sb;
+    up_g += up_sg;
+    if (up_g >= kgf_s) {
+      up_g -= kgf_s;
+      ++up_blk;
+    }
     if (e < n_up) {
-      const int g = e / NB, blk = e - g * NB;
       const int bi = blk / 9, bj = blk - bi * 9;
-      const T* c00 = &ctile[(bi * CC + bj) * kn8 + g * 8];
+      const float* c00 = &ctile[(bi * CC + bj) * kn8 + g * 8];
       float a00[8], a01[8], a10[8], a11[8];
-      load8<T>(c00, a00);
-      load8<T>(c00 + kn8, a01);
-      load8<T>(c00 + CC * kn8, a10);
-      load8<T>(c00 + (CC + 1) * kn8, a11);
+      load8<float>(c00, a00);
+      load8<float>(c00 + kn8, a01);
+      load8<float>(c00 + CC * kn8, a10);
+      load8<float>(c00 + (CC + 1) * kn8, a11);
       // horizontal: left fine column (3/4 a_0 + 1/4 a_1), right (1/4, 3/4)
       float tl[8], tr[8], bl[8], br[8];
 #pragma unroll
@@ -290,21 +327,27 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
         bl[j] = fmaf(0.25f, a11[j], 0.75f * a10[j]);
         br[j] = fmaf(0.75f, a11[j], 0.25f * a10[j]);
       }
+      auto put = [&](auto inside_tag) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int dy = q >> 1, dx = q & 1;
-        const int hy = 2 * bi + dy, hx = 2 * bj + dx;
-        const int y = oy + hy - 1, x = ox + hx - 1;
-        float v[8];
-        const bool in = y >= 0 && y < S && x >= 0 && x < S;
+        for (int q = 0; q < 4; ++q) {
+          const int dy = q >> 1, dx = q & 1;
+          const int hy = 2 * bi + dy, hx = 2 * bj + dx;
+          const int y = oy + hy - 1, x = ox + hx - 1;
+          const bool in = decltype(inside_tag)::value || (y >= 0 && y < S && x >= 0 && x < S);
+          float v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float top = dx ? tr[j] : tl[j], bot = dx ? br[j] : bl[j];
-          const float val = dy ? fmaf(0.75f, bot, 0.25f * top) : fmaf(0.25f, bot, 0.75f * top);
-          v[j] = in ? val : 0.0f;
+          for (int j = 0; j < 8; ++j) {
+            const float top = dx ? tr[j] : tl[j], bot = dx ? br[j] : bl[j];
+            const float val = dy ? fmaf(0.75f, bot, 0.25f * top) : fmaf(0.25f, bot, 0.75f * top);
+            v[j] = in ? val : 0.0f;
+          }
+          store8<T>(&tile[(hy * 18 + hx) * cin8 + g * 8], v);
         }
-        store8<T>(&tile[(hy * 18 + hx) * cin8 + g * 8], v);
-      }
+      };
+      if (interior)
+        put(std::true_type{});
+      else
+        put(std::false_type{});
     } else {
       const int e2 = e - n_up;
       const int g = kgf + e2 / NPIX, pix = e2 - (g - kgf) * NPIX;
@@ -348,13 +391,7 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
     for (int j = 0; j < NT; ++j) acc[r][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   const int r0 = wave * RPW;
   const int col = lane & 15, kq = lane >> 4;
-  // this lane's k position as (tap, channel unit): unit = 8-channel group
-  // (BF16, 4 lanes x 8 = one k-step of 32) or channel (FP32, 4 per k-step);
-  // advanced by 4 units per k-step without divisions
-  const int units = sizeof(T) == 2 ? (cin8 >> 3) : cin8;
-  int tap = 0, cu = kq;
-  while (cu >= units) { cu -= units; ++tap; }
-  int dy = tap / 3, dx = tap - 3 * (tap / 3);
+  const int rowbase = (r0 * 18 + col) * cin8;
   for (int c = 0; c < nchunks; ++c) {
     if (!ONE && c + 1 < nchunks) load_chunk(c + 1);
     const T* B = sB + (ONE ? 0 : (c & 1)) * NOUT * BROW;
@@ -362,16 +399,12 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
     for (int s = 0; s < CHS; ++s) {
       const int ks = c * CHS + s;
       if (ks >= nsteps) break;
+      const int abase = rowbase + s_aoff[ks * 4 + kq];
       if constexpr (sizeof(T) == 2) {
-        const int abase = ((r0 + dy) * 18 + col + dx) * cin8 + cu * 8;
         v8bf a[RPW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          if (tap < 9)
-            a[r] = *reinterpret_cast<const v8bf*>(&tile[abase + r * 18 * cin8]);
-          else
-            a[r] = v8bf{0, 0, 0, 0, 0, 0, 0, 0};
-        }
+        for (int r = 0; r < RPW; ++r)
+          a[r] = *reinterpret_cast<const v8bf*>(&tile[abase + r * 18 * cin8]);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const v8bf b = *reinterpret_cast<const v8bf*>(&B[(j * 16 + col) * BROW + s * KSTEP + kq * 8]);
@@ -380,27 +413,15 @@ __global__ __launch_bounds__(256) void k_dec_conv(DecLevel d, const float* __res
             acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[r], acc[r][j], 0, 0, 0);
         }
       } else {
-        const int abase = ((r0 + dy) * 18 + col + dx) * cin8 + cu;
         float a[RPW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
-          a[r] = tap < 9 ? to_f(tile[abase + r * 18 * cin8]) : 0.0f;
+        for (int r = 0; r < RPW; ++r) a[r] = to_f(tile[abase + r * 18 * cin8]);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const float b = to_f(B[(j * 16 + col) * BROW + s * KSTEP + kq]);
 #pragma unroll
           for (int r = 0; r < RPW; ++r)
             acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a[r], acc[r][j], 0, 0, 0);
-        }
-      }
-      // next k-step: four units further
-      cu += 4;
-      while (cu >= units) {
-        cu -= units;
-        ++tap;
-        if (++dx == 3) {
-          dx = 0;
-          ++dy;
         }
       }
     }
@@ -700,8 +721,8 @@ static hipError_t launch_nt(const DecLevel& d, int blocks, const float* pyr, con
   // the whole weight operand in one LDS chunk when it fits
   using One = ConvCfg<T, NT, true>;
   const bool one = d.kpad <= One::CK;
-  const size_t need = one ? conv_smem_bytes<T, NT, true>(d.cin8, d.kn)
-                          : conv_smem_bytes<T, NT, false>(d.cin8, d.kn);
+  const size_t need = one ? conv_smem_bytes<T, NT, true>(d.cin8, d.kn, d.kpad)
+                          : conv_smem_bytes<T, NT, false>(d.cin8, d.kn, d.kpad);
   if (need > max_lds_bytes()) return hipErrorInvalidValue;
   if (one)
     hipLaunchKernelGGL((k_dec_conv<T, NT, true>), dim3(blocks), dim3(256), need, st, d, pyr,

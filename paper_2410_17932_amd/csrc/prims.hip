@@ -125,8 +125,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
 // counts over partitions, and the downsweep ranks its partition in LDS and
 // writes every item straight to its final position.  No inter-workgroup
 // waiting anywhere; deterministic.
-constexpr int kSortBlock = 256, kSortWaves = kSortBlock / 64, kSortItems = 15;
-constexpr int kWaveChunk = 64 * kSortItems, kSortTile = kSortBlock * kSortItems;  // 3840
+constexpr int kSortBlock = 256, kSortWaves = kSortBlock / 64, kSortItems = 8;
+constexpr int kWaveChunk = 64 * kSortItems, kSortTile = kSortBlock * kSortItems;  // 2048
 constexpr int64_t kSortGrid = 1024;
 
 __device__ inline int64_t sort_n(const uint32_t* n_dev, int64_t n_max) {
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
 #pragma unroll
     for (int w = 0; w < kSortWaves; ++w) s_wh[w][tid] = 0;
     __syncthreads();
-    // load: wave w owns [base + w*960, +960); item j of lane l at j*64 + l
+    // load: wave w owns [base + w*512, +512); item j of lane l at j*64 + l
     uint32_t key[kSortItems];
     V val[kSortItems];
     uint32_t rank[kSortItems];
