@@ -163,38 +163,36 @@ __global__ void k_pt_cropgrid(KCrops crops, int nv, int levels, int gx, int gy,
   grid[idx] = mask;
 }
 
-// Fragment count of one point in view v (0 if culled): footprint targets
-// over the crops the grid lists for the point's cell and the point's one or
-// two layers, then the depth cull for a point that reaches any crop.  The
-// cell comes from a reciprocal-based pixel estimate (within 1e-2 px of the
-// exact one, well inside the grid's slack), so the exact projection runs
-// only for points near a crop; a non-positive or non-finite estimate falls
-// back to every crop.
-__device__ inline uint32_t pt_count(const KView& cv, int v, const KCrops& crops, const PtArgs& a,
-                                    const uint32_t* __restrict__ grid, int gx, int gy,
-                                    float x, float y, float z, float r, const float* depth,
-                                    const float* tfinal, float& zkey_depth) {
-  uint32_t cand = crops.n >= 32 ? 0xffffffffu : ((1u << crops.n) - 1u);
-  {
-    const float tx = cv.R[0] * x + cv.R[1] * y + cv.R[2] * z + cv.t[0];
-    const float ty = cv.R[3] * x + cv.R[4] * y + cv.R[5] * z + cv.t[1];
-    const float tz = cv.R[6] * x + cv.R[7] * y + cv.R[8] * z + cv.t[2];
-    if (tz > 0.0f) {
-      const float rz = __builtin_amdgcn_rcpf(tz);
-      const float ex = (cv.fx * (tx * rz) + cv.cx) * (1.0f / kGridCell);
-      const float ey = (cv.fy * (ty * rz) + cv.cy) * (1.0f / kGridCell);
-      if (isfinite(ex) && isfinite(ey)) {
-        const float fx = fminf(fmaxf(floorf(ex), 0.0f), (float)(gx - 1));
-        const float fy = fminf(fmaxf(floorf(ey), 0.0f), (float)(gy - 1));
-        cand = grid[((int64_t)v * gy + (int)fy) * gx + (int)fx];
-        if (!cand) return 0;
-      }
+// Candidate crops of one point in view v: the crop-lookup grid cell of a
+// reciprocal-based pixel estimate (within 1e-2 px of the exact one, well
+// inside the grid's slack).  A non-positive or non-finite estimate gives
+// every crop.
+__device__ inline uint32_t pt_candidates(const KView& cv, int v, int n_crops,
+                                         const uint32_t* __restrict__ grid, int gx, int gy,
+                                         float x, float y, float z) {
+  uint32_t cand = n_crops >= 32 ? 0xffffffffu : ((1u << n_crops) - 1u);
+  const float tx = cv.R[0] * x + cv.R[1] * y + cv.R[2] * z + cv.t[0];
+  const float ty = cv.R[3] * x + cv.R[4] * y + cv.R[5] * z + cv.t[1];
+  const float tz = cv.R[6] * x + cv.R[7] * y + cv.R[8] * z + cv.t[2];
+  if (tz > 0.0f) {
+    const float rz = __builtin_amdgcn_rcpf(tz);
+    const float ex = (cv.fx * (tx * rz) + cv.cx) * (1.0f / kGridCell);
+    const float ey = (cv.fy * (ty * rz) + cv.cy) * (1.0f / kGridCell);
+    if (isfinite(ex) && isfinite(ey)) {
+      const float fx = fminf(fmaxf(floorf(ex), 0.0f), (float)(gx - 1));
+      const float fy = fminf(fmaxf(floorf(ey), 0.0f), (float)(gy - 1));
+      cand = grid[((int64_t)v * gy + (int)fy) * gx + (int)fx];
     }
   }
-  PtGeom g;
-  if (!pt_geom32(cv, x, y, z, r, a.levels, g)) return 0;
+  return cand;
+}
+
+// Footprint targets of a projected point over the candidate crops of view v
+// and the point's one or two pyramid layers.
+__device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, const KCrops& crops,
+                                           uint32_t cand, int levels) {
   uint32_t cnt = 0;
-  const float M = (float)(1 << a.levels);
+  const float M = (float)(1 << levels);
   while (cand) {
     const int k = __builtin_ctz(cand);
     cand &= cand - 1;
@@ -209,8 +207,6 @@ __device__ inline uint32_t pt_count(const KView& cv, int v, const KCrops& crops,
       if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) cnt += pt_targets(ix, iy, Sl);
     }
   }
-  if (cnt && tfinal && pt_occluded(cv, g, depth, tfinal, a.cov_min, a.slack)) cnt = 0;
-  zkey_depth = g.t[2];
   return cnt;
 }
 
@@ -248,22 +244,56 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
   for (int e = tid; e < NSLOT; e += kSelBlock) s_mask[e] = 0;
   __syncthreads();
   const int64_t part = s_part;
-  // ---- counts of every (round, view, point)
+  // ---- counts of every (round, view, point), in stages so that each
+  // stage's loads (positions; grid cells; T' and depth under the points) are
+  // in flight together: a point's fragment count is its footprint targets
+  // over the candidate crops, zero if the depth cull hides it.  The cull
+  // runs before the targets (the result is the same: a hidden point counts
+  // zero either way) because it removes most points that reach a crop.
+  float px[kSelRounds], py[kSelRounds], pz[kSelRounds], pr[kSelRounds];
+  bool pin[kSelRounds];
+#pragma unroll
   for (int j = 0; j < kSelRounds; ++j) {
     const int64_t i = part * kSelPart + (int64_t)j * kSelBlock + tid;
-    const bool in = i < np;
-    float x = 0, y = 0, z = 0, r = 0;
-    if (in) { x = pos[i]; y = pos[np + i]; z = pos[2 * np + i]; r = radius[i]; }
-    for (int v = 0; v < nv; ++v) {
-      uint32_t cnt = 0;
-      float zd = 0.0f;
-      if (in && ((a.view_mask >> v) & 1u)) {
-        const int64_t plane = (int64_t)views.v[v].W * views.v[v].H;
-        cnt = pt_count(views.v[v], v, crops, a, grid, gx, gy, x, y, z, r,
-                       depth ? depth + v * plane : nullptr, tfinal ? tfinal + v * plane : nullptr,
-                       zd);
+    pin[j] = i < np;
+    px[j] = py[j] = pz[j] = pr[j] = 0.0f;
+    if (pin[j]) { px[j] = pos[i]; py[j] = pos[np + i]; pz[j] = pos[2 * np + i]; pr[j] = radius[i]; }
+  }
+  for (int v = 0; v < nv; ++v) {
+    const KView& cv = views.v[v];
+    const bool vm = (a.view_mask >> v) & 1u;
+    const int64_t plane = (int64_t)cv.W * cv.H;
+    uint32_t cand[kSelRounds];
+#pragma unroll
+    for (int j = 0; j < kSelRounds; ++j)
+      cand[j] = pin[j] && vm ? pt_candidates(cv, v, crops.n, grid, gx, gy, px[j], py[j], pz[j]) : 0u;
+    bool ok[kSelRounds], cull[kSelRounds];
+    float tz[kSelRounds], tf[kSelRounds], dp[kSelRounds];
+#pragma unroll
+    for (int j = 0; j < kSelRounds; ++j) {
+      ok[j] = cull[j] = false;
+      tz[j] = tf[j] = dp[j] = 0.0f;
+      if (cand[j]) {
+        PtGeom g;
+        ok[j] = pt_geom32(cv, px[j], py[j], pz[j], pr[j], a.levels, g);
+        tz[j] = g.t[2];
+        int64_t pi;
+        cull[j] = ok[j] && tfinal && pt_cull_pixel(cv, g, pi);
+        if (cull[j]) {
+          tf[j] = tfinal[v * plane + pi];
+          dp[j] = depth[v * plane + pi];
+        }
       }
-      s_zd[(j * nv + v) * kSelBlock + tid] = zd;
+    }
+#pragma unroll
+    for (int j = 0; j < kSelRounds; ++j) {
+      uint32_t cnt = 0;
+      if (ok[j] && !(cull[j] && pt_hidden(tz[j], tf[j], dp[j], a.cov_min, a.slack))) {
+        PtGeom g;   // recomputed for the few points the cull keeps
+        pt_geom32(cv, px[j], py[j], pz[j], pr[j], a.levels, g);
+        cnt = pt_targets_over(g, v, crops, cand[j], a.levels);
+      }
+      s_zd[(j * nv + v) * kSelBlock + tid] = tz[j];
       s_cnt[(j * nv + v) * kSelBlock + tid] = cnt;
       const uint64_t m = __ballot(cnt != 0);
       if (lane == 0) s_mask[(v * kSelRounds + j) * NW + wave] = m;

@@ -54,20 +54,22 @@ __device__ inline bool pt_geom32(const KView& cv, float x, float y, float z, flo
 // Depth-occlusion cull against the periphery's approximate depth (Eq. 1)
 // at the pixel under the point: where the periphery's coverage 1 - T' is at
 // least cov_min, a point farther than slack x (depth / coverage) is hidden.
-// depth/tfinal point at the view's planes.  Every other culling test is
-// independent of this one, so callers run it last, only for points that
-// reach a crop.
-__device__ inline bool pt_occluded(const KView& cv, const PtGeom& g, const float* depth,
-                                   const float* tfinal, float cov_min, float slack) {
-#pragma clang fp contract(off)
+// pt_cull_pixel gives the pixel (false outside the view: never hidden);
+// pt_hidden decides from that pixel's T' and depth, so callers can issue
+// both loads early.  Every other culling test is independent of this one.
+__device__ inline bool pt_cull_pixel(const KView& cv, const PtGeom& g, int64_t& pi) {
   if (!(g.px >= 0.0f && g.px < (float)cv.W && g.py >= 0.0f && g.py < (float)cv.H)) return false;
   const int X = (int)floorf(g.px), Y = (int)floorf(g.py);
-  const int64_t pi = (int64_t)Y * cv.W + X;
-  const float A = 1.0f - tfinal[pi];
+  pi = (int64_t)Y * cv.W + X;
+  return true;
+}
+__device__ inline bool pt_hidden(float tz, float tf, float dep, float cov_min, float slack) {
+#pragma clang fp contract(off)
+  const float A = 1.0f - tf;
   if (!(A >= cov_min)) return false;
-  const float q = depth[pi] / A;
+  const float q = dep / A;
   const float lim = slack * q;
-  return g.t[2] > lim;
+  return tz > lim;
 }
 
 // Layer-l coordinates of the point in a crop with origin (x0, y0) and the
