@@ -22,11 +22,12 @@
 //                     and column ballots
 //   k_gs_bin_prefix   per super-tile: prefix of those counts over its units
 //                     and the tile totals; scan -> tile list offsets
-//   k_gs_tile_ranges  [begin, end) and a length bucket per tile
+//   k_gs_schedule     [begin, end) per tile and the blend order, longest
+//                     list first (one workgroup: counting sort by length
+//                     bucket)
 //   k_gs_bin_scatter  one wave per unit: every Gaussian index goes to its
 //                     final place in each tile list it belongs to, its rank
 //                     within a round from one ballot per tile
-//   radix sort        (one 8-bit pass) of the tiles, longest list first
 //   k_gs_blend        one workgroup per tile in that order, one wave per
 //                     sub-tile; records staged in LDS in batches,
 //                     front-to-back blend with per-wave and block-wide early
@@ -288,9 +289,11 @@ __global__ __launch_bounds__(256) void k_gs_runs(const uint32_t* __restrict__ sk
 // One workgroup: units per run, their exclusive scan (first unit of each
 // super-tile, ubase[st_total] = number of units), and the exact number of
 // tile pairs from the preprocess blocks' partial sums (whatever the
-// capacity).
+// capacity).  With run lengths given (a one-pass sort's digit counts) the
+// runs are their exclusive scan, written here; else k_gs_runs found them.
 constexpr int kUnitsBlock = 1024;
-__global__ __launch_bounds__(kUnitsBlock) void k_gs_units(const uint2* __restrict__ srange,
+__global__ __launch_bounds__(kUnitsBlock) void k_gs_units(uint2* __restrict__ srange,
+                                                          const uint32_t* __restrict__ run_len,
                                                           int64_t st_total,
                                                           const uint64_t* __restrict__ psum,
                                                           int64_t nps, uint32_t* __restrict__ ubase,
@@ -304,15 +307,10 @@ __global__ __launch_bounds__(kUnitsBlock) void k_gs_units(const uint2* __restric
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
   if (lane == 0) s_p[wave] = p;
-  uint32_t carry = 0;
-  for (int64_t s0 = 0; s0 < st_total; s0 += kUnitsBlock) {
-    const int64_t s = s0 + tid;
-    uint32_t u = 0;
-    if (s < st_total) {
-      const uint2 r = srange[s];
-      u = r.y > r.x ? (r.y - r.x + kBinUnit - 1) / kBinUnit : 0u;
-    }
-    uint32_t incl = u;
+  // block-wide exclusive scan of x over the chunk's super-tiles; returns the
+  // chunk total
+  auto block_scan = [&](uint32_t x, uint32_t& excl) {
+    uint32_t incl = x;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t y = __shfl_up(incl, o, 64);
@@ -326,9 +324,33 @@ __global__ __launch_bounds__(kUnitsBlock) void k_gs_units(const uint2* __restric
       woff += w < wave ? s_w[w] : 0u;
       btot += s_w[w];
     }
-    if (s < st_total) ubase[s] = carry + woff + incl - u;
-    carry += btot;
-    __syncthreads();   // s_w is rewritten by the next chunk
+    excl = woff + incl - x;
+    __syncthreads();   // s_w is rewritten by the next scan
+    return btot;
+  };
+  uint32_t carry = 0, rcarry = 0;
+  for (int64_t s0 = 0; s0 < st_total; s0 += kUnitsBlock) {
+    const int64_t s = s0 + tid;
+    uint32_t len = 0;
+    if (s < st_total) {
+      if (run_len) {
+        len = run_len[s];
+      } else {
+        const uint2 r = srange[s];
+        len = r.y > r.x ? r.y - r.x : 0u;
+      }
+    }
+    if (run_len) {
+      uint32_t b;
+      const uint32_t tot = block_scan(len, b);
+      if (s < st_total) srange[s] = make_uint2(rcarry + b, rcarry + b + len);
+      rcarry += tot;
+    }
+    const uint32_t u = (len + kBinUnit - 1) / kBinUnit;
+    uint32_t ue;
+    const uint32_t utot = block_scan(u, ue);
+    if (s < st_total) ubase[s] = carry + ue;
+    carry += utot;
   }
   if (tid == 0) {
     ubase[st_total] = carry;
@@ -429,26 +451,79 @@ __global__ __launch_bounds__(64 * kPrefixWaves) void k_gs_bin_prefix(
   if (wave == 0 && bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t)) tcnt[t] = tot;
 }
 
-// Tile ranges and the schedule key (descending in 16 log2(1 + length)):
-// work per tile is very uneven, and starting the long lists first keeps them
-// off the end of the blend.  Past the capacity every list is left empty.
-__global__ __launch_bounds__(256) void k_gs_tile_ranges(const uint32_t* __restrict__ toff,
-                                                        const uint32_t* __restrict__ tcnt,
-                                                        const uint32_t* __restrict__ total_p,
-                                                        int64_t max_pairs, int64_t tiles_total,
-                                                        uint2* __restrict__ ranges,
-                                                        uint32_t* __restrict__ okey,
-                                                        uint32_t* __restrict__ oval,
-                                                        int32_t* status) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= tiles_total) return;
+// Tile ranges and the blend schedule, in one workgroup: tiles ordered by
+// length bucket, descending in 16 log2(1 + length) (work per tile is very
+// uneven, and starting the long lists first keeps them off the end of the
+// blend).  A counting sort: bucket histogram, its scan, then each tile takes
+// the next place of its bucket (the order within a bucket is free: tiles
+// are independent).  Past the capacity every list is left empty.
+constexpr int kSchedBlock = 1024, kSchedItems = 8;
+__device__ inline uint32_t sched_bucket(uint32_t len) {
+  const float lb = 16.0f * log2f(1.0f + (float)len);
+  return 255u - (uint32_t)fminf(lb, 255.0f);
+}
+__global__ __launch_bounds__(kSchedBlock) void k_gs_schedule(
+    const uint32_t* __restrict__ toff, const uint32_t* __restrict__ tcnt,
+    const uint32_t* __restrict__ total_p, int64_t max_pairs, int64_t tiles_total,
+    uint2* __restrict__ ranges, uint32_t* __restrict__ order, int32_t* status) {
+  __shared__ uint32_t s_hist[256], s_base[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool over = (int64_t)*total_p > max_pairs;
-  if (t == 0 && over) set_status(status, VRS_ECAPACITY);
-  const uint32_t b = over ? 0u : toff[t], e = over ? 0u : b + tcnt[t];
-  ranges[t] = make_uint2(b, e);
-  const float lb = 16.0f * log2f(1.0f + (float)(e - b));
-  okey[t] = 255u - (uint32_t)fminf(lb, 255.0f);
-  oval[t] = (uint32_t)t;
+  if (tid == 0 && over) set_status(status, VRS_ECAPACITY);
+  if (tid < 256) s_hist[tid] = 0;
+  __syncthreads();
+  constexpr int64_t kStep = (int64_t)kSchedBlock * kSchedItems;
+  for (int64_t t0 = 0; t0 < tiles_total; t0 += kStep) {
+    uint32_t b[kSchedItems], c[kSchedItems];   // every load in flight first
+#pragma unroll
+    for (int k = 0; k < kSchedItems; ++k) {
+      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
+      b[k] = c[k] = 0u;
+      if (t < tiles_total && !over) {
+        b[k] = toff[t];
+        c[k] = tcnt[t];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSchedItems; ++k) {
+      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
+      if (t < tiles_total) {
+        ranges[t] = make_uint2(b[k], b[k] + c[k]);
+        atomicAdd(&s_hist[sched_bucket(c[k])], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {   // exclusive scan of the 256 buckets, four per lane
+    uint32_t h[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      h[q] = sum;
+      sum += s_hist[lane * 4 + q];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_base[lane * 4 + q] = incl - sum + h[q];
+  }
+  __syncthreads();
+  for (int64_t t0 = 0; t0 < tiles_total; t0 += kStep) {
+    uint32_t c[kSchedItems];
+#pragma unroll
+    for (int k = 0; k < kSchedItems; ++k) {
+      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
+      c[k] = t < tiles_total && !over ? tcnt[t] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kSchedItems; ++k) {
+      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
+      if (t < tiles_total) order[atomicAdd(&s_base[sched_bucket(c[k])], 1u)] = (uint32_t)t;
+    }
+  }
 }
 
 // Per unit: tile l's cursor starts at the tile's list offset plus the counts
@@ -890,18 +965,23 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     VRS_HIP_CHECK(fill_u32(super_count, 0, 1, st));
     VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, L.srange), 0, 2 * L.st_total, st));
   }
-  // binning: runs, units, per unit and tile counts, tile offsets, ranges,
-  // scatter; then the tiles longest list first (one stable 8-bit pass).
-  // Timed with the sorts, so the blend stage is the blend alone.
+  // binning: runs, units, per unit and tile counts, tile offsets, ranges and
+  // the longest-first schedule, scatter.  Timed with the sorts, so the blend
+  // stage is the blend alone.
   const uint32_t* skeys = at<uint32_t>(ws, s1 ? L.skey1 : L.skey0);
   const uint64_t* svals = at<uint64_t>(ws, s1 ? L.sval1 : L.sval0);
   const int64_t mp = std::max<int64_t>(max_pairs, 1);
   const unsigned unit_blocks =
       (unsigned)std::min<int64_t>(2048, div_up(bin_units_max(mp, L.st_total), 4));
-  hipLaunchKernelGGL(k_gs_runs, dim3((unsigned)std::min<int64_t>(4096, div_up(mp, 256))),
-                     dim3(256), 0, st, skeys, super_count, max_pairs, at<uint2>(ws, L.srange));
-  VRS_LAUNCH_CHECK();
+  // one sort pass: its digit counts are the run lengths; else find the runs
+  const bool one_pass = vn > 0 && L.st_bits <= 8;
+  if (!one_pass) {
+    hipLaunchKernelGGL(k_gs_runs, dim3((unsigned)std::min<int64_t>(4096, div_up(mp, 256))),
+                       dim3(256), 0, st, skeys, super_count, max_pairs, at<uint2>(ws, L.srange));
+    VRS_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_gs_units, dim3(1), dim3(kUnitsBlock), 0, st, at<uint2>(ws, L.srange),
+                     one_pass ? radix_sort_digit_totals(at<void>(ws, L.sort_tmp)) : nullptr,
                      L.st_total, at<uint64_t>(ws, L.psum), vn > 0 ? nps : 0,
                      at<uint32_t>(ws, L.ubase), at<uint32_t>(ws, L.nunits), pair_count);
   VRS_LAUNCH_CHECK();
@@ -916,10 +996,9 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.tcnt), nullptr, at<uint32_t>(ws, L.toff),
                                    nullptr, nullptr, L.tiles_total, at<void>(ws, L.scan_tmp),
                                    dev_status, st));
-  hipLaunchKernelGGL(k_gs_tile_ranges, dim3(div_up(L.tiles_total, 256)), dim3(256), 0, st,
-                     at<uint32_t>(ws, L.toff), at<uint32_t>(ws, L.tcnt), pair_count, max_pairs,
-                     L.tiles_total, at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.okey0),
-                     at<uint32_t>(ws, L.oval0), dev_status);
+  hipLaunchKernelGGL(k_gs_schedule, dim3(1), dim3(kSchedBlock), 0, st, at<uint32_t>(ws, L.toff),
+                     at<uint32_t>(ws, L.tcnt), pair_count, max_pairs, L.tiles_total,
+                     at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.order), dev_status);
   VRS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_gs_bin_scatter, dim3(unit_blocks), dim3(256), 0, st, svals,
                      at<uint2>(ws, L.srange), at<uint32_t>(ws, L.ubase),
@@ -927,11 +1006,7 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                      at<uint32_t>(ws, L.toff), pair_count, max_pairs, L.sxn, L.spv, L.tiles_x,
                      L.tiles_y, at<uint32_t>(ws, L.ids));
   VRS_LAUNCH_CHECK();
-  bool o1 = false;
-  VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.okey0), at<uint32_t>(ws, L.oval0),
-                               at<uint32_t>(ws, L.okey1), at<uint32_t>(ws, L.oval1), nullptr,
-                               L.tiles_total, 8, at<void>(ws, L.sort_tmp), dev_status, st, &o1));
-  const uint32_t* order = at<uint32_t>(ws, o1 ? L.oval1 : L.oval0);
+  const uint32_t* order = at<uint32_t>(ws, L.order);
   trace_end(VRS_TRACE_GS_SORT, st);
   trace_begin(VRS_TRACE_GS_BLEND, st);
   switch (o.tile) {

@@ -15,7 +15,7 @@ struct RenderWs {
       srange, ubase, nunits,        // per super-tile run and first work unit
       ucnt, tcnt, toff,             // per (unit, tile) and per tile counts, tile offsets
       ids,                          // tile lists (Gaussian indices), tile-id order
-      okey0, oval0, okey1, oval1,   // tile schedule (length bucket, tile), sorted once
+      order,                        // tile schedule: tile ids, longest list first
       ranges, last, evals, g2d, sort_tmp, scan_tmp, total;
   int64_t vn, tiles_x, tiles_y, tiles_total, npix, sxn, syn, spv, st_total;
   int st_bits;
@@ -76,15 +76,11 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->toff = c.take((size_t)L->tiles_total * 4);
   L->ids = c.take(mp * 4);
   L->ranges = c.take((size_t)L->tiles_total * 8);
-  L->okey0 = c.take((size_t)L->tiles_total * 4);
-  L->oval0 = c.take((size_t)L->tiles_total * 4);
-  L->okey1 = c.take((size_t)L->tiles_total * 4);
-  L->oval1 = c.take((size_t)L->tiles_total * 4);
+  L->order = c.take((size_t)L->tiles_total * 4);
   L->last = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->evals = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->g2d = c.take((size_t)vn * 10 * 4);   // per (view, Gaussian) screen-space gradients
-  L->sort_tmp = c.take(std::max(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->st_bits)),
-                                sort_tmp_bytes(L->tiles_total, 8)));
+  L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->st_bits)));
   L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(L->tiles_total)));
   L->total = c.off;
   return true;

@@ -140,10 +140,8 @@ struct PtArgs {
 // listed in every cell that meets [x0 - 2^levels - 2, x0 + size + 2^levels + 2)
 // (likewise y); border cells extend to infinity so that lookups of pixels
 // outside the view clamp to them.
-__global__ void k_pt_cropgrid(KCrops crops, int nv, int levels, int gx, int gy,
-                              uint32_t* __restrict__ grid) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nv * gx * gy) return;
+__device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx, int gy,
+                                        int64_t idx, uint32_t* __restrict__ grid) {
   const int v = (int)(idx / ((int64_t)gx * gy));
   const int cell = (int)(idx - (int64_t)v * gx * gy);
   const int cy = cell / gx, cx = cell - cy * gx;
@@ -161,6 +159,22 @@ __global__ void k_pt_cropgrid(KCrops crops, int nv, int levels, int gx, int gy,
     if (x0 < hi_x && x1 > lo_x && y0 < hi_y && y1 > lo_y) mask |= 1u << k;
   }
   grid[idx] = mask;
+}
+
+// Per-call set-up in one launch: the pyramid zeroed (fragments accumulate
+// into it), the selection's partition counter and look-back flags zeroed,
+// and the crop-lookup grid.
+__global__ void k_pt_prep(float4* __restrict__ pyramid, int64_t pix_total,
+                          uint32_t* __restrict__ sel_tmp, int64_t sel_words, KCrops crops, int nv,
+                          int levels, int gx, int gy, uint32_t* __restrict__ grid) {
+  const int64_t cells = (int64_t)nv * gx * gy;
+  const int64_t n = std::max(std::max(pix_total, sel_words), cells);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < pix_total) pyramid[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i < sel_words) sel_tmp[i] = 0u;
+    if (i < cells) pt_cropgrid_cell(crops, levels, gx, gy, i, grid);
+  }
 }
 
 // Candidate crops of one point in view v: the crop-lookup grid cell of a
@@ -515,13 +529,13 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   const int64_t vn = L.vn;
   uint32_t* frag_count = at<uint32_t>(ws, L.frag_count);
   trace_begin(VRS_TRACE_SPLAT, st);
-  if (L.pix_total > 0) {
-    const int blocks = (int)std::min<int64_t>(4096, div_up(L.pix_total, 256));
-    hipLaunchKernelGGL(k_zero4, dim3(blocks), dim3(256), 0, st,
-                       reinterpret_cast<float4*>(pyramid), L.pix_total);
-    VRS_LAUNCH_CHECK();
-  }
   if (vn == 0 || n_crops == 0) {
+    if (L.pix_total > 0) {
+      const int blocks = (int)std::min<int64_t>(4096, div_up(L.pix_total, 256));
+      hipLaunchKernelGGL(k_zero4, dim3(blocks), dim3(256), 0, st,
+                         reinterpret_cast<float4*>(pyramid), L.pix_total);
+      VRS_LAUNCH_CHECK();
+    }
     VRS_HIP_CHECK(fill_u32(frag_count, 0, 1, st));
     trace_end(VRS_TRACE_SPLAT, st);
     return VRS_OK;
@@ -531,12 +545,16 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   uint64_t* sel_flags = at<uint64_t>(ws, L.sel_tmp + 256);
   const int sel_parts = div_up(np, kSelPart);
   const size_t sel_lds = (size_t)kSelRounds * n_views * kSelBlock * 8;
-  VRS_HIP_CHECK(fill_u32(sel_counter, 0, (int64_t)(sel_tmp_bytes(np) / 4), st));
   uint32_t* grid = at<uint32_t>(ws, L.grid);
-  const int64_t cells = (int64_t)n_views * L.gx * L.gy;
-  hipLaunchKernelGGL(k_pt_cropgrid, dim3(div_up(cells, 256)), dim3(256), 0, st, kc, n_views, levels,
-                     L.gx, L.gy, grid);
-  VRS_LAUNCH_CHECK();
+  {
+    const int64_t sel_words = (int64_t)(sel_tmp_bytes(np) / 4);
+    const int64_t cells = (int64_t)n_views * L.gx * L.gy;
+    const int64_t most = std::max(std::max(L.pix_total, sel_words), cells);
+    hipLaunchKernelGGL(k_pt_prep, dim3((unsigned)std::min<int64_t>(4096, div_up(most, 256))),
+                       dim3(256), 0, st, reinterpret_cast<float4*>(pyramid), L.pix_total,
+                       sel_counter, sel_words, kc, n_views, levels, L.gx, L.gy, grid);
+    VRS_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), sel_lds, st, pos, radius, np, kv,
                      kc, a, depth, t_final, grid, L.gx, L.gy, sel_counter, sel_flags, at<uint32_t>(ws, L.ckey0),
                      at<uint32_t>(ws, L.cval0), at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt),

@@ -38,12 +38,17 @@ __global__ void k_fill(uint32_t* p, uint32_t v, int64_t n) {
 // ------------------------------------------------------------------ scan
 constexpr int kScanBlock = 256, kScanItems = 8, kScanTile = kScanBlock * kScanItems;
 
-__global__ void k_scan_clear(uint32_t* counter, uint64_t* flags, const uint32_t* n_dev,
-                             int64_t n_max) {
+// Clears the partition counter, the look-back flags the scan will use and
+// the total (n may turn out to be 0 on the device: the total is then 0).
+__global__ void k_scan_clear(uint32_t* counter, uint64_t* flags, uint32_t* total,
+                             const uint32_t* n_dev, int64_t n_max) {
   int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
   int64_t parts = (n + kScanTile - 1) / kScanTile;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i == 0) *counter = 0;
+  if (i == 0) {
+    *counter = 0;
+    if (total) *total = 0;
+  }
   for (; i < parts; i += (int64_t)gridDim.x * blockDim.x) flags[i] = 0;
 }
 
@@ -371,11 +376,8 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* o
   uint64_t* flags = reinterpret_cast<uint64_t*>(static_cast<char*>(tmp) + 256);
   int64_t parts = (n_max + kScanTile - 1) / kScanTile;
   int cb = (int)std::min<int64_t>(1024, (parts + 255) / 256 + 1);
-  hipLaunchKernelGGL(k_scan_clear, dim3(cb), dim3(256), 0, st, counter, flags, n_dev, n_max);
-  if (total) {
-    // n may turn out to be 0 on the device: start from a defined total
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, total, 0u, (int64_t)1);
-  }
+  hipLaunchKernelGGL(k_scan_clear, dim3(cb), dim3(256), 0, st, counter, flags, total, n_dev,
+                     n_max);
   hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kScanBlock), 0, st, in, idx, out, total,
                      n_dev, n_max, counter, flags, status, flags_mode);
   return hipGetLastError();
@@ -390,6 +392,10 @@ hipError_t exclusive_scan_u32(const uint32_t* in, const uint32_t* idx, uint32_t*
 hipError_t exclusive_scan_flags_u32(const uint32_t* in, uint32_t* out, uint32_t* total,
                                     int64_t n, void* tmp, int32_t* status, hipStream_t st) {
   return scan_impl(in, nullptr, out, total, nullptr, n, tmp, status, st, 1);
+}
+
+const uint32_t* radix_sort_digit_totals(const void* tmp) {
+  return static_cast<const uint32_t*>(tmp);   // totals lead the temporary
 }
 
 size_t sort_tmp_bytes(int64_t n_max, int key_bits) {

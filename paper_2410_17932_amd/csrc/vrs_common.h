@@ -99,6 +99,9 @@ hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1
 hipError_t radix_sort_u64(uint32_t* k0, uint64_t* v0, uint32_t* k1, uint64_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
                           int32_t* status, hipStream_t st, bool* result_in_1);
+// After a sort, the key count of each digit value of its last pass
+// (uint32 [256], device): for a one-pass sort, the run length of every key.
+const uint32_t* radix_sort_digit_totals(const void* tmp);
 
 // Stage timing hook (vrs_trace_set).
 void trace_begin(int stage, hipStream_t st);
