@@ -32,6 +32,8 @@
 //                     sub-tile; records staged in LDS in batches,
 //                     front-to-back blend with per-wave and block-wide early
 //                     exit
+#include <type_traits>
+
 #include "gs_layout.h"
 
 namespace vrs {
@@ -649,8 +651,9 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   // sub-tile of this wave and the lane's pixels
   const int sx0 = tx * TILE + (wave % NQ) * SUB, sy0 = ty * TILE + (wave / NQ) * SUB;
   const int px = sx0 + lane % SUB;
-  // ry[q] is the pixel row tested against record rectangles; a pixel that has
-  // stopped (or lies outside the image) gets kStopped, which fails every test
+  // ry[q] is the pixel row tested against record rectangles; a pixel outside
+  // the image gets kStopped, one that has stopped kStopped + the count of
+  // sub-tile-holding records it evaluated (both fail every rectangle test)
   constexpr int kStopped = 1 << 30;
   int py[PPT], ry[PPT];
   float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
@@ -673,11 +676,13 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   float yc[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) yc[q] = (float)py[q] + 0.5f;
-  int all_ry = kStopped;
+  int all_ry = kStopped;   // bit 30 stays set only while every pixel has stopped
 #pragma unroll
   for (int q = 0; q < PPT; ++q) all_ry &= ry[q];
-  bool alive = __ballot(all_ry != kStopped) != 0;   // wave-uniform
-  uint32_t pending = 0;   // out-of-reach records holding the sub-tile, not yet counted
+  bool alive = __ballot((all_ry & kStopped) == 0) != 0;   // wave-uniform
+  // records whose rectangle holds the sub-tile, so far: every live pixel
+  // evaluated each of them, so they are counted per wave, not per pixel
+  uint32_t ncov = 0;
   for (uint32_t b0 = begin; b0 < end; b0 += BLOCK) {
     if (__syncthreads_count(alive) == 0) break;
     const uint32_t jr = b0 + tid;
@@ -736,15 +741,14 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
       while (m) {
         // Records out of reach of the ellipse before the next one that may
         // contribute: no pixel can pass alpha_min, so only the evaluation
-        // count of in-rectangle live pixels moves.  Liveness changes only at
-        // contributing records, so those whose rectangle holds the whole
-        // sub-tile are only counted (added to every live pixel before the
-        // next record that may contribute), the others tested per pixel, in
-        // a loop of their own: the blend state flows through this loop alone.
+        // count of in-rectangle live pixels moves.  Those whose rectangle
+        // holds the whole sub-tile are only counted; the others are tested
+        // per pixel, in a loop of their own: the blend state flows through
+        // this loop alone.
         const uint64_t mf = m & mfull;
         const uint64_t cheap = mf ? (m & ((mf & (~mf + 1ull)) - 1ull)) : m;
         m &= ~cheap;
-        pending += (uint32_t)__popcll(cheap & mcov);
+        ncov += (uint32_t)__popcll(cheap & mcov);
         uint64_t cpart = cheap & ~mcov;
         while (cpart) {
           const int kc = g * 64 + __builtin_ctzll(cpart);
@@ -759,11 +763,6 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
             evals[q] += (cin & ((uint32_t)(ry[q] - cy0) <= cspan)) ? 1u : 0u;
         }
         if (!m) break;
-        if (pending) {   // uniform over the wave
-#pragma unroll
-          for (int q = 0; q < PPT; ++q) evals[q] += ry[q] != kStopped ? pending : 0u;
-          pending = 0;
-        }
         const int bit = __builtin_ctzll(m);
         const int k = g * 64 + bit;
         m &= m - 1;
@@ -776,7 +775,10 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
         // and inside the record's rectangle (tested as unsigned range checks,
         // combined with bitwise operators so that nothing branches; where the
         // rectangle holds the sub-tile, liveness alone).
-        auto blend_record = [&](auto in_rect) {
+        auto blend_record = [&](auto in_rect, auto cover_tag) {
+          constexpr bool kCover = decltype(cover_tag)::value;
+          if (kCover) ++ncov;
+          const int stopped = kStopped + (int)ncov;
           all_ry = kStopped;
 #pragma unroll
           for (int q = 0; q < PPT; ++q) {
@@ -793,7 +795,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
             const bool ok0 = inr & (al >= amin);
             const bool stop = ok0 & (Tn < tmin);
             const bool ok = ok0 & !stop;
-            ry[q] = stop ? kStopped : ry[q];
+            ry[q] = stop ? stopped : ry[q];
             const float wgt = ok ? w0 : 0.0f;
             C0[q] = fmaf(c.x, wgt, C0[q]);
             C1[q] = fmaf(c.y, wgt, C1[q]);
@@ -802,29 +804,30 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
             T[q] -= wgt;
             cnt[q] += ok ? 1 : 0;
             last[q] = ok ? pos : last[q];
-            evals[q] += inr ? 1u : 0u;
+            if (!kCover) evals[q] += inr ? 1u : 0u;
             all_ry &= ry[q];
           }
         };
         if ((mcov >> bit) & 1ull) {
-          blend_record([&](int q) { return ry[q] != kStopped; });
+          blend_record([&](int q) { return ry[q] < kStopped; }, std::true_type{});
         } else {
           const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
           const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
           const bool inx = (uint32_t)(px - rx0) <= (uint32_t)((int)(hi & 0xffffu) - rx0);
           const uint32_t ry_span = (uint32_t)((int)(hi >> 16) - ry0);
-          blend_record([&](int q) { return inx & ((uint32_t)(ry[q] - ry0) <= ry_span); });
+          blend_record([&](int q) { return inx & ((uint32_t)(ry[q] - ry0) <= ry_span); },
+                       std::false_type{});
         }
-        if (__ballot(all_ry != kStopped) == 0) {
+        if (__ballot((all_ry & kStopped) == 0) == 0) {
           alive = false;
           break;
         }
       }
     }
   }
-  // records counted but not yet added: every pixel still live saw them
+  // sub-tile-holding records: up to its stop, or all of them
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) evals[q] += ry[q] != kStopped ? pending : 0u;
+  for (int q = 0; q < PPT; ++q) evals[q] += ry[q] >= kStopped ? (uint32_t)(ry[q] - kStopped) : ncov;
   const int64_t plane = (int64_t)W * H;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
