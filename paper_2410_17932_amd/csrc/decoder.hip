@@ -158,7 +158,9 @@ struct HeadFuse {
 // of CHS k-steps are double-buffered.
 template <typename T, int NT, bool ONE>
 struct ConvCfg {
-  static constexpr int TH = DecTraits<T>::TH, KSTEP = DecTraits<T>::KSTEP;
+  // 8-row tiles where the accumulators would leave one wave per SIMD
+  static constexpr int TH = sizeof(T) == 2 && NT >= 8 ? 8 : DecTraits<T>::TH;
+  static constexpr int KSTEP = DecTraits<T>::KSTEP;
   static constexpr int NPIX = (TH + 2) * 18;
   static constexpr int CR = TH / 2 + 2, CC = 10;       // coarse rows / columns staged
   static constexpr int NOUT = NT * 16;
@@ -191,9 +193,10 @@ __host__ __device__ inline size_t conv_smem_bytes(int cin8, int kn, int kpad) {
 }
 
 // Register budget per N-tile count: the occupancy the accumulators allow
-// (4, 3, 2, 1 waves per SIMD for 2, 4, 6, 8 N-tiles).
+// (4, 3, 2, 2 waves per SIMD for 2, 4, 6, 8 N-tiles; 8 N-tiles use 8-row
+// tiles).
 template <int NT>
-constexpr int conv_waves() { return NT <= 2 ? 4 : (NT <= 4 ? 3 : (NT <= 6 ? 2 : 1)); }
+constexpr int conv_waves() { return NT <= 2 ? 4 : (NT <= 4 ? 3 : 2); }
 template <typename T, int NT, bool ONE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(conv_waves<NT>())))
 void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
@@ -655,7 +658,8 @@ static bool dec_plan(const vrs_decoder_desc* dd, const vrs_crop* crops, int n_cr
 
 static void level_args(const DecPlan& P, int l, const vrs_crop* crops, int n_crops,
                        const KViews& kv, int levels, DecLevel* d, int* blocks) {
-  const int TH = P.dtype == VRS_BF16 ? 16 : 8;
+  const int NT = 2 * P.kp[l] / 16;
+  const int TH = P.dtype == VRS_BF16 && NT < 8 ? 16 : 8;   // as ConvCfg
   d->C = P.C;
   d->cin = P.cin[l];
   d->cin8 = P.cin8[l];
