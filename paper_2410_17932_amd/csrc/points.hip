@@ -2,22 +2,26 @@
 // Sec. 4 "Inference": one count, one scan and one fill over all pyramid
 // layers and all crops).
 //
-// Instead of per-pixel fragment lists sorted in place, the pass orders all
-// surviving (view, point) entries by depth once, emits every fragment in
-// that order, and sorts the fragments stably by layer pixel -- the same
-// radix sort the periphery uses -- so each pixel's list comes out in
-// (depth, point index) order with no atomics and no per-pixel sort.
+// Fragments go straight to per-pixel segments: emission counts each layer
+// pixel's fragments (an atomic per fragment gives its slot), a scan turns
+// the counts into segment offsets, and each fragment's place in its segment
+// is its rank by (float32 bits of t.z, point index) among the segment's
+// fragments -- so the lists come out in blend order with no global sort,
+// and deterministic (the slots only place fragments in a scratch copy).
+//   k_pt_prep      per-pixel counters and selection flags zeroed, crop grid
 //   k_pt_select    one thread per point, points read once for all crops:
-//                  projection, layer, crop footprints, then the depth cull
-//                  for points that reach a crop; survivors (depth key, entry,
-//                  fragment count) are compacted in the same pass
-//                  (decoupled look-back), per view in point order
-//   radix sort     of the survivors by depth key (stable)
-//   scan           fragment counts in depth order -> offsets
-//   k_pt_emit      one thread per survivor writes its fragments
-//                  (layer pixel key, weight | point index)
-//   radix sort     by layer pixel key (stable)
-//   k_pt_blend     segment heads walk their pixel's list front to back
+//                  projection, layer, crop footprints, then the depth cull;
+//                  survivors (depth key, entry, fragment count) compacted in
+//                  the same pass (decoupled look-back), per view in point
+//                  order
+//   scan           fragment counts of the survivors -> offsets
+//   k_pt_emit      one thread per survivor writes its fragments (layer
+//                  pixel, weight | point index, depth key, slot in pixel)
+//   scan           per-pixel counts -> segment offsets
+//   k_pt_scatter   (depth key, point index) of each fragment into its
+//                  pixel's segment, at its slot
+//   k_pt_rank      each fragment's rank in its segment -> its final place
+//   k_pt_blend     one thread per layer pixel walks its list front to back
 #include <hip/hip_fp16.h>
 
 #include "lookback.h"
@@ -26,12 +30,14 @@
 namespace vrs {
 
 struct SplatWs {
-  size_t cent, ccnt, ckey0, cval0, ckey1, cval1, live, foffs, frag_count, fkey0, fval0, fkey1,
-      fval1, sel_tmp, grid, sort_tmp, scan_tmp, total;
+  size_t cent, ccnt, ckey0, cval0, live, foffs, frag_count,
+      fkey0, fval0, fdep, fslot,   // fragments in emission order
+      useg,                        // (depth key, point index) per segment place
+      fkey1, fval1,                // fragments in blend order
+      pcnt, poff,                  // per layer pixel: fragment count, segment offset
+      sel_tmp, grid, scan_tmp, total;
   int gx, gy;   // crop-lookup grid cells per view row / column
   int64_t vn, pix_total;
-  int key_bits;
-  bool frags_in_1;
 };
 
 constexpr int kSelBlock = 256;
@@ -40,12 +46,6 @@ constexpr int kSelBlock = 256;
 // (partitions of kSelPart points; one word per 256 points bounds them)
 static size_t sel_tmp_bytes(int64_t np) {
   return 256 + (size_t)std::max<int64_t>(1, div_up(np, kSelBlock)) * 8;
-}
-
-static int bits_for_p(int64_t n) {
-  int b = 1;
-  while (b < 32 && (int64_t(1) << b) < n) ++b;
-  return b;
 }
 
 static int64_t pyramid_pixels(const vrs_crop* crops, int n_crops, int levels) {
@@ -71,27 +71,28 @@ static bool splat_layout(int64_t np, int nv, int W, int H, const vrs_crop* crops
   L->gy = (H + kGridCell - 1) / kGridCell;
   L->vn = np * nv;
   L->pix_total = pyramid_pixels(crops, n_crops, levels);
-  L->key_bits = bits_for_p(std::max<int64_t>(L->pix_total, 2));
-  L->frags_in_1 = (((L->key_bits + 7) / 8) & 1) != 0;
   const int64_t vn = std::max<int64_t>(L->vn, 1), mf = std::max<int64_t>(max_frags, 1);
+  const int64_t pt = std::max<int64_t>(L->pix_total, 1);
   Carver c;
   L->cent = c.take(vn * 4);
   L->ccnt = c.take(vn * 4);
   L->ckey0 = c.take(vn * 4);
   L->cval0 = c.take(vn * 4);
-  L->ckey1 = c.take(vn * 4);
-  L->cval1 = c.take(vn * 4);
   L->live = c.take(4);
   L->foffs = c.take(vn * 4);
   L->frag_count = c.take(4);
   L->fkey0 = c.take(mf * 4);
   L->fval0 = c.take(mf * 8);
+  L->fdep = c.take(mf * 4);
+  L->fslot = c.take(mf * 4);
+  L->useg = c.take(mf * 8);
   L->fkey1 = c.take(mf * 4);
   L->fval1 = c.take(mf * 8);
+  L->pcnt = c.take(pt * 4);
+  L->poff = c.take(pt * 4);
   L->sel_tmp = c.take(sel_tmp_bytes(np));
   L->grid = c.take((size_t)nv * L->gx * L->gy * 4);
-  L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mf, L->key_bits)));
-  L->scan_tmp = c.take(scan_tmp_bytes(vn));
+  L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(pt)));
   L->total = c.off;
   return true;
 }
@@ -161,17 +162,17 @@ __device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx,
   grid[idx] = mask;
 }
 
-// Per-call set-up in one launch: the pyramid zeroed (fragments accumulate
-// into it), the selection's partition counter and look-back flags zeroed,
-// and the crop-lookup grid.
-__global__ void k_pt_prep(float4* __restrict__ pyramid, int64_t pix_total,
+// Per-call set-up in one launch: the per-pixel fragment counters and the
+// selection's partition counter and look-back flags zeroed, and the
+// crop-lookup grid.
+__global__ void k_pt_prep(uint32_t* __restrict__ pcnt, int64_t pix_total,
                           uint32_t* __restrict__ sel_tmp, int64_t sel_words, KCrops crops, int nv,
                           int levels, int gx, int gy, uint32_t* __restrict__ grid) {
   const int64_t cells = (int64_t)nv * gx * gy;
   const int64_t n = std::max(std::max(pix_total, sel_words), cells);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    if (i < pix_total) pyramid[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i < pix_total) pcnt[i] = 0u;
     if (i < sel_words) sel_tmp[i] = 0u;
     if (i < cells) pt_cropgrid_cell(crops, levels, gx, gy, i, grid);
   }
@@ -371,18 +372,24 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
 }
 
 // ------------------------------------------------------------------ emit
+// One thread per survivor (compaction order): its fragments at its offset,
+// each with its layer pixel, weight | point index, depth key and slot in
+// the pixel's segment (the pixel's count before this fragment).
 __global__ __launch_bounds__(256) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
-    KCrops crops, PtArgs a, const uint32_t* __restrict__ sorted_c,
-    const uint32_t* __restrict__ cent, const uint32_t* __restrict__ live_p, const uint32_t* __restrict__ foffs,
-    const uint32_t* __restrict__ total_p, int64_t max_frags, uint32_t* __restrict__ fkey,
-    uint64_t* __restrict__ fval, int32_t* status) {
+    KCrops crops, PtArgs a, const uint32_t* __restrict__ ckey,
+    const uint32_t* __restrict__ cent, const uint32_t* __restrict__ live_p,
+    const uint32_t* __restrict__ foffs, const uint32_t* __restrict__ total_p, int64_t max_frags,
+    uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval, uint32_t* __restrict__ fdep,
+    uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt, int32_t* status) {
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
+  if (total > max_frags) return;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t e = cent[sorted_c[j]];
+    const uint32_t e = cent[j];
+    const uint32_t dz = ckey[j];
     const int v = (int)(e / np);
     const int64_t i = e - (int64_t)v * np;
     const KView& cv = views.v[v];
@@ -411,10 +418,11 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               const int xx = ix + dx, yy = iy + dy;
               if (xx < 0 || xx >= Sl || yy < 0 || yy >= Sl) continue;
               const float w = wl * (dx ? bx : 1.0f - bx) * (dy ? by : 1.0f - by);
-              if (o < max_frags) {
-                fkey[o] = (uint32_t)(lb + yy * Sl + xx);
-                fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
-              }
+              const uint32_t px = (uint32_t)(lb + yy * Sl + xx);
+              fkey[o] = px;
+              fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
+              fdep[o] = dz;
+              fslot[o] = atomicAdd(&pcnt[px], 1u);
               ++o;
             }
         }
@@ -424,23 +432,67 @@ __global__ __launch_bounds__(256) void k_pt_emit(
   }
 }
 
+// Each fragment's (depth key, point index) into its pixel's segment, at its
+// slot.
+__global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__ fkey,
+                                                    const uint64_t* __restrict__ fval,
+                                                    const uint32_t* __restrict__ fdep,
+                                                    const uint32_t* __restrict__ fslot,
+                                                    const uint32_t* __restrict__ poff,
+                                                    const uint32_t* __restrict__ total_p,
+                                                    int64_t max_frags, uint64_t* __restrict__ useg) {
+  const int64_t total = *total_p;
+  if (total > max_frags) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    useg[poff[fkey[i]] + fslot[i]] = ((uint64_t)fdep[i] << 32) | (uint32_t)fval[i];
+}
+
+// A fragment's place in blend order: its segment's offset plus the number of
+// the segment's fragments before it in (depth key, point index) order (a
+// point reaches a layer pixel at most once, so the pairs are distinct).
+__global__ __launch_bounds__(256) void k_pt_rank(const uint32_t* __restrict__ fkey,
+                                                 const uint64_t* __restrict__ fval,
+                                                 const uint32_t* __restrict__ fdep,
+                                                 const uint32_t* __restrict__ pcnt,
+                                                 const uint32_t* __restrict__ poff,
+                                                 const uint64_t* __restrict__ useg,
+                                                 const uint32_t* __restrict__ total_p,
+                                                 int64_t max_frags, uint32_t* __restrict__ okey,
+                                                 uint64_t* __restrict__ oval) {
+  const int64_t total = *total_p;
+  if (total > max_frags) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t px = fkey[i];
+    const uint64_t v = fval[i];
+    const uint64_t own = ((uint64_t)fdep[i] << 32) | (uint32_t)v;
+    const uint32_t start = poff[px], n = pcnt[px];
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < n; ++j) rank += useg[start + j] < own ? 1u : 0u;
+    okey[start + rank] = px;
+    oval[start + rank] = v;
+  }
+}
+
 // ----------------------------------------------------------------- blend
-__global__ __launch_bounds__(256) void k_pt_blend(const uint32_t* __restrict__ fkey,
-                                                  const uint64_t* __restrict__ fval,
+// One thread per layer pixel: its list front to back (zero where empty).
+__global__ __launch_bounds__(256) void k_pt_blend(const uint64_t* __restrict__ fval,
+                                                  const uint32_t* __restrict__ pcnt,
+                                                  const uint32_t* __restrict__ poff,
                                                   const uint32_t* __restrict__ total_p,
                                                   int64_t max_frags,
                                                   const uint16_t* __restrict__ feat,
                                                   const float* __restrict__ opacity, int64_t np,
                                                   int64_t pix_total, float4* __restrict__ pyr) {
-  const int64_t cnt = std::min<int64_t>(*total_p, max_frags);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = fkey[i];
-    if (i > 0 && fkey[i - 1] == k) continue;
-    if (k >= (uint64_t)pix_total) continue;
+  const bool over = (int64_t)*total_p > max_frags;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < pix_total;
+       k += (int64_t)gridDim.x * blockDim.x) {
     float T = 1.0f;
     float4 F = make_float4(0, 0, 0, 0);
-    for (int64_t j = i; j < cnt && fkey[j] == k; ++j) {
+    const uint32_t n = over ? 0u : pcnt[k];
+    const uint32_t start = n ? poff[k] : 0u;
+    for (uint32_t j = start; j < start + n; ++j) {
       const uint64_t vv = fval[j];
       const uint32_t id = (uint32_t)vv;
       if (id >= (uint64_t)np) continue;
@@ -461,7 +513,7 @@ __global__ __launch_bounds__(256) void k_pt_blend(const uint32_t* __restrict__ f
 __global__ void k_zero4(float4* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = make_float4(0, 0, 0, 0);
+    p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 }  // namespace vrs
@@ -493,8 +545,8 @@ extern "C" vrs_status vrs_splat_workspace_layout(int64_t np, int n_views, const 
   if (!out || !splat_layout_for(np, n_views, views, crops, n_crops, levels, max_frags, &L))
     return VRS_EINVAL;
   out->frag_count = L.frag_count;
-  out->sorted_keys = L.frags_in_1 ? L.fkey1 : L.fkey0;
-  out->sorted_ids = L.frags_in_1 ? L.fval1 : L.fval0;   // low 32 bits of each 64-bit value
+  out->sorted_keys = L.fkey1;
+  out->sorted_ids = L.fval1;   // low 32 bits of each 64-bit value
   out->pyramid_pixels = L.pix_total;
   return VRS_OK;
 }
@@ -551,8 +603,8 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
     const int64_t cells = (int64_t)n_views * L.gx * L.gy;
     const int64_t most = std::max(std::max(L.pix_total, sel_words), cells);
     hipLaunchKernelGGL(k_pt_prep, dim3((unsigned)std::min<int64_t>(4096, div_up(most, 256))),
-                       dim3(256), 0, st, reinterpret_cast<float4*>(pyramid), L.pix_total,
-                       sel_counter, sel_words, kc, n_views, levels, L.gx, L.gy, grid);
+                       dim3(256), 0, st, at<uint32_t>(ws, L.pcnt), L.pix_total, sel_counter,
+                       sel_words, kc, n_views, levels, L.gx, L.gy, grid);
     VRS_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), sel_lds, st, pos, radius, np, kv,
@@ -560,26 +612,32 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
                      at<uint32_t>(ws, L.cval0), at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt),
                      live, dev_status);
   VRS_LAUNCH_CHECK();
-  bool c1 = false;
-  VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.ckey0), at<uint32_t>(ws, L.cval0),
-                               at<uint32_t>(ws, L.ckey1), at<uint32_t>(ws, L.cval1), live, vn, 32,
-                               at<void>(ws, L.sort_tmp), dev_status, st, &c1));
-  const uint32_t* sorted_c = at<uint32_t>(ws, c1 ? L.cval1 : L.cval0);
-  VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.ccnt), sorted_c, at<uint32_t>(ws, L.foffs),
+  // fragment offsets of the survivors (compaction order), then emission
+  VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.ccnt), nullptr, at<uint32_t>(ws, L.foffs),
                                    frag_count, live, vn, at<void>(ws, L.scan_tmp), dev_status, st));
+  uint32_t* pcnt = at<uint32_t>(ws, L.pcnt);
+  uint32_t* poff = at<uint32_t>(ws, L.poff);
   hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)std::min<int64_t>(8192, div_up(vn, 256))),
-                     dim3(256), 0, st, pos, radius, np, kv, kc, a, sorted_c,
+                     dim3(256), 0, st, pos, radius, np, kv, kc, a, at<uint32_t>(ws, L.ckey0),
                      at<uint32_t>(ws, L.cent), live, at<uint32_t>(ws, L.foffs), frag_count,
-                     max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0), dev_status);
+                     max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
+                     at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot), pcnt, dev_status);
   VRS_LAUNCH_CHECK();
-  bool f1 = false;
-  VRS_HIP_CHECK(radix_sort_u64(at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
-                               at<uint32_t>(ws, L.fkey1), at<uint64_t>(ws, L.fval1), frag_count,
-                               std::max<int64_t>(max_frags, 1), L.key_bits,
-                               at<void>(ws, L.sort_tmp), dev_status, st, &f1));
-  const int bb = (int)std::min<int64_t>(8192, std::max(1, div_up(max_frags, 256)));
-  hipLaunchKernelGGL(k_pt_blend, dim3(bb), dim3(256), 0, st,
-                     at<uint32_t>(ws, f1 ? L.fkey1 : L.fkey0), at<uint64_t>(ws, f1 ? L.fval1 : L.fval0),
+  // per-pixel segments, then each fragment to its place in blend order
+  VRS_HIP_CHECK(exclusive_scan_u32(pcnt, nullptr, poff, nullptr, nullptr, L.pix_total,
+                                   at<void>(ws, L.scan_tmp), dev_status, st));
+  const unsigned fb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, div_up(max_frags, 256)));
+  hipLaunchKernelGGL(k_pt_scatter, dim3(fb), dim3(256), 0, st, at<uint32_t>(ws, L.fkey0),
+                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot),
+                     poff, frag_count, max_frags, at<uint64_t>(ws, L.useg));
+  VRS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_pt_rank, dim3(fb), dim3(256), 0, st, at<uint32_t>(ws, L.fkey0),
+                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), pcnt, poff,
+                     at<uint64_t>(ws, L.useg), frag_count, max_frags, at<uint32_t>(ws, L.fkey1),
+                     at<uint64_t>(ws, L.fval1));
+  VRS_LAUNCH_CHECK();
+  const unsigned pb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, div_up(L.pix_total, 256)));
+  hipLaunchKernelGGL(k_pt_blend, dim3(pb), dim3(256), 0, st, at<uint64_t>(ws, L.fval1), pcnt, poff,
                      frag_count, max_frags, feat, opacity, np, L.pix_total,
                      reinterpret_cast<float4*>(pyramid));
   VRS_LAUNCH_CHECK();
@@ -740,8 +798,7 @@ extern "C" vrs_status vrs_splat_points_backward(const float* pos, const float* r
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int bb = (int)std::min<int64_t>(8192, std::max(1, div_up(max_frags, 256)));
   hipLaunchKernelGGL(k_pt_blend_bwd, dim3(bb), dim3(256), 0, st,
-                     at<uint32_t>(ws, L.frags_in_1 ? L.fkey1 : L.fkey0),
-                     at<uint64_t>(ws, L.frags_in_1 ? L.fval1 : L.fval0),
+                     at<uint32_t>(ws, L.fkey1), at<uint64_t>(ws, L.fval1),
                      at<uint32_t>(ws, L.frag_count), max_frags, pos, radius, feat, opacity, np, kv,
                      kc, a, L.pix_total, reinterpret_cast<const float4*>(d_pyramid), d_feat, d_pos,
                      d_radius, d_opacity);
