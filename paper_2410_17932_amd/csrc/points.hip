@@ -3,11 +3,11 @@
 // layers and all crops).
 //
 // Fragments go straight to per-pixel segments: emission counts each layer
-// pixel's fragments (an atomic per fragment gives its slot), a scan turns
-// the counts into segment offsets, and each fragment's place in its segment
-// is its rank by (float32 bits of t.z, point index) among the segment's
-// fragments -- so the lists come out in blend order with no global sort,
-// and deterministic (the slots only place fragments in a scratch copy).
+// pixel's fragments, a scan turns the counts into segment offsets, and each
+// fragment's place in its segment is its rank by (float32 bits of t.z,
+// point index) among the segment's fragments -- so the lists come out in
+// blend order with no global sort, and deterministically (atomics only
+// place fragments in a scratch copy of each segment).
 //   k_pt_prep      per-pixel counters and selection flags zeroed, crop grid
 //   k_pt_select    one thread per point, points read once for all crops:
 //                  projection, layer, crop footprints, then the depth cull;
@@ -16,10 +16,11 @@
 //                  order
 //   scan           fragment counts of the survivors -> offsets
 //   k_pt_emit      one thread per survivor writes its fragments (layer
-//                  pixel, weight | point index, depth key, slot in pixel)
+//                  pixel, weight | point index, depth key) and counts them
+//                  per pixel
 //   scan           per-pixel counts -> segment offsets
 //   k_pt_scatter   (depth key, point index) of each fragment into its
-//                  pixel's segment, at its slot
+//                  pixel's segment, at a free place
 //   k_pt_rank      each fragment's rank in its segment -> its final place
 //   k_pt_blend     one thread per layer pixel walks its list front to back
 #include <hip/hip_fp16.h>
@@ -31,10 +32,10 @@ namespace vrs {
 
 struct SplatWs {
   size_t cent, ccnt, ckey0, cval0, live, foffs, frag_count,
-      fkey0, fval0, fdep, fslot,   // fragments in emission order
+      fkey0, fval0, fdep,          // fragments in emission order
       useg,                        // (depth key, point index) per segment place
       fkey1, fval1,                // fragments in blend order
-      pcnt, poff,                  // per layer pixel: fragment count, segment offset
+      pcnt, poff,                  // per layer pixel: fragment count, segment offsets [P + 1]
       sel_tmp, grid, scan_tmp, total;
   int gx, gy;   // crop-lookup grid cells per view row / column
   int64_t vn, pix_total;
@@ -84,12 +85,11 @@ static bool splat_layout(int64_t np, int nv, int W, int H, const vrs_crop* crops
   L->fkey0 = c.take(mf * 4);
   L->fval0 = c.take(mf * 8);
   L->fdep = c.take(mf * 4);
-  L->fslot = c.take(mf * 4);
   L->useg = c.take(mf * 8);
   L->fkey1 = c.take(mf * 4);
   L->fval1 = c.take(mf * 8);
   L->pcnt = c.take(pt * 4);
-  L->poff = c.take(pt * 4);
+  L->poff = c.take((pt + 1) * 4);
   L->sel_tmp = c.take(sel_tmp_bytes(np));
   L->grid = c.take((size_t)nv * L->gx * L->gy * 4);
   L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(pt)));
@@ -372,16 +372,62 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
 }
 
 // ------------------------------------------------------------------ emit
+// counts[px] += 1 for every active lane.  Lanes of a wave often hold the
+// same pixel (neighbouring points on a coarse layer), and atomics of one
+// instruction to one address serialise: while the first remaining lane's
+// pixel is shared, one lane adds for all that share it; the rest add
+// directly.
+__device__ inline void count_pixel(uint32_t* __restrict__ counts, uint32_t px) {
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(true);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const uint32_t lpx = (uint32_t)__shfl((int)px, leader, 64);
+    const uint64_t same = __ballot(px == lpx) & todo;
+    if (__popcll(same) == 1) break;   // uniform
+    if (lane == leader) atomicAdd(&counts[lpx], (uint32_t)__popcll(same));
+    todo &= ~same;
+  }
+  if ((todo >> lane) & 1ull) atomicAdd(&counts[px], 1u);
+}
+
+// counts[px] -= 1 for every active lane, returning a distinct slot in
+// [new count, old count) per lane (grouped like count_pixel).
+__device__ inline uint32_t take_slot(uint32_t* __restrict__ counts, uint32_t px) {
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(true);
+  uint32_t slot = 0;
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const uint32_t lpx = (uint32_t)__shfl((int)px, leader, 64);
+    const uint64_t same = __ballot(px == lpx) & todo;
+    const uint32_t k = (uint32_t)__popcll(same);
+    if (k == 1) break;   // uniform
+    uint32_t old = 0;
+    if (lane == leader) old = atomicSub(&counts[lpx], k);
+    old = (uint32_t)__shfl((int)old, leader, 64);
+    if ((same >> lane) & 1ull) {
+      const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+      slot = old - 1u - r;
+    }
+    todo &= ~same;
+  }
+  if ((todo >> lane) & 1ull) slot = atomicSub(&counts[px], 1u) - 1u;
+  return slot;
+}
+
 // One thread per survivor (compaction order): its fragments at its offset,
-// each with its layer pixel, weight | point index, depth key and slot in
-// the pixel's segment (the pixel's count before this fragment).
+// each with its layer pixel, weight | point index and depth key; the
+// pixel's fragment count goes up by one (an atomic whose result is not
+// waited for).
 __global__ __launch_bounds__(256) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const uint32_t* __restrict__ ckey,
     const uint32_t* __restrict__ cent, const uint32_t* __restrict__ live_p,
     const uint32_t* __restrict__ foffs, const uint32_t* __restrict__ total_p, int64_t max_frags,
     uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval, uint32_t* __restrict__ fdep,
-    uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt, int32_t* status) {
+    uint32_t* __restrict__ pcnt, int32_t* status) {
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
@@ -422,7 +468,7 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               fkey[o] = px;
               fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
               fdep[o] = dz;
-              fslot[o] = atomicAdd(&pcnt[px], 1u);
+              count_pixel(pcnt, px);
               ++o;
             }
         }
@@ -432,20 +478,23 @@ __global__ __launch_bounds__(256) void k_pt_emit(
   }
 }
 
-// Each fragment's (depth key, point index) into its pixel's segment, at its
-// slot.
+// Each fragment's (depth key, point index) into its pixel's segment, at a
+// free place (the pixel's count, taken down by one per fragment, ends at 0).
 __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__ fkey,
                                                     const uint64_t* __restrict__ fval,
                                                     const uint32_t* __restrict__ fdep,
-                                                    const uint32_t* __restrict__ fslot,
+                                                    uint32_t* __restrict__ pcnt,
                                                     const uint32_t* __restrict__ poff,
                                                     const uint32_t* __restrict__ total_p,
                                                     int64_t max_frags, uint64_t* __restrict__ useg) {
   const int64_t total = *total_p;
   if (total > max_frags) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x)
-    useg[poff[fkey[i]] + fslot[i]] = ((uint64_t)fdep[i] << 32) | (uint32_t)fval[i];
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t px = fkey[i];
+    const uint32_t slot = take_slot(pcnt, px);
+    useg[poff[px] + slot] = ((uint64_t)fdep[i] << 32) | (uint32_t)fval[i];
+  }
 }
 
 // A fragment's place in blend order: its segment's offset plus the number of
@@ -454,7 +503,6 @@ __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__
 __global__ __launch_bounds__(256) void k_pt_rank(const uint32_t* __restrict__ fkey,
                                                  const uint64_t* __restrict__ fval,
                                                  const uint32_t* __restrict__ fdep,
-                                                 const uint32_t* __restrict__ pcnt,
                                                  const uint32_t* __restrict__ poff,
                                                  const uint64_t* __restrict__ useg,
                                                  const uint32_t* __restrict__ total_p,
@@ -467,7 +515,7 @@ __global__ __launch_bounds__(256) void k_pt_rank(const uint32_t* __restrict__ fk
     const uint32_t px = fkey[i];
     const uint64_t v = fval[i];
     const uint64_t own = ((uint64_t)fdep[i] << 32) | (uint32_t)v;
-    const uint32_t start = poff[px], n = pcnt[px];
+    const uint32_t start = poff[px], n = poff[px + 1] - start;
     uint32_t rank = 0;
     for (uint32_t j = 0; j < n; ++j) rank += useg[start + j] < own ? 1u : 0u;
     okey[start + rank] = px;
@@ -478,7 +526,6 @@ __global__ __launch_bounds__(256) void k_pt_rank(const uint32_t* __restrict__ fk
 // ----------------------------------------------------------------- blend
 // One thread per layer pixel: its list front to back (zero where empty).
 __global__ __launch_bounds__(256) void k_pt_blend(const uint64_t* __restrict__ fval,
-                                                  const uint32_t* __restrict__ pcnt,
                                                   const uint32_t* __restrict__ poff,
                                                   const uint32_t* __restrict__ total_p,
                                                   int64_t max_frags,
@@ -490,8 +537,7 @@ __global__ __launch_bounds__(256) void k_pt_blend(const uint64_t* __restrict__ f
        k += (int64_t)gridDim.x * blockDim.x) {
     float T = 1.0f;
     float4 F = make_float4(0, 0, 0, 0);
-    const uint32_t n = over ? 0u : pcnt[k];
-    const uint32_t start = n ? poff[k] : 0u;
+    const uint32_t start = over ? 0u : poff[k], n = over ? 0u : poff[k + 1] - start;
     for (uint32_t j = start; j < start + n; ++j) {
       const uint64_t vv = fval[j];
       const uint32_t id = (uint32_t)vv;
@@ -621,23 +667,23 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
                      dim3(256), 0, st, pos, radius, np, kv, kc, a, at<uint32_t>(ws, L.ckey0),
                      at<uint32_t>(ws, L.cent), live, at<uint32_t>(ws, L.foffs), frag_count,
                      max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
-                     at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot), pcnt, dev_status);
+                     at<uint32_t>(ws, L.fdep), pcnt, dev_status);
   VRS_LAUNCH_CHECK();
   // per-pixel segments, then each fragment to its place in blend order
-  VRS_HIP_CHECK(exclusive_scan_u32(pcnt, nullptr, poff, nullptr, nullptr, L.pix_total,
+  VRS_HIP_CHECK(exclusive_scan_u32(pcnt, nullptr, poff, poff + L.pix_total, nullptr, L.pix_total,
                                    at<void>(ws, L.scan_tmp), dev_status, st));
   const unsigned fb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, div_up(max_frags, 256)));
   hipLaunchKernelGGL(k_pt_scatter, dim3(fb), dim3(256), 0, st, at<uint32_t>(ws, L.fkey0),
-                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot),
-                     poff, frag_count, max_frags, at<uint64_t>(ws, L.useg));
+                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), pcnt, poff, frag_count,
+                     max_frags, at<uint64_t>(ws, L.useg));
   VRS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_pt_rank, dim3(fb), dim3(256), 0, st, at<uint32_t>(ws, L.fkey0),
-                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), pcnt, poff,
+                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), poff,
                      at<uint64_t>(ws, L.useg), frag_count, max_frags, at<uint32_t>(ws, L.fkey1),
                      at<uint64_t>(ws, L.fval1));
   VRS_LAUNCH_CHECK();
   const unsigned pb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, div_up(L.pix_total, 256)));
-  hipLaunchKernelGGL(k_pt_blend, dim3(pb), dim3(256), 0, st, at<uint64_t>(ws, L.fval1), pcnt, poff,
+  hipLaunchKernelGGL(k_pt_blend, dim3(pb), dim3(256), 0, st, at<uint64_t>(ws, L.fval1), poff,
                      frag_count, max_frags, feat, opacity, np, L.pix_total,
                      reinterpret_cast<float4*>(pyramid));
   VRS_LAUNCH_CHECK();

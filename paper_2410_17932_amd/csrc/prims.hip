@@ -36,7 +36,7 @@ __global__ void k_fill(uint32_t* p, uint32_t v, int64_t n) {
 }
 
 // ------------------------------------------------------------------ scan
-constexpr int kScanBlock = 256, kScanItems = 8, kScanTile = kScanBlock * kScanItems;
+constexpr int kScanBlock = 256, kScanItems = 16, kScanTile = kScanBlock * kScanItems;
 
 // Clears the partition counter, the look-back flags the scan will use and
 // the total (n may turn out to be 0 on the device: the total is then 0).
@@ -52,9 +52,9 @@ __global__ void k_scan_clear(uint32_t* counter, uint64_t* flags, uint32_t* total
   for (; i < parts; i += (int64_t)gridDim.x * blockDim.x) flags[i] = 0;
 }
 
-// Thread t of a partition owns items [8t, 8t + 8) of it; when the input is
-// read directly (no index) and 16-byte aligned, they come in as two 16-byte
-// loads.
+// Thread t of a partition owns kScanItems consecutive items of it; when the
+// input is read directly (no index) and 16-byte aligned, they come in as
+// 16-byte loads.
 __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict__ in,
                                                       const uint32_t* __restrict__ idx,
                                                       uint32_t* __restrict__ out,
@@ -76,10 +76,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
   const int64_t i0 = base + (int64_t)tid * kScanItems;
   uint32_t x[kScanItems];
   if (!idx && i0 + kScanItems <= n && (reinterpret_cast<uintptr_t>(in) & 15) == 0) {
-    const uint4 a = *reinterpret_cast<const uint4*>(in + i0);
-    const uint4 b = *reinterpret_cast<const uint4*>(in + i0 + 4);
-    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q) {
+      const uint4 a = *reinterpret_cast<const uint4*>(in + i0 + 4 * q);
+      x[4 * q] = a.x; x[4 * q + 1] = a.y; x[4 * q + 2] = a.z; x[4 * q + 3] = a.w;
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
@@ -114,9 +115,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
   __syncthreads();
   const uint32_t off = s_prefix + woff + (incl - sum);
   if (i0 + kScanItems <= n && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
-    *reinterpret_cast<uint4*>(out + i0) = make_uint4(off + v[0], off + v[1], off + v[2], off + v[3]);
-    *reinterpret_cast<uint4*>(out + i0 + 4) =
-        make_uint4(off + v[4], off + v[5], off + v[6], off + v[7]);
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q)
+      *reinterpret_cast<uint4*>(out + i0 + 4 * q) =
+          make_uint4(off + v[4 * q], off + v[4 * q + 1], off + v[4 * q + 2], off + v[4 * q + 3]);
   } else {
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j)
