@@ -77,6 +77,12 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* __re
       if (a.view[k] != v) continue;
       const int lx = x - a.x0[k], ly = y - a.y0[k], S = a.S[k];
       if (lx < 0 || ly < 0 || lx >= S || ly >= S) continue;
+      {
+        // outside the crop's inscribed circle the mask is 0 in both modes
+        const float dx = (float)(a.x0[k] + lx) + 0.5f - a.gx[k];
+        const float dy = (float)(a.y0[k] + ly) + 0.5f - a.gy[k];
+        if (!(sqrtf(dx * dx + dy * dy) < 0.5f * (float)S)) continue;
+      }
       const float* Fk = F + a.fbase[k];
       float u, gx, gy;
       const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy);
@@ -123,6 +129,13 @@ __global__ __launch_bounds__(256) void k_composite4(CompArgs a, const float* __r
       for (int j = 0; j < 4; ++j) {
         const int lx = x + j - a.x0[k];
         if (lx < 0 || lx >= S) continue;
+        {
+          // outside the crop's inscribed circle the mask is 0 in both modes
+          // (the same operations as blend_mask): the pixel keeps its value
+          const float dx = (float)(a.x0[k] + lx) + 0.5f - a.gx[k];
+          const float dy = (float)(a.y0[k] + ly) + 0.5f - a.gy[k];
+          if (!(sqrtf(dx * dx + dy * dy) < 0.5f * (float)S)) continue;
+        }
         float u, gx, gy;
         const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy);
         const long long fo = (long long)ly * S + lx;

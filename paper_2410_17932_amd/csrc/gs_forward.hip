@@ -595,11 +595,12 @@ __device__ inline uint64_t wave_uniform_u64(uint64_t v) {
 // over the box dx in [X0, X1], dy in [Y0, Y1]: 0 if the box holds the
 // origin, else the least of the four edge minima (the minimiser of a convex
 // quadratic over a box lies on its boundary; on an edge it is the clamped
-// stationary point).
-__device__ inline float box_min_quadratic(float ga, float gb, float gc, float X0, float X1,
-                                          float Y0, float Y1) {
+// stationary point).  ia, ic = 1 / (2 ga), 1 / (2 gc): a stationary point off
+// by a relative rounding error changes the edge minimum by its square, far
+// inside the caller's margin.
+__device__ inline float box_min_quadratic(float ga, float gb, float gc, float ia, float ic,
+                                          float X0, float X1, float Y0, float Y1) {
   if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
-  const float ia = 0.5f / ga, ic = 0.5f / gc;
   float m = 3.0e38f;
   float Xe[2] = {X0, X1}, Ye[2] = {Y0, Y1};
 #pragma unroll
@@ -672,6 +673,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   const uint2 rg = ranges[tglob];
   const uint32_t begin = rg.x, end = rg.y;
   const float aclamp = o.aclamp, amin = o.amin, tmin = o.tmin;
+  const float inv_amin = 1.0f / amin;   // infinite for alpha_min = 0: never out of reach
   const float xc = (float)px + 0.5f;
   float yc[PPT];
 #pragma unroll
@@ -692,7 +694,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
     // alpha_min); thr carries a margin far above the rounding of q so that a
     // sub-tile is declared out of reach only where every pixel's own test
     // would fail
-    float cx = 0.0f, cy = 0.0f, ga = 1.0f, gb = 0.0f, gc = 1.0f, thr = -1.0f;
+    float cx = 0.0f, cy = 0.0f, ga = 1.0f, gb = 0.0f, gc = 1.0f, ia = 0.5f, ic = 0.5f, thr = -1.0f;
     if (has) {
       const uint32_t id = ids[jr];
       const int64_t e = (int64_t)v * n + (id < (uint64_t)n ? id : 0);
@@ -706,7 +708,10 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
       x1 = (int)(hi & 0xffffu); y1 = (int)(hi >> 16);
       cx = a.x; cy = a.y;
       ga = -a.z; gb = -a.w; gc = -b.x;
-      thr = b.y >= amin ? log2f(b.y / amin) * 1.001f + 1.0e-3f : -1.0f;
+      ia = 0.5f * __builtin_amdgcn_rcpf(ga);
+      ic = 0.5f * __builtin_amdgcn_rcpf(gc);
+      // (hardware log2 and reciprocal: their error is far inside the margin)
+      thr = b.y >= amin ? __builtin_amdgcn_logf(b.y * inv_amin) * 1.001f + 1.0e-3f : -1.0f;
       if (!(ga > 0.0f && gc > 0.0f)) thr = 3.0e38f;   // never declared out of reach
     }
 #pragma unroll
@@ -720,7 +725,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
       bool full = false;
       if (hit) {
         // d = centre - pixel centre over the pixel centres of the overlap
-        const float g = box_min_quadratic(ga, gb, gc, cx - ((float)xhi + 0.5f),
+        const float g = box_min_quadratic(ga, gb, gc, ia, ic, cx - ((float)xhi + 0.5f),
                                           cx - ((float)xlo + 0.5f), cy - ((float)yhi + 0.5f),
                                           cy - ((float)ylo + 0.5f));
         full = !(g > thr);
