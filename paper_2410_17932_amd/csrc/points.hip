@@ -517,6 +517,7 @@ __global__ __launch_bounds__(256) void k_pt_rank(const uint32_t* __restrict__ fk
     const uint64_t own = ((uint64_t)fdep[i] << 32) | (uint32_t)v;
     const uint32_t start = poff[px], n = poff[px + 1] - start;
     uint32_t rank = 0;
+#pragma unroll 8
     for (uint32_t j = 0; j < n; ++j) rank += useg[start + j] < own ? 1u : 0u;
     okey[start + rank] = px;
     oval[start + rank] = v;
@@ -538,19 +539,36 @@ __global__ __launch_bounds__(256) void k_pt_blend(const uint64_t* __restrict__ f
     float T = 1.0f;
     float4 F = make_float4(0, 0, 0, 0);
     const uint32_t start = over ? 0u : poff[k], n = over ? 0u : poff[k + 1] - start;
-    for (uint32_t j = start; j < start + n; ++j) {
-      const uint64_t vv = fval[j];
-      const uint32_t id = (uint32_t)vv;
-      if (id >= (uint64_t)np) continue;
-      const float w = __uint_as_float((uint32_t)(vv >> 32));
-      const float al = opacity ? w * opacity[id] : w;
-      const uint2 hb = *reinterpret_cast<const uint2*>(feat + (int64_t)id * 4);
-      const float aT = al * T;
-      F.x += h2f((uint16_t)(hb.x & 0xffffu)) * aT;
-      F.y += h2f((uint16_t)(hb.x >> 16)) * aT;
-      F.z += h2f((uint16_t)(hb.y & 0xffffu)) * aT;
-      F.w += h2f((uint16_t)(hb.y >> 16)) * aT;
-      T = T * (1.0f - al);
+    // fragments in groups of kPtBatch, every group's loads in flight before
+    // its (sequential) compositing: long lists are otherwise one load
+    // latency per fragment
+    constexpr int kPtBatch = 8;
+    for (uint32_t j0 = 0; j0 < n; j0 += kPtBatch) {
+      uint64_t vv[kPtBatch];
+      float op[kPtBatch];
+      uint2 hb[kPtBatch];
+#pragma unroll
+      for (int q = 0; q < kPtBatch; ++q)
+        vv[q] = j0 + q < n ? fval[start + j0 + q] : ~0ull;
+#pragma unroll
+      for (int q = 0; q < kPtBatch; ++q) {
+        const uint32_t id = (uint32_t)vv[q];
+        const bool ok = id < (uint64_t)np;
+        op[q] = ok && opacity ? opacity[id] : 1.0f;
+        hb[q] = ok ? *reinterpret_cast<const uint2*>(feat + (int64_t)id * 4) : make_uint2(0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < kPtBatch; ++q) {
+        if (j0 + q >= n || (uint32_t)vv[q] >= (uint64_t)np) continue;
+        const float w = __uint_as_float((uint32_t)(vv[q] >> 32));
+        const float al = opacity ? w * op[q] : w;
+        const float aT = al * T;
+        F.x += h2f((uint16_t)(hb[q].x & 0xffffu)) * aT;
+        F.y += h2f((uint16_t)(hb[q].x >> 16)) * aT;
+        F.z += h2f((uint16_t)(hb[q].y & 0xffffu)) * aT;
+        F.w += h2f((uint16_t)(hb[q].y >> 16)) * aT;
+        T = T * (1.0f - al);
+      }
     }
     pyr[k] = F;
   }
