@@ -372,49 +372,35 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
 }
 
 // ------------------------------------------------------------------ emit
-// counts[px] += 1 for every active lane.  Lanes of a wave often hold the
-// same pixel (neighbouring points on a coarse layer), and atomics of one
-// instruction to one address serialise: while the first remaining lane's
-// pixel is shared, one lane adds for all that share it; the rest add
-// directly.
-__device__ inline void count_pixel(uint32_t* __restrict__ counts, uint32_t px) {
-  const int lane = threadIdx.x & 63;
-  uint64_t todo = __ballot(true);
-  while (todo) {
-    const int leader = __builtin_ctzll(todo);
-    const uint32_t lpx = (uint32_t)__shfl((int)px, leader, 64);
-    const uint64_t same = __ballot(px == lpx) & todo;
-    if (__popcll(same) == 1) break;   // uniform
-    if (lane == leader) atomicAdd(&counts[lpx], (uint32_t)__popcll(same));
-    todo &= ~same;
+// Per-workgroup pixel table in LDS: open addressing with a short linear
+// probe.  Device-wide atomics to one address serialise and are slow on
+// their own, so fragment counts (and segment places) are gathered per
+// workgroup first and the table's entries go out as one atomic each; a
+// fragment whose probe finds no place falls back to its own atomic.
+constexpr int kPixHash = 2048, kPixProbe = 8;
+constexpr uint32_t kPixEmpty = 0xffffffffu;
+struct PixHash {
+  uint32_t key[kPixHash], cnt[kPixHash];
+};
+__device__ inline void pix_hash_clear(PixHash& h) {
+  for (int i = threadIdx.x; i < kPixHash; i += blockDim.x) {
+    h.key[i] = kPixEmpty;
+    h.cnt[i] = 0u;
   }
-  if ((todo >> lane) & 1ull) atomicAdd(&counts[px], 1u);
 }
-
-// counts[px] -= 1 for every active lane, returning a distinct slot in
-// [new count, old count) per lane (grouped like count_pixel).
-__device__ inline uint32_t take_slot(uint32_t* __restrict__ counts, uint32_t px) {
-  const int lane = threadIdx.x & 63;
-  uint64_t todo = __ballot(true);
-  uint32_t slot = 0;
-  while (todo) {
-    const int leader = __builtin_ctzll(todo);
-    const uint32_t lpx = (uint32_t)__shfl((int)px, leader, 64);
-    const uint64_t same = __ballot(px == lpx) & todo;
-    const uint32_t k = (uint32_t)__popcll(same);
-    if (k == 1) break;   // uniform
-    uint32_t old = 0;
-    if (lane == leader) old = atomicSub(&counts[lpx], k);
-    old = (uint32_t)__shfl((int)old, leader, 64);
-    if ((same >> lane) & 1ull) {
-      const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
-      slot = old - 1u - r;
+// one more fragment of pixel px: its table place (or -1) and its rank
+// among the table's fragments of px
+__device__ inline int pix_hash_add(PixHash& h, uint32_t px, uint32_t& rank) {
+  uint32_t s = (px * 2654435761u) >> (32 - 11);   // 11 bits: kPixHash places
+  for (int q = 0; q < kPixProbe; ++q) {
+    const uint32_t k = atomicCAS(&h.key[s], kPixEmpty, px);
+    if (k == kPixEmpty || k == px) {
+      rank = atomicAdd(&h.cnt[s], 1u);
+      return (int)s;
     }
-    todo &= ~same;
+    s = (s + 1) & (kPixHash - 1);
   }
-  if ((todo >> lane) & 1ull) slot = atomicSub(&counts[px], 1u) - 1u;
-  return slot;
+  return -1;
 }
 
 // One thread per survivor (compaction order): its fragments at its offset,
@@ -428,10 +414,13 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     const uint32_t* __restrict__ foffs, const uint32_t* __restrict__ total_p, int64_t max_frags,
     uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval, uint32_t* __restrict__ fdep,
     uint32_t* __restrict__ pcnt, int32_t* status) {
+  __shared__ PixHash h;
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
-  if (total > max_frags) return;
+  if (total > max_frags || (int64_t)blockIdx.x * blockDim.x >= live) return;   // uniform
+  pix_hash_clear(h);
+  __syncthreads();
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
        j += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t e = cent[j];
@@ -468,7 +457,8 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               fkey[o] = px;
               fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
               fdep[o] = dz;
-              count_pixel(pcnt, px);
+              uint32_t r;
+              if (pix_hash_add(h, px, r) < 0) atomicAdd(&pcnt[px], 1u);
               ++o;
             }
         }
@@ -476,10 +466,16 @@ __global__ __launch_bounds__(256) void k_pt_emit(
       }
     }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kPixHash; i += blockDim.x)
+    if (h.key[i] != kPixEmpty) atomicAdd(&pcnt[h.key[i]], h.cnt[i]);
 }
 
 // Each fragment's (depth key, point index) into its pixel's segment, at a
-// free place (the pixel's count, taken down by one per fragment, ends at 0).
+// free place: per workgroup the fragments are grouped by pixel in the LDS
+// table, each group takes its places with one atomic (the pixel's count,
+// taken down, ends at 0), and a fragment's place is the group's start plus
+// its rank in the group.
 __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__ fkey,
                                                     const uint64_t* __restrict__ fval,
                                                     const uint32_t* __restrict__ fdep,
@@ -487,13 +483,32 @@ __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ poff,
                                                     const uint32_t* __restrict__ total_p,
                                                     int64_t max_frags, uint64_t* __restrict__ useg) {
+  __shared__ PixHash h;
+  __shared__ uint32_t s_base[kPixHash];
   const int64_t total = *total_p;
   if (total > max_frags) return;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t px = fkey[i];
-    const uint32_t slot = take_slot(pcnt, px);
-    useg[poff[px] + slot] = ((uint64_t)fdep[i] << 32) | (uint32_t)fval[i];
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < total;
+       i0 += (int64_t)gridDim.x * blockDim.x) {   // uniform over the workgroup
+    pix_hash_clear(h);
+    __syncthreads();
+    const int64_t i = i0 + threadIdx.x;
+    const bool in = i < total;
+    uint32_t px = 0, r = 0, slot = 0;
+    int hs = -1;
+    if (in) {
+      px = fkey[i];
+      hs = pix_hash_add(h, px, r);
+      if (hs < 0) slot = atomicSub(&pcnt[px], 1u) - 1u;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kPixHash; e += blockDim.x)
+      if (h.key[e] != kPixEmpty) s_base[e] = atomicSub(&pcnt[h.key[e]], h.cnt[e]);
+    __syncthreads();
+    if (in) {
+      if (hs >= 0) slot = s_base[hs] - 1u - r;
+      useg[poff[px] + slot] = ((uint64_t)fdep[i] << 32) | (uint32_t)fval[i];
+    }
+    __syncthreads();   // the table is cleared for the next round
   }
 }
 
