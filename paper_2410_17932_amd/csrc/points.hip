@@ -377,31 +377,34 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
 // their own, so fragment counts (and segment places) are gathered per
 // workgroup first and the table's entries go out as one atomic each; a
 // fragment whose probe finds no place falls back to its own atomic.
-constexpr int kPixHash = 2048, kPixProbe = 8;
+constexpr int kPixProbe = 8;
 constexpr uint32_t kPixEmpty = 0xffffffffu;
+template <int N>   // places, a power of two
 struct PixHash {
-  uint32_t key[kPixHash], cnt[kPixHash];
-};
-__device__ inline void pix_hash_clear(PixHash& h) {
-  for (int i = threadIdx.x; i < kPixHash; i += blockDim.x) {
-    h.key[i] = kPixEmpty;
-    h.cnt[i] = 0u;
-  }
-}
-// one more fragment of pixel px: its table place (or -1) and its rank
-// among the table's fragments of px
-__device__ inline int pix_hash_add(PixHash& h, uint32_t px, uint32_t& rank) {
-  uint32_t s = (px * 2654435761u) >> (32 - 11);   // 11 bits: kPixHash places
-  for (int q = 0; q < kPixProbe; ++q) {
-    const uint32_t k = atomicCAS(&h.key[s], kPixEmpty, px);
-    if (k == kPixEmpty || k == px) {
-      rank = atomicAdd(&h.cnt[s], 1u);
-      return (int)s;
+  static constexpr int kBits = N == 2048 ? 11 : (N == 1024 ? 10 : 9);
+  static_assert((1 << kBits) == N, "PixHash size");
+  uint32_t key[N], cnt[N];
+  __device__ void clear() {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      key[i] = kPixEmpty;
+      cnt[i] = 0u;
     }
-    s = (s + 1) & (kPixHash - 1);
   }
-  return -1;
-}
+  // one more fragment of pixel px: its table place (or -1) and its rank
+  // among the table's fragments of px
+  __device__ int add(uint32_t px, uint32_t& rank) {
+    uint32_t s = (px * 2654435761u) >> (32 - kBits);
+    for (int q = 0; q < kPixProbe; ++q) {
+      const uint32_t k = atomicCAS(&key[s], kPixEmpty, px);
+      if (k == kPixEmpty || k == px) {
+        rank = atomicAdd(&cnt[s], 1u);
+        return (int)s;
+      }
+      s = (s + 1) & (N - 1);
+    }
+    return -1;
+  }
+};
 
 // One thread per survivor (compaction order): its fragments at its offset,
 // each with its layer pixel, weight | point index and depth key; the
@@ -414,12 +417,12 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     const uint32_t* __restrict__ foffs, const uint32_t* __restrict__ total_p, int64_t max_frags,
     uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval, uint32_t* __restrict__ fdep,
     uint32_t* __restrict__ pcnt, int32_t* status) {
-  __shared__ PixHash h;
+  __shared__ PixHash<2048> h;   // a workgroup emits ~2000 fragments
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
   if (total > max_frags || (int64_t)blockIdx.x * blockDim.x >= live) return;   // uniform
-  pix_hash_clear(h);
+  h.clear();
   __syncthreads();
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
        j += (int64_t)gridDim.x * blockDim.x) {
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
               fdep[o] = dz;
               uint32_t r;
-              if (pix_hash_add(h, px, r) < 0) atomicAdd(&pcnt[px], 1u);
+              if (h.add(px, r) < 0) atomicAdd(&pcnt[px], 1u);
               ++o;
             }
         }
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kPixHash; i += blockDim.x)
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x)
     if (h.key[i] != kPixEmpty) atomicAdd(&pcnt[h.key[i]], h.cnt[i]);
 }
 
@@ -483,13 +486,13 @@ __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ poff,
                                                     const uint32_t* __restrict__ total_p,
                                                     int64_t max_frags, uint64_t* __restrict__ useg) {
-  __shared__ PixHash h;
-  __shared__ uint32_t s_base[kPixHash];
+  __shared__ PixHash<512> h;   // a round has 256 fragments
+  __shared__ uint32_t s_base[512];
   const int64_t total = *total_p;
   if (total > max_frags) return;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < total;
        i0 += (int64_t)gridDim.x * blockDim.x) {   // uniform over the workgroup
-    pix_hash_clear(h);
+    h.clear();
     __syncthreads();
     const int64_t i = i0 + threadIdx.x;
     const bool in = i < total;
@@ -497,11 +500,11 @@ __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__
     int hs = -1;
     if (in) {
       px = fkey[i];
-      hs = pix_hash_add(h, px, r);
+      hs = h.add(px, r);
       if (hs < 0) slot = atomicSub(&pcnt[px], 1u) - 1u;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kPixHash; e += blockDim.x)
+    for (int e = threadIdx.x; e < 512; e += blockDim.x)
       if (h.key[e] != kPixEmpty) s_base[e] = atomicSub(&pcnt[h.key[e]], h.cnt[e]);
     __syncthreads();
     if (in) {
