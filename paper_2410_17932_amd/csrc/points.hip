@@ -7,13 +7,14 @@
 // fragment's place in its segment is its rank by (float32 bits of t.z,
 // point index) among the segment's fragments -- so the lists come out in
 // blend order with no global sort, and deterministically (atomics only
-// place fragments in a scratch copy of each segment).
-//   k_pt_prep      per-pixel counters and selection flags zeroed, crop grid
+// place survivors and fragments in scratch lists whose order the ranking
+// removes).
+//   k_pt_prep      per-pixel counters and the survivor count zeroed, crop
+//                  grid
 //   k_pt_select    one thread per point, points read once for all crops:
 //                  projection, layer, crop footprints, then the depth cull;
 //                  survivors (depth key, entry, fragment count) compacted in
-//                  the same pass (decoupled look-back), per view in point
-//                  order
+//                  the same pass, one atomic per workgroup
 //   scan           fragment counts of the survivors -> offsets
 //   k_pt_emit      one thread per survivor writes its fragments (layer
 //                  pixel, weight | point index, depth key) and counts them
@@ -25,29 +26,22 @@
 //   k_pt_blend     one thread per layer pixel walks its list front to back
 #include <hip/hip_fp16.h>
 
-#include "lookback.h"
 #include "pt_device.h"
 
 namespace vrs {
 
 struct SplatWs {
-  size_t cent, ccnt, ckey0, cval0, live, foffs, frag_count,
+  size_t cent, ccnt, ckey0, live, foffs, frag_count,
       fkey0, fval0, fdep,          // fragments in emission order
       useg,                        // (depth key, point index) per segment place
       fkey1, fval1,                // fragments in blend order
       pcnt, poff,                  // per layer pixel: fragment count, segment offsets [P + 1]
-      sel_tmp, grid, scan_tmp, total;
+      grid, scan_tmp, total;
   int gx, gy;   // crop-lookup grid cells per view row / column
   int64_t vn, pix_total;
 };
 
 constexpr int kSelBlock = 256;
-
-// look-back partition counter (256 bytes) + one status word per partition
-// (partitions of kSelPart points; one word per 256 points bounds them)
-static size_t sel_tmp_bytes(int64_t np) {
-  return 256 + (size_t)std::max<int64_t>(1, div_up(np, kSelBlock)) * 8;
-}
 
 static int64_t pyramid_pixels(const vrs_crop* crops, int n_crops, int levels) {
   int64_t s = 0;
@@ -78,7 +72,6 @@ static bool splat_layout(int64_t np, int nv, int W, int H, const vrs_crop* crops
   L->cent = c.take(vn * 4);
   L->ccnt = c.take(vn * 4);
   L->ckey0 = c.take(vn * 4);
-  L->cval0 = c.take(vn * 4);
   L->live = c.take(4);
   L->foffs = c.take(vn * 4);
   L->frag_count = c.take(4);
@@ -90,7 +83,6 @@ static bool splat_layout(int64_t np, int nv, int W, int H, const vrs_crop* crops
   L->fval1 = c.take(mf * 8);
   L->pcnt = c.take(pt * 4);
   L->poff = c.take((pt + 1) * 4);
-  L->sel_tmp = c.take(sel_tmp_bytes(np));
   L->grid = c.take((size_t)nv * L->gx * L->gy * 4);
   L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(pt)));
   L->total = c.off;
@@ -163,17 +155,16 @@ __device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx,
 }
 
 // Per-call set-up in one launch: the per-pixel fragment counters and the
-// selection's partition counter and look-back flags zeroed, and the
-// crop-lookup grid.
+// survivor count zeroed, and the crop-lookup grid.
 __global__ void k_pt_prep(uint32_t* __restrict__ pcnt, int64_t pix_total,
-                          uint32_t* __restrict__ sel_tmp, int64_t sel_words, KCrops crops, int nv,
-                          int levels, int gx, int gy, uint32_t* __restrict__ grid) {
+                          uint32_t* __restrict__ live, KCrops crops, int nv, int levels, int gx,
+                          int gy, uint32_t* __restrict__ grid) {
   const int64_t cells = (int64_t)nv * gx * gy;
-  const int64_t n = std::max(std::max(pix_total, sel_words), cells);
+  const int64_t n = std::max(std::max<int64_t>(pix_total, 1), cells);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (i < pix_total) pcnt[i] = 0u;
-    if (i < sel_words) sel_tmp[i] = 0u;
+    if (i == 0) *live = 0u;
     if (i < cells) pt_cropgrid_cell(crops, levels, gx, gy, i, grid);
   }
 }
@@ -225,27 +216,25 @@ __device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, const KCrops&
   return cnt;
 }
 
-// Partition p (taken from an atomic counter, launch order) holds points
-// [1024p, 1024p+1024), handled in four rounds of 256.  Per round and view
-// each lane's fragment count and depth key go to LDS and each wave ballots
-// its survivors; one look-back per partition gives the partition's output
-// base; then the survivors go out view by view, each view's in point order
-// (rounds, then waves, then lanes), after all survivors of earlier
-// partitions.  Within one view the compacted list is in point order, which
-// is all the later stable sorts need (fragments of different views never
-// share a pyramid pixel).  One atomic per 1024 points: a single counter
-// address serialises its atomics, so partitions are kept large.
+// Workgroup b holds points [1024b, 1024b+1024), handled in four rounds of
+// 256.  Per round and view each lane's fragment count and depth key go to
+// LDS and each wave ballots its survivors; a scan over the (view, round,
+// wave) slots places them within the workgroup, and one atomic on the
+// survivor count gives the workgroup's output base.  The compacted order is
+// therefore arbitrary across workgroups, which nothing downstream sees: each
+// fragment's final place is its rank by (depth key, point index) in its
+// pixel.  One atomic per 1024 points: a single counter address serialises
+// its atomics, so workgroups are kept large.
 constexpr int kSelRounds = 4, kSelPart = kSelBlock * kSelRounds;
 
 __global__ __launch_bounds__(kSelBlock) void k_pt_select(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
-    const uint32_t* __restrict__ grid, int gx, int gy, uint32_t* counter, uint64_t* flags,
-    uint32_t* __restrict__ ckey, uint32_t* __restrict__ cval, uint32_t* __restrict__ cent,
-    uint32_t* __restrict__ ccnt, uint32_t* __restrict__ live, int32_t* status) {
+    const uint32_t* __restrict__ grid, int gx, int gy, uint32_t* __restrict__ ckey,
+    uint32_t* __restrict__ cent, uint32_t* __restrict__ ccnt, uint32_t* __restrict__ live) {
   constexpr int NW = kSelBlock / 64;
   constexpr int NSLOT = kSelRounds * VRS_MAX_VIEWS * NW;   // (view, round, wave), view-major
-  __shared__ uint32_t s_part, s_base;
+  __shared__ uint32_t s_base;
   __shared__ uint64_t s_mask[NSLOT];
   __shared__ uint32_t s_pre[NSLOT];
   __shared__ uint32_t s_wsum[NW];
@@ -254,11 +243,9 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
   float* s_zd = reinterpret_cast<float*>(s_dyn);                               // [round][view][tid]
   uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_dyn) + kSelRounds * nv * kSelBlock;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t n_parts = (np + kSelPart - 1) / kSelPart;
-  if (tid == 0) s_part = atomicAdd(counter, 1u);
   for (int e = tid; e < NSLOT; e += kSelBlock) s_mask[e] = 0;
   __syncthreads();
-  const int64_t part = s_part;
+  const int64_t part = blockIdx.x;
   // ---- counts of every (round, view, point), in stages so that each
   // stage's loads (positions; grid cells; T' and depth under the points) are
   // in flight together: a point's fragment count is its footprint targets
@@ -342,13 +329,7 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
 #pragma unroll
     for (int q = 0; q < Q; ++q)
       if (tid * Q + q < NSLOT) s_pre[tid * Q + q] = woff + incl - sum + c[q];
-    if (wave == 0) {
-      const uint32_t excl = wave_lookback(flags, part, total, status);
-      if (lane == 0) {
-        s_base = excl;
-        if (part == n_parts - 1) *live = excl + total;
-      }
-    }
+    if (tid == 0) s_base = total ? atomicAdd(live, total) : 0u;
   }
   __syncthreads();
   // ---- survivors to their positions
@@ -364,7 +345,6 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
           (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       const uint32_t p = base + s_pre[slot] + below;
       ckey[p] = __float_as_uint(s_zd[(j * nv + v) * kSelBlock + tid]);
-      cval[p] = p;
       cent[p] = (uint32_t)(v * np + i);
       ccnt[p] = cnt;
     }
@@ -675,24 +655,20 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
     return VRS_OK;
   }
   uint32_t* live = at<uint32_t>(ws, L.live);
-  uint32_t* sel_counter = at<uint32_t>(ws, L.sel_tmp);
-  uint64_t* sel_flags = at<uint64_t>(ws, L.sel_tmp + 256);
   const int sel_parts = div_up(np, kSelPart);
   const size_t sel_lds = (size_t)kSelRounds * n_views * kSelBlock * 8;
   uint32_t* grid = at<uint32_t>(ws, L.grid);
   {
-    const int64_t sel_words = (int64_t)(sel_tmp_bytes(np) / 4);
     const int64_t cells = (int64_t)n_views * L.gx * L.gy;
-    const int64_t most = std::max(std::max(L.pix_total, sel_words), cells);
+    const int64_t most = std::max(std::max<int64_t>(L.pix_total, 1), cells);
     hipLaunchKernelGGL(k_pt_prep, dim3((unsigned)std::min<int64_t>(4096, div_up(most, 256))),
-                       dim3(256), 0, st, at<uint32_t>(ws, L.pcnt), L.pix_total, sel_counter,
-                       sel_words, kc, n_views, levels, L.gx, L.gy, grid);
+                       dim3(256), 0, st, at<uint32_t>(ws, L.pcnt), L.pix_total, live, kc,
+                       n_views, levels, L.gx, L.gy, grid);
     VRS_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), sel_lds, st, pos, radius, np, kv,
-                     kc, a, depth, t_final, grid, L.gx, L.gy, sel_counter, sel_flags, at<uint32_t>(ws, L.ckey0),
-                     at<uint32_t>(ws, L.cval0), at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt),
-                     live, dev_status);
+                     kc, a, depth, t_final, grid, L.gx, L.gy, at<uint32_t>(ws, L.ckey0),
+                     at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt), live);
   VRS_LAUNCH_CHECK();
   // fragment offsets of the survivors (compaction order), then emission
   VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.ccnt), nullptr, at<uint32_t>(ws, L.foffs),
