@@ -21,10 +21,10 @@
 //                     super-tile) the unit's pairs reaching it, from row
 //                     and column ballots
 //   k_gs_bin_prefix   per super-tile: prefix of those counts over its units
-//                     and the tile totals; scan -> tile list offsets
-//   k_gs_schedule     [begin, end) per tile and the blend order, longest
-//                     list first (one workgroup: counting sort by length
-//                     bucket)
+//                     and the tile totals
+//   k_gs_schedule     one workgroup: tile list offsets (scan of the tile
+//                     totals), [begin, end) per tile and the blend order,
+//                     longest list first (counting sort by length bucket)
 //   k_gs_bin_scatter  one wave per unit: every Gaussian index goes to its
 //                     final place in each tile list it belongs to, its rank
 //                     within a round from one ballot per tile
@@ -59,9 +59,12 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
     const float* __restrict__ mean, const float* __restrict__ cov,
     const float* __restrict__ opacity, const float* __restrict__ sh, int deg, int64_t n,
     KViews views, GsOpt o, float4* __restrict__ rec, uint32_t* __restrict__ dkey,
-    uint32_t* __restrict__ dval, uint32_t* __restrict__ nsup, uint64_t* __restrict__ psum) {
+    uint32_t* __restrict__ dval, uint32_t* __restrict__ nsup, uint64_t* __restrict__ psum,
+    uint32_t* __restrict__ scan_clear, int64_t clear_words) {
   __shared__ uint64_t s_p[4];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // the depth-order scan's temporary, zeroed here so that scan is one launch
+  for (int64_t w = i; w < clear_words; w += (int64_t)gridDim.x * blockDim.x) scan_clear[w] = 0u;
   uint64_t pairs = 0;   // tiles reached, over the views
   if (i < n) {
     const float mx = mean[i], my = mean[n + i], mz = mean[2 * n + i];
@@ -453,7 +456,8 @@ __global__ __launch_bounds__(64 * kPrefixWaves) void k_gs_bin_prefix(
   if (wave == 0 && bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t)) tcnt[t] = tot;
 }
 
-// Tile ranges and the blend schedule, in one workgroup: tiles ordered by
+// Tile list offsets (exclusive scan of the tile totals in tile order), tile
+// ranges and the blend schedule, in one workgroup: tiles ordered by
 // length bucket, descending in 16 log2(1 + length) (work per tile is very
 // uneven, and starting the long lists first keeps them off the end of the
 // blend).  A counting sort: bucket histogram, its scan, then each tile takes
@@ -465,37 +469,53 @@ __device__ inline uint32_t sched_bucket(uint32_t len) {
   return 255u - (uint32_t)fminf(lb, 255.0f);
 }
 __global__ __launch_bounds__(kSchedBlock) void k_gs_schedule(
-    const uint32_t* __restrict__ toff, const uint32_t* __restrict__ tcnt,
-    const uint32_t* __restrict__ total_p, int64_t max_pairs, int64_t tiles_total,
-    uint2* __restrict__ ranges, uint32_t* __restrict__ order, int32_t* status) {
-  __shared__ uint32_t s_hist[256], s_base[256];
+    const uint32_t* __restrict__ tcnt, const uint32_t* __restrict__ total_p, int64_t max_pairs,
+    int64_t tiles_total, uint32_t* __restrict__ toff, uint2* __restrict__ ranges,
+    uint32_t* __restrict__ order, int32_t* status) {
+  __shared__ uint32_t s_hist[256], s_base[256], s_wsum[kSchedBlock / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool over = (int64_t)*total_p > max_pairs;
   if (tid == 0 && over) set_status(status, VRS_ECAPACITY);
   if (tid < 256) s_hist[tid] = 0;
   __syncthreads();
   constexpr int64_t kStep = (int64_t)kSchedBlock * kSchedItems;
+  uint32_t carry = 0;   // pairs of the tiles before the chunk
   for (int64_t t0 = 0; t0 < tiles_total; t0 += kStep) {
-    uint32_t b[kSchedItems], c[kSchedItems];   // every load in flight first
+    // thread tid owns kSchedItems consecutive tiles of the chunk
+    const int64_t tb = t0 + (int64_t)tid * kSchedItems;
+    uint32_t c[kSchedItems], ex[kSchedItems], sum = 0;
 #pragma unroll
     for (int k = 0; k < kSchedItems; ++k) {
-      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
-      b[k] = c[k] = 0u;
-      if (t < tiles_total && !over) {
-        b[k] = toff[t];
-        c[k] = tcnt[t];
-      }
+      c[k] = tb + k < tiles_total && !over ? tcnt[tb + k] : 0u;
+      ex[k] = sum;
+      sum += c[k];
     }
+    uint32_t incl = sum;
 #pragma unroll
-    for (int k = 0; k < kSchedItems; ++k) {
-      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
-      if (t < tiles_total) {
-        ranges[t] = make_uint2(b[k], b[k] + c[k]);
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0, btot = 0;
+#pragma unroll
+    for (int w = 0; w < kSchedBlock / 64; ++w) {
+      if (w < wave) woff += s_wsum[w];
+      btot += s_wsum[w];
+    }
+    const uint32_t base = carry + woff + incl - sum;
+#pragma unroll
+    for (int k = 0; k < kSchedItems; ++k)
+      if (tb + k < tiles_total) {
+        const uint32_t b = base + ex[k];
+        toff[tb + k] = b;
+        ranges[tb + k] = make_uint2(b, b + c[k]);
         atomicAdd(&s_hist[sched_bucket(c[k])], 1u);
       }
-    }
+    carry += btot;
+    __syncthreads();   // s_wsum is rewritten by the next chunk
   }
-  __syncthreads();
   if (wave == 0) {   // exclusive scan of the 256 buckets, four per lane
     uint32_t h[4], sum = 0;
 #pragma unroll
@@ -942,7 +962,8 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     hipLaunchKernelGGL(k_gs_preprocess, dim3((unsigned)nps), dim3(256), 0, st, mean, cov,
                        opacity, sh, sh_degree, n, kv, o, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
-                       at<uint32_t>(ws, L.nsup), at<uint64_t>(ws, L.psum));
+                       at<uint32_t>(ws, L.nsup), at<uint64_t>(ws, L.psum),
+                       at<uint32_t>(ws, L.scan_tmp), (int64_t)(scan_tmp_bytes(vn) / 4));
     VRS_LAUNCH_CHECK();
     trace_end(VRS_TRACE_GS_PREPROCESS, st);
     trace_begin(VRS_TRACE_GS_DEPTH_SORT, st);
@@ -953,7 +974,7 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     const uint32_t* sorted_e = at<uint32_t>(ws, d1 ? L.dval1 : L.dval0);
     VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.nsup), sorted_e, at<uint32_t>(ws, L.soffs),
                                      super_count, nullptr, vn, at<void>(ws, L.scan_tmp),
-                                     dev_status, st));
+                                     dev_status, st, true));
     trace_end(VRS_TRACE_GS_DEPTH_SORT, st);
     trace_begin(VRS_TRACE_GS_EMIT, st);
     hipLaunchKernelGGL(k_gs_emit_super, dim3(div_up(vn, kEmitBlock)), dim3(kEmitBlock), 0, st,
@@ -1001,11 +1022,8 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                      at<uint32_t>(ws, L.ubase), L.sxn, L.spv, L.tiles_x, L.tiles_y,
                      at<uint32_t>(ws, L.ucnt), at<uint32_t>(ws, L.tcnt));
   VRS_LAUNCH_CHECK();
-  VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.tcnt), nullptr, at<uint32_t>(ws, L.toff),
-                                   nullptr, nullptr, L.tiles_total, at<void>(ws, L.scan_tmp),
-                                   dev_status, st));
-  hipLaunchKernelGGL(k_gs_schedule, dim3(1), dim3(kSchedBlock), 0, st, at<uint32_t>(ws, L.toff),
-                     at<uint32_t>(ws, L.tcnt), pair_count, max_pairs, L.tiles_total,
+  hipLaunchKernelGGL(k_gs_schedule, dim3(1), dim3(kSchedBlock), 0, st, at<uint32_t>(ws, L.tcnt),
+                     pair_count, max_pairs, L.tiles_total, at<uint32_t>(ws, L.toff),
                      at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.order), dev_status);
   VRS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_gs_bin_scatter, dim3(unit_blocks), dim3(256), 0, st, svals,

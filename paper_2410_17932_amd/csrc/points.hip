@@ -9,20 +9,23 @@
 // blend order with no global sort, and deterministically (atomics only
 // place survivors and fragments in scratch lists whose order the ranking
 // removes).
-//   k_pt_prep      per-pixel counters and the survivor count zeroed, crop
-//                  grid
+//   k_pt_prep      per-pixel counters, the survivor and fragment counts and
+//                  the pixel scan's temporary zeroed, crop grid
 //   k_pt_select    one thread per point, points read once for all crops:
 //                  projection, layer, crop footprints, then the depth cull;
-//                  survivors (depth key, entry, fragment count) compacted in
-//                  the same pass, one atomic per workgroup
-//   scan           fragment counts of the survivors -> offsets
+//                  survivors (depth key, entry, fragment offset) compacted in
+//                  the same pass, one 64-bit atomic per workgroup for the
+//                  survivor and fragment bases
 //   k_pt_emit      one thread per survivor writes its fragments (layer
-//                  pixel, weight | point index, depth key) and counts them
-//                  per pixel
+//                  pixel, weight | point index, depth key), counts them per
+//                  pixel and takes each one a free place in its pixel's
+//                  segment (the counting atomics' old values)
 //   scan           per-pixel counts -> segment offsets
-//   k_pt_scatter   (depth key, point index) of each fragment into its
-//                  pixel's segment, at a free place
-//   k_pt_rank      each fragment's rank in its segment -> its final place
+//   k_pt_scatter   each fragment's record (point index, depth key, weight,
+//                  pixel) to its segment place: no atomics
+//   k_pt_rank      one thread per segment place: the record's rank in its
+//                  segment -> its final place (the lanes of one segment
+//                  read the same records)
 //   k_pt_blend     one thread per layer pixel walks its list front to back
 #include <hip/hip_fp16.h>
 
@@ -31,9 +34,9 @@
 namespace vrs {
 
 struct SplatWs {
-  size_t cent, ccnt, ckey0, live, foffs, frag_count,
-      fkey0, fval0, fdep,          // fragments in emission order
-      useg,                        // (depth key, point index) per segment place
+  size_t cent, ckey0, ctr, live, foffs, frag_count,
+      fkey0, fval0, fdep, fslot,   // fragments in emission order, place in segment
+      seg,                         // (point index, depth key, weight, pixel) per segment place
       fkey1, fval1,                // fragments in blend order
       pcnt, poff,                  // per layer pixel: fragment count, segment offsets [P + 1]
       grid, scan_tmp, total;
@@ -70,21 +73,22 @@ static bool splat_layout(int64_t np, int nv, int W, int H, const vrs_crop* crops
   const int64_t pt = std::max<int64_t>(L->pix_total, 1);
   Carver c;
   L->cent = c.take(vn * 4);
-  L->ccnt = c.take(vn * 4);
   L->ckey0 = c.take(vn * 4);
-  L->live = c.take(4);
+  L->ctr = c.take(8);   // survivors in the low word, fragments in the high word
+  L->live = L->ctr;
+  L->frag_count = L->ctr + 4;
   L->foffs = c.take(vn * 4);
-  L->frag_count = c.take(4);
   L->fkey0 = c.take(mf * 4);
   L->fval0 = c.take(mf * 8);
   L->fdep = c.take(mf * 4);
-  L->useg = c.take(mf * 8);
+  L->fslot = c.take(mf * 4);
+  L->seg = c.take(mf * 16);
   L->fkey1 = c.take(mf * 4);
   L->fval1 = c.take(mf * 8);
   L->pcnt = c.take(pt * 4);
   L->poff = c.take((pt + 1) * 4);
   L->grid = c.take((size_t)nv * L->gx * L->gy * 4);
-  L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(pt)));
+  L->scan_tmp = c.take(scan_tmp_bytes(pt));
   L->total = c.off;
   return true;
 }
@@ -154,17 +158,20 @@ __device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx,
   grid[idx] = mask;
 }
 
-// Per-call set-up in one launch: the per-pixel fragment counters and the
-// survivor count zeroed, and the crop-lookup grid.
+// Per-call set-up in one launch: the per-pixel fragment counters, the
+// survivor and fragment counts and the pixel scan's temporary zeroed, and
+// the crop-lookup grid.
 __global__ void k_pt_prep(uint32_t* __restrict__ pcnt, int64_t pix_total,
-                          uint32_t* __restrict__ live, KCrops crops, int nv, int levels, int gx,
-                          int gy, uint32_t* __restrict__ grid) {
+                          uint64_t* __restrict__ ctr, uint32_t* __restrict__ scan_tmp,
+                          int64_t scan_words, KCrops crops, int nv, int levels, int gx, int gy,
+                          uint32_t* __restrict__ grid) {
   const int64_t cells = (int64_t)nv * gx * gy;
-  const int64_t n = std::max(std::max<int64_t>(pix_total, 1), cells);
+  const int64_t n = std::max(std::max(pix_total, scan_words), std::max<int64_t>(cells, 1));
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (i < pix_total) pcnt[i] = 0u;
-    if (i == 0) *live = 0u;
+    if (i < scan_words) scan_tmp[i] = 0u;
+    if (i == 0) *ctr = 0ull;
     if (i < cells) pt_cropgrid_cell(crops, levels, gx, gy, i, grid);
   }
 }
@@ -219,8 +226,10 @@ __device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, const KCrops&
 // Workgroup b holds points [1024b, 1024b+1024), handled in four rounds of
 // 256.  Per round and view each lane's fragment count and depth key go to
 // LDS and each wave ballots its survivors; a scan over the (view, round,
-// wave) slots places them within the workgroup, and one atomic on the
-// survivor count gives the workgroup's output base.  The compacted order is
+// wave) slots places them and their fragments within the workgroup, and one
+// 64-bit atomic on the (survivor, fragment) counts gives the workgroup's
+// output bases, so no separate scan of fragment counts is needed.  The
+// compacted order is
 // therefore arbitrary across workgroups, which nothing downstream sees: each
 // fragment's final place is its rank by (depth key, point index) in its
 // pixel.  One atomic per 1024 points: a single counter address serialises
@@ -231,19 +240,24 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
     const uint32_t* __restrict__ grid, int gx, int gy, uint32_t* __restrict__ ckey,
-    uint32_t* __restrict__ cent, uint32_t* __restrict__ ccnt, uint32_t* __restrict__ live) {
+    uint32_t* __restrict__ cent, uint32_t* __restrict__ foffs, uint64_t* __restrict__ ctr,
+    int32_t* status) {
   constexpr int NW = kSelBlock / 64;
   constexpr int NSLOT = kSelRounds * VRS_MAX_VIEWS * NW;   // (view, round, wave), view-major
-  __shared__ uint32_t s_base;
+  static_assert(NSLOT <= kSelBlock, "one slot per thread in the slot scan");
+  __shared__ uint32_t s_base, s_fbase;
   __shared__ uint64_t s_mask[NSLOT];
-  __shared__ uint32_t s_pre[NSLOT];
-  __shared__ uint32_t s_wsum[NW];
+  __shared__ uint32_t s_pre[NSLOT], s_fsum[NSLOT], s_fpre[NSLOT];
+  __shared__ uint32_t s_wsum[NW], s_wfsum[NW];
   extern __shared__ __align__(16) char s_dyn[];
   const int nv = views.n;
   float* s_zd = reinterpret_cast<float*>(s_dyn);                               // [round][view][tid]
   uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_dyn) + kSelRounds * nv * kSelBlock;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < NSLOT; e += kSelBlock) s_mask[e] = 0;
+  for (int e = tid; e < NSLOT; e += kSelBlock) {
+    s_mask[e] = 0;
+    s_fsum[e] = 0;
+  }
   __syncthreads();
   const int64_t part = blockIdx.x;
   // ---- counts of every (round, view, point), in stages so that each
@@ -298,55 +312,82 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
       s_zd[(j * nv + v) * kSelBlock + tid] = tz[j];
       s_cnt[(j * nv + v) * kSelBlock + tid] = cnt;
       const uint64_t m = __ballot(cnt != 0);
-      if (lane == 0) s_mask[(v * kSelRounds + j) * NW + wave] = m;
+      if (m) {   // the slot's fragment total
+        uint32_t fs = cnt;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) fs += __shfl_xor(fs, o, 64);
+        if (lane == 0) {
+          s_mask[(v * kSelRounds + j) * NW + wave] = m;
+          s_fsum[(v * kSelRounds + j) * NW + wave] = fs;
+        }
+      }
     }
   }
   __syncthreads();
-  // ---- exclusive scan of the slot counts in output order
+  // ---- exclusive scans of the slot survivor and fragment counts in output
+  // order, then the workgroup's bases
   {
-    constexpr int Q = NSLOT >= kSelBlock ? NSLOT / kSelBlock : 1;   // slots per thread
-    uint32_t c[Q], sum = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = tid * Q + q;
-      c[q] = sum;
-      sum += e < NSLOT ? (uint32_t)__popcll(s_mask[e]) : 0u;
-    }
-    uint32_t incl = sum;
+    const uint32_t c = tid < NSLOT ? (uint32_t)__popcll(s_mask[tid]) : 0u;
+    const uint32_t f = tid < NSLOT ? s_fsum[tid] : 0u;
+    uint32_t ic = c, jf = f;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
+      const uint32_t y = __shfl_up(ic, o, 64), z = __shfl_up(jf, o, 64);
+      if (lane >= o) {
+        ic += y;
+        jf += z;
+      }
     }
-    if (lane == 63) s_wsum[wave] = incl;
+    if (lane == 63) {
+      s_wsum[wave] = ic;
+      s_wfsum[wave] = jf;
+    }
     __syncthreads();
-    uint32_t woff = 0, total = 0;
+    uint32_t woff = 0, wfoff = 0, total = 0, ftotal = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      if (w < wave) woff += s_wsum[w];
+      if (w < wave) {
+        woff += s_wsum[w];
+        wfoff += s_wfsum[w];
+      }
       total += s_wsum[w];
+      ftotal += s_wfsum[w];
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (tid * Q + q < NSLOT) s_pre[tid * Q + q] = woff + incl - sum + c[q];
-    if (tid == 0) s_base = total ? atomicAdd(live, total) : 0u;
+    if (tid < NSLOT) {
+      s_pre[tid] = woff + ic - c;
+      s_fpre[tid] = wfoff + jf - f;
+    }
+    if (tid == 0) {
+      const uint64_t old = total ? atomicAdd(ctr, ((uint64_t)ftotal << 32) | total) : 0ull;
+      s_base = (uint32_t)old;
+      s_fbase = (uint32_t)(old >> 32);
+      // the fragment count wraps only far beyond any capacity
+      if ((old >> 32) + ftotal > 0xffffffffull) set_status(status, VRS_ECAPACITY);
+    }
   }
   __syncthreads();
-  // ---- survivors to their positions
-  const uint32_t base = s_base;
+  // ---- survivors to their positions, with their fragment offsets
+  const uint32_t base = s_base, fbase = s_fbase;
   for (int j = 0; j < kSelRounds; ++j) {
     const int64_t i = part * kSelPart + (int64_t)j * kSelBlock + tid;
     for (int v = 0; v < nv; ++v) {
-      const uint32_t cnt = s_cnt[(j * nv + v) * kSelBlock + tid];
-      if (!cnt) continue;
       const int slot = (v * kSelRounds + j) * NW + wave;
       const uint64_t m = s_mask[slot];
+      if (!m) continue;   // uniform
+      const uint32_t cnt = s_cnt[(j * nv + v) * kSelBlock + tid];
+      uint32_t fi = cnt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(fi, o, 64);
+        if (lane >= o) fi += y;
+      }
+      if (!cnt) continue;
       const uint32_t below = __builtin_amdgcn_mbcnt_hi(
           (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       const uint32_t p = base + s_pre[slot] + below;
       ckey[p] = __float_as_uint(s_zd[(j * nv + v) * kSelBlock + tid]);
       cent[p] = (uint32_t)(v * np + i);
-      ccnt[p] = cnt;
+      foffs[p] = fbase + s_fpre[slot] + fi - cnt;
     }
   }
 }
@@ -387,17 +428,24 @@ struct PixHash {
 };
 
 // One thread per survivor (compaction order): its fragments at its offset,
-// each with its layer pixel, weight | point index and depth key; the
-// pixel's fragment count goes up by one (an atomic whose result is not
-// waited for).
+// each with its layer pixel, weight | point index and depth key, and its
+// place in the pixel's segment.  Places come from the pixel counters' old
+// values: the workgroup gathers its fragments per pixel in the LDS table,
+// each table entry adds its count with one atomic whose old value is the
+// entry's first place, and a fragment's place is that plus its rank in the
+// entry (held meanwhile as a tagged table reference).  A fragment whose
+// probe finds no table place takes its own with its own atomic.
+constexpr uint32_t kSlotRef = 0x80000000u;   // tag | table place << 20 | rank
 __global__ __launch_bounds__(256) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const uint32_t* __restrict__ ckey,
     const uint32_t* __restrict__ cent, const uint32_t* __restrict__ live_p,
     const uint32_t* __restrict__ foffs, const uint32_t* __restrict__ total_p, int64_t max_frags,
     uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval, uint32_t* __restrict__ fdep,
-    uint32_t* __restrict__ pcnt, int32_t* status) {
+    uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt, int32_t* status) {
   __shared__ PixHash<2048> h;   // a workgroup emits ~2000 fragments
+  __shared__ uint32_t s_first[2048];
+  static_assert(2048 <= (1 << 11), "table place fits the tag");
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
@@ -437,11 +485,16 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               if (xx < 0 || xx >= Sl || yy < 0 || yy >= Sl) continue;
               const float w = wl * (dx ? bx : 1.0f - bx) * (dy ? by : 1.0f - by);
               const uint32_t px = (uint32_t)(lb + yy * Sl + xx);
+              if (o >= max_frags) continue;   // only after a wrapped count (flagged)
               fkey[o] = px;
               fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
               fdep[o] = dz;
+              // a point reaches a pixel once, so a pixel's rank in the table
+              // is below the number of survivors the workgroup handles
+              // (< 2^20: survivors < 2^30, at least 2^21 threads)
               uint32_t r;
-              if (h.add(px, r) < 0) atomicAdd(&pcnt[px], 1u);
+              const int hs = h.add(px, r);
+              fslot[o] = hs >= 0 ? (kSlotRef | (uint32_t)hs << 20 | r) : atomicAdd(&pcnt[px], 1u);
               ++o;
             }
         }
@@ -450,75 +503,66 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2048; i += blockDim.x)
-    if (h.key[i] != kPixEmpty) atomicAdd(&pcnt[h.key[i]], h.cnt[i]);
-}
-
-// Each fragment's (depth key, point index) into its pixel's segment, at a
-// free place: per workgroup the fragments are grouped by pixel in the LDS
-// table, each group takes its places with one atomic (the pixel's count,
-// taken down, ends at 0), and a fragment's place is the group's start plus
-// its rank in the group.
-__global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__ fkey,
-                                                    const uint64_t* __restrict__ fval,
-                                                    const uint32_t* __restrict__ fdep,
-                                                    uint32_t* __restrict__ pcnt,
-                                                    const uint32_t* __restrict__ poff,
-                                                    const uint32_t* __restrict__ total_p,
-                                                    int64_t max_frags, uint64_t* __restrict__ useg) {
-  __shared__ PixHash<512> h;   // a round has 256 fragments
-  __shared__ uint32_t s_base[512];
-  const int64_t total = *total_p;
-  if (total > max_frags) return;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < total;
-       i0 += (int64_t)gridDim.x * blockDim.x) {   // uniform over the workgroup
-    h.clear();
-    __syncthreads();
-    const int64_t i = i0 + threadIdx.x;
-    const bool in = i < total;
-    uint32_t px = 0, r = 0, slot = 0;
-    int hs = -1;
-    if (in) {
-      px = fkey[i];
-      hs = h.add(px, r);
-      if (hs < 0) slot = atomicSub(&pcnt[px], 1u) - 1u;
+  for (int q = threadIdx.x; q < 2048; q += blockDim.x)
+    if (h.key[q] != kPixEmpty) s_first[q] = atomicAdd(&pcnt[h.key[q]], h.cnt[q]);
+  __syncthreads();
+  // tagged places -> places: each thread revisits the fragments it wrote
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lo = foffs[j], hi = std::min<int64_t>(j + 1 < live ? foffs[j + 1] : total, max_frags);
+    for (int64_t o = lo; o < hi; ++o) {
+      const uint32_t t = fslot[o];
+      if (t & kSlotRef) fslot[o] = s_first[(t >> 20) & 0x7ffu] + (t & 0xfffffu);
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 512; e += blockDim.x)
-      if (h.key[e] != kPixEmpty) s_base[e] = atomicSub(&pcnt[h.key[e]], h.cnt[e]);
-    __syncthreads();
-    if (in) {
-      if (hs >= 0) slot = s_base[hs] - 1u - r;
-      useg[poff[px] + slot] = ((uint64_t)fdep[i] << 32) | (uint32_t)fval[i];
-    }
-    __syncthreads();   // the table is cleared for the next round
   }
 }
 
-// A fragment's place in blend order: its segment's offset plus the number of
-// the segment's fragments before it in (depth key, point index) order (a
-// point reaches a layer pixel at most once, so the pairs are distinct).
-__global__ __launch_bounds__(256) void k_pt_rank(const uint32_t* __restrict__ fkey,
-                                                 const uint64_t* __restrict__ fval,
-                                                 const uint32_t* __restrict__ fdep,
-                                                 const uint32_t* __restrict__ poff,
-                                                 const uint64_t* __restrict__ useg,
-                                                 const uint32_t* __restrict__ total_p,
-                                                 int64_t max_frags, uint32_t* __restrict__ okey,
-                                                 uint64_t* __restrict__ oval) {
+// Each fragment's record (point index, depth key, weight, pixel) to its
+// segment place (checked against the segment, so an unresolved place can
+// never write outside it).
+__global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__ fkey,
+                                                    const uint64_t* __restrict__ fval,
+                                                    const uint32_t* __restrict__ fdep,
+                                                    const uint32_t* __restrict__ fslot,
+                                                    const uint32_t* __restrict__ poff,
+                                                    const uint32_t* __restrict__ total_p,
+                                                    int64_t max_frags, uint4* __restrict__ seg) {
   const int64_t total = *total_p;
   if (total > max_frags) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t px = fkey[i];
     const uint64_t v = fval[i];
-    const uint64_t own = ((uint64_t)fdep[i] << 32) | (uint32_t)v;
-    const uint32_t start = poff[px], n = poff[px + 1] - start;
+    const uint32_t at = poff[px] + fslot[i];
+    if (at < poff[px + 1]) seg[at] = make_uint4((uint32_t)v, fdep[i], (uint32_t)(v >> 32), px);
+  }
+}
+
+// One thread per segment place: the record's final place is its segment's
+// offset plus the number of the segment's records before it in (depth key,
+// point index) order (a point reaches a layer pixel at most once, so the
+// pairs are distinct).  Consecutive places share segments, so the lanes of
+// a segment read the same records.
+__global__ __launch_bounds__(256) void k_pt_rank(const uint4* __restrict__ seg,
+                                                 const uint32_t* __restrict__ poff,
+                                                 const uint32_t* __restrict__ total_p,
+                                                 int64_t max_frags, int64_t pix_total,
+                                                 uint32_t* __restrict__ okey,
+                                                 uint64_t* __restrict__ oval) {
+  const int64_t total = *total_p;
+  if (total > max_frags) return;
+  const uint64_t* key = reinterpret_cast<const uint64_t*>(seg);   // depth key << 32 | index
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < total;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 rec = seg[s];
+    if (rec.w >= pix_total) continue;   // every place is filled; never taken
+    const uint64_t own = ((uint64_t)rec.y << 32) | rec.x;
+    const uint32_t start = poff[rec.w], n = poff[rec.w + 1] - start;
     uint32_t rank = 0;
 #pragma unroll 8
-    for (uint32_t j = 0; j < n; ++j) rank += useg[start + j] < own ? 1u : 0u;
-    okey[start + rank] = px;
-    oval[start + rank] = v;
+    for (uint32_t j = 0; j < n; ++j) rank += key[2 * (int64_t)(start + j)] < own ? 1u : 0u;
+    okey[start + rank] = rec.w;
+    oval[start + rank] = ((uint64_t)rec.z << 32) | rec.x;
   }
 }
 
@@ -660,38 +704,39 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   uint32_t* grid = at<uint32_t>(ws, L.grid);
   {
     const int64_t cells = (int64_t)n_views * L.gx * L.gy;
-    const int64_t most = std::max(std::max<int64_t>(L.pix_total, 1), cells);
+    const int64_t scan_words = (int64_t)(scan_tmp_bytes(L.pix_total) / 4);
+    const int64_t most = std::max(std::max<int64_t>(L.pix_total, scan_words), cells);
     hipLaunchKernelGGL(k_pt_prep, dim3((unsigned)std::min<int64_t>(4096, div_up(most, 256))),
-                       dim3(256), 0, st, at<uint32_t>(ws, L.pcnt), L.pix_total, live, kc,
+                       dim3(256), 0, st, at<uint32_t>(ws, L.pcnt), L.pix_total,
+                       at<uint64_t>(ws, L.ctr), at<uint32_t>(ws, L.scan_tmp), scan_words, kc,
                        n_views, levels, L.gx, L.gy, grid);
     VRS_LAUNCH_CHECK();
   }
+  // survivors with their fragment offsets (compaction order), then emission
   hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), sel_lds, st, pos, radius, np, kv,
                      kc, a, depth, t_final, grid, L.gx, L.gy, at<uint32_t>(ws, L.ckey0),
-                     at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.ccnt), live);
+                     at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.foffs), at<uint64_t>(ws, L.ctr),
+                     dev_status);
   VRS_LAUNCH_CHECK();
-  // fragment offsets of the survivors (compaction order), then emission
-  VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.ccnt), nullptr, at<uint32_t>(ws, L.foffs),
-                                   frag_count, live, vn, at<void>(ws, L.scan_tmp), dev_status, st));
   uint32_t* pcnt = at<uint32_t>(ws, L.pcnt);
   uint32_t* poff = at<uint32_t>(ws, L.poff);
   hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)std::min<int64_t>(8192, div_up(vn, 256))),
                      dim3(256), 0, st, pos, radius, np, kv, kc, a, at<uint32_t>(ws, L.ckey0),
                      at<uint32_t>(ws, L.cent), live, at<uint32_t>(ws, L.foffs), frag_count,
                      max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
-                     at<uint32_t>(ws, L.fdep), pcnt, dev_status);
+                     at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot), pcnt, dev_status);
   VRS_LAUNCH_CHECK();
   // per-pixel segments, then each fragment to its place in blend order
   VRS_HIP_CHECK(exclusive_scan_u32(pcnt, nullptr, poff, poff + L.pix_total, nullptr, L.pix_total,
-                                   at<void>(ws, L.scan_tmp), dev_status, st));
+                                   at<void>(ws, L.scan_tmp), dev_status, st, true));
   const unsigned fb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, div_up(max_frags, 256)));
   hipLaunchKernelGGL(k_pt_scatter, dim3(fb), dim3(256), 0, st, at<uint32_t>(ws, L.fkey0),
-                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), pcnt, poff, frag_count,
-                     max_frags, at<uint64_t>(ws, L.useg));
+                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep),
+                     at<uint32_t>(ws, L.fslot), poff, frag_count, max_frags,
+                     at<uint4>(ws, L.seg));
   VRS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_pt_rank, dim3(fb), dim3(256), 0, st, at<uint32_t>(ws, L.fkey0),
-                     at<uint64_t>(ws, L.fval0), at<uint32_t>(ws, L.fdep), poff,
-                     at<uint64_t>(ws, L.useg), frag_count, max_frags, at<uint32_t>(ws, L.fkey1),
+  hipLaunchKernelGGL(k_pt_rank, dim3(fb), dim3(256), 0, st, at<uint4>(ws, L.seg), poff,
+                     frag_count, max_frags, L.pix_total, at<uint32_t>(ws, L.fkey1),
                      at<uint64_t>(ws, L.fval1));
   VRS_LAUNCH_CHECK();
   const unsigned pb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, div_up(L.pix_total, 256)));

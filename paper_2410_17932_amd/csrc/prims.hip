@@ -68,7 +68,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
   // the grid is sized for n_max; blocks beyond the partitions n needs leave
   // before taking a partition id, so exactly those take ids 0..parts-1
   const int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
-  if ((int64_t)blockIdx.x * kScanTile >= n) return;
+  if ((int64_t)blockIdx.x * kScanTile >= n) {
+    if (n == 0 && blockIdx.x == 0 && tid == 0 && total) *total = 0;
+    return;
+  }
   if (tid == 0) s_part = atomicAdd(counter, 1u);
   __syncthreads();
   const int64_t part = s_part;
@@ -369,7 +372,7 @@ size_t scan_tmp_bytes(int64_t n_max) {
 
 static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* out,
                             uint32_t* total, const uint32_t* n_dev, int64_t n_max, void* tmp,
-                            int32_t* status, hipStream_t st, int flags_mode) {
+                            int32_t* status, hipStream_t st, int flags_mode, bool cleared) {
   if (n_max <= 0) {
     if (total) return fill_u32(total, 0, 1, st);
     return hipSuccess;
@@ -377,9 +380,11 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* o
   uint32_t* counter = static_cast<uint32_t*>(tmp);
   uint64_t* flags = reinterpret_cast<uint64_t*>(static_cast<char*>(tmp) + 256);
   int64_t parts = (n_max + kScanTile - 1) / kScanTile;
-  int cb = (int)std::min<int64_t>(1024, (parts + 255) / 256 + 1);
-  hipLaunchKernelGGL(k_scan_clear, dim3(cb), dim3(256), 0, st, counter, flags, total, n_dev,
-                     n_max);
+  if (!cleared) {
+    const int cb = (int)std::min<int64_t>(1024, (parts + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_scan_clear, dim3(cb), dim3(256), 0, st, counter, flags, total, n_dev,
+                       n_max);
+  }
   hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kScanBlock), 0, st, in, idx, out, total,
                      n_dev, n_max, counter, flags, status, flags_mode);
   return hipGetLastError();
@@ -387,13 +392,13 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* o
 
 hipError_t exclusive_scan_u32(const uint32_t* in, const uint32_t* idx, uint32_t* out,
                               uint32_t* total, const uint32_t* n_dev, int64_t n_max, void* tmp,
-                              int32_t* status, hipStream_t st) {
-  return scan_impl(in, idx, out, total, n_dev, n_max, tmp, status, st, 0);
+                              int32_t* status, hipStream_t st, bool cleared) {
+  return scan_impl(in, idx, out, total, n_dev, n_max, tmp, status, st, 0, cleared);
 }
 
 hipError_t exclusive_scan_flags_u32(const uint32_t* in, uint32_t* out, uint32_t* total,
                                     int64_t n, void* tmp, int32_t* status, hipStream_t st) {
-  return scan_impl(in, nullptr, out, total, nullptr, n, tmp, status, st, 1);
+  return scan_impl(in, nullptr, out, total, nullptr, n, tmp, status, st, 1, false);
 }
 
 const uint32_t* radix_sort_digit_totals(const void* tmp) {

@@ -76,10 +76,12 @@ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // look-back, Merrill & Garland 2016).  in[i] (or in[idx[i]] when idx is not
 // null) for i < n, n = min(*n_dev, n_max) (n_dev may be null).  Writes
 // out[i] and *total (may be null) = sum.  tmp: scan_tmp_bytes(n_max).
+// cleared: an earlier kernel on the stream zeroed those bytes of tmp since
+// their last use, so the scan runs as one launch.
 size_t scan_tmp_bytes(int64_t n_max);
 hipError_t exclusive_scan_u32(const uint32_t* in, const uint32_t* idx, uint32_t* out,
                               uint32_t* total, const uint32_t* n_dev, int64_t n_max, void* tmp,
-                              int32_t* status, hipStream_t st);
+                              int32_t* status, hipStream_t st, bool cleared = false);
 
 // Exclusive scan of the flags (in[i] != 0), i < n: stream-compaction
 // positions in index order; *total = number of set flags.
