@@ -402,7 +402,7 @@ constexpr int kPixProbe = 8;
 constexpr uint32_t kPixEmpty = 0xffffffffu;
 template <int N>   // places, a power of two
 struct PixHash {
-  static constexpr int kBits = N == 2048 ? 11 : (N == 1024 ? 10 : 9);
+  static constexpr int kBits = N == 4096 ? 12 : (N == 2048 ? 11 : (N == 1024 ? 10 : 9));
   static_assert((1 << kBits) == N, "PixHash size");
   uint32_t key[N], cnt[N];
   __device__ void clear() {
@@ -435,7 +435,8 @@ struct PixHash {
 // entry's first place, and a fragment's place is that plus its rank in the
 // entry (held meanwhile as a tagged table reference).  A fragment whose
 // probe finds no table place takes its own with its own atomic.
-constexpr uint32_t kSlotRef = 0x80000000u;   // tag | table place << 20 | rank
+constexpr uint32_t kSlotRef = 0x80000000u;   // tag | table place << kRankBits | rank
+constexpr int kEmitPlaces = 4096, kRankBits = 19;   // table at half load for ~2000 fragments
 __global__ __launch_bounds__(256) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const uint32_t* __restrict__ ckey,
@@ -443,9 +444,9 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     const uint32_t* __restrict__ foffs, const uint32_t* __restrict__ total_p, int64_t max_frags,
     uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval, uint32_t* __restrict__ fdep,
     uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt, int32_t* status) {
-  __shared__ PixHash<2048> h;   // a workgroup emits ~2000 fragments
-  __shared__ uint32_t s_first[2048];
-  static_assert(2048 <= (1 << 11), "table place fits the tag");
+  __shared__ PixHash<kEmitPlaces> h;   // a workgroup emits ~2000 fragments
+  __shared__ uint32_t s_first[kEmitPlaces];
+  static_assert(kEmitPlaces <= (1 << (31 - kRankBits)), "table place fits the tag");
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
@@ -491,10 +492,11 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               fdep[o] = dz;
               // a point reaches a pixel once, so a pixel's rank in the table
               // is below the number of survivors the workgroup handles
-              // (< 2^20: survivors < 2^30, at least 2^21 threads)
+              // (< 2^17 < 2^kRankBits: survivors < 2^30, at least 2^21 threads)
               uint32_t r;
               const int hs = h.add(px, r);
-              fslot[o] = hs >= 0 ? (kSlotRef | (uint32_t)hs << 20 | r) : atomicAdd(&pcnt[px], 1u);
+              fslot[o] = hs >= 0 ? (kSlotRef | (uint32_t)hs << kRankBits | r)
+                                 : atomicAdd(&pcnt[px], 1u);
               ++o;
             }
         }
@@ -503,16 +505,21 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < 2048; q += blockDim.x)
+  for (int q = threadIdx.x; q < kEmitPlaces; q += blockDim.x)
     if (h.key[q] != kPixEmpty) s_first[q] = atomicAdd(&pcnt[h.key[q]], h.cnt[q]);
   __syncthreads();
   // tagged places -> places: each thread revisits the fragments it wrote
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
        j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t lo = foffs[j], hi = std::min<int64_t>(j + 1 < live ? foffs[j + 1] : total, max_frags);
-    for (int64_t o = lo; o < hi; ++o) {
-      const uint32_t t = fslot[o];
-      if (t & kSlotRef) fslot[o] = s_first[(t >> 20) & 0x7ffu] + (t & 0xfffffu);
+    for (int64_t o0 = lo; o0 < hi; o0 += 8) {   // eight loads in flight, then the stores
+      uint32_t t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = o0 + q < hi ? fslot[o0 + q] : 0u;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (t[q] & kSlotRef)
+          fslot[o0 + q] = s_first[(t[q] & ~kSlotRef) >> kRankBits] + (t[q] & ((1u << kRankBits) - 1u));
     }
   }
 }
