@@ -36,14 +36,19 @@ __global__ void k_fill(uint32_t* p, uint32_t v, int64_t n) {
 }
 
 // ------------------------------------------------------------------ scan
-constexpr int kScanBlock = 256, kScanItems = 16, kScanTile = kScanBlock * kScanItems;
+// Partition shapes: direct reads take 16K-item partitions (1024 threads x
+// 16 items: fewer partitions, so fewer ticket atomics and look-back rounds);
+// gathered reads (in[idx[i]]) take 4K-item partitions (512 x 8), where more
+// workgroups keep more gathers in flight.  Temporaries are sized for the
+// smaller one.
+constexpr int kScanTileMin = 4096;
 
 // Clears the partition counter, the look-back flags the scan will use and
 // the total (n may turn out to be 0 on the device: the total is then 0).
 __global__ void k_scan_clear(uint32_t* counter, uint64_t* flags, uint32_t* total,
                              const uint32_t* n_dev, int64_t n_max) {
   int64_t n = n_dev ? (int64_t)min((uint64_t)*n_dev, (uint64_t)n_max) : n_max;
-  int64_t parts = (n + kScanTile - 1) / kScanTile;
+  int64_t parts = (n + kScanTileMin - 1) / kScanTileMin;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i == 0) {
     *counter = 0;
@@ -55,6 +60,7 @@ __global__ void k_scan_clear(uint32_t* counter, uint64_t* flags, uint32_t* total
 // Thread t of a partition owns kScanItems consecutive items of it; when the
 // input is read directly (no index) and 16-byte aligned, they come in as
 // 16-byte loads.
+template <int kScanBlock, int kScanItems>
 __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict__ in,
                                                       const uint32_t* __restrict__ idx,
                                                       uint32_t* __restrict__ out,
@@ -63,6 +69,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
                                                       uint64_t* flags, int32_t* status,
                                                       int flags_mode) {
   __shared__ uint32_t s_part, s_prefix;
+  constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanItems;
+  static_assert(kScanTile >= kScanTileMin && kScanItems % 4 == 0, "partition shape");
   __shared__ uint32_t s_wsum[kScanBlock / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // the grid is sized for n_max; blocks beyond the partitions n needs leave
@@ -366,7 +374,7 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
 }
 
 size_t scan_tmp_bytes(int64_t n_max) {
-  int64_t parts = (n_max + kScanTile - 1) / kScanTile;
+  int64_t parts = (n_max + kScanTileMin - 1) / kScanTileMin;
   return 256 + (size_t)std::max<int64_t>(parts, 1) * 8;
 }
 
@@ -379,14 +387,19 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* o
   }
   uint32_t* counter = static_cast<uint32_t*>(tmp);
   uint64_t* flags = reinterpret_cast<uint64_t*>(static_cast<char*>(tmp) + 256);
-  int64_t parts = (n_max + kScanTile - 1) / kScanTile;
+  const int64_t tile = idx ? 512 * 8 : 1024 * 16;
+  const int64_t parts = (n_max + tile - 1) / tile;
   if (!cleared) {
     const int cb = (int)std::min<int64_t>(1024, (parts + 255) / 256 + 1);
     hipLaunchKernelGGL(k_scan_clear, dim3(cb), dim3(256), 0, st, counter, flags, total, n_dev,
                        n_max);
   }
-  hipLaunchKernelGGL(k_scan, dim3((unsigned)parts), dim3(kScanBlock), 0, st, in, idx, out, total,
-                     n_dev, n_max, counter, flags, status, flags_mode);
+  if (idx)
+    hipLaunchKernelGGL((k_scan<512, 8>), dim3((unsigned)parts), dim3(512), 0, st, in, idx, out,
+                       total, n_dev, n_max, counter, flags, status, flags_mode);
+  else
+    hipLaunchKernelGGL((k_scan<1024, 16>), dim3((unsigned)parts), dim3(1024), 0, st, in, idx, out,
+                       total, n_dev, n_max, counter, flags, status, flags_mode);
   return hipGetLastError();
 }
 
