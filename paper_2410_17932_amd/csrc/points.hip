@@ -575,6 +575,9 @@ __global__ __launch_bounds__(256) void k_pt_rank(const uint4* __restrict__ seg,
 
 // ----------------------------------------------------------------- blend
 // One thread per layer pixel: its list front to back (zero where empty).
+// Pixels go in reverse pyramid order: each crop's coarse layers (the long
+// lists) come after its finest layer in the pyramid, so in reverse the
+// long lists start early and the finest layers' short lists fill the end.
 __global__ __launch_bounds__(256) void k_pt_blend(const uint64_t* __restrict__ fval,
                                                   const uint32_t* __restrict__ poff,
                                                   const uint32_t* __restrict__ total_p,
@@ -583,8 +586,9 @@ __global__ __launch_bounds__(256) void k_pt_blend(const uint64_t* __restrict__ f
                                                   const float* __restrict__ opacity, int64_t np,
                                                   int64_t pix_total, float4* __restrict__ pyr) {
   const bool over = (int64_t)*total_p > max_frags;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < pix_total;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t kr = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; kr < pix_total;
+       kr += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = pix_total - 1 - kr;
     float T = 1.0f;
     float4 F = make_float4(0, 0, 0, 0);
     const uint32_t start = over ? 0u : poff[k], n = over ? 0u : poff[k + 1] - start;
