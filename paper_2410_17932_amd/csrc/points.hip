@@ -549,7 +549,8 @@ __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__
 // offset plus the number of the segment's records before it in (depth key,
 // point index) order (a point reaches a layer pixel at most once, so the
 // pairs are distinct).  Consecutive places share segments, so the lanes of
-// a segment read the same records.
+// a segment read the same records; places go in reverse, so that the long
+// segments of each crop's coarse layers start early.
 __global__ __launch_bounds__(256) void k_pt_rank(const uint4* __restrict__ seg,
                                                  const uint32_t* __restrict__ poff,
                                                  const uint32_t* __restrict__ total_p,
@@ -559,9 +560,9 @@ __global__ __launch_bounds__(256) void k_pt_rank(const uint4* __restrict__ seg,
   const int64_t total = *total_p;
   if (total > max_frags) return;
   const uint64_t* key = reinterpret_cast<const uint64_t*>(seg);   // depth key << 32 | index
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < total;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    const uint4 rec = seg[s];
+  for (int64_t sr = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sr < total;
+       sr += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 rec = seg[total - 1 - sr];
     if (rec.w >= pix_total) continue;   // every place is filled; never taken
     const uint64_t own = ((uint64_t)rec.y << 32) | rec.x;
     const uint32_t start = poff[rec.w], n = poff[rec.w + 1] - start;
