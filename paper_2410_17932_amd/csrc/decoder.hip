@@ -154,8 +154,10 @@ struct HeadFuse {
 
 // Geometry of one workgroup's LDS: halo tile, the coarser level's footprint
 // and the weights.  ONE: the whole weight operand (up to 24 KB) is loaded
-// once, at the start, overlapping the halo fill; otherwise two 8 KB chunks
-// of CHS k-steps are double-buffered.
+// once, at the start, overlapping the halo fill; otherwise two chunks of CHS
+// k-steps are double-buffered: 8 KB, or 4 KB for two N-tiles, whose level
+// (the finest) is bound by the halo fill's latency, so four workgroups per
+// CU (38 KB each) beat whole weights at three.
 template <typename T, int NT, bool ONE>
 struct ConvCfg {
   // 8-row tiles where the accumulators would leave one wave per SIMD
@@ -165,7 +167,7 @@ struct ConvCfg {
   static constexpr int CR = TH / 2 + 2, CC = 10;       // coarse rows / columns staged
   static constexpr int NOUT = NT * 16;
   static constexpr int NBUF = ONE ? 1 : 2;
-  static constexpr int CBYTES = ONE ? 24576 : 8192;
+  static constexpr int CBYTES = ONE ? 24576 : (NT <= 2 ? 4096 : 8192);
   static constexpr int CHS = CBYTES / (NOUT * KSTEP * (int)sizeof(T)) > 0
                                  ? CBYTES / (NOUT * KSTEP * (int)sizeof(T)) : 1;
   static constexpr int CK = CHS * KSTEP;                // k per chunk
@@ -722,9 +724,10 @@ template <typename T, int NT>
 static hipError_t launch_nt(const DecLevel& d, int blocks, const float* pyr, const float* periph,
                             const T* hn, const T* wp, const float* bp, T* h, float* pre,
                             const HeadFuse& hf, hipStream_t st) {
-  // the whole weight operand in one LDS chunk when it fits
+  // the whole weight operand in one LDS chunk when it fits (not with two
+  // N-tiles: see ConvCfg)
   using One = ConvCfg<T, NT, true>;
-  const bool one = d.kpad <= One::CK;
+  const bool one = NT > 2 && d.kpad <= One::CK;
   const size_t need = one ? conv_smem_bytes<T, NT, true>(d.cin8, d.kn, d.kpad)
                           : conv_smem_bytes<T, NT, false>(d.cin8, d.kn, d.kpad);
   if (need > max_lds_bytes()) return hipErrorInvalidValue;
