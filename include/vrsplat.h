@@ -294,7 +294,9 @@ vrs_status vrs_decode_fovea_backward(const float* pyramid, int levels,
  *     f_p = (r_n - m)/(1 - m) (Eq. 3), f_e = |Sobel(mean_rgb(F))|/4 with
  *     replicated crop borders (Eq. 4), c = 1 - S2(clamp(f_p + gamma f_e, 0,
  *     1)), S2(x) = 6x^5 - 15x^4 + 10x^3 (Eq. 5);
- *   out = (1 - c) out + c F.  Elsewhere out = P. */
+ *   out = (1 - c) out + c F.  Elsewhere out = P.
+ * out may be rgb_periphery itself (in place): then only the pixels under
+ * the crops are read and written (the rest already hold P). */
 vrs_status vrs_composite_frame(const float* rgb_periphery, int n_views, int width, int height,
                                const float* fovea_rgb, const vrs_crop* crops, int n_crops,
                                int mode, float ring, float m, float gamma, float* out,

@@ -5,7 +5,8 @@
 // One thread per four full-frame pixels of a row (one per pixel when the
 // width is not a multiple of 4): the crop table travels as a kernel argument,
 // each pixel walks the crops of its view in index order.  HBM-bound: P is
-// read and out written once; F is read only under the crops.
+// read and out written once; F is read only under the crops.  In place (out
+// is P) only the four-pixel groups under some crop are read and written.
 #include "vrs_common.h"
 
 namespace vrs {
@@ -61,9 +62,8 @@ __device__ inline float blend_mask(const CompArgs& a, int k, const float* F, int
   return 1.0f - smootherstep(clamp01(u_out));
 }
 
-__global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* __restrict__ P,
-                                                   const float* __restrict__ F,
-                                                   float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* P,
+                                                   const float* __restrict__ F, float* out) {
   const long long plane = (long long)a.W * a.H;
   const long long total = plane * a.nv;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -100,6 +100,51 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* __re
 // Same per pixel as k_composite, four consecutive pixels of a row per thread
 // (W % 4 == 0): 16-byte loads and stores of P and out, crops rejected once
 // per four pixels.
+// Four pixels (v, y, x..x+3) of a row: their crop chain from P into out
+// (which may be P: every read comes before the writes).
+__device__ inline void comp_quad(const CompArgs& a, const float* P, const float* __restrict__ F,
+                                 float* out, int v, int y, int x) {
+  const long long plane = (long long)a.W * a.H;
+  const long long base = (long long)v * 3 * plane + (long long)y * a.W + x;
+  float4 c4[3] = {*reinterpret_cast<const float4*>(P + base),
+                  *reinterpret_cast<const float4*>(P + base + plane),
+                  *reinterpret_cast<const float4*>(P + base + 2 * plane)};
+  float o[3][4];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    o[ch][0] = c4[ch].x; o[ch][1] = c4[ch].y; o[ch][2] = c4[ch].z; o[ch][3] = c4[ch].w;
+  }
+  for (int k = 0; k < a.n_crops; ++k) {
+    if (a.view[k] != v) continue;
+    const int S = a.S[k], ly = y - a.y0[k];
+    if (ly < 0 || ly >= S || x + 3 < a.x0[k] || x >= a.x0[k] + S) continue;
+    const float* Fk = F + a.fbase[k];
+    const long long fp = (long long)S * S;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int lx = x + j - a.x0[k];
+      if (lx < 0 || lx >= S) continue;
+      {
+        // outside the crop's inscribed circle the mask is 0 in both modes
+        // (the same operations as blend_mask): the pixel keeps its value
+        const float dx = (float)(a.x0[k] + lx) + 0.5f - a.gx[k];
+        const float dy = (float)(a.y0[k] + ly) + 0.5f - a.gy[k];
+        if (!(sqrtf(dx * dx + dy * dy) < 0.5f * (float)S)) continue;
+      }
+      float u, gx, gy;
+      const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy);
+      const long long fo = (long long)ly * S + lx;
+      o[0][j] = (1.0f - c) * o[0][j] + c * Fk[fo];
+      o[1][j] = (1.0f - c) * o[1][j] + c * Fk[fp + fo];
+      o[2][j] = (1.0f - c) * o[2][j] + c * Fk[2 * fp + fo];
+    }
+  }
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch)
+    *reinterpret_cast<float4*>(out + base + ch * plane) =
+        make_float4(o[ch][0], o[ch][1], o[ch][2], o[ch][3]);
+}
+
 __global__ __launch_bounds__(256) void k_composite4(CompArgs a, const float* __restrict__ P,
                                                     const float* __restrict__ F,
                                                     float* __restrict__ out) {
@@ -110,45 +155,28 @@ __global__ __launch_bounds__(256) void k_composite4(CompArgs a, const float* __r
     const int v = (int)(q / qplane);
     const long long pi = (q - v * qplane) * 4;
     const int y = (int)(pi / a.W), x = (int)(pi - (long long)y * a.W);
-    const long long base = (long long)v * 3 * plane + pi;
-    float4 c4[3] = {*reinterpret_cast<const float4*>(P + base),
-                    *reinterpret_cast<const float4*>(P + base + plane),
-                    *reinterpret_cast<const float4*>(P + base + 2 * plane)};
-    float o[3][4];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      o[ch][0] = c4[ch].x; o[ch][1] = c4[ch].y; o[ch][2] = c4[ch].z; o[ch][3] = c4[ch].w;
-    }
-    for (int k = 0; k < a.n_crops; ++k) {
-      if (a.view[k] != v) continue;
-      const int S = a.S[k], ly = y - a.y0[k];
-      if (ly < 0 || ly >= S || x + 3 < a.x0[k] || x >= a.x0[k] + S) continue;
-      const float* Fk = F + a.fbase[k];
-      const long long fp = (long long)S * S;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int lx = x + j - a.x0[k];
-        if (lx < 0 || lx >= S) continue;
-        {
-          // outside the crop's inscribed circle the mask is 0 in both modes
-          // (the same operations as blend_mask): the pixel keeps its value
-          const float dx = (float)(a.x0[k] + lx) + 0.5f - a.gx[k];
-          const float dy = (float)(a.y0[k] + ly) + 0.5f - a.gy[k];
-          if (!(sqrtf(dx * dx + dy * dy) < 0.5f * (float)S)) continue;
-        }
-        float u, gx, gy;
-        const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy);
-        const long long fo = (long long)ly * S + lx;
-        o[0][j] = (1.0f - c) * o[0][j] + c * Fk[fo];
-        o[1][j] = (1.0f - c) * o[1][j] + c * Fk[fp + fo];
-        o[2][j] = (1.0f - c) * o[2][j] + c * Fk[2 * fp + fo];
-      }
-    }
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch)
-      *reinterpret_cast<float4*>(out + base + ch * plane) =
-          make_float4(o[ch][0], o[ch][1], o[ch][2], o[ch][3]);
+    comp_quad(a, P, F, out, v, y, x);
   }
+}
+
+// In place: workgroup (b, k) takes crop k's four-pixel groups [256 b,
+// 256 b + 256) in row order over the crop's rows and the groups its columns
+// touch; a group under several crops is done once, by the first of them,
+// with the whole crop chain.  Pixels under no crop are not touched.
+__global__ __launch_bounds__(256) void k_composite4_inplace(CompArgs a, float* io,
+                                                            const float* __restrict__ F) {
+  const int kc = blockIdx.y;
+  const int S = a.S[kc], v = a.view[kc];
+  const int gx0 = a.x0[kc] >> 2, ng = ((a.x0[kc] + S - 1) >> 2) - gx0 + 1;
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= (long long)S * ng) return;
+  const int ly = (int)(i / ng);
+  const int y = a.y0[kc] + ly, x = (gx0 + (int)(i - (long long)ly * ng)) * 4;
+  for (int k = 0; k < kc; ++k)
+    if (a.view[k] == v && y >= a.y0[k] && y < a.y0[k] + a.S[k] && x + 3 >= a.x0[k] &&
+        x < a.x0[k] + a.S[k])
+      return;   // an earlier crop's group
+  comp_quad(a, io, F, io, v, y, x);
 }
 
 // Adjoint.  Per pixel the crop chain is replayed forward to recover the
@@ -325,7 +353,15 @@ extern "C" vrs_status vrs_composite_frame(const float* rgb_periphery, int n_view
   trace_begin(VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
   const bool vec4 = width % 4 == 0 && (reinterpret_cast<uintptr_t>(rgb_periphery) & 15) == 0 &&
                     (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-  if (vec4) {
+  if (vec4 && out == rgb_periphery) {
+    long long most = 0;   // four-pixel groups of the largest crop
+    for (int k = 0; k < n_crops; ++k)
+      most = std::max<long long>(most, (long long)crops[k].size *
+                                           (((crops[k].x0 + crops[k].size - 1) >> 2) - (crops[k].x0 >> 2) + 1));
+    if (n_crops > 0)
+      hipLaunchKernelGGL(k_composite4_inplace, dim3((unsigned)((most + 255) / 256), n_crops),
+                         dim3(256), 0, static_cast<hipStream_t>(stream), a, out, fovea_rgb);
+  } else if (vec4) {
     const int blocks = (int)std::min<long long>(16384, (total / 4 + 255) / 256);
     hipLaunchKernelGGL(k_composite4, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
                        a, rgb_periphery, fovea_rgb, out);

@@ -28,7 +28,11 @@ class Frame:
     def __init__(self, scene: dict, decoder_dtype: int = api.VRS_BF16, tile: int = 16,
                  mode: int = api.BLEND_LINEAR, ring: float = 64.0, m: float = 0.75,
                  gamma: float = 0.2, cull: bool = True, pair_margin: float = 1.10,
-                 frag_margin: float = 1.25, spatial_order: bool = True):
+                 frag_margin: float = 1.25, spatial_order: bool = True,
+                 in_place: bool = True):
+        # in_place: the combination writes into the periphery image, touching
+        # only the pixels under the crops (run() returns that image)
+        self.in_place = in_place
         g, p = scene["gaussians"], scene["points"]
         self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
         self.sh_degree = g["sh_degree"]
@@ -66,7 +70,7 @@ class Frame:
         self.depth = torch.empty((V, H, W), device=dev)
         self.tfinal = torch.empty((V, H, W), device=dev)
         self.ncontrib = torch.empty((V, H, W), device=dev, dtype=torch.int32)
-        self.out = torch.empty((V, 3, H, W), device=dev)
+        self.out = self.rgb if self.in_place else torch.empty((V, 3, H, W), device=dev)
         self.r_out = dict(rgb=self.rgb, depth=self.depth, tfinal=self.tfinal, ncontrib=self.ncontrib)
         # counting pass: capacity 1 computes the totals on the device
         ws = api.RenderWorkspace(self.n, self.views, self.opts, 1)

@@ -66,3 +66,23 @@ def test_composite_parity(mode, W):
     torch.cuda.synchronize()
     err = np.abs(out.cpu().numpy() - ref).max()
     assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("mode", [api.BLEND_LINEAR, api.BLEND_PAPER])
+@pytest.mark.parametrize("W", [180, 181])
+def test_composite_in_place(mode, W):
+    """Combination into the periphery image itself (only the pixels under the
+    crops are touched, overlapping crops once each) equals the combination
+    into a separate image bit for bit."""
+    rng = np.random.default_rng(9)
+    H = 150
+    crops = [synth.crop_at(0, 60.3, 70.7, 64, W, H), synth.crop_at(0, 80.0, 80.0, 96, W, H),
+             synth.crop_at(0, 70.0, 60.0, 32, W, H), synth.crop_at(1, 170.0, 10.0, 32, W, H),
+             synth.crop_at(1, 90.0, 75.0, 128, W, H)]
+    P = dev(rng.uniform(size=(2, 3, H, W)).astype(np.float32))
+    F = dev(rng.uniform(size=sum(3 * c.size ** 2 for c in crops)).astype(np.float32))
+    sep = api.composite_frame(P, F, crops, mode=mode, ring=16.0)
+    io = P.clone()
+    api.composite_frame(io, F, crops, mode=mode, ring=16.0, out=io)
+    torch.cuda.synchronize()
+    assert torch.equal(io, sep)
