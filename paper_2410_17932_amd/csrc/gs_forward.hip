@@ -968,13 +968,15 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     trace_end(VRS_TRACE_GS_PREPROCESS, st);
     trace_begin(VRS_TRACE_GS_DEPTH_SORT, st);
     bool d1 = false;
+    // the last pass also lays the super-tile counts out in depth order
     VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
                                  at<uint32_t>(ws, L.dkey1), at<uint32_t>(ws, L.dval1), nullptr, vn,
-                                 32, at<void>(ws, L.sort_tmp), dev_status, st, &d1));
+                                 32, at<void>(ws, L.sort_tmp), dev_status, st, &d1,
+                                 at<uint32_t>(ws, L.nsup), at<uint32_t>(ws, L.nsorted)));
     const uint32_t* sorted_e = at<uint32_t>(ws, d1 ? L.dval1 : L.dval0);
-    VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.nsup), sorted_e, at<uint32_t>(ws, L.soffs),
-                                     super_count, nullptr, vn, at<void>(ws, L.scan_tmp),
-                                     dev_status, st, true));
+    VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.nsorted), nullptr,
+                                     at<uint32_t>(ws, L.soffs), super_count, nullptr, vn,
+                                     at<void>(ws, L.scan_tmp), dev_status, st, true));
     trace_end(VRS_TRACE_GS_DEPTH_SORT, st);
     trace_begin(VRS_TRACE_GS_EMIT, st);
     hipLaunchKernelGGL(k_gs_emit_super, dim3(div_up(vn, kEmitBlock)), dim3(kEmitBlock), 0, st,

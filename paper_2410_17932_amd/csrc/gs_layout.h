@@ -10,7 +10,7 @@ namespace vrs {
 constexpr int kSuper = 8;
 
 struct RenderWs {
-  size_t rec, dkey0, dval0, dkey1, dval1, nsup, soffs, psum, pair_count, super_count,
+  size_t rec, dkey0, dval0, dkey1, dval1, nsup, nsorted, soffs, psum, pair_count, super_count,
       skey0, sval0, skey1, sval1,   // (super-tile, Gaussian) pairs
       srange, ubase, nunits,        // per super-tile run and first work unit
       ucnt, tcnt, toff,             // per (unit, tile) and per tile counts, tile offsets
@@ -60,6 +60,7 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->dkey1 = c.take(vn * 4);
   L->dval1 = c.take(vn * 4);
   L->nsup = c.take(vn * 4);
+  L->nsorted = c.take(vn * 4);   // nsup in depth order
   L->soffs = c.take(vn * 4);
   L->psum = c.take((size_t)(vn + 255) / 256 * 8);   // per preprocess block: tile pairs
   L->pair_count = c.take(4);

@@ -245,7 +245,8 @@ template <typename V>
 __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
     const uint32_t* __restrict__ kin, const V* __restrict__ vin, uint32_t* __restrict__ kout,
     V* __restrict__ vout, const uint32_t* n_dev, int64_t n_max, int shift, int64_t parts,
-    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals) {
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
+    const uint32_t* __restrict__ gsrc, uint32_t* __restrict__ gdst) {
   __shared__ uint32_t s_wh[kSortWaves][256];
   __shared__ uint32_t s_lstart[256], s_gstart[256], s_scan[kSortWaves];
   __shared__ uint32_t s_keys[kSortTile];
@@ -333,6 +334,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
       const uint32_t g = s_gstart[dk] + (uint32_t)i - s_lstart[dk];
       kout[g] = k;
       vout[g] = s_vals[i];
+      if (gdst) gdst[g] = gsrc[(uint64_t)s_vals[i]];   // last pass: gather in sorted order
     }
     __syncthreads();   // LDS is rewritten by the next partition
   }
@@ -341,7 +343,8 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
 template <typename V>
 hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t* n_dev,
                            int64_t n_max, int key_bits, void* tmp, int32_t* status,
-                           hipStream_t st, bool* result_in_1) {
+                           hipStream_t st, bool* result_in_1, const uint32_t* gather_src,
+                           uint32_t* gather_dst) {
   (void)status;   // nothing in the sort waits on another workgroup
   const int passes = key_bits <= 0 ? 0 : (key_bits + 7) / 8;
   *result_in_1 = (passes & 1) != 0;
@@ -357,9 +360,11 @@ hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint3
                        n_dev, n_max, 8 * p, parts, counts);
     hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, st, counts, n_dev, n_max, parts,
                        totals);
+    const bool last = p == passes - 1;
     hipLaunchKernelGGL(k_sort_scatter<V>, dim3(grid), dim3(kSortBlock), 0, st,
                        kb[p & 1], vb[p & 1], kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, n_max,
-                       8 * p, parts, counts, totals);
+                       8 * p, parts, counts, totals, last ? gather_src : nullptr,
+                       last ? gather_dst : nullptr);
   }
   return hipGetLastError();
 }
@@ -426,16 +431,17 @@ size_t sort_tmp_bytes(int64_t n_max, int key_bits) {
 
 hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
-                          int32_t* status, hipStream_t st, bool* result_in_1) {
+                          int32_t* status, hipStream_t st, bool* result_in_1,
+                          const uint32_t* gather_src, uint32_t* gather_dst) {
   return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, status, st,
-                                   result_in_1);
+                                   result_in_1, gather_src, gather_dst);
 }
 
 hipError_t radix_sort_u64(uint32_t* k0, uint64_t* v0, uint32_t* k1, uint64_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
                           int32_t* status, hipStream_t st, bool* result_in_1) {
   return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, status, st,
-                                   result_in_1);
+                                   result_in_1, nullptr, nullptr);
 }
 
 }  // namespace vrs

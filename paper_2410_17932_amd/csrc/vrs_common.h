@@ -95,9 +95,13 @@ hipError_t exclusive_scan_flags_u32(const uint32_t* in, uint32_t* out, uint32_t*
 // between (k0, v0) and (k1, v1); returns through *result_in_1 whether the
 // sorted data ended in the second buffer.  n = min(*n_dev, n_max).
 size_t sort_tmp_bytes(int64_t n_max, int key_bits);
+// gather_src/gather_dst (both or neither): the last pass also writes
+// gather_dst[i] = gather_src[value i] in sorted order (a per-value word
+// carried into the sorted order without a pass of its own).
 hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
-                          int32_t* status, hipStream_t st, bool* result_in_1);
+                          int32_t* status, hipStream_t st, bool* result_in_1,
+                          const uint32_t* gather_src = nullptr, uint32_t* gather_dst = nullptr);
 hipError_t radix_sort_u64(uint32_t* k0, uint64_t* v0, uint32_t* k1, uint64_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
                           int32_t* status, hipStream_t st, bool* result_in_1);
