@@ -20,11 +20,13 @@
 //   k_gs_bin_count    one wave per unit: per tile (tile = lane of an 8 x 8
 //                     super-tile) the unit's pairs reaching it, from row
 //                     and column ballots
-//   k_gs_bin_prefix   per super-tile: prefix of those counts over its units
-//                     and the tile totals
-//   k_gs_schedule     one workgroup: tile list offsets (scan of the tile
-//                     totals), [begin, end) per tile and the blend order,
-//                     longest list first (counting sort by length bucket)
+//   k_gs_bin_prefix   per super-tile: prefix of those counts over its units,
+//                     the tile totals and their length buckets; the last
+//                     workgroup scans the super-tile totals (lists are laid
+//                     out super-tile by super-tile) and the bucket counts
+//   k_gs_schedule     one wave per super-tile: tile list offsets,
+//                     [begin, end) per tile and the blend order, longest
+//                     list first (counting sort by length bucket)
 //   k_gs_bin_scatter  one wave per unit: every Gaussian index goes to its
 //                     final place in each tile list it belongs to, its rank
 //                     within a round from one ballot per tile
@@ -414,11 +416,43 @@ __global__ __launch_bounds__(256) void k_gs_bin_count(const uint64_t* __restrict
 // One workgroup per super-tile: exclusive prefix of its units' counts per
 // tile (in place) and the tile totals.  Wave w takes a contiguous share of
 // the units, loads kPrefixBatch of them at a time.
+// Device-coherent word access for the last-workgroup hand-over below.
+__device__ inline uint32_t coh_load32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void coh_store32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Length bucket of a tile list: descending in 16 log2(1 + length), so that
+// the blend runs long lists first (work per tile is very uneven, and
+// starting the long lists first keeps them off the end of the blend).
+__device__ inline uint32_t sched_bucket(uint32_t len) {
+  const float lb = 16.0f * log2f(1.0f + (float)len);
+  return 255u - (uint32_t)fminf(lb, 255.0f);
+}
+// The active lanes holding the same 8-bit value b (eight ballots): one
+// atomic per distinct bucket of a wave.
+__device__ inline uint64_t match_u8(uint32_t b) {
+  uint64_t m = __ballot(true);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const bool bit = (b >> i) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
 constexpr int kPrefixWaves = 16, kPrefixBatch = 8;
 __global__ __launch_bounds__(64 * kPrefixWaves) void k_gs_bin_prefix(
     const uint32_t* __restrict__ ubase, int64_t sxn, int64_t spv, int64_t tiles_x,
-    int64_t tiles_y, uint32_t* __restrict__ ucnt, uint32_t* __restrict__ tcnt) {
+    int64_t tiles_y, uint32_t* __restrict__ ucnt, uint32_t* __restrict__ tcnt,
+    const uint32_t* __restrict__ total_p, int64_t max_pairs, int64_t st_total,
+    uint32_t* __restrict__ stot, uint32_t* __restrict__ sbase, uint32_t* __restrict__ sched) {
   __shared__ uint32_t s_c[kPrefixWaves][64];
+  __shared__ uint32_t s_w[kPrefixWaves];
+  __shared__ bool s_last;
   const int64_t s = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t u0 = ubase[s], nu = ubase[s + 1] - u0;
@@ -453,75 +487,61 @@ __global__ __launch_bounds__(64 * kPrefixWaves) void k_gs_bin_prefix(
     }
   }
   int64_t t;
-  if (wave == 0 && bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t)) tcnt[t] = tot;
-}
-
-// Tile list offsets (exclusive scan of the tile totals in tile order), tile
-// ranges and the blend schedule, in one workgroup: tiles ordered by
-// length bucket, descending in 16 log2(1 + length) (work per tile is very
-// uneven, and starting the long lists first keeps them off the end of the
-// blend).  A counting sort: bucket histogram, its scan, then each tile takes
-// the next place of its bucket (the order within a bucket is free: tiles
-// are independent).  Past the capacity every list is left empty.
-constexpr int kSchedBlock = 1024, kSchedItems = 8;
-__device__ inline uint32_t sched_bucket(uint32_t len) {
-  const float lb = 16.0f * log2f(1.0f + (float)len);
-  return 255u - (uint32_t)fminf(lb, 255.0f);
-}
-__global__ __launch_bounds__(kSchedBlock) void k_gs_schedule(
-    const uint32_t* __restrict__ tcnt, const uint32_t* __restrict__ total_p, int64_t max_pairs,
-    int64_t tiles_total, uint32_t* __restrict__ toff, uint2* __restrict__ ranges,
-    uint32_t* __restrict__ order, int32_t* status) {
-  __shared__ uint32_t s_hist[256], s_base[256], s_wsum[kSchedBlock / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool over = (int64_t)*total_p > max_pairs;
-  if (tid == 0 && over) set_status(status, VRS_ECAPACITY);
-  if (tid < 256) s_hist[tid] = 0;
-  __syncthreads();
-  constexpr int64_t kStep = (int64_t)kSchedBlock * kSchedItems;
-  uint32_t carry = 0;   // pairs of the tiles before the chunk
-  for (int64_t t0 = 0; t0 < tiles_total; t0 += kStep) {
-    // thread tid owns kSchedItems consecutive tiles of the chunk
-    const int64_t tb = t0 + (int64_t)tid * kSchedItems;
-    uint32_t c[kSchedItems], ex[kSchedItems], sum = 0;
+  if (wave == 0) {
+    // the tile totals, the super-tile's total and the tiles' length buckets
+    // (past the capacity every list is empty)
+    const bool valid = bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t);
+    const uint32_t c = valid && (int64_t)*total_p <= max_pairs ? tot : 0u;
+    if (valid) tcnt[t] = tot;
+    uint32_t st = c;
 #pragma unroll
-    for (int k = 0; k < kSchedItems; ++k) {
-      c[k] = tb + k < tiles_total && !over ? tcnt[tb + k] : 0u;
-      ex[k] = sum;
-      sum += c[k];
+    for (int o = 32; o > 0; o >>= 1) st += __shfl_xor(st, o, 64);
+    if (lane == 0) coh_store32(&stot[s], st);
+    if (valid) {
+      const uint32_t bk = sched_bucket(c);
+      const uint64_t m = match_u8(bk);
+      if (lane == __builtin_ctzll(m)) atomicAdd(&sched[kSchedHist + bk], (uint32_t)__popcll(m));
     }
-    uint32_t incl = sum;
+  }
+  // the last workgroup to finish: list bases of the super-tiles (their tile
+  // lists are laid out super-tile by super-tile) and the bucket cursors.
+  // The hand-over words are device-coherent (agent-scope store, device
+  // atomics); wave 0, which wrote them, waits until they have completed
+  // before it counts the workgroup done.
+  if (wave == 0) {
+    __builtin_amdgcn_s_waitcnt(0);   // every counter drained: vector memory included
+    if (lane == 0) s_last = atomicAdd(&sched[kSchedDone], 1u) == (uint32_t)(st_total - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < st_total; b0 += 64 * kPrefixWaves) {
+    const int64_t i = b0 + tid;
+    const uint32_t x = i < st_total ? coh_load32(&stot[i]) : 0u;
+    uint32_t incl = x;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t y = __shfl_up(incl, o, 64);
       if (lane >= o) incl += y;
     }
-    if (lane == 63) s_wsum[wave] = incl;
+    if (lane == 63) s_w[wave] = incl;
     __syncthreads();
     uint32_t woff = 0, btot = 0;
 #pragma unroll
-    for (int w = 0; w < kSchedBlock / 64; ++w) {
-      if (w < wave) woff += s_wsum[w];
-      btot += s_wsum[w];
+    for (int w = 0; w < kPrefixWaves; ++w) {
+      woff += w < wave ? s_w[w] : 0u;
+      btot += s_w[w];
     }
-    const uint32_t base = carry + woff + incl - sum;
-#pragma unroll
-    for (int k = 0; k < kSchedItems; ++k)
-      if (tb + k < tiles_total) {
-        const uint32_t b = base + ex[k];
-        toff[tb + k] = b;
-        ranges[tb + k] = make_uint2(b, b + c[k]);
-        atomicAdd(&s_hist[sched_bucket(c[k])], 1u);
-      }
+    if (i < st_total) sbase[i] = carry + woff + incl - x;
     carry += btot;
-    __syncthreads();   // s_wsum is rewritten by the next chunk
+    __syncthreads();   // s_w is rewritten by the next chunk
   }
   if (wave == 0) {   // exclusive scan of the 256 buckets, four per lane
     uint32_t h[4], sum = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       h[q] = sum;
-      sum += s_hist[lane * 4 + q];
+      sum += coh_load32(&sched[kSchedHist + lane * 4 + q]);
     }
     uint32_t incl = sum;
 #pragma unroll
@@ -530,22 +550,45 @@ __global__ __launch_bounds__(kSchedBlock) void k_gs_schedule(
       if (lane >= o) incl += y;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s_base[lane * 4 + q] = incl - sum + h[q];
+    for (int q = 0; q < 4; ++q) sched[kSchedCursor + lane * 4 + q] = incl - sum + h[q];
   }
-  __syncthreads();
-  for (int64_t t0 = 0; t0 < tiles_total; t0 += kStep) {
-    uint32_t c[kSchedItems];
+}
+
+// One wave per super-tile, one lane per tile: the tile's list offset (its
+// super-tile's base plus the counts of the super-tile's earlier tiles), its
+// [begin, end) range and its place in the blend order (the next place of
+// its length bucket; the order within a bucket is free: tiles are
+// independent).  Past the capacity every list is left empty.
+__global__ __launch_bounds__(64) void k_gs_schedule(
+    const uint32_t* __restrict__ tcnt, const uint32_t* __restrict__ sbase,
+    const uint32_t* __restrict__ total_p, int64_t max_pairs, int64_t sxn, int64_t spv,
+    int64_t tiles_x, int64_t tiles_y, uint32_t* __restrict__ sched, uint32_t* __restrict__ toff,
+    uint2* __restrict__ ranges, uint32_t* __restrict__ order, int32_t* status) {
+  const int64_t s = blockIdx.x;
+  const int lane = threadIdx.x;
+  const bool over = (int64_t)*total_p > max_pairs;
+  if (s == 0 && lane == 0 && over) set_status(status, VRS_ECAPACITY);
+  int64_t t;
+  const bool valid = bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t);
+  const uint32_t c = valid && !over ? tcnt[t] : 0u;
+  uint32_t incl = c;
 #pragma unroll
-    for (int k = 0; k < kSchedItems; ++k) {
-      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
-      c[k] = t < tiles_total && !over ? tcnt[t] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kSchedItems; ++k) {
-      const int64_t t = t0 + (int64_t)k * kSchedBlock + tid;
-      if (t < tiles_total) order[atomicAdd(&s_base[sched_bucket(c[k])], 1u)] = (uint32_t)t;
-    }
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
   }
+  if (!valid) return;
+  const uint32_t b = sbase[s] + incl - c;
+  toff[t] = b;
+  ranges[t] = make_uint2(b, b + c);
+  const uint32_t bk = sched_bucket(c);
+  const uint64_t m = match_u8(bk);
+  const int leader = __builtin_ctzll(m);
+  uint32_t at = 0;
+  if (lane == leader) at = atomicAdd(&sched[kSchedCursor + bk], (uint32_t)__popcll(m));
+  at = __shfl(at, leader, 64);
+  order[at + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint32_t)t;
 }
 
 // Per unit: tile l's cursor starts at the tile's list offset plus the counts
@@ -963,7 +1006,8 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                        opacity, sh, sh_degree, n, kv, o, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
                        at<uint32_t>(ws, L.nsup), at<uint64_t>(ws, L.psum),
-                       at<uint32_t>(ws, L.scan_tmp), (int64_t)(scan_tmp_bytes(vn) / 4));
+                       at<uint32_t>(ws, L.scan_tmp),
+                       (int64_t)((L.sched - L.scan_tmp) / 4 + kSchedDone + 1));
     VRS_LAUNCH_CHECK();
     trace_end(VRS_TRACE_GS_PREPROCESS, st);
     trace_begin(VRS_TRACE_GS_DEPTH_SORT, st);
@@ -995,6 +1039,7 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
     trace_begin(VRS_TRACE_GS_SORT, st);
     VRS_HIP_CHECK(fill_u32(super_count, 0, 1, st));
     VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, L.srange), 0, 2 * L.st_total, st));
+    VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, L.sched), 0, kSchedDone + 1, st));
   }
   // binning: runs, units, per unit and tile counts, tile offsets, ranges and
   // the longest-first schedule, scatter.  Timed with the sorts, so the blend
@@ -1022,11 +1067,15 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   VRS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_gs_bin_prefix, dim3((unsigned)L.st_total), dim3(64 * kPrefixWaves), 0, st,
                      at<uint32_t>(ws, L.ubase), L.sxn, L.spv, L.tiles_x, L.tiles_y,
-                     at<uint32_t>(ws, L.ucnt), at<uint32_t>(ws, L.tcnt));
+                     at<uint32_t>(ws, L.ucnt), at<uint32_t>(ws, L.tcnt), pair_count, max_pairs,
+                     L.st_total, at<uint32_t>(ws, L.stot), at<uint32_t>(ws, L.sbase),
+                     at<uint32_t>(ws, L.sched));
   VRS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gs_schedule, dim3(1), dim3(kSchedBlock), 0, st, at<uint32_t>(ws, L.tcnt),
-                     pair_count, max_pairs, L.tiles_total, at<uint32_t>(ws, L.toff),
-                     at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.order), dev_status);
+  hipLaunchKernelGGL(k_gs_schedule, dim3((unsigned)L.st_total), dim3(64), 0, st,
+                     at<uint32_t>(ws, L.tcnt), at<uint32_t>(ws, L.sbase), pair_count, max_pairs,
+                     L.sxn, L.spv, L.tiles_x, L.tiles_y, at<uint32_t>(ws, L.sched),
+                     at<uint32_t>(ws, L.toff), at<uint2>(ws, L.ranges), at<uint32_t>(ws, L.order),
+                     dev_status);
   VRS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_gs_bin_scatter, dim3(unit_blocks), dim3(256), 0, st, svals,
                      at<uint2>(ws, L.srange), at<uint32_t>(ws, L.ubase),

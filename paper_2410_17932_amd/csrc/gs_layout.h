@@ -8,15 +8,22 @@ namespace vrs {
 // Tiles are grouped in super-tiles of kSuper x kSuper tiles (one tile per
 // lane of a wave) for binning.
 constexpr int kSuper = 8;
+// Tile schedule words: [0, 256) length-bucket histogram, 256 the count of
+// finished prefix workgroups (both zeroed before the binning), [320, 576)
+// the bucket cursors.
+constexpr int kSchedHist = 0, kSchedDone = 256, kSchedCursor = 320, kSchedWords = 576;
 
 struct RenderWs {
   size_t rec, dkey0, dval0, dkey1, dval1, nsup, nsorted, soffs, psum, pair_count, super_count,
       skey0, sval0, skey1, sval1,   // (super-tile, Gaussian) pairs
       srange, ubase, nunits,        // per super-tile run and first work unit
       ucnt, tcnt, toff,             // per (unit, tile) and per tile counts, tile offsets
-      ids,                          // tile lists (Gaussian indices), tile-id order
+      ids,                          // tile lists (Gaussian indices), super-tile order
       order,                        // tile schedule: tile ids, longest list first
-      ranges, last, evals, g2d, sort_tmp, scan_tmp, total;
+      ranges, last, evals, g2d, sort_tmp, scan_tmp,
+      sched,                        // length-bucket histogram, done count, bucket cursors
+      stot, sbase,                  // per super-tile: tile pairs, list base
+      total;
   int64_t vn, tiles_x, tiles_y, tiles_total, npix, sxn, syn, spv, st_total;
   int st_bits;
   bool super_in_1;
@@ -83,6 +90,9 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->g2d = c.take((size_t)vn * 10 * 4);   // per (view, Gaussian) screen-space gradients
   L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->st_bits)));
   L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(L->tiles_total)));
+  L->sched = c.take((size_t)kSchedWords * 4);   // follows scan_tmp: cleared together
+  L->stot = c.take((size_t)L->st_total * 4);
+  L->sbase = c.take((size_t)L->st_total * 4);
   L->total = c.off;
   return true;
 }
