@@ -434,9 +434,14 @@ struct PixHash {
 // each table entry adds its count with one atomic whose old value is the
 // entry's first place, and a fragment's place is that plus its rank in the
 // entry (held meanwhile as a tagged table reference).  A fragment whose
-// probe finds no table place takes its own with its own atomic.
+// probe finds no table place takes its own with its own atomic.  The
+// workgroup's fragments are one contiguous range (its survivors are
+// consecutive), so the first kEmitStage of them are staged in LDS and go
+// out as coalesced stores once their places are known; a lane's own
+// fragments would otherwise be 64 scattered stores per instruction.
 constexpr uint32_t kSlotRef = 0x80000000u;   // tag | table place << kRankBits | rank
 constexpr int kEmitPlaces = 4096, kRankBits = 19;   // table at half load for ~2000 fragments
+constexpr int kEmitStage = 2048;
 __global__ __launch_bounds__(256) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const uint32_t* __restrict__ ckey,
@@ -446,19 +451,31 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt, int32_t* status) {
   __shared__ PixHash<kEmitPlaces> h;   // a workgroup emits ~2000 fragments
   __shared__ uint32_t s_first[kEmitPlaces];
+  // staged fragments: pixel, weight bits, place (or tag), owning thread;
+  // per thread its survivor's point index and depth key
+  __shared__ uint32_t s_spx[kEmitStage], s_sw[kEmitStage], s_stag[kEmitStage];
+  __shared__ uint8_t s_sown[kEmitStage];
+  __shared__ uint32_t s_pi[256], s_dz[256];
   static_assert(kEmitPlaces <= (1 << (31 - kRankBits)), "table place fits the tag");
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
   if (total > max_frags || (int64_t)blockIdx.x * blockDim.x >= live) return;   // uniform
+  const int64_t jb = (int64_t)blockIdx.x * blockDim.x;   // first survivor of the first pass
+  const int64_t wlo = foffs[jb];
   h.clear();
   __syncthreads();
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
        j += (int64_t)gridDim.x * blockDim.x) {
+    const bool first = j < jb + (int64_t)blockDim.x;
     const uint32_t e = cent[j];
     const uint32_t dz = ckey[j];
     const int v = (int)(e / np);
     const int64_t i = e - (int64_t)v * np;
+    if (first) {
+      s_pi[threadIdx.x] = (uint32_t)i;
+      s_dz[threadIdx.x] = dz;
+    }
     const KView& cv = views.v[v];
     PtGeom g;
     // the depth cull already passed in k_pt_select; the same single-precision
@@ -487,16 +504,25 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               const float w = wl * (dx ? bx : 1.0f - bx) * (dy ? by : 1.0f - by);
               const uint32_t px = (uint32_t)(lb + yy * Sl + xx);
               if (o >= max_frags) continue;   // only after a wrapped count (flagged)
-              fkey[o] = px;
-              fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
-              fdep[o] = dz;
               // a point reaches a pixel once, so a pixel's rank in the table
               // is below the number of survivors the workgroup handles
               // (< 2^17 < 2^kRankBits: survivors < 2^30, at least 2^21 threads)
               uint32_t r;
               const int hs = h.add(px, r);
-              fslot[o] = hs >= 0 ? (kSlotRef | (uint32_t)hs << kRankBits | r)
-                                 : atomicAdd(&pcnt[px], 1u);
+              const uint32_t tag = hs >= 0 ? (kSlotRef | (uint32_t)hs << kRankBits | r)
+                                           : atomicAdd(&pcnt[px], 1u);
+              const int64_t local = o - wlo;
+              if (first && local < kEmitStage) {
+                s_spx[local] = px;
+                s_sw[local] = __float_as_uint(w);
+                s_stag[local] = tag;
+                s_sown[local] = (uint8_t)threadIdx.x;
+              } else {
+                fkey[o] = px;
+                fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
+                fdep[o] = dz;
+                fslot[o] = tag;
+              }
               ++o;
             }
         }
@@ -508,10 +534,29 @@ __global__ __launch_bounds__(256) void k_pt_emit(
   for (int q = threadIdx.x; q < kEmitPlaces; q += blockDim.x)
     if (h.key[q] != kPixEmpty) s_first[q] = atomicAdd(&pcnt[h.key[q]], h.cnt[q]);
   __syncthreads();
-  // tagged places -> places: each thread revisits the fragments it wrote
+  // the staged fragments out, coalesced, with their places
+  {
+    const int64_t whi = std::min<int64_t>(jb + (int64_t)blockDim.x < live ? foffs[jb + blockDim.x] : total,
+                                          max_frags);
+    const int nst = (int)std::min<int64_t>(whi - wlo, kEmitStage);
+    for (int q = threadIdx.x; q < nst; q += blockDim.x) {
+      const uint32_t t = s_stag[q];
+      const int own = s_sown[q];
+      fkey[wlo + q] = s_spx[q];
+      fval[wlo + q] = ((uint64_t)s_sw[q] << 32) | (uint64_t)s_pi[own];
+      fdep[wlo + q] = s_dz[own];
+      fslot[wlo + q] = (t & kSlotRef)
+                           ? s_first[(t & ~kSlotRef) >> kRankBits] + (t & ((1u << kRankBits) - 1u))
+                           : t;
+    }
+  }
+  // tagged places -> places for the rest: each thread revisits the
+  // fragments it wrote to memory
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t lo = foffs[j], hi = std::min<int64_t>(j + 1 < live ? foffs[j + 1] : total, max_frags);
+    const bool first = j < jb + (int64_t)blockDim.x;
+    const int64_t lo0 = foffs[j], hi = std::min<int64_t>(j + 1 < live ? foffs[j + 1] : total, max_frags);
+    const int64_t lo = first ? std::max<int64_t>(lo0, wlo + kEmitStage) : lo0;
     for (int64_t o0 = lo; o0 < hi; o0 += 8) {   // eight loads in flight, then the stores
       uint32_t t[8];
 #pragma unroll
