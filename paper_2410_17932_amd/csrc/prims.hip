@@ -66,8 +66,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
                                                       uint32_t* __restrict__ out,
                                                       uint32_t* total, const uint32_t* n_dev,
                                                       int64_t n_max, uint32_t* counter,
-                                                      uint64_t* flags, int32_t* status,
-                                                      int flags_mode) {
+                                                      uint64_t* flags, int32_t* status) {
   __shared__ uint32_t s_part, s_prefix;
   constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanItems;
   static_assert(kScanTile >= kScanTileMin && kScanItems % 4 == 0, "partition shape");
@@ -103,9 +102,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
   uint32_t sum = 0;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    const uint32_t xj = flags_mode ? (x[j] != 0u ? 1u : 0u) : x[j];
     v[j] = sum;
-    sum += xj;
+    sum += x[j];
   }
   const uint32_t incl = wave_incl_scan(sum);
   if (lane == 63) s_wsum[wave] = incl;
@@ -385,7 +383,7 @@ size_t scan_tmp_bytes(int64_t n_max) {
 
 static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* out,
                             uint32_t* total, const uint32_t* n_dev, int64_t n_max, void* tmp,
-                            int32_t* status, hipStream_t st, int flags_mode, bool cleared) {
+                            int32_t* status, hipStream_t st, bool cleared) {
   if (n_max <= 0) {
     if (total) return fill_u32(total, 0, 1, st);
     return hipSuccess;
@@ -401,22 +399,17 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* o
   }
   if (idx)
     hipLaunchKernelGGL((k_scan<512, 8>), dim3((unsigned)parts), dim3(512), 0, st, in, idx, out,
-                       total, n_dev, n_max, counter, flags, status, flags_mode);
+                       total, n_dev, n_max, counter, flags, status);
   else
     hipLaunchKernelGGL((k_scan<1024, 16>), dim3((unsigned)parts), dim3(1024), 0, st, in, idx, out,
-                       total, n_dev, n_max, counter, flags, status, flags_mode);
+                       total, n_dev, n_max, counter, flags, status);
   return hipGetLastError();
 }
 
 hipError_t exclusive_scan_u32(const uint32_t* in, const uint32_t* idx, uint32_t* out,
                               uint32_t* total, const uint32_t* n_dev, int64_t n_max, void* tmp,
                               int32_t* status, hipStream_t st, bool cleared) {
-  return scan_impl(in, idx, out, total, n_dev, n_max, tmp, status, st, 0, cleared);
-}
-
-hipError_t exclusive_scan_flags_u32(const uint32_t* in, uint32_t* out, uint32_t* total,
-                                    int64_t n, void* tmp, int32_t* status, hipStream_t st) {
-  return scan_impl(in, nullptr, out, total, nullptr, n, tmp, status, st, 1, false);
+  return scan_impl(in, idx, out, total, n_dev, n_max, tmp, status, st, cleared);
 }
 
 const uint32_t* radix_sort_digit_totals(const void* tmp) {

@@ -83,11 +83,6 @@ hipError_t exclusive_scan_u32(const uint32_t* in, const uint32_t* idx, uint32_t*
                               uint32_t* total, const uint32_t* n_dev, int64_t n_max, void* tmp,
                               int32_t* status, hipStream_t st, bool cleared = false);
 
-// Exclusive scan of the flags (in[i] != 0), i < n: stream-compaction
-// positions in index order; *total = number of set flags.
-hipError_t exclusive_scan_flags_u32(const uint32_t* in, uint32_t* out, uint32_t* total,
-                                    int64_t n, void* tmp, int32_t* status, hipStream_t st);
-
 // Stable LSD radix sort of (uint32 key, value) pairs over the low key_bits
 // bits, 8 bits per pass, reduce-then-scan per pass (digit counts per
 // partition, their scan per digit, then a ranking scatter; Merrill &
