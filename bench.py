@@ -202,8 +202,8 @@ def main():
     ap.add_argument("--profile-pass", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the frame is measured on one GPU only (asked for --gpus {args.gpus}); "
+              "the path has no multi-GPU form", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2410_17932_amd import api, synth
