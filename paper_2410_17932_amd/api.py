@@ -410,6 +410,8 @@ def decode_fovea_backward(pyramid, levels, periphery, views, crops, weights, ws,
 # ------------------------------------------------------------- combine
 def composite_frame(periphery, fovea, crops, mode=BLEND_LINEAR, ring=64.0, m=0.75, gamma=0.2,
                     out=None):
+    """vrs_composite_frame; out may be `periphery` itself (in place: only the
+    pixels under the crops are read and written)."""
     V, _, H, W = periphery.shape
     if out is None:
         out = torch.empty_like(periphery)
