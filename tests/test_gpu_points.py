@@ -64,6 +64,19 @@ def test_points_multi_crop_stereo():
     _run(sc, cull=True)
 
 
+def test_points_stacked_crops():
+    """Five crops around one gaze point: a survivor reaches every crop, so a
+    workgroup emits far more fragments than its LDS stage and pixel table
+    hold (the direct-store and per-fragment-atomic paths run too)."""
+    crops = ((100.0, 80.0, 64), (101.0, 79.0, 64), (99.0, 81.0, 96), (100.0, 80.0, 96),
+             (98.0, 82.0, 128))
+    sc = synth.small_scene(33, n_gauss=500, n_points=20000, width=200, height=160, f=150.0,
+                           crops=crops, radius="lognormal")
+    sc["points"]["radius"] *= 4.0
+    nf = _run(sc, cull=False)
+    assert nf > 4 * 2048
+
+
 def test_points_with_opacity_and_levels():
     sc = synth.small_scene(32, n_points=4000, crops=((64.0, 64.0, 64), (20.0, 20.0, 32)))
     op = np.random.default_rng(0).uniform(0.2, 1.0, sc["points"]["n"]).astype(np.float32)
