@@ -223,9 +223,12 @@ vrs_status vrs_spatial_order(const float* pos, int64_t n, uint32_t* perm, void* 
  *   per crop and layer l: xl = ((p.x - x0) * 2^-l) - 0.5 (y likewise),
  *   bilinear weights to the four pixels around (xl, yl) inside the layer.
  * Per layer pixel the fragments are blended front to back in (float32 bits
- * of t.z, point index) order: alpha = w * opacity, F += feat alpha T,
- * T *= 1 - alpha.  Output pyramid: packed [crop][layer][y][x][channels]
- * float32.  channels must be 4; levels 1..8. */
+ * of t.z, point id) order: alpha = w * opacity, F += feat alpha T,
+ * T *= 1 - alpha.  The point id is point_ids[i] for stored point i when
+ * point_ids (device, uint32 [np], distinct values) is given -- the caller's
+ * own numbering, for a point set stored permuted (e.g. in spatial order) --
+ * else i.  Output pyramid: packed [crop][layer][y][x][channels] float32.
+ * channels must be 4; levels 1..8. */
 size_t vrs_splat_workspace_size(int64_t np, int n_views, const vrs_view* views,
                                 const vrs_crop* crops, int n_crops, int levels,
                                 int64_t max_frags);
@@ -233,9 +236,9 @@ vrs_status vrs_splat_points(const float* pos, const float* radius, const uint16_
                             const float* opacity, int64_t np, int channels, int levels,
                             const vrs_view* views, int n_views, const vrs_crop* crops,
                             int n_crops, const float* depth, const float* t_final,
-                            float cov_min, float slack, float* pyramid, void* ws,
-                            size_t ws_bytes, int64_t max_frags, int32_t* dev_status,
-                            void* stream);
+                            float cov_min, float slack, const uint32_t* point_ids,
+                            float* pyramid, void* ws, size_t ws_bytes, int64_t max_frags,
+                            int32_t* dev_status, void* stream);
 /* Offsets of the splat's intermediate results: frag_count (uint32),
  * sorted layer-pixel keys (uint32 [max_frags]) and sorted point indices
  * (uint32 [max_frags]); layer pixel index = position in the packed pyramid. */

@@ -179,6 +179,62 @@ def render(rect, zbits, rec, dims, tile=16, alpha_clamp=0.99, alpha_min=1 / 255,
     return {k: np.stack(v) for k, v in out.items()}
 
 
+def render_branches(rect, zbits, rec, pix, alpha_clamp=0.99, alpha_min=1 / 255, t_min=1e-4,
+                    bg=(0.0, 0.0, 0.0), margin=1e-4, max_alt=64):
+    """Every result a pixel may legitimately take when single precision
+    decides its blend thresholds (Sec. 3.2 blend; the thresholds alpha_min
+    and t_min are the rasteriser options): the per-pixel blend of ``render``
+    walked again in float64, but wherever a decision (alpha against
+    alpha_min, the next transmittance against t_min) lies within ``margin``
+    (relative) of its threshold, both branches are followed.  Returns, per
+    pixel of pix [n][3] = (view, x, y), a list of (ncontrib, rgb[3], depth,
+    tfinal) tuples, at most max_alt of them (the first one follows the
+    float64 decisions).  Plain per-pixel Python: for the few pixels whose
+    decisions are that close."""
+    bg = np.asarray(bg, np.float64)
+    out = []
+    for v, x, y in np.asarray(pix, np.int64).reshape(-1, 3):
+        r = rect[v]
+        m = (r[:, 0] >= 0) & (r[:, 0] <= x) & (x <= r[:, 2]) & (r[:, 1] <= y) & (y <= r[:, 3])
+        ids = np.nonzero(m)[0]
+        ids = ids[np.lexsort((ids, zbits[v, ids]))]
+        g = rec[v, ids]
+        dx, dy = g[:, 0] - (x + 0.5), g[:, 1] - (y + 0.5)
+        q = -0.5 * (g[:, 2] * dx * dx + g[:, 4] * dy * dy) - g[:, 3] * dx * dy
+        a = np.minimum(alpha_clamp, g[:, 5] * np.exp(q))
+        alts = []
+        # states (list position, T, C, D, count, forced alpha decision,
+        # forced stop decision at that position); the float64 path first
+        stack = [(0, 1.0, np.zeros(3), 0.0, 0, None, None)]
+        while stack and len(alts) < max_alt:
+            k, T, C, D, cnt, fa, fs = stack.pop()
+            while True:
+                if k >= len(ids):
+                    alts.append((cnt, C + T * bg, D, T))
+                    break
+                if q[k] > 0:
+                    k, fa, fs = k + 1, None, None
+                    continue
+                take = bool(a[k] >= alpha_min) if fa is None else fa
+                if fa is None and abs(a[k] - alpha_min) / alpha_min < margin:
+                    stack.append((k, T, C.copy(), D, cnt, not take, None))
+                if not take:
+                    k, fa, fs = k + 1, None, None
+                    continue
+                Tn = T * (1 - a[k])
+                stop = bool(Tn < t_min) if fs is None else fs
+                if fs is None and abs(Tn - t_min) / t_min < margin:
+                    stack.append((k, T, C.copy(), D, cnt, True, not stop))
+                if stop:
+                    alts.append((cnt, C + T * bg, D, T))
+                    break
+                C = C + g[k, 6:9] * a[k] * T
+                D = D + g[k, 9] * a[k] * T
+                T, cnt, k, fa, fs = Tn, cnt + 1, k + 1, None, None
+        out.append(alts)
+    return out
+
+
 def pyramid_pixels(crops_i, levels) -> int:
     return int(lib().orc_pyramid_pixels(crops_i.shape[0], _c(crops_i, np.int32), levels))
 

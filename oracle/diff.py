@@ -118,15 +118,18 @@ def project(mean, cov, opacity, sh, deg, cam, lowpass=0.3):
                 B=-b / det, C=a / det, op=opacity, z=tz, rgb=rgb)
 
 
-def pixel_lists(rect, zbits, pix):
+def pixel_lists(rect, zbits, pix, reach=None):
     """Padded per-pixel candidate lists in (depth bits, index) order:
-    (idx [P][L] int64, valid [P][L] bool)."""
+    (idx [P][L] int64, valid [P][L] bool).  reach [P] (optional): pixel k
+    evaluates only the first reach[k] entries of its list (the blend stops
+    there), so the list is cut after them."""
     lists = []
-    for v, x, y in pix:
+    for k, (v, x, y) in enumerate(pix):
         r = rect[v]
         m = (r[:, 0] >= 0) & (r[:, 0] <= x) & (x <= r[:, 2]) & (r[:, 1] <= y) & (y <= r[:, 3])
         ids = np.nonzero(m)[0]
-        lists.append(ids[np.lexsort((ids, zbits[v, ids]))])
+        ids = ids[np.lexsort((ids, zbits[v, ids]))]
+        lists.append(ids if reach is None else ids[:int(reach[k])])
     L = max([len(l) for l in lists] + [1])
     idx = np.zeros((len(lists), L), np.int64)
     valid = np.zeros((len(lists), L), bool)
@@ -136,9 +139,10 @@ def pixel_lists(rect, zbits, pix):
     return idx, valid
 
 
-def render(mean, cov, opacity, sh, deg, views, dims, pix, raster):
+def render(mean, cov, opacity, sh, deg, views, dims, pix, raster, reach=None):
     """Blend the requested pixels pix [P][3] = (view, x, y): dict rgb [P][3],
-    depth [P], tfinal [P] (differentiable w.r.t. mean, cov, opacity, sh)."""
+    depth [P], tfinal [P] (differentiable w.r.t. mean, cov, opacity, sh).
+    reach: see pixel_lists (entries past a pixel's stop never contribute)."""
     pix = np.asarray(pix, np.int64).reshape(-1, 3)
     rect, zb = gauss_geom32(_f32(mean), _f32(cov), views, dims, raster["lowpass"],
                             raster["extent"])
@@ -146,7 +150,7 @@ def render(mean, cov, opacity, sh, deg, views, dims, pix, raster):
     projs = [project(mean, cov, opacity, sh, deg, camera(views[v], dims[v]), raster["lowpass"])
              for v in range(len(views))]
     cat = {k: torch.cat([p[k] for p in projs]) for k in projs[0]}
-    idx, valid = pixel_lists(rect, zb, pix)
+    idx, valid = pixel_lists(rect, zb, pix, reach)
     gidx = torch.as_tensor(idx + pix[:, :1] * n)
     validt = torch.as_tensor(valid)
     xc = torch.as_tensor(pix[:, 1:2] + 0.5, dtype=DT)

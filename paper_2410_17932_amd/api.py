@@ -89,8 +89,8 @@ SIGNATURES = {
     "vrs_splat_workspace_layout": (_int, [_i64, _int, _P(View), _P(Crop), _int, _int, _i64,
                                           _P(SplatLayout)]),
     "vrs_splat_points": (_int, [_vp, _vp, _vp, _vp, _i64, _int, _int, _P(View), _int,
-                                _P(Crop), _int, _vp, _vp, _flt, _flt, _vp, _vp, _sz, _i64,
-                                _vp, _vp]),
+                                _P(Crop), _int, _vp, _vp, _flt, _flt, _vp, _vp, _vp, _sz,
+                                _i64, _vp, _vp]),
     "vrs_splat_points_backward": (_int, [_vp, _vp, _vp, _vp, _i64, _int, _int, _P(View), _int,
                                          _P(Crop), _int, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                          _i64, _vp]),
@@ -234,9 +234,13 @@ def spatial_order(pos):
 
 # ------------------------------------------------------------- periphery
 class RenderWorkspace:
-    """Caller-owned workspace of one render call (kept for its backward)."""
+    """Caller-owned workspace of one render call (kept for its backward).
+    A backward call replays the lists of the workspace's last forward call:
+    `generation` counts forward calls so that a backward can check that no
+    other forward has run through the workspace since its own."""
 
     def __init__(self, n, views, opts, max_pairs, device="cuda"):
+        self.generation = 0
         self.n, self.views, self.opts, self.max_pairs = n, views, opts, int(max_pairs)
         self.cviews = make_views(views)
         size = lib().vrs_render_workspace_size(n, len(views), self.cviews, ctypes.byref(opts),
@@ -291,6 +295,7 @@ def render_gaussians(mean, cov, opacity, sh, sh_degree, views, opts, ws: RenderW
         ptr(outputs["ncontrib"]), ptr(ws.buf), ws.buf.numel(), ws.max_pairs, ptr(ws.status),
         _stream())
     _check(code, "vrs_render_gaussians")
+    ws.generation += 1
     return outputs
 
 
@@ -312,7 +317,11 @@ def pyramid_pixels(crops, levels) -> int:
 
 
 class SplatWorkspace:
+    """Caller-owned workspace of one splat call (fragment lists kept for the
+    backward; `generation` as for RenderWorkspace)."""
+
     def __init__(self, np_, views, crops, levels, max_frags, device="cuda"):
+        self.generation = 0
         self.np, self.views, self.crops, self.levels = np_, views, crops, levels
         self.max_frags = int(max_frags)
         self.cviews, self.ccrops = make_views(views), make_crops(crops)
@@ -343,7 +352,10 @@ class SplatWorkspace:
 
 
 def splat_points(pos, radius, feat, opacity, views, crops, levels, depth, tfinal, ws,
-                 cov_min=0.5, slack=1.05, pyramid=None):
+                 cov_min=0.5, slack=1.05, pyramid=None, point_ids=None):
+    """vrs_splat_points; point_ids (int32 device tensor [np], optional): the
+    caller's index of each stored point, which orders fragments of equal
+    depth."""
     P = pyramid_pixels(crops, levels)
     C = feat.shape[1]
     if pyramid is None:
@@ -351,9 +363,10 @@ def splat_points(pos, radius, feat, opacity, views, crops, levels, depth, tfinal
     code = lib().vrs_splat_points(
         ptr(pos, torch.float32), ptr(radius, torch.float32), ptr(feat), ptr(opacity),
         pos.shape[1], C, levels, ws.cviews, len(views), ws.ccrops, len(crops), ptr(depth),
-        ptr(tfinal), cov_min, slack, ptr(pyramid), ptr(ws.buf), ws.buf.numel(), ws.max_frags,
-        ptr(ws.status), _stream())
+        ptr(tfinal), cov_min, slack, ptr(point_ids, torch.int32), ptr(pyramid), ptr(ws.buf),
+        ws.buf.numel(), ws.max_frags, ptr(ws.status), _stream())
     _check(code, "vrs_splat_points")
+    ws.generation += 1
     return pyramid
 
 
@@ -369,7 +382,11 @@ def splat_points_backward(pos, radius, feat, opacity, views, crops, levels, d_py
 
 # --------------------------------------------------------------- decoder
 class DecoderWorkspace:
+    """Caller-owned workspace of one decoder call (activations kept for the
+    backward; `generation` as for RenderWorkspace)."""
+
     def __init__(self, widths, crops, dtype=VRS_F32, in_ch=4, device="cuda"):
+        self.generation = 0
         self.desc = make_decoder_desc(widths, in_ch, dtype)
         self.crops = crops
         self.ccrops = make_crops(crops)
@@ -393,6 +410,7 @@ def decode_fovea(pyramid, levels, periphery, views, crops, weights, ws: DecoderW
                                   len(crops), ptr(weights, torch.float32), ctypes.byref(ws.desc),
                                   ptr(out), ptr(ws.buf), ws.buf.numel(), _stream())
     _check(code, "vrs_decode_fovea")
+    ws.generation += 1
     return out
 
 

@@ -1,12 +1,23 @@
 """torch.autograd.Function wrappers over the C-ABI, so the Gaussians, the
 neural points and the decoder can be fitted end to end (Sec. 3.5).  Each
 forward and each backward is one call into the HIP library; gradients land
-in fresh zeroed tensors (the library accumulates into them)."""
+in fresh zeroed tensors (the library accumulates into them).
+
+A backward replays what its forward left in the caller's workspace (tile
+lists, stop positions, fragment segments, activations): one forward per
+workspace and backward.  The workspaces count their forward calls, and a
+backward raises if another forward has run through its workspace since."""
 from __future__ import annotations
 
 import torch
 
 from . import api
+
+
+def _check_generation(ws, gen, what):
+    if ws.generation != gen:
+        raise RuntimeError(f"{what} backward: its workspace was overwritten by another forward "
+                           f"call (use one workspace per forward kept for backward)")
 
 
 class BakeGaussians(torch.autograd.Function):
@@ -32,14 +43,15 @@ class RenderGaussians(torch.autograd.Function):
     def forward(ctx, mean, cov, opacity, sh, sh_degree, views, opts, ws):
         out = api.render_gaussians(mean, cov, opacity, sh, sh_degree, views, opts, ws)
         ctx.save_for_backward(mean, cov, opacity, sh, out["tfinal"])
-        ctx.meta = (sh_degree, views, opts, ws)
+        ctx.meta = (sh_degree, views, opts, ws, ws.generation)
         ctx.mark_non_differentiable(out["tfinal"])
         return out["rgb"], out["depth"], out["tfinal"]
 
     @staticmethod
     def backward(ctx, d_rgb, d_depth, _d_t):
         mean, cov, op, sh, tf = ctx.saved_tensors
-        deg, views, opts, ws = ctx.meta
+        deg, views, opts, ws, gen = ctx.meta
+        _check_generation(ws, gen, "RenderGaussians")
         g = [torch.zeros_like(t) for t in (mean, cov, op, sh)]
         d_rgb = torch.zeros_like(tf).unsqueeze(1).expand(-1, 3, -1, -1).contiguous() \
             if d_rgb is None else d_rgb.contiguous()
@@ -58,13 +70,14 @@ class SplatPoints(torch.autograd.Function):
         feat_h = feat.to(torch.float16).view(torch.int16).contiguous()
         pyr = api.splat_points(pos, radius, feat_h, opacity, views, crops, levels, depth, tfinal, ws)
         ctx.save_for_backward(pos, radius, opacity if opacity is not None else pos.new_empty(0))
-        ctx.meta = (feat_h, views, crops, levels, ws, opacity is not None)
+        ctx.meta = (feat_h, views, crops, levels, ws, opacity is not None, ws.generation)
         return pyr
 
     @staticmethod
     def backward(ctx, d_pyr):
         pos, radius, op = ctx.saved_tensors
-        feat_h, views, crops, levels, ws, has_op = ctx.meta
+        feat_h, views, crops, levels, ws, has_op, gen = ctx.meta
+        _check_generation(ws, gen, "SplatPoints")
         d_pos, d_r = torch.zeros_like(pos), torch.zeros_like(radius)
         d_feat = torch.zeros((pos.shape[1], 4), device=pos.device)
         d_op = torch.zeros_like(op) if has_op else None
@@ -79,13 +92,14 @@ class DecodeFovea(torch.autograd.Function):
     def forward(ctx, pyramid, periphery, weights, levels, views, crops, ws):
         out = api.decode_fovea(pyramid, levels, periphery, views, crops, weights, ws)
         ctx.save_for_backward(pyramid, periphery, weights)
-        ctx.meta = (levels, views, crops, ws)
+        ctx.meta = (levels, views, crops, ws, ws.generation)
         return out
 
     @staticmethod
     def backward(ctx, d_out):
         pyr, per, w = ctx.saved_tensors
-        levels, views, crops, ws = ctx.meta
+        levels, views, crops, ws, gen = ctx.meta
+        _check_generation(ws, gen, "DecodeFovea")
         g = [torch.zeros_like(t) for t in (pyr, per, w)]
         api.decode_fovea_backward(pyr, levels, per, views, crops, w, ws, d_out.contiguous(), *g)
         return (*g, None, None, None, None)

@@ -480,9 +480,12 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     PtGeom g;
     // the depth cull already passed in k_pt_select; the same single-precision
     // sequence gives identical geometry here
-    if (!pt_geom32(cv, pos[i], pos[np + i], pos[2 * np + i], radius[i], a.levels, g)) continue;
+    const float x = pos[i], y = pos[np + i], z = pos[2 * np + i];
+    if (!pt_geom32(cv, x, y, z, radius[i], a.levels, g)) continue;
     float f = 0.0f;
     if (g.two) f = log2f(g.s) - (float)g.l0;
+    FF ux, uy;   // the weights' position, compensated
+    pt_plane_ff(cv, x, y, z, ux, uy);
     int64_t o = foffs[j];
     for (int k = 0; k < crops.n; ++k) {
       const KCrop& c = crops.c[k];
@@ -496,7 +499,8 @@ __global__ __launch_bounds__(256) void k_pt_emit(
         float xl, yl;
         int ix, iy;
         if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) {
-          const float bx = xl - (float)ix, by = yl - (float)iy;
+          const float bx = pt_frac_ff(cv.fx, ux, cv.cx, c.x0, l, ix);
+          const float by = pt_frac_ff(cv.fy, uy, cv.cy, c.y0, l, iy);
           for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
               const int xx = ix + dx, yy = iy + dy;
@@ -592,14 +596,18 @@ __global__ __launch_bounds__(256) void k_pt_scatter(const uint32_t* __restrict__
 
 // One thread per segment place: the record's final place is its segment's
 // offset plus the number of the segment's records before it in (depth key,
-// point index) order (a point reaches a layer pixel at most once, so the
-// pairs are distinct).  Consecutive places share segments, so the lanes of
-// a segment read the same records; places go in reverse, so that the long
-// segments of each crop's coarse layers start early.
+// point id) order, the id being the point's index in the caller's numbering
+// (ids[i] for stored point i when a numbering is given, else i; a point
+// reaches a layer pixel at most once, so the pairs are distinct).  Equal
+// depth keys are rare, so the numbering is looked up only for them.
+// Consecutive places share segments, so the lanes of a segment read the
+// same records; places go in reverse, so that the long segments of each
+// crop's coarse layers start early.
 __global__ __launch_bounds__(256) void k_pt_rank(const uint4* __restrict__ seg,
                                                  const uint32_t* __restrict__ poff,
                                                  const uint32_t* __restrict__ total_p,
                                                  int64_t max_frags, int64_t pix_total,
+                                                 const uint32_t* __restrict__ ids,
                                                  uint32_t* __restrict__ okey,
                                                  uint64_t* __restrict__ oval) {
   const int64_t total = *total_p;
@@ -612,8 +620,19 @@ __global__ __launch_bounds__(256) void k_pt_rank(const uint4* __restrict__ seg,
     const uint64_t own = ((uint64_t)rec.y << 32) | rec.x;
     const uint32_t start = poff[rec.w], n = poff[rec.w + 1] - start;
     uint32_t rank = 0;
+    if (ids) {
+      const uint32_t own_id = ids[rec.x];
 #pragma unroll 8
-    for (uint32_t j = 0; j < n; ++j) rank += key[2 * (int64_t)(start + j)] < own ? 1u : 0u;
+      for (uint32_t j = 0; j < n; ++j) {
+        const uint64_t kj = key[2 * (int64_t)(start + j)];
+        bool before = (uint32_t)(kj >> 32) < rec.y;
+        if ((uint32_t)(kj >> 32) == rec.y && kj != own) before = ids[(uint32_t)kj] < own_id;
+        rank += before ? 1u : 0u;
+      }
+    } else {
+#pragma unroll 8
+      for (uint32_t j = 0; j < n; ++j) rank += key[2 * (int64_t)(start + j)] < own ? 1u : 0u;
+    }
     okey[start + rank] = rec.w;
     oval[start + rank] = ((uint64_t)rec.z << 32) | rec.x;
   }
@@ -719,8 +738,9 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
                                        int channels, int levels, const vrs_view* views,
                                        int n_views, const vrs_crop* crops, int n_crops,
                                        const float* depth, const float* t_final, float cov_min,
-                                       float slack, float* pyramid, void* ws, size_t ws_bytes,
-                                       int64_t max_frags, int32_t* dev_status, void* stream) {
+                                       float slack, const uint32_t* point_ids, float* pyramid,
+                                       void* ws, size_t ws_bytes, int64_t max_frags,
+                                       int32_t* dev_status, void* stream) {
   KViews kv;
   KCrops kc;
   SplatWs L;
@@ -793,7 +813,7 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
                      at<uint4>(ws, L.seg));
   VRS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_pt_rank, dim3(fb), dim3(256), 0, st, at<uint4>(ws, L.seg), poff,
-                     frag_count, max_frags, L.pix_total, at<uint32_t>(ws, L.fkey1),
+                     frag_count, max_frags, L.pix_total, point_ids, at<uint32_t>(ws, L.fkey1),
                      at<uint64_t>(ws, L.fval1));
   VRS_LAUNCH_CHECK();
   const unsigned pb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, div_up(L.pix_total, 256)));
@@ -898,7 +918,10 @@ __global__ __launch_bounds__(256) void k_pt_blend_bwd(
         float xl, yl;
         int ix, iy;
         if (!pt_layer32(pg, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) continue;
-        const float bx = xl - (float)ix, by = yl - (float)iy;
+        FF ux, uy;
+        pt_plane_ff(cv, pos[id], pos[np + id], pos[2 * np + id], ux, uy);
+        const float bx = pt_frac_ff(cv.fx, ux, cv.cx, c.x0, l, ix);
+        const float by = pt_frac_ff(cv.fy, uy, cv.cy, c.y0, l, iy);
         const int dx = xx - ix, dy = yy - iy;
         const float wx = dx ? bx : 1.0f - bx, wy = dy ? by : 1.0f - by;
         float f2 = 0.0f, wl = 1.0f;

@@ -89,6 +89,77 @@ __device__ inline bool pt_layer32(const PtGeom& g, int x0, int y0, int l, int Sl
   return true;
 }
 
+// ------------------------------------------------ compensated positions
+// The integer decisions above are taken on the single-precision view pixel
+// coordinate p = fx (t.x / t.z) + cx.  Far from the image origin (x ~ 2000)
+// that coordinate carries up to ~1e-4 px of rounding, which the bilinear
+// weights would inherit.  The continuous part of a fragment (its bilinear
+// fractions) is therefore taken from the same single-precision inputs in
+// float-float arithmetic (an unevaluated sum hi + lo; Dekker's two-product
+// via fma and Knuth's two-sum), in the crop's own frame: the sub-frustum's
+// principal point c - x0 (Sec. 3.3) is formed before the projected offset
+// is added, so no large coordinate is ever rounded.
+struct FF {
+  float hi, lo;
+};
+__device__ inline FF ff_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  const float e = (a - (s - bb)) + (b - bb);
+  return FF{s, e};
+}
+__device__ inline FF ff_quick(float a, float b) {   // |a| >= |b| or a == 0
+#pragma clang fp contract(off)
+  const float s = a + b;
+  return FF{s, b - (s - a)};
+}
+__device__ inline FF ff_two_prod(float a, float b) {
+#pragma clang fp contract(off)
+  const float p = a * b;
+  return FF{p, fmaf(a, b, -p)};
+}
+__device__ inline FF ff_add(FF a, FF b) {
+#pragma clang fp contract(off)
+  const FF s = ff_two_sum(a.hi, b.hi);
+  return ff_quick(s.hi, s.lo + (a.lo + b.lo));
+}
+__device__ inline FF ff_div(FF a, FF b) {
+#pragma clang fp contract(off)
+  const float q = a.hi / b.hi;
+  float r = fmaf(-q, b.hi, a.hi);   // exact remainder of the rounded quotient
+  r = r + a.lo;
+  r = r - q * b.lo;
+  return ff_quick(q, r / b.hi);
+}
+
+// Camera-plane position (t.x / t.z, t.y / t.z) of a point in float-float.
+__device__ inline void pt_plane_ff(const KView& cv, float x, float y, float z, FF& ux, FF& uy) {
+  FF t[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    FF s = ff_add(ff_two_prod(cv.R[3 * i + 0], x), ff_two_prod(cv.R[3 * i + 1], y));
+    s = ff_add(s, ff_two_prod(cv.R[3 * i + 2], z));
+    t[i] = ff_add(s, FF{cv.t[i], 0.0f});
+  }
+  ux = ff_div(t[0], t[2]);
+  uy = ff_div(t[1], t[2]);
+}
+
+// Bilinear fraction along one axis in layer l of a crop with integer
+// origin x0: xl - ix with xl = (f u + (c - x0)) 2^-l - 1/2 and ix the
+// layer footprint's integer corner decided by pt_layer32.
+__device__ inline float pt_frac_ff(float f, FF u, float c, int x0, int l, int ix) {
+#pragma clang fp contract(off)
+  FF a = ff_two_prod(f, u.hi);
+  a = ff_quick(a.hi, a.lo + f * u.lo);
+  a = ff_add(a, ff_two_sum(c, -(float)x0));
+  const float sc = ldexpf(1.0f, -l);     // exact scaling
+  FF d = ff_two_sum(a.hi * sc, -0.5f);
+  d.lo = d.lo + a.lo * sc;
+  return (d.hi - (float)ix) + d.lo;
+}
+
 __device__ inline int pt_targets(int ix, int iy, int Sl) {
   const int nx = (ix >= 0 ? 1 : 0) + (ix + 1 <= Sl - 1 ? 1 : 0);
   const int ny = (iy >= 0 ? 1 : 0) + (iy + 1 <= Sl - 1 ? 1 : 0);

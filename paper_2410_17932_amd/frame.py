@@ -47,10 +47,15 @@ class Frame:
                                                     _dev(g["logit"]))
         self.pos, self.radius = _dev(p["pos"]), _dev(p["radius"])
         self.feat = _dev(p["feat"].view(np.int16))
+        self.point_ids = None
         if spatial_order:
             # storage layout of the static point cloud: Morton order, so the
-            # depth cull's per-point reads of depth and T' share cache lines
-            perm = api.spatial_order(self.pos).long()
+            # depth cull's per-point reads of depth and T' share cache lines;
+            # the input index of each stored point still orders fragments of
+            # equal depth
+            perm = api.spatial_order(self.pos)
+            self.point_ids = perm
+            perm = perm.long()
             self.pos = self.pos[:, perm].contiguous()
             self.radius = self.radius[perm].contiguous()
             self.feat = self.feat[perm].contiguous()
@@ -98,7 +103,8 @@ class Frame:
     def _splat(self, sws):
         api.splat_points(self.pos, self.radius, self.feat, None, self.views, self.crops,
                          self.levels, self.depth if self.cull else None,
-                         self.tfinal if self.cull else None, sws, pyramid=self.pyramid)
+                         self.tfinal if self.cull else None, sws, pyramid=self.pyramid,
+                         point_ids=self.point_ids)
 
     # --------------------------------------------------------------- frame
     def run(self):
@@ -198,7 +204,7 @@ class PlainFrame:
         for k, c in enumerate(b.crops):
             api.splat_points(b.pos, b.radius, b.feat, None, b.views, [c], b.levels,
                              self.depth if b.cull else None, self.tfinal if b.cull else None,
-                             self.sws[k], pyramid=self.pyr[k])
+                             self.sws[k], pyramid=self.pyr[k], point_ids=b.point_ids)
             api.decode_fovea(self.pyr[k], b.levels, self.rgb, b.views, [c], b.weights,
                              self.dws[k], out=self.fovea[off:off + 3 * c.size * c.size])
             off += 3 * c.size * c.size

@@ -61,13 +61,12 @@ def test_fit_step_gradients_subset():
     Tp["mean"], Tp["sh"] = torch.tensor(tg["mean"], dtype=DT), torch.tensor(tg["sh"], dtype=DT)
     with torch.no_grad():
         target, _, _ = _oracle_chain(sc, g, Tp, False)
-    # keep every pixel away from |pred - target| = 0, where the L1 sign is
-    # decided by rounding (regions the perturbation does not reach)
-    rng = np.random.default_rng(11)
-    target = target + torch.tensor(rng.choice([-1.0, 1.0], target.shape) *
-                                   rng.uniform(0.01, 0.02, target.shape))
-    # ambiguous pixels (threshold decisions within 1e-4 of a flip) and their
-    # 3x3 neighbourhood (the decoder's finest kernel) are masked out
+    # pixels left out of the loss (mask 0 on both sides): near-threshold
+    # pixels (a blend decision within 1e-4 of a flip) with their 3x3
+    # neighbourhood (the decoder's finest kernel), and pixels where the
+    # prediction is within 1e-3 of the target, whose L1 sign a float32
+    # forward error could flip (mostly where the perturbation does not reach
+    # and both images agree exactly)
     cov32, op32 = (a.astype(np.float32) for a in oracle.bake(g["logscale"], g["quat"], g["logit"]))
     V, D = synth.views_array(sc["views"]), synth.views_dims(sc["views"])
     rect, zb = oracle.gauss_geom32(g["mean"], cov32, V, D)
@@ -77,9 +76,13 @@ def test_fit_step_gradients_subset():
     for dy in (-1, 0, 1):
         for dx in (-1, 0, 1):
             dil |= np.roll(np.roll(amb, dy, 1), dx, 2)
-    mask = np.repeat((~dil)[:, None], 3, 1).astype(np.float64)
     Rp = {k: torch.tensor(np.asarray(v), dtype=DT, requires_grad=True) for k, v in P.items()}
     out, _, _ = _oracle_chain(sc, g, Rp, True)
+    close = (out.detach() - target).abs().numpy() < 1e-3
+    mask = (np.repeat((~dil)[:, None], 3, 1) & ~close).astype(np.float64)
+    print(f"loss pixels: {mask.mean():.3f} of all (ambiguous {dil.mean():.4f}, "
+          f"within 1e-3 of the target {close.mean():.3f})")
+    assert mask.mean() > 0.05
     tgt = target.detach()
     diff.l1(out * torch.tensor(mask), tgt * torch.tensor(mask)).backward()
     # GPU
@@ -88,20 +91,17 @@ def test_fit_step_gradients_subset():
                   cull=False, mask=mask.astype(np.float32))
     loss = fit.step()
     assert fit.status() == 0
-    # The chained float32 pipeline sums many sign-valued L1 cotangents with
-    # cancellation; each stage alone meets the element-wise 1e-3 bound
-    # (test_gpu_grad.py).  Here: normwise 1e-3 against the largest entry and
-    # the element-wise measure for 99% of the entries.
+    # every entry of every parameter's gradient within 1e-3 (relative, on a
+    # floor of 1e-3 of the tensor's largest magnitude)
     bad = []
     for k in P:
         gg, ref = fit.params[k].grad.cpu().numpy(), Rp[k].grad.numpy()
         scale = np.abs(ref).max()
         den = np.maximum(np.abs(ref), 1e-3 * scale)
         rel = np.abs(gg - ref) / den
-        norm = float(np.abs(gg - ref).max() / scale)
-        print(f"fit d_{k}: normwise {norm:.2e}, element-wise p99 {np.quantile(rel, 0.99):.2e} "
-              f"max {rel.max():.2e} (|g|max {scale:.2e})")
-        if norm > 1e-3 or np.quantile(rel, 0.99) > 1e-3:
+        print(f"fit d_{k}: element-wise max {rel.max():.2e} at {np.unravel_index(rel.argmax(), rel.shape)}"
+              f" (|g|max {scale:.2e})")
+        if rel.max() > 1e-3:
             bad.append(k)
     assert not bad, bad
 
@@ -132,3 +132,145 @@ def test_fit_step_full_size():
         _, loss1 = fit.forward()
     print(f"full-size fit: loss {loss0:.6f} -> {float(loss1):.6f} (expected -{eps * g2:.2e})")
     assert float(loss1) < loss0
+
+
+def _fullsize_reference(sc, cot_pix, cot_val, params, full, rect):
+    """FP64 analytic gradients of sum(out[0] * cot) for the fitting workload
+    at full size, restricted to camera 0 and its crop (the cotangent is zero
+    on the other cameras): a float64 constant periphery from the reference's
+    renderer (full, camera 0), with the differentiable render spliced in at
+    the cotangent's pixels and their 3x3 neighbourhoods (the decoder sees
+    the periphery crop only through its finest 3x3 convolution).  Only the
+    Gaussians whose rectangle (rect, camera 0) holds one of those pixels can
+    receive a gradient; the differentiable render runs on that subset (its
+    per-pixel lists are the same)."""
+    views, crops, L = sc["views"], sc["crops"], sc["levels"]
+    V0, D0 = synth.views_array(views[:1]), synth.views_dims(views[:1])
+    c0 = crops[0]
+    ci0, cf0 = synth.crops_array([c0])
+    W = H = 1024
+    # differentiable pixels
+    need = np.zeros((H, W), bool)
+    for x, y in cot_pix:
+        inside = c0.x0 <= x < c0.x0 + c0.size and c0.y0 <= y < c0.y0 + c0.size
+        r = 1 if inside else 0
+        need[max(y - r, 0):y + r + 1, max(x - r, 0):x + r + 1] = True
+    yy, xx = np.nonzero(need)
+    pix = np.stack([np.zeros_like(xx), xx, yy], 1)
+    # each pixel evaluates its list only up to its stop (the reference's
+    # work count); the Gaussians of those list heads are the ones that can
+    # receive a gradient, and the differentiable render runs on them alone
+    # (in index order, so each head keeps its order)
+    reach = full["evals"][0][yy, xx]
+    zb0 = full["zb"][0]
+    r0 = rect[0]
+    hit = np.zeros(r0.shape[0], bool)
+    for (_, x, y), e in zip(pix, reach):
+        m = (r0[:, 0] >= 0) & (r0[:, 0] <= x) & (x <= r0[:, 2]) & (r0[:, 1] <= y) & (y <= r0[:, 3])
+        ids = np.nonzero(m)[0]
+        hit[ids[np.lexsort((ids, zb0[ids]))][:e]] = True
+    sub = torch.as_tensor(np.flatnonzero(hit))
+    cov, op = diff.bake(params["logscale"][:, sub], params["quat"][:, sub], params["logit"][sub])
+    r = diff.render(params["mean"][:, sub], cov, op, params["sh"][:, :, sub], 3, V0, D0, pix,
+                    sc["raster"], reach=reach)
+    P = torch.tensor(full["rgb"][0].reshape(3, -1), dtype=DT)
+    P = P.index_put((torch.arange(3)[:, None], torch.as_tensor(yy * W + xx)[None]), r["rgb"].T)
+    P = P.reshape(1, 3, H, W)
+    depth32, tf32 = full["depth"].astype(np.float32), full["tfinal"].astype(np.float32)
+    pyr = diff.splat(params["pos"], params["radius"], params["feat"], None, V0, D0, ci0, L,
+                     depth32, tf32)
+    lv, hd = diff.unpack_decoder(params["weights"], sc["decoder"]["widths"])
+    F = diff.decode(pyr, P, ci0, L, sc["decoder"]["widths"], lv, hd)
+    out = diff.composite(P, F, ci0, cf0, mode=0, ring=64.0)
+    cot = torch.zeros((3, H, W), dtype=DT)
+    cot[:, cot_pix[:, 1], cot_pix[:, 0]] = torch.tensor(cot_val.T)
+    (out[0] * cot).sum().backward()
+    return full, depth32, tf32
+
+
+def test_fit_step_full_size_sampled_gradients():
+    """The fitting workload at its full shape (1M Gaussians SH3, 2M points,
+    four 1024^2 cameras, one 512 crop each, FP32 decoder): the GPU chain's
+    gradients of a cotangent on 240 pixels of camera 0 (half inside its
+    crop) against the FP64 analytic gradients, every entry within 1e-3."""
+    import time
+    t0 = time.time()
+    sc = synth.config(4)
+    g, p = sc["gaussians"], sc["points"]
+    views, crops, L = sc["views"], sc["crops"], sc["levels"]
+    c0 = crops[0]
+    P = dict(mean=g["mean"], logscale=g["logscale"], quat=g["quat"], logit=g["logit"], sh=g["sh"],
+             pos=p["pos"], radius=p["radius"], feat=p["feat"].view(np.float16).astype(np.float32),
+             weights=synth.pack_decoder(sc["decoder"]))
+    # cotangent pixels: unambiguous, 150 inside crop 0 (with an unambiguous
+    # 3x3 neighbourhood, away from the crop border) and 150 outside any crop
+    V0, D0 = synth.views_array(views[:1]), synth.views_dims(views[:1])
+    cov32, op32 = (a.astype(np.float32) for a in oracle.bake(g["logscale"], g["quat"], g["logit"]))
+    rect, zb = oracle.gauss_geom32(g["mean"], cov32, V0, D0)
+    rec = oracle.gauss_project64(g["mean"], cov32, op32, g["sh"], 3, V0, D0)
+    full = oracle.render(rect, zb, rec, D0, 16)
+    full["zb"] = zb
+    mg = full["margin"][0]
+    amb = mg < 1e-4
+    amb3 = amb.copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            amb3 |= np.roll(np.roll(amb, dy, 0), dx, 1)
+    rng = np.random.default_rng(44)
+    ys, xs = np.mgrid[0:1024, 0:1024]
+    inside = (xs >= c0.x0 + 2) & (xs < c0.x0 + c0.size - 2) & (ys >= c0.y0 + 2) & (ys < c0.y0 + c0.size - 2)
+    outside = (xs < c0.x0) | (xs >= c0.x0 + c0.size) | (ys < c0.y0) | (ys >= c0.y0 + c0.size)
+    cand_in = np.flatnonzero(inside & ~amb3)
+    cand_out = np.flatnonzero(outside & ~amb)
+    sel = np.concatenate([rng.choice(cand_in, 120, replace=False),
+                          rng.choice(cand_out, 120, replace=False)])
+    cot_pix = np.stack([sel % 1024, sel // 1024], 1)
+    cot_val = rng.normal(size=(len(sel), 3))
+    Rp = {k: torch.tensor(np.asarray(v), dtype=DT, requires_grad=True) for k, v in P.items()}
+    full, depth32, tf32 = _fullsize_reference(sc, cot_pix, cot_val, Rp, full, rect)
+    print(f"reference: {time.time() - t0:.1f} s")
+    # GPU: the chain through the autograd wrappers, all four cameras; the
+    # depth cull of camera 0 takes the reference's depth and transmittance
+    from paper_2410_17932_amd.autograd import (BakeGaussians, CompositeFrame, DecodeFovea,
+                                               RenderGaussians, SplatPoints)
+    T = {k: torch.tensor(np.asarray(v)).cuda().requires_grad_(True) for k, v in P.items()}
+    opts = api.make_opts(**dict(sc["raster"], tile=16))
+    V, D = synth.views_array(views), synth.views_dims(views)
+    rect4, _ = oracle.gauss_geom32(g["mean"], cov32, V, D)
+    from gpu_helpers import pair_total
+    rws = api.RenderWorkspace(g["n"], views, opts, pair_total(rect4, D, 16) + 4096)
+    cov, op = BakeGaussians.apply(T["logscale"], T["quat"], T["logit"])
+    rgb, depth, tf = RenderGaussians.apply(T["mean"], cov, op, T["sh"], 3, views, opts, rws)
+    dcull, tcull = depth.detach().clone(), tf.detach().clone()
+    dcull[0] = torch.from_numpy(depth32[0]).cuda()
+    tcull[0] = torch.from_numpy(tf32[0]).cuda()
+    ci, _ = synth.crops_array(crops)
+    nf = len(oracle.point_lists(p["pos"], p["radius"], V, D, ci, L, dcull.cpu().numpy(),
+                                tcull.cpu().numpy())[1])
+    sws = api.SplatWorkspace(p["n"], views, crops, L, nf + 4096)
+    pyr = SplatPoints.apply(T["pos"], T["radius"], T["feat"], None, views, crops, L, dcull, tcull,
+                            sws)
+    dws = api.DecoderWorkspace(sc["decoder"]["widths"], crops, api.VRS_F32)
+    F = DecodeFovea.apply(pyr, rgb, T["weights"], L, views, crops, dws)
+    out = CompositeFrame.apply(rgb, F, crops, api.BLEND_LINEAR, 64.0, 0.75, 0.2)
+    cot = torch.zeros_like(out)
+    cot[0, :, cot_pix[:, 1], cot_pix[:, 0]] = torch.tensor(cot_val.T, dtype=torch.float32).cuda()
+    (out * cot).sum().backward()
+    torch.cuda.synchronize()
+    assert int(rws.status.item()) == 0 and int(sws.status.item()) == 0
+    # forward at the cotangent's pixels
+    o_gpu = out[0, :, cot_pix[:, 1], cot_pix[:, 0]].detach().cpu().numpy()
+    assert np.isfinite(o_gpu).all()
+    bad = []
+    for k in P:
+        gg, ref = T[k].grad.cpu().numpy(), Rp[k].grad.numpy()
+        scale = np.abs(ref).max()
+        den = np.maximum(np.abs(ref), 1e-3 * scale)
+        rel = np.abs(gg - ref) / den
+        print(f"full-size d_{k}: nonzero {int((ref != 0).sum())}, element-wise max {rel.max():.2e} "
+              f"(|g|max {scale:.2e})")
+        assert scale > 0, k
+        if rel.max() > 1e-3:
+            bad.append(k)
+    print(f"total {time.time() - t0:.1f} s")
+    assert not bad, bad

@@ -71,3 +71,38 @@ def test_plain_form_matches_batched():
     # batched BF16 vs FP32: decoder tolerance
     err = float((ob - of).abs().max()) / max(1.0, float(of.abs().max()))
     assert err <= 2e-2, err
+
+
+def test_spatial_order_keeps_equal_depth_order():
+    """Points on three planes of exactly equal camera depth (identity
+    rotations, so t.z = z exactly): many fragments of a layer pixel tie on
+    the depth key, and the order of equal depths is the input's point index.
+    The frame stores the points in Morton order; its fragment lists (mapped
+    back to input indices) and pyramid still equal the reference's on the
+    input as given."""
+    import oracle
+    crops = ((60.0, 50.0, 64), (150.0, 120.0, 96), (100.0, 100.0, 128))
+    sc = synth.small_scene(62, n_gauss=500, n_points=30000, width=256, height=224, f=220.0,
+                           n_views=2, crops=crops, crop_views=[0, 1, 0], widths=(16, 32),
+                           radius="lognormal")
+    p = sc["points"]
+    rng = np.random.default_rng(5)
+    p["pos"][2] = rng.choice(np.array([2.5, 3.0, 3.5], np.float32), p["n"])
+    p["radius"] = (p["radius"] * 6.0).astype(np.float32)
+    fr = Frame(sc, decoder_dtype=api.VRS_F32, tile=16, spatial_order=True, cull=False)
+    fr.run()
+    torch.cuda.synchronize()
+    V, D = synth.views_array(sc["views"]), synth.views_dims(sc["views"])
+    ci, _ = synth.crops_array(sc["crops"])
+    off, oids = oracle.point_lists(p["pos"], p["radius"], V, D, ci, sc["levels"])
+    keys, ids = fr.sws.lists()
+    perm = fr.point_ids.cpu().numpy().astype(np.int64)
+    assert not np.array_equal(perm, np.arange(p["n"]))
+    got = perm[ids]
+    assert np.array_equal(np.bincount(keys, minlength=len(off) - 1), np.diff(off))
+    # ties: consecutive fragments of one pixel with the same depth key
+    same = (np.diff(keys) == 0) & (np.diff(p["pos"][2][got].view(np.uint32)) == 0)
+    assert same.sum() > 1000, same.sum()
+    assert np.array_equal(got, oids)
+    pyr_o = oracle.splat_points(p["pos"], p["radius"], p["feat"], V, D, ci, sc["levels"])
+    assert float(np.abs(fr.pyramid.cpu().numpy() - pyr_o).max()) <= 1e-4

@@ -11,7 +11,7 @@ import torch
 import oracle
 from paper_2410_17932_amd import api, synth
 
-from gpu_helpers import baked, check_render, dev
+from gpu_helpers import baked, check_render, dev, pair_total, super_pair_total, tile_counts
 
 pytestmark = pytest.mark.gpu
 
@@ -28,41 +28,47 @@ def full():
     return dict(sc=sc, cov=cov, op=op, rect=rect, zb=zb, rec=rec, V=V, D=D)
 
 
-def test_fullsize_periphery_sampled(full):
+@pytest.mark.parametrize("tile", [32, 16, 8])
+def test_fullsize_periphery_sampled(full, tile):
+    """Every tile size the autotuner may pick.  With 8 x 8-tile super-tiles,
+    tile 32 numbers 144 super-tiles over both eyes (8-bit ids: one sort
+    pass), tile 16 576 (10 bits) and tile 8 2,304 (12 bits): the last two
+    take the two-pass super-tile sort and the run search."""
     sc, g = full["sc"], full["sc"]["gaussians"]
-    views, raster = sc["views"], dict(sc["raster"], tile=32)
-    r = full["rect"][full["rect"][..., 0] >= 0]
-    pairs = int(((r[:, 2] // 32 - r[:, 0] // 32 + 1) * (r[:, 3] // 32 - r[:, 1] // 32 + 1)).sum())
+    views, raster = sc["views"], dict(sc["raster"], tile=tile)
+    pairs = pair_total(full["rect"], full["D"], tile)
+    supers = super_pair_total(full["rect"], tile)
     opts = api.make_opts(**raster)
     ws = api.RenderWorkspace(g["n"], views, opts, pairs + 1024)
+    n_super = 2 * -(-2016 // (8 * tile)) * -(-2240 // (8 * tile))
+    print(f"tile {tile}: {pairs} tile pairs, {supers} super pairs over {n_super} super-tiles")
     out = api.render_gaussians(dev(g["mean"]), dev(full["cov"]), dev(full["op"]), dev(g["sh"]), 3,
                                views, opts, ws)
     torch.cuda.synchronize()
-    assert int(ws.status.item()) == 0 and ws.pair_count() == pairs
-    rng = np.random.default_rng(0)
+    assert int(ws.status.item()) == 0
+    assert ws.pair_count() == pairs and ws.super_pair_count() == supers
+    rng = np.random.default_rng(tile)
     W, H = 2016, 2240
     pix = np.stack([rng.integers(0, 2, 6000), rng.integers(0, W, 6000), rng.integers(0, H, 6000)], 1)
-    o = oracle.render(full["rect"], full["zb"], full["rec"], full["D"], 32, pix=pix.astype(np.int32))
+    o = oracle.render(full["rect"], full["zb"], full["rec"], full["D"], tile,
+                      pix=pix.astype(np.int32))
     v, x, y = pix[:, 0], pix[:, 1], pix[:, 2]
-    g_rgb = out["rgb"].cpu().numpy()[v, :, y, x]            # [n][3]
-    g_depth = out["depth"].cpu().numpy()[v, y, x]
-    g_t = out["tfinal"].cpu().numpy()[v, y, x]
-    g_n = out["ncontrib"].cpu().numpy()[v, y, x]
-    ok = o["margin"] >= 1e-4                               # unambiguous pixels
-    assert (~ok).mean() < 0.005
-    assert np.abs(g_rgb[ok] - o["rgb"][ok]).max() <= 1e-4
-    assert np.abs(g_t[ok] - o["tfinal"][ok]).max() <= 1e-4
-    assert np.abs(g_depth[ok] - o["depth"][ok]).max() <= 1e-4 * 6   # depth up to ~6
-    assert np.array_equal(g_n[ok], o["ncontrib"][ok])
-    # sampled tile lists, bit-exact
+    gpu = dict(rgb=out["rgb"].cpu().numpy()[v, :, y, x], depth=out["depth"].cpu().numpy()[v, y, x],
+               tfinal=out["tfinal"].cpu().numpy()[v, y, x],
+               ncontrib=out["ncontrib"].cpu().numpy()[v, y, x])
+    check_render(o, gpu, max_ambiguous=0.005,
+                 branches=dict(rect=full["rect"], zb=full["zb"], rec=full["rec"], pix=pix,
+                               raster=raster))
+    # sampled tile lists, bit-exact, and the exact length of every list
     ranges, ids = ws.tile_lists()
     tiles = rng.choice(ws.layout.tiles_total, 24, replace=False)
     tpv = ws.layout.tiles_x * ws.layout.tiles_y
     sel_t = np.array([[t // tpv, t % tpv] for t in tiles], np.int32)
-    off, oids = oracle.tile_lists(full["rect"], full["zb"], full["D"], 32, sel_t)
+    off, oids = oracle.tile_lists(full["rect"], full["zb"], full["D"], tile, sel_t)
     for s, t in enumerate(tiles):
         b, e = ranges[t]
         assert np.array_equal(ids[b:e], oids[off[s]:off[s + 1]])
+    assert np.array_equal(ranges[:, 1] - ranges[:, 0], tile_counts(full["rect"], full["D"], tile))
 
 
 def test_fullsize_splat_decoder_composite(full):
@@ -96,13 +102,9 @@ def test_fullsize_splat_decoder_composite(full):
     keys, ids = ws.lists()
     assert np.array_equal(np.bincount(keys, minlength=len(off) - 1), np.diff(off))
     assert np.array_equal(ids, oids)
-    # features within 1e-4 of the largest feature magnitude: single-precision
-    # view pixel coordinates near x = 2000 carry ~6e-5 px of rounding, which
-    # the bilinear weights pass on to features of size up to ~4.5
-    fmax = float(np.abs(p["feat"].view(np.float16).astype(np.float64)).max())
     err = float(np.abs(pyr.cpu().numpy() - pyr_o).max())
-    print(f"full-size pyramid max err {err:.2e} (features up to {fmax:.2f})")
-    assert err <= 1e-4 * max(1.0, fmax)
+    print(f"full-size pyramid max err {err:.2e}")
+    assert err <= 1e-4
     # decoder on the reference pyramid and periphery, BF16 as benchmarked
     dw = sc["decoder"]
     packed = synth.pack_decoder(dw)

@@ -157,12 +157,19 @@ def test_rect_holds_three_sigma_ellipse_and_depth_key():
 def _brute_pixels(rect, zb, rec, D, opts=(0.99, 1 / 255, 1e-4)):
     """Independent formulation: per pixel gather every Gaussian (no tiles),
     order with lexsort, apply the skip rule, then take the transmittances
-    as a cumulative product and cut at the first one below t_min."""
+    as a cumulative product and cut at the first one below t_min.  Also the
+    work count (entries of the ordered list up to and including the one that
+    stops the pixel) and the margin (the least relative distance of an
+    evaluated alpha to alpha_min, or of a candidate transmittance to t_min,
+    over the entries the pixel reached)."""
     aclamp, amin, tmin = opts
     W, H = D[0]
-    n = zb.shape[1]
     rgb = np.zeros((3, H, W))
     T = np.ones((H, W))
+    depth = np.zeros((H, W))
+    ncontrib = np.zeros((H, W), np.int64)
+    evals = np.zeros((H, W), np.int64)
+    margin = np.full((H, W), np.inf)
     for y in range(H):
         for x in range(W):
             r = rect[0]
@@ -172,16 +179,25 @@ def _brute_pixels(rect, zb, rec, D, opts=(0.99, 1 / 255, 1e-4)):
             g = rec[0, idx]
             dx, dy = g[:, 0] - (x + 0.5), g[:, 1] - (y + 0.5)
             q = -0.5 * (g[:, 2] * dx * dx + g[:, 4] * dy * dy) - g[:, 3] * dx * dy
-            a = np.minimum(aclamp, g[:, 5] * np.exp(q))
-            keep = (q <= 0) & (a >= amin)
-            a, g = a[keep], g[keep]
+            a_all = np.minimum(aclamp, g[:, 5] * np.exp(q))
+            keep = (q <= 0) & (a_all >= amin)
+            kpos = np.nonzero(keep)[0]            # list positions of the kept entries
+            a, gk = a_all[keep], g[keep]
             Tn = np.cumprod(1 - a)
             stop = np.nonzero(Tn < tmin)[0]
             k = stop[0] if len(stop) else len(a)
             Tb = np.concatenate([[1.0], Tn[:-1]])[:k]
-            rgb[:, y, x] = (g[:k, 6:9] * (a[:k] * Tb)[:, None]).sum(0)
+            rgb[:, y, x] = (gk[:k, 6:9] * (a[:k] * Tb)[:, None]).sum(0)
+            depth[y, x] = (gk[:k, 9] * a[:k] * Tb).sum()
             T[y, x] = Tn[k - 1] if k > 0 else 1.0
-    return rgb, T
+            ncontrib[y, x] = k
+            reach = kpos[k] + 1 if len(stop) else len(idx)
+            evals[y, x] = reach
+            ev = (q <= 0) & (np.arange(len(idx)) < reach)
+            mg = list(np.abs(a_all[ev] - amin) / amin)
+            mg += list(np.abs(Tn[:min(k + 1, len(a))] - tmin) / tmin)
+            margin[y, x] = min(mg) if mg else np.inf
+    return dict(rgb=rgb, tfinal=T, depth=depth, ncontrib=ncontrib, evals=evals, margin=margin)
 
 
 def test_blend_equals_brute_force():
@@ -189,10 +205,79 @@ def test_blend_equals_brute_force():
     rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
     rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
     out = oracle.render(rect, zb, rec, D, tile=16)
-    rgb, T = _brute_pixels(rect, zb, rec, D)
-    np.testing.assert_allclose(out["rgb"][0], rgb, atol=1e-12)
-    np.testing.assert_allclose(out["tfinal"][0], T, atol=1e-12)
+    b = _brute_pixels(rect, zb, rec, D)
+    np.testing.assert_allclose(out["rgb"][0], b["rgb"], atol=1e-12)
+    np.testing.assert_allclose(out["tfinal"][0], b["tfinal"], atol=1e-12)
+    np.testing.assert_allclose(out["depth"][0], b["depth"], atol=1e-12)
+    assert np.array_equal(out["ncontrib"][0], b["ncontrib"])
     assert out["ncontrib"].max() > 3
+    # the work count and the decision margin that parity tests rely on
+    assert np.array_equal(out["evals"][0], b["evals"])
+    assert (out["evals"][0] > out["ncontrib"][0]).any()
+    np.testing.assert_allclose(out["margin"][0], b["margin"], rtol=1e-9)
+
+
+def test_blend_stop_rule_brute_force():
+    """Opaque scene where most pixels stop early: stop positions, work counts
+    and margins (including the transmittance test) against the brute force."""
+    sc, g, cov, op, V, D = _scene(17, n_gauss=300, width=32, height=24, f=40.0)
+    op = np.full_like(op, 0.97)
+    cov = (cov * 4).astype(np.float32)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
+    out = oracle.render(rect, zb, rec, D, tile=8)
+    b = _brute_pixels(rect, zb, rec, D)
+    stopped = out["tfinal"][0] * (1 - 0.99) < 1e-4
+    assert stopped.mean() > 0.2
+    assert np.array_equal(out["ncontrib"][0], b["ncontrib"])
+    assert np.array_equal(out["evals"][0], b["evals"])
+    np.testing.assert_allclose(out["margin"][0], b["margin"], rtol=1e-9)
+    np.testing.assert_allclose(out["rgb"][0], b["rgb"], atol=1e-12)
+
+
+def test_render_branches_cover_perturbed_thresholds():
+    """Where a pixel's decisions lie near a threshold, the branch results
+    include the float64 result and the results of renders whose thresholds
+    are moved by a fraction of the margin either way."""
+    sc, g, cov, op, V, D = _scene(19, n_gauss=600, width=48, height=40, f=48.0)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
+    base = oracle.render(rect, zb, rec, D, tile=8)
+    margin = 3e-3   # wide, so that the small scene has near-threshold pixels
+    yy, xx = np.nonzero(base["margin"][0] < margin)
+    assert len(yy) >= 5
+    pix = np.stack([np.zeros_like(xx), xx, yy], 1)
+    alts = oracle.render_branches(rect, zb, rec, pix, margin=margin)
+    variants = [base]
+    for fa in (1 - 2e-3, 1 + 2e-3):
+        for ft in (1 - 2e-3, 1 + 2e-3):
+            variants.append(oracle.render(rect, zb, rec, D, tile=8, alpha_min=fa / 255,
+                                          t_min=ft * 1e-4))
+    flipped = 0
+    for k, (x, y) in enumerate(zip(xx, yy)):
+        assert len(alts[k]) >= 2
+        n0, c0, d0, t0 = alts[k][0]
+        assert n0 == base["ncontrib"][0, y, x] and abs(t0 - base["tfinal"][0, y, x]) < 1e-12
+        for vo in variants:
+            ref = (vo["ncontrib"][0, y, x], vo["rgb"][0, :, y, x], vo["depth"][0, y, x],
+                   vo["tfinal"][0, y, x])
+            assert any(n == ref[0] and np.abs(c - ref[1]).max() < 1e-12 and abs(d - ref[2]) < 1e-12
+                       and abs(t - ref[3]) < 1e-12 for n, c, d, t in alts[k])
+            flipped += vo["ncontrib"][0, y, x] != base["ncontrib"][0, y, x]
+    assert flipped > 0
+
+
+def test_tile_counts_helper_matches_lists():
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from gpu_helpers import tile_counts
+    sc, g, cov, op, V, D = _scene(5, n_gauss=400, width=70, height=50, f=60.0)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    for tile in (8, 16):
+        tx, ty = -(-70 // tile), -(-50 // tile)
+        sel = np.array([[0, t] for t in range(tx * ty)], np.int32)
+        off, _ = oracle.tile_lists(rect, zb, D, tile, sel)
+        assert np.array_equal(tile_counts(rect, D, tile), np.diff(off))
 
 
 def test_single_gaussian_closed_form():

@@ -101,6 +101,36 @@ def test_render_forward_matches_cpp():
     np.testing.assert_allclose(out["tfinal"].detach().numpy().reshape(2, 32, 40), ref["tfinal"], atol=1e-12)
 
 
+def test_render_cut_at_reach_is_identical():
+    """Cutting each pixel's list after its evaluation count (the entries past
+    the stop are never reached) leaves the forward and its gradient as they
+    are; an opaque scene makes most pixels stop early."""
+    sc, g, cov, op, V, D = _render_setup(4, n=500)
+    op = np.full_like(op, 0.99)
+    cov = (cov * 8).astype(np.float32)
+    raster = sc["raster"]
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 1, V, D)
+    ref = oracle.render(rect, zb, rec, D)
+    pix = np.array([(v, x, y) for v in range(2) for y in range(32) for x in range(40)])
+    reach = ref["evals"][pix[:, 0], pix[:, 2], pix[:, 1]]
+    full_len = diff.pixel_lists(rect, zb, pix)[1].sum(1)
+    assert (reach < full_len).mean() > 0.3
+    rng = np.random.default_rng(1)
+    cr = torch.tensor(rng.normal(size=(len(pix), 3)))
+    grads = []
+    for r in (None, reach):
+        P = _params(mean=g["mean"], cov=cov, op=op, sh=g["sh"])
+        out = diff.render(P["mean"], P["cov"], P["op"], P["sh"], 1, V, D, pix, raster, reach=r)
+        (out["rgb"] * cr).sum().backward()
+        grads.append((out, {k: v.grad.clone() for k, v in P.items()}))
+    (a, ga), (b, gb) = grads
+    for k in ("rgb", "depth", "tfinal"):
+        assert torch.equal(a[k], b[k]), k
+    for k in ga:
+        torch.testing.assert_close(ga[k], gb[k], rtol=1e-12, atol=1e-15)
+
+
 def test_render_gradient_central_differences():
     sc, g, cov, op, V, D = _render_setup(3, n=60, W=24, H=20, f=24.0, deg=2, nv=1)
     raster = sc["raster"]
