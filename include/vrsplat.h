@@ -205,6 +205,18 @@ vrs_status vrs_render_gaussians_backward(const float* mean, const float* cov,
 size_t vrs_spatial_order_workspace_size(int64_t n);
 vrs_status vrs_spatial_order(const float* pos, int64_t n, uint32_t* perm, void* ws,
                              size_t ws_bytes, void* stream);
+/* Allocation-free form of vrs_spatial_order, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same permutation, with the scratch
+ * memory taken from a fixed device array inside the library (12.5 MB per
+ * device, held until the process ends) instead of a workspace.  At most
+ * VRS_NOALLOC_MAX_POINTS points per call (VRS_EINVAL beyond, or on null
+ * pointers or n < 1).  Every call on one device shares that array, so calls
+ * that overlap on a device (concurrent streams or threads) race; calls on one
+ * stream are ordered and safe.  Allocates nothing, not even on its first call
+ * on a device (which only looks up the array's device address). */
+enum { VRS_NOALLOC_MAX_POINTS = 1 << 20 };
+vrs_status vrs_spatial_order_noalloc(const float* pos, int64_t n, uint32_t* perm, void* stream);
 
 /* ---------------------------------------------------------------- fovea
  * Neural-point splat into a multi-resolution pyramid for every crop

@@ -75,6 +75,7 @@ SIGNATURES = {
     "vrs_bake_gaussians": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "vrs_spatial_order_workspace_size": (_sz, [_i64]),
     "vrs_spatial_order": (_int, [_vp, _i64, _vp, _vp, _sz, _vp]),
+    "vrs_spatial_order_noalloc": (_int, [_vp, _i64, _vp, _vp]),
     "vrs_bake_gaussians_backward": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "vrs_render_workspace_size": (_sz, [_i64, _int, _P(View), _P(RasterOpts), _i64]),
     "vrs_render_workspace_layout": (_int, [_i64, _int, _P(View), _P(RasterOpts), _i64,
@@ -229,6 +230,19 @@ def spatial_order(pos):
     perm = torch.empty(n, dtype=torch.int32, device=pos.device)
     _check(lib().vrs_spatial_order(ptr(pos, torch.float32), n, ptr(perm), ptr(ws), size, _stream()),
            "vrs_spatial_order")
+    return perm
+
+
+NOALLOC_MAX_POINTS = 1 << 20
+
+
+def spatial_order_noalloc(pos):
+    """vrs_spatial_order_noalloc: the same permutation with no workspace
+    (the library's fixed scratch; at most NOALLOC_MAX_POINTS points)."""
+    n = pos.shape[1]
+    perm = torch.empty(n, dtype=torch.int32, device=pos.device)
+    _check(lib().vrs_spatial_order_noalloc(ptr(pos, torch.float32), n, ptr(perm), _stream()),
+           "vrs_spatial_order_noalloc")
     return perm
 
 

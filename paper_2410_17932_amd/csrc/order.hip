@@ -9,6 +9,8 @@
 //                         encoding of floats, so min/max are integer atomics)
 //   k_morton              10 bits per axis, interleaved x, y, z -> 30-bit key
 //   radix sort            stable, 30 bits: ties keep index order
+#include <mutex>
+
 #include "vrs_common.h"
 
 namespace vrs {
@@ -113,21 +115,43 @@ bool order_layout(int64_t n, OrderWs* L) {
   return true;
 }
 
-}  // namespace
-}  // namespace vrs
+// Allocation-free variant: its scratch is a file-scope device array sized
+// for kNoAllocMaxPoints points (the layout above at that size: bounds, Morton
+// keys, the sort's second key and value buffers and its partition counts).
+constexpr int64_t kNoAllocMaxPoints = int64_t(1) << 20;
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kNoAllocBytes =
+    align256(align256(align256(align256(24) + kNoAllocMaxPoints * 4) + kNoAllocMaxPoints * 4) +
+             kNoAllocMaxPoints * 4) +
+    (256 + 256 * (size_t)((kNoAllocMaxPoints + 2047) / 2048)) * 4;
 
-using namespace vrs;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
-extern "C" size_t vrs_spatial_order_workspace_size(int64_t n) {
-  OrderWs L;
-  return order_layout(n, &L) ? L.total : 0;
+// Device address of `scratch` on each device, taken once per device (with
+// that device current) on the first call there.  In host code the array's
+// name is only a stand-in symbol; kernels and copies get this address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
-extern "C" vrs_status vrs_spatial_order(const float* pos, int64_t n, uint32_t* perm, void* ws,
-                                        size_t ws_bytes, void* stream) {
-  OrderWs L;
-  if (!pos || !perm || !ws || !order_layout(n, &L) || ws_bytes < L.total) return VRS_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+vrs_status spatial_order_run(const float* pos, int64_t n, uint32_t* perm, void* ws,
+                             const OrderWs& L, hipStream_t st) {
   uint32_t* bb = at<uint32_t>(ws, L.bb);
   hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, bb);
   VRS_LAUNCH_CHECK();
@@ -148,4 +172,31 @@ extern "C" vrs_status vrs_spatial_order(const float* pos, int64_t n, uint32_t* p
     VRS_LAUNCH_CHECK();
   }
   return VRS_OK;
+}
+
+}  // namespace
+}  // namespace vrs
+
+using namespace vrs;
+
+extern "C" size_t vrs_spatial_order_workspace_size(int64_t n) {
+  OrderWs L;
+  return order_layout(n, &L) ? L.total : 0;
+}
+
+extern "C" vrs_status vrs_spatial_order(const float* pos, int64_t n, uint32_t* perm, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  OrderWs L;
+  if (!pos || !perm || !ws || !order_layout(n, &L) || ws_bytes < L.total) return VRS_EINVAL;
+  return spatial_order_run(pos, n, perm, ws, L, static_cast<hipStream_t>(stream));
+}
+
+extern "C" vrs_status vrs_spatial_order_noalloc(const float* pos, int64_t n, uint32_t* perm,
+                                                void* stream) {
+  OrderWs L;
+  if (!pos || !perm || n > kNoAllocMaxPoints || !order_layout(n, &L) || L.total > kNoAllocBytes)
+    return VRS_EINVAL;
+  void* ws = nullptr;
+  VRS_HIP_CHECK(scratch_address(&ws));
+  return spatial_order_run(pos, n, perm, ws, L, static_cast<hipStream_t>(stream));
 }
