@@ -34,18 +34,18 @@ def log(*a):
 
 
 def stage_ms(frame, stage, steps):
-    """Average duration of one stage's kernels over `steps` eager frames,
-    from HIP events recorded by the library around the stage."""
+    """Average duration of one stage's kernels over `steps` eager inference
+    frames, from HIP events the library records around the stage on the
+    frame's stream (the plan's trace table)."""
     import torch
-    from paper_2410_17932_amd import api
     evs = []
     tot = 0.0
     for _ in range(steps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        api.trace_set(stage, a, b)
+        frame.trace(stage, a, b)
         frame.run()
         evs.append((a, b))
-    api.trace_set("off")
+    frame.trace("off")
     torch.cuda.synchronize()
     for a, b in evs:
         tot += a.elapsed_time(b)
@@ -161,11 +161,14 @@ def measured_traffic(profile, source):
 
 
 def blend_work(frame):
-    """Algorithmic floating-point work of the last periphery blend: every
+    """Algorithmic floating-point work of the periphery blend: every
     evaluation of a Gaussian at a pixel inside its rectangle costs 14 flops
     (offset, quadratic form, exp, opacity, clamp, transmittance product) and
-    each blended contribution 11 more (colour and depth accumulation)."""
+    each blended contribution 11 more (colour and depth accumulation).  The
+    counts come from one instrumented frame (the timed frames do not count)."""
     import torch
+    frame.run(stats=True)
+    torch.cuda.synchronize()
     npix = frame.depth.numel()
     evals = frame.rws.pixel_evals(npix).to(torch.int64).sum().item()
     contrib = frame.ncontrib.to(torch.int64).sum().item()

@@ -80,10 +80,27 @@ typedef struct {
   float gaze_x, gaze_y;
 } vrs_crop;
 
-/* Rasteriser options.  Defaults: tile 16, alpha_clamp 0.99,
- * alpha_min 1/255, t_min 1e-4, lowpass 0.3, extent 3, bg 0. */
+/* Run-time placement of crop k, in DEVICE memory (an array [n_crops] of
+ * these, 16 bytes each): origin (x0, y0) and fixation point (gaze_x,
+ * gaze_y) in view pixels.  Entry points that take a `place` argument read
+ * the crops' origins and gazes from it when it is not NULL (the host
+ * vrs_crop then supplies only view and size, and its origin is not
+ * checked), so a captured frame takes a new fixation by rewriting this
+ * table -- the paper queries the eye tracker only after the periphery is
+ * rendered (Sec. 4 "Inference").  Origins read from the table are clamped
+ * into the view, [0, W - size] x [0, H - size]. */
+typedef struct {
+  int32_t x0, y0;
+  float gaze_x, gaze_y;
+} vrs_crop_place;
+
+/* Rasteriser options.  Defaults: tile 16, radix_bits 8, alpha_clamp 0.99,
+ * alpha_min 1/255, t_min 1e-4, lowpass 0.3, extent 3, bg 0.  tile and
+ * radix_bits change only the work's organisation, never a result: they are
+ * the autotuner's choices. */
 typedef struct {
   int32_t tile;          /* screen tile edge: 8, 16 or 32 */
+  int32_t radix_bits;    /* digit width of the radix sorts: 4, 6, 8 or 11 (0 = 8) */
   float alpha_clamp;     /* alpha = min(alpha_clamp, opacity e^q) */
   float alpha_min;       /* contributions with alpha < alpha_min are skipped */
   float t_min;           /* a pixel stops before T would fall below t_min */
@@ -247,7 +264,8 @@ size_t vrs_splat_workspace_size(int64_t np, int n_views, const vrs_view* views,
 vrs_status vrs_splat_points(const float* pos, const float* radius, const uint16_t* feat,
                             const float* opacity, int64_t np, int channels, int levels,
                             const vrs_view* views, int n_views, const vrs_crop* crops,
-                            int n_crops, const float* depth, const float* t_final,
+                            int n_crops, const vrs_crop_place* place, const float* depth,
+                            const float* t_final,
                             float cov_min, float slack, const uint32_t* point_ids,
                             float* pyramid, void* ws, size_t ws_bytes, int64_t max_frags,
                             int32_t* dev_status, void* stream);
@@ -269,9 +287,22 @@ vrs_status vrs_splat_points_backward(const float* pos, const float* radius,
                                      const uint16_t* feat, const float* opacity, int64_t np,
                                      int channels, int levels, const vrs_view* views,
                                      int n_views, const vrs_crop* crops, int n_crops,
-                                     const float* d_pyramid, float* d_feat, float* d_pos,
-                                     float* d_radius, float* d_opacity, void* ws,
-                                     size_t ws_bytes, int64_t max_frags, void* stream);
+                                     const vrs_crop_place* place, const float* d_pyramid,
+                                     float* d_feat, float* d_pos, float* d_radius,
+                                     float* d_opacity, void* ws, size_t ws_bytes,
+                                     int64_t max_frags, void* stream);
+
+/* Crop placement from fixation points (Sec. 3.3 sub-frustum around the
+ * gaze; Sec. 4 "Inference"): gaze [n_crops][2] float32 (DEVICE, view pixels)
+ * -> place [n_crops] (DEVICE), each crop of its host size centred on its
+ * gaze with the integer origin x0 = clamp(rint(gaze_x - size/2), 0,
+ * W - size) (rint rounds ties to even; y0 likewise), the gaze stored beside
+ * it.  One small kernel on `stream`, capturable; view and size come from the
+ * host crops (their origins are ignored).  VRS_EINVAL on null pointers, no
+ * crops, a bad view or a crop larger than its view. */
+vrs_status vrs_place_crops(const float* gaze, const vrs_view* views, int n_views,
+                           const vrs_crop* crops, int n_crops, vrs_crop_place* place,
+                           void* stream);
 
 /* -------------------------------------------------------------- decoder
  * Small gated CNN turning each crop's pyramid into its foveal image F
@@ -287,15 +318,17 @@ size_t vrs_decoder_workspace_size(const vrs_decoder_desc* dd, const vrs_crop* cr
                                   int n_crops);
 vrs_status vrs_decode_fovea(const float* pyramid, int levels, const float* rgb_periphery,
                             const vrs_view* views, int n_views, const vrs_crop* crops,
-                            int n_crops, const float* weights, const vrs_decoder_desc* dd,
-                            float* fovea_rgb, void* ws, size_t ws_bytes, void* stream);
+                            int n_crops, const vrs_crop_place* place, const float* weights,
+                            const vrs_decoder_desc* dd, float* fovea_rgb, void* ws,
+                            size_t ws_bytes, void* stream);
 /* Adjoint of vrs_decode_fovea: from d_fovea accumulates d_pyramid (may be
  * NULL), d_rgb_periphery (may be NULL) and d_weights (packed like weights,
  * may be NULL). */
 vrs_status vrs_decode_fovea_backward(const float* pyramid, int levels,
                                      const float* rgb_periphery, const vrs_view* views,
                                      int n_views, const vrs_crop* crops, int n_crops,
-                                     const float* weights, const vrs_decoder_desc* dd,
+                                     const vrs_crop_place* place, const float* weights,
+                                     const vrs_decoder_desc* dd,
                                      const float* d_fovea, float* d_pyramid,
                                      float* d_rgb_periphery, float* d_weights, void* ws,
                                      size_t ws_bytes, void* stream);
@@ -314,14 +347,15 @@ vrs_status vrs_decode_fovea_backward(const float* pyramid, int levels,
  * the crops are read and written (the rest already hold P). */
 vrs_status vrs_composite_frame(const float* rgb_periphery, int n_views, int width, int height,
                                const float* fovea_rgb, const vrs_crop* crops, int n_crops,
-                               int mode, float ring, float m, float gamma, float* out,
-                               void* stream);
+                               const vrs_crop_place* place, int mode, float ring, float m,
+                               float gamma, float* out, void* stream);
 /* Adjoint: from d_out accumulates d_rgb_periphery and d_fovea (either may be
  * NULL).  In VRS_BLEND_PAPER mode the edge term's dependence on F is
  * differentiated too. */
 vrs_status vrs_composite_frame_backward(const float* rgb_periphery, int n_views, int width,
                                         int height, const float* fovea_rgb,
-                                        const vrs_crop* crops, int n_crops, int mode,
+                                        const vrs_crop* crops, int n_crops,
+                                        const vrs_crop_place* place, int mode,
                                         float ring, float m, float gamma, const float* d_out,
                                         float* d_rgb_periphery, float* d_fovea, void* stream);
 
@@ -332,21 +366,100 @@ vrs_status vrs_composite_frame_backward(const float* rgb_periphery, int n_views,
 vrs_status vrs_l1_loss(const float* pred, const float* target, int64_t n, float* loss,
                        float* d_pred, float scale, void* stream);
 
-/* ------------------------------------------------------------- tracing
- * Stage timing hook: while set, every call that runs `stage` records the
- * caller's HIP event `start_event` on its stream right before the stage's
- * first kernel and `stop_event` right after its last one (the events may be
- * recorded many times; the caller reads the last pair).  stage 0 turns the
- * hook off.  Process-wide setting, not thread-safe; meant for benchmarks
- * and profilers.  Stages: 1 periphery blend, 2 periphery tile-pair sort,
- * 3 periphery preprocess, 4 periphery pair emission, 5 whole point splat,
- * 6 whole decoder, 7 composite, 8 periphery depth sort + scan. */
+/* ---------------------------------------------------------- frame plan
+ * Everything fixed across the frames of one scene and rig: views, crop
+ * views and sizes, the pyramid depth, the rasteriser options with the
+ * autotuned tile size and sort radix, the capacities (tile pairs, point
+ * fragments) sized by counting passes, the decoder shape, the depth cull and
+ * the combination.  The plan is host memory only (a copy of the descriptor
+ * and of the views and crops arrays); it owns no device memory: the
+ * workspaces are the caller's, of vrs_workspace_size bytes each.  It may be
+ * shared by streams that each have their own workspaces and buffers. */
+typedef struct {
+  int32_t n_views;
+  const vrs_view* views;        /* [n_views], all of one width and height */
+  int64_t n_gaussians;
+  int32_t sh_degree;
+  int64_t n_points;
+  int32_t point_channels;       /* 4 */
+  int32_t levels;               /* pyramid layers */
+  int32_t n_crops;
+  const vrs_crop* crops;        /* [n_crops]: view and size (origins are the
+                                   frame's gaze placement, or these) */
+  vrs_raster_opts raster;
+  vrs_decoder_desc decoder;
+  int32_t depth_cull;           /* cull points against the periphery (Sec. 3.3) */
+  float cov_min, slack;         /* depth-cull rule, see vrs_splat_points */
+  int32_t blend_mode;           /* VRS_BLEND_LINEAR or VRS_BLEND_PAPER */
+  float ring, m, gamma;         /* combination (Sec. 3.4) */
+  int64_t max_pairs, max_frags; /* capacities */
+} vrs_plan_desc;
+typedef struct vrs_plan vrs_plan;   /* opaque */
+enum { VRS_WS_RENDER = 0, VRS_WS_SPLAT = 1, VRS_WS_DECODER = 2 };
+/* VRS_EINVAL for any bad field (each stage's own checks), VRS_EUNSUPPORTED
+ * for point_channels other than 4; *plan is NULL then. */
+vrs_status vrs_plan_create(const vrs_plan_desc* desc, vrs_plan** plan);
+void vrs_plan_destroy(vrs_plan* plan);
+/* Workspace bytes of the frame's stage `which` (VRS_WS_*), 0 if invalid. */
+size_t vrs_workspace_size(const vrs_plan* plan, int which);
+/* Copy of the plan's descriptor (its pointers refer to the plan's copies). */
+vrs_status vrs_plan_describe(const vrs_plan* plan, vrs_plan_desc* out);
+
+/* Stage timing on a plan: while set, vrs_render_frame records the caller's
+ * HIP event start_event on its stream right before stage `stage`'s first
+ * kernel and stop_event right after its last one (the caller reads the last
+ * pair).  VRS_TRACE_OFF clears every stage.  Not to be changed while a
+ * frame of this plan is being enqueued by another thread. */
 enum {
   VRS_TRACE_OFF = 0, VRS_TRACE_GS_BLEND = 1, VRS_TRACE_GS_SORT = 2, VRS_TRACE_GS_PREPROCESS = 3,
   VRS_TRACE_GS_EMIT = 4, VRS_TRACE_SPLAT = 5, VRS_TRACE_DECODER = 6, VRS_TRACE_COMPOSITE = 7,
   VRS_TRACE_GS_DEPTH_SORT = 8
 };
-vrs_status vrs_trace_set(int stage, void* start_event, void* stop_event);
+vrs_status vrs_plan_trace(vrs_plan* plan, int stage, void* start_event, void* stop_event);
+
+/* Scene of a frame (DEVICE pointers, caller-owned): baked Gaussians as for
+ * vrs_render_gaussians, points as for vrs_splat_points (point_opacity and
+ * point_ids may be NULL), decoder weights packed as for vrs_decode_fovea. */
+typedef struct {
+  const float *mean, *cov, *opacity, *sh;
+  const float *pos, *radius;
+  const uint16_t* feat;
+  const float* point_opacity;
+  const uint32_t* point_ids;
+  const float* decoder_weights;
+} vrs_scene;
+
+/* Per-frame buffers (DEVICE, caller-owned).  rgb receives the periphery and
+ * then, in place, the combined frame; depth, t_final and n_contrib the
+ * periphery's; pyramid and fovea_rgb the foveal stages' (packed as for
+ * vrs_splat_points and vrs_decode_fovea); place the crops' placement when a
+ * gaze is given; the three workspaces of vrs_workspace_size bytes; the
+ * capacity status words (zeroed by the caller). */
+typedef struct {
+  float *rgb, *depth, *t_final;
+  int32_t* n_contrib;
+  float *pyramid, *fovea_rgb;
+  vrs_crop_place* place;
+  void *ws_render, *ws_splat, *ws_decoder;
+  int32_t *status_render, *status_splat;
+} vrs_frame_buffers;
+
+/* One stereo foveated frame (Fig. 5): periphery of every view
+ * (vrs_render_gaussians), then -- when gaze (DEVICE, float32 [n_crops][2],
+ * view pixels) is given -- the crops placed on the device from the gaze read
+ * at that point (vrs_place_crops; else the plan's crop origins), the point
+ * splat culled against the periphery's depth (vrs_splat_points), the decoder
+ * (vrs_decode_fovea) and the combination written into rgb
+ * (vrs_composite_frame in place).  Results equal those of the stage entry
+ * points called in that order.  flags: VRS_FRAME_STATS also keeps in the
+ * render workspace the per-pixel last contributing positions and evaluation
+ * counts (the adjoint's replay start and the blend's work count, see
+ * vrs_render_workspace_layout); an inference frame leaves them out.
+ * Asynchronous on `stream`, capturable into a HIP graph; a captured frame
+ * follows new gaze-buffer contents without being captured again. */
+enum { VRS_FRAME_STATS = 1 };
+vrs_status vrs_render_frame(const vrs_plan* plan, const vrs_scene* scene, const float* gaze,
+                            const vrs_frame_buffers* buffers, int32_t flags, void* stream);
 
 #ifdef __cplusplus
 }

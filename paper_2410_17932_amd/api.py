@@ -41,7 +41,8 @@ class Crop(ctypes.Structure):
 
 
 class RasterOpts(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("alpha_clamp", ctypes.c_float),
+    _fields_ = [("tile", ctypes.c_int32), ("radix_bits", ctypes.c_int32),
+                ("alpha_clamp", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("lowpass", ctypes.c_float), ("extent", ctypes.c_float),
                 ("bg", ctypes.c_float * 3)]
@@ -68,6 +69,29 @@ class SplatLayout(ctypes.Structure):
 _vp, _i64, _int, _flt, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
 _P = ctypes.POINTER
 
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32), ("views", _P(View)),
+                ("n_gaussians", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
+                ("n_points", ctypes.c_int64), ("point_channels", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("n_crops", ctypes.c_int32), ("crops", _P(Crop)),
+                ("raster", RasterOpts), ("decoder", DecoderDesc),
+                ("depth_cull", ctypes.c_int32), ("cov_min", ctypes.c_float),
+                ("slack", ctypes.c_float), ("blend_mode", ctypes.c_int32),
+                ("ring", ctypes.c_float), ("m", ctypes.c_float), ("gamma", ctypes.c_float),
+                ("max_pairs", ctypes.c_int64), ("max_frags", ctypes.c_int64)]
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("mean", "cov", "opacity", "sh", "pos", "radius", "feat",
+                                   "point_opacity", "point_ids", "decoder_weights")]
+
+
+class FrameBuffers(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("rgb", "depth", "t_final", "n_contrib", "pyramid",
+                                   "fovea_rgb", "place", "ws_render", "ws_splat", "ws_decoder",
+                                   "status_render", "status_splat")]
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = {
     "vrs_status_string": (ctypes.c_char_p, [_int]),
@@ -90,23 +114,32 @@ SIGNATURES = {
     "vrs_splat_workspace_layout": (_int, [_i64, _int, _P(View), _P(Crop), _int, _int, _i64,
                                           _P(SplatLayout)]),
     "vrs_splat_points": (_int, [_vp, _vp, _vp, _vp, _i64, _int, _int, _P(View), _int,
-                                _P(Crop), _int, _vp, _vp, _flt, _flt, _vp, _vp, _vp, _sz,
-                                _i64, _vp, _vp]),
+                                _P(Crop), _int, _vp, _vp, _vp, _flt, _flt, _vp, _vp, _vp,
+                                _sz, _i64, _vp, _vp]),
     "vrs_splat_points_backward": (_int, [_vp, _vp, _vp, _vp, _i64, _int, _int, _P(View), _int,
-                                         _P(Crop), _int, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
-                                         _i64, _vp]),
+                                         _P(Crop), _int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _sz, _i64, _vp]),
+    "vrs_place_crops": (_int, [_vp, _P(View), _int, _P(Crop), _int, _vp, _vp]),
     "vrs_decoder_workspace_size": (_sz, [_P(DecoderDesc), _P(Crop), _int]),
-    "vrs_decode_fovea": (_int, [_vp, _int, _vp, _P(View), _int, _P(Crop), _int, _vp,
+    "vrs_decode_fovea": (_int, [_vp, _int, _vp, _P(View), _int, _P(Crop), _int, _vp, _vp,
                                 _P(DecoderDesc), _vp, _vp, _sz, _vp]),
     "vrs_decode_fovea_backward": (_int, [_vp, _int, _vp, _P(View), _int, _P(Crop), _int, _vp,
-                                         _P(DecoderDesc), _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
-    "vrs_composite_frame": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _int, _flt,
-                                   _flt, _flt, _vp, _vp]),
-    "vrs_composite_frame_backward": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _int,
-                                            _flt, _flt, _flt, _vp, _vp, _vp, _vp]),
+                                         _vp, _P(DecoderDesc), _vp, _vp, _vp, _vp, _vp, _sz,
+                                         _vp]),
+    "vrs_composite_frame": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _vp, _int,
+                                   _flt, _flt, _flt, _vp, _vp]),
+    "vrs_composite_frame_backward": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _vp,
+                                            _int, _flt, _flt, _flt, _vp, _vp, _vp, _vp]),
     "vrs_l1_loss": (_int, [_vp, _vp, _i64, _vp, _vp, _flt, _vp]),
-    "vrs_trace_set": (_int, [_int, _vp, _vp]),
+    "vrs_plan_create": (_int, [_P(PlanDesc), _P(_vp)]),
+    "vrs_plan_destroy": (None, [_vp]),
+    "vrs_workspace_size": (_sz, [_vp, _int]),
+    "vrs_plan_describe": (_int, [_vp, _P(PlanDesc)]),
+    "vrs_plan_trace": (_int, [_vp, _int, _vp, _vp]),
+    "vrs_render_frame": (_int, [_vp, _P(Scene), _vp, _P(FrameBuffers), ctypes.c_int32, _vp]),
 }
+WS_RENDER, WS_SPLAT, WS_DECODER = 0, 1, 2
+FRAME_STATS = 1
 
 TRACE = dict(off=0, gs_blend=1, gs_sort=2, gs_preprocess=3, gs_emit=4, splat=5, decoder=6,
              composite=7, gs_depth_sort=8)
@@ -182,9 +215,10 @@ def make_crops(crops) -> ctypes.Array:
 
 
 def make_opts(tile=16, alpha_clamp=0.99, alpha_min=1 / 255, t_min=1e-4, lowpass=0.3, extent=3.0,
-              bg=(0.0, 0.0, 0.0), **_) -> RasterOpts:
+              bg=(0.0, 0.0, 0.0), radix_bits=8, **_) -> RasterOpts:
     o = RasterOpts()
-    o.tile, o.alpha_clamp, o.alpha_min, o.t_min = tile, alpha_clamp, alpha_min, t_min
+    o.tile, o.radix_bits = tile, radix_bits
+    o.alpha_clamp, o.alpha_min, o.t_min = alpha_clamp, alpha_min, t_min
     o.lowpass, o.extent = lowpass, extent
     for k in range(3):
         o.bg[k] = bg[k]
@@ -365,19 +399,35 @@ class SplatWorkspace:
         return keys, vals[0::2].astype(np.int64)   # low word of each 64-bit value
 
 
+def crop_places(n_crops, device="cuda"):
+    """Device table of vrs_crop_place records [n][4] (int32 x0, y0 and the
+    float32 gaze bits), filled by place_crops."""
+    return torch.zeros((max(n_crops, 1), 4), dtype=torch.int32, device=device)
+
+
+def place_crops(gaze, views, crops, place):
+    """vrs_place_crops: gaze [n][2] float32 device tensor -> place table."""
+    _check(lib().vrs_place_crops(ptr(gaze, torch.float32), make_views(views), len(views),
+                                 make_crops(crops), len(crops), ptr(place, torch.int32),
+                                 _stream()), "vrs_place_crops")
+    return place
+
+
 def splat_points(pos, radius, feat, opacity, views, crops, levels, depth, tfinal, ws,
-                 cov_min=0.5, slack=1.05, pyramid=None, point_ids=None):
+                 cov_min=0.5, slack=1.05, pyramid=None, point_ids=None, place=None):
     """vrs_splat_points; point_ids (int32 device tensor [np], optional): the
     caller's index of each stored point, which orders fragments of equal
-    depth."""
+    depth; place (crop_places table, optional): crop origins and gazes read
+    on the device."""
     P = pyramid_pixels(crops, levels)
     C = feat.shape[1]
     if pyramid is None:
         pyramid = torch.empty((P, C), device=pos.device, dtype=torch.float32)
     code = lib().vrs_splat_points(
         ptr(pos, torch.float32), ptr(radius, torch.float32), ptr(feat), ptr(opacity),
-        pos.shape[1], C, levels, ws.cviews, len(views), ws.ccrops, len(crops), ptr(depth),
-        ptr(tfinal), cov_min, slack, ptr(point_ids, torch.int32), ptr(pyramid), ptr(ws.buf),
+        pos.shape[1], C, levels, ws.cviews, len(views), ws.ccrops, len(crops),
+        ptr(place, torch.int32), ptr(depth), ptr(tfinal), cov_min, slack,
+        ptr(point_ids, torch.int32), ptr(pyramid), ptr(ws.buf),
         ws.buf.numel(), ws.max_frags, ptr(ws.status), _stream())
     _check(code, "vrs_splat_points")
     ws.generation += 1
@@ -385,11 +435,11 @@ def splat_points(pos, radius, feat, opacity, views, crops, levels, depth, tfinal
 
 
 def splat_points_backward(pos, radius, feat, opacity, views, crops, levels, d_pyramid, ws,
-                          d_feat=None, d_pos=None, d_radius=None, d_opacity=None):
+                          d_feat=None, d_pos=None, d_radius=None, d_opacity=None, place=None):
     code = lib().vrs_splat_points_backward(
         ptr(pos, torch.float32), ptr(radius, torch.float32), ptr(feat), ptr(opacity),
         pos.shape[1], feat.shape[1], levels, ws.cviews, len(views), ws.ccrops, len(crops),
-        ptr(d_pyramid, torch.float32), ptr(d_feat), ptr(d_pos), ptr(d_radius), ptr(d_opacity),
+        ptr(place, torch.int32), ptr(d_pyramid, torch.float32), ptr(d_feat), ptr(d_pos), ptr(d_radius), ptr(d_opacity),
         ptr(ws.buf), ws.buf.numel(), ws.max_frags, _stream())
     _check(code, "vrs_splat_points_backward")
 
@@ -415,13 +465,14 @@ def fovea_elements(crops) -> int:
 
 
 def decode_fovea(pyramid, levels, periphery, views, crops, weights, ws: DecoderWorkspace,
-                 out=None):
+                 out=None, place=None):
     if out is None:
         out = torch.empty(fovea_elements(crops), device=pyramid.device, dtype=torch.float32)
     cviews = make_views(views)
     code = lib().vrs_decode_fovea(ptr(pyramid, torch.float32), levels,
                                   ptr(periphery, torch.float32), cviews, len(views), ws.ccrops,
-                                  len(crops), ptr(weights, torch.float32), ctypes.byref(ws.desc),
+                                  len(crops), ptr(place, torch.int32),
+                                  ptr(weights, torch.float32), ctypes.byref(ws.desc),
                                   ptr(out), ptr(ws.buf), ws.buf.numel(), _stream())
     _check(code, "vrs_decode_fovea")
     ws.generation += 1
@@ -429,11 +480,12 @@ def decode_fovea(pyramid, levels, periphery, views, crops, weights, ws: DecoderW
 
 
 def decode_fovea_backward(pyramid, levels, periphery, views, crops, weights, ws, d_fovea,
-                          d_pyramid=None, d_periphery=None, d_weights=None):
+                          d_pyramid=None, d_periphery=None, d_weights=None, place=None):
     cviews = make_views(views)
     code = lib().vrs_decode_fovea_backward(
         ptr(pyramid, torch.float32), levels, ptr(periphery, torch.float32), cviews, len(views),
-        ws.ccrops, len(crops), ptr(weights, torch.float32), ctypes.byref(ws.desc),
+        ws.ccrops, len(crops), ptr(place, torch.int32), ptr(weights, torch.float32),
+        ctypes.byref(ws.desc),
         ptr(d_fovea, torch.float32), ptr(d_pyramid), ptr(d_periphery), ptr(d_weights),
         ptr(ws.buf), ws.buf.numel(), _stream())
     _check(code, "vrs_decode_fovea_backward")
@@ -441,7 +493,7 @@ def decode_fovea_backward(pyramid, levels, periphery, views, crops, weights, ws,
 
 # ------------------------------------------------------------- combine
 def composite_frame(periphery, fovea, crops, mode=BLEND_LINEAR, ring=64.0, m=0.75, gamma=0.2,
-                    out=None):
+                    out=None, place=None):
     """vrs_composite_frame; out may be `periphery` itself (in place: only the
     pixels under the crops are read and written)."""
     V, _, H, W = periphery.shape
@@ -449,30 +501,72 @@ def composite_frame(periphery, fovea, crops, mode=BLEND_LINEAR, ring=64.0, m=0.7
         out = torch.empty_like(periphery)
     code = lib().vrs_composite_frame(ptr(periphery, torch.float32), V, W, H,
                                      ptr(fovea, torch.float32), make_crops(crops), len(crops),
-                                     mode, ring, m, gamma, ptr(out), _stream())
+                                     ptr(place, torch.int32), mode, ring, m, gamma, ptr(out),
+                                     _stream())
     _check(code, "vrs_composite_frame")
     return out
 
 
 def composite_frame_backward(periphery, fovea, crops, d_out, d_periphery=None, d_fovea=None,
-                             mode=BLEND_LINEAR, ring=64.0, m=0.75, gamma=0.2):
+                             mode=BLEND_LINEAR, ring=64.0, m=0.75, gamma=0.2, place=None):
     V, _, H, W = periphery.shape
     code = lib().vrs_composite_frame_backward(
         ptr(periphery, torch.float32), V, W, H, ptr(fovea, torch.float32), make_crops(crops),
-        len(crops), mode, ring, m, gamma, ptr(d_out, torch.float32), ptr(d_periphery),
+        len(crops), ptr(place, torch.int32), mode, ring, m, gamma, ptr(d_out, torch.float32), ptr(d_periphery),
         ptr(d_fovea), _stream())
     _check(code, "vrs_composite_frame_backward")
 
 
-def trace_set(stage: str, start=None, stop=None):
-    """Record torch.cuda.Event `start`/`stop` around a stage's kernels."""
-    code = TRACE[stage]
-    for e in (start, stop):
-        if e is not None and e.cuda_event == 0:
-            e.record()   # torch creates the HIP event on first record
-    a = ctypes.c_void_p(start.cuda_event) if start is not None else None
-    b = ctypes.c_void_p(stop.cuda_event) if stop is not None else None
-    _check(lib().vrs_trace_set(code, a, b), "vrs_trace_set")
+# ------------------------------------------------------------ frame plan
+class Plan:
+    """vrs_plan: views, crop views and sizes, the tuned tile size and sort
+    radix, capacities, decoder shape, depth cull and combination of one
+    scene and rig (host memory; destroyed with this object)."""
+
+    def __init__(self, views, crops, n_gaussians, sh_degree, n_points, levels, opts, widths,
+                 decoder_dtype, max_pairs, max_frags, cull=True, cov_min=0.5, slack=1.05,
+                 mode=BLEND_LINEAR, ring=64.0, m=0.75, gamma=0.2):
+        self.cviews, self.ccrops = make_views(views), make_crops(crops)
+        d = PlanDesc()
+        d.n_views, d.views = len(views), self.cviews
+        d.n_gaussians, d.sh_degree = int(n_gaussians), sh_degree
+        d.n_points, d.point_channels, d.levels = int(n_points), 4, levels
+        d.n_crops, d.crops = len(crops), self.ccrops
+        d.raster = opts
+        d.decoder = make_decoder_desc(widths, 4, decoder_dtype)
+        d.depth_cull, d.cov_min, d.slack = int(bool(cull)), cov_min, slack
+        d.blend_mode, d.ring, d.m, d.gamma = mode, ring, m, gamma
+        d.max_pairs, d.max_frags = int(max_pairs), int(max_frags)
+        self.desc = d
+        h = ctypes.c_void_p()
+        _check(lib().vrs_plan_create(ctypes.byref(d), ctypes.byref(h)), "vrs_plan_create")
+        self.handle = h
+
+    def workspace_size(self, which) -> int:
+        return int(lib().vrs_workspace_size(self.handle, which))
+
+    def trace(self, stage: str, start=None, stop=None):
+        """Record torch.cuda.Event start/stop around stage `stage` of every
+        frame of this plan ("off" clears)."""
+        code = TRACE[stage]
+        for e in (start, stop):
+            if e is not None and e.cuda_event == 0:
+                e.record()   # torch creates the HIP event on first record
+        a = ctypes.c_void_p(start.cuda_event) if start is not None else None
+        b = ctypes.c_void_p(stop.cuda_event) if stop is not None else None
+        _check(lib().vrs_plan_trace(self.handle, code, a, b), "vrs_plan_trace")
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vrs_plan_destroy(self.handle)
+            self.handle = None
+
+
+def render_frame(plan: Plan, scene: Scene, gaze, buffers: FrameBuffers, stats=False):
+    """vrs_render_frame on the current stream."""
+    _check(lib().vrs_render_frame(plan.handle, ctypes.byref(scene), ptr(gaze, torch.float32),
+                                  ctypes.byref(buffers), FRAME_STATS if stats else 0, _stream()),
+           "vrs_render_frame")
 
 
 def l1_loss(pred, target, d_pred=None, scale=1.0):

@@ -17,7 +17,23 @@ struct CompArgs {
   int view[VRS_MAX_CROPS], x0[VRS_MAX_CROPS], y0[VRS_MAX_CROPS], S[VRS_MAX_CROPS];
   float gx[VRS_MAX_CROPS], gy[VRS_MAX_CROPS];
   long long fbase[VRS_MAX_CROPS];
+  const int4* place;   // device crop placement (x0, y0, gaze), or null
 };
+
+// Origin and gaze of crop k: the host values, or the device placement
+// table's (origins clamped into the view).
+__device__ inline int cx0(const CompArgs& a, int k) {
+  return a.place ? clamp_origin(a.place[k].x, a.W - a.S[k]) : a.x0[k];
+}
+__device__ inline int cy0(const CompArgs& a, int k) {
+  return a.place ? clamp_origin(a.place[k].y, a.H - a.S[k]) : a.y0[k];
+}
+__device__ inline float cgx(const CompArgs& a, int k) {
+  return a.place ? __int_as_float(a.place[k].z) : a.gx[k];
+}
+__device__ inline float cgy(const CompArgs& a, int k) {
+  return a.place ? __int_as_float(a.place[k].w) : a.gy[k];
+}
 
 __device__ inline float clamp01(float x) { return x < 0.0f ? 0.0f : (x > 1.0f ? 1.0f : x); }
 
@@ -45,8 +61,8 @@ __device__ inline float smootherstep_d(float x) { return 30.0f * x * x * (x - 1.
 // (PAPER mode), fe_out = edge term.
 __device__ inline float blend_mask(const CompArgs& a, int k, const float* F, int lx, int ly,
                                    float& u_out, float& gx, float& gy) {
-  const float dx = (float)(a.x0[k] + lx) + 0.5f - a.gx[k];
-  const float dy = (float)(a.y0[k] + ly) + 0.5f - a.gy[k];
+  const float dx = (float)(cx0(a, k) + lx) + 0.5f - cgx(a, k);
+  const float dy = (float)(cy0(a, k) + ly) + 0.5f - cgy(a, k);
   const float r = sqrtf(dx * dx + dy * dy);
   const float df = 0.5f * (float)a.S[k];
   if (a.mode == VRS_BLEND_LINEAR) {
@@ -75,12 +91,12 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* P,
     float o0 = P[base], o1 = P[base + plane], o2 = P[base + 2 * plane];
     for (int k = 0; k < a.n_crops; ++k) {
       if (a.view[k] != v) continue;
-      const int lx = x - a.x0[k], ly = y - a.y0[k], S = a.S[k];
+      const int lx = x - cx0(a, k), ly = y - cy0(a, k), S = a.S[k];
       if (lx < 0 || ly < 0 || lx >= S || ly >= S) continue;
       {
         // outside the crop's inscribed circle the mask is 0 in both modes
-        const float dx = (float)(a.x0[k] + lx) + 0.5f - a.gx[k];
-        const float dy = (float)(a.y0[k] + ly) + 0.5f - a.gy[k];
+        const float dx = (float)(cx0(a, k) + lx) + 0.5f - cgx(a, k);
+        const float dy = (float)(cy0(a, k) + ly) + 0.5f - cgy(a, k);
         if (!(sqrtf(dx * dx + dy * dy) < 0.5f * (float)S)) continue;
       }
       const float* Fk = F + a.fbase[k];
@@ -116,19 +132,19 @@ __device__ inline void comp_quad(const CompArgs& a, const float* P, const float*
   }
   for (int k = 0; k < a.n_crops; ++k) {
     if (a.view[k] != v) continue;
-    const int S = a.S[k], ly = y - a.y0[k];
-    if (ly < 0 || ly >= S || x + 3 < a.x0[k] || x >= a.x0[k] + S) continue;
+    const int S = a.S[k], ly = y - cy0(a, k);
+    if (ly < 0 || ly >= S || x + 3 < cx0(a, k) || x >= cx0(a, k) + S) continue;
     const float* Fk = F + a.fbase[k];
     const long long fp = (long long)S * S;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int lx = x + j - a.x0[k];
+      const int lx = x + j - cx0(a, k);
       if (lx < 0 || lx >= S) continue;
       {
         // outside the crop's inscribed circle the mask is 0 in both modes
         // (the same operations as blend_mask): the pixel keeps its value
-        const float dx = (float)(a.x0[k] + lx) + 0.5f - a.gx[k];
-        const float dy = (float)(a.y0[k] + ly) + 0.5f - a.gy[k];
+        const float dx = (float)(cx0(a, k) + lx) + 0.5f - cgx(a, k);
+        const float dy = (float)(cy0(a, k) + ly) + 0.5f - cgy(a, k);
         if (!(sqrtf(dx * dx + dy * dy) < 0.5f * (float)S)) continue;
       }
       float u, gx, gy;
@@ -167,14 +183,14 @@ __global__ __launch_bounds__(256) void k_composite4_inplace(CompArgs a, float* i
                                                             const float* __restrict__ F) {
   const int kc = blockIdx.y;
   const int S = a.S[kc], v = a.view[kc];
-  const int gx0 = a.x0[kc] >> 2, ng = ((a.x0[kc] + S - 1) >> 2) - gx0 + 1;
+  const int gx0 = cx0(a, kc) >> 2, ng = ((cx0(a, kc) + S - 1) >> 2) - gx0 + 1;
   const long long i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= (long long)S * ng) return;
   const int ly = (int)(i / ng);
-  const int y = a.y0[kc] + ly, x = (gx0 + (int)(i - (long long)ly * ng)) * 4;
+  const int y = cy0(a, kc) + ly, x = (gx0 + (int)(i - (long long)ly * ng)) * 4;
   for (int k = 0; k < kc; ++k)
-    if (a.view[k] == v && y >= a.y0[k] && y < a.y0[k] + a.S[k] && x + 3 >= a.x0[k] &&
-        x < a.x0[k] + a.S[k])
+    if (a.view[k] == v && y >= cy0(a, k) && y < cy0(a, k) + a.S[k] && x + 3 >= cx0(a, k) &&
+        x < cx0(a, k) + a.S[k])
       return;   // an earlier crop's group
   comp_quad(a, io, F, io, v, y, x);
 }
@@ -201,7 +217,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompArgs a, const float* 
     int nk = 0;
     for (int k = 0; k < a.n_crops; ++k) {
       if (a.view[k] != v) continue;
-      const int lx = x - a.x0[k], ly = y - a.y0[k];
+      const int lx = x - cx0(a, k), ly = y - cy0(a, k);
       if (lx < 0 || ly < 0 || lx >= a.S[k] || ly >= a.S[k]) continue;
       ks[nk++] = k;
     }
@@ -213,7 +229,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompArgs a, const float* 
       o[0][0] = P[base]; o[0][1] = P[base + plane]; o[0][2] = P[base + 2 * plane];
       for (int j = 0; j < nk; ++j) {
         const int k = ks[j], S = a.S[k];
-        const int lx = x - a.x0[k], ly = y - a.y0[k];
+        const int lx = x - cx0(a, k), ly = y - cy0(a, k);
         const float* Fk = F + a.fbase[k];
         cs[j] = blend_mask(a, k, Fk, lx, ly, us[j], gxs[j], gys[j]);
         const long long fp = (long long)S * S, fo = (long long)ly * S + lx;
@@ -222,7 +238,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompArgs a, const float* 
       }
       for (int j = nk - 1; j >= 0; --j) {
         const int k = ks[j], S = a.S[k];
-        const int lx = x - a.x0[k], ly = y - a.y0[k];
+        const int lx = x - cx0(a, k), ly = y - cy0(a, k);
         const float* Fk = F + a.fbase[k];
         const long long fp = (long long)S * S, fo = (long long)ly * S + lx;
         const float c = cs[j];
@@ -304,7 +320,8 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ pred,
 __global__ void k_zero1(float* p) { *p = 0.0f; }
 
 static bool comp_args(int nv, int W, int H, const vrs_crop* crops, int n_crops, int mode,
-                      float ring, float m, float gamma, CompArgs* a) {
+                      float ring, float m, float gamma, const vrs_crop_place* place,
+                      CompArgs* a) {
   if (nv < 1 || nv > VRS_MAX_VIEWS || W < 1 || H < 1 || n_crops < 0 || n_crops > VRS_MAX_CROPS ||
       (n_crops > 0 && !crops))
     return false;
@@ -319,12 +336,12 @@ static bool comp_args(int nv, int W, int H, const vrs_crop* crops, int n_crops, 
   a->ring = ring;
   a->m = m;
   a->gamma = gamma;
+  a->place = reinterpret_cast<const int4*>(place);
   long long fb = 0;
   for (int k = 0; k < n_crops; ++k) {
     const vrs_crop& c = crops[k];
-    if (c.view < 0 || c.view >= nv || c.size < 1 || c.x0 < 0 || c.y0 < 0 || c.x0 + c.size > W ||
-        c.y0 + c.size > H)
-      return false;
+    if (c.view < 0 || c.view >= nv || c.size < 1 || c.size > W || c.size > H) return false;
+    if (!place && (c.x0 < 0 || c.y0 < 0 || c.x0 + c.size > W || c.y0 + c.size > H)) return false;
     a->view[k] = c.view;
     a->x0[k] = c.x0;
     a->y0[k] = c.y0;
@@ -341,23 +358,29 @@ static bool comp_args(int nv, int W, int H, const vrs_crop* crops, int n_crops, 
 
 using namespace vrs;
 
-extern "C" vrs_status vrs_composite_frame(const float* rgb_periphery, int n_views, int width,
-                                          int height, const float* fovea_rgb,
-                                          const vrs_crop* crops, int n_crops, int mode, float ring,
-                                          float m, float gamma, float* out, void* stream) {
+namespace vrs {
+vrs_status composite_impl(const float* rgb_periphery, int n_views, int width, int height,
+                          const float* fovea_rgb, const vrs_crop* crops, int n_crops,
+                          const vrs_crop_place* place, int mode, float ring, float m, float gamma,
+                          float* out, void* stream, const Trace* tr) {
   CompArgs a;
-  if (!comp_args(n_views, width, height, crops, n_crops, mode, ring, m, gamma, &a))
+  if (!comp_args(n_views, width, height, crops, n_crops, mode, ring, m, gamma, place, &a))
     return VRS_EINVAL;
   if (!rgb_periphery || !out || (n_crops > 0 && !fovea_rgb)) return VRS_EINVAL;
   const long long total = (long long)width * height * n_views;
-  trace_begin(VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
+  trace_begin(tr, VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
   const bool vec4 = width % 4 == 0 && (reinterpret_cast<uintptr_t>(rgb_periphery) & 15) == 0 &&
                     (reinterpret_cast<uintptr_t>(out) & 15) == 0;
   if (vec4 && out == rgb_periphery) {
-    long long most = 0;   // four-pixel groups of the largest crop
-    for (int k = 0; k < n_crops; ++k)
-      most = std::max<long long>(most, (long long)crops[k].size *
-                                           (((crops[k].x0 + crops[k].size - 1) >> 2) - (crops[k].x0 >> 2) + 1));
+    // four-pixel groups of the largest crop (for origins read on the
+    // device, as many as any origin can give: ((S + 2) >> 2) + 1 per row)
+    long long most = 0;
+    for (int k = 0; k < n_crops; ++k) {
+      const int S = crops[k].size;
+      const long long row = place ? ((S + 2) >> 2) + 1
+                                  : ((crops[k].x0 + S - 1) >> 2) - (crops[k].x0 >> 2) + 1;
+      most = std::max<long long>(most, (long long)S * row);
+    }
     if (n_crops > 0)
       hipLaunchKernelGGL(k_composite4_inplace, dim3((unsigned)((most + 255) / 256), n_crops),
                          dim3(256), 0, static_cast<hipStream_t>(stream), a, out, fovea_rgb);
@@ -371,18 +394,29 @@ extern "C" vrs_status vrs_composite_frame(const float* rgb_periphery, int n_view
                        a, rgb_periphery, fovea_rgb, out);
   }
   VRS_LAUNCH_CHECK();
-  trace_end(VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
+  trace_end(tr, VRS_TRACE_COMPOSITE, static_cast<hipStream_t>(stream));
   return VRS_OK;
+}
+}  // namespace vrs
+
+extern "C" vrs_status vrs_composite_frame(const float* rgb_periphery, int n_views, int width,
+                                          int height, const float* fovea_rgb,
+                                          const vrs_crop* crops, int n_crops,
+                                          const vrs_crop_place* place, int mode, float ring,
+                                          float m, float gamma, float* out, void* stream) {
+  return composite_impl(rgb_periphery, n_views, width, height, fovea_rgb, crops, n_crops, place,
+                        mode, ring, m, gamma, out, stream, nullptr);
 }
 
 extern "C" vrs_status vrs_composite_frame_backward(const float* rgb_periphery, int n_views,
                                                    int width, int height, const float* fovea_rgb,
-                                                   const vrs_crop* crops, int n_crops, int mode,
+                                                   const vrs_crop* crops, int n_crops,
+                                                   const vrs_crop_place* place, int mode,
                                                    float ring, float m, float gamma,
                                                    const float* d_out, float* d_rgb_periphery,
                                                    float* d_fovea, void* stream) {
   CompArgs a;
-  if (!comp_args(n_views, width, height, crops, n_crops, mode, ring, m, gamma, &a))
+  if (!comp_args(n_views, width, height, crops, n_crops, mode, ring, m, gamma, place, &a))
     return VRS_EINVAL;
   if (!rgb_periphery || !d_out || (n_crops > 0 && !fovea_rgb)) return VRS_EINVAL;
   const long long total = (long long)width * height * n_views;

@@ -35,6 +35,8 @@ struct DecLevel {
   int tiles_x[VRS_MAX_CROPS];
   int S[VRS_MAX_CROPS];
   int view[VRS_MAX_CROPS], x0[VRS_MAX_CROPS], y0[VRS_MAX_CROPS];
+  int mx0[VRS_MAX_CROPS], my0[VRS_MAX_CROPS];   // largest origin inside the view
+  const int4* place;                 // device crop placement (x0, y0, gaze), or null
   long long pyr_off[VRS_MAX_CROPS];  // float offset of this layer in the pyramid
   long long h_off[VRS_MAX_CROPS];    // element offset of h_l
   long long hn_off[VRS_MAX_CROPS];   // element offset of h_{l+1}
@@ -53,6 +55,15 @@ struct DecTraits<__bf16> {
   static constexpr int KSTEP = 32;
   static constexpr int TH = 16;
 };
+
+// Origin of crop k in its view: the host value, or the device placement
+// table's clamped into the view.
+__device__ inline int dec_x0(const DecLevel& d, int k) {
+  return d.place ? clamp_origin(d.place[k].x, d.mx0[k]) : d.x0[k];
+}
+__device__ inline int dec_y0(const DecLevel& d, int k) {
+  return d.place ? clamp_origin(d.place[k].y, d.my0[k]) : d.y0[k];
+}
 
 __device__ inline float to_f(float x) { return x; }
 __device__ inline float to_f(__bf16 x) { return (float)x; }
@@ -95,7 +106,7 @@ __device__ inline float dec_input(const DecLevel& d, int k, int S, int y, int x,
   if (d.has_p && c < 3) {
     const long long plane = (long long)d.W * d.H;
     return periph[(long long)d.view[k] * 3 * plane + c * plane +
-                  (long long)(d.y0[k] + y) * d.W + (d.x0[k] + x)];
+                  (long long)(dec_y0(d, k) + y) * d.W + (dec_x0(d, k) + x)];
   }
   return 0.0f;
 }
@@ -369,7 +380,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
           v[0] = pv.x; v[1] = pv.y; v[2] = pv.z; v[3] = pv.w;
           if (d.has_p) {
             const float* pp = periph + (long long)d.view[k] * 3 * plane +
-                              (long long)(d.y0[k] + y) * d.W + (d.x0[k] + x);
+                              (long long)(dec_y0(d, k) + y) * d.W + (dec_x0(d, k) + x);
             v[4] = pp[0];
             v[5] = pp[plane];
             v[6] = pp[2 * plane];
@@ -659,7 +670,9 @@ static bool dec_plan(const vrs_decoder_desc* dd, const vrs_crop* crops, int n_cr
 }
 
 static void level_args(const DecPlan& P, int l, const vrs_crop* crops, int n_crops,
-                       const KViews& kv, int levels, DecLevel* d, int* blocks) {
+                       const KViews& kv, int levels, const vrs_crop_place* place, DecLevel* d,
+                       int* blocks) {
+  d->place = reinterpret_cast<const int4*>(place);
   const int NT = 2 * P.kp[l] / 16;
   const int TH = P.dtype == VRS_BF16 && NT < 8 ? 16 : 8;   // as ConvCfg
   d->C = P.C;
@@ -687,6 +700,8 @@ static void level_args(const DecPlan& P, int l, const vrs_crop* crops, int n_cro
     d->view[k] = crops[k].view;
     d->x0[k] = crops[k].x0;
     d->y0[k] = crops[k].y0;
+    d->mx0[k] = kv.v[crops[k].view].W - crops[k].size;
+    d->my0[k] = kv.v[crops[k].view].H - crops[k].size;
     long long lay = pyr;
     for (int q = 0; q < l; ++q) lay += (long long)(crops[k].size >> q) * (crops[k].size >> q);
     d->pyr_off[k] = lay * P.C;
@@ -755,8 +770,8 @@ static hipError_t launch_conv(const DecLevel& d, int NT, int blocks, const float
 template <typename T>
 static vrs_status decode_impl(const DecPlan& P, const float* pyramid, int levels,
                               const float* periph, const KViews& kv, const vrs_crop* crops,
-                              int n_crops, const float* weights, float* out, void* ws,
-                              bool keep_pre, hipStream_t st) {
+                              int n_crops, const vrs_crop_place* place, const float* weights,
+                              float* out, void* ws, bool keep_pre, hipStream_t st) {
   {
     PackArgs<T> pa;
     pa.n = P.nd;
@@ -784,7 +799,7 @@ static vrs_status decode_impl(const DecPlan& P, const float* pyramid, int levels
   DecLevel d;
   for (int l = P.nd - 1; l >= 0; --l) {
     int blocks = 0;
-    level_args(P, l, crops, n_crops, kv, levels, &d, &blocks);
+    level_args(P, l, crops, n_crops, kv, levels, place, &d, &blocks);
     const T* hn = l + 1 < P.nd ? at<T>(ws, P.h[l + 1]) : nullptr;
     HeadFuse hf{};
     if (l == 0) {
@@ -823,12 +838,30 @@ extern "C" size_t vrs_decoder_workspace_size(const vrs_decoder_desc* dd, const v
   return P.total;
 }
 
-extern "C" vrs_status vrs_decode_fovea(const float* pyramid, int levels,
-                                       const float* rgb_periphery, const vrs_view* views,
-                                       int n_views, const vrs_crop* crops, int n_crops,
-                                       const float* weights, const vrs_decoder_desc* dd,
-                                       float* fovea_rgb, void* ws, size_t ws_bytes,
-                                       void* stream) {
+// crops inside their (equally sized) views, sizes multiples of the coarsest
+// layer; the origins only when no device placement table overrides them
+static bool dec_crops_ok(const vrs_view* views, int n_views, const vrs_crop* crops, int n_crops,
+                         int levels, const vrs_crop_place* place) {
+  for (int i = 1; i < n_views; ++i)
+    if (views[i].width != views[0].width || views[i].height != views[0].height) return false;
+  for (int k = 0; k < n_crops; ++k) {
+    const vrs_crop& c = crops[k];
+    if (c.view < 0 || c.view >= n_views || c.size < 1 || c.size > views[c.view].width ||
+        c.size > views[c.view].height || c.size % (1 << (levels - 1)))
+      return false;
+    if (!place && (c.x0 < 0 || c.y0 < 0 || c.x0 + c.size > views[c.view].width ||
+                   c.y0 + c.size > views[c.view].height))
+      return false;
+  }
+  return true;
+}
+
+namespace vrs {
+vrs_status decode_impl_entry(const float* pyramid, int levels, const float* rgb_periphery,
+                             const vrs_view* views, int n_views, const vrs_crop* crops,
+                             int n_crops, const vrs_crop_place* place, const float* weights,
+                             const vrs_decoder_desc* dd, float* fovea_rgb, void* ws,
+                             size_t ws_bytes, void* stream, const Trace* tr) {
   DecPlan P;
   KViews kv;
   if (!make_views(views, n_views, &kv) || !dec_plan(dd, crops, n_crops, &P)) return VRS_EINVAL;
@@ -836,26 +869,29 @@ extern "C" vrs_status vrs_decode_fovea(const float* pyramid, int levels,
   if (!pyramid || !rgb_periphery || !weights || !fovea_rgb || !ws || ws_bytes < P.total)
     return VRS_EINVAL;
   if (dd->in_ch != 4) return VRS_EUNSUPPORTED;
-  for (int k = 0; k < n_crops; ++k) {
-    const vrs_crop& c = crops[k];
-    if (c.view < 0 || c.view >= n_views || c.x0 < 0 || c.y0 < 0 ||
-        c.x0 + c.size > views[c.view].width || c.y0 + c.size > views[c.view].height ||
-        c.size % (1 << (levels - 1)))
-      return VRS_EINVAL;
-  }
-  for (int i = 1; i < n_views; ++i)
-    if (views[i].width != views[0].width || views[i].height != views[0].height) return VRS_EINVAL;
+  if (!dec_crops_ok(views, n_views, crops, n_crops, levels, place)) return VRS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  trace_begin(VRS_TRACE_DECODER, st);
+  trace_begin(tr, VRS_TRACE_DECODER, st);
   vrs_status r;
   if (P.dtype == VRS_BF16)
-    r = decode_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
-                            fovea_rgb, ws, false, st);
+    r = decode_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, place,
+                            weights, fovea_rgb, ws, false, st);
   else
-    r = decode_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
-                           fovea_rgb, ws, false, st);
-  trace_end(VRS_TRACE_DECODER, st);
+    r = decode_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, place,
+                           weights, fovea_rgb, ws, false, st);
+  trace_end(tr, VRS_TRACE_DECODER, st);
   return r;
+}
+}  // namespace vrs
+
+extern "C" vrs_status vrs_decode_fovea(const float* pyramid, int levels,
+                                       const float* rgb_periphery, const vrs_view* views,
+                                       int n_views, const vrs_crop* crops, int n_crops,
+                                       const vrs_crop_place* place, const float* weights,
+                                       const vrs_decoder_desc* dd, float* fovea_rgb, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  return decode_impl_entry(pyramid, levels, rgb_periphery, views, n_views, crops, n_crops, place,
+                           weights, dd, fovea_rgb, ws, ws_bytes, stream, nullptr);
 }
 
 // ------------------------------------------------------------- backward
@@ -983,7 +1019,7 @@ __global__ __launch_bounds__(256) void k_dec_dgrad(DecLevel d, const float* __re
       const int cc = c - d.C - d.kn;
       const long long plane = (long long)d.W * d.H;
       atomicAdd(&dper[(long long)d.view[k] * 3 * plane + cc * plane +
-                      (long long)(d.y0[k] + y) * d.W + (d.x0[k] + x)],
+                      (long long)(dec_y0(d, k) + y) * d.W + (dec_x0(d, k) + x)],
                 acc);
     }
   }
@@ -1045,14 +1081,15 @@ __global__ __launch_bounds__(256) void k_dec_wgrad(DecLevel d, const float* __re
 template <typename T>
 static vrs_status decode_bwd_impl(const DecPlan& P, const float* pyramid, int levels,
                                   const float* periph, const KViews& kv, const vrs_crop* crops,
-                                  int n_crops, const float* weights, const float* d_fovea,
+                                  int n_crops, const vrs_crop_place* place,
+                                  const float* weights, const float* d_fovea,
                                   float* d_pyr, float* d_per, float* d_w, void* ws,
                                   hipStream_t st) {
   // recompute every level's pre-activations (the forward's h_l stay valid)
   for (int l = P.nd - 1; l >= 0; --l) {
     DecLevel d;
     int blocks = 0;
-    level_args(P, l, crops, n_crops, kv, levels, &d, &blocks);
+    level_args(P, l, crops, n_crops, kv, levels, place, &d, &blocks);
     const T* hn = l + 1 < P.nd ? at<T>(ws, P.h[l + 1]) : nullptr;
     VRS_HIP_CHECK(launch_conv<T>(d, 2 * P.kp[l] / 16, blocks, pyramid, periph, hn,
                                  at<T>(ws, P.wp[l]), at<float>(ws, P.bp[l]), at<T>(ws, P.h[l]),
@@ -1068,7 +1105,7 @@ static vrs_status decode_bwd_impl(const DecPlan& P, const float* pyramid, int le
     long long p = 0, o = 0;
     DecLevel d0;
     int b0 = 0;
-    level_args(P, 0, crops, n_crops, kv, levels, &d0, &b0);
+    level_args(P, 0, crops, n_crops, kv, levels, place, &d0, &b0);
     for (int k = 0; k < n_crops; ++k) {
       ha.S[k] = crops[k].size;
       ha.pix_base[k] = p;
@@ -1086,7 +1123,7 @@ static vrs_status decode_bwd_impl(const DecPlan& P, const float* pyramid, int le
   for (int l = 0; l < P.nd; ++l) {
     DecLevel d;
     int blocks = 0;
-    level_args(P, l, crops, n_crops, kv, levels, &d, &blocks);
+    level_args(P, l, crops, n_crops, kv, levels, place, &d, &blocks);
     long long npix = 0;
     for (int k = 0; k < n_crops; ++k) npix += (long long)d.S[k] * d.S[k];
     const int gb = (int)std::min<long long>(16384, (npix * P.kp[l] + 255) / 256);
@@ -1123,6 +1160,7 @@ static vrs_status decode_bwd_impl(const DecPlan& P, const float* pyramid, int le
 extern "C" vrs_status vrs_decode_fovea_backward(const float* pyramid, int levels,
                                                 const float* rgb_periphery, const vrs_view* views,
                                                 int n_views, const vrs_crop* crops, int n_crops,
+                                                const vrs_crop_place* place,
                                                 const float* weights, const vrs_decoder_desc* dd,
                                                 const float* d_fovea, float* d_pyramid,
                                                 float* d_rgb_periphery, float* d_weights,
@@ -1134,10 +1172,12 @@ extern "C" vrs_status vrs_decode_fovea_backward(const float* pyramid, int levels
       !d_fovea || !ws || ws_bytes < P.total)
     return VRS_EINVAL;
   if (dd->in_ch != 4) return VRS_EUNSUPPORTED;
+  if (!dec_crops_ok(views, n_views, crops, n_crops, levels, place)) return VRS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (P.dtype == VRS_BF16)
-    return decode_bwd_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
-                                   d_fovea, d_pyramid, d_rgb_periphery, d_weights, ws, st);
-  return decode_bwd_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, weights,
-                                d_fovea, d_pyramid, d_rgb_periphery, d_weights, ws, st);
+    return decode_bwd_impl<__bf16>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, place,
+                                   weights, d_fovea, d_pyramid, d_rgb_periphery, d_weights, ws,
+                                   st);
+  return decode_bwd_impl<float>(P, pyramid, levels, rgb_periphery, kv, crops, n_crops, place,
+                                weights, d_fovea, d_pyramid, d_rgb_periphery, d_weights, ws, st);
 }

@@ -367,7 +367,8 @@ extern "C" vrs_status vrs_render_gaussians_backward(
   for (int i = 1; i < n_views; ++i)
     if (views[i].width != views[0].width || views[i].height != views[0].height) return VRS_EINVAL;
   if (sh_degree < 0 || sh_degree > 3 || n < 0) return VRS_EINVAL;
-  if (!render_layout(n, n_views, views, o.tile, max_pairs, &L) || !ws || ws_bytes < L.total)
+  if (!render_layout(n, n_views, views, o.tile, opts_radix(ro), max_pairs, &L) || !ws ||
+      ws_bytes < L.total)
     return VRS_EINVAL;
   if (!t_final || !d_rgb || (n > 0 && (!mean || !cov || !opacity || !sh || !d_mean || !d_cov ||
                                        !d_opacity || !d_sh)))

@@ -40,22 +40,6 @@
 
 namespace vrs {
 
-bool gs_render_layout(int64_t n, int nv, const vrs_view* views, int tile, int64_t max_pairs,
-                      size_t* rec, size_t* ranges, size_t* sorted_ids, size_t* last,
-                      size_t* pair_count, int64_t* tiles_x, int64_t* tiles_y, size_t* total) {
-  RenderWs L;
-  if (!render_layout(n, nv, views, tile, max_pairs, &L)) return false;
-  *rec = L.rec;
-  *ranges = L.ranges;
-  *sorted_ids = L.ids;
-  *last = L.last;
-  *pair_count = L.pair_count;
-  *tiles_x = L.tiles_x;
-  *tiles_y = L.tiles_y;
-  *total = L.total;
-  return true;
-}
-
 // ------------------------------------------------------------ preprocess
 __global__ __launch_bounds__(256) void k_gs_preprocess(
     const float* __restrict__ mean, const float* __restrict__ cov,
@@ -690,7 +674,11 @@ struct BlendCfg {
 // Register budget for five waves per SIMD (96 VGPRs; no spills): the
 // staging and the per-pixel state compete for registers, and occupancy hides
 // the LDS and gather latency better than the extra registers would help.
-template <int TILE, int SUB>
+// STATS: also write each pixel's last contributing list position (the
+// adjoint's replay start) and its evaluation count (the work count); an
+// inference frame leaves both out, and with them the counting of records
+// out of reach of the ellipse.
+template <int TILE, int SUB, bool STATS>
 __global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
@@ -816,19 +804,21 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
         const uint64_t mf = m & mfull;
         const uint64_t cheap = mf ? (m & ((mf & (~mf + 1ull)) - 1ull)) : m;
         m &= ~cheap;
-        ncov += (uint32_t)__popcll(cheap & mcov);
-        uint64_t cpart = cheap & ~mcov;
-        while (cpart) {
-          const int kc = g * 64 + __builtin_ctzll(cpart);
-          cpart &= cpart - 1;
-          const float4 bc = s_b[kc];
-          const uint32_t clo = __float_as_uint(bc.z), chi = __float_as_uint(bc.w);
-          const int cx0 = (int)(clo & 0xffffu), cy0 = (int)(clo >> 16);
-          const bool cin = (uint32_t)(px - cx0) <= (uint32_t)((int)(chi & 0xffffu) - cx0);
-          const uint32_t cspan = (uint32_t)((int)(chi >> 16) - cy0);
+        if constexpr (STATS) {
+          ncov += (uint32_t)__popcll(cheap & mcov);
+          uint64_t cpart = cheap & ~mcov;
+          while (cpart) {
+            const int kc = g * 64 + __builtin_ctzll(cpart);
+            cpart &= cpart - 1;
+            const float4 bc = s_b[kc];
+            const uint32_t clo = __float_as_uint(bc.z), chi = __float_as_uint(bc.w);
+            const int cx0 = (int)(clo & 0xffffu), cy0 = (int)(clo >> 16);
+            const bool cin = (uint32_t)(px - cx0) <= (uint32_t)((int)(chi & 0xffffu) - cx0);
+            const uint32_t cspan = (uint32_t)((int)(chi >> 16) - cy0);
 #pragma unroll
-          for (int q = 0; q < PPT; ++q)
-            evals[q] += (cin & ((uint32_t)(ry[q] - cy0) <= cspan)) ? 1u : 0u;
+            for (int q = 0; q < PPT; ++q)
+              evals[q] += (cin & ((uint32_t)(ry[q] - cy0) <= cspan)) ? 1u : 0u;
+          }
         }
         if (!m) break;
         const int bit = __builtin_ctzll(m);
@@ -845,8 +835,8 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
         // rectangle holds the sub-tile, liveness alone).
         auto blend_record = [&](auto in_rect, auto cover_tag) {
           constexpr bool kCover = decltype(cover_tag)::value;
-          if (kCover) ++ncov;
-          const int stopped = kStopped + (int)ncov;
+          if (STATS && kCover) ++ncov;
+          const int stopped = kStopped + (STATS ? (int)ncov : 0);
           all_ry = kStopped;
 #pragma unroll
           for (int q = 0; q < PPT; ++q) {
@@ -871,8 +861,10 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
             D[q] = fmaf(c.w, wgt, D[q]);
             T[q] -= wgt;
             cnt[q] += ok ? 1 : 0;
-            last[q] = ok ? pos : last[q];
-            if (!kCover) evals[q] += inr ? 1u : 0u;
+            if constexpr (STATS) {
+              last[q] = ok ? pos : last[q];
+              if (!kCover) evals[q] += inr ? 1u : 0u;
+            }
             all_ry &= ry[q];
           }
         };
@@ -895,7 +887,8 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   }
   // sub-tile-holding records: up to its stop, or all of them
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) evals[q] += ry[q] >= kStopped ? (uint32_t)(ry[q] - kStopped) : ncov;
+  for (int q = 0; q < PPT; ++q)
+    if constexpr (STATS) evals[q] += ry[q] >= kStopped ? (uint32_t)(ry[q] - kStopped) : ncov;
   const int64_t plane = (int64_t)W * H;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
@@ -909,8 +902,10 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
     out_depth[pix] = D[q];
     out_t[pix] = T[q];
     out_n[pix] = cnt[q];
-    out_last[pix] = last[q];
-    out_evals[pix] = evals[q];
+    if constexpr (STATS) {
+      out_last[pix] = last[q];
+      out_evals[pix] = evals[q];
+    }
   }
 }
 
@@ -927,8 +922,8 @@ static bool read_opts(const vrs_raster_opts* ro, GsOpt* o) {
   o->lowpass = ro->lowpass;
   o->extent = ro->extent;
   for (int k = 0; k < 3; ++k) o->bg[k] = ro->bg[k];
-  return (o->tile == 8 || o->tile == 16 || o->tile == 32) && o->extent > 0 && o->lowpass >= 0 &&
-         o->amin >= 0;
+  return (o->tile == 8 || o->tile == 16 || o->tile == 32) && radix_bits_ok(opts_radix(ro)) &&
+         o->extent > 0 && o->lowpass >= 0 && o->amin >= 0;
 }
 
 static bool same_dims(const vrs_view* views, int nv) {
@@ -940,7 +935,8 @@ static bool same_dims(const vrs_view* views, int nv) {
 extern "C" size_t vrs_render_workspace_size(int64_t n, int n_views, const vrs_view* views,
                                             const vrs_raster_opts* opts, int64_t max_pairs) {
   RenderWs L;
-  if (!opts || !render_layout(n, n_views, views, opts->tile, max_pairs, &L)) return 0;
+  if (!opts || !render_layout(n, n_views, views, opts->tile, opts_radix(opts), max_pairs, &L))
+    return 0;
   return L.total;
 }
 
@@ -948,7 +944,8 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
                                                   const vrs_raster_opts* opts,
                                                   int64_t max_pairs, vrs_render_layout* out) {
   RenderWs L;
-  if (!opts || !out || !render_layout(n, n_views, views, opts->tile, max_pairs, &L))
+  if (!opts || !out ||
+      !render_layout(n, n_views, views, opts->tile, opts_radix(opts), max_pairs, &L))
     return VRS_EINVAL;
   out->pair_count = L.pair_count;
   out->sorted_ids = L.ids;
@@ -963,25 +960,35 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
 
 // Sub-tile edge per tile size: 16x16 sub-tiles (4 pixels per lane) for
 // 32-pixel tiles, 8x8 (one pixel per lane) below.
-template <int TILE>
+template <int TILE, bool STATS>
 static void launch_blend(const RenderWs& L, void* ws, int64_t n, const uint32_t* order,
                          const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
                          int32_t* nc, hipStream_t st) {
   constexpr int SUB = TILE == 32 ? 16 : 8;
   const uint32_t* ids = at<uint32_t>(ws, L.ids);
-  hipLaunchKernelGGL((k_gs_blend<TILE, SUB>), dim3((unsigned)L.tiles_total),
+  hipLaunchKernelGGL((k_gs_blend<TILE, SUB, STATS>), dim3((unsigned)L.tiles_total),
                      dim3(BlendCfg<TILE, SUB>::BLOCK), 0, st, order, ids, at<float4>(ws, L.rec), n,
                      kv, o, L.tiles_x, L.tiles_x * L.tiles_y, at<uint2>(ws, L.ranges), rgb, depth,
                      tf, nc, at<uint32_t>(ws, L.last), at<uint32_t>(ws, L.evals));
 }
 
-extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
-                                           const float* opacity, const float* sh, int sh_degree,
-                                           int64_t n, const vrs_view* views, int n_views,
-                                           const vrs_raster_opts* opts, float* rgb, float* depth,
-                                           float* t_final, int32_t* n_contrib, void* ws,
-                                           size_t ws_bytes, int64_t max_pairs,
-                                           int32_t* dev_status, void* stream) {
+template <int TILE>
+static void launch_blend(bool stats, const RenderWs& L, void* ws, int64_t n,
+                         const uint32_t* order, const KViews& kv, const GsOpt& o, float* rgb,
+                         float* depth, float* tf, int32_t* nc, hipStream_t st) {
+  if (stats) launch_blend<TILE, true>(L, ws, n, order, kv, o, rgb, depth, tf, nc, st);
+  else launch_blend<TILE, false>(L, ws, n, order, kv, o, rgb, depth, tf, nc, st);
+}
+
+namespace vrs {
+// flags: kRenderStats keeps the per-pixel last positions (for the adjoint)
+// and evaluation counts in the workspace.
+vrs_status render_impl(const float* mean, const float* cov, const float* opacity,
+                       const float* sh, int sh_degree, int64_t n, const vrs_view* views,
+                       int n_views, const vrs_raster_opts* opts, float* rgb, float* depth,
+                       float* t_final, int32_t* n_contrib, void* ws, size_t ws_bytes,
+                       int64_t max_pairs, int32_t* dev_status, void* stream, int flags,
+                       const Trace* tr) {
   GsOpt o;
   KViews kv;
   RenderWs L;
@@ -992,7 +999,8 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   if (sh_degree < 0 || sh_degree > 3) return VRS_EINVAL;
   if (!rgb || !depth || !t_final || !n_contrib || !ws) return VRS_EINVAL;
   if (max_pairs < 0 || max_pairs >= (int64_t(1) << 30)) return VRS_EINVAL;
-  if (!render_layout(n, n_views, views, o.tile, max_pairs, &L) || ws_bytes < L.total)
+  if (!render_layout(n, n_views, views, o.tile, opts_radix(opts), max_pairs, &L) ||
+      ws_bytes < L.total)
     return VRS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t vn = L.vn;
@@ -1001,7 +1009,7 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   const int64_t nps = div_up(n, 256);
   bool s1 = false;
   if (vn > 0) {
-    trace_begin(VRS_TRACE_GS_PREPROCESS, st);
+    trace_begin(tr, VRS_TRACE_GS_PREPROCESS, st);
     hipLaunchKernelGGL(k_gs_preprocess, dim3((unsigned)nps), dim3(256), 0, st, mean, cov,
                        opacity, sh, sh_degree, n, kv, o, at<float4>(ws, L.rec),
                        at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
@@ -1009,34 +1017,34 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                        at<uint32_t>(ws, L.scan_tmp),
                        (int64_t)((L.sched - L.scan_tmp) / 4 + kSchedDone + 1));
     VRS_LAUNCH_CHECK();
-    trace_end(VRS_TRACE_GS_PREPROCESS, st);
-    trace_begin(VRS_TRACE_GS_DEPTH_SORT, st);
+    trace_end(tr, VRS_TRACE_GS_PREPROCESS, st);
+    trace_begin(tr, VRS_TRACE_GS_DEPTH_SORT, st);
     bool d1 = false;
     // the last pass also lays the super-tile counts out in depth order
     VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
                                  at<uint32_t>(ws, L.dkey1), at<uint32_t>(ws, L.dval1), nullptr, vn,
-                                 32, at<void>(ws, L.sort_tmp), dev_status, st, &d1,
+                                 32, L.radix, at<void>(ws, L.sort_tmp), dev_status, st, &d1,
                                  at<uint32_t>(ws, L.nsup), at<uint32_t>(ws, L.nsorted)));
     const uint32_t* sorted_e = at<uint32_t>(ws, d1 ? L.dval1 : L.dval0);
     VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.nsorted), nullptr,
                                      at<uint32_t>(ws, L.soffs), super_count, nullptr, vn,
                                      at<void>(ws, L.scan_tmp), dev_status, st, true));
-    trace_end(VRS_TRACE_GS_DEPTH_SORT, st);
-    trace_begin(VRS_TRACE_GS_EMIT, st);
+    trace_end(tr, VRS_TRACE_GS_DEPTH_SORT, st);
+    trace_begin(tr, VRS_TRACE_GS_EMIT, st);
     hipLaunchKernelGGL(k_gs_emit_super, dim3(div_up(vn, kEmitBlock)), dim3(kEmitBlock), 0, st,
                        at<uint32_t>(ws, L.soffs), sorted_e, at<float4>(ws, L.rec), super_count,
                        vn, n, max_pairs, o.tile, L.sxn, L.spv, at<uint32_t>(ws, L.skey0),
                        at<uint64_t>(ws, L.sval0), L.st_total, at<uint2>(ws, L.srange),
                        dev_status);
     VRS_LAUNCH_CHECK();
-    trace_end(VRS_TRACE_GS_EMIT, st);
-    trace_begin(VRS_TRACE_GS_SORT, st);
+    trace_end(tr, VRS_TRACE_GS_EMIT, st);
+    trace_begin(tr, VRS_TRACE_GS_SORT, st);
     VRS_HIP_CHECK(radix_sort_u64(at<uint32_t>(ws, L.skey0), at<uint64_t>(ws, L.sval0),
                                  at<uint32_t>(ws, L.skey1), at<uint64_t>(ws, L.sval1), super_count,
-                                 max_pairs, L.st_bits, at<void>(ws, L.sort_tmp), dev_status, st,
-                                 &s1));
+                                 max_pairs, L.st_bits, L.radix, at<void>(ws, L.sort_tmp),
+                                 dev_status, st, &s1));
   } else {
-    trace_begin(VRS_TRACE_GS_SORT, st);
+    trace_begin(tr, VRS_TRACE_GS_SORT, st);
     VRS_HIP_CHECK(fill_u32(super_count, 0, 1, st));
     VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, L.srange), 0, 2 * L.st_total, st));
     VRS_HIP_CHECK(fill_u32(at<uint32_t>(ws, L.sched), 0, kSchedDone + 1, st));
@@ -1050,7 +1058,7 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
   const unsigned unit_blocks =
       (unsigned)std::min<int64_t>(2048, div_up(bin_units_max(mp, L.st_total), 4));
   // one sort pass: its digit counts are the run lengths; else find the runs
-  const bool one_pass = vn > 0 && L.st_bits <= 8;
+  const bool one_pass = vn > 0 && L.st_bits <= L.radix;
   if (!one_pass) {
     hipLaunchKernelGGL(k_gs_runs, dim3((unsigned)std::min<int64_t>(4096, div_up(mp, 256))),
                        dim3(256), 0, st, skeys, super_count, max_pairs, at<uint2>(ws, L.srange));
@@ -1084,14 +1092,28 @@ extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
                      L.tiles_y, at<uint32_t>(ws, L.ids));
   VRS_LAUNCH_CHECK();
   const uint32_t* order = at<uint32_t>(ws, L.order);
-  trace_end(VRS_TRACE_GS_SORT, st);
-  trace_begin(VRS_TRACE_GS_BLEND, st);
+  trace_end(tr, VRS_TRACE_GS_SORT, st);
+  trace_begin(tr, VRS_TRACE_GS_BLEND, st);
+  const bool stats = (flags & kRenderStats) != 0;
   switch (o.tile) {
-    case 8: launch_blend<8>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    case 16: launch_blend<16>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    default: launch_blend<32>(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    case 8: launch_blend<8>(stats, L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    case 16: launch_blend<16>(stats, L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
+    default: launch_blend<32>(stats, L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
   }
   VRS_LAUNCH_CHECK();
-  trace_end(VRS_TRACE_GS_BLEND, st);
+  trace_end(tr, VRS_TRACE_GS_BLEND, st);
   return VRS_OK;
+}
+}  // namespace vrs
+
+extern "C" vrs_status vrs_render_gaussians(const float* mean, const float* cov,
+                                           const float* opacity, const float* sh, int sh_degree,
+                                           int64_t n, const vrs_view* views, int n_views,
+                                           const vrs_raster_opts* opts, float* rgb, float* depth,
+                                           float* t_final, int32_t* n_contrib, void* ws,
+                                           size_t ws_bytes, int64_t max_pairs,
+                                           int32_t* dev_status, void* stream) {
+  return render_impl(mean, cov, opacity, sh, sh_degree, n, views, n_views, opts, rgb, depth,
+                     t_final, n_contrib, ws, ws_bytes, max_pairs, dev_status, stream,
+                     kRenderStats, nullptr);
 }

@@ -26,7 +26,7 @@ struct RenderWs {
       total;
   int64_t vn, tiles_x, tiles_y, tiles_total, npix, sxn, syn, spv, st_total;
   int st_bits;
-  bool super_in_1;
+  int radix;   // digit width of the sorts
 };
 
 inline int bits_for(int64_t n) {
@@ -42,10 +42,15 @@ inline int64_t bin_units_max(int64_t max_pairs, int64_t st_total) {
   return (std::max<int64_t>(max_pairs, 1) + kBinUnit - 1) / kBinUnit + st_total;
 }
 
-inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, int64_t max_pairs,
-                          RenderWs* L) {
+// Digit width of the periphery's radix sorts from the options (0: 8 bits).
+inline int opts_radix(const vrs_raster_opts* o) { return o->radix_bits == 0 ? 8 : o->radix_bits; }
+
+inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, int radix,
+                          int64_t max_pairs, RenderWs* L) {
   if (n < 0 || nv < 1 || nv > VRS_MAX_VIEWS || !views || max_pairs < 0) return false;
   if (tile != 8 && tile != 16 && tile != 32) return false;
+  if (!radix_bits_ok(radix)) return false;
+  L->radix = radix;
   const int W = views[0].width, H = views[0].height;
   L->vn = n * nv;
   L->tiles_x = (W + tile - 1) / tile;
@@ -57,7 +62,6 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->spv = L->sxn * L->syn;
   L->st_total = L->spv * nv;
   L->st_bits = bits_for(L->st_total);
-  L->super_in_1 = (((L->st_bits + 7) / 8) & 1) != 0;
   const int64_t vn = std::max<int64_t>(L->vn, 1);
   const int64_t mp = std::max<int64_t>(max_pairs, 1);
   Carver c;
@@ -88,7 +92,7 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->last = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->evals = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
   L->g2d = c.take((size_t)vn * 10 * 4);   // per (view, Gaussian) screen-space gradients
-  L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32), sort_tmp_bytes(mp, L->st_bits)));
+  L->sort_tmp = c.take(std::max(sort_tmp_bytes(vn, 32, radix), sort_tmp_bytes(mp, L->st_bits, radix)));
   L->scan_tmp = c.take(std::max(scan_tmp_bytes(vn), scan_tmp_bytes(L->tiles_total)));
   L->sched = c.take((size_t)kSchedWords * 4);   // follows scan_tmp: cleared together
   L->stot = c.take((size_t)L->st_total * 4);

@@ -28,30 +28,7 @@ bool make_views(const vrs_view* views, int n, KViews* out) {
   return true;
 }
 
-namespace {
-struct TraceHook {
-  int stage = 0;
-  hipEvent_t start = nullptr, stop = nullptr;
-} g_trace;
-}  // namespace
-
-void trace_begin(int stage, hipStream_t st) {
-  if (g_trace.stage == stage && g_trace.start) (void)hipEventRecord(g_trace.start, st);
-}
-void trace_end(int stage, hipStream_t st) {
-  if (g_trace.stage == stage && g_trace.stop) (void)hipEventRecord(g_trace.stop, st);
-}
-
 }  // namespace vrs
-
-extern "C" vrs_status vrs_trace_set(int stage, void* start_event, void* stop_event) {
-  if (stage < 0 || stage > VRS_TRACE_GS_DEPTH_SORT) return VRS_EINVAL;
-  if (stage != 0 && (!start_event || !stop_event)) return VRS_EINVAL;
-  vrs::g_trace.stage = stage;
-  vrs::g_trace.start = static_cast<hipEvent_t>(start_event);
-  vrs::g_trace.stop = static_cast<hipEvent_t>(stop_event);
-  return VRS_OK;
-}
 
 extern "C" const char* vrs_status_string(vrs_status s) {
   switch (s) {

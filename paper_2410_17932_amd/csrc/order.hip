@@ -110,7 +110,7 @@ bool order_layout(int64_t n, OrderWs* L) {
   L->k0 = c.take((size_t)n * 4);
   L->k1 = c.take((size_t)n * 4);
   L->v1 = c.take((size_t)n * 4);
-  L->sort_tmp = c.take(sort_tmp_bytes(n, 30));
+  L->sort_tmp = c.take(sort_tmp_bytes(n, 30, 8));
   L->total = c.off;
   return true;
 }
@@ -164,8 +164,8 @@ vrs_status spatial_order_run(const float* pos, int64_t n, uint32_t* perm, void* 
   VRS_LAUNCH_CHECK();
   bool in1 = false;
   VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.k0), perm, at<uint32_t>(ws, L.k1),
-                               at<uint32_t>(ws, L.v1), nullptr, n, 30, at<void>(ws, L.sort_tmp),
-                               nullptr, st, &in1));
+                               at<uint32_t>(ws, L.v1), nullptr, n, 30, 8,
+                               at<void>(ws, L.sort_tmp), nullptr, st, &in1));
   if (in1) {
     hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)std::min<int64_t>(4096, div_up(n, 256))),
                        dim3(256), 0, st, at<uint32_t>(ws, L.v1), perm, n);

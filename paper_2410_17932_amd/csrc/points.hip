@@ -100,10 +100,15 @@ static bool splat_layout_for(int64_t np, int n_views, const vrs_view* views, con
                       max_frags, L);
 }
 
-// host: crop table with packed-pyramid and packed-output bases
-bool make_crops(const vrs_crop* crops, int n_crops, int levels, const KViews& kv, KCrops* out) {
-  if (n_crops < 0 || n_crops > VRS_MAX_CROPS) return false;
+// host: crop table with packed-pyramid and packed-output bases; with a
+// device placement table the host origins are not used (nor checked)
+bool make_crops(const vrs_crop* crops, int n_crops, int levels, const KViews& kv, KCrops* out,
+                const vrs_crop_place* place, bool check_origins = true) {
+  if (n_crops < 0 || n_crops > VRS_MAX_CROPS || levels < 1 || levels > VRS_MAX_LEVELS)
+    return false;
+  if (n_crops > 0 && !crops) return false;
   out->n = n_crops;
+  out->place = reinterpret_cast<const int4*>(place);
   int64_t pb = 0, ob = 0;
   const int unit = 1 << (levels - 1);
   for (int k = 0; k < n_crops; ++k) {
@@ -111,10 +116,15 @@ bool make_crops(const vrs_crop* crops, int n_crops, int levels, const KViews& kv
     if (c.view < 0 || c.view >= kv.n) return false;
     if (c.size < unit || c.size % unit != 0) return false;
     const KView& v = kv.v[c.view];
-    if (c.x0 < 0 || c.y0 < 0 || c.x0 + c.size > v.W || c.y0 + c.size > v.H) return false;
+    if (c.size > v.W || c.size > v.H) return false;
+    if (!place && check_origins &&
+        (c.x0 < 0 || c.y0 < 0 || c.x0 + c.size > v.W || c.y0 + c.size > v.H))
+      return false;
     KCrop& d = out->c[k];
     d.view = c.view; d.x0 = c.x0; d.y0 = c.y0; d.size = c.size;
     d.gx = c.gaze_x; d.gy = c.gaze_y;
+    d.mx0 = v.W - c.size;
+    d.my0 = v.H - c.size;
     d.pix_base = (int)pb;
     d.out_base = (int)ob;
     for (int l = 0; l < levels; ++l) pb += (int64_t)(c.size >> l) * (c.size >> l);
@@ -151,8 +161,9 @@ __device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx,
   for (int k = 0; k < crops.n; ++k) {
     const KCrop& c = crops.c[k];
     if (c.view != v) continue;
-    const int64_t x0 = (int64_t)c.x0 - M, x1 = (int64_t)c.x0 + c.size + M;
-    const int64_t y0 = (int64_t)c.y0 - M, y1 = (int64_t)c.y0 + c.size + M;
+    const int cx0 = crop_x0(crops, k), cy0 = crop_y0(crops, k);
+    const int64_t x0 = (int64_t)cx0 - M, x1 = (int64_t)cx0 + c.size + M;
+    const int64_t y0 = (int64_t)cy0 - M, y1 = (int64_t)cy0 + c.size + M;
     if (x0 < hi_x && x1 > lo_x && y0 < hi_y && y1 > lo_y) mask |= 1u << k;
   }
   grid[idx] = mask;
@@ -211,13 +222,14 @@ __device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, const KCrops&
     cand &= cand - 1;
     const KCrop& c = crops.c[k];
     if (c.view != v) continue;
-    const float ax = g.px - (float)c.x0, ay = g.py - (float)c.y0, lim = (float)c.size + M;
+    const int cx0 = crop_x0(crops, k), cy0 = crop_y0(crops, k);
+    const float ax = g.px - (float)cx0, ay = g.py - (float)cy0, lim = (float)c.size + M;
     if (!(ax >= -M && ax < lim && ay >= -M && ay < lim)) continue;
     for (int li = 0; li < (g.two ? 2 : 1); ++li) {
       const int l = g.l0 + li, Sl = c.size >> l;
       float xl, yl;
       int ix, iy;
-      if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) cnt += pt_targets(ix, iy, Sl);
+      if (pt_layer32(g, cx0, cy0, l, Sl, xl, yl, ix, iy)) cnt += pt_targets(ix, iy, Sl);
     }
   }
   return cnt;
@@ -490,6 +502,7 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     for (int k = 0; k < crops.n; ++k) {
       const KCrop& c = crops.c[k];
       if (c.view != v) continue;
+      const int cx0 = crop_x0(crops, k), cy0 = crop_y0(crops, k);
       int lb = c.pix_base;
       int l = 0;
       for (; l < g.l0; ++l) lb += (c.size >> l) * (c.size >> l);
@@ -498,9 +511,9 @@ __global__ __launch_bounds__(256) void k_pt_emit(
         const float wl = g.two ? (li == 0 ? 1.0f - f : f) : 1.0f;
         float xl, yl;
         int ix, iy;
-        if (pt_layer32(g, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) {
-          const float bx = pt_frac_ff(cv.fx, ux, cv.cx, c.x0, l, ix);
-          const float by = pt_frac_ff(cv.fy, uy, cv.cy, c.y0, l, iy);
+        if (pt_layer32(g, cx0, cy0, l, Sl, xl, yl, ix, iy)) {
+          const float bx = pt_frac_ff(cv.fx, ux, cv.cx, cx0, l, ix);
+          const float by = pt_frac_ff(cv.fy, uy, cv.cy, cy0, l, iy);
           for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
               const int xx = ix + dx, yy = iy + dy;
@@ -715,7 +728,9 @@ extern "C" size_t vrs_splat_workspace_size(int64_t np, int n_views, const vrs_vi
   SplatWs L;
   KViews kv;
   KCrops kc;
-  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc)) return 0;
+  if (!check_views(views, n_views, &kv) ||
+      !make_crops(crops, n_crops, levels, kv, &kc, nullptr, false))
+    return 0;
   if (!splat_layout_for(np, n_views, views, crops, n_crops, levels, max_frags, &L)) return 0;
   return L.total;
 }
@@ -733,19 +748,19 @@ extern "C" vrs_status vrs_splat_workspace_layout(int64_t np, int n_views, const 
   return VRS_OK;
 }
 
-extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
-                                       const uint16_t* feat, const float* opacity, int64_t np,
-                                       int channels, int levels, const vrs_view* views,
-                                       int n_views, const vrs_crop* crops, int n_crops,
-                                       const float* depth, const float* t_final, float cov_min,
-                                       float slack, const uint32_t* point_ids, float* pyramid,
-                                       void* ws, size_t ws_bytes, int64_t max_frags,
-                                       int32_t* dev_status, void* stream) {
+namespace vrs {
+vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* feat,
+                      const float* opacity, int64_t np, int channels, int levels,
+                      const vrs_view* views, int n_views, const vrs_crop* crops, int n_crops,
+                      const vrs_crop_place* place, const float* depth, const float* t_final,
+                      float cov_min, float slack, const uint32_t* point_ids, float* pyramid,
+                      void* ws, size_t ws_bytes, int64_t max_frags, int32_t* dev_status,
+                      void* stream, const Trace* tr) {
   KViews kv;
   KCrops kc;
   SplatWs L;
   if (channels != 4) return channels > 0 ? VRS_EUNSUPPORTED : VRS_EINVAL;
-  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc))
+  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc, place))
     return VRS_EINVAL;
   if (np < 0 || np * n_views >= (int64_t(1) << 30) ||
       (np > 0 && (!pos || !radius || !feat)))
@@ -763,7 +778,7 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
   for (int k = 0; k < n_crops; ++k) a.view_mask |= 1u << crops[k].view;
   const int64_t vn = L.vn;
   uint32_t* frag_count = at<uint32_t>(ws, L.frag_count);
-  trace_begin(VRS_TRACE_SPLAT, st);
+  trace_begin(tr, VRS_TRACE_SPLAT, st);
   if (vn == 0 || n_crops == 0) {
     if (L.pix_total > 0) {
       const int blocks = (int)std::min<int64_t>(4096, div_up(L.pix_total, 256));
@@ -772,7 +787,7 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
       VRS_LAUNCH_CHECK();
     }
     VRS_HIP_CHECK(fill_u32(frag_count, 0, 1, st));
-    trace_end(VRS_TRACE_SPLAT, st);
+    trace_end(tr, VRS_TRACE_SPLAT, st);
     return VRS_OK;
   }
   uint32_t* live = at<uint32_t>(ws, L.live);
@@ -821,8 +836,23 @@ extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
                      frag_count, max_frags, feat, opacity, np, L.pix_total,
                      reinterpret_cast<float4*>(pyramid));
   VRS_LAUNCH_CHECK();
-  trace_end(VRS_TRACE_SPLAT, st);
+  trace_end(tr, VRS_TRACE_SPLAT, st);
   return VRS_OK;
+}
+}  // namespace vrs
+
+extern "C" vrs_status vrs_splat_points(const float* pos, const float* radius,
+                                       const uint16_t* feat, const float* opacity, int64_t np,
+                                       int channels, int levels, const vrs_view* views,
+                                       int n_views, const vrs_crop* crops, int n_crops,
+                                       const vrs_crop_place* place, const float* depth,
+                                       const float* t_final, float cov_min, float slack,
+                                       const uint32_t* point_ids, float* pyramid, void* ws,
+                                       size_t ws_bytes, int64_t max_frags, int32_t* dev_status,
+                                       void* stream) {
+  return splat_impl(pos, radius, feat, opacity, np, channels, levels, views, n_views, crops,
+                    n_crops, place, depth, t_final, cov_min, slack, point_ids, pyramid, ws,
+                    ws_bytes, max_frags, dev_status, stream, nullptr);
 }
 
 // ------------------------------------------------------------- backward
@@ -917,11 +947,12 @@ __global__ __launch_bounds__(256) void k_pt_blend_bwd(
           continue;
         float xl, yl;
         int ix, iy;
-        if (!pt_layer32(pg, c.x0, c.y0, l, Sl, xl, yl, ix, iy)) continue;
+        const int cx0 = crop_x0(crops, k), cy0 = crop_y0(crops, k);
+        if (!pt_layer32(pg, cx0, cy0, l, Sl, xl, yl, ix, iy)) continue;
         FF ux, uy;
         pt_plane_ff(cv, pos[id], pos[np + id], pos[2 * np + id], ux, uy);
-        const float bx = pt_frac_ff(cv.fx, ux, cv.cx, c.x0, l, ix);
-        const float by = pt_frac_ff(cv.fy, uy, cv.cy, c.y0, l, iy);
+        const float bx = pt_frac_ff(cv.fx, ux, cv.cx, cx0, l, ix);
+        const float by = pt_frac_ff(cv.fy, uy, cv.cy, cy0, l, iy);
         const int dx = xx - ix, dy = yy - iy;
         const float wx = dx ? bx : 1.0f - bx, wy = dy ? by : 1.0f - by;
         float f2 = 0.0f, wl = 1.0f;
@@ -957,6 +988,7 @@ extern "C" vrs_status vrs_splat_points_backward(const float* pos, const float* r
                                                 int64_t np, int channels, int levels,
                                                 const vrs_view* views, int n_views,
                                                 const vrs_crop* crops, int n_crops,
+                                                const vrs_crop_place* place,
                                                 const float* d_pyramid, float* d_feat,
                                                 float* d_pos, float* d_radius, float* d_opacity,
                                                 void* ws, size_t ws_bytes, int64_t max_frags,
@@ -965,7 +997,7 @@ extern "C" vrs_status vrs_splat_points_backward(const float* pos, const float* r
   KCrops kc;
   SplatWs L;
   if (channels != 4) return channels > 0 ? VRS_EUNSUPPORTED : VRS_EINVAL;
-  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc))
+  if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc, place))
     return VRS_EINVAL;
   if (!splat_layout_for(np, n_views, views, crops, n_crops, levels, max_frags, &L) || !ws ||
       ws_bytes < L.total || !d_pyramid)
@@ -985,6 +1017,42 @@ extern "C" vrs_status vrs_splat_points_backward(const float* pos, const float* r
                      at<uint32_t>(ws, L.frag_count), max_frags, pos, radius, feat, opacity, np, kv,
                      kc, a, L.pix_total, reinterpret_cast<const float4*>(d_pyramid), d_feat, d_pos,
                      d_radius, d_opacity);
+  VRS_LAUNCH_CHECK();
+  return VRS_OK;
+}
+
+// ------------------------------------------------------- crop placement
+namespace vrs {
+
+// Crop origins from gaze points on the device (Sec. 4 "Inference": the eye
+// tracker is read after the periphery is rendered): the crop of size S
+// centred on the gaze, x0 = clamp(rint(gaze_x - S/2), 0, W - S) (ties to
+// even), y0 likewise.
+__global__ void k_place_crops(const float2* __restrict__ gaze, KCrops kc, int4* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= kc.n) return;
+  const float2 g = gaze[k];
+  const float h = 0.5f * (float)kc.c[k].size;
+  const float fx = rintf(g.x - h), fy = rintf(g.y - h);
+  // clamp in float first: a non-finite or huge gaze gives a valid origin
+  const float cx = fminf(fmaxf(fx, 0.0f), (float)kc.c[k].mx0);
+  const float cy = fminf(fmaxf(fy, 0.0f), (float)kc.c[k].my0);
+  out[k] = make_int4(cx == cx ? (int)cx : 0, cy == cy ? (int)cy : 0, __float_as_int(g.x),
+                     __float_as_int(g.y));
+}
+
+}  // namespace vrs
+
+extern "C" vrs_status vrs_place_crops(const float* gaze, const vrs_view* views, int n_views,
+                                      const vrs_crop* crops, int n_crops, vrs_crop_place* place,
+                                      void* stream) {
+  KViews kv;
+  KCrops kc;
+  if (!gaze || !place || n_crops < 1 || !check_views(views, n_views, &kv) ||
+      !make_crops(crops, n_crops, 1, kv, &kc, nullptr, false))
+    return VRS_EINVAL;
+  hipLaunchKernelGGL(k_place_crops, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<const float2*>(gaze), kc, reinterpret_cast<int4*>(place));
   VRS_LAUNCH_CHECK();
   return VRS_OK;
 }

@@ -136,11 +136,13 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* __restrict_
 }
 
 // ------------------------------------------------------------------ sort
-// LSD radix sort, 8 bits per pass, reduce-then-scan: per pass an upsweep
-// counts each partition's digits, one workgroup per digit scans those
-// counts over partitions, and the downsweep ranks its partition in LDS and
-// writes every item straight to its final position.  No inter-workgroup
-// waiting anywhere; deterministic.
+// LSD radix sort, R bits per pass (R = 4, 6, 8 or 11: the digit width is
+// tuned per workload; fewer wider passes move the data fewer times, narrower
+// digits keep the per-partition histograms small), reduce-then-scan: per
+// pass an upsweep counts each partition's digits, one workgroup per digit
+// scans those counts over partitions, and the downsweep ranks its partition
+// in LDS and writes every item straight to its final position.  No
+// inter-workgroup waiting anywhere; deterministic.
 constexpr int kSortBlock = 256, kSortWaves = kSortBlock / 64, kSortItems = 8;
 constexpr int kWaveChunk = 64 * kSortItems, kSortTile = kSortBlock * kSortItems;  // 2048
 constexpr int64_t kSortGrid = 1024;
@@ -155,16 +157,19 @@ __device__ inline int64_t sort_n(const uint32_t* n_dev, int64_t n_max) {
 // Workgroups take partitions in grid-stride order: the grid is sized for at
 // most kSortGrid workgroups whatever the capacity, the count is read on the
 // device.
+template <int R>
 __global__ __launch_bounds__(kSortBlock) void k_sort_count(const uint32_t* __restrict__ keys,
                                                             const uint32_t* n_dev, int64_t n_max,
                                                             int shift, int64_t parts,
                                                             uint32_t* __restrict__ counts) {
-  __shared__ uint32_t s_h[256];
+  constexpr int NB = 1 << R;
+  constexpr uint32_t MASK = NB - 1;
+  __shared__ uint32_t s_h[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = sort_n(n_dev, n_max);
   for (int64_t part = blockIdx.x; part * kSortTile < n; part += gridDim.x) {
     const int64_t base = part * kSortTile;
-    s_h[tid] = 0;
+    for (int d = tid; d < NB; d += kSortBlock) s_h[d] = 0;
     __syncthreads();
     const int64_t wbase = base + (int64_t)wave * kWaveChunk;
     uint32_t kv[kSortItems];   // every load in flight before the first atomic
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(const uint32_t* __res
     for (int j = 0; j < kSortItems; ++j) {
       const int64_t i = wbase + j * 64 + lane;
       if (i < n) {
-        const uint32_t d = (kv[j] >> shift) & 255u;
+        const uint32_t d = (kv[j] >> shift) & MASK;
         const uint64_t act = __ballot(true);
         const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
         if (__ballot(d != d0) == 0) {
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_count(const uint32_t* __res
       }
     }
     __syncthreads();
-    counts[(int64_t)tid * parts + part] = s_h[tid];
+    for (int d = tid; d < NB; d += kSortBlock) counts[(int64_t)d * parts + part] = s_h[d];
     __syncthreads();   // s_h is cleared for the next partition
   }
 }
@@ -234,27 +239,55 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t* counts, const uint3
   if (tid == 0) totals[blockIdx.x] = carry;
 }
 
+// Exclusive scan over the NB digits of a workgroup: thread t owns digits
+// [t DPT, t DPT + DPT) (DPT = NB / 256, or one digit for t < NB when NB is
+// smaller); x[j] is digit t DPT + j's value, replaced by its exclusive prefix.
+template <int NB>
+__device__ inline void block_digit_scan(uint32_t* x, uint32_t* s_scan) {
+  constexpr int DPT = NB >= kSortBlock ? NB / kSortBlock : 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const uint32_t v = x[j];
+    x[j] = sum;
+    sum += v;
+  }
+  const uint32_t incl = wave_incl_scan(sum);
+  if (lane == 63) s_scan[wave] = incl;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int w = 0; w < wave; ++w) woff += s_scan[w];
+  __syncthreads();   // s_scan is reused by the caller's next scan
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) x[j] += woff + incl - sum;
+}
+
 // Downsweep of a partition (grid-stride order, as the upsweep): stable rank of every item among the
 // partition's items of the same digit (wave ballots, then waves in order),
 // items regrouped by digit in LDS, then written to
 //   base(digit) + count of the digit in earlier partitions + local rank,
 // with base(digit) the exclusive scan of the digit totals.
-template <typename V>
+template <typename V, int R>
 __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
     const uint32_t* __restrict__ kin, const V* __restrict__ vin, uint32_t* __restrict__ kout,
     V* __restrict__ vout, const uint32_t* n_dev, int64_t n_max, int shift, int64_t parts,
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
     const uint32_t* __restrict__ gsrc, uint32_t* __restrict__ gdst) {
-  __shared__ uint32_t s_wh[kSortWaves][256];
-  __shared__ uint32_t s_lstart[256], s_gstart[256], s_scan[kSortWaves];
+  constexpr int NB = 1 << R;
+  constexpr uint32_t MASK = NB - 1;
+  constexpr int DPT = NB >= kSortBlock ? NB / kSortBlock : 1;
+  __shared__ uint32_t s_wh[kSortWaves][NB];
+  __shared__ uint32_t s_lstart[NB], s_gstart[NB], s_scan[kSortWaves];
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ V s_vals[kSortTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = sort_n(n_dev, n_max);
   for (int64_t part = blockIdx.x; part * kSortTile < n; part += gridDim.x) {
     const int64_t base = part * kSortTile;
+    for (int d = tid; d < NB; d += kSortBlock)
 #pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) s_wh[w][tid] = 0;
+      for (int w = 0; w < kSortWaves; ++w) s_wh[w][d] = 0;
     __syncthreads();
     // load: wave w owns [base + w*512, +512); item j of lane l at j*64 + l
     uint32_t key[kSortItems];
@@ -273,10 +306,10 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       const bool ok = wbase + j * 64 + lane < n;
-      const uint32_t d = (key[j] >> shift) & 255u;
+      const uint32_t d = (key[j] >> shift) & MASK;
       uint64_t m = __ballot(ok);
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < R; ++b) {
         const bool bit = (d >> b) & 1u;
         const uint64_t bb = __ballot(bit);
         m &= bit ? bb : ~bb;
@@ -289,36 +322,41 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit d = tid: exclusive prefix over waves and the partition's count
-    const uint32_t d = tid;
-    uint32_t cnt = 0;
+    // per digit: exclusive prefix over waves and the partition's count; the
+    // local start of each digit (scan of those counts) and its global base
+    // (scan of the digit totals plus the earlier partitions' count)
+    uint32_t cnt[DPT], glob[DPT];
 #pragma unroll
-    for (int w = 0; w < kSortWaves; ++w) {
-      const uint32_t c = s_wh[w][d];
-      s_wh[w][d] = cnt;
-      cnt += c;
+    for (int j = 0; j < DPT; ++j) {
+      const int d = tid * DPT + j;
+      uint32_t c = 0;
+      if (d < NB) {
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+          const uint32_t x = s_wh[w][d];
+          s_wh[w][d] = c;
+          c += x;
+        }
+      }
+      cnt[j] = c;
+      glob[j] = d < NB ? totals[d] : 0u;
     }
-    // local start of each digit (block scan of cnt) and its global base (block
-    // scan of the digit totals)
-    const uint32_t h = totals[d];
-    const uint32_t incl = wave_incl_scan(cnt), hincl = wave_incl_scan(h);
-    if (lane == 63) s_scan[wave] = incl;
-    __syncthreads();
-    uint32_t woff = 0;
-    for (int w = 0; w < wave; ++w) woff += s_scan[w];
-    s_lstart[d] = woff + incl - cnt;
-    __syncthreads();
-    if (lane == 63) s_scan[wave] = hincl;
-    __syncthreads();
-    uint32_t hoff = 0;
-    for (int w = 0; w < wave; ++w) hoff += s_scan[w];
-    s_gstart[d] = hoff + hincl - h + counts[(int64_t)d * parts + part];
+    block_digit_scan<NB>(cnt, s_scan);
+    block_digit_scan<NB>(glob, s_scan);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = tid * DPT + j;
+      if (d < NB) {
+        s_lstart[d] = cnt[j];
+        s_gstart[d] = glob[j] + counts[(int64_t)d * parts + part];
+      }
+    }
     __syncthreads();
     // regroup by digit in LDS, then coalesced runs to the output
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       if (wbase + j * 64 + lane < n) {
-        const uint32_t dj = (key[j] >> shift) & 255u;
+        const uint32_t dj = (key[j] >> shift) & MASK;
         const uint32_t lpos = s_lstart[dj] + s_wh[wave][dj] + rank[j];
         s_keys[lpos] = key[j];
         s_vals[lpos] = val[j];
@@ -328,7 +366,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
     const int cnt_tile = (int)min((int64_t)kSortTile, n - base);
     for (int i = tid; i < cnt_tile; i += kSortBlock) {
       const uint32_t k = s_keys[i];
-      const uint32_t dk = (k >> shift) & 255u;
+      const uint32_t dk = (k >> shift) & MASK;
       const uint32_t g = s_gstart[dk] + (uint32_t)i - s_lstart[dk];
       kout[g] = k;
       vout[g] = s_vals[i];
@@ -338,33 +376,54 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
   }
 }
 
-template <typename V>
-hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t* n_dev,
-                           int64_t n_max, int key_bits, void* tmp, int32_t* status,
-                           hipStream_t st, bool* result_in_1, const uint32_t* gather_src,
-                           uint32_t* gather_dst) {
-  (void)status;   // nothing in the sort waits on another workgroup
-  const int passes = key_bits <= 0 ? 0 : (key_bits + 7) / 8;
+template <typename V, int R>
+hipError_t radix_sort_r(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t* n_dev,
+                        int64_t n_max, int key_bits, void* tmp, hipStream_t st,
+                        bool* result_in_1, const uint32_t* gather_src, uint32_t* gather_dst) {
+  constexpr int NB = 1 << R;
+  const int passes = key_bits <= 0 ? 0 : (key_bits + R - 1) / R;
   *result_in_1 = (passes & 1) != 0;
   if (passes == 0 || n_max == 0) return hipSuccess;
   const int64_t parts = (n_max + kSortTile - 1) / kSortTile;
   const unsigned grid = (unsigned)std::min<int64_t>(parts, kSortGrid);
   uint32_t* totals = static_cast<uint32_t*>(tmp);
-  uint32_t* counts = totals + 256;
+  uint32_t* counts = totals + NB;
   uint32_t* kb[2] = {k0, k1};
   V* vb[2] = {v0, v1};
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_sort_count, dim3(grid), dim3(kSortBlock), 0, st, kb[p & 1],
-                       n_dev, n_max, 8 * p, parts, counts);
-    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, st, counts, n_dev, n_max, parts,
+    hipLaunchKernelGGL(k_sort_count<R>, dim3(grid), dim3(kSortBlock), 0, st, kb[p & 1],
+                       n_dev, n_max, R * p, parts, counts);
+    hipLaunchKernelGGL(k_sort_scan, dim3(NB), dim3(256), 0, st, counts, n_dev, n_max, parts,
                        totals);
     const bool last = p == passes - 1;
-    hipLaunchKernelGGL(k_sort_scatter<V>, dim3(grid), dim3(kSortBlock), 0, st,
+    hipLaunchKernelGGL((k_sort_scatter<V, R>), dim3(grid), dim3(kSortBlock), 0, st,
                        kb[p & 1], vb[p & 1], kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, n_max,
-                       8 * p, parts, counts, totals, last ? gather_src : nullptr,
+                       R * p, parts, counts, totals, last ? gather_src : nullptr,
                        last ? gather_dst : nullptr);
   }
   return hipGetLastError();
+}
+
+template <typename V>
+hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t* n_dev,
+                           int64_t n_max, int key_bits, int radix_bits, void* tmp,
+                           int32_t* status, hipStream_t st, bool* result_in_1,
+                           const uint32_t* gather_src, uint32_t* gather_dst) {
+  (void)status;   // nothing in the sort waits on another workgroup
+  switch (radix_bits) {
+    case 4:
+      return radix_sort_r<V, 4>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
+                                gather_src, gather_dst);
+    case 6:
+      return radix_sort_r<V, 6>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
+                                gather_src, gather_dst);
+    case 11:
+      return radix_sort_r<V, 11>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
+                                 gather_src, gather_dst);
+    default:
+      return radix_sort_r<V, 8>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
+                                gather_src, gather_dst);
+  }
 }
 
 }  // namespace
@@ -416,25 +475,30 @@ const uint32_t* radix_sort_digit_totals(const void* tmp) {
   return static_cast<const uint32_t*>(tmp);   // totals lead the temporary
 }
 
-size_t sort_tmp_bytes(int64_t n_max, int key_bits) {
+bool radix_bits_ok(int radix_bits) {
+  return radix_bits == 4 || radix_bits == 6 || radix_bits == 8 || radix_bits == 11;
+}
+
+size_t sort_tmp_bytes(int64_t n_max, int key_bits, int radix_bits) {
   (void)key_bits;   // one counts matrix, reused by every pass
   const int64_t parts = std::max<int64_t>(1, (n_max + kSortTile - 1) / kSortTile);
-  return (size_t)(256 + 256 * parts) * 4;
+  const int64_t nb = int64_t(1) << (radix_bits_ok(radix_bits) ? radix_bits : 8);
+  return (size_t)(nb + nb * parts) * 4;
 }
 
 hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
-                          const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
-                          int32_t* status, hipStream_t st, bool* result_in_1,
+                          const uint32_t* n_dev, int64_t n_max, int key_bits, int radix_bits,
+                          void* tmp, int32_t* status, hipStream_t st, bool* result_in_1,
                           const uint32_t* gather_src, uint32_t* gather_dst) {
-  return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, status, st,
-                                   result_in_1, gather_src, gather_dst);
+  return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, radix_bits, tmp,
+                                   status, st, result_in_1, gather_src, gather_dst);
 }
 
 hipError_t radix_sort_u64(uint32_t* k0, uint64_t* v0, uint32_t* k1, uint64_t* v1,
-                          const uint32_t* n_dev, int64_t n_max, int key_bits, void* tmp,
-                          int32_t* status, hipStream_t st, bool* result_in_1) {
-  return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, status, st,
-                                   result_in_1, nullptr, nullptr);
+                          const uint32_t* n_dev, int64_t n_max, int key_bits, int radix_bits,
+                          void* tmp, int32_t* status, hipStream_t st, bool* result_in_1) {
+  return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, radix_bits, tmp,
+                                   status, st, result_in_1, nullptr, nullptr);
 }
 
 }  // namespace vrs

@@ -25,21 +25,22 @@ def _dev(a, dtype=None):
 
 
 class Frame:
+    """The batched frame on a plan (vrs_plan_create) with one
+    vrs_render_frame call per frame: the periphery's rgb image receives the
+    combined frame in place."""
+
     def __init__(self, scene: dict, decoder_dtype: int = api.VRS_BF16, tile: int = 16,
-                 mode: int = api.BLEND_LINEAR, ring: float = 64.0, m: float = 0.75,
-                 gamma: float = 0.2, cull: bool = True, pair_margin: float = 1.10,
-                 frag_margin: float = 1.25, spatial_order: bool = True,
-                 in_place: bool = True):
-        # in_place: the combination writes into the periphery image, touching
-        # only the pixels under the crops (run() returns that image)
-        self.in_place = in_place
+                 radix_bits: int = 8, mode: int = api.BLEND_LINEAR, ring: float = 64.0,
+                 m: float = 0.75, gamma: float = 0.2, cull: bool = True,
+                 pair_margin: float = 1.10, frag_margin: float = 1.25,
+                 spatial_order: bool = True):
         g, p = scene["gaussians"], scene["points"]
         self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
         self.sh_degree = g["sh_degree"]
         self.mode, self.ring, self.m, self.gamma, self.cull = mode, ring, m, gamma, cull
         self.decoder_dtype = decoder_dtype
         self.widths = scene["decoder"]["widths"]
-        self.raster = dict(scene["raster"], tile=tile)
+        self.raster = dict(scene["raster"], tile=tile, radix_bits=radix_bits)
         # primitives resident in HBM; attributes baked once (Sec. 4 "Inference")
         self.mean = _dev(g["mean"])
         self.sh = _dev(g["sh"])
@@ -61,13 +62,23 @@ class Frame:
             self.feat = self.feat[perm].contiguous()
         from .synth import pack_decoder
         self.weights = _dev(pack_decoder(scene["decoder"]))
+        # fixation points in device memory: each frame places its crops from
+        # them on the device, after the periphery (Sec. 4 "Inference"), so a
+        # captured frame follows set_gaze() without being captured again
+        self.gaze = _dev(np.array([[c.gaze_x, c.gaze_y] for c in self.crops], np.float32))
+        self.place = api.crop_places(len(self.crops))
         self.n, self.np = g["n"], p["n"]
         self.pair_margin, self.frag_margin = pair_margin, frag_margin
-        self._plan(tile)
+        self._plan(tile, radix_bits)
 
     # ------------------------------------------------------------ planning
-    def _plan(self, tile):
-        self.raster["tile"] = tile
+    def _plan(self, tile, radix_bits=None):
+        """Counting passes (capacity 1: the totals are computed on the
+        device) size the tile-pair and fragment capacities, then the plan and
+        its workspaces."""
+        if radix_bits is None:
+            radix_bits = self.raster["radix_bits"]
+        self.raster.update(tile=tile, radix_bits=radix_bits)
         self.opts = api.make_opts(**self.raster)
         V, H, W = len(self.views), self.views[0].height, self.views[0].width
         dev = self.mean.device
@@ -75,47 +86,67 @@ class Frame:
         self.depth = torch.empty((V, H, W), device=dev)
         self.tfinal = torch.empty((V, H, W), device=dev)
         self.ncontrib = torch.empty((V, H, W), device=dev, dtype=torch.int32)
-        self.out = self.rgb if self.in_place else torch.empty((V, 3, H, W), device=dev)
-        self.r_out = dict(rgb=self.rgb, depth=self.depth, tfinal=self.tfinal, ncontrib=self.ncontrib)
-        # counting pass: capacity 1 computes the totals on the device
+        self.out = self.rgb
+        r_out = dict(rgb=self.rgb, depth=self.depth, tfinal=self.tfinal, ncontrib=self.ncontrib)
+        self.plan = self.rws = self.sws = self.dws = None
         ws = api.RenderWorkspace(self.n, self.views, self.opts, 1)
         api.render_gaussians(self.mean, self.cov, self.opacity, self.sh, self.sh_degree,
-                             self.views, self.opts, ws, self.r_out)
+                             self.views, self.opts, ws, r_out)
         self.pairs = ws.pair_count()
+        del ws
         self.rws = api.RenderWorkspace(self.n, self.views, self.opts,
                                        int(self.pairs * self.pair_margin) + 4096)
-        del ws
         api.render_gaussians(self.mean, self.cov, self.opacity, self.sh, self.sh_degree,
-                             self.views, self.opts, self.rws, self.r_out)
+                             self.views, self.opts, self.rws, r_out)
         P = api.pyramid_pixels(self.crops, self.levels)
         self.pyramid = torch.empty((P, 4), device=dev)
         sws = api.SplatWorkspace(self.np, self.views, self.crops, self.levels, 1)
-        self._splat(sws)
+        api.place_crops(self.gaze, self.views, self.crops, self.place)
+        api.splat_points(self.pos, self.radius, self.feat, None, self.views, self.crops,
+                         self.levels, self.depth if self.cull else None,
+                         self.tfinal if self.cull else None, sws, pyramid=self.pyramid,
+                         point_ids=self.point_ids, place=self.place)
         self.frags = sws.frag_count()
         del sws
         self.sws = api.SplatWorkspace(self.np, self.views, self.crops, self.levels,
                                       int(self.frags * self.frag_margin) + 4096)
         self.dws = api.DecoderWorkspace(self.widths, self.crops, self.decoder_dtype)
         self.fovea = torch.empty(api.fovea_elements(self.crops), device=dev)
+        self.plan = api.Plan(self.views, self.crops, self.n, self.sh_degree, self.np,
+                             self.levels, self.opts, self.widths, self.decoder_dtype,
+                             self.rws.max_pairs, self.sws.max_frags, self.cull,
+                             mode=self.mode, ring=self.ring, m=self.m, gamma=self.gamma)
+        for which, w in ((api.WS_RENDER, self.rws), (api.WS_SPLAT, self.sws),
+                         (api.WS_DECODER, self.dws)):
+            assert self.plan.workspace_size(which) == w.buf.numel()
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self.c_scene = api.Scene(
+            mean=ptr(self.mean), cov=ptr(self.cov), opacity=ptr(self.opacity), sh=ptr(self.sh),
+            pos=ptr(self.pos), radius=ptr(self.radius), feat=ptr(self.feat), point_opacity=None,
+            point_ids=ptr(self.point_ids), decoder_weights=ptr(self.weights))
+        self.c_buf = api.FrameBuffers(
+            rgb=ptr(self.rgb), depth=ptr(self.depth), t_final=ptr(self.tfinal),
+            n_contrib=ptr(self.ncontrib), pyramid=ptr(self.pyramid), fovea_rgb=ptr(self.fovea),
+            place=ptr(self.place), ws_render=ptr(self.rws.buf), ws_splat=ptr(self.sws.buf),
+            ws_decoder=ptr(self.dws.buf), status_render=ptr(self.rws.status),
+            status_splat=ptr(self.sws.status))
         torch.cuda.synchronize()
         self.graph = None
 
-    def _splat(self, sws):
-        api.splat_points(self.pos, self.radius, self.feat, None, self.views, self.crops,
-                         self.levels, self.depth if self.cull else None,
-                         self.tfinal if self.cull else None, sws, pyramid=self.pyramid,
-                         point_ids=self.point_ids)
+    def set_gaze(self, gaze):
+        """New fixation points [n_crops][2] (view pixels) for the next frames:
+        written into the device buffer the frame reads (a captured graph
+        picks them up on its next replay)."""
+        self.gaze.copy_(torch.as_tensor(np.asarray(gaze, np.float32)).reshape(-1, 2))
+
+    def trace(self, stage, start=None, stop=None):
+        self.plan.trace(stage, start, stop)
 
     # --------------------------------------------------------------- frame
-    def run(self):
-        """Enqueue one batched frame on the current stream."""
-        api.render_gaussians(self.mean, self.cov, self.opacity, self.sh, self.sh_degree,
-                             self.views, self.opts, self.rws, self.r_out)
-        self._splat(self.sws)
-        api.decode_fovea(self.pyramid, self.levels, self.rgb, self.views, self.crops,
-                         self.weights, self.dws, out=self.fovea)
-        api.composite_frame(self.rgb, self.fovea, self.crops, self.mode, self.ring, self.m,
-                            self.gamma, out=self.out)
+    def run(self, stats: bool = False):
+        """Enqueue one batched frame on the current stream (stats: also keep
+        the periphery's per-pixel evaluation counts and last positions)."""
+        api.render_frame(self.plan, self.c_scene, self.gaze, self.c_buf, stats)
         return self.out
 
     def capture(self):
@@ -140,25 +171,27 @@ class Frame:
         return max(int(self.rws.status.item()), int(self.sws.status.item()))
 
     # ----------------------------------------------------------- autotune
-    def autotune(self, tiles=(8, 16, 32), reps: int = 5) -> dict:
-        """Time the periphery for each tile size on the live scene and keep
-        the fastest (results are tile-size invariant)."""
+    def autotune(self, tiles=(8, 16, 32), radix=(4, 6, 8, 11), reps: int = 5) -> dict:
+        """Time the frame for every tile size and sort radix on the live
+        scene and keep the fastest (neither changes a result)."""
         times = {}
         for t in tiles:
-            self._plan(t)
-            for _ in range(2):
-                self.run()
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(reps):
-                self.run()
-            b.record()
-            torch.cuda.synchronize()
-            times[t] = a.elapsed_time(b) / reps
+            for r in radix:
+                self._plan(t, r)
+                for _ in range(2):
+                    self.run()
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    self.run()
+                b.record()
+                torch.cuda.synchronize()
+                times[(t, r)] = a.elapsed_time(b) / reps
         best = min(times, key=times.get)
-        self._plan(best)
-        return dict(tile=best, ms=times)
+        self._plan(*best)
+        return dict(tile=best[0], radix_bits=best[1],
+                    ms={f"{t}/{r}": round(v, 4) for (t, r), v in times.items()})
 
 
 class PlainFrame:

@@ -1,0 +1,272 @@
+"""Host-side argument checks of every entry point, through the C-ABI: each
+bad argument returns VRS_EINVAL (or VRS_EUNSUPPORTED for a valid but
+unsupported shape) before anything is launched.  Device pointers here are
+stand-in addresses that are never dereferenced; the tests run where no GPU
+is present (a missing check would then fail to launch rather than touch
+memory) and are skipped where one is."""
+import ctypes
+
+import pytest
+import torch
+
+from paper_2410_17932_amd import api, synth
+
+pytestmark = pytest.mark.skipif(torch.cuda.is_available(),
+                                reason="host-side checks only; run without a GPU")
+
+EINVAL, EUNSUP = api.VRS_EINVAL, api.VRS_EUNSUPPORTED
+P = ctypes.c_void_p(0x1000)   # stand-in device address, never dereferenced
+NUL = None
+
+
+def _views(n=2, W=64, H=48):
+    return api.make_views([synth.pinhole(W, H, 60.0, (0.03 * i, 0, 0)) for i in range(n)])
+
+
+def _crops(spec):
+    """spec: (view, x0, y0, size) tuples."""
+    arr = (api.Crop * max(len(spec), 1))()
+    for i, (v, x, y, s) in enumerate(spec):
+        arr[i].view, arr[i].x0, arr[i].y0, arr[i].size = v, x, y, s
+        arr[i].gaze_x, arr[i].gaze_y = x + s / 2, y + s / 2
+    return arr
+
+
+def L():
+    return api.lib()
+
+
+# ------------------------------------------------------------------ render
+def _render(**kw):
+    a = dict(mean=P, cov=P, op=P, sh=P, deg=0, n=10, views=_views(), nv=2,
+             opts=api.make_opts(tile=16), rgb=P, depth=P, tf=P, nc=P, ws=P, ws_bytes=1 << 40,
+             max_pairs=100, status=P)
+    a.update(kw)
+    opts = ctypes.byref(a["opts"]) if a["opts"] is not None else None
+    return L().vrs_render_gaussians(a["mean"], a["cov"], a["op"], a["sh"], a["deg"], a["n"],
+                                    a["views"], a["nv"], opts, a["rgb"], a["depth"], a["tf"],
+                                    a["nc"], a["ws"], a["ws_bytes"], a["max_pairs"], a["status"],
+                                    None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(opts=None), dict(opts=api.make_opts(tile=12)), dict(opts=api.make_opts(tile=64)),
+    dict(opts=api.make_opts(radix_bits=5)), dict(opts=api.make_opts(radix_bits=16)),
+    dict(opts=api.make_opts(extent=0.0)), dict(opts=api.make_opts(lowpass=-1.0)),
+    dict(nv=0), dict(nv=9), dict(views=None), dict(deg=-1), dict(deg=4), dict(n=-1),
+    dict(mean=NUL), dict(cov=NUL), dict(op=NUL), dict(sh=NUL), dict(rgb=NUL), dict(depth=NUL),
+    dict(tf=NUL), dict(nc=NUL), dict(ws=NUL), dict(ws_bytes=16), dict(max_pairs=-1),
+    dict(max_pairs=1 << 30)])
+def test_render_rejects(bad):
+    assert _render(**bad) == EINVAL
+
+
+def test_render_rejects_unequal_views():
+    v = _views()
+    v[1].width = 80
+    assert _render(views=v) == EINVAL
+    v = _views()
+    v[0].fx = 0.0
+    assert _render(views=v) == EINVAL
+
+
+def test_render_workspace_size_zero_on_bad_args():
+    v = _views()
+    assert L().vrs_render_workspace_size(10, 2, v, ctypes.byref(api.make_opts(tile=12)), 10) == 0
+    assert L().vrs_render_workspace_size(10, 2, v, ctypes.byref(api.make_opts(radix_bits=3)), 10) == 0
+    assert L().vrs_render_workspace_size(-1, 2, v, ctypes.byref(api.make_opts()), 10) == 0
+    assert L().vrs_render_workspace_size(10, 9, v, ctypes.byref(api.make_opts()), 10) == 0
+    for r in (4, 6, 8, 11):
+        assert L().vrs_render_workspace_size(10, 2, v, ctypes.byref(api.make_opts(radix_bits=r)), 10) > 0
+
+
+@pytest.mark.parametrize("bad", [dict(opts=None), dict(deg=5), dict(tf=NUL), dict(drgb=NUL),
+                                 dict(dmean=NUL), dict(ws=NUL), dict(ws_bytes=8),
+                                 dict(opts=api.make_opts(tile=7))])
+def test_render_backward_rejects(bad):
+    a = dict(opts=api.make_opts(), deg=0, tf=P, drgb=P, dmean=P, ws=P, ws_bytes=1 << 40)
+    a.update(bad)
+    opts = ctypes.byref(a["opts"]) if a["opts"] is not None else None
+    r = L().vrs_render_gaussians_backward(P, P, P, P, a["deg"], 10, _views(), 2, opts, a["tf"],
+                                          a["drgb"], None, a["dmean"], P, P, P, a["ws"],
+                                          a["ws_bytes"], 100, None)
+    assert r == EINVAL
+
+
+# ------------------------------------------------------------------- splat
+def _splat(**kw):
+    a = dict(pos=P, radius=P, feat=P, np_=10, ch=4, levels=4, views=_views(), nv=2,
+             crops=_crops([(0, 0, 0, 32)]), nc=1, place=None, depth=P, tf=P, pyr=P, ws=P,
+             ws_bytes=1 << 40, max_frags=100)
+    a.update(kw)
+    return L().vrs_splat_points(a["pos"], a["radius"], a["feat"], None, a["np_"], a["ch"],
+                                a["levels"], a["views"], a["nv"], a["crops"], a["nc"], a["place"],
+                                a["depth"], a["tf"], 0.5, 1.05, None, a["pyr"], a["ws"],
+                                a["ws_bytes"], a["max_frags"], P, None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(levels=0), dict(levels=9), dict(nv=0), dict(nv=9), dict(nc=33), dict(nc=-1),
+    dict(crops=_crops([(0, 0, 0, 30)])),           # size not a multiple of 2^(levels-1)
+    dict(crops=_crops([(2, 0, 0, 32)])),           # view out of range
+    dict(crops=_crops([(0, 40, 0, 32)])),          # outside the 64-pixel-wide view
+    dict(crops=_crops([(0, -8, 0, 32)])),
+    dict(crops=_crops([(0, 0, 0, 64)])),           # taller than the view
+    dict(pos=NUL), dict(radius=NUL), dict(feat=NUL), dict(pyr=NUL), dict(ws=NUL),
+    dict(ws_bytes=64), dict(depth=NUL), dict(tf=NUL), dict(np_=-1), dict(max_frags=-1),
+    dict(ch=0)])
+def test_splat_rejects(bad):
+    assert _splat(**bad) == EINVAL
+
+
+def test_splat_unsupported_channels_and_placed_origin():
+    assert _splat(ch=3) == EUNSUP
+    # with a device placement table the host origin is not used, so an
+    # out-of-view host origin passes the host checks (a missing pyramid
+    # then still fails)
+    assert _splat(crops=_crops([(0, 40, 0, 32)]), place=P, pyr=NUL) == EINVAL
+
+
+def test_splat_backward_rejects():
+    base = (P, P, P, None, 10, 4, 4, _views(), 2, _crops([(0, 0, 0, 32)]), 1, None)
+    assert L().vrs_splat_points_backward(*base, None, P, P, P, None, P, 1 << 40, 100, None) == EINVAL
+    assert L().vrs_splat_points_backward(*base, P, P, P, P, None, None, 1 << 40, 100, None) == EINVAL
+    bad = (P, P, P, None, 10, 4, 4, _views(), 2, _crops([(0, 0, 0, 31)]), 1, None)
+    assert L().vrs_splat_points_backward(*bad, P, P, P, P, None, P, 1 << 40, 100, None) == EINVAL
+
+
+def test_place_crops_rejects():
+    v, c = _views(), _crops([(0, 0, 0, 32)])
+    assert L().vrs_place_crops(None, v, 2, c, 1, P, None) == EINVAL
+    assert L().vrs_place_crops(P, v, 2, c, 1, None, None) == EINVAL
+    assert L().vrs_place_crops(P, v, 2, c, 0, P, None) == EINVAL
+    assert L().vrs_place_crops(P, v, 2, _crops([(0, 0, 0, 80)]), 1, P, None) == EINVAL
+    assert L().vrs_place_crops(P, v, 2, _crops([(5, 0, 0, 16)]), 1, P, None) == EINVAL
+
+
+# ----------------------------------------------------------------- decoder
+def _dec(**kw):
+    a = dict(pyr=P, levels=4, per=P, views=_views(), nv=2, crops=_crops([(0, 0, 0, 32)]), nc=1,
+             w=P, dd=api.make_decoder_desc((16, 32)), out=P, ws=P, ws_bytes=1 << 40)
+    a.update(kw)
+    dd = ctypes.byref(a["dd"]) if a["dd"] is not None else None
+    return L().vrs_decode_fovea(a["pyr"], a["levels"], a["per"], a["views"], a["nv"], a["crops"],
+                                a["nc"], None, a["w"], dd, a["out"], a["ws"], a["ws_bytes"], None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dd=None), dict(dd=api.make_decoder_desc(())), dict(dd=api.make_decoder_desc((16, 256))),
+    dict(dd=api.make_decoder_desc((16, 32), dtype=7)), dict(levels=1), dict(levels=9),
+    dict(nc=0), dict(nc=33), dict(crops=_crops([(0, 0, 0, 30)])),
+    dict(crops=_crops([(0, 40, 0, 32)])), dict(crops=_crops([(3, 0, 0, 32)])), dict(pyr=NUL),
+    dict(per=NUL), dict(w=NUL), dict(out=NUL), dict(ws=NUL), dict(ws_bytes=4)])
+def test_decoder_rejects(bad):
+    assert _dec(**bad) == EINVAL
+
+
+def test_decoder_unsupported_and_backward():
+    assert _dec(dd=api.make_decoder_desc((16, 32), in_ch=3)) == EUNSUP
+    dd = ctypes.byref(api.make_decoder_desc((16, 32)))
+    args = (P, 4, P, _views(), 2, _crops([(0, 40, 0, 32)]), 1, None, P, dd, P, P, P, P, P,
+            1 << 40, None)
+    assert L().vrs_decode_fovea_backward(*args) == EINVAL   # crop outside its view
+
+
+# --------------------------------------------------------------- composite
+@pytest.mark.parametrize("bad", [
+    dict(mode=2), dict(mode=0, ring=0.0), dict(mode=1, m=1.0), dict(nv=0), dict(nv=9),
+    dict(W=0), dict(nc=33), dict(crops=_crops([(0, 40, 0, 32)])), dict(crops=_crops([(2, 0, 0, 16)])),
+    dict(P_=NUL), dict(out=NUL), dict(F=NUL)])
+def test_composite_rejects(bad):
+    a = dict(P_=P, nv=2, W=64, H=48, F=P, crops=_crops([(0, 0, 0, 32)]), nc=1, mode=0, ring=8.0,
+             m=0.75, out=P)
+    a.update(bad)
+    r = L().vrs_composite_frame(a["P_"], a["nv"], a["W"], a["H"], a["F"], a["crops"], a["nc"],
+                                None, a["mode"], a["ring"], a["m"], 0.2, a["out"], None)
+    assert r == EINVAL
+    rb = L().vrs_composite_frame_backward(a["P_"], a["nv"], a["W"], a["H"], a["F"], a["crops"],
+                                          a["nc"], None, a["mode"], a["ring"], a["m"], 0.2, P, P,
+                                          P, None)
+    if "out" not in bad:
+        assert rb == EINVAL
+
+
+# ------------------------------------------------------- small entry points
+def test_bake_loss_order_reject():
+    assert L().vrs_bake_gaussians(None, P, P, 10, P, P, None) == EINVAL
+    assert L().vrs_bake_gaussians(P, P, P, -1, P, P, None) == EINVAL
+    assert L().vrs_bake_gaussians_backward(P, P, P, 10, None, None, P, P, P, None) == EINVAL
+    assert L().vrs_bake_gaussians_backward(P, P, P, 10, P, P, P, P, None, None) == EINVAL
+    assert L().vrs_l1_loss(P, P, 0, P, None, 1.0, None) == EINVAL
+    assert L().vrs_l1_loss(None, P, 10, P, None, 1.0, None) == EINVAL
+    assert L().vrs_spatial_order(P, 0, P, P, 1 << 30, None) == EINVAL
+    assert L().vrs_spatial_order(P, 100, P, P, 8, None) == EINVAL
+    assert L().vrs_spatial_order_workspace_size(0) == 0
+
+
+# -------------------------------------------------------------------- plan
+def _plan_desc(**kw):
+    views = _views()
+    crops = _crops([(0, 0, 0, 32), (1, 8, 8, 16)])
+    d = api.PlanDesc()
+    d.n_views, d.views = 2, views
+    d.n_gaussians, d.sh_degree, d.n_points, d.point_channels, d.levels = 100, 3, 200, 4, 4
+    d.n_crops, d.crops = 2, crops
+    d.raster = api.make_opts(tile=16, radix_bits=8)
+    d.decoder = api.make_decoder_desc((16, 32))
+    d.depth_cull, d.cov_min, d.slack = 1, 0.5, 1.05
+    d.blend_mode, d.ring, d.m, d.gamma = 0, 16.0, 0.75, 0.2
+    d.max_pairs, d.max_frags = 1000, 1000
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d, (views, crops)
+
+
+def test_plan_create_and_sizes():
+    d, keep = _plan_desc()
+    h = ctypes.c_void_p()
+    assert L().vrs_plan_create(ctypes.byref(d), ctypes.byref(h)) == api.VRS_OK and h.value
+    for which in (api.WS_RENDER, api.WS_SPLAT, api.WS_DECODER):
+        assert L().vrs_workspace_size(h, which) > 0
+    assert L().vrs_workspace_size(h, 3) == 0 and L().vrs_workspace_size(None, 0) == 0
+    out = api.PlanDesc()
+    assert L().vrs_plan_describe(h, ctypes.byref(out)) == api.VRS_OK
+    assert out.n_crops == 2 and out.crops[1].size == 16 and out.raster.radix_bits == 8
+    assert L().vrs_plan_trace(h, 99, P, P) == EINVAL
+    assert L().vrs_plan_trace(h, 1, P, None) == EINVAL
+    assert L().vrs_plan_trace(h, 0, None, None) == api.VRS_OK
+    assert L().vrs_render_frame(h, None, None, None, 0, None) == EINVAL
+    sc, bf = api.Scene(), api.FrameBuffers()
+    assert L().vrs_render_frame(h, ctypes.byref(sc), P, ctypes.byref(bf), 0, None) == EINVAL
+    assert L().vrs_render_frame(h, ctypes.byref(sc), None, ctypes.byref(bf), 2, None) == EINVAL
+    L().vrs_plan_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_views=0), dict(n_views=9), dict(n_crops=0), dict(n_crops=33), dict(sh_degree=4),
+    dict(levels=0), dict(levels=9), dict(n_gaussians=-1), dict(max_pairs=-1),
+    dict(raster=api.make_opts(tile=24)), dict(raster=api.make_opts(radix_bits=7)),
+    dict(decoder=api.make_decoder_desc((16, 32, 64, 64, 64))),   # deeper than the pyramid
+    dict(blend_mode=3), dict(crops=_crops([(0, 0, 0, 31), (1, 8, 8, 16)]))])
+def test_plan_rejects(bad):
+    d, keep = _plan_desc(**bad)
+    h = ctypes.c_void_p(1)
+    assert L().vrs_plan_create(ctypes.byref(d), ctypes.byref(h)) == EINVAL
+    assert not h.value
+    assert L().vrs_plan_create(None, ctypes.byref(h)) == EINVAL
+
+
+def test_plan_unsupported_channels():
+    d, keep = _plan_desc(point_channels=3)
+    h = ctypes.c_void_p()
+    assert L().vrs_plan_create(ctypes.byref(d), ctypes.byref(h)) == EUNSUP
+
+
+def test_valid_arguments_pass_the_host_checks():
+    """Controls: the same calls with valid arguments get past every host
+    check (here, with no device, they then fail to launch)."""
+    for code in (_render(), _splat(), _dec()):
+        assert code not in (api.VRS_OK, EINVAL, EUNSUP), code
+    r = L().vrs_composite_frame(P, 2, 64, 48, P, _crops([(0, 0, 0, 32)]), 1, None, 0, 8.0, 0.75,
+                                0.2, P, None)
+    assert r not in (api.VRS_OK, EINVAL)

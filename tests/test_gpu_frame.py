@@ -106,3 +106,49 @@ def test_spatial_order_keeps_equal_depth_order():
     assert np.array_equal(got, oids)
     pyr_o = oracle.splat_points(p["pos"], p["radius"], p["feat"], V, D, ci, sc["levels"])
     assert float(np.abs(fr.pyramid.cpu().numpy() - pyr_o).max()) <= 1e-4
+
+
+def test_graph_follows_new_gaze():
+    """One captured frame, replayed with two gaze tables written into the
+    frame's device gaze buffer (no re-capture): each replay equals the eager
+    frame of crops placed at those gazes, bit for bit; the crop origins are
+    the host rule's (clamp(round(gaze - S/2))), and the pyramid equals the
+    reference's splat at those crops (same periphery depth)."""
+    import oracle
+    sc = _scene()
+    W, H = sc["views"][0].width, sc["views"][0].height
+    gA = np.array([[c.gaze_x, c.gaze_y] for c in sc["crops"]], np.float32)
+    gB = gA + np.array([17.3, -9.6], np.float32) * np.array([1, -1, 1, -1, 1], np.float32)[:, None]
+    gB[2] = (3.0, 250.0)                        # pushed against the image border: clamped
+    fr = Frame(sc, decoder_dtype=api.VRS_BF16, tile=16, frag_margin=3.0)
+    eager_A = fr.run().clone()
+    torch.cuda.synchronize()
+    fr.capture()
+
+    def crops_at(g):
+        return [synth.crop_at(c.view, float(x), float(y), c.size, W, H)
+                for c, (x, y) in zip(sc["crops"], g)]
+
+    for g in (gB, gA, gB):
+        fr.set_gaze(g)
+        out = fr.replay().clone()
+        pyr = fr.pyramid.clone()
+        torch.cuda.synchronize()
+        assert fr.status() == 0
+        cr = crops_at(g)
+        place = fr.place.cpu().numpy()
+        assert np.array_equal(place[:, :2], np.array([[c.x0, c.y0] for c in cr]))
+        ref = Frame(dict(sc, crops=cr), decoder_dtype=api.VRS_BF16, tile=16)
+        eager = ref.run().clone()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
+        if g is gA:
+            assert torch.equal(out, eager_A)
+        # the pyramid against the reference, culled by the frame's own
+        # periphery depth and transmittance
+        V, D = synth.views_array(sc["views"]), synth.views_dims(sc["views"])
+        ci, _ = synth.crops_array(cr)
+        p = sc["points"]
+        pyr_o = oracle.splat_points(p["pos"], p["radius"], p["feat"], V, D, ci, sc["levels"],
+                                    ref.depth.cpu().numpy(), ref.tfinal.cpu().numpy())
+        assert float(np.abs(pyr.cpu().numpy() - pyr_o).max()) <= 1e-4

@@ -121,3 +121,27 @@ def test_fullsize_splat_decoder_composite(full):
     out = api.composite_frame(dev(rgb), dev(F_o.astype(np.float32)), crops, api.BLEND_LINEAR, 64.0)
     torch.cuda.synchronize()
     assert float(np.abs(out.cpu().numpy() - out_o).max()) <= 1e-5
+
+
+@pytest.mark.parametrize("radix", [4, 6, 11])
+def test_fullsize_radix_width_keeps_lists(full, radix):
+    """At tile 16 (576 super-tiles, 10-bit ids) every digit width gives the
+    8-bit sort's tile lists and images bit for bit (the 8-bit lists are the
+    reference's, above)."""
+    sc, g = full["sc"], full["sc"]["gaussians"]
+    views = sc["views"]
+    pairs = pair_total(full["rect"], full["D"], 16)
+    outs = []
+    for r in (8, radix):
+        opts = api.make_opts(**dict(sc["raster"], tile=16, radix_bits=r))
+        ws = api.RenderWorkspace(g["n"], views, opts, pairs + 1024)
+        out = api.render_gaussians(dev(g["mean"]), dev(full["cov"]), dev(full["op"]),
+                                   dev(g["sh"]), 3, views, opts, ws)
+        torch.cuda.synchronize()
+        assert int(ws.status.item()) == 0 and ws.pair_count() == pairs
+        ranges, ids = ws.tile_lists()
+        outs.append((ranges, ids, {k: v.cpu() for k, v in out.items()}))
+    (r8, i8, o8), (rr, ir, orr) = outs
+    assert np.array_equal(r8, rr) and np.array_equal(i8, ir)
+    for k in o8:
+        assert torch.equal(o8[k], orr[k]), k

@@ -125,3 +125,25 @@ def test_bake_parity():
     scale = cov_o[[0, 3, 5]].max(0)
     assert (np.abs(cov.cpu().numpy() - cov_o) <= 1e-5 * scale[None]).all()
     np.testing.assert_allclose(op.cpu().numpy(), op_o, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("tile,radix", [(8, 4), (8, 6), (16, 11), (32, 4)])
+def test_radix_width_keeps_lists(tile, radix):
+    """Every digit width the autotuner may pick sorts to the same lists (the
+    reference's, bit for bit) and images (bit-identical to 8-bit digits):
+    4-bit digits take 8 passes over the depth keys and two over the
+    super-tile ids here, 11-bit digits three and one."""
+    sc = synth.small_scene(25, n_gauss=4000, width=256, height=224, f=220.0, sh_degree=1,
+                           n_views=2)
+    g, views = sc["gaussians"], sc["views"]
+    cov, op = baked(g)
+    raster = dict(sc["raster"], tile=tile, radix_bits=radix)
+    o, rect, zb = oracle_render(g, cov, op, views, raster)
+    total = pair_total(rect, synth.views_dims(views), tile)
+    gpu, ws = gpu_render(g, cov, op, views, raster, max_pairs=total + 64)
+    assert int(ws.status.item()) == 0
+    check_render(o, gpu)
+    _lists_equal(ws, rect, zb, views, tile)
+    ref, _ = gpu_render(g, cov, op, views, dict(raster, radix_bits=8), max_pairs=total + 64)
+    for k in ref:
+        assert np.array_equal(ref[k], gpu[k]), k
