@@ -175,14 +175,158 @@ def blend_work(frame):
     return 14 * evals + 11 * contrib, evals, contrib
 
 
+def decoder_flops(crops, widths, in_ch=4):
+    """Algorithmic flops of the decoder per frame: per crop and level l
+    (size S_l = S / 2^l) one 3x3 gated convolution producing 2 K_l channels
+    (feature and gate halves) from C_l = in_ch + K_{l+1} (+3 at level 0)
+    inputs, 2 * 9 * C_l * 2 K_l flops per output pixel, plus the 1x1 RGB
+    head, 2 * 3 * K_0 per pixel."""
+    n = len(widths)
+    tot = 0
+    for c in crops:
+        for l in range(n):
+            S = c.size >> l
+            cin = in_ch + (widths[l + 1] if l + 1 < n else 0) + (3 if l == 0 else 0)
+            tot += 2 * 9 * cin * 2 * widths[l] * S * S
+        tot += 2 * 3 * widths[0] * c.size * c.size
+    return tot
+
+
+def replay_ms(frame, warmup=3, steps=10):
+    """Milliseconds per frame of the captured frame's graph replay."""
+    import torch
+    frame.capture()
+    for _ in range(warmup):
+        frame.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        frame.replay()
+    torch.cuda.synchronize()
+    assert frame.status() == 0, f"device status {frame.status()}"
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def free():
+    """Return the device memory of frames the caller has dropped."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def secondary_and_standalone(scene, tile, radix, steps):
+    """The paper's own VR setting (one 512 crop per eye at the view centre,
+    d_f = 256) on the full-frame scene, and the periphery (config 1) and
+    foveal (config 2) workloads on their own."""
+    from paper_2410_17932_amd import api, synth
+    from paper_2410_17932_amd.frame import Frame
+    out = {}
+    W, H = scene["views"][0].width, scene["views"][0].height
+    vr = dict(scene, crops=[synth.crop_at(v, W / 2, H / 2, 512, W, H) for v in range(2)])
+    fr = Frame(vr, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix)
+    ms = replay_ms(fr, steps=steps)
+    out["secondary_vr_frame"] = dict(workload="one 512 crop per eye (d_f = 256), rest as the "
+                                     "full frame", ms_per_frame=round(ms, 4),
+                                     frames_per_s=round(1e3 / ms, 1))
+    del fr
+    free()
+    sc1 = synth.config(1)
+    fr = Frame(sc1, tile=tile, radix_bits=radix)
+    ms = replay_ms(fr, steps=steps)
+    out["config1_periphery"] = dict(workload="500k Gaussians SH3, stereo 2016x2240, periphery "
+                                    "only", ms_per_frame=round(ms, 4),
+                                    frames_per_s=round(1e3 / ms, 1), tile_pairs=fr.pairs)
+    del fr
+    free()
+    sc2 = synth.config(2)
+    fr = Frame(sc2, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix)
+    fr.run()
+    st = {k: stage_ms(fr, k, steps) for k in ("splat", "decoder")}
+    out["config2_fovea"] = dict(workload="5M points, one 512 crop at the left-eye centre culled "
+                                "against the periphery, decoder 16/32/64/64 BF16",
+                                splat_ms=round(st["splat"], 4), decoder_ms=round(st["decoder"], 4),
+                                fovea_ms=round(st["splat"] + st["decoder"], 4),
+                                fragments=fr.frags)
+    del fr
+    free()
+    return out
+
+
+def table3_and_fig2(scene, tile, radix, steps):
+    """Synthetic reproductions of the paper's performance ablation (Table 3:
+    depth culling off, full-width finest decoder level, combination with and
+    without the Sobel edge term) and scaling curves (Fig. 2: periphery time
+    against the number of Gaussians, foveal time against the crop size)."""
+    import numpy as np
+    from paper_2410_17932_amd import api, synth
+    from paper_2410_17932_amd.frame import Frame
+    t3 = {}
+    fr = Frame(scene, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix)
+    fr.run()
+    base = {k: stage_ms(fr, k, steps) for k in ("splat", "decoder", "composite")}
+    frags_on = fr.frags
+    del fr
+    free()
+    fr = Frame(scene, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix, cull=False,
+               frag_margin=1.1)
+    fr.run()
+    t3["depth_cull"] = dict(on_splat_ms=round(base["splat"], 4),
+                            off_splat_ms=round(stage_ms(fr, "splat", steps), 4),
+                            on_fragments=frags_on, off_fragments=fr.frags)
+    del fr
+    free()
+    wide = dict(scene, decoder=synth.decoder_weights(np.random.default_rng(7), (32, 32, 64, 64), 4))
+    fr = Frame(wide, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix)
+    fr.run()
+    t3["finest_decoder_width"] = dict(width16_ms=round(base["decoder"], 4),
+                                      width32_ms=round(stage_ms(fr, "decoder", steps), 4))
+    del fr
+    free()
+    comp = dict(linear_ring_ms=round(base["composite"], 4))
+    for name, gamma in (("paper_edge_ms", 0.2), ("paper_no_edge_ms", 0.0)):
+        fr = Frame(scene, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix,
+                   mode=api.BLEND_PAPER, gamma=gamma)
+        fr.run()
+        comp[name] = round(stage_ms(fr, "composite", steps), 4)
+        del fr
+        free()
+    t3["combination"] = comp
+    # Fig. 2: periphery against the number of Gaussians (stereo 2016x2240)
+    views = scene["views"]
+    g_sweep = {}
+    for n in (100_000, 250_000, 500_000, 1_000_000):
+        g = synth.gaussians(np.random.default_rng(n), n, 3)
+        sc = dict(gaussians=g, points=None, decoder=None, views=views, crops=[],
+                  levels=4, raster=dict(scene["raster"]))
+        fr = Frame(sc, tile=tile, radix_bits=radix)
+        g_sweep[str(n)] = round(replay_ms(fr, steps=steps), 4)
+        del fr
+        free()
+    # ... and the fovea against the crop size (one crop per eye)
+    W, H = views[0].width, views[0].height
+    c_sweep = {}
+    for S in (256, 512, 768, 1024):
+        sc = dict(scene, crops=[synth.crop_at(v, W / 2, H / 2, S, W, H) for v in range(2)])
+        fr = Frame(sc, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix)
+        fr.run()
+        c_sweep[str(S)] = round(stage_ms(fr, "splat", steps) + stage_ms(fr, "decoder", steps), 4)
+        del fr
+        free()
+    return dict(table3=t3, fig2=dict(periphery_ms_by_gaussians=g_sweep,
+                                     fovea_ms_by_crop_size=c_sweep))
+
+
 def profile_pass(args):
-    """A short eager run for hardware-counter passes: two frames, then a
-    plain device copy of known size for the HBM byte-counter calibration."""
+    """A short eager run for hardware-counter passes: two inference frames,
+    then a plain device copy of known size for the HBM byte-counter
+    calibration."""
     import torch
     from paper_2410_17932_amd import api, synth
     from paper_2410_17932_amd.frame import Frame
     scene = synth.config(args.config)
-    fr = Frame(scene, decoder_dtype=api.VRS_BF16, tile=args.tile or 32)
+    fr = Frame(scene, decoder_dtype=api.VRS_BF16, tile=args.tile or 32, radix_bits=args.radix)
     for _ in range(2):
         fr.run()
     torch.cuda.synchronize()
@@ -201,7 +345,10 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--tile", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary frame, standalone configs and sweeps")
+    ap.add_argument("--tile", type=int, default=0, help="0 = autotune tile and radix")
+    ap.add_argument("--radix", type=int, default=8)
     ap.add_argument("--profile-pass", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -220,7 +367,12 @@ def main():
     scene = synth.config(args.config)
     log(f"scene generated in {time.perf_counter() - t0:.1f} s")
     fr = Frame(scene, decoder_dtype=api.VRS_BF16)
-    tune = fr.autotune() if args.tile == 0 else (fr._plan(args.tile) or dict(tile=args.tile))
+    if args.tile == 0:
+        tune = fr.autotune()
+    else:
+        fr._plan(args.tile, args.radix)
+        tune = dict(tile=args.tile, radix_bits=args.radix)
+    tile, radix = tune["tile"], tune["radix_bits"]
     log(f"autotune: {tune}; pairs {fr.pairs}, fragments {fr.frags}")
     fr.capture()
     for _ in range(args.warmup):
@@ -235,8 +387,8 @@ def main():
     fps = args.steps / dt
     assert fr.status() == 0, f"device status {fr.status()}"
     log(f"graph replay: {ms:.3f} ms/frame, {fps:.1f} frames/s")
-    # per-stage kernel time over K eager frames (library-recorded HIP events
-    # on the frame's stream)
+    # per-stage kernel time over K eager inference frames (library-recorded
+    # HIP events on the frame's stream)
     stages = {}
     for st in ("gs_preprocess", "gs_depth_sort", "gs_emit", "gs_sort", "gs_blend", "splat",
                "decoder", "composite"):
@@ -252,15 +404,23 @@ def main():
                                              "paper_2410_17932_amd/csrc/gs_forward.hip"),
                     work=dict(flops=flops, evaluations=evals, contributions=contrib,
                               ms=round(stages["gs_blend"], 4)))
+    # decoder on the matrix cores: algorithmic flops over its stage time
+    dflops = decoder_flops(scene["crops"], scene["decoder"]["widths"])
+    dtf = dflops / (stages["decoder"] * 1e-3) / 1e12
+    decoder_mfma = dict(kernel="k_dec_conv (gated 3x3 conv, BF16 MFMA)", bound="mfma",
+                        achieved=round(dtf, 2), peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=round(dtf / BF16_MFMA_PEAK_TFLOPS, 4), flops_per_frame=dflops,
+                        ms=round(stages["decoder"], 4))
     # rasterizer HBM rate: the periphery's tile binning (its HBM-bound stage).
-    # Algorithmic bytes: per (super-tile, Gaussian) pair and 8-bit sort pass
-    # 4 B read by the digit count and 2 x 12 B (key + value) by the scatter,
-    # then 4 B (run bounds) + 8 B (unit counts) + 8 B (scatter) read; per
-    # (tile, Gaussian) pair the 4 B index written to its list.
+    # Algorithmic bytes: per (super-tile, Gaussian) pair and sort pass 4 B
+    # read by the digit count and 2 x 12 B (key + value) by the scatter, then
+    # 4 B (run bounds) + 8 B (unit counts) + 8 B (scatter) read; per (tile,
+    # Gaussian) pair the 4 B index written to its list.
     supers = fr.rws.super_pair_count()
     sxn, syn = -(-fr.rws.layout.tiles_x // 8), -(-fr.rws.layout.tiles_y // 8)
     st_total = sxn * syn * len(fr.views)
-    st_passes = max(1, (max(1, (st_total - 1).bit_length()) + 7) // 8)
+    st_bits = max(1, (st_total - 1).bit_length())
+    st_passes = max(1, -(-st_bits // radix))
     bin_bytes = supers * (28 * st_passes + 20) + fr.pairs * 4
     bin_gbs = bin_bytes / (stages["gs_sort"] * 1e-3) / 1e9
     result = dict(metric="stereo foveated frames/s @2016x2240/eye; rasterizer HBM GB/s vs peak",
@@ -270,14 +430,15 @@ def main():
                   config=dict(workload=f"config {args.config}: stereo 2016x2240/eye, 500k "
                               "Gaussians SH3, 5M neural points, 8 crops/eye 256..640 px, "
                               "decoder 16/32/64/64 BF16, hipGraph replay",
-                              tile=tune["tile"], pairs=fr.pairs, fragments=fr.frags),
-                  roofline=roofline,
+                              tile=tile, radix_bits=radix, pairs=fr.pairs, fragments=fr.frags),
+                  roofline=roofline, decoder_mfma=decoder_mfma,
                   rasterizer_hbm=dict(stage="periphery tile binning (super-tile sort, "
                                       "count, scatter)", achieved=round(bin_gbs, 1),
                                       peak=HBM_PEAK_GBS, unit="GB/s",
                                       frac=round(bin_gbs / HBM_PEAK_GBS, 4),
                                       bytes=bin_bytes, super_pairs=supers),
-                  stages_ms={k: round(v, 4) for k, v in stages.items()})
+                  stages_ms={k: round(v, 4) for k, v in stages.items()},
+                  autotune=tune)
     if not args.no_plain:
         pf = PlainFrame(fr)
         for _ in range(2):
@@ -291,6 +452,17 @@ def main():
         pms = (time.perf_counter() - t0) / k * 1e3
         result["plain_fp32_eager"] = dict(ms_per_frame=round(pms, 4), frames_per_s=round(1e3 / pms, 3))
         log(f"plain FP32 eager: {pms:.3f} ms/frame")
+        del pf
+    del fr
+    free()
+    if not args.no_extras:
+        k = max(5, args.steps // 3)
+        result.update(secondary_and_standalone(scene, tile, radix, k))
+        log("secondary / standalone:", json.dumps({x: result[x] for x in
+                                                   ("secondary_vr_frame", "config1_periphery",
+                                                    "config2_fovea")}))
+        result.update(table3_and_fig2(scene, tile, radix, k))
+        log("table 3 / fig 2:", json.dumps({x: result[x] for x in ("table3", "fig2")}))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(scene)
         result["cpu_baseline"] = cb

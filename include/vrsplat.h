@@ -383,7 +383,7 @@ typedef struct {
   int64_t n_points;
   int32_t point_channels;       /* 4 */
   int32_t levels;               /* pyramid layers */
-  int32_t n_crops;
+  int32_t n_crops;              /* 0: the frame is the periphery alone */
   const vrs_crop* crops;        /* [n_crops]: view and size (origins are the
                                    frame's gaze placement, or these) */
   vrs_raster_opts raster;
@@ -400,7 +400,8 @@ enum { VRS_WS_RENDER = 0, VRS_WS_SPLAT = 1, VRS_WS_DECODER = 2 };
  * for point_channels other than 4; *plan is NULL then. */
 vrs_status vrs_plan_create(const vrs_plan_desc* desc, vrs_plan** plan);
 void vrs_plan_destroy(vrs_plan* plan);
-/* Workspace bytes of the frame's stage `which` (VRS_WS_*), 0 if invalid. */
+/* Workspace bytes of the frame's stage `which` (VRS_WS_*); 0 if invalid,
+ * and for the foveal stages of a plan without crops. */
 size_t vrs_workspace_size(const vrs_plan* plan, int which);
 /* Copy of the plan's descriptor (its pointers refer to the plan's copies). */
 vrs_status vrs_plan_describe(const vrs_plan* plan, vrs_plan_desc* out);

@@ -72,7 +72,9 @@ __device__ inline float blend_mask(const CompArgs& a, int k, const float* F, int
   }
   const float rn = clamp01(r / df);
   const float fp = (rn - a.m) / (1.0f - a.m);
-  sobel(F, a.S[k], lx, ly, gx, gy);
+  // gamma = 0: Eq. 5 without the edge term (Eq. 4), no Sobel work
+  gx = gy = 0.0f;
+  if (a.gamma != 0.0f) sobel(F, a.S[k], lx, ly, gx, gy);
   const float fe = 0.25f * sqrtf(gx * gx + gy * gy);
   u_out = fp + a.gamma * fe;
   return 1.0f - smootherstep(clamp01(u_out));

@@ -36,8 +36,10 @@ extern "C" vrs_status vrs_plan_create(const vrs_plan_desc* desc, vrs_plan** out)
   *out = nullptr;
   const vrs_plan_desc& d = *desc;
   if (d.n_views < 1 || d.n_views > VRS_MAX_VIEWS || !d.views) return VRS_EINVAL;
-  if (d.n_crops < 1 || d.n_crops > VRS_MAX_CROPS || !d.crops) return VRS_EINVAL;
-  if (d.n_gaussians < 0 || d.n_points < 0 || d.sh_degree < 0 || d.sh_degree > 3) return VRS_EINVAL;
+  if (d.n_crops < 0 || d.n_crops > VRS_MAX_CROPS || (d.n_crops > 0 && !d.crops))
+    return VRS_EINVAL;
+  if (d.n_gaussians < 0 || d.n_points < 0 || d.sh_degree < 0 || d.sh_degree > 3)
+    return VRS_EINVAL;
   if (d.levels < 1 || d.levels > VRS_MAX_LEVELS || !decoder_ok(d.decoder, d.levels))
     return VRS_EINVAL;
   if (d.point_channels != 4) return VRS_EUNSUPPORTED;
@@ -47,7 +49,7 @@ extern "C" vrs_status vrs_plan_create(const vrs_plan_desc* desc, vrs_plan** out)
   if (!p) return VRS_EINVAL;
   p->d = d;
   p->views.assign(d.views, d.views + d.n_views);
-  p->crops.assign(d.crops, d.crops + d.n_crops);
+  if (d.n_crops > 0) p->crops.assign(d.crops, d.crops + d.n_crops);
   p->d.views = p->views.data();
   p->d.crops = p->crops.data();
   for (int s = 0; s < vrs::kTraceStages; ++s) p->trace.start[s] = p->trace.stop[s] = nullptr;
@@ -55,10 +57,15 @@ extern "C" vrs_status vrs_plan_create(const vrs_plan_desc* desc, vrs_plan** out)
   // radix, crop sizes against the views and the pyramid depth, decoder)
   p->ws[VRS_WS_RENDER] = vrs_render_workspace_size(d.n_gaussians, d.n_views, p->d.views,
                                                    &d.raster, d.max_pairs);
-  p->ws[VRS_WS_SPLAT] = vrs_splat_workspace_size(d.n_points, d.n_views, p->d.views, p->d.crops,
-                                                 d.n_crops, d.levels, d.max_frags);
-  p->ws[VRS_WS_DECODER] = vrs_decoder_workspace_size(&d.decoder, p->d.crops, d.n_crops);
-  if (!p->ws[0] || !p->ws[1] || !p->ws[2]) {
+  // (a plan without crops renders the periphery alone: no foveal workspaces)
+  const bool fovea = d.n_crops > 0;
+  p->ws[VRS_WS_SPLAT] = fovea ? vrs_splat_workspace_size(d.n_points, d.n_views, p->d.views,
+                                                         p->d.crops, d.n_crops, d.levels,
+                                                         d.max_frags)
+                              : 0;
+  p->ws[VRS_WS_DECODER] = fovea ? vrs_decoder_workspace_size(&d.decoder, p->d.crops, d.n_crops)
+                                : 0;
+  if (!p->ws[0] || (fovea && (!p->ws[1] || !p->ws[2]))) {
     delete p;
     return VRS_EINVAL;
   }
@@ -83,7 +90,8 @@ extern "C" vrs_status vrs_plan_trace(vrs_plan* plan, int stage, void* start_even
                                      void* stop_event) {
   if (!plan || stage < VRS_TRACE_OFF || stage > VRS_TRACE_GS_DEPTH_SORT) return VRS_EINVAL;
   if (stage == VRS_TRACE_OFF) {
-    for (int s = 0; s < vrs::kTraceStages; ++s) plan->trace.start[s] = plan->trace.stop[s] = nullptr;
+    for (int s = 0; s < vrs::kTraceStages; ++s)
+      plan->trace.start[s] = plan->trace.stop[s] = nullptr;
     return VRS_OK;
   }
   if ((start_event == nullptr) != (stop_event == nullptr)) return VRS_EINVAL;
@@ -99,7 +107,9 @@ extern "C" vrs_status vrs_render_frame(const vrs_plan* plan, const vrs_scene* sc
   if (flags & ~VRS_FRAME_STATS) return VRS_EINVAL;
   const vrs_plan_desc& d = plan->d;
   if (gaze && !b->place) return VRS_EINVAL;
-  if (!b->ws_render || !b->ws_splat || !b->ws_decoder || !b->pyramid || !b->fovea_rgb)
+  const bool fovea = d.n_crops > 0;
+  if (!b->ws_render ||
+      (fovea && (!b->ws_splat || !b->ws_decoder || !b->pyramid || !b->fovea_rgb)))
     return VRS_EINVAL;
   const vrs::Trace* tr = &plan->trace;
   const int W = d.views[0].width, H = d.views[0].height;
@@ -108,7 +118,7 @@ extern "C" vrs_status vrs_render_frame(const vrs_plan* plan, const vrs_scene* sc
                                   b->t_final, b->n_contrib, b->ws_render, plan->ws[VRS_WS_RENDER],
                                   d.max_pairs, b->status_render, stream,
                                   (flags & VRS_FRAME_STATS) ? vrs::kRenderStats : 0, tr);
-  if (r != VRS_OK) return r;
+  if (r != VRS_OK || !fovea) return r;
   // the gaze is read here, after the periphery
   const vrs_crop_place* place = nullptr;
   if (gaze) {

@@ -36,19 +36,29 @@ class Frame:
                  spatial_order: bool = True):
         g, p = scene["gaussians"], scene["points"]
         self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
+        # without points or crops the frame is the periphery alone
+        self.fovea_on = bool(self.crops) and p is not None
+        if not self.fovea_on:
+            self.crops = []
         self.sh_degree = g["sh_degree"]
         self.mode, self.ring, self.m, self.gamma, self.cull = mode, ring, m, gamma, cull
         self.decoder_dtype = decoder_dtype
-        self.widths = scene["decoder"]["widths"]
+        self.widths = scene["decoder"]["widths"] if scene.get("decoder") else (16, 32, 64, 64)
         self.raster = dict(scene["raster"], tile=tile, radix_bits=radix_bits)
         # primitives resident in HBM; attributes baked once (Sec. 4 "Inference")
         self.mean = _dev(g["mean"])
         self.sh = _dev(g["sh"])
         self.cov, self.opacity = api.bake_gaussians(_dev(g["logscale"]), _dev(g["quat"]),
                                                     _dev(g["logit"]))
+        self.pos = self.radius = self.feat = self.point_ids = self.weights = None
+        self.n, self.np = g["n"], p["n"] if self.fovea_on else 0
+        self.pair_margin, self.frag_margin = pair_margin, frag_margin
+        self.gaze = self.place = None
+        if not self.fovea_on:
+            self._plan(tile, radix_bits)
+            return
         self.pos, self.radius = _dev(p["pos"]), _dev(p["radius"])
         self.feat = _dev(p["feat"].view(np.int16))
-        self.point_ids = None
         if spatial_order:
             # storage layout of the static point cloud: Morton order, so the
             # depth cull's per-point reads of depth and T' share cache lines;
@@ -67,8 +77,6 @@ class Frame:
         # captured frame follows set_gaze() without being captured again
         self.gaze = _dev(np.array([[c.gaze_x, c.gaze_y] for c in self.crops], np.float32))
         self.place = api.crop_places(len(self.crops))
-        self.n, self.np = g["n"], p["n"]
-        self.pair_margin, self.frag_margin = pair_margin, frag_margin
         self._plan(tile, radix_bits)
 
     # ------------------------------------------------------------ planning
@@ -98,6 +106,34 @@ class Frame:
                                        int(self.pairs * self.pair_margin) + 4096)
         api.render_gaussians(self.mean, self.cov, self.opacity, self.sh, self.sh_degree,
                              self.views, self.opts, self.rws, r_out)
+        self.frags = 0
+        self.pyramid = self.fovea = None
+        if self.fovea_on:
+            self._plan_fovea(dev)
+        self.plan = api.Plan(self.views, self.crops, self.n, self.sh_degree, self.np,
+                             self.levels, self.opts, self.widths, self.decoder_dtype,
+                             self.rws.max_pairs, self.sws.max_frags if self.sws else 0, self.cull,
+                             mode=self.mode, ring=self.ring, m=self.m, gamma=self.gamma)
+        for which, w in ((api.WS_RENDER, self.rws), (api.WS_SPLAT, self.sws),
+                         (api.WS_DECODER, self.dws)):
+            assert self.plan.workspace_size(which) == (w.buf.numel() if w else 0)
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self.c_scene = api.Scene(
+            mean=ptr(self.mean), cov=ptr(self.cov), opacity=ptr(self.opacity), sh=ptr(self.sh),
+            pos=ptr(self.pos), radius=ptr(self.radius), feat=ptr(self.feat), point_opacity=None,
+            point_ids=ptr(self.point_ids), decoder_weights=ptr(self.weights))
+        self.c_buf = api.FrameBuffers(
+            rgb=ptr(self.rgb), depth=ptr(self.depth), t_final=ptr(self.tfinal),
+            n_contrib=ptr(self.ncontrib), pyramid=ptr(self.pyramid), fovea_rgb=ptr(self.fovea),
+            place=ptr(self.place), ws_render=ptr(self.rws.buf),
+            ws_splat=ptr(self.sws.buf) if self.sws else None,
+            ws_decoder=ptr(self.dws.buf) if self.dws else None,
+            status_render=ptr(self.rws.status),
+            status_splat=ptr(self.sws.status) if self.sws else None)
+        torch.cuda.synchronize()
+        self.graph = None
+
+    def _plan_fovea(self, dev):
         P = api.pyramid_pixels(self.crops, self.levels)
         self.pyramid = torch.empty((P, 4), device=dev)
         sws = api.SplatWorkspace(self.np, self.views, self.crops, self.levels, 1)
@@ -112,26 +148,6 @@ class Frame:
                                       int(self.frags * self.frag_margin) + 4096)
         self.dws = api.DecoderWorkspace(self.widths, self.crops, self.decoder_dtype)
         self.fovea = torch.empty(api.fovea_elements(self.crops), device=dev)
-        self.plan = api.Plan(self.views, self.crops, self.n, self.sh_degree, self.np,
-                             self.levels, self.opts, self.widths, self.decoder_dtype,
-                             self.rws.max_pairs, self.sws.max_frags, self.cull,
-                             mode=self.mode, ring=self.ring, m=self.m, gamma=self.gamma)
-        for which, w in ((api.WS_RENDER, self.rws), (api.WS_SPLAT, self.sws),
-                         (api.WS_DECODER, self.dws)):
-            assert self.plan.workspace_size(which) == w.buf.numel()
-        ptr = lambda t: None if t is None else t.data_ptr()
-        self.c_scene = api.Scene(
-            mean=ptr(self.mean), cov=ptr(self.cov), opacity=ptr(self.opacity), sh=ptr(self.sh),
-            pos=ptr(self.pos), radius=ptr(self.radius), feat=ptr(self.feat), point_opacity=None,
-            point_ids=ptr(self.point_ids), decoder_weights=ptr(self.weights))
-        self.c_buf = api.FrameBuffers(
-            rgb=ptr(self.rgb), depth=ptr(self.depth), t_final=ptr(self.tfinal),
-            n_contrib=ptr(self.ncontrib), pyramid=ptr(self.pyramid), fovea_rgb=ptr(self.fovea),
-            place=ptr(self.place), ws_render=ptr(self.rws.buf), ws_splat=ptr(self.sws.buf),
-            ws_decoder=ptr(self.dws.buf), status_render=ptr(self.rws.status),
-            status_splat=ptr(self.sws.status))
-        torch.cuda.synchronize()
-        self.graph = None
 
     def set_gaze(self, gaze):
         """New fixation points [n_crops][2] (view pixels) for the next frames:
@@ -168,7 +184,7 @@ class Frame:
         return self.out
 
     def status(self) -> int:
-        return max(int(self.rws.status.item()), int(self.sws.status.item()))
+        return max(int(self.rws.status.item()), int(self.sws.status.item()) if self.sws else 0)
 
     # ----------------------------------------------------------- autotune
     def autotune(self, tiles=(8, 16, 32), radix=(4, 6, 8, 11), reps: int = 5) -> dict:

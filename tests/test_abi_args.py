@@ -243,7 +243,7 @@ def test_plan_create_and_sizes():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n_views=0), dict(n_views=9), dict(n_crops=0), dict(n_crops=33), dict(sh_degree=4),
+    dict(n_views=0), dict(n_views=9), dict(n_crops=-1), dict(n_crops=33), dict(sh_degree=4),
     dict(levels=0), dict(levels=9), dict(n_gaussians=-1), dict(max_pairs=-1),
     dict(raster=api.make_opts(tile=24)), dict(raster=api.make_opts(radix_bits=7)),
     dict(decoder=api.make_decoder_desc((16, 32, 64, 64, 64))),   # deeper than the pyramid
@@ -254,6 +254,16 @@ def test_plan_rejects(bad):
     assert L().vrs_plan_create(ctypes.byref(d), ctypes.byref(h)) == EINVAL
     assert not h.value
     assert L().vrs_plan_create(None, ctypes.byref(h)) == EINVAL
+
+
+def test_plan_without_crops_is_the_periphery_alone():
+    d, keep = _plan_desc(n_crops=0)
+    h = ctypes.c_void_p()
+    assert L().vrs_plan_create(ctypes.byref(d), ctypes.byref(h)) == api.VRS_OK
+    assert L().vrs_workspace_size(h, api.WS_RENDER) > 0
+    assert L().vrs_workspace_size(h, api.WS_SPLAT) == 0
+    assert L().vrs_workspace_size(h, api.WS_DECODER) == 0
+    L().vrs_plan_destroy(h)
 
 
 def test_plan_unsupported_channels():
