@@ -56,7 +56,9 @@ def lib():
         l.orc_tile_lists.argtypes = [_i64, _int, _I, _int, _I, _U, _i64, _I, _L, _vp]
         l.orc_tile_lists.restype = _i64
         l.orc_render.argtypes = [_i64, _int, _I, _int, _I, _U, _D, _D, _i64, _vp,
-                                 _D, _D, _D, _I, _D, _I]
+                                 _D, _D, _D, _I, _D, _I, _vp, _vp, _vp]
+        l.orc_gauss_pixdepth32.argtypes = [_i64, _F, _F, _int, _F, _I, _F]
+        l.orc_gauss_pixdepth64.argtypes = [_i64, _F, _F, _int, _F, _I, _D]
         l.orc_pyramid_pixels.argtypes = [_int, _I, _int]
         l.orc_pyramid_pixels.restype = _i64
         l.orc_point_lists.argtypes = [_i64, _F, _F, _int, _F, _I, _int, _I, _int, _vp, _vp,
@@ -143,20 +145,41 @@ def tile_lists(rect, zbits, dims, tile, sel):
     return off, ids[:off[-1]]
 
 
+def gauss_pixdepth(mean, cov, views, dims):
+    """Per-pixel depth coefficients of every (view, Gaussian) for the
+    per-pixel order (Sec. 3.2): (single-precision [v][n][9] decision mirror,
+    double-precision [v][n][9] values), see orc_gauss_pixdepth32."""
+    n = mean.shape[1]
+    nv = views.shape[0]
+    c32 = np.zeros((nv, n, 9), np.float32)
+    c64 = np.zeros((nv, n, 9))
+    args = (n, _c(mean, np.float32), _c(cov, np.float32), nv, _c(views, np.float32),
+            _c(dims, np.int32))
+    lib().orc_gauss_pixdepth32(*args, c32)
+    lib().orc_gauss_pixdepth64(*args, c64)
+    return c32, c64
+
+
 def render(rect, zbits, rec, dims, tile=16, alpha_clamp=0.99, alpha_min=1 / 255, t_min=1e-4,
-           bg=(0.0, 0.0, 0.0), pix=None):
+           bg=(0.0, 0.0, 0.0), pix=None, per_pixel=None):
     """Blend.  With ``pix`` None: dict of full images rgb [v][3][H][W],
     depth/tfinal/margin [v][H][W], ncontrib [v][H][W]; else per-pixel arrays
-    for pix [n][3] = (view, x, y)."""
+    for pix [n][3] = (view, x, y).  per_pixel = (coef32, coef64, views):
+    the per-pixel order (gauss_pixdepth's coefficients, the views array)."""
     nv, n = zbits.shape
     dims = _c(dims, np.int32)
+    pp = (None, None, None)
+    if per_pixel is not None:
+        c32, c64, vw = per_pixel
+        keep = (_c(c32, np.float32), _c(c64, np.float64), _c(vw, np.float32))
+        pp = tuple(_ptr(a) for a in keep)
     opts = np.array([alpha_clamp, alpha_min, t_min, *bg], np.float64)
     if pix is None:
         npix = int(sum(int(w) * int(h) for w, h in dims))
-        pp = None
+        pixarr = None
     else:
-        pp = _c(pix, np.int32).reshape(-1, 3)
-        npix = pp.shape[0]
+        pixarr = _c(pix, np.int32).reshape(-1, 3)
+        npix = pixarr.shape[0]
     rgb = np.zeros((npix, 3))
     depth = np.zeros(npix)
     tf = np.zeros(npix)
@@ -164,7 +187,8 @@ def render(rect, zbits, rec, dims, tile=16, alpha_clamp=0.99, alpha_min=1 / 255,
     mg = np.zeros(npix)
     ev = np.zeros(npix, np.int32)
     lib().orc_render(n, nv, dims, tile, _c(rect, np.int32), _c(zbits, np.uint32),
-                     _c(rec, np.float64), opts, npix, _ptr(pp), rgb, depth, tf, nc, mg, ev)
+                     _c(rec, np.float64), opts, npix, _ptr(pixarr), rgb, depth, tf, nc, mg, ev,
+                     *pp)
     if pix is not None:
         return dict(rgb=rgb, depth=depth, tfinal=tf, ncontrib=nc, margin=mg, evals=ev)
     out = dict(rgb=[], depth=[], tfinal=[], ncontrib=[], margin=[], evals=[])
@@ -179,8 +203,31 @@ def render(rect, zbits, rec, dims, tile=16, alpha_clamp=0.99, alpha_min=1 / 255,
     return {k: np.stack(v) for k, v in out.items()}
 
 
+def _pix_order(c32, c64, view_row, x, y, ids):
+    """Per-pixel order of ids at pixel (x, y) (see orc_gauss_pixdepth32):
+    (ids sorted by (order-preserving bits of the single-precision key,
+    index), their double-precision z*)."""
+    f = np.float32
+    fx, fy, cx, cy = (f(view_row[k]) for k in range(4))
+    u = (f(x) + f(0.5) - cx) / fx
+    v = (f(y) + f(0.5) - cy) / fy
+    k = c32[ids]
+    num = (k[:, 6] * u + k[:, 7] * v) + k[:, 8]
+    den = ((k[:, 0] * u + k[:, 1] * v + k[:, 2]) * u + (k[:, 3] * v + k[:, 4]) * v) + k[:, 5]
+    bits = (num / den).astype(np.float32).view(np.uint32)
+    ordk = np.where(bits >> 31 == 1, ~bits, bits | np.uint32(0x80000000))
+    ids = ids[np.lexsort((ids, ordk))]
+    ud = (x + 0.5 - float(view_row[2])) / float(view_row[0])
+    vd = (y + 0.5 - float(view_row[3])) / float(view_row[1])
+    k = c64[ids]
+    z = (k[:, 6] * ud + k[:, 7] * vd + k[:, 8]) / (k[:, 0] * ud * ud + k[:, 1] * ud * vd +
+                                                   k[:, 2] * ud + k[:, 3] * vd * vd +
+                                                   k[:, 4] * vd + k[:, 5])
+    return ids, z
+
+
 def render_branches(rect, zbits, rec, pix, alpha_clamp=0.99, alpha_min=1 / 255, t_min=1e-4,
-                    bg=(0.0, 0.0, 0.0), margin=1e-4, max_alt=64):
+                    bg=(0.0, 0.0, 0.0), margin=1e-4, max_alt=64, per_pixel=None):
     """Every result a pixel may legitimately take when single precision
     decides its blend thresholds (Sec. 3.2 blend; the thresholds alpha_min
     and t_min are the rasteriser options): the per-pixel blend of ``render``
@@ -190,15 +237,22 @@ def render_branches(rect, zbits, rec, pix, alpha_clamp=0.99, alpha_min=1 / 255, 
     pixel of pix [n][3] = (view, x, y), a list of (ncontrib, rgb[3], depth,
     tfinal) tuples, at most max_alt of them (the first one follows the
     float64 decisions).  Plain per-pixel Python: for the few pixels whose
-    decisions are that close."""
+    decisions are that close.  per_pixel = (coef32, coef64, views): the
+    per-pixel order, as for render."""
     bg = np.asarray(bg, np.float64)
     out = []
     for v, x, y in np.asarray(pix, np.int64).reshape(-1, 3):
         r = rect[v]
         m = (r[:, 0] >= 0) & (r[:, 0] <= x) & (x <= r[:, 2]) & (r[:, 1] <= y) & (y <= r[:, 3])
         ids = np.nonzero(m)[0]
-        ids = ids[np.lexsort((ids, zbits[v, ids]))]
-        g = rec[v, ids]
+        if per_pixel is None:
+            ids = ids[np.lexsort((ids, zbits[v, ids]))]
+            g = rec[v, ids]
+            depth = g[:, 9]
+        else:
+            c32, c64, vw = per_pixel
+            ids, depth = _pix_order(c32[v], c64[v], np.asarray(vw)[v], x, y, ids)
+            g = rec[v, ids]
         dx, dy = g[:, 0] - (x + 0.5), g[:, 1] - (y + 0.5)
         q = -0.5 * (g[:, 2] * dx * dx + g[:, 4] * dy * dy) - g[:, 3] * dx * dy
         a = np.minimum(alpha_clamp, g[:, 5] * np.exp(q))
@@ -229,7 +283,7 @@ def render_branches(rect, zbits, rec, pix, alpha_clamp=0.99, alpha_min=1 / 255, 
                     alts.append((cnt, C + T * bg, D, T))
                     break
                 C = C + g[k, 6:9] * a[k] * T
-                D = D + g[k, 9] * a[k] * T
+                D = D + depth[k] * a[k] * T
                 T, cnt, k, fa, fs = Tn, cnt + 1, k + 1, None, None
         out.append(alts)
     return out

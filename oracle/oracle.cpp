@@ -329,6 +329,153 @@ void orc_gauss_project64(int64_t n, const float* mean, const float* cov, const f
   }
 }
 
+// --------------------------------------------------- per-pixel depth
+// Per-pixel order of the periphery (Sec. 3.2: contributions sorted per
+// pixel instead of per primitive, after Radl and Steiner et al.): the depth
+// of Gaussian g at pixel p is the camera depth z* of the maximum of g's 3D
+// density along the ray through p's centre.  With the camera-space mean
+// mu = R mean + T, camera-space precision M = (R Sigma R^T)^-1 and the ray
+// direction d = ((p_x + 1/2 - cx)/fx, (p_y + 1/2 - cy)/fy, 1) (z = 1), the
+// density along t d is largest at t* = (d^T M mu) / (d^T M d), and z* = t*.
+// Coefficients per (view, Gaussian): (m00, 2 m01, 2 m02, m11, 2 m12, m22,
+// b0, b1, b2) with b = M mu, so that
+//   num = (b0 u + b1 v) + b2
+//   den = ((m00 u + 2m01 v + 2m02) u + (m11 v + 2m12) v) + m22
+//   z*  = num / den.
+// Single precision, as the order decision (documented operation order, no
+// contraction): Sigma^-1 by cofactors over the determinant
+// ((s00 c00 + s01 c01) + s02 c02), Q = R Sigma^-1 (rows, each sum as
+// ((a0 b0 + a1 b1) + a2 b2)), M_ij = Q_i . R_j, b_i = M_i . mu; per pixel
+// u = ((x + 0.5) - cx) / fx, v likewise.  A Gaussian with a non-positive or
+// non-finite determinant takes its mean depth at every pixel.
+static float dot3f(float a0, float a1, float a2, float b0, float b1, float b2) {
+  float s = a0 * b0;
+  s = s + a1 * b1;
+  return s + a2 * b2;
+}
+
+void orc_gauss_pixdepth32(int64_t n, const float* mean, const float* cov, int nv,
+                          const float* views, const int* dims, float* coef) {
+  for (int v = 0; v < nv; ++v) {
+    const CamF c = cam_f(views + 17 * v, dims + 2 * v);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      float* o = coef + ((int64_t)v * n + i) * 9;
+      float t[3];
+      xform32(c, mean[i], mean[n + i], mean[2 * n + i], t);
+      const float s00 = cov[i], s01 = cov[n + i], s02 = cov[2 * n + i];
+      const float s11 = cov[3 * n + i], s12 = cov[4 * n + i], s22 = cov[5 * n + i];
+      const float c00 = s11 * s22 - s12 * s12, c01 = s02 * s12 - s01 * s22;
+      const float c02 = s01 * s12 - s02 * s11, c11 = s00 * s22 - s02 * s02;
+      const float c12 = s01 * s02 - s00 * s12, c22 = s00 * s11 - s01 * s01;
+      float det = s00 * c00;
+      det = det + s01 * c01;
+      det = det + s02 * c02;
+      if (!(det > 0.0f) || !std::isfinite(det)) {
+        for (int k = 0; k < 9; ++k) o[k] = 0.0f;
+        o[5] = 1.0f;    // den = 1, num = b2 = mean depth
+        o[8] = t[2];
+        continue;
+      }
+      const float id = 1.0f / det;
+      const float P[3][3] = {{c00 * id, c01 * id, c02 * id},
+                             {c01 * id, c11 * id, c12 * id},
+                             {c02 * id, c12 * id, c22 * id}};
+      float Q[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k)
+          Q[a][k] = dot3f(c.R[3 * a], c.R[3 * a + 1], c.R[3 * a + 2], P[0][k], P[1][k], P[2][k]);
+      float M[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b)
+          M[a][b] = dot3f(Q[a][0], Q[a][1], Q[a][2], c.R[3 * b], c.R[3 * b + 1], c.R[3 * b + 2]);
+      o[0] = M[0][0];
+      o[1] = 2.0f * M[0][1];
+      o[2] = 2.0f * M[0][2];
+      o[3] = M[1][1];
+      o[4] = 2.0f * M[1][2];
+      o[5] = M[2][2];
+      o[6] = dot3f(M[0][0], M[0][1], M[0][2], t[0], t[1], t[2]);
+      o[7] = dot3f(M[0][1], M[1][1], M[1][2], t[0], t[1], t[2]);
+      o[8] = dot3f(M[0][2], M[1][2], M[2][2], t[0], t[1], t[2]);
+    }
+  }
+}
+
+static float pixdepth_key32(const float* k, const CamF& c, int x, int y) {
+  const float u = (((float)x + 0.5f) - c.cx) / c.fx;
+  const float v = (((float)y + 0.5f) - c.cy) / c.fy;
+  float num = k[6] * u;
+  num = num + k[7] * v;
+  num = num + k[8];
+  float a = k[0] * u;
+  a = a + k[1] * v;
+  a = a + k[2];
+  float b = k[3] * v;
+  b = b + k[4];
+  float den = a * u;
+  den = den + b * v;
+  den = den + k[5];
+  return num / den;
+}
+
+// The same coefficients in double precision (the value accumulated into
+// Eq. 1's depth in per-pixel order): the exact inverse and products.
+void orc_gauss_pixdepth64(int64_t n, const float* mean, const float* cov, int nv,
+                          const float* views, const int* dims, double* coef) {
+  for (int v = 0; v < nv; ++v) {
+    const CamD c = cam_d(views + 17 * v, dims + 2 * v);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double* o = coef + ((int64_t)v * n + i) * 9;
+      double t[3];
+      for (int a = 0; a < 3; ++a)
+        t[a] = c.R[3 * a] * mean[i] + c.R[3 * a + 1] * mean[n + i] + c.R[3 * a + 2] * mean[2 * n + i] +
+               c.t[a];
+      const double s00 = cov[i], s01 = cov[n + i], s02 = cov[2 * n + i];
+      const double s11 = cov[3 * n + i], s12 = cov[4 * n + i], s22 = cov[5 * n + i];
+      const double c00 = s11 * s22 - s12 * s12, c01 = s02 * s12 - s01 * s22;
+      const double c02 = s01 * s12 - s02 * s11, c11 = s00 * s22 - s02 * s02;
+      const double c12 = s01 * s02 - s00 * s12, c22 = s00 * s11 - s01 * s01;
+      const double det = s00 * c00 + s01 * c01 + s02 * c02;
+      if (!(det > 0)) {
+        for (int k = 0; k < 9; ++k) o[k] = 0;
+        o[5] = 1;
+        o[8] = t[2];
+        continue;
+      }
+      const double P[3][3] = {{c00 / det, c01 / det, c02 / det},
+                              {c01 / det, c11 / det, c12 / det},
+                              {c02 / det, c12 / det, c22 / det}};
+      double M[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double acc = 0;
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) acc += c.R[3 * a + k] * P[k][l] * c.R[3 * b + l];
+          M[a][b] = acc;
+        }
+      o[0] = M[0][0]; o[1] = 2 * M[0][1]; o[2] = 2 * M[0][2];
+      o[3] = M[1][1]; o[4] = 2 * M[1][2]; o[5] = M[2][2];
+      for (int a = 0; a < 3; ++a) o[6 + a] = M[a][0] * t[0] + M[a][1] * t[1] + M[a][2] * t[2];
+    }
+  }
+}
+
+static double pixdepth64(const double* k, const CamD& c, int x, int y) {
+  const double u = (x + 0.5 - c.cx) / c.fx, v = (y + 0.5 - c.cy) / c.fy;
+  const double num = k[6] * u + k[7] * v + k[8];
+  const double den = k[0] * u * u + k[1] * u * v + k[2] * u + k[3] * v * v + k[4] * v + k[5];
+  return num / den;
+}
+
+// order-preserving unsigned image of a float (negative values first)
+static uint32_t ford(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
 // ------------------------------------------------------------ tile lists
 // Per (view, tile): every non-culled Gaussian whose tile rectangle
 // [xmin/T, xmax/T] x [ymin/T, ymax/T] contains the tile, ordered by
@@ -378,10 +525,16 @@ int64_t orc_tile_lists(int64_t n, int nv, const int* dims, int tile, const int32
 // opts = alpha_clamp, alpha_min, t_min, bg0, bg1, bg2.
 // pix [npix][3] = (view, x, y); null renders every pixel of every view in
 // [v][y][x] order (npix ignored).
+// Per-pixel order (pix32/pix64 given: the coefficients of
+// orc_gauss_pixdepth32/64 and views [v][17]): the Gaussians whose rectangle
+// holds p are ordered by (order-preserving bits of their single-precision
+// per-pixel depth key, index) instead, and Eq. 1 accumulates their
+// double-precision per-pixel depth z* instead of tz; nothing else changes.
 void orc_render(int64_t n, int nv, const int* dims, int tile, const int32_t* rect,
                 const uint32_t* zbits, const double* rec, const double* opts, int64_t npix,
                 const int32_t* pix, double* rgb, double* depth, double* tfinal,
-                int32_t* ncontrib, double* margin, int32_t* evals) {
+                int32_t* ncontrib, double* margin, int32_t* evals, const float* pix32,
+                const double* pix64, const float* views) {
   // enumerate requested pixels
   std::vector<int32_t> all;
   if (!pix) {
@@ -429,15 +582,33 @@ void orc_render(int64_t n, int nv, const int* dims, int tile, const int32_t* rec
   for (int64_t k = 0; k < npix; ++k) {
     int v = pix[3 * k], x = pix[3 * k + 1], y = pix[3 * k + 2];
     int tx_n = (dims[2 * v] + tile - 1) / tile;
-    const auto& L = lists[tile_base[v] + (y / tile) * tx_n + x / tile];
+    const auto* L = &lists[tile_base[v] + (y / tile) * tx_n + x / tile];
+    std::vector<std::pair<uint32_t, int32_t>> own;   // per-pixel order
+    std::vector<double> zstar;
+    if (pix32) {
+      const CamF cf = cam_f(views + 17 * v, dims + 2 * v);
+      for (const auto& e : *L) {
+        const int32_t* r = rect + ((int64_t)v * n + e.second) * 4;
+        if (x < r[0] || x > r[2] || y < r[1] || y > r[3]) continue;
+        own.push_back({ford(pixdepth_key32(pix32 + ((int64_t)v * n + e.second) * 9, cf, x, y)),
+                       e.second});
+      }
+      std::sort(own.begin(), own.end());
+      const CamD cd = cam_d(views + 17 * v, dims + 2 * v);
+      for (const auto& e : own)
+        zstar.push_back(pixdepth64(pix64 + ((int64_t)v * n + e.second) * 9, cd, x, y));
+      L = &own;
+    }
     double T = 1, C[3] = {0, 0, 0}, D = 0, mg = INFINITY;
     int cnt = 0, ev = 0;
-    for (const auto& e : L) {
+    for (size_t j = 0; j < L->size(); ++j) {
+      const auto& e = (*L)[j];
       int64_t i = e.second;
       const int32_t* r = rect + ((int64_t)v * n + i) * 4;
       if (x < r[0] || x > r[2] || y < r[1] || y > r[3]) continue;
       ++ev;
       const double* g = rec + ((int64_t)v * n + i) * 10;
+      const double di = pix32 ? zstar[j] : g[9];
       double dx = g[0] - (x + 0.5), dy = g[1] - (y + 0.5);
       double q = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
       if (q > 0) continue;
@@ -448,7 +619,7 @@ void orc_render(int64_t n, int nv, const int* dims, int tile, const int32_t* rec
       mg = std::min(mg, std::fabs(Tn - tmin) / tmin);
       if (Tn < tmin) break;
       for (int ch = 0; ch < 3; ++ch) C[ch] += g[6 + ch] * a * T;
-      D += g[9] * a * T;
+      D += di * a * T;
       T = Tn;
       ++cnt;
     }

@@ -369,3 +369,203 @@ def test_tile_lists_sorted_and_cover_contributors():
             r = rect[v, i]
             hit = r[0] >= 0 and r[0] // 16 <= tx <= r[2] // 16 and r[1] // 16 <= ty <= r[3] // 16
             assert hit == (i in set(lst.tolist()))
+
+
+# ----------------------------------------------------- per-pixel order
+def _pix_uv(cam, x, y):
+    return (x + 0.5 - cam.cx) / cam.fx, (y + 0.5 - cam.cy) / cam.fy
+
+
+def test_pixdepth_is_the_density_maximum_along_the_ray():
+    """z* of the per-pixel order is where the Gaussian's 3D density peaks on
+    the ray through the pixel centre: checked against a golden-section
+    search of the Mahalanobis distance along the ray (FP64), under a
+    rotated, translated camera; the single-precision key within 1e-5."""
+    cam = synth.pinhole(96, 80, 90.0, eye=(0.1, -0.05, -0.3), rot=synth.yaw_pitch(9, -6))
+    V, D = synth.views_array([cam]), synth.views_dims([cam])
+    rng = np.random.default_rng(12)
+    n = 40
+    g = synth.gaussians(rng, n, 0)
+    g["logscale"] = (g["logscale"] + rng.uniform(-0.5, 1.0, g["logscale"].shape)).astype(np.float32)
+    cov64, _ = oracle.bake(g["logscale"], g["quat"], g["logit"])
+    cov = cov64.astype(np.float32)
+    c32, c64 = oracle.gauss_pixdepth(g["mean"], cov, V, D)
+    rect, _ = oracle.gauss_geom32(g["mean"], cov, V, D)
+    R = np.asarray(cam.rot, np.float32).astype(np.float64).reshape(3, 3)
+    tr = np.asarray(cam.trans, np.float32).astype(np.float64)
+    checked = 0
+    for i in range(n):
+        S = cov[:, i].astype(np.float64)[[0, 1, 2, 1, 3, 4, 2, 4, 5]].reshape(3, 3)
+        M = np.linalg.inv(R @ S @ R.T)
+        mu = R @ g["mean"][:, i].astype(np.float64) + tr
+        r = rect[0, i]
+        if r[0] < 0:
+            continue
+        for _ in range(5):   # pixels of the Gaussian's rectangle, where its key is used
+            x, y = rng.integers(r[0], r[2] + 1), rng.integers(r[1], r[3] + 1)
+            u, v = _pix_uv(cam, x, y)
+            d = np.array([u, v, 1.0])
+            f = lambda t: (t * d - mu) @ M @ (t * d - mu)
+            a, b = 1e-3, 50.0
+            gr = (np.sqrt(5) - 1) / 2
+            for _ in range(200):
+                c1, c2 = b - gr * (b - a), a + gr * (b - a)
+                a, b = (a, c2) if f(c1) < f(c2) else (c1, b)
+            t_num = 0.5 * (a + b)
+            k = c64[0, i]
+            z64 = (k[6] * u + k[7] * v + k[8]) / (k[0] * u * u + k[1] * u * v + k[2] * u +
+                                                  k[3] * v * v + k[4] * v + k[5])
+            assert abs(z64 - t_num) <= 1e-6 * t_num, (i, x, y, z64, t_num)   # search: ~sqrt(eps)
+            k32 = c32[0, i].astype(np.float64)
+            z32 = (k32[6] * u + k32[7] * v + k32[8]) / (k32[0] * u * u + k32[1] * u * v +
+                                                        k32[2] * u + k32[3] * v * v +
+                                                        k32[4] * v + k32[5])
+            assert abs(z32 - z64) <= 1e-5 * z64
+            checked += 1
+    assert checked >= 100
+
+
+def _pix_key32(k, cam, x, y):
+    """The single-precision key in its documented operation order (numpy
+    float32 arithmetic is IEEE single precision, correctly rounded)."""
+    f = np.float32
+    u = (f(x) + f(0.5) - f(cam.cx)) / f(cam.fx)
+    v = (f(y) + f(0.5) - f(cam.cy)) / f(cam.fy)
+    num = (k[6] * u + k[7] * v) + k[8]
+    den = ((k[0] * u + k[1] * v + k[2]) * u + (k[3] * v + k[4]) * v) + k[5]
+    return f(num / den)
+
+
+def test_per_pixel_blend_equals_brute_force():
+    """Every pixel: the Gaussians whose rectangle holds it, ordered by their
+    single-precision per-pixel key (recomputed here) and index, blended with
+    cumulative products; depth accumulates the FP64 z*."""
+    sc, g, cov, op, V, D = _scene(27, n_gauss=250, width=40, height=32, f=40.0)
+    cam = sc["views"][0]
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
+    c32, c64 = oracle.gauss_pixdepth(g["mean"], cov, V, D)
+    out = oracle.render(rect, zb, rec, D, tile=8, per_pixel=(c32, c64, V))
+    prim = oracle.render(rect, zb, rec, D, tile=8)
+    aclamp, amin, tmin = 0.99, 1 / 255, 1e-4
+    differ = 0
+    for y in range(32):
+        for x in range(40):
+            r = rect[0]
+            idx = np.nonzero((r[:, 0] >= 0) & (r[:, 0] <= x) & (x <= r[:, 2]) & (r[:, 1] <= y) &
+                             (y <= r[:, 3]))[0]
+            keys = np.array([_pix_key32(c32[0, i], cam, x, y) for i in idx], np.float32)
+            ordk = np.where(keys.view(np.uint32) >> 31 == 1, ~keys.view(np.uint32),
+                            keys.view(np.uint32) | np.uint32(0x80000000))
+            idx = idx[np.lexsort((idx, ordk))]
+            gg = rec[0, idx]
+            u, v = _pix_uv(cam, x, y)
+            k = c64[0, idx]
+            zs = (k[:, 6] * u + k[:, 7] * v + k[:, 8]) / (k[:, 0] * u * u + k[:, 1] * u * v +
+                                                        k[:, 2] * u + k[:, 3] * v * v +
+                                                        k[:, 4] * v + k[:, 5])
+            dx, dy = gg[:, 0] - (x + 0.5), gg[:, 1] - (y + 0.5)
+            q = -0.5 * (gg[:, 2] * dx * dx + gg[:, 4] * dy * dy) - gg[:, 3] * dx * dy
+            a = np.minimum(aclamp, gg[:, 5] * np.exp(q))
+            keep = (q <= 0) & (a >= amin)
+            a, gk, zk = a[keep], gg[keep], zs[keep]
+            Tn = np.cumprod(1 - a)
+            stop = np.nonzero(Tn < tmin)[0]
+            kk = stop[0] if len(stop) else len(a)
+            Tb = np.concatenate([[1.0], Tn[:-1]])[:kk]
+            rgb = (gk[:kk, 6:9] * (a[:kk] * Tb)[:, None]).sum(0)
+            np.testing.assert_allclose(out["rgb"][0, :, y, x], rgb, atol=1e-12)
+            np.testing.assert_allclose(out["depth"][0, y, x], (zk[:kk] * a[:kk] * Tb).sum(),
+                                       atol=1e-11)
+            assert out["ncontrib"][0, y, x] == kk
+            differ += np.abs(out["rgb"][0, :, y, x] - prim["rgb"][0, :, y, x]).max() > 1e-9
+    assert differ > 10   # the orders do differ somewhere in this scene
+
+
+def test_per_pixel_order_of_two_crossing_gaussians():
+    """Two elongated Gaussians tilted in depth in opposite directions cross
+    at the image centre: left of it one is in front, right of it the other
+    (their means share a depth, so the per-primitive order keeps one in
+    front everywhere).  Closed-form two-layer blends on both sides."""
+    import math
+    f = 64.0
+    cam = synth.pinhole(64, 16, f)
+    V, D = synth.views_array([cam]), synth.views_dims([cam])
+
+    def tilted(angle):
+        c, s = math.cos(angle), math.sin(angle)
+        Rz = np.array([[c, 0, -s], [0, 1, 0], [s, 0, c]])   # rotation in the x-z plane
+        S = Rz @ np.diag([0.3 ** 2, 0.02 ** 2, 0.01 ** 2]) @ Rz.T
+        return [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
+
+    mean = np.array([[0.0, 0.0], [0.0, 0.0], [3.0, 3.0 + 1e-3]], np.float32)
+    cov = np.array([tilted(0.4), tilted(-0.4)], np.float32).T.copy()
+    op = np.array([0.8, 0.7], np.float32)
+    rgb = np.array([[1.0, 0, 0], [0, 0, 1.0]], np.float32)
+    sh = ((rgb.T - 0.5) * 2 * math.sqrt(math.pi))[None].astype(np.float32)
+    rect, zb = oracle.gauss_geom32(mean, cov, V, D)
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)
+    c32, c64 = oracle.gauss_pixdepth(mean, cov, V, D)
+    pix = np.array([[0, 20, 8], [0, 43, 8]])
+    pp = oracle.render(rect, zb, rec, D, pix=pix, per_pixel=(c32, c64, V))
+    pr = oracle.render(rect, zb, rec, D, pix=pix)
+    fronts = []
+    for k, (_, x, y) in enumerate(pix):
+        g = rec[0]
+        dx, dy = g[:, 0] - (x + 0.5), g[:, 1] - (y + 0.5)
+        a = np.minimum(0.99, g[:, 5] * np.exp(-0.5 * (g[:, 2] * dx * dx + g[:, 4] * dy * dy) -
+                                              g[:, 3] * dx * dy))
+        u, v = _pix_uv(cam, x, y)
+        zs = [(c[6] * u + c[7] * v + c[8]) / (c[0] * u * u + c[1] * u * v + c[2] * u + c[3] * v * v +
+                                              c[4] * v + c[5]) for c in c64[0]]
+        fr, bk = (0, 1) if zs[0] < zs[1] else (1, 0)
+        fronts.append(fr)
+        want = rgb[fr] * a[fr] + rgb[bk] * a[bk] * (1 - a[fr])
+        np.testing.assert_allclose(pp["rgb"][k], want, atol=1e-12)
+        np.testing.assert_allclose(pp["depth"][k], zs[fr] * a[fr] + zs[bk] * a[bk] * (1 - a[fr]),
+                                   rtol=1e-12)
+    assert fronts[0] != fronts[1]
+    # the per-primitive order keeps the nearer mean (index 0) in front everywhere
+    assert np.abs(pr["rgb"][0] - pp["rgb"][0]).max() > 1e-3 or np.abs(pr["rgb"][1] - pp["rgb"][1]).max() > 1e-3
+
+
+def test_per_pixel_order_of_depth_separated_spheres_is_the_primitive_order():
+    """Isotropic Gaussians whose depth ranges do not overlap: every pixel's
+    per-pixel order is the per-primitive one (colours, transmittance and
+    counts equal)."""
+    rng = np.random.default_rng(3)
+    n = 60
+    cam = synth.pinhole(48, 40, 48.0)
+    V, D = synth.views_array([cam]), synth.views_dims([cam])
+    mean = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.4, 0.4, n),
+                     2.0 + 0.1 * np.arange(n)]).astype(np.float32)
+    s = rng.uniform(0.02, 0.04, n)
+    cov = np.stack([s * s, 0 * s, 0 * s, s * s, 0 * s, s * s]).astype(np.float32)
+    op = rng.uniform(0.3, 0.9, n).astype(np.float32)
+    sh = rng.uniform(-1, 1, (1, 3, n)).astype(np.float32)
+    rect, zb = oracle.gauss_geom32(mean, cov, V, D)
+    rec = oracle.gauss_project64(mean, cov, op, sh, 0, V, D)
+    c32, c64 = oracle.gauss_pixdepth(mean, cov, V, D)
+    pp = oracle.render(rect, zb, rec, D, tile=8, per_pixel=(c32, c64, V))
+    pr = oracle.render(rect, zb, rec, D, tile=8)
+    np.testing.assert_allclose(pp["rgb"], pr["rgb"], atol=1e-12)
+    np.testing.assert_allclose(pp["tfinal"], pr["tfinal"], atol=1e-12)
+    assert np.array_equal(pp["ncontrib"], pr["ncontrib"])
+
+
+def test_render_branches_first_result_is_the_render_in_both_orders():
+    sc, g, cov, op, V, D = _scene(31, n_gauss=500, width=40, height=32, f=40.0)
+    rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D)
+    rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], 0, V, D)
+    c32, c64 = oracle.gauss_pixdepth(g["mean"], cov, V, D)
+    rng = np.random.default_rng(4)
+    pix = np.stack([np.zeros(60, int), rng.integers(0, 40, 60), rng.integers(0, 32, 60)], 1)
+    for pp in (None, (c32, c64, V)):
+        ref = oracle.render(rect, zb, rec, D, tile=8, pix=pix, per_pixel=pp)
+        alts = oracle.render_branches(rect, zb, rec, pix, per_pixel=pp)
+        for k in range(len(pix)):
+            n, c, d, t = alts[k][0]
+            assert n == ref["ncontrib"][k]
+            np.testing.assert_allclose(c, ref["rgb"][k], atol=1e-12)
+            np.testing.assert_allclose(d, ref["depth"][k], atol=1e-11)
+            np.testing.assert_allclose(t, ref["tfinal"][k], atol=1e-12)
