@@ -94,6 +94,25 @@ typedef struct {
   float gaze_x, gaze_y;
 } vrs_crop_place;
 
+/* Blend order of the periphery.  PRIMITIVE: every pixel of a tile blends
+ * its Gaussians in (float32 bits of the mean's view depth t.z, index) order.
+ * PIXEL (Sec. 3.2, the per-pixel sorting that removes popping): pixel p
+ * blends them in (key, index) order, the key being the camera depth z* of
+ * the maximum of the Gaussian's 3D density along the ray through p's centre,
+ *   z* = (d^T M mu) / (d^T M d),  d = ((p_x + 0.5 - cx)/fx, (p_y + 0.5 - cy)/fy, 1),
+ * mu = rot*mean + trans, M = (rot Sigma rot^T)^-1, computed in float32 in
+ * this order: Sigma^-1 by cofactors over ((s00 c00 + s01 c01) + s02 c02);
+ * Q = rot Sigma^-1 and M_ij = Q_i . rot_j, b = M mu, each dot product as
+ * ((a0 b0 + a1 b1) + a2 b2); u = ((x + 0.5) - cx)/fx, v likewise;
+ * num = (b0 u + b1 v) + b2, den = ((m00 u + 2m01 v + 2m02) u + (m11 v +
+ * 2m12) v) + m22 with 2m01 = 2*m01 etc.; key = num / den, compared by its
+ * order-preserving bits (a non-positive or non-finite det(Sigma) gives the
+ * key t.z).  Eq. 1 then accumulates that per-pixel depth; everything else
+ * is as in PRIMITIVE order.  The backward entry supports PRIMITIVE only, and
+ * the per-pixel work counts and replay positions are not kept in PIXEL
+ * order; PIXEL order takes tiles of 8 or 16 (VRS_EUNSUPPORTED for 32). */
+enum { VRS_ORDER_PRIMITIVE = 0, VRS_ORDER_PIXEL = 1 };
+
 /* Rasteriser options.  Defaults: tile 16, radix_bits 8, alpha_clamp 0.99,
  * alpha_min 1/255, t_min 1e-4, lowpass 0.3, extent 3, bg 0.  tile and
  * radix_bits change only the work's organisation, never a result: they are
@@ -101,6 +120,7 @@ typedef struct {
 typedef struct {
   int32_t tile;          /* screen tile edge: 8, 16 or 32 */
   int32_t radix_bits;    /* digit width of the radix sorts: 4, 6, 8 or 11 (0 = 8) */
+  int32_t order;         /* VRS_ORDER_PRIMITIVE or VRS_ORDER_PIXEL, see below */
   float alpha_clamp;     /* alpha = min(alpha_clamp, opacity e^q) */
   float alpha_min;       /* contributions with alpha < alpha_min are skipped */
   float t_min;           /* a pixel stops before T would fall below t_min */
@@ -185,12 +205,14 @@ vrs_status vrs_render_gaussians(const float* mean, const float* cov, const float
  * number of Gaussians whose rectangle held the pixel and that the pixel
  * evaluated before it stopped (uint32 [V][H][W]: the blend's work count);
  * super_pair_count (uint32, device): the number of (super-tile, Gaussian)
- * pairs the binning sorted, a super-tile being 8 x 8 tiles.
+ * pairs the binning sorted, a super-tile being 8 x 8 tiles;
+ * exact_pass_count (uint32, device; PIXEL order only, else 0): the number of
+ * pixels whose per-pixel order was resolved by the exact pass.
  * For inspection, tests and throughput accounting. */
 typedef struct {
   size_t pair_count, sorted_ids, tile_ranges, pixel_evals;
   int64_t tiles_x, tiles_y, tiles_total;
-  size_t super_pair_count;
+  size_t super_pair_count, exact_pass_count;
 } vrs_render_layout;
 vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const vrs_view* views,
                                        const vrs_raster_opts* opts, int64_t max_pairs,

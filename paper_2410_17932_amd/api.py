@@ -42,7 +42,7 @@ class Crop(ctypes.Structure):
 
 class RasterOpts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("radix_bits", ctypes.c_int32),
-                ("alpha_clamp", ctypes.c_float),
+                ("order", ctypes.c_int32), ("alpha_clamp", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("lowpass", ctypes.c_float), ("extent", ctypes.c_float),
                 ("bg", ctypes.c_float * 3)]
@@ -58,7 +58,7 @@ class RenderLayout(ctypes.Structure):
                 ("tile_ranges", ctypes.c_size_t), ("pixel_evals", ctypes.c_size_t),
                 ("tiles_x", ctypes.c_int64),
                 ("tiles_y", ctypes.c_int64), ("tiles_total", ctypes.c_int64),
-                ("super_pair_count", ctypes.c_size_t)]
+                ("super_pair_count", ctypes.c_size_t), ("exact_pass_count", ctypes.c_size_t)]
 
 
 class SplatLayout(ctypes.Structure):
@@ -214,10 +214,13 @@ def make_crops(crops) -> ctypes.Array:
     return arr
 
 
+ORDER_PRIMITIVE, ORDER_PIXEL = 0, 1
+
+
 def make_opts(tile=16, alpha_clamp=0.99, alpha_min=1 / 255, t_min=1e-4, lowpass=0.3, extent=3.0,
-              bg=(0.0, 0.0, 0.0), radix_bits=8, **_) -> RasterOpts:
+              bg=(0.0, 0.0, 0.0), radix_bits=8, order=ORDER_PRIMITIVE, **_) -> RasterOpts:
     o = RasterOpts()
-    o.tile, o.radix_bits = tile, radix_bits
+    o.tile, o.radix_bits, o.order = tile, radix_bits, order
     o.alpha_clamp, o.alpha_min, o.t_min = alpha_clamp, alpha_min, t_min
     o.lowpass, o.extent = lowpass, extent
     for k in range(3):
@@ -311,6 +314,13 @@ class RenderWorkspace:
 
     def super_pair_count(self) -> int:
         return int(self.u32(self.layout.super_pair_count, 1).item())
+
+    def exact_pass_count(self) -> int:
+        """Pixels of the last per-pixel-order render resolved by the exact
+        pass (0 in per-primitive order)."""
+        if self.layout.exact_pass_count == 0:
+            return 0
+        return int(self.u32(self.layout.exact_pass_count, 1).item())
 
     def pixel_evals(self, npix):
         """Per-pixel evaluation counts of the last blend (device tensor)."""

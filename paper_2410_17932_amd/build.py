@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvrsplat.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["host.hip", "prims.hip", "gs_forward.hip", "points.hip", "decoder.hip", "composite.hip",
+SOURCES = ["host.hip", "prims.hip", "gs_forward.hip", "gs_blend.hip", "gs_pixel.hip", "points.hip", "decoder.hip", "composite.hip",
            "bake.hip", "gs_backward.hip", "order.hip", "frame.hip"]
 
 

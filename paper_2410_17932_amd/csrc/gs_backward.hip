@@ -361,7 +361,9 @@ extern "C" vrs_status vrs_render_gaussians_backward(
   KViews kv;
   RenderWs L;
   if (!ro || !make_views(views, n_views, &kv)) return VRS_EINVAL;
+  if (ro->order != VRS_ORDER_PRIMITIVE) return VRS_EUNSUPPORTED;
   o.tile = ro->tile; o.aclamp = ro->alpha_clamp; o.amin = ro->alpha_min; o.tmin = ro->t_min;
+  o.order = ro->order;
   o.lowpass = ro->lowpass; o.extent = ro->extent;
   for (int k = 0; k < 3; ++k) o.bg[k] = ro->bg[k];
   for (int i = 1; i < n_views; ++i)

@@ -10,6 +10,7 @@ struct GsOpt {
   float aclamp, amin, tmin, lowpass, extent;
   float bg[3];
   int tile;
+  int order;   // VRS_ORDER_PRIMITIVE or VRS_ORDER_PIXEL
 };
 
 struct Geom {

@@ -30,10 +30,10 @@
 //   k_gs_bin_scatter  one wave per unit: every Gaussian index goes to its
 //                     final place in each tile list it belongs to, its rank
 //                     within a round from one ballot per tile
-//   k_gs_blend        one workgroup per tile in that order, one wave per
-//                     sub-tile; records staged in LDS in batches,
-//                     front-to-back blend with per-wave and block-wide early
-//                     exit
+//   k_gs_blend        (gs_blend.hip) one workgroup per tile in that order,
+//                     one wave per sub-tile; records staged in LDS in
+//                     batches, front-to-back blend with per-wave and
+//                     block-wide early exit
 #include <type_traits>
 
 #include "gs_layout.h"
@@ -618,297 +618,6 @@ __global__ __launch_bounds__(256) void k_gs_bin_scatter(
   }
 }
 
-// One workgroup per (view, tile).  The tile is cut into SUB x SUB sub-tiles,
-// one wave each; a lane holds PPT pixels of its sub-tile (a column, rows
-// 64/SUB apart).  Records of the tile list are staged in LDS in batches of
-// BLOCK (one per thread, conic pre-scaled for exp2); while staging, each wave
-// ballots which of the batch's records reach each sub-tile, so a wave walks
-// only the records that touch its sub-tile, in list order, with scalar bit
-// scans.  The per-pixel step is branch-free: every lane evaluates, and
-// selects decide.  A wave stops evaluating once all its pixels have
-// stopped; the block leaves the list when every wave has.  Workgroup i
-// takes the i-th tile of the longest-first schedule.
-
-// A 64-bit value known to be equal in every lane, moved to scalar registers
-// (the builtin returns a signed 32-bit int: each half goes through uint32_t
-// so that the low half is not sign-extended into the high one).
-__device__ inline uint64_t wave_uniform_u64(uint64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Lower bound of G(d) = ga dx^2 + gb dx dy + gc dy^2 (positive definite)
-// over the box dx in [X0, X1], dy in [Y0, Y1]: 0 if the box holds the
-// origin, else the least of the four edge minima (the minimiser of a convex
-// quadratic over a box lies on its boundary; on an edge it is the clamped
-// stationary point).  ia, ic = 1 / (2 ga), 1 / (2 gc): a stationary point off
-// by a relative rounding error changes the edge minimum by its square, far
-// inside the caller's margin.
-__device__ inline float box_min_quadratic(float ga, float gb, float gc, float ia, float ic,
-                                          float X0, float X1, float Y0, float Y1) {
-  if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
-  float m = 3.0e38f;
-  float Xe[2] = {X0, X1}, Ye[2] = {Y0, Y1};
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const float X = Xe[i];
-    const float dy = fminf(fmaxf(-gb * X * ic, Y0), Y1);
-    m = fminf(m, ga * X * X + gb * X * dy + gc * dy * dy);
-    const float Y = Ye[i];
-    const float dx = fminf(fmaxf(-gb * Y * ia, X0), X1);
-    m = fminf(m, ga * dx * dx + gb * dx * Y + gc * Y * Y);
-  }
-  return m;
-}
-
-template <int TILE, int SUB>
-struct BlendCfg {
-  static constexpr int NQ = TILE / SUB;          // sub-tiles per side
-  static constexpr int NW = NQ * NQ;             // waves per block
-  static constexpr int BLOCK = 64 * NW;
-  static constexpr int PPT = SUB * SUB / 64;     // pixels per lane
-  static constexpr int ROWS = 64 / SUB;          // rows between a lane's pixels
-};
-
-// Register budget for five waves per SIMD (96 VGPRs; no spills): the
-// staging and the per-pixel state compete for registers, and occupancy hides
-// the LDS and gather latency better than the extra registers would help.
-// STATS: also write each pixel's last contributing list position (the
-// adjoint's replay start) and its evaluation count (the work count); an
-// inference frame leaves both out, and with them the counting of records
-// out of reach of the ellipse.
-template <int TILE, int SUB, bool STATS>
-__global__ __launch_bounds__((BlendCfg<TILE, SUB>::BLOCK))
-__attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ rec, int64_t n, KViews views, GsOpt o, int64_t tiles_x,
-    int64_t tiles_per_view, const uint2* __restrict__ ranges, float* __restrict__ out_rgb,
-    float* __restrict__ out_depth,
-    float* __restrict__ out_t, int32_t* __restrict__ out_n, uint32_t* __restrict__ out_last,
-    uint32_t* __restrict__ out_evals) {
-  using Cfg = BlendCfg<TILE, SUB>;
-  constexpr int BLOCK = Cfg::BLOCK, PPT = Cfg::PPT, NW = Cfg::NW, NQ = Cfg::NQ;
-  __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK];
-  __shared__ uint64_t s_mask[NW][NW];   // [sub-tile][group of 64 records]: rectangle reaches it
-  __shared__ uint64_t s_full[NW][NW];   // ... and the contributing ellipse may too
-  __shared__ uint64_t s_cover[NW][NW];  // ... and the rectangle holds its in-image pixels
-  const int64_t tglob = order[blockIdx.x];
-  const int v = (int)(tglob / tiles_per_view);
-  const int64_t tl = tglob - (int64_t)v * tiles_per_view;
-  const int ty = (int)(tl / tiles_x), tx = (int)(tl - (int64_t)ty * tiles_x);
-  const KView& cv = views.v[v];
-  const int W = cv.W, H = cv.H;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  // sub-tile of this wave and the lane's pixels
-  const int sx0 = tx * TILE + (wave % NQ) * SUB, sy0 = ty * TILE + (wave / NQ) * SUB;
-  const int px = sx0 + lane % SUB;
-  // ry[q] is the pixel row tested against record rectangles; a pixel outside
-  // the image gets kStopped, one that has stopped kStopped + the count of
-  // sub-tile-holding records it evaluated (both fail every rectangle test)
-  constexpr int kStopped = 1 << 30;
-  int py[PPT], ry[PPT];
-  float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
-  int cnt[PPT];
-  uint32_t last[PPT], evals[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    py[q] = sy0 + lane / SUB + q * Cfg::ROWS;
-    ry[q] = px >= W || py[q] >= H ? kStopped : py[q];
-    T[q] = 1.0f;
-    C0[q] = C1[q] = C2[q] = D[q] = 0.0f;
-    cnt[q] = 0;
-    last[q] = 0;
-    evals[q] = 0;
-  }
-  const uint2 rg = ranges[tglob];
-  const uint32_t begin = rg.x, end = rg.y;
-  const float aclamp = o.aclamp, amin = o.amin, tmin = o.tmin;
-  const float inv_amin = 1.0f / amin;   // infinite for alpha_min = 0: never out of reach
-  const float xc = (float)px + 0.5f;
-  float yc[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) yc[q] = (float)py[q] + 0.5f;
-  int all_ry = kStopped;   // bit 30 stays set only while every pixel has stopped
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) all_ry &= ry[q];
-  bool alive = __ballot((all_ry & kStopped) == 0) != 0;   // wave-uniform
-  // records whose rectangle holds the sub-tile, so far: every live pixel
-  // evaluated each of them, so they are counted per wave, not per pixel
-  uint32_t ncov = 0;
-  for (uint32_t b0 = begin; b0 < end; b0 += BLOCK) {
-    if (__syncthreads_count(alive) == 0) break;
-    const uint32_t jr = b0 + tid;
-    bool has = jr < end;
-    int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
-    // contributing region: alpha >= alpha_min <=> G(d) = -q(d) <= log2(op /
-    // alpha_min); thr carries a margin far above the rounding of q so that a
-    // sub-tile is declared out of reach only where every pixel's own test
-    // would fail
-    float cx = 0.0f, cy = 0.0f, ga = 1.0f, gb = 0.0f, gc = 1.0f, ia = 0.5f, ic = 0.5f, thr = -1.0f;
-    if (has) {
-      const uint32_t id = ids[jr];
-      const int64_t e = (int64_t)v * n + (id < (uint64_t)n ? id : 0);
-      float4 a, b, c;
-      gs_stage(rec, e, a, b, c);
-      s_a[tid] = a;
-      s_b[tid] = b;
-      s_c[tid] = c;
-      const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
-      x0 = (int)(lo & 0xffffu); y0 = (int)(lo >> 16);
-      x1 = (int)(hi & 0xffffu); y1 = (int)(hi >> 16);
-      cx = a.x; cy = a.y;
-      ga = -a.z; gb = -a.w; gc = -b.x;
-      ia = 0.5f * __builtin_amdgcn_rcpf(ga);
-      ic = 0.5f * __builtin_amdgcn_rcpf(gc);
-      // (hardware log2 and reciprocal: their error is far inside the margin)
-      thr = b.y >= amin ? __builtin_amdgcn_logf(b.y * inv_amin) * 1.001f + 1.0e-3f : -1.0f;
-      if (!(ga > 0.0f && gc > 0.0f)) thr = 3.0e38f;   // never declared out of reach
-    }
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const int qx0 = tx * TILE + (w % NQ) * SUB, qy0 = ty * TILE + (w / NQ) * SUB;
-      const int xlo = max(x0, qx0), xhi = min(x1, qx0 + SUB - 1);
-      const int ylo = max(y0, qy0), yhi = min(y1, qy0 + SUB - 1);
-      const bool hit = has && xlo <= xhi && ylo <= yhi;
-      const bool cover = hit && x0 <= qx0 && x1 >= min(qx0 + SUB - 1, W - 1) && y0 <= qy0 &&
-                         y1 >= min(qy0 + SUB - 1, H - 1);
-      bool full = false;
-      if (hit) {
-        // d = centre - pixel centre over the pixel centres of the overlap
-        const float g = box_min_quadratic(ga, gb, gc, ia, ic, cx - ((float)xhi + 0.5f),
-                                          cx - ((float)xlo + 0.5f), cy - ((float)yhi + 0.5f),
-                                          cy - ((float)ylo + 0.5f));
-        full = !(g > thr);
-      }
-      const uint64_t m = __ballot(hit), mf = __ballot(full), mc = __ballot(cover);
-      if (lane == 0) {
-        s_mask[w][wave] = m;
-        s_full[w][wave] = mf;
-        s_cover[w][wave] = mc;
-      }
-    }
-    __syncthreads();
-    if (!alive) continue;
-    for (int g = 0; g < NW && alive; ++g) {
-      uint64_t m = wave_uniform_u64(s_mask[wave][g]);
-      const uint64_t mfull = wave_uniform_u64(s_full[wave][g]);
-      const uint64_t mcov = wave_uniform_u64(s_cover[wave][g]);
-      while (m) {
-        // Records out of reach of the ellipse before the next one that may
-        // contribute: no pixel can pass alpha_min, so only the evaluation
-        // count of in-rectangle live pixels moves.  Those whose rectangle
-        // holds the whole sub-tile are only counted; the others are tested
-        // per pixel, in a loop of their own: the blend state flows through
-        // this loop alone.
-        const uint64_t mf = m & mfull;
-        const uint64_t cheap = mf ? (m & ((mf & (~mf + 1ull)) - 1ull)) : m;
-        m &= ~cheap;
-        if constexpr (STATS) {
-          ncov += (uint32_t)__popcll(cheap & mcov);
-          uint64_t cpart = cheap & ~mcov;
-          while (cpart) {
-            const int kc = g * 64 + __builtin_ctzll(cpart);
-            cpart &= cpart - 1;
-            const float4 bc = s_b[kc];
-            const uint32_t clo = __float_as_uint(bc.z), chi = __float_as_uint(bc.w);
-            const int cx0 = (int)(clo & 0xffffu), cy0 = (int)(clo >> 16);
-            const bool cin = (uint32_t)(px - cx0) <= (uint32_t)((int)(chi & 0xffffu) - cx0);
-            const uint32_t cspan = (uint32_t)((int)(chi >> 16) - cy0);
-#pragma unroll
-            for (int q = 0; q < PPT; ++q)
-              evals[q] += (cin & ((uint32_t)(ry[q] - cy0) <= cspan)) ? 1u : 0u;
-          }
-        }
-        if (!m) break;
-        const int bit = __builtin_ctzll(m);
-        const int k = g * 64 + bit;
-        m &= m - 1;
-        const float4 a = s_a[k], b = s_b[k], c = s_c[k];
-        const uint32_t pos = b0 + (uint32_t)k + 1u - begin;
-        const float dx = a.x - xc;
-        // the exponent's per-column part (same operations as gs_exponent)
-        const float P = (a.z * dx) * dx, R = a.w * dx;
-        // One record over the lane's pixels.  in_rect(q): the pixel is live
-        // and inside the record's rectangle (tested as unsigned range checks,
-        // combined with bitwise operators so that nothing branches; where the
-        // rectangle holds the sub-tile, liveness alone).
-        auto blend_record = [&](auto in_rect, auto cover_tag) {
-          constexpr bool kCover = decltype(cover_tag)::value;
-          if (STATS && kCover) ++ncov;
-          const int stopped = kStopped + (STATS ? (int)ncov : 0);
-          all_ry = kStopped;
-#pragma unroll
-          for (int q = 0; q < PPT; ++q) {
-#pragma clang fp contract(off)   // T - w0 rounded once, the same in test and update
-            const float dy = a.y - yc[q];
-            const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
-            const float e = __builtin_amdgcn_exp2f(qq);
-            const float al = fminf(b.y * e, aclamp);
-            const bool inr = in_rect(q);
-            // w0 = alpha T is the contribution's weight and T - w0 the new
-            // transmittance: every state update below is then in place
-            const float w0 = al * T[q];
-            const float Tn = T[q] - w0;
-            const bool ok0 = inr & (al >= amin);
-            const bool stop = ok0 & (Tn < tmin);
-            const bool ok = ok0 & !stop;
-            ry[q] = stop ? stopped : ry[q];
-            const float wgt = ok ? w0 : 0.0f;
-            C0[q] = fmaf(c.x, wgt, C0[q]);
-            C1[q] = fmaf(c.y, wgt, C1[q]);
-            C2[q] = fmaf(c.z, wgt, C2[q]);
-            D[q] = fmaf(c.w, wgt, D[q]);
-            T[q] -= wgt;
-            cnt[q] += ok ? 1 : 0;
-            if constexpr (STATS) {
-              last[q] = ok ? pos : last[q];
-              if (!kCover) evals[q] += inr ? 1u : 0u;
-            }
-            all_ry &= ry[q];
-          }
-        };
-        if ((mcov >> bit) & 1ull) {
-          blend_record([&](int q) { return ry[q] < kStopped; }, std::true_type{});
-        } else {
-          const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
-          const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
-          const bool inx = (uint32_t)(px - rx0) <= (uint32_t)((int)(hi & 0xffffu) - rx0);
-          const uint32_t ry_span = (uint32_t)((int)(hi >> 16) - ry0);
-          blend_record([&](int q) { return inx & ((uint32_t)(ry[q] - ry0) <= ry_span); },
-                       std::false_type{});
-        }
-        if (__ballot((all_ry & kStopped) == 0) == 0) {
-          alive = false;
-          break;
-        }
-      }
-    }
-  }
-  // sub-tile-holding records: up to its stop, or all of them
-#pragma unroll
-  for (int q = 0; q < PPT; ++q)
-    if constexpr (STATS) evals[q] += ry[q] >= kStopped ? (uint32_t)(ry[q] - kStopped) : ncov;
-  const int64_t plane = (int64_t)W * H;
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    if (px >= W || py[q] >= H) continue;
-    const int64_t off = (int64_t)py[q] * W + px;
-    const int64_t pix = (int64_t)v * plane + off;
-    float* rgb = out_rgb + (int64_t)v * 3 * plane + off;
-    rgb[0] = C0[q] + T[q] * o.bg[0];
-    rgb[plane] = C1[q] + T[q] * o.bg[1];
-    rgb[2 * plane] = C2[q] + T[q] * o.bg[2];
-    out_depth[pix] = D[q];
-    out_t[pix] = T[q];
-    out_n[pix] = cnt[q];
-    if constexpr (STATS) {
-      out_last[pix] = last[q];
-      out_evals[pix] = evals[q];
-    }
-  }
-}
-
 }  // namespace vrs
 
 using namespace vrs;
@@ -922,8 +631,17 @@ static bool read_opts(const vrs_raster_opts* ro, GsOpt* o) {
   o->lowpass = ro->lowpass;
   o->extent = ro->extent;
   for (int k = 0; k < 3; ++k) o->bg[k] = ro->bg[k];
+  o->order = ro->order;
   return (o->tile == 8 || o->tile == 16 || o->tile == 32) && radix_bits_ok(opts_radix(ro)) &&
-         o->extent > 0 && o->lowpass >= 0 && o->amin >= 0;
+         (o->order == VRS_ORDER_PRIMITIVE || o->order == VRS_ORDER_PIXEL) && o->extent > 0 &&
+         o->lowpass >= 0 && o->amin >= 0;
+}
+
+// Per-pixel order runs one pixel per lane with its window in registers:
+// tiles of 8 and 16 pixels (a 32-pixel tile's 1024-lane workgroup would leave
+// too few registers per lane).
+static bool order_supported(const GsOpt& o) {
+  return o.order != VRS_ORDER_PIXEL || o.tile <= 16;
 }
 
 static bool same_dims(const vrs_view* views, int nv) {
@@ -935,7 +653,8 @@ static bool same_dims(const vrs_view* views, int nv) {
 extern "C" size_t vrs_render_workspace_size(int64_t n, int n_views, const vrs_view* views,
                                             const vrs_raster_opts* opts, int64_t max_pairs) {
   RenderWs L;
-  if (!opts || !render_layout(n, n_views, views, opts->tile, opts_radix(opts), max_pairs, &L))
+  if (!opts || !render_layout(n, n_views, views, opts->tile, opts_radix(opts), max_pairs, &L,
+                             opts->order))
     return 0;
   return L.total;
 }
@@ -945,7 +664,8 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
                                                   int64_t max_pairs, vrs_render_layout* out) {
   RenderWs L;
   if (!opts || !out ||
-      !render_layout(n, n_views, views, opts->tile, opts_radix(opts), max_pairs, &L))
+      !render_layout(n, n_views, views, opts->tile, opts_radix(opts), max_pairs, &L,
+                     opts->order))
     return VRS_EINVAL;
   out->pair_count = L.pair_count;
   out->sorted_ids = L.ids;
@@ -955,29 +675,8 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
   out->tiles_total = L.tiles_total;
   out->pixel_evals = L.evals;
   out->super_pair_count = L.super_count;
+  out->exact_pass_count = L.fix_count;
   return VRS_OK;
-}
-
-// Sub-tile edge per tile size: 16x16 sub-tiles (4 pixels per lane) for
-// 32-pixel tiles, 8x8 (one pixel per lane) below.
-template <int TILE, bool STATS>
-static void launch_blend(const RenderWs& L, void* ws, int64_t n, const uint32_t* order,
-                         const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
-                         int32_t* nc, hipStream_t st) {
-  constexpr int SUB = TILE == 32 ? 16 : 8;
-  const uint32_t* ids = at<uint32_t>(ws, L.ids);
-  hipLaunchKernelGGL((k_gs_blend<TILE, SUB, STATS>), dim3((unsigned)L.tiles_total),
-                     dim3(BlendCfg<TILE, SUB>::BLOCK), 0, st, order, ids, at<float4>(ws, L.rec), n,
-                     kv, o, L.tiles_x, L.tiles_x * L.tiles_y, at<uint2>(ws, L.ranges), rgb, depth,
-                     tf, nc, at<uint32_t>(ws, L.last), at<uint32_t>(ws, L.evals));
-}
-
-template <int TILE>
-static void launch_blend(bool stats, const RenderWs& L, void* ws, int64_t n,
-                         const uint32_t* order, const KViews& kv, const GsOpt& o, float* rgb,
-                         float* depth, float* tf, int32_t* nc, hipStream_t st) {
-  if (stats) launch_blend<TILE, true>(L, ws, n, order, kv, o, rgb, depth, tf, nc, st);
-  else launch_blend<TILE, false>(L, ws, n, order, kv, o, rgb, depth, tf, nc, st);
 }
 
 namespace vrs {
@@ -994,12 +693,13 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
   RenderWs L;
   if (!read_opts(opts, &o) || !make_views(views, n_views, &kv) || !same_dims(views, n_views))
     return VRS_EINVAL;
+  if (!order_supported(o)) return VRS_EUNSUPPORTED;
   if (n < 0 || n > (int64_t(1) << 28) || (n > 0 && (!mean || !cov || !opacity || !sh)))
     return VRS_EINVAL;
   if (sh_degree < 0 || sh_degree > 3) return VRS_EINVAL;
   if (!rgb || !depth || !t_final || !n_contrib || !ws) return VRS_EINVAL;
   if (max_pairs < 0 || max_pairs >= (int64_t(1) << 30)) return VRS_EINVAL;
-  if (!render_layout(n, n_views, views, o.tile, opts_radix(opts), max_pairs, &L) ||
+  if (!render_layout(n, n_views, views, o.tile, opts_radix(opts), max_pairs, &L, o.order) ||
       ws_bytes < L.total)
     return VRS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1017,6 +717,10 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
                        at<uint32_t>(ws, L.scan_tmp),
                        (int64_t)((L.sched - L.scan_tmp) / 4 + kSchedDone + 1));
     VRS_LAUNCH_CHECK();
+    if (o.order == VRS_ORDER_PIXEL) {
+      launch_gs_pixdepth(L, ws, mean, cov, n, kv, st);
+      VRS_LAUNCH_CHECK();
+    }
     trace_end(tr, VRS_TRACE_GS_PREPROCESS, st);
     trace_begin(tr, VRS_TRACE_GS_DEPTH_SORT, st);
     bool d1 = false;
@@ -1094,12 +798,11 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
   const uint32_t* order = at<uint32_t>(ws, L.order);
   trace_end(tr, VRS_TRACE_GS_SORT, st);
   trace_begin(tr, VRS_TRACE_GS_BLEND, st);
-  const bool stats = (flags & kRenderStats) != 0;
-  switch (o.tile) {
-    case 8: launch_blend<8>(stats, L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    case 16: launch_blend<16>(stats, L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
-    default: launch_blend<32>(stats, L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st); break;
-  }
+  if (o.order == VRS_ORDER_PIXEL)
+    launch_gs_blend_px(L, ws, n, order, kv, o, rgb, depth, t_final, n_contrib, st);
+  else
+    launch_gs_blend((flags & kRenderStats) != 0, L, ws, n, order, kv, o, rgb, depth, t_final,
+                    n_contrib, st);
   VRS_LAUNCH_CHECK();
   trace_end(tr, VRS_TRACE_GS_BLEND, st);
   return VRS_OK;

@@ -23,6 +23,7 @@ struct RenderWs {
       ranges, last, evals, g2d, sort_tmp, scan_tmp,
       sched,                        // length-bucket histogram, done count, bucket cursors
       stot, sbase,                  // per super-tile: tile pairs, list base
+      pcoef, fix_list, fix_count,   // per-pixel order: key coefficients, exact-pass queue
       total;
   int64_t vn, tiles_x, tiles_y, tiles_total, npix, sxn, syn, spv, st_total;
   int st_bits;
@@ -46,7 +47,8 @@ inline int64_t bin_units_max(int64_t max_pairs, int64_t st_total) {
 inline int opts_radix(const vrs_raster_opts* o) { return o->radix_bits == 0 ? 8 : o->radix_bits; }
 
 inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, int radix,
-                          int64_t max_pairs, RenderWs* L) {
+                          int64_t max_pairs, RenderWs* L, int order = VRS_ORDER_PRIMITIVE) {
+  if (order != VRS_ORDER_PRIMITIVE && order != VRS_ORDER_PIXEL) return false;
   if (n < 0 || nv < 1 || nv > VRS_MAX_VIEWS || !views || max_pairs < 0) return false;
   if (tile != 8 && tile != 16 && tile != 32) return false;
   if (!radix_bits_ok(radix)) return false;
@@ -97,8 +99,28 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->sched = c.take((size_t)kSchedWords * 4);   // follows scan_tmp: cleared together
   L->stot = c.take((size_t)L->st_total * 4);
   L->sbase = c.take((size_t)L->st_total * 4);
+  L->pcoef = L->fix_list = L->fix_count = 0;
+  if (order == VRS_ORDER_PIXEL) {
+    L->pcoef = c.take((size_t)vn * 48);
+    L->fix_list = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
+    L->fix_count = c.take(4);
+  }
   L->total = c.off;
   return true;
 }
+
+// Per-pixel order (gs_pixel.hip): key coefficients and sort keys after the
+// preprocess, and the blend with its exact pass for unresolved pixels.
+void launch_gs_pixdepth(const RenderWs& L, void* ws, const float* mean, const float* cov,
+                        int64_t n, const KViews& kv, hipStream_t st);
+void launch_gs_blend_px(const RenderWs& L, void* ws, int64_t n, const uint32_t* order,
+                        const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
+                        int32_t* nc, hipStream_t st);
+
+// The blend kernel of the tile size in o.tile (stats: also the adjoint's
+// last positions and the evaluation counts), gs_blend.hip.
+void launch_gs_blend(bool stats, const RenderWs& L, void* ws, int64_t n, const uint32_t* order,
+                     const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
+                     int32_t* nc, hipStream_t st);
 
 }  // namespace vrs

@@ -33,7 +33,7 @@ class Frame:
                  radix_bits: int = 8, mode: int = api.BLEND_LINEAR, ring: float = 64.0,
                  m: float = 0.75, gamma: float = 0.2, cull: bool = True,
                  pair_margin: float = 1.10, frag_margin: float = 1.25,
-                 spatial_order: bool = True):
+                 spatial_order: bool = True, order: int = api.ORDER_PRIMITIVE):
         g, p = scene["gaussians"], scene["points"]
         self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
         # without points or crops the frame is the periphery alone
@@ -44,7 +44,7 @@ class Frame:
         self.mode, self.ring, self.m, self.gamma, self.cull = mode, ring, m, gamma, cull
         self.decoder_dtype = decoder_dtype
         self.widths = scene["decoder"]["widths"] if scene.get("decoder") else (16, 32, 64, 64)
-        self.raster = dict(scene["raster"], tile=tile, radix_bits=radix_bits)
+        self.raster = dict(scene["raster"], tile=tile, radix_bits=radix_bits, order=order)
         # primitives resident in HBM; attributes baked once (Sec. 4 "Inference")
         self.mean = _dev(g["mean"])
         self.sh = _dev(g["sh"])
@@ -189,7 +189,10 @@ class Frame:
     # ----------------------------------------------------------- autotune
     def autotune(self, tiles=(8, 16, 32), radix=(4, 6, 8, 11), reps: int = 5) -> dict:
         """Time the frame for every tile size and sort radix on the live
-        scene and keep the fastest (neither changes a result)."""
+        scene and keep the fastest (neither changes a result; per-pixel
+        order takes tiles of 8 and 16)."""
+        if self.raster["order"] == api.ORDER_PIXEL:
+            tiles = tuple(t for t in tiles if t <= 16)
         times = {}
         for t in tiles:
             for r in radix:

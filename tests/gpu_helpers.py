@@ -26,14 +26,22 @@ def baked(g):
 
 
 def oracle_render(g, cov, op, views, raster, pix=None):
+    """The reference's periphery on the same inputs, in the order raster
+    asks for (order 1: per pixel)."""
     V, D = synth.views_array(views), synth.views_dims(views)
     rect, zb = oracle.gauss_geom32(g["mean"], cov, V, D, raster["lowpass"], raster["extent"])
     rec = oracle.gauss_project64(g["mean"], cov, op, g["sh"], g["sh_degree"], V, D,
                                  raster["lowpass"])
+    per_pixel = None
+    if raster.get("order", 0) == 1:
+        c32, c64 = oracle.gauss_pixdepth(g["mean"], cov, V, D)
+        per_pixel = (c32, c64, V)
     out = oracle.render(rect, zb, rec, D, raster["tile"], raster["alpha_clamp"],
-                        raster["alpha_min"], raster["t_min"], raster["bg"], pix=pix)
+                        raster["alpha_min"], raster["t_min"], raster["bg"], pix=pix,
+                        per_pixel=per_pixel)
     # what check_render needs to resolve near-threshold pixels
-    out["branches"] = dict(rect=rect, zb=zb, rec=rec, raster=raster, pix=pix)
+    out["branches"] = dict(rect=rect, zb=zb, rec=rec, raster=raster, pix=pix,
+                           per_pixel=per_pixel)
     return out, rect, zb
 
 
@@ -118,7 +126,8 @@ def check_render(o, gpu, tol=1e-4, margin=1e-4, max_ambiguous=0.002, branches=No
             sel = (idx,)
         r = b["raster"]
         alts = oracle.render_branches(b["rect"], b["zb"], b["rec"], pix, r["alpha_clamp"],
-                                      r["alpha_min"], r["t_min"], r["bg"], margin)
+                                      r["alpha_min"], r["t_min"], r["bg"], margin,
+                                      per_pixel=b.get("per_pixel"))
         for k, alt in enumerate(alts):
             gn, gd, gt = (int(gpu["ncontrib"][sel][k]), float(gpu["depth"][sel][k]),
                           float(gpu["tfinal"][sel][k]))
