@@ -242,11 +242,11 @@ def secondary_and_standalone(scene, tile, radix, steps):
     free()
     # the same periphery in per-pixel order (the paper's popping fix) against
     # the per-primitive order above
-    px = {}
+    px, exact = {}, {}
     for t in (8, 16):
         fr = Frame(sc1, tile=t, radix_bits=radix, order=api.ORDER_PIXEL)
-        px[str(t)] = round(replay_ms(fr, steps=steps), 4)
-        exact = fr.rws.exact_pass_count()
+        px[str(t)] = round(replay_ms(fr, warmup=1, steps=3), 4)
+        exact[str(t)] = fr.rws.exact_pass_count()
         del fr
         free()
     best = min(px, key=px.get)
@@ -254,7 +254,7 @@ def secondary_and_standalone(scene, tile, radix, steps):
         workload="config 1 periphery in per-pixel order (exact per-pixel sort)",
         ms_per_frame=px[best], tile=int(best), ms_by_tile=px,
         primitive_order_ms=out["config1_periphery"]["ms_per_frame"],
-        exact_pass_pixels=exact)
+        exact_pass_pixels=exact[best], exact_pass_pixels_by_tile=exact)
     sc2 = synth.config(2)
     fr = Frame(sc2, decoder_dtype=api.VRS_BF16, tile=tile, radix_bits=radix)
     fr.run()

@@ -207,12 +207,18 @@ vrs_status vrs_render_gaussians(const float* mean, const float* cov, const float
  * super_pair_count (uint32, device): the number of (super-tile, Gaussian)
  * pairs the binning sorted, a super-tile being 8 x 8 tiles;
  * exact_pass_count (uint32, device; PIXEL order only, else 0): the number of
- * pixels whose per-pixel order was resolved by the exact pass.
+ * pixels whose per-pixel order was resolved by the exact pass;
+ * tile_words (uint64 [max_pairs]; PIXEL order only, else 0): at the first
+ * min(length, 2048) positions of each tile range, the blend's reordering of
+ * those records as (order-preserving bits of beta) << 32 | Gaussian index,
+ * beta non-decreasing and at most every single-precision per-pixel key, at
+ * the tile's pixels in its rectangle, of every record at that position or
+ * later (later positions keep sorted_ids' order; other words unused).
  * For inspection, tests and throughput accounting. */
 typedef struct {
   size_t pair_count, sorted_ids, tile_ranges, pixel_evals;
   int64_t tiles_x, tiles_y, tiles_total;
-  size_t super_pair_count, exact_pass_count;
+  size_t super_pair_count, exact_pass_count, tile_words;
 } vrs_render_layout;
 vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const vrs_view* views,
                                        const vrs_raster_opts* opts, int64_t max_pairs,

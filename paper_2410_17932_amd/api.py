@@ -58,7 +58,8 @@ class RenderLayout(ctypes.Structure):
                 ("tile_ranges", ctypes.c_size_t), ("pixel_evals", ctypes.c_size_t),
                 ("tiles_x", ctypes.c_int64),
                 ("tiles_y", ctypes.c_int64), ("tiles_total", ctypes.c_int64),
-                ("super_pair_count", ctypes.c_size_t), ("exact_pass_count", ctypes.c_size_t)]
+                ("super_pair_count", ctypes.c_size_t), ("exact_pass_count", ctypes.c_size_t),
+                ("tile_words", ctypes.c_size_t)]
 
 
 class SplatLayout(ctypes.Structure):
@@ -321,6 +322,17 @@ class RenderWorkspace:
         if self.layout.exact_pass_count == 0:
             return 0
         return int(self.u32(self.layout.exact_pass_count, 1).item())
+
+    def tile_words(self):
+        """Per-pixel order: the blend's tile lists as uint64 words
+        (z_t bits << 32 | index), int64-viewed on the host, over the ranges
+        of tile_lists."""
+        if self.layout.tile_words == 0:
+            raise ValueError("tile words exist in per-pixel order only")
+        cnt = min(self.pair_count(), self.max_pairs)
+        off = self.layout.tile_words
+        w = self.buf[off:off + 8 * max(cnt, 1)].view(torch.int64)[:cnt]
+        return w.cpu().numpy().view(np.uint64)
 
     def pixel_evals(self, npix):
         """Per-pixel evaluation counts of the last blend (device tensor)."""

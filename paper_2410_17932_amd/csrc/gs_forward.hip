@@ -676,6 +676,7 @@ extern "C" vrs_status vrs_render_workspace_layout(int64_t n, int n_views, const 
   out->pixel_evals = L.evals;
   out->super_pair_count = L.super_count;
   out->exact_pass_count = L.fix_count;
+  out->tile_words = L.tkey;
   return VRS_OK;
 }
 
@@ -796,6 +797,10 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
                      L.tiles_y, at<uint32_t>(ws, L.ids));
   VRS_LAUNCH_CHECK();
   const uint32_t* order = at<uint32_t>(ws, L.order);
+  if (o.order == VRS_ORDER_PIXEL) {
+    launch_gs_tile_zsort(L, ws, n, kv, o.tile, st);
+    VRS_LAUNCH_CHECK();
+  }
   trace_end(tr, VRS_TRACE_GS_SORT, st);
   trace_begin(tr, VRS_TRACE_GS_BLEND, st);
   if (o.order == VRS_ORDER_PIXEL)

@@ -24,6 +24,7 @@ struct RenderWs {
       sched,                        // length-bucket histogram, done count, bucket cursors
       stot, sbase,                  // per super-tile: tile pairs, list base
       pcoef, fix_list, fix_count,   // per-pixel order: key coefficients, exact-pass queue
+      tkey,                         // per-pixel order: tile-list bound words
       total;
   int64_t vn, tiles_x, tiles_y, tiles_total, npix, sxn, syn, spv, st_total;
   int st_bits;
@@ -99,8 +100,11 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   L->sched = c.take((size_t)kSchedWords * 4);   // follows scan_tmp: cleared together
   L->stot = c.take((size_t)L->st_total * 4);
   L->sbase = c.take((size_t)L->st_total * 4);
-  L->pcoef = L->fix_list = L->fix_count = 0;
+  L->pcoef = L->fix_list = L->fix_count = L->tkey = 0;
   if (order == VRS_ORDER_PIXEL) {
+    // the tile lists' bound words (64-bit): the pair sort's value buffer,
+    // free once the binning has scattered it
+    L->tkey = L->sval0;
     L->pcoef = c.take((size_t)vn * 48);
     L->fix_list = c.take((size_t)std::max<int64_t>(L->npix, 1) * 4);
     L->fix_count = c.take(4);
@@ -110,9 +114,12 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
 }
 
 // Per-pixel order (gs_pixel.hip): key coefficients and sort keys after the
-// preprocess, and the blend with its exact pass for unresolved pixels.
+// preprocess, the tile lists sorted by per-tile bound after the binning, and
+// the blend with its exact pass for unresolved pixels.
 void launch_gs_pixdepth(const RenderWs& L, void* ws, const float* mean, const float* cov,
                         int64_t n, const KViews& kv, hipStream_t st);
+void launch_gs_tile_zsort(const RenderWs& L, void* ws, int64_t n, const KViews& kv, int tile,
+                         hipStream_t st);
 void launch_gs_blend_px(const RenderWs& L, void* ws, int64_t n, const uint32_t* order,
                         const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
                         int32_t* nc, hipStream_t st);

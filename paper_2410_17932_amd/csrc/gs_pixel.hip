@@ -9,19 +9,28 @@
 // The exact per-pixel order without per-pixel lists:
 //   k_gs_pixdepth   per (view, Gaussian): the key's coefficients in single
 //                   precision (the order decision, in a documented operation
-//                   order) and z_lo, a lower bound of the key over every
-//                   pixel of the Gaussian's rectangle; z_lo replaces the
-//                   depth-sort key, so each tile list comes out in z_lo order
+//                   order) and a lower bound of the key over the Gaussian's
+//                   rectangle, which replaces the depth-sort key (only an
+//                   initial order: the tile lists are sorted again)
+//   k_gs_tile_zsort per tile: bound words for the list positions (see
+//                   zs_word), the first kZsPrefix records sorted by z_t, a
+//                   rigorous lower bound of the single-precision key over
+//                   the tile's pixels
 //   k_gs_blend_px   one lane per pixel keeps a sorted window of its pending
-//                   contributions (key, index, alpha); before record j is
-//                   considered, every pending entry with key below z_lo(j)
-//                   precedes all later records (their keys are at least
-//                   their z_lo, which is at least z_lo(j)) and is blended.  A
-//                   pixel whose window fills up with no entry so released
-//                   has its order unresolved: it is queued
-//   k_gs_blend_px_fix  one wave per queued pixel redoes it exactly: each
-//                   round selects the least (key, index) above the last one
-//                   over the pixel's whole tile list
+//                   contributions (key, index, alpha, colour).  Before record
+//                   j is considered, a pending entry whose key is below
+//                   every later record's least key over the 8x8 sub-tile
+//                   precedes all of them and is blended.  At tile 8 that
+//                   bound is j's bound word; with several sub-tiles, per
+//                   staged batch, a suffix minimum of exact sub-tile minima
+//                   (one wave minimum per record), closed by the bound word
+//                   of the next batch's first position.  A pixel whose window fills
+//                   up with no entry so released has its order unresolved:
+//                   it is queued
+//   k_gs_blend_px_fix  one wave per queued pixel redoes it exactly with a
+//                   pending set in LDS, released against z_t after every 64
+//                   records (repeated selection over the whole list should
+//                   that set outgrow its capacity)
 // The adjoint is not provided for this order.
 #include "gs_layout.h"
 
@@ -98,7 +107,8 @@ __device__ inline float pix_ray(int x, float c, float f) {
 
 // Numerator and denominator of the key at ray coordinates (u, v), with the
 // coefficients staged as q0 = (m00, 2m01, 2m02, m11), q1 = (2m12, m22, b0,
-// b1), q2 = (b2, z_lo, -, -).
+// b1), q2 = (b2, z_lo, -, -) with z_lo the bound below over the Gaussian's
+// whole rectangle.
 __device__ inline void pix_numden(const float4& q0, const float4& q1, const float4& q2, float u,
                                   float v, float& num, float& den) {
 #pragma clang fp contract(off)
@@ -122,14 +132,72 @@ __device__ inline uint32_t pix_key_bits(const float4& q0, const float4& q1, cons
   return f2ord(num / den);
 }
 
-// Coefficients and the sort key z_lo of every (view, Gaussian) entry the
-// preprocess kept (its depth key is replaced; culled entries keep theirs).
-// z_lo: the numerator is linear in (u, v) and the denominator a convex
-// quadratic, so over the box of the rectangle's pixel centres the key is at
-// least (least corner numerator) / (largest corner denominator) when that
-// numerator is positive (else no bound: -inf); it is lowered by 2^-12 of
-// itself, far above the rounding of either side.  Thread 0 also clears the
-// count of pixels queued for the exact pass.
+// A lower bound of the single-precision key over every pixel centre of the
+// box [x0, x1] x [y0, y1] (-inf where none is proven).
+//   The exact numerator N is linear in the ray coordinates (u, v) and the
+//   exact denominator D a quadratic, convex when its 2x2 part is positive
+//   definite (checked with a margin).  The evaluation order of the key
+//   rounds N by at most An = 8 eps sum|terms| and D by at most Bd = 16 eps
+//   sum|terms| (eps = 2^-24; three and six roundings deep), the sums taken
+//   at the largest |u| and |v| of the box, so wherever N - An > 0 and
+//   D - Bd > 0 the key is at least f = (N - An) / (D + Bd) (1 - eps).  For
+//   c > 0, (N - An) - c (D + Bd) is concave, so its least value over the box
+//   is at a corner: f is least at a corner, and the corners are pixel
+//   centres.  Positivity: N's least value is at a corner; D is at least its
+//   tangent plane at the (u0, v0) corner, least at one of the box's ends.  Corner values are computed with
+//   2 An and 2 Bd to cover their own rounding, and the result is lowered by
+//   2^-20 of itself, which covers the last few roundings.  Ray coordinates
+//   round monotonically, so every pixel's (u, v) lies in the corners' box.
+__device__ inline float pix_box_bound_uv(const float4& q0, const float4& q1, const float4& q2,
+                                         float u0, float u1, float v0, float v1) {
+#pragma clang fp contract(off)
+  const float m00 = q0.x, m01 = 0.5f * q0.y, m11 = q0.w;
+  const float pd = m00 * m11, od = m01 * m01;
+  if (!(m00 > 0.0f) || !(m11 > 0.0f) || !(pd > od * (1.0f + 0x1p-20f)) || !isfinite(pd))
+    return -INFINITY;
+  const float U = fmaxf(fabsf(u0), fabsf(u1)), V = fmaxf(fabsf(v0), fabsf(v1));
+  const float nabs = (fabsf(q1.z) * U + fabsf(q1.w) * V) + fabsf(q2.x);
+  const float dabs = ((fabsf(q0.x) * U + fabsf(q0.y) * V) + fabsf(q0.z)) * U +
+                     (fabsf(q0.w) * V + fabsf(q1.x)) * V + fabsf(q1.y);
+  const float An = 0x1p-21f * nabs, Bd = 0x1p-20f * dabs;
+  // tangent plane of D at (u0, v0) over the box
+  const float du = (u1 - u0) * (1.0f + 0x1p-20f), dv = (v1 - v0) * (1.0f + 0x1p-20f);
+  float n00, d00;
+  pix_numden(q0, q1, q2, u0, v0, n00, d00);
+  const float gu = ((2.0f * q0.x) * u0 + q0.y * v0) + q0.z;
+  const float gv = (q0.y * u0 + (2.0f * q0.w) * v0) + q1.x;
+  const float dlb = (d00 + fminf(gu * du, 0.0f)) + fminf(gv * dv, 0.0f);
+  const float dlb_abs =
+      (dabs + (((2.0f * fabsf(q0.x)) * U + fabsf(q0.y) * V) + fabsf(q0.z)) * fabsf(du)) +
+      ((fabsf(q0.y) * U + (2.0f * fabsf(q0.w)) * V) + fabsf(q1.x)) * fabsf(dv);
+  if (!(dlb - 0x1p-20f * dlb_abs > 2.0f * Bd) || !isfinite(dlb_abs)) return -INFINITY;
+  const float us[2] = {u0, u1}, vs[2] = {v0, v1};
+  float z = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      float num, den;
+      pix_numden(q0, q1, q2, us[a], vs[b], num, den);
+      const float nn = num - 2.0f * An;
+      if (!(nn > 0.0f)) return -INFINITY;
+      z = fminf(z, nn / (den + 2.0f * Bd));
+    }
+  if (!isfinite(z)) return -INFINITY;
+  return z - z * 0x1p-20f;
+}
+
+__device__ inline float pix_box_bound(const float4& q0, const float4& q1, const float4& q2,
+                                      const KView& cv, int x0, int x1, int y0, int y1) {
+  return pix_box_bound_uv(q0, q1, q2, pix_ray(x0, cv.cx, cv.fx), pix_ray(x1, cv.cx, cv.fx),
+                          pix_ray(y0, cv.cy, cv.fy), pix_ray(y1, cv.cy, cv.fy));
+}
+
+// Coefficients and the sort key of every (view, Gaussian) entry the
+// preprocess kept (its depth key is replaced; culled entries keep theirs):
+// z_lo, the bound above over the Gaussian's whole rectangle, so that every
+// tile list comes out of the binning in z_lo order.  Thread 0 also clears
+// the count of pixels queued for the exact pass.
 __global__ __launch_bounds__(256) void k_gs_pixdepth(const float* __restrict__ mean,
                                                      const float* __restrict__ cov, int64_t n,
                                                      KViews views,
@@ -170,30 +238,93 @@ __global__ __launch_bounds__(256) void k_gs_pixdepth(const float* __restrict__ m
     const float4 q1 = make_float4(k[4], k[5], k[6], k[7]);
     const float4 r2 = rec[3 * e + 2];
     const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
-    const float u0 = pix_ray((int)(lo & 0xffffu), cv.cx, cv.fx);
-    const float u1 = pix_ray((int)(hi & 0xffffu), cv.cx, cv.fx);
-    const float v0 = pix_ray((int)(lo >> 16), cv.cy, cv.fy);
-    const float v1 = pix_ray((int)(hi >> 16), cv.cy, cv.fy);
-    float nmin = 3.0e38f, dmax = -3.0e38f;
-    const float us[2] = {u0, u1}, vs[2] = {v0, v1};
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        float num, den;
-        pix_numden(q0, q1, make_float4(k[8], 0, 0, 0), us[a], vs[b], num, den);
-        nmin = fminf(nmin, num);
-        dmax = fmaxf(dmax, den);
-      }
-    float zlo = -INFINITY;
-    if (nmin > 0.0f && dmax > 0.0f && isfinite(nmin) && isfinite(dmax)) {
-      zlo = nmin / dmax;
-      zlo = zlo - zlo * 0x1p-12f;
-    }
+    const float zlo = pix_box_bound(q0, q1, make_float4(k[8], 0.0f, 0.0f, 0.0f), cv,
+                                    (int)(lo & 0xffffu), (int)(hi & 0xffffu), (int)(lo >> 16),
+                                    (int)(hi >> 16));
     pcoef[3 * e] = q0;
     pcoef[3 * e + 1] = q1;
     pcoef[3 * e + 2] = make_float4(k[8], zlo, 0.0f, 0.0f);
     dkey[e] = f2ord(zlo);
+  }
+}
+
+// ---------------------------------------------------------------- tile sort
+// Bound words.  Every list position j gets w(j) = beta(j) << 32 | index with
+// beta non-decreasing along the list and every key of every record at
+// positions >= j, at every pixel of the tile in its rectangle, at least
+// beta(j) (order-preserving bits throughout).  The first kZsPrefix records
+// (or all) are sorted by z_t, the bound over the tile's pixel box, its bits
+// rounded down to 21 (so that a 32-bit word carries it with an 11-bit slot
+// in the prefix): beta = min(rounded z_t, z_lo of the first record after the
+// prefix).  After the prefix the list keeps its z_lo order and beta = z_lo.
+// Blending stops long before most lists end, so only the prefix is sorted; a
+// pixel that reads past it still gets valid, if looser, bounds.
+constexpr int kZsBlock = 256, kZsPrefix = 2048, kZsSlotBits = 11;
+static_assert(kZsPrefix == 1 << kZsSlotBits, "one slot per prefix position");
+
+__device__ inline uint64_t zs_word(const uint64_t* __restrict__ tkey,
+                                   const uint32_t* __restrict__ ids,
+                                   const float4* __restrict__ pcoef, int64_t vbase, uint32_t begin,
+                                   uint32_t j) {
+  if (j - begin < (uint32_t)kZsPrefix) return tkey[j];
+  const uint32_t id = ids[j];
+  return ((uint64_t)f2ord(pcoef[3 * (vbase + id) + 2].y) << 32) | id;
+}
+
+// One workgroup per tile: the prefix's words, sorted in LDS (bitonic over
+// 32-bit (rounded z_t bits | slot) words).
+__global__ __launch_bounds__(kZsBlock) void k_gs_tile_zsort(
+    const uint32_t* __restrict__ ids, const float4* __restrict__ pcoef, int64_t n, KViews views,
+    int tile, int64_t tiles_x, int64_t tiles_per_view, const uint2* __restrict__ ranges,
+    uint64_t* __restrict__ out) {
+  __shared__ uint32_t s[kZsPrefix];
+  const int64_t tglob = blockIdx.x;
+  const uint2 rg = ranges[tglob];
+  const uint32_t begin = rg.x;
+  const int len = (int)(rg.y - rg.x);
+  if (len <= 0) return;
+  const int v = (int)(tglob / tiles_per_view);
+  const int64_t tl = tglob - (int64_t)v * tiles_per_view;
+  const int ty = (int)(tl / tiles_x), tx = (int)(tl - (int64_t)ty * tiles_x);
+  const KView& cv = views.v[v];
+  const int X0 = tx * tile, Y0 = ty * tile;
+  const int X1 = min(X0 + tile, cv.W) - 1, Y1 = min(Y0 + tile, cv.H) - 1;
+  const float u0 = pix_ray(X0, cv.cx, cv.fx), u1 = pix_ray(X1, cv.cx, cv.fx);
+  const float v0 = pix_ray(Y0, cv.cy, cv.fy), v1 = pix_ray(Y1, cv.cy, cv.fy);
+  const int64_t vbase = (int64_t)v * n;
+  const int m = min(len, kZsPrefix);
+  uint32_t cap = 0xffffffffu;   // z_lo of the first record after the prefix
+  if (len > m) cap = f2ord(pcoef[3 * (vbase + ids[begin + m]) + 2].y);
+  int P = 64;
+  while (P < m) P <<= 1;
+  constexpr uint32_t kSlot = (1u << kZsSlotBits) - 1u;
+  for (int i = threadIdx.x; i < P; i += kZsBlock) {
+    uint32_t w = 0xffffffffu;
+    if (i < m) {
+      const int64_t e = vbase + ids[begin + i];
+      const float z = pix_box_bound_uv(pcoef[3 * e], pcoef[3 * e + 1], pcoef[3 * e + 2], u0, u1,
+                                       v0, v1);
+      w = (f2ord(z) & ~kSlot) | (uint32_t)i;
+    }
+    s[i] = w;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < (P >> 1); i += kZsBlock) {
+        const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1)), b = a + j;
+        const uint32_t x = s[a], y = s[b];
+        if ((x > y) == ((a & k) == 0)) {
+          s[a] = y;
+          s[b] = x;
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < m; i += kZsBlock) {
+    const uint32_t w = s[i];
+    const uint32_t beta = min(w & ~kSlot, cap);
+    out[begin + i] = ((uint64_t)beta << 32) | ids[begin + (w & kSlot)];
   }
 }
 
@@ -206,13 +337,13 @@ struct PxWindow {
   typedef unsigned long long KeyV __attribute__((ext_vector_type(K)));
   typedef float AlphaV __attribute__((ext_vector_type(K)));
   KeyV k;
-  AlphaV a;
+  AlphaV a, r, g, b;   // alpha and colour of each entry
   int n;
   __device__ __attribute__((always_inline)) void clear() {
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       k[q] = ~0ull;
-      a[q] = 0.0f;
+      a[q] = r[q] = g[q] = b[q] = 0.0f;
     }
     n = 0;
   }
@@ -222,21 +353,32 @@ struct PxWindow {
     for (int q = 0; q < K - 1; ++q) {
       k[q] = go ? k[q + 1] : k[q];
       a[q] = go ? a[q + 1] : a[q];
+      r[q] = go ? r[q + 1] : r[q];
+      g[q] = go ? g[q + 1] : g[q];
+      b[q] = go ? b[q + 1] : b[q];
     }
     k[K - 1] = go ? ~0ull : k[K - 1];
     n -= go ? 1 : 0;
   }
   // insert into a window with a free slot: one compare-exchange pass
-  __device__ __attribute__((always_inline)) void insert(uint64_t key, float al) {
+  __device__ __attribute__((always_inline)) void insert(uint64_t key, float al, float cr, float cg,
+                                                        float cb) {
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       const bool lt = key < k[q];
       const uint64_t tk = lt ? k[q] : key;
-      const float ta = lt ? a[q] : al;
+      const float ta = lt ? a[q] : al, tr = lt ? r[q] : cr, tg = lt ? g[q] : cg,
+                  tb = lt ? b[q] : cb;
       k[q] = lt ? key : k[q];
       a[q] = lt ? al : a[q];
+      r[q] = lt ? cr : r[q];
+      g[q] = lt ? cg : g[q];
+      b[q] = lt ? cb : b[q];
       key = tk;
       al = ta;
+      cr = tr;
+      cg = tg;
+      cb = tb;
     }
     ++n;
   }
@@ -252,21 +394,23 @@ struct PxCfg {
 // One workgroup per tile in the longest-first schedule, one wave per 8x8
 // sub-tile, one pixel per lane.  Records are staged in batches with a ballot
 // per sub-tile of those whose rectangle reaches it.  A lane's window holds
-// (key bits << 32 | index) ascending with the contribution's alpha; free
-// slots hold ~0.
+// (key bits << 32 | index) ascending with the contribution's alpha and
+// colour; free slots hold ~0.
 template <int TILE>
 __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ rec, const float4* __restrict__ pcoef, int64_t n, KViews views,
+    const uint32_t* __restrict__ order, const uint64_t* __restrict__ tkey,
+    const uint32_t* __restrict__ ids, const float4* __restrict__ rec, const float4* __restrict__ pcoef, int64_t n, KViews views,
     GsOpt o, int64_t tiles_x, int64_t tiles_per_view, const uint2* __restrict__ ranges,
     float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_t,
     int32_t* __restrict__ out_n, uint32_t* __restrict__ fix_list,
     uint32_t* __restrict__ fix_count) {
   using Cfg = PxCfg<TILE>;
   constexpr int BLOCK = Cfg::BLOCK, NW = Cfg::NW, NQ = Cfg::NQ, K = kPxWindow;
-  __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_q0[BLOCK], s_q1[BLOCK], s_q2[BLOCK];
+  __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK], s_q0[BLOCK], s_q1[BLOCK], s_q2[BLOCK];
   __shared__ uint32_t s_id[BLOCK];
   __shared__ uint64_t s_mask[NW][NW];
+  __shared__ uint32_t s_beta[BLOCK];         // per record: its position's bound word
+  __shared__ uint32_t s_bound[NW][BLOCK];   // per sub-tile and record: release bound
   const int64_t tglob = order[blockIdx.x];
   const int v = (int)(tglob / tiles_per_view);
   const int64_t tl = tglob - (int64_t)v * tiles_per_view;
@@ -288,17 +432,14 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
   // blend the window's first entry (lanes where `go`), then shift it out
   auto pop = [&](bool go) __attribute__((always_inline)) {
     if (go) {
-      const uint32_t gi = (uint32_t)win.k[0];
-      const int64_t e = (int64_t)v * n + gi;
-      const float4 r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
       const float w0 = win.a[0] * T;
       const float Tn = T - w0;
       if (Tn < tmin) {
         alive = false;   // stops before this contribution; the rest is moot
       } else {
-        C0 = fmaf(r1.z, w0, C0);
-        C1 = fmaf(r1.w, w0, C1);
-        C2 = fmaf(r2.x, w0, C2);
+        C0 = fmaf(win.r[0], w0, C0);
+        C1 = fmaf(win.g[0], w0, C1);
+        C2 = fmaf(win.b[0], w0, C2);
         D = fmaf(ord2f((uint32_t)(win.k[0] >> 32)), w0, D);
         T = Tn;
         ++cnt;
@@ -314,12 +455,15 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
     const bool has = jr < end;
     int x0 = 1, x1 = 0, y0 = 1, y1 = 0;
     if (has) {
-      const uint32_t id = ids[jr];
+      const uint64_t wd = zs_word(tkey, ids, pcoef, (int64_t)v * n, begin, jr);
+      const uint32_t id = (uint32_t)wd;
+      s_beta[tid] = (uint32_t)(wd >> 32);
       const int64_t e = (int64_t)v * n + (id < (uint64_t)n ? id : 0);
       float4 a, b, c;
       gs_stage(rec, e, a, b, c);
       s_a[tid] = a;
       s_b[tid] = b;
+      s_c[tid] = c;
       s_q0[tid] = pcoef[3 * e];
       s_q1[tid] = pcoef[3 * e + 1];
       s_q2[tid] = pcoef[3 * e + 2];
@@ -336,14 +480,49 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
       if (lane == 0) s_mask[w][wave] = m;
     }
     __syncthreads();
+    if (!__ballot(alive)) continue;
+    // Release bounds.  One sub-tile: the bound word of record k's position.
+    // Several: walking this batch's records backwards, before record k every
+    // later key at any pixel of the sub-tile is at least the least key of
+    // records k.. of the batch over the sub-tile's pixels (a wave minimum of
+    // exact keys), and at least the bound word of the next batch's first
+    // position.
+    if constexpr (NW > 1) {
+      uint32_t bound =
+          b0 + BLOCK < end
+              ? (uint32_t)(zs_word(tkey, ids, pcoef, (int64_t)v * n, begin, b0 + BLOCK) >> 32)
+              : 0xffffffffu;
+      for (int g = NW - 1; g >= 0; --g) {
+        uint64_t m = s_mask[wave][g];
+        while (m) {
+          const int bit = 63 - __builtin_clzll(m);
+          m &= ~(1ull << bit);
+          const int k = g * 64 + bit;
+          const float4 b = s_b[k];
+          const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
+          const bool inr = px < W && py < H && px >= (int)(lo & 0xffffu) &&
+                           px <= (int)(hi & 0xffffu) && py >= (int)(lo >> 16) &&
+                           py <= (int)(hi >> 16);
+          uint32_t kb = inr ? pix_key_bits(s_q0[k], s_q1[k], s_q2[k], ur, vr) : 0xffffffffu;
+#pragma unroll
+          for (int sh = 32; sh > 0; sh >>= 1) kb = min(kb, (uint32_t)__shfl_xor((int)kb, sh, 64));
+          bound = min(bound, kb);
+          if (lane == 0) s_bound[wave][k] = bound;
+        }
+      }
+      // lane 0's bounds are read by the whole wave below
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     for (int g = 0; g < NW; ++g) {
       uint64_t m = s_mask[wave][g];
       while (m && __ballot(alive)) {
         const int k = g * 64 + __builtin_ctzll(m);
         m &= m - 1;
         const float4 q2 = s_q2[k];
-        const uint32_t zlo = f2ord(q2.y);
-        // pending entries below this record's bound precede every later one
+        const uint32_t zlo = NW > 1 ? s_bound[wave][k] : s_beta[k];
+        // pending entries below the bound precede every later contribution
         while (true) {
           const bool go = alive && win.n > 0 && (uint32_t)(win.k[0] >> 32) < zlo;
           if (!__ballot(go)) break;
@@ -363,10 +542,18 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
                                s_id[k];
           // a full window must release its least entry before it is known
           // to be the next: the pixel is redone exactly
-          const bool full = win.n == K;
-          if (full && !((uint32_t)(win.k[0] >> 32) < zlo)) inexact = true;
-          if (full) pop(true);
-          if (alive) win.insert(key, al);
+          if (win.n == K) {
+            if ((uint32_t)(win.k[0] >> 32) < zlo) {
+              pop(true);
+            } else {
+              inexact = true;   // the rest of this pixel is moot
+              alive = false;
+            }
+          }
+          if (alive) {
+            const float4 c = s_c[k];
+            win.insert(key, al, c.x, c.y, c.z);
+          }
         }
       }
     }
@@ -391,20 +578,65 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
   }
 }
 
-// Exact per-pixel order for the queued pixels: one wave per pixel; every
-// round the lanes scan the pixel's tile list for the least (key, index) above
-// the last blended one, reduce it over the wave and blend it, until the pixel
-// stops or no contribution is left.
-__global__ __launch_bounds__(256) void k_gs_blend_px_fix(
+// Exact per-pixel order for the queued pixels, one wave per pixel.  The
+// pixel's tile list (in bound-word order) is read 64 records at a time;
+// its contributions join a pending set in LDS, and after each chunk the
+// pending entries below the next position's bound are taken out, sorted
+// (bitonic, in LDS) and blended in order.  A pixel
+// whose pending set outgrows kFixCap continues by repeated selection: each
+// round picks the least (key, index) above the last blended one, scanning
+// the list until the bound words pass it.
+constexpr int kFixCap = 512, kFixWaves = 4;
+
+struct FixAcc {
+  float T, C0, C1, C2, D;
+  int cnt;
+  bool stop;
+};
+
+// Blend one contribution (wave-uniform values); false once the pixel stops.
+__device__ __attribute__((always_inline)) inline bool fix_blend(FixAcc& s, float al, float r0,
+                                                                float r1, float r2, float z,
+                                                                float tmin) {
+  const float w0 = al * s.T;
+  const float Tn = s.T - w0;
+  if (Tn < tmin) {
+    s.stop = true;
+    return false;
+  }
+  s.C0 = fmaf(r0, w0, s.C0);
+  s.C1 = fmaf(r1, w0, s.C1);
+  s.C2 = fmaf(r2, w0, s.C2);
+  s.D = fmaf(z, w0, s.D);
+  s.T = Tn;
+  ++s.cnt;
+  return true;
+}
+
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * kFixWaves) void k_gs_blend_px_fix(
     const uint32_t* __restrict__ fix_list, const uint32_t* __restrict__ fix_count,
-    const uint32_t* __restrict__ ids, const float4* __restrict__ rec,
-    const float4* __restrict__ pcoef, int64_t n, KViews views, GsOpt o, int tile,
+    const uint64_t* __restrict__ tkey, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ rec, const float4* __restrict__ pcoef, int64_t n, KViews views,
+    GsOpt o, int tile,
     int64_t tiles_x, int64_t tiles_per_view, const uint2* __restrict__ ranges,
     float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_t,
     int32_t* __restrict__ out_n) {
-  const int lane = threadIdx.x & 63;
+  __shared__ uint64_t s_pk[kFixWaves][kFixCap], s_rk[kFixWaves][kFixCap];
+  __shared__ float s_pa[kFixWaves][kFixCap], s_ra[kFixWaves][kFixCap];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t* pk = s_pk[wave];
+  uint64_t* rk = s_rk[wave];
+  float* pa = s_pa[wave];
+  float* ra = s_ra[wave];
+  const uint64_t below = (1ull << lane) - 1ull;
   const uint32_t nfix = *fix_count;
-  for (uint32_t f = blockIdx.x * 4u + (threadIdx.x >> 6); f < nfix; f += gridDim.x * 4u) {
+  for (uint32_t f = blockIdx.x * kFixWaves + wave; f < nfix; f += gridDim.x * kFixWaves) {
     const int64_t pix = fix_list[f];
     const KView& cv0 = views.v[0];
     const int64_t plane = (int64_t)cv0.W * cv0.H;
@@ -414,68 +646,195 @@ __global__ __launch_bounds__(256) void k_gs_blend_px_fix(
     const int py = (int)(off / cv.W), px = (int)(off - (int64_t)py * cv.W);
     const float xc = (float)px + 0.5f, yc = (float)py + 0.5f;
     const float ur = pix_ray(px, cv.cx, cv.fx), vr = pix_ray(py, cv.cy, cv.fy);
-    const uint2 rg = ranges[(int64_t)v * tiles_per_view + (int64_t)(py / tile) * tiles_x + px / tile];
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
-    int cnt = 0;
-    uint64_t last = 0;
-    bool first = true;
-    while (true) {
-      uint64_t best = ~0ull;
-      float best_al = 0.0f;
-      for (uint32_t j = rg.x + lane; j < rg.y; j += 64) {
-        const uint32_t id = ids[j];
-        const int64_t e = (int64_t)v * n + id;
-        float4 a, b, c;
-        gs_stage(rec, e, a, b, c);
-        const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
-        if (!(px >= (int)(lo & 0xffffu) && px <= (int)(hi & 0xffffu) && py >= (int)(lo >> 16) &&
-              py <= (int)(hi >> 16)))
-          continue;
-        const float dx = a.x - xc, dy = a.y - yc;
-        const float P = (a.z * dx) * dx, R = a.w * dx;
-        const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
-        const float al = fminf(b.y * __builtin_amdgcn_exp2f(qq), o.aclamp);
-        if (!(al >= o.amin)) continue;
-        const uint64_t key =
-            ((uint64_t)pix_key_bits(pcoef[3 * e], pcoef[3 * e + 1], pcoef[3 * e + 2], ur, vr)
+    const uint2 rg =
+        ranges[(int64_t)v * tiles_per_view + (int64_t)(py / tile) * tiles_x + px / tile];
+    // this lane's record j: its (key, index) and alpha at the pixel, if it
+    // contributes
+    auto eval = [&](uint32_t j, uint64_t& key, float& al) -> bool {
+      const uint32_t id = (uint32_t)zs_word(tkey, ids, pcoef, (int64_t)v * n, rg.x, j);
+      const int64_t e = (int64_t)v * n + id;
+      float4 a, b, c;
+      gs_stage(rec, e, a, b, c);
+      const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
+      if (!(px >= (int)(lo & 0xffffu) && px <= (int)(hi & 0xffffu) && py >= (int)(lo >> 16) &&
+            py <= (int)(hi >> 16)))
+        return false;
+      const float dx = a.x - xc, dy = a.y - yc;
+      const float P = (a.z * dx) * dx, R = a.w * dx;
+      const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
+      al = fminf(b.y * __builtin_amdgcn_exp2f(qq), o.aclamp);
+      if (!(al >= o.amin)) return false;
+      key = ((uint64_t)pix_key_bits(pcoef[3 * e], pcoef[3 * e + 1], pcoef[3 * e + 2], ur, vr)
              << 32) | id;
-        if ((first || key > last) && key < best) {
-          best = key;
-          best_al = al;
+      return true;
+    };
+    FixAcc acc{1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, false};
+    int np = 0;   // pending entries (wave-uniform)
+    bool overflow = false;
+    uint64_t last = 0;   // the last blended (key, index), valid unless `first`
+    bool first = true;
+    // take the pending entries below `bound` out, sort them, blend them
+    auto release = [&](uint32_t bound) {
+      int r = 0, keep = 0;
+      for (int b0 = 0; b0 < np; b0 += 64) {
+        const int i = b0 + lane;
+        const bool has = i < np;
+        const uint64_t k = has ? pk[i] : ~0ull;
+        const float al = has ? pa[i] : 0.0f;
+        const bool out = has && (uint32_t)(k >> 32) < bound;
+        const uint64_t mo = __ballot(out), mk = __ballot(has && !out);
+        wave_sync_lds();
+        if (out) {
+          const int q = r + __builtin_popcountll(mo & below);
+          rk[q] = k;
+          ra[q] = al;
         }
+        if (has && !out) {
+          const int q = keep + __builtin_popcountll(mk & below);
+          pk[q] = k;
+          pa[q] = al;
+        }
+        r += __builtin_popcountll(mo);
+        keep += __builtin_popcountll(mk);
       }
-      uint64_t mn = best;
+      wave_sync_lds();
+      np = keep;
+      if (r == 0) return;
+      // blend sorted entries: lane q holds the q-th of m (key, alpha)
+      auto blend64 = [&](uint64_t k, float al, int m) {
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        if (lane < m) {
+          const int64_t e = (int64_t)v * n + (uint32_t)k;
+          const float4 r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
+          c0 = r1.z;
+          c1 = r1.w;
+          c2 = r2.x;
+        }
+        for (int q = 0; q < m; ++q) {
+          const uint64_t kq = __shfl(k, q, 64);
+          if (!fix_blend(acc, __shfl(al, q, 64), __shfl(c0, q, 64), __shfl(c1, q, 64),
+                         __shfl(c2, q, 64), ord2f((uint32_t)(kq >> 32)), o.tmin))
+            break;
+          last = kq;
+          first = false;
+        }
+      };
+      if (r <= 64) {
+        // bitonic sort across the wave's lanes, in registers
+        uint64_t k = lane < r ? rk[lane] : ~0ull;
+        float al = lane < r ? ra[lane] : 0.0f;
+        for (int kk = 2; kk <= 64; kk <<= 1)
+          for (int j = kk >> 1; j > 0; j >>= 1) {
+            const uint64_t ok = __shfl_xor(k, j, 64);
+            const float oa = __shfl_xor(al, j, 64);
+            const bool take_min = ((lane & j) == 0) == ((lane & kk) == 0);
+            if (take_min ? ok < k : ok > k) {
+              k = ok;
+              al = oa;
+            }
+          }
+        blend64(k, al, r);
+        return;
+      }
+      int P = 64;
+      while (P < r) P <<= 1;
+      for (int i = r + lane; i < P; i += 64) rk[i] = ~0ull;
+      wave_sync_lds();
+      for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = lane; i < (P >> 1); i += 64) {
+            const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1)), b = a + j;
+            const uint64_t x = rk[a], y = rk[b];
+            if ((x > y) == ((a & k) == 0)) {
+              rk[a] = y;
+              rk[b] = x;
+              const float t = ra[a];
+              ra[a] = ra[b];
+              ra[b] = t;
+            }
+          }
+          wave_sync_lds();
+        }
+      for (int b0 = 0; b0 < r && !acc.stop; b0 += 64) {
+        const int i = b0 + lane;
+        blend64(i < r ? rk[i] : ~0ull, i < r ? ra[i] : 0.0f, min(64, r - b0));
+      }
+    };
+    for (uint32_t c0 = rg.x; c0 < rg.y && !acc.stop; c0 += 64) {
+      const uint32_t j = c0 + lane;
+      uint64_t key = 0;
+      float al = 0.0f;
+      const bool ok = j < rg.y && eval(j, key, al);
+      const uint64_t m = __ballot(ok);
+      const int add = __builtin_popcountll(m);
+      if (np + add > kFixCap) {
+        overflow = true;
+        break;
+      }
+      if (ok) {
+        const int q = np + __builtin_popcountll(m & below);
+        pk[q] = key;
+        pa[q] = al;
+      }
+      np += add;
+      wave_sync_lds();
+      release(c0 + 64 < rg.y
+                  ? (uint32_t)(zs_word(tkey, ids, pcoef, (int64_t)v * n, rg.x, c0 + 64) >> 32)
+                  : 0xffffffffu);
+    }
+    if (!overflow && !acc.stop) release(0xffffffffu);
+    if (overflow) {
+      // What is blended so far is exact; continue by repeated selection of
+      // the least (key, index) above the last one.  A round's scan ends at
+      // the first chunk whose bound word passes the best key found so far.
+      while (true) {
+        uint64_t best = ~0ull;
+        float best_al = 0.0f;
+        for (uint32_t c0 = rg.x; c0 < rg.y; c0 += 64) {
+          const uint32_t j = c0 + lane;
+          uint64_t key;
+          float al;
+          if (j < rg.y && eval(j, key, al) && (first || key > last) && key < best) {
+            best = key;
+            best_al = al;
+          }
+          uint64_t mn = best;
 #pragma unroll
-      for (int s = 32; s > 0; s >>= 1) {
-        const uint64_t y = __shfl_xor(mn, s, 64);
-        mn = y < mn ? y : mn;
+          for (int sh = 32; sh > 0; sh >>= 1) {
+            const uint64_t y = __shfl_xor(mn, sh, 64);
+            mn = y < mn ? y : mn;
+          }
+          if (c0 + 64 < rg.y &&
+              (uint32_t)(zs_word(tkey, ids, pcoef, (int64_t)v * n, rg.x, c0 + 64) >> 32) >
+                  (uint32_t)(mn >> 32))
+            break;
+        }
+        uint64_t mn = best;
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) {
+          const uint64_t y = __shfl_xor(mn, sh, 64);
+          mn = y < mn ? y : mn;
+        }
+        if (mn == ~0ull) break;   // wave-uniform
+        const uint64_t holders = __ballot(best == mn);
+        const float al = __shfl(best_al, __builtin_ctzll(holders), 64);
+        const int64_t e = (int64_t)v * n + (uint32_t)mn;
+        const float4 r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
+        if (!fix_blend(acc, al, r1.z, r1.w, r2.x, ord2f((uint32_t)(mn >> 32)), o.tmin)) break;
+        last = mn;
+        first = false;
       }
-      if (mn == ~0ull) break;   // wave-uniform
-      const uint64_t holders = __ballot(best == mn);
-      const float al = __shfl(best_al, __builtin_ctzll(holders), 64);
-      const int64_t e = (int64_t)v * n + (uint32_t)mn;
-      const float4 r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
-      const float w0 = al * T;
-      const float Tn = T - w0;
-      if (Tn < o.tmin) break;
-      C0 = fmaf(r1.z, w0, C0);
-      C1 = fmaf(r1.w, w0, C1);
-      C2 = fmaf(r2.x, w0, C2);
-      D = fmaf(ord2f((uint32_t)(mn >> 32)), w0, D);
-      T = Tn;
-      ++cnt;
-      last = mn;
-      first = false;
     }
     if (lane == 0) {
       float* rgb = out_rgb + (int64_t)v * 3 * plane + off;
-      rgb[0] = C0 + T * o.bg[0];
-      rgb[plane] = C1 + T * o.bg[1];
-      rgb[2 * plane] = C2 + T * o.bg[2];
-      out_depth[(int64_t)v * plane + off] = D;
-      out_t[(int64_t)v * plane + off] = T;
-      out_n[(int64_t)v * plane + off] = cnt;
+      rgb[0] = acc.C0 + acc.T * o.bg[0];
+      rgb[plane] = acc.C1 + acc.T * o.bg[1];
+      rgb[2 * plane] = acc.C2 + acc.T * o.bg[2];
+      out_depth[(int64_t)v * plane + off] = acc.D;
+      out_t[(int64_t)v * plane + off] = acc.T;
+      out_n[(int64_t)v * plane + off] = acc.cnt;
     }
+    wave_sync_lds();   // LDS reuse by the next pixel
   }
 }
 
@@ -488,9 +847,18 @@ void launch_gs_pixdepth(const RenderWs& L, void* ws, const float* mean, const fl
                      at<uint32_t>(ws, L.fix_count));
 }
 
+void launch_gs_tile_zsort(const RenderWs& L, void* ws, int64_t n, const KViews& kv, int tile,
+                         hipStream_t st) {
+  if (L.tiles_total == 0) return;
+  hipLaunchKernelGGL(k_gs_tile_zsort, dim3((unsigned)L.tiles_total), dim3(kZsBlock), 0, st,
+                     at<uint32_t>(ws, L.ids), at<float4>(ws, L.pcoef), n, kv, tile, L.tiles_x,
+                     L.tiles_x * L.tiles_y, at<uint2>(ws, L.ranges), at<uint64_t>(ws, L.tkey));
+}
+
 void launch_gs_blend_px(const RenderWs& L, void* ws, int64_t n, const uint32_t* order,
                         const KViews& kv, const GsOpt& o, float* rgb, float* depth, float* tf,
                         int32_t* nc, hipStream_t st) {
+  const uint64_t* tk = at<uint64_t>(ws, L.tkey);
   const uint32_t* ids = at<uint32_t>(ws, L.ids);
   const float4* rec = at<float4>(ws, L.rec);
   const float4* pc = at<float4>(ws, L.pcoef);
@@ -501,22 +869,17 @@ void launch_gs_blend_px(const RenderWs& L, void* ws, int64_t n, const uint32_t* 
   switch (o.tile) {
     case 8:
       hipLaunchKernelGGL(k_gs_blend_px<8>, dim3((unsigned)L.tiles_total), dim3(PxCfg<8>::BLOCK),
-                         0, st, order, ids, rec, pc, n, kv, o, L.tiles_x, tpv, ranges, rgb, depth,
-                         tf, nc, fl, fc);
+                         0, st, order, tk, ids, rec, pc, n, kv, o, L.tiles_x, tpv, ranges, rgb,
+                         depth, tf, nc, fl, fc);
       break;
-    case 16:
+    default:  // 16 (the entry point rejects larger tiles in this order)
       hipLaunchKernelGGL(k_gs_blend_px<16>, dim3((unsigned)L.tiles_total), dim3(PxCfg<16>::BLOCK),
-                         0, st, order, ids, rec, pc, n, kv, o, L.tiles_x, tpv, ranges, rgb, depth,
-                         tf, nc, fl, fc);
-      break;
-    default:
-      hipLaunchKernelGGL(k_gs_blend_px<32>, dim3((unsigned)L.tiles_total), dim3(PxCfg<32>::BLOCK),
-                         0, st, order, ids, rec, pc, n, kv, o, L.tiles_x, tpv, ranges, rgb, depth,
-                         tf, nc, fl, fc);
+                         0, st, order, tk, ids, rec, pc, n, kv, o, L.tiles_x, tpv, ranges, rgb,
+                         depth, tf, nc, fl, fc);
       break;
   }
-  hipLaunchKernelGGL(k_gs_blend_px_fix, dim3(1024), dim3(256), 0, st, fl, fc, ids, rec, pc, n, kv,
-                     o, o.tile, L.tiles_x, tpv, ranges, rgb, depth, tf, nc);
+  hipLaunchKernelGGL(k_gs_blend_px_fix, dim3(1024), dim3(64 * kFixWaves), 0, st, fl, fc, tk, ids,
+                     rec, pc, n, kv, o, o.tile, L.tiles_x, tpv, ranges, rgb, depth, tf, nc);
 }
 
 }  // namespace vrs
