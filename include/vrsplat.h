@@ -236,6 +236,81 @@ vrs_status vrs_render_gaussians_backward(const float* mean, const float* cov,
                                          float* d_cov, float* d_opacity, float* d_sh, void* ws,
                                          size_t ws_bytes, int64_t max_pairs, void* stream);
 
+/* ------------------------------------------------------- tone mapping
+ * The combined image mapped to a displayable range by a differentiable
+ * camera model (Sec. 3.4, last paragraph, following ADOP; the paper does not
+ * restate the model, so this is the library's reading).  Per view v, channel
+ * c and pixel (x, y):
+ *   t = ((x_in * e) * wb[c]) * vig,  e = 2^-ev (double precision, rounded),
+ *   vig = ((k3 r2 + k2) r2 + k1) r2 + 1,  r2 = (dy dy + dx dx) inv_d2,
+ *   dx = (x + 0.5) - cx, dy = (y + 0.5) - cy (the view's principal point),
+ *   inv_d2 = 1 / ((W/2)^2 + (H/2)^2) rounded from double precision,
+ *   s = clamp(t, 0, 1) (n - 1), i = min(floor(s), n - 2), f = s - i,
+ *   out = R_i + f (R_{i+1} - R_i)
+ * (single precision, in that order: t decides the segment and the clamp).
+ * in, out: DEVICE float32 [V][3][H][W] (out may be in; every view of one
+ * size).  params: DEVICE float32 [V][7 + n_resp] = ev, wb_r, wb_g, wb_b, k1,
+ * k2, k3, R_0 .. R_{n_resp-1}.  2 <= n_resp <= 256.  VRS_EINVAL on null
+ * pointers, mismatched view sizes or a bad n_resp. */
+vrs_status vrs_tonemap(const float* in, const vrs_view* views, int n_views, const float* params,
+                       int n_resp, float* out, void* stream);
+/* Adjoint of vrs_tonemap for d_out [V][3][H][W]: d_in (may be NULL) is
+ * WRITTEN; d_params [V][7 + n_resp] (may be NULL) is ACCUMULATED (sums over
+ * the pixels reduced in a fixed order per parameter; the response samples'
+ * sums are accumulated per block with LDS atomics, whose order may vary).
+ * The clamp has zero derivative outside (0, 1).  ws: DEVICE workspace of
+ * vrs_tonemap_workspace_size bytes, needed when d_params is given. */
+size_t vrs_tonemap_workspace_size(const vrs_view* views, int n_views, int n_resp);
+vrs_status vrs_tonemap_backward(const float* in, const vrs_view* views, int n_views,
+                                const float* params, int n_resp, const float* d_out, float* d_in,
+                                float* d_params, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------- training loss
+ * D-SSIM of Eq. 6 (as in 3DGS): 1 - mean over every element of the SSIM
+ * map of x against y, planes of [planes][H][W] float32 (DEVICE; e.g.
+ * images x channels), with the 11 x 11 window of the 11-tap Gaussian of
+ * sigma 1.5 normalised to sum 1 (outer product), zero padding outside each
+ * plane, C1 = 0.01^2, C2 = 0.03^2, the variances as E[x^2] - mu^2.  loss:
+ * DEVICE float32 [1] written.  ws: DEVICE workspace of
+ * vrs_dssim_workspace_size bytes (the same size serves the adjoint). */
+size_t vrs_dssim_workspace_size(int planes, int width, int height);
+vrs_status vrs_dssim(const float* x, const float* y, int planes, int width, int height,
+                     float* loss, void* ws, size_t ws_bytes, void* stream);
+/* Adjoint with respect to x: d_x += d_loss * d(D-SSIM)/dx, d_loss a DEVICE
+ * float32 scalar (NULL: 1). */
+vrs_status vrs_dssim_backward(const float* x, const float* y, int planes, int width, int height,
+                              const float* d_loss, float* d_x, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* The regulariser of Eq. 7: R = |mean F - mean crop(P)|, the means over
+ * every pixel and channel of all crops together: F the decoder output
+ * (DEVICE, packed [crop][3][S][S] as vrs_decode_fovea writes it), P the
+ * periphery [V][3][H][W] (DEVICE), crop k covering view pixels
+ * [x0, x0 + S) x [y0, y0 + S) (from `place` when not NULL, as for
+ * vrs_composite_frame).  r: DEVICE float32 [2] = R, mean F - mean crop(P)
+ * (sums in double precision, fixed order).  ws: DEVICE workspace of
+ * vrs_regulariser_workspace_size() bytes. */
+size_t vrs_regulariser_workspace_size(void);
+vrs_status vrs_regulariser(const float* fovea_rgb, const float* rgb, int n_views, int width,
+                           int height, const vrs_crop* crops, int n_crops,
+                           const vrs_crop_place* place, float* r, void* ws, size_t ws_bytes,
+                           void* stream);
+/* Adjoint: with g = d_r sign(r[1]) / (3 sum S^2) (d_r a DEVICE scalar, NULL:
+ * 1; sign(0) = 0), d_fovea += g and d_rgb -= g over every crop pixel (either
+ * may be NULL; overlapping crops add up). */
+vrs_status vrs_regulariser_backward(int n_views, int width, int height, const vrs_crop* crops,
+                                    int n_crops, const vrs_crop_place* place, const float* r,
+                                    const float* d_r, float* d_fovea, float* d_rgb,
+                                    void* stream);
+
+/* One Adam step (Kingma and Ba; the optimiser of Sec. 3.5) over n float32
+ * parameters in DEVICE memory, in place: m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, p -= lr (m / (1 - b1^step)) /
+ * (sqrt(v / (1 - b2^step)) + eps), step >= 1 (bias corrections from double
+ * precision).  All four arrays 16-byte aligned; VRS_EINVAL otherwise. */
+vrs_status vrs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
+                         int step, float lr, float beta1, float beta2, float eps, void* stream);
+
 /* ------------------------------------------------------- scene layout
  * Spatial (Morton, Z-order) permutation of a point set, for storing a static
  * scene so that points adjacent in memory are adjacent in space (a load-time

@@ -16,7 +16,9 @@ of the image, and R a response curve, piecewise linear through n samples
 at s_i = i / (n - 1).  Parameters per view: [ev, wb_r, wb_g, wb_b, k1, k2,
 k3, R_0 .. R_{n-1}].  On the segment [s_i, s_{i+1}] (i = min(floor(t (n-1)),
 n - 2)) R(t) = (1 - f) R_i + f R_{i+1}, f = t (n - 1) - i; the clamp has zero
-derivative outside (0, 1).
+derivative outside (0, 1).  The segment and the clamp are integer decisions:
+they are taken on t evaluated in single precision in a fixed order (see
+_decide32), the values in double precision.
 
 Training objective (Sec. 3.5, Eqs. 6-7): D-SSIM as in 3DGS (1 - SSIM,
 11 x 11 Gaussian window with sigma 1.5 normalised to sum 1, zero padding,
@@ -52,11 +54,25 @@ def vignette_r2(W, H, cx, cy):
     return (y[:, None] ** 2 + x[None, :] ** 2) / d2
 
 
-def _segments(t, n):
-    tc = np.clip(t, 0.0, 1.0)
-    s = tc * (n - 1)
+def _decide32(x, ev, wb_c, k, n, W, H, cx, cy):
+    """Segment index and inside-(0, 1) flag of every pixel of one channel,
+    from t in single precision: dx = (x + 0.5) - cx, r2 = (dx dx + dy dy)
+    inv_d2 with inv_d2 the rounded 1 / half-diagonal^2, vig = ((k3 r2 + k2)
+    r2 + k1) r2 + 1, e the rounded 2^-ev, t = ((x e) wb) vig; then
+    s = clamp(t, 0, 1) (n - 1), i = min(floor(s), n - 2)."""
+    f32 = np.float32
+    inv_d2 = f32(1.0 / ((W / 2.0) ** 2 + (H / 2.0) ** 2))
+    dx = (np.arange(W, dtype=f32) + f32(0.5)) - f32(cx)
+    dy = (np.arange(H, dtype=f32) + f32(0.5)) - f32(cy)
+    r2 = (dy[:, None] * dy[:, None] + dx[None, :] * dx[None, :]) * inv_d2
+    k = np.asarray(k, f32)
+    vig = ((k[2] * r2 + k[1]) * r2 + k[0]) * r2 + f32(1.0)
+    e = f32(2.0 ** (-float(ev)))
+    t = ((np.asarray(x, f32) * e) * f32(wb_c)) * vig
+    inside = (t > 0) & (t < 1)
+    s = np.clip(t, f32(0), f32(1)) * f32(n - 1)
     i = np.minimum(np.floor(s), n - 2).astype(np.int64)
-    return tc, i, s - i
+    return i, inside
 
 
 def tonemap(img, params, principal):
@@ -74,7 +90,8 @@ def tonemap(img, params, principal):
         vig = 1.0 + k[0] * r2 + k[1] * r2 ** 2 + k[2] * r2 ** 3
         for c in range(3):
             t = img[v, c] * 2.0 ** (-ev) * wb[c] * vig
-            tc, i, f = _segments(t, n)
+            i, _ = _decide32(img[v, c], ev, wb[c], k, n, W, H, *principal[v])
+            f = np.clip(t, 0.0, 1.0) * (n - 1) - i
             out[v, c] = (1.0 - f) * lut[i] + f * lut[i + 1]
             ts[v, c] = t
     return out, ts
@@ -97,13 +114,13 @@ def tonemap_backward(img, params, principal, d_out):
         for c in range(3):
             x = img[v, c]
             t = x * e * wb[c] * vig
-            tc, i, f = _segments(t, n)
+            i, inside = _decide32(x, ev, wb[c], k, n, W, H, *principal[v])
+            f = np.clip(t, 0.0, 1.0) * (n - 1) - i
             g = d_out[v, c]
             # response samples
             np.add.at(d_par[v, 7:], i, g * (1.0 - f))
             np.add.at(d_par[v, 7:], i + 1, g * f)
             # through the clamp: slope of the segment inside (0, 1)
-            inside = (t > 0.0) & (t < 1.0)
             dt = np.where(inside, g * (lut[i + 1] - lut[i]) * (n - 1), 0.0)
             d_img[v, c] = dt * e * wb[c] * vig
             d_par[v, 0] += np.sum(dt * t) * -np.log(2.0)

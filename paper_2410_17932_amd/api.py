@@ -132,6 +132,19 @@ SIGNATURES = {
     "vrs_composite_frame_backward": (_int, [_vp, _int, _int, _int, _vp, _P(Crop), _int, _vp,
                                             _int, _flt, _flt, _flt, _vp, _vp, _vp, _vp]),
     "vrs_l1_loss": (_int, [_vp, _vp, _i64, _vp, _vp, _flt, _vp]),
+    "vrs_tonemap": (_int, [_vp, _P(View), _int, _vp, _int, _vp, _vp]),
+    "vrs_tonemap_workspace_size": (_sz, [_P(View), _int, _int]),
+    "vrs_tonemap_backward": (_int, [_vp, _P(View), _int, _vp, _int, _vp, _vp, _vp, _vp, _sz,
+                                    _vp]),
+    "vrs_dssim_workspace_size": (_sz, [_int, _int, _int]),
+    "vrs_dssim": (_int, [_vp, _vp, _int, _int, _int, _vp, _vp, _sz, _vp]),
+    "vrs_dssim_backward": (_int, [_vp, _vp, _int, _int, _int, _vp, _vp, _vp, _sz, _vp]),
+    "vrs_regulariser_workspace_size": (_sz, []),
+    "vrs_regulariser": (_int, [_vp, _vp, _int, _int, _int, _P(Crop), _int, _vp, _vp, _vp, _sz,
+                               _vp]),
+    "vrs_regulariser_backward": (_int, [_int, _int, _int, _P(Crop), _int, _vp, _vp, _vp, _vp,
+                                        _vp, _vp]),
+    "vrs_adam_step": (_int, [_vp, _vp, _vp, _vp, _i64, _int, _flt, _flt, _flt, _flt, _vp]),
     "vrs_plan_create": (_int, [_P(PlanDesc), _P(_vp)]),
     "vrs_plan_destroy": (None, [_vp]),
     "vrs_workspace_size": (_sz, [_vp, _int]),
@@ -537,6 +550,101 @@ def composite_frame_backward(periphery, fovea, crops, d_out, d_periphery=None, d
         len(crops), ptr(place, torch.int32), mode, ring, m, gamma, ptr(d_out, torch.float32), ptr(d_periphery),
         ptr(d_fovea), _stream())
     _check(code, "vrs_composite_frame_backward")
+
+
+# ------------------------------------------------------------ tone mapping
+def tonemap_params(n_views, n_resp=32, gamma=1.0 / 2.2, device="cuda"):
+    """Neutral camera model (ev 0, unit white balance, no vignetting) with a
+    gamma response: float32 [V][7 + n_resp]."""
+    p = torch.zeros((n_views, 7 + n_resp), dtype=torch.float32)
+    p[:, 1:4] = 1.0
+    p[:, 7:] = torch.linspace(0.0, 1.0, n_resp, dtype=torch.float64).pow(gamma).float()
+    return p.to(device)
+
+
+def tonemap(img, views, params, out=None):
+    """vrs_tonemap: img [V][3][H][W] -> out (may be img)."""
+    V = img.shape[0]
+    n = params.shape[1] - 7
+    if out is None:
+        out = torch.empty_like(img)
+    _check(lib().vrs_tonemap(ptr(img, torch.float32), make_views(views), V,
+                             ptr(params, torch.float32), n, ptr(out), _stream()), "vrs_tonemap")
+    return out
+
+
+def tonemap_backward(img, views, params, d_out, d_img=None, d_params=None):
+    """vrs_tonemap_backward: d_img written (may be None), d_params
+    accumulated (may be None)."""
+    V = img.shape[0]
+    n = params.shape[1] - 7
+    cv = make_views(views)
+    ws = None
+    if d_params is not None:
+        size = lib().vrs_tonemap_workspace_size(cv, V, n)
+        ws = torch.empty(max(size, 1), dtype=torch.uint8, device=img.device)
+    _check(lib().vrs_tonemap_backward(ptr(img, torch.float32), cv, V, ptr(params, torch.float32),
+                                      n, ptr(d_out, torch.float32), ptr(d_img), ptr(d_params),
+                                      ptr(ws), 0 if ws is None else ws.numel(), _stream()),
+           "vrs_tonemap_backward")
+
+
+# --------------------------------------------------------- training loss
+class DssimWorkspace:
+    def __init__(self, planes, width, height, device="cuda"):
+        self.shape = (planes, height, width)
+        size = lib().vrs_dssim_workspace_size(planes, width, height)
+        if size == 0:
+            raise VrsError(VRS_EINVAL, "vrs_dssim_workspace_size")
+        self.buf = torch.empty(size, dtype=torch.uint8, device=device)
+
+
+def dssim(x, y, ws: DssimWorkspace, loss=None):
+    """vrs_dssim over x, y viewed as [planes][H][W]: device scalar."""
+    P, H, W = ws.shape
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().vrs_dssim(ptr(x, torch.float32), ptr(y, torch.float32), P, W, H, ptr(loss),
+                           ptr(ws.buf), ws.buf.numel(), _stream()), "vrs_dssim")
+    return loss
+
+
+def dssim_backward(x, y, ws: DssimWorkspace, d_x, d_loss=None):
+    P, H, W = ws.shape
+    _check(lib().vrs_dssim_backward(ptr(x, torch.float32), ptr(y, torch.float32), P, W, H,
+                                    ptr(d_loss, torch.float32), ptr(d_x), ptr(ws.buf),
+                                    ws.buf.numel(), _stream()), "vrs_dssim_backward")
+
+
+def regulariser(fovea, periphery, crops, place=None, r=None):
+    """vrs_regulariser: device [2] = (R, mean F - mean crop(P))."""
+    V, _, H, W = periphery.shape
+    if r is None:
+        r = torch.empty(2, dtype=torch.float32, device=periphery.device)
+    ws = torch.empty(lib().vrs_regulariser_workspace_size(), dtype=torch.uint8,
+                     device=periphery.device)
+    _check(lib().vrs_regulariser(ptr(fovea, torch.float32), ptr(periphery, torch.float32), V, W,
+                                 H, make_crops(crops), len(crops), ptr(place, torch.int32),
+                                 ptr(r), ptr(ws), ws.numel(), _stream()), "vrs_regulariser")
+    return r
+
+
+def regulariser_backward(periphery_shape, crops, r, d_r=None, d_fovea=None, d_periphery=None,
+                         place=None):
+    V, _, H, W = periphery_shape
+    _check(lib().vrs_regulariser_backward(V, W, H, make_crops(crops), len(crops),
+                                          ptr(place, torch.int32), ptr(r, torch.float32),
+                                          ptr(d_r, torch.float32), ptr(d_fovea),
+                                          ptr(d_periphery), _stream()),
+           "vrs_regulariser_backward")
+
+
+def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """vrs_adam_step in place on float32 tensors of one size."""
+    n = param.numel()
+    _check(lib().vrs_adam_step(ptr(param, torch.float32), ptr(grad, torch.float32),
+                               ptr(m, torch.float32), ptr(v, torch.float32), n, step, lr, beta1,
+                               beta2, eps, _stream()), "vrs_adam_step")
 
 
 # ------------------------------------------------------------ frame plan

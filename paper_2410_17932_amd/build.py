@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libvrsplat.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["host.hip", "prims.hip", "gs_forward.hip", "gs_blend.hip", "gs_pixel.hip", "points.hip", "decoder.hip", "composite.hip",
-           "bake.hip", "gs_backward.hip", "order.hip", "frame.hip"]
+           "bake.hip", "gs_backward.hip", "order.hip", "frame.hip", "post.hip"]
 
 
 def hipcc() -> str:

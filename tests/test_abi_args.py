@@ -280,3 +280,78 @@ def test_valid_arguments_pass_the_host_checks():
     r = L().vrs_composite_frame(P, 2, 64, 48, P, _crops([(0, 0, 0, 32)]), 1, None, 0, 8.0, 0.75,
                                 0.2, P, None)
     assert r not in (api.VRS_OK, EINVAL)
+
+
+# ------------------------------------------------ tone mapping and losses
+def _tonemap(**kw):
+    a = dict(inp=P, views=_views(), nv=2, params=P, n=32, out=P)
+    a.update(kw)
+    return L().vrs_tonemap(a["inp"], a["views"], a["nv"], a["params"], a["n"], a["out"], None)
+
+
+@pytest.mark.parametrize("bad", [dict(inp=NUL), dict(params=NUL), dict(out=NUL), dict(n=1),
+                                 dict(n=257), dict(nv=0), dict(nv=9), dict(views=None)])
+def test_tonemap_rejects(bad):
+    assert _tonemap(**bad) == EINVAL
+
+
+def test_tonemap_rejects_mixed_view_sizes():
+    v = api.make_views([synth.pinhole(64, 48, 60.0), synth.pinhole(64, 40, 60.0)])
+    assert _tonemap(views=v) == EINVAL
+    assert L().vrs_tonemap_workspace_size(v, 2, 32) == 0
+
+
+@pytest.mark.parametrize("bad", [dict(inp=NUL), dict(d_out=NUL), dict(ws=NUL),
+                                 dict(ws_bytes=8), dict(n=300)])
+def test_tonemap_backward_rejects(bad):
+    a = dict(inp=P, params=P, n=32, d_out=P, d_in=P, d_par=P, ws=P, ws_bytes=1 << 40)
+    a.update(bad)
+    assert L().vrs_tonemap_backward(a["inp"], _views(), 2, a["params"], a["n"], a["d_out"],
+                                    a["d_in"], a["d_par"], a["ws"], a["ws_bytes"], None) == EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(x=NUL), dict(y=NUL), dict(loss=NUL), dict(ws=NUL),
+                                 dict(ws_bytes=4), dict(planes=0), dict(w=0), dict(h=-3)])
+def test_dssim_rejects(bad):
+    a = dict(x=P, y=P, planes=3, w=64, h=48, loss=P, ws=P, ws_bytes=1 << 40)
+    a.update(bad)
+    assert L().vrs_dssim(a["x"], a["y"], a["planes"], a["w"], a["h"], a["loss"], a["ws"],
+                         a["ws_bytes"], None) == EINVAL
+    assert L().vrs_dssim_backward(a["x"], a["y"], a["planes"], a["w"], a["h"], None,
+                                  a["loss"], a["ws"], a["ws_bytes"], None) == EINVAL
+
+
+def test_dssim_workspace_holds_the_adjoint_maps():
+    assert L().vrs_dssim_workspace_size(3, 64, 48) >= 3 * 3 * 64 * 48 * 4
+    assert L().vrs_dssim_workspace_size(0, 64, 48) == 0
+
+
+@pytest.mark.parametrize("bad", [dict(crops=[]), dict(crops=[(2, 0, 0, 16)]),
+                                 dict(crops=[(0, 60, 0, 16)]), dict(crops=[(0, 0, 0, 49)]),
+                                 dict(fov=NUL), dict(rgb=NUL), dict(r=NUL), dict(ws=NUL),
+                                 dict(ws_bytes=8), dict(nv=0)])
+def test_regulariser_rejects(bad):
+    a = dict(fov=P, rgb=P, nv=2, crops=[(0, 4, 4, 16), (1, 10, 2, 32)], r=P, ws=P,
+             ws_bytes=1 << 20)
+    a.update(bad)
+    c = a["crops"]
+    assert L().vrs_regulariser(a["fov"], a["rgb"], a["nv"], 64, 48, _crops(c), len(c), None,
+                               a["r"], a["ws"], a["ws_bytes"], None) == EINVAL
+
+
+def test_regulariser_backward_rejects():
+    c = [(0, 4, 4, 16)]
+    assert L().vrs_regulariser_backward(2, 64, 48, _crops(c), 1, None, None, None, P, P,
+                                        None) == EINVAL
+    assert L().vrs_regulariser_backward(2, 64, 48, _crops([]), 0, None, P, None, P, P,
+                                        None) == EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(step=0), dict(n=-1), dict(p=NUL), dict(g=NUL),
+                                 dict(m=NUL), dict(v=NUL), dict(b1=1.0), dict(b2=-0.1),
+                                 dict(eps=-1.0), dict(p=ctypes.c_void_p(0x1004))])
+def test_adam_rejects(bad):
+    a = dict(p=P, g=P, m=P, v=P, n=100, step=1, b1=0.9, b2=0.999, eps=1e-15)
+    a.update(bad)
+    assert L().vrs_adam_step(a["p"], a["g"], a["m"], a["v"], a["n"], a["step"], 0.01, a["b1"],
+                             a["b2"], a["eps"], None) == EINVAL
