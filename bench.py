@@ -269,6 +269,87 @@ def secondary_and_standalone(scene, tile, radix, steps):
     return out
 
 
+def _event_ms(fn, steps):
+    """Milliseconds per call of fn() (enqueued on the current stream),
+    between HIP events, after one untimed call."""
+    import torch
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def post_and_training(scene, steps):
+    """Tone mapping of the full stereo frame (forward and adjoint), and the
+    training objective's kernels at the fitting step's sizes: D-SSIM of four
+    1024^2 RGB views (forward and adjoint), the regulariser over this frame's
+    crops, and one Adam step over the fitting scene's parameter count (1M
+    Gaussians x 59 floats + 2M points x 8 floats).  Each with its
+    algorithmic HBM bytes and the fraction of 8 TB/s."""
+    import torch
+    from paper_2410_17932_amd import api
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(9)
+
+    def hbm(ms, nbytes):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return dict(ms=round(ms, 4), bytes=int(nbytes), gb_per_s=round(gbs, 1),
+                    frac_of_8tbs=round(gbs / 8000.0, 3))
+
+    views = scene["views"]
+    V, H, W = len(views), views[0].height, views[0].width
+    img = torch.rand((V, 3, H, W), device="cuda", generator=g)
+    par = api.tonemap_params(V)
+    par[:, 0] = 0.3
+    par[:, 4] = -0.2
+    res = torch.empty_like(img)
+    nimg = img.numel() * 4
+    out["tonemap_frame"] = hbm(_event_ms(lambda: api.tonemap(img, views, par, out=res), steps),
+                               2 * nimg)
+    d_in = torch.empty_like(img)
+    d_par = torch.zeros_like(par)
+    out["tonemap_frame_backward"] = hbm(_event_ms(
+        lambda: api.tonemap_backward(img, views, par, res, d_img=d_in, d_params=d_par), steps),
+        3 * nimg)
+    del img, res, d_in
+    x = torch.rand((12, 1024, 1024), device="cuda", generator=g)
+    y = (x + 0.1 * torch.randn(x.shape, device="cuda", generator=g)).clamp(0, 1)
+    ws = api.DssimWorkspace(12, 1024, 1024)
+    loss = torch.empty(1, device="cuda")
+    nx = x.numel() * 4
+    out["dssim_4x1024sq"] = hbm(_event_ms(lambda: api.dssim(x, y, ws, loss=loss), steps), 2 * nx)
+    dx = torch.zeros_like(x)
+    # maps written and read back (3 planes each), x and y read twice, d_x
+    # read and written
+    out["dssim_4x1024sq_backward"] = hbm(_event_ms(lambda: api.dssim_backward(x, y, ws, dx),
+                                                   steps), 6 * nx + 4 * nx + 2 * nx)
+    del x, y, ws, dx
+    crops = scene["crops"]
+    if crops:
+        nf = sum(3 * c.size * c.size for c in crops)
+        fov = torch.rand(nf, device="cuda", generator=g)
+        per = torch.rand((V, 3, H, W), device="cuda", generator=g)
+        r = torch.empty(2, device="cuda")
+        out["regulariser_crops"] = hbm(_event_ms(lambda: api.regulariser(fov, per, crops, r=r),
+                                                 steps), 2 * nf * 4)
+        del fov, per
+    n = 1_000_000 * 59 + 2_000_000 * 8
+    p_ = torch.zeros(n, device="cuda")
+    g_ = torch.randn(n, device="cuda", generator=g) * 1e-3
+    m_ = torch.zeros(n, device="cuda")
+    v_ = torch.zeros(n, device="cuda")
+    out["adam_fit_params"] = hbm(_event_ms(lambda: api.adam_step(p_, g_, m_, v_, 1, 1e-3), steps),
+                                 7 * 4 * n)
+    out["adam_fit_params"]["params"] = n
+    del p_, g_, m_, v_
+    free()
+    return {"post_and_training": out}
+
+
 def table3_and_fig2(scene, tile, radix, steps):
     """Synthetic reproductions of the paper's performance ablation (Table 3:
     depth culling off, full-width finest decoder level, combination with and
@@ -478,6 +559,8 @@ def main():
                                                     "periphery_pixel_order", "config2_fovea")}))
         result.update(table3_and_fig2(scene, tile, radix, k))
         log("table 3 / fig 2:", json.dumps({x: result[x] for x in ("table3", "fig2")}))
+        result.update(post_and_training(scene, k))
+        log("post / training:", json.dumps(result["post_and_training"]))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(scene)
         result["cpu_baseline"] = cb

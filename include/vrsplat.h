@@ -270,8 +270,12 @@ vrs_status vrs_tonemap_backward(const float* in, const vrs_view* views, int n_vi
  * map of x against y, planes of [planes][H][W] float32 (DEVICE; e.g.
  * images x channels), with the 11 x 11 window of the 11-tap Gaussian of
  * sigma 1.5 normalised to sum 1 (outer product), zero padding outside each
- * plane, C1 = 0.01^2, C2 = 0.03^2, the variances as E[x^2] - mu^2.  loss:
- * DEVICE float32 [1] written.  ws: DEVICE workspace of
+ * plane, C1 = 0.01^2, C2 = 0.03^2.  Evaluated (single precision) in terms of
+ * the difference e = x - y, whose blurred mean D and variance v_e make the
+ * map's complement (b1 v_e + D^2 a2) / (b1 b2) free of cancellation where x
+ * and y agree (a1, a2, b1, b2 the usual numerator and denominator factors,
+ * b1 = a1 + D^2, b2 = a2 + v_e); the adjoint likewise.  loss: DEVICE
+ * float32 [1] written.  ws: DEVICE workspace of
  * vrs_dssim_workspace_size bytes (the same size serves the adjoint). */
 size_t vrs_dssim_workspace_size(int planes, int width, int height);
 vrs_status vrs_dssim(const float* x, const float* y, int planes, int width, int height,

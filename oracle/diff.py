@@ -329,3 +329,60 @@ def composite(P, F, crops_i, gaze, mode=0, ring=64.0, m=0.75, gamma=0.2):
 
 def l1(pred, target):
     return (pred - target).abs().mean()
+
+
+# ------------------------------------------------- tone mapping and losses
+def tonemap(img, params, principal):
+    """oracle.post.tonemap as differentiable torch ops: the segment and the
+    clamp are decided as there (single precision, post._decide32), the
+    values in float64.  img [V][3][H][W], params [V][7 + n]."""
+    from .post import PARAMS_FIXED, _decide32, vignette_r2
+    V, _, H, W = img.shape
+    n = params.shape[1] - PARAMS_FIXED
+    outs = []
+    for v in range(V):
+        ev, k, lut = params[v, 0], params[v, 4:7], params[v, 7:]
+        r2 = torch.tensor(vignette_r2(W, H, *principal[v]), dtype=DT)
+        vig = 1.0 + k[0] * r2 + k[1] * r2 ** 2 + k[2] * r2 ** 3
+        ch = []
+        for c in range(3):
+            t = img[v, c] * torch.pow(torch.tensor(2.0, dtype=DT), -ev) * params[v, 1 + c] * vig
+            i, inside = _decide32(img[v, c].detach().numpy(), float(ev.detach()),
+                                  float(params[v, 1 + c].detach()), k.detach().numpy(), n, W, H,
+                                  *principal[v])
+            i = torch.tensor(i)
+            tc = torch.where(torch.tensor(inside), t, torch.clamp(t, 0.0, 1.0).detach())
+            f = tc * (n - 1) - i
+            ch.append((1.0 - f) * lut[i] + f * lut[i + 1])
+        outs.append(torch.stack(ch))
+    return torch.stack(outs)
+
+
+def _blur(a):
+    from .post import SSIM_WINDOW, ssim_window
+    g = torch.tensor(ssim_window(), dtype=DT)
+    h = SSIM_WINDOW // 2
+    x = a.reshape(-1, 1, *a.shape[-2:])
+    x = Fnn.conv2d(x, g.reshape(1, 1, 1, -1), padding=(0, h))
+    x = Fnn.conv2d(x, g.reshape(1, 1, -1, 1), padding=(h, 0))
+    return x.reshape(a.shape)
+
+
+def dssim(x, y):
+    """oracle.post.dssim as differentiable torch ops."""
+    from .post import SSIM_C1, SSIM_C2
+    mx, my = _blur(x), _blur(y)
+    sxx = _blur(x * x) - mx * mx
+    syy = _blur(y * y) - my * my
+    sxy = _blur(x * y) - mx * my
+    s = ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2) /
+         ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2)))
+    return 1.0 - s.mean()
+
+
+def regulariser(F, P, crops_i):
+    """oracle.post.regulariser for packed F [sum 3 S^2] and P [V][3][H][W]."""
+    crops_i = np.asarray(crops_i, np.int32).reshape(-1, 4)
+    cnt = int(sum(3 * int(s) * int(s) for (_, _, _, s) in crops_i))
+    ps = sum(P[v, :, y0:y0 + s, x0:x0 + s].sum() for (v, x0, y0, s) in crops_i)
+    return torch.abs((F.sum() - ps) / cnt)

@@ -134,3 +134,79 @@ class L1Loss(torch.autograd.Function):
         d = torch.zeros_like(pred)
         api.l1_loss(pred.contiguous(), target.contiguous(), d_pred=d, scale=float(g))
         return d, None
+
+
+class Tonemap(torch.autograd.Function):
+    """vrs_tonemap with its adjoint (image and camera-model parameters)."""
+
+    @staticmethod
+    def forward(ctx, img, params, views):
+        img, params = img.contiguous(), params.contiguous()
+        ctx.save_for_backward(img, params)
+        ctx.views = views
+        return api.tonemap(img, views, params)
+
+    @staticmethod
+    def backward(ctx, g):
+        img, params = ctx.saved_tensors
+        d_img = torch.empty_like(img) if ctx.needs_input_grad[0] else None
+        d_par = torch.zeros_like(params) if ctx.needs_input_grad[1] else None
+        if d_img is not None or d_par is not None:
+            api.tonemap_backward(img, ctx.views, params, g.contiguous(), d_img=d_img,
+                                 d_params=d_par)
+        return d_img, d_par, None
+
+
+_DSSIM_WS = {}
+
+
+def _dssim_ws(planes, W, H, device):
+    key = (planes, W, H, str(device))
+    if key not in _DSSIM_WS:
+        _DSSIM_WS[key] = api.DssimWorkspace(planes, W, H, device)
+    return _DSSIM_WS[key]
+
+
+class Dssim(torch.autograd.Function):
+    """D-SSIM (Eq. 6, as in 3DGS) of pred against target over [..][H][W]
+    planes; the gradient flows to pred.  Scalar (0-d) result."""
+
+    @staticmethod
+    def forward(ctx, pred, target):
+        pred, target = pred.contiguous(), target.contiguous()
+        H, W = pred.shape[-2:]
+        planes = pred.numel() // (H * W)
+        ws = _dssim_ws(planes, W, H, pred.device)
+        ctx.save_for_backward(pred, target)
+        return api.dssim(pred, target, ws)[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        pred, target = ctx.saved_tensors
+        H, W = pred.shape[-2:]
+        ws = _dssim_ws(pred.numel() // (H * W), W, H, pred.device)
+        d = torch.zeros_like(pred)
+        api.dssim_backward(pred, target, ws, d, d_loss=g.reshape(1).contiguous())
+        return d, None
+
+
+class Regulariser(torch.autograd.Function):
+    """R of Eq. 7 (|mean F - mean crop(P)|) with its adjoint."""
+
+    @staticmethod
+    def forward(ctx, fovea, periphery, crops):
+        fovea, periphery = fovea.contiguous(), periphery.contiguous()
+        r = api.regulariser(fovea, periphery, crops)
+        ctx.save_for_backward(r)
+        ctx.crops, ctx.shape = crops, tuple(periphery.shape)
+        ctx.fshape = fovea.shape
+        return r[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (r,) = ctx.saved_tensors
+        d_f = torch.zeros(ctx.fshape, device=r.device) if ctx.needs_input_grad[0] else None
+        d_p = torch.zeros(ctx.shape, device=r.device) if ctx.needs_input_grad[1] else None
+        api.regulariser_backward(ctx.shape, ctx.crops, r, d_r=g.reshape(1).contiguous(),
+                                 d_fovea=d_f, d_periphery=d_p)
+        return d_f, d_p, None

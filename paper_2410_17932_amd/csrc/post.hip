@@ -244,61 +244,83 @@ __device__ inline void ss_stage(const float* const src[NM], const SsArgs& a, int
   __syncthreads();
 }
 
-// SSIM over one tile.  MAPS: writes the map's partials in (mu_x, E[x^2],
-// E[xy]) to maps [3][planes][H][W]; else the block's sum of SSIM to
-// partial[block].
+// SSIM over one tile, from seven blurred moments of x, y and e = x - y
+// (mu_x, mu_y, E[x^2], E[y^2], E[xy], D = mu_e, E[e^2]).  With a1 = 2 mu_x
+// mu_y + C1, a2 = 2 s_xy + C2, b1 = a1 + D^2 (= mu_x^2 + mu_y^2 + C1),
+// b2 = a2 + v_e (= s_xx + s_yy + C2, v_e = E[e^2] - D^2), the map's
+// complement is 1 - SSIM = (b1 v_e + D^2 a2) / (b1 b2): no difference of
+// nearly equal terms where x and y agree.  MAPS: writes the map's partials
+// in (mu_x, E[x^2]) and their combination with E[xy]'s, in the same
+// difference form (A, B, C' = C + 2B: A = -2 a2 D (mu_y (mu_x + mu_y) + C1)
+// / (b1^2 b2) + 2 a1 (D a2 - mu_y v_e) / (b1 b2^2), B = -SSIM / b2,
+// C' = 2 a1 v_e / (b1 b2^2)) to maps [3][planes][H][W]; else the block's sum
+// of 1 - SSIM to partial[block].
 template <bool MAPS>
 __global__ __launch_bounds__(kSsBlock) void k_ssim(const float* __restrict__ x,
                                                    const float* __restrict__ y, SsArgs a,
                                                    float* __restrict__ maps,
                                                    float* __restrict__ partial) {
-  __shared__ float s_in[5][kSsIn][kSsIn + 1];
-  __shared__ float s_h[5][kSsIn][kSsTile + 1];
+  __shared__ float s_in[2][kSsIn][kSsIn + 1];
+  __shared__ float s_h[7][kSsIn][kSsTile + 1];
   __shared__ float s_red[kSsBlock / 64];
   const int pl = blockIdx.z;
   const int X0 = blockIdx.x * kSsTile, Y0 = blockIdx.y * kSsTile;
   const int64_t plane = (int64_t)a.W * a.H;
-  const float* px = x + pl * plane;
-  const float* py = y + pl * plane;
-  // stage x and y, then derive the products in LDS
   {
-    const float* src[2] = {px, py};
+    const float* src[2] = {x + pl * plane, y + pl * plane};
     ss_stage<2>(src, a, X0, Y0, s_in);
-    for (int idx = threadIdx.x; idx < kSsIn * kSsIn; idx += kSsBlock) {
-      const int r = idx / kSsIn, c = idx - r * kSsIn;
-      const float u = s_in[0][r][c], w = s_in[1][r][c];
-      s_in[2][r][c] = u * u;
-      s_in[3][r][c] = w * w;
-      s_in[4][r][c] = u * w;
-    }
-    __syncthreads();
   }
-  float o[5][4];
-  ss_blur<5>(a, s_in, s_h, o);
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // horizontal pass: the seven moments from x and y on the fly
+  for (int r = ty; r < kSsIn; r += 8) {
+    float h[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 11; ++j) {
+      const float w = a.w[j], u = s_in[0][r][tx + j], v = s_in[1][r][tx + j], e = u - v;
+      h[0] = fmaf(w, u, h[0]);
+      h[1] = fmaf(w, v, h[1]);
+      h[2] = fmaf(w, u * u, h[2]);
+      h[3] = fmaf(w, v * v, h[3]);
+      h[4] = fmaf(w, u * v, h[4]);
+      h[5] = fmaf(w, e, h[5]);
+      h[6] = fmaf(w, e * e, h[6]);
+    }
+#pragma unroll
+    for (int m = 0; m < 7; ++m) s_h[m][r][tx] = h[m];
+  }
+  __syncthreads();
   const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
   float sum = 0.0f;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int gx = X0 + tx, gy = Y0 + ty + 8 * q;
+    const int r = ty + 8 * q;
+    float o[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      float t = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 11; ++j) t = fmaf(a.w[j], s_h[m][r + j][tx], t);
+      o[m] = t;
+    }
+    const int gx = X0 + tx, gy = Y0 + r;
     if (gx >= a.W || gy >= a.H) continue;
-    const float mx = o[0][q], my = o[1][q];
-    const float sxx = o[2][q] - mx * mx, syy = o[3][q] - my * my, sxy = o[4][q] - mx * my;
+    const float mx = o[0], my = o[1], D = o[5];
+    const float sxy = o[4] - mx * my;
+    const float ve = o[6] - D * D;
     const float a1 = 2.0f * mx * my + C1, a2 = 2.0f * sxy + C2;
-    const float b1 = mx * mx + my * my + C1, b2 = sxx + syy + C2;
-    const float s = (a1 * a2) / (b1 * b2);
+    const float b1 = a1 + D * D, b2 = a2 + ve;
+    const float inv = 1.0f / (b1 * b2);
     if (MAPS) {
-      const float inv = 1.0f / (b1 * b2);
-      const float d_mx = 2.0f * my * a2 * inv - s * 2.0f * mx / b1;
-      const float d_sxx = -s / b2;
-      const float d_sxy = 2.0f * a1 * inv;
+      const float s = a1 * a2 * inv;
+      const float A = -2.0f * a2 * D * (my * (mx + my) + C1) * inv / b1 +
+                      2.0f * a1 * (D * a2 - my * ve) * inv / b2;
       const int64_t o2 = pl * plane + (int64_t)gy * a.W + gx;
       const int64_t all = (int64_t)a.planes * plane;
-      maps[o2] = d_mx - 2.0f * mx * d_sxx - my * d_sxy;
-      maps[all + o2] = d_sxx;
-      maps[2 * all + o2] = d_sxy;
+      maps[o2] = A;
+      maps[all + o2] = -s / b2;
+      maps[2 * all + o2] = 2.0f * a1 * ve * inv / b2;
     } else {
-      sum += s;
+      sum += (b1 * ve + D * D * a2) * inv;
     }
   }
   if (!MAPS) {
@@ -315,7 +337,8 @@ __global__ __launch_bounds__(kSsBlock) void k_ssim(const float* __restrict__ x,
   }
 }
 
-// d_x += scale (blur(A) + 2 x blur(B) + y blur(C)), scale = -d_loss / N.
+// d_x += scale (blur(A) + 2 (x - y) blur(B) + y blur(C')), scale =
+// -d_loss / N (the partials' adjoint: A + 2 x B + y C with C = C' - 2B).
 __global__ __launch_bounds__(kSsBlock) void k_ssim_bwd(const float* __restrict__ x,
                                                        const float* __restrict__ y, SsArgs a,
                                                        const float* __restrict__ maps,
@@ -338,12 +361,14 @@ __global__ __launch_bounds__(kSsBlock) void k_ssim_bwd(const float* __restrict__
     const int gx = X0 + tx, gy = Y0 + ty + 8 * q;
     if (gx >= a.W || gy >= a.H) continue;
     const int64_t i = pl * plane + (int64_t)gy * a.W + gx;
-    const float g = o[0][q] + 2.0f * x[i] * o[1][q] + y[i] * o[2][q];
+    const float yi = y[i];
+    const float g = o[0][q] + 2.0f * (x[i] - yi) * o[1][q] + yi * o[2][q];
     d_x[i] += scale * g;
   }
 }
 
-// out[0] = 1 - sum(partial) / N, in a fixed order.
+// out[0] = sum(partial) / N (the blocks' sums of 1 - SSIM), in a fixed
+// order.
 __global__ __launch_bounds__(256) void k_dssim_finish(const float* __restrict__ partial,
                                                       int64_t nb, double inv_n,
                                                       float* __restrict__ out) {
@@ -356,7 +381,7 @@ __global__ __launch_bounds__(256) void k_dssim_finish(const float* __restrict__ 
     if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = (float)(1.0 - s[0] * inv_n);
+  if (threadIdx.x == 0) out[0] = (float)(s[0] * inv_n);
 }
 
 bool ss_args(int planes, int W, int H, SsArgs* a) {

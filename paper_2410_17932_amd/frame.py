@@ -267,13 +267,25 @@ class PlainFrame:
 
 class FitStep:
     """One differentiable fitting step (Sec. 3.5): bake -> periphery ->
-    depth-culled point splat -> decoder -> combination -> L1 against a
-    target, then the hand-written adjoints of every stage through
-    torch.autograd.  Parameters live in HBM as leaf tensors with .grad."""
+    depth-culled point splat -> decoder -> combination [-> tone mapping] ->
+    loss against a target, then the hand-written adjoints of every stage
+    through torch.autograd.  Parameters live in HBM as leaf tensors with
+    .grad.  loss "l1": L1; "paper": Eq. 6 without the VGG term,
+    (1 - lam) L1 + lam D-SSIM + beta R (lam = 0.2, beta = 1e-5; R of Eq. 7
+    over the crops).  tonemap: the camera model's parameters (float32
+    [V][7 + n]) join the fitted parameters and map the combined image before
+    the loss.  step(): plain gradient descent, or Adam (vrs_adam_step) with
+    optimizer="adam"."""
 
     def __init__(self, scene: dict, target, decoder_dtype: int = api.VRS_BF16, tile: int = 16,
                  ring: float = 64.0, cull: bool = True, pair_margin: float = 1.5,
-                 frag_margin: float = 2.0, mask=None):
+                 frag_margin: float = 2.0, mask=None, loss: str = "l1", lam: float = 0.2,
+                 beta: float = 1e-5, tonemap=None):
+        if loss not in ("l1", "paper"):
+            raise ValueError("loss must be 'l1' or 'paper'")
+        self.loss_kind, self.lam, self.beta = loss, lam, beta
+        self.adam_state = {}
+        self.adam_t = 0
         self.mask = None if mask is None else (mask if torch.is_tensor(mask) else _dev(mask))
         g, p = scene["gaussians"], scene["points"]
         self.views, self.crops, self.levels = scene["views"], scene["crops"], scene["levels"]
@@ -286,6 +298,9 @@ class FitStep:
             radius=_dev(p["radius"]),
             feat=_dev(p["feat"].view(np.float16).astype(np.float32)),
             weights=_dev(pack_decoder(scene["decoder"])))
+        if tonemap is not None:
+            self.params["tonemap"] = (tonemap.detach().clone().float().contiguous()
+                                      if torch.is_tensor(tonemap) else _dev(tonemap))
         for t in self.params.values():
             t.requires_grad_(True)
         self.target = None if target is None else (target if torch.is_tensor(target) else _dev(target))
@@ -314,8 +329,8 @@ class FitStep:
         self.dws = api.DecoderWorkspace(self.widths, self.crops, decoder_dtype)
 
     def forward(self):
-        from .autograd import (BakeGaussians, CompositeFrame, DecodeFovea, L1Loss,
-                               RenderGaussians, SplatPoints)
+        from .autograd import (BakeGaussians, CompositeFrame, DecodeFovea, Dssim, L1Loss,
+                               Regulariser, RenderGaussians, SplatPoints, Tonemap)
         P = self.params
         cov, op = BakeGaussians.apply(P["logscale"], P["quat"], P["logit"])
         rgb, depth, tfinal = RenderGaussians.apply(P["mean"], cov, op, P["sh"], self.deg,
@@ -326,18 +341,35 @@ class FitStep:
         fovea = DecodeFovea.apply(pyr, rgb, P["weights"], self.levels, self.views, self.crops,
                                   self.dws)
         out = CompositeFrame.apply(rgb, fovea, self.crops, api.BLEND_LINEAR, self.ring, 0.75, 0.2)
+        if "tonemap" in P:
+            out = Tonemap.apply(out, P["tonemap"], self.views)
+        self.last = dict(out=out, fovea=fovea, rgb=rgb)
         if self.target is None:
             return out, None
+        pred, tgt = out, self.target
         if self.mask is not None:
-            return out, L1Loss.apply(out * self.mask, self.target * self.mask)
-        return out, L1Loss.apply(out, self.target)
+            pred, tgt = out * self.mask, self.target * self.mask
+        l1 = L1Loss.apply(pred, tgt)
+        if self.loss_kind == "l1":
+            return out, l1
+        loss = (1.0 - self.lam) * l1 + self.lam * Dssim.apply(pred, tgt)
+        if self.crops:
+            loss = loss + self.beta * Regulariser.apply(fovea, rgb, self.crops)
+        return out, loss
 
-    def step(self, lr: float = 0.0):
+    def step(self, lr: float = 0.0, optimizer: str = "sgd"):
         for t in self.params.values():
             t.grad = None
         out, loss = self.forward()
         loss.backward()
-        if lr:
+        if lr and optimizer == "adam":
+            self.adam_t += 1
+            for k, t in self.params.items():
+                if k not in self.adam_state:
+                    self.adam_state[k] = (torch.zeros_like(t), torch.zeros_like(t))
+                m, v = self.adam_state[k]
+                api.adam_step(t.data, t.grad.contiguous(), m, v, self.adam_t, lr)
+        elif lr:
             with torch.no_grad():
                 for t in self.params.values():
                     t -= lr * t.grad

@@ -249,3 +249,39 @@ def test_adam_zero_gradient_leaves_parameters():
     p = np.array([1.0, -2.0])
     q, _, _ = post.adam(p, np.zeros(2), np.zeros(2), np.zeros(2), 1, lr=0.1)
     assert np.array_equal(p, q)
+
+
+# ------------------------------------- the differentiable forms (oracle.diff)
+def test_diff_forms_equal_the_reference_and_its_gradients():
+    import torch
+    from oracle import diff
+    rng = np.random.default_rng(12)
+    x = _img(rng, lo=0.05, hi=1.3)
+    p = _params(rng)
+    d = rng.normal(0, 1, x.shape)
+    xt = torch.tensor(x, requires_grad=True)
+    pt = torch.tensor(p, requires_grad=True)
+    out = diff.tonemap(xt, pt, PRINC)
+    want, _ = post.tonemap(x, p, PRINC)
+    assert np.abs(out.detach().numpy() - want).max() < 1e-14
+    (out * torch.tensor(d)).sum().backward()
+    d_img, d_par = post.tonemap_backward(x, p, PRINC, d)
+    assert np.abs(xt.grad.numpy() - d_img).max() < 1e-12
+    assert np.abs(pt.grad.numpy() - d_par).max() < 1e-9 * max(1, np.abs(d_par).max())
+    a = rng.uniform(0, 1, (2, 3, 20, 24))
+    b = np.clip(a + rng.normal(0, 0.2, a.shape), 0, 1)
+    at = torch.tensor(a, requires_grad=True)
+    s = diff.dssim(at, torch.tensor(b))
+    assert abs(float(s) - post.dssim(a, b)) < 1e-13
+    s.backward()
+    assert np.abs(at.grad.numpy() - post.dssim_backward(a, b)).max() < 1e-15
+    crops = [(0, 2, 3, 8), (1, 10, 4, 12)]
+    F = [rng.uniform(0, 1, (3, s_, s_)) for (_, _, _, s_) in crops]
+    Fp = torch.tensor(np.concatenate([f.ravel() for f in F]), requires_grad=True)
+    Pt = torch.tensor(a, requires_grad=True)
+    r = diff.regulariser(Fp, Pt, crops)
+    assert abs(float(r) - post.regulariser(F, a, crops)[0]) < 1e-15
+    r.backward()
+    dF, dP = post.regulariser_backward(F, a, crops)
+    assert np.abs(Fp.grad.numpy() - np.concatenate([f.ravel() for f in dF])).max() < 1e-16
+    assert np.abs(Pt.grad.numpy() - dP).max() < 1e-16
