@@ -497,7 +497,7 @@ def main():
                     achieved=round(achieved, 3), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
                     traffic=measured_traffic("gs_blend_config3_hbm_counters.md",
-                                             "paper_2410_17932_amd/csrc/gs_forward.hip"),
+                                             "paper_2410_17932_amd/csrc/gs_blend.hip"),
                     work=dict(flops=flops, evaluations=evals, contributions=contrib,
                               ms=round(stages["gs_blend"], 4)))
     # decoder on the matrix cores: algorithmic flops over its stage time
