@@ -209,7 +209,7 @@ vrs_status vrs_render_gaussians(const float* mean, const float* cov, const float
  * exact_pass_count (uint32, device; PIXEL order only, else 0): the number of
  * pixels whose per-pixel order was resolved by the exact pass;
  * tile_words (uint64 [max_pairs]; PIXEL order only, else 0): at the first
- * min(length, 2048) positions of each tile range, the blend's reordering of
+ * min(length, 4096) positions of each tile range, the blend's reordering of
  * those records as (order-preserving bits of beta) << 32 | Gaussian index,
  * beta non-decreasing and at most every single-precision per-pixel key, at
  * the tile's pixels in its rectangle, of every record at that position or

@@ -27,16 +27,16 @@
 //                   of the next batch's first position.  A pixel whose window fills
 //                   up with no entry so released has its order unresolved:
 //                   it is queued
-//   k_gs_blend_px_fix  one wave per queued pixel redoes it exactly with a
-//                   pending set in LDS, released against z_t after every 64
-//                   records (repeated selection over the whole list should
-//                   that set outgrow its capacity)
+//   k_gs_blend_px_fix  one wave per queued pixel redoes it exactly, in
+//                   rounds of streaming selection of the least keys above
+//                   the last blended one (scans cut off by the bound words)
 // The adjoint is not provided for this order.
 #include "gs_layout.h"
 
 namespace vrs {
 
-constexpr int kPxWindow = 16;   // pending contributions per pixel
+constexpr int kPxWindow = 20;   // pending contributions per pixel
+constexpr int kPxRing = 1024;   // records whose colours stay in LDS
 
 // order-preserving unsigned image of a float, and back
 __device__ inline uint32_t f2ord(float f) {
@@ -254,12 +254,12 @@ __global__ __launch_bounds__(256) void k_gs_pixdepth(const float* __restrict__ m
 // positions >= j, at every pixel of the tile in its rectangle, at least
 // beta(j) (order-preserving bits throughout).  The first kZsPrefix records
 // (or all) are sorted by z_t, the bound over the tile's pixel box, its bits
-// rounded down to 21 (so that a 32-bit word carries it with an 11-bit slot
+// rounded down to 20 (so that a 32-bit word carries it with a 12-bit slot
 // in the prefix): beta = min(rounded z_t, z_lo of the first record after the
 // prefix).  After the prefix the list keeps its z_lo order and beta = z_lo.
 // Blending stops long before most lists end, so only the prefix is sorted; a
 // pixel that reads past it still gets valid, if looser, bounds.
-constexpr int kZsBlock = 256, kZsPrefix = 2048, kZsSlotBits = 11;
+constexpr int kZsBlock = 256, kZsPrefix = 4096, kZsSlotBits = 12;
 static_assert(kZsPrefix == 1 << kZsSlotBits, "one slot per prefix position");
 
 __device__ inline uint64_t zs_word(const uint64_t* __restrict__ tkey,
@@ -329,58 +329,70 @@ __global__ __launch_bounds__(kZsBlock) void k_gs_tile_zsort(
 }
 
 // A lane's pending contributions, ascending in (key bits << 32 | index),
-// with their alphas; free slots hold ~0.  Fixed-size and fully unrolled so
-// that it stays in registers.
+// with their alphas and list positions (the colour waits in the tile's LDS
+// ring under the position); free slots hold ~0.  Fixed-size and fully
+// unrolled so that it stays in registers.
 template <int K>
 struct PxWindow {
   // vector types are register values (element access needs no memory)
   typedef unsigned long long KeyV __attribute__((ext_vector_type(K)));
   typedef float AlphaV __attribute__((ext_vector_type(K)));
+  typedef unsigned int PosV __attribute__((ext_vector_type(K)));
   KeyV k;
-  AlphaV a, r, g, b;   // alpha and colour of each entry
+  AlphaV a;
+  PosV p;
   int n;
   __device__ __attribute__((always_inline)) void clear() {
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       k[q] = ~0ull;
-      a[q] = r[q] = g[q] = b[q] = 0.0f;
+      a[q] = 0.0f;
+      p[q] = 0u;
     }
     n = 0;
   }
-  // drop the first entry where `go`
+  // drop the first entry where `go`.  Written as masked bit moves: with
+  // selects on one condition for every slot the compiler rebuilds the shift
+  // as a variable-index gather, quadratic in the window size.
   __device__ __attribute__((always_inline)) void shift(bool go) {
+    const uint64_t m64 = go ? ~0ull : 0ull;
+    const uint32_t m32 = (uint32_t)m64;
 #pragma unroll
     for (int q = 0; q < K - 1; ++q) {
-      k[q] = go ? k[q + 1] : k[q];
-      a[q] = go ? a[q + 1] : a[q];
-      r[q] = go ? r[q + 1] : r[q];
-      g[q] = go ? g[q + 1] : g[q];
-      b[q] = go ? b[q + 1] : b[q];
+      k[q] = k[q] ^ ((k[q] ^ k[q + 1]) & m64);
+      const uint32_t u = __float_as_uint(a[q]);
+      a[q] = __uint_as_float(u ^ ((u ^ __float_as_uint(a[q + 1])) & m32));
+      p[q] = p[q] ^ ((p[q] ^ p[q + 1]) & m32);
     }
-    k[K - 1] = go ? ~0ull : k[K - 1];
+    k[K - 1] = k[K - 1] | m64;
     n -= go ? 1 : 0;
   }
-  // insert into a window with a free slot: one compare-exchange pass
-  __device__ __attribute__((always_inline)) void insert(uint64_t key, float al, float cr, float cg,
-                                                        float cb) {
+  // insert into a window with a free slot.  The slots are ascending, so the
+  // slots above the key are a suffix: slot q takes the key if it is the
+  // first of them, its lower neighbour if it is a later one, and keeps its
+  // entry otherwise (two selects per word; every index static).
+  __device__ __attribute__((always_inline)) void insert(uint64_t key, float al, uint32_t pos) {
+    bool above[K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-      const bool lt = key < k[q];
-      const uint64_t tk = lt ? k[q] : key;
-      const float ta = lt ? a[q] : al, tr = lt ? r[q] : cr, tg = lt ? g[q] : cg,
-                  tb = lt ? b[q] : cb;
-      k[q] = lt ? key : k[q];
-      a[q] = lt ? al : a[q];
-      r[q] = lt ? cr : r[q];
-      g[q] = lt ? cg : g[q];
-      b[q] = lt ? cb : b[q];
-      key = tk;
-      al = ta;
-      cr = tr;
-      cg = tg;
-      cb = tb;
+    for (int q = 0; q < K; ++q) above[q] = key < k[q];
+#pragma unroll
+    for (int q = K - 1; q >= 1; --q) {
+      const bool take = above[q], from_left = above[q - 1];
+      k[q] = take ? (from_left ? k[q - 1] : key) : k[q];
+      a[q] = take ? (from_left ? a[q - 1] : al) : a[q];
+      p[q] = take ? (from_left ? p[q - 1] : pos) : p[q];
     }
+    k[0] = above[0] ? key : k[0];
+    a[0] = above[0] ? al : a[0];
+    p[0] = above[0] ? pos : p[0];
     ++n;
+  }
+  // least list position among the entries (~0 when empty)
+  __device__ __attribute__((always_inline)) uint32_t oldest() const {
+    uint32_t m = 0xffffffffu;
+#pragma unroll
+    for (int q = 0; q < K; ++q) m = q < n ? min(m, p[q]) : m;
+    return m;
   }
 };
 
@@ -394,8 +406,8 @@ struct PxCfg {
 // One workgroup per tile in the longest-first schedule, one wave per 8x8
 // sub-tile, one pixel per lane.  Records are staged in batches with a ballot
 // per sub-tile of those whose rectangle reaches it.  A lane's window holds
-// (key bits << 32 | index) ascending with the contribution's alpha and
-// colour; free slots hold ~0.
+// (key bits << 32 | index) ascending with the contribution's alpha and list
+// position (its colour is in the LDS ring); free slots hold ~0.
 template <int TILE>
 __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
     const uint32_t* __restrict__ order, const uint64_t* __restrict__ tkey,
@@ -406,7 +418,9 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
     uint32_t* __restrict__ fix_count) {
   using Cfg = PxCfg<TILE>;
   constexpr int BLOCK = Cfg::BLOCK, NW = Cfg::NW, NQ = Cfg::NQ, K = kPxWindow;
-  __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_c[BLOCK], s_q0[BLOCK], s_q1[BLOCK], s_q2[BLOCK];
+  static_assert(kPxRing % BLOCK == 0, "batches fill whole ring slots");
+  __shared__ float4 s_a[BLOCK], s_b[BLOCK], s_q0[BLOCK], s_q1[BLOCK], s_q2[BLOCK];
+  __shared__ float s_ring[3][kPxRing];      // colours by list position mod kPxRing
   __shared__ uint32_t s_id[BLOCK];
   __shared__ uint64_t s_mask[NW][NW];
   __shared__ uint32_t s_beta[BLOCK];         // per record: its position's bound word
@@ -437,9 +451,10 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
       if (Tn < tmin) {
         alive = false;   // stops before this contribution; the rest is moot
       } else {
-        C0 = fmaf(win.r[0], w0, C0);
-        C1 = fmaf(win.g[0], w0, C1);
-        C2 = fmaf(win.b[0], w0, C2);
+        const uint32_t slot = win.p[0] & (kPxRing - 1);
+        C0 = fmaf(s_ring[0][slot], w0, C0);
+        C1 = fmaf(s_ring[1][slot], w0, C1);
+        C2 = fmaf(s_ring[2][slot], w0, C2);
         D = fmaf(ord2f((uint32_t)(win.k[0] >> 32)), w0, D);
         T = Tn;
         ++cnt;
@@ -450,6 +465,12 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
   const uint2 rg = ranges[tglob];
   const uint32_t begin = rg.x, end = rg.y;
   for (uint32_t b0 = begin; b0 < end; b0 += BLOCK) {
+    // this batch's colours overwrite the ring slots of positions b0 - kPxRing
+    // onwards: a pixel still holding one of those cannot be finished here
+    if (alive && win.n > 0 && win.oldest() + kPxRing < (b0 - begin) + BLOCK) {
+      inexact = true;
+      alive = false;
+    }
     if (__syncthreads_count(alive) == 0) break;
     const uint32_t jr = b0 + tid;
     const bool has = jr < end;
@@ -463,7 +484,10 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
       gs_stage(rec, e, a, b, c);
       s_a[tid] = a;
       s_b[tid] = b;
-      s_c[tid] = c;
+      const uint32_t slot = (jr - begin) & (kPxRing - 1);
+      s_ring[0][slot] = c.x;
+      s_ring[1][slot] = c.y;
+      s_ring[2][slot] = c.z;
       s_q0[tid] = pcoef[3 * e];
       s_q1[tid] = pcoef[3 * e + 1];
       s_q2[tid] = pcoef[3 * e + 2];
@@ -550,10 +574,7 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
               alive = false;
             }
           }
-          if (alive) {
-            const float4 c = s_c[k];
-            win.insert(key, al, c.x, c.y, c.z);
-          }
+          if (alive) win.insert(key, al, b0 - begin + (uint32_t)k);
         }
       }
     }
@@ -578,15 +599,17 @@ __global__ __launch_bounds__(PxCfg<TILE>::BLOCK) void k_gs_blend_px(
   }
 }
 
-// Exact per-pixel order for the queued pixels, one wave per pixel.  The
-// pixel's tile list (in bound-word order) is read 64 records at a time;
-// its contributions join a pending set in LDS, and after each chunk the
-// pending entries below the next position's bound are taken out, sorted
-// (bitonic, in LDS) and blended in order.  A pixel
-// whose pending set outgrows kFixCap continues by repeated selection: each
-// round picks the least (key, index) above the last blended one, scanning
-// the list until the bound words pass it.
-constexpr int kFixCap = 512, kFixWaves = 4;
+// Exact per-pixel order for the queued pixels, one wave per pixel, in
+// rounds.  A round streams the pixel's tile list 64 records at a time and
+// keeps, in LDS, the kFixCap least (key, index) above the last blended one:
+// candidates go into a buffer of twice that size; when it overflows it is
+// sorted and cut back, and its kFixCap-th key becomes a threshold below
+// which a candidate must lie.  The scan stops at the first position whose
+// bound word exceeds the threshold (every later key is at least that word),
+// so the kept entries are exactly the least ones of the whole list.  They
+// are blended in order; a round that keeps fewer than kFixCap entries has
+// exhausted the list.
+constexpr int kFixCap = 256, kFixWaves = 4;
 
 struct FixAcc {
   float T, C0, C1, C2, D;
@@ -619,21 +642,39 @@ __device__ inline void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Ascending bitonic sort of one wave's (key, alpha) pairs in LDS, P a power
+// of two (pads hold ~0).
+__device__ inline void wave_sort(uint64_t* ck, float* ca, int P, int lane) {
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < (P >> 1); i += 64) {
+        const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1)), b = a + j;
+        const uint64_t x = ck[a], y = ck[b];
+        if ((x > y) == ((a & k) == 0)) {
+          ck[a] = y;
+          ck[b] = x;
+          const float t = ca[a];
+          ca[a] = ca[b];
+          ca[b] = t;
+        }
+      }
+      wave_sync_lds();
+    }
+}
+
 __global__ __launch_bounds__(64 * kFixWaves) void k_gs_blend_px_fix(
     const uint32_t* __restrict__ fix_list, const uint32_t* __restrict__ fix_count,
     const uint64_t* __restrict__ tkey, const uint32_t* __restrict__ ids,
     const float4* __restrict__ rec, const float4* __restrict__ pcoef, int64_t n, KViews views,
-    GsOpt o, int tile,
-    int64_t tiles_x, int64_t tiles_per_view, const uint2* __restrict__ ranges,
+    GsOpt o, int tile, int64_t tiles_x, int64_t tiles_per_view, const uint2* __restrict__ ranges,
     float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_t,
     int32_t* __restrict__ out_n) {
-  __shared__ uint64_t s_pk[kFixWaves][kFixCap], s_rk[kFixWaves][kFixCap];
-  __shared__ float s_pa[kFixWaves][kFixCap], s_ra[kFixWaves][kFixCap];
+  constexpr int CAP2 = 2 * kFixCap;
+  __shared__ uint64_t s_ck[kFixWaves][CAP2];
+  __shared__ float s_ca[kFixWaves][CAP2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t* pk = s_pk[wave];
-  uint64_t* rk = s_rk[wave];
-  float* pa = s_pa[wave];
-  float* ra = s_ra[wave];
+  uint64_t* ck = s_ck[wave];
+  float* ca = s_ca[wave];
   const uint64_t below = (1ull << lane) - 1ull;
   const uint32_t nfix = *fix_count;
   for (uint32_t f = blockIdx.x * kFixWaves + wave; f < nfix; f += gridDim.x * kFixWaves) {
@@ -648,69 +689,78 @@ __global__ __launch_bounds__(64 * kFixWaves) void k_gs_blend_px_fix(
     const float ur = pix_ray(px, cv.cx, cv.fx), vr = pix_ray(py, cv.cy, cv.fy);
     const uint2 rg =
         ranges[(int64_t)v * tiles_per_view + (int64_t)(py / tile) * tiles_x + px / tile];
-    // this lane's record j: its (key, index) and alpha at the pixel, if it
-    // contributes
-    auto eval = [&](uint32_t j, uint64_t& key, float& al) -> bool {
-      const uint32_t id = (uint32_t)zs_word(tkey, ids, pcoef, (int64_t)v * n, rg.x, j);
-      const int64_t e = (int64_t)v * n + id;
-      float4 a, b, c;
-      gs_stage(rec, e, a, b, c);
-      const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
-      if (!(px >= (int)(lo & 0xffffu) && px <= (int)(hi & 0xffffu) && py >= (int)(lo >> 16) &&
-            py <= (int)(hi >> 16)))
-        return false;
-      const float dx = a.x - xc, dy = a.y - yc;
-      const float P = (a.z * dx) * dx, R = a.w * dx;
-      const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
-      al = fminf(b.y * __builtin_amdgcn_exp2f(qq), o.aclamp);
-      if (!(al >= o.amin)) return false;
-      key = ((uint64_t)pix_key_bits(pcoef[3 * e], pcoef[3 * e + 1], pcoef[3 * e + 2], ur, vr)
-             << 32) | id;
-      return true;
-    };
+    const int64_t vbase = (int64_t)v * n;
     FixAcc acc{1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, false};
-    int np = 0;   // pending entries (wave-uniform)
-    bool overflow = false;
     uint64_t last = 0;   // the last blended (key, index), valid unless `first`
     bool first = true;
-    // take the pending entries below `bound` out, sort them, blend them
-    auto release = [&](uint32_t bound) {
-      int r = 0, keep = 0;
-      for (int b0 = 0; b0 < np; b0 += 64) {
-        const int i = b0 + lane;
-        const bool has = i < np;
-        const uint64_t k = has ? pk[i] : ~0ull;
-        const float al = has ? pa[i] : 0.0f;
-        const bool out = has && (uint32_t)(k >> 32) < bound;
-        const uint64_t mo = __ballot(out), mk = __ballot(has && !out);
+    while (!acc.stop) {
+      int nc = 0;
+      uint64_t thr = ~0ull;   // candidates must lie below
+      for (uint32_t c0 = rg.x; c0 < rg.y; c0 += 64) {
+        if (thr != ~0ull &&
+            (uint32_t)(zs_word(tkey, ids, pcoef, vbase, rg.x, c0) >> 32) > (uint32_t)(thr >> 32))
+          break;   // every key from here on is above the threshold
+        const uint32_t j = c0 + lane;
+        uint64_t key = ~0ull;
+        float al = 0.0f;
+        bool ok = false;
+        if (j < rg.y) {
+          const uint32_t id = (uint32_t)zs_word(tkey, ids, pcoef, vbase, rg.x, j);
+          const int64_t e = vbase + id;
+          float4 a, b, c;
+          gs_stage(rec, e, a, b, c);
+          const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
+          if (px >= (int)(lo & 0xffffu) && px <= (int)(hi & 0xffffu) && py >= (int)(lo >> 16) &&
+              py <= (int)(hi >> 16)) {
+            const float dx = a.x - xc, dy = a.y - yc;
+            const float P = (a.z * dx) * dx, R = a.w * dx;
+            const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
+            al = fminf(b.y * __builtin_amdgcn_exp2f(qq), o.aclamp);
+            if (al >= o.amin) {
+              key = ((uint64_t)pix_key_bits(pcoef[3 * e], pcoef[3 * e + 1], pcoef[3 * e + 2], ur,
+                                            vr) << 32) | id;
+              ok = (first || key > last) && key < thr;
+            }
+          }
+        }
+        const uint64_t m = __ballot(ok);
+        if (ok) {
+          const int q = nc + __builtin_popcountll(m & below);
+          ck[q] = key;
+          ca[q] = al;
+        }
+        nc += __builtin_popcountll(m);
         wave_sync_lds();
-        if (out) {
-          const int q = r + __builtin_popcountll(mo & below);
-          rk[q] = k;
-          ra[q] = al;
+        if (nc > kFixCap + (CAP2 - kFixCap - 64)) {
+          // buffer nearly full: keep the kFixCap least, tighten the threshold
+          for (int i = nc + lane; i < CAP2; i += 64) ck[i] = ~0ull;
+          wave_sync_lds();
+          wave_sort(ck, ca, CAP2, lane);
+          nc = kFixCap;
+          thr = ck[kFixCap - 1];
         }
-        if (has && !out) {
-          const int q = keep + __builtin_popcountll(mk & below);
-          pk[q] = k;
-          pa[q] = al;
-        }
-        r += __builtin_popcountll(mo);
-        keep += __builtin_popcountll(mk);
       }
+      // the round's least entries, in order
+      int P = 64;
+      while (P < nc) P <<= 1;
+      for (int i = nc + lane; i < P; i += 64) ck[i] = ~0ull;
       wave_sync_lds();
-      np = keep;
-      if (r == 0) return;
-      // blend sorted entries: lane q holds the q-th of m (key, alpha)
-      auto blend64 = [&](uint64_t k, float al, int m) {
+      wave_sort(ck, ca, P, lane);
+      const int m = min(nc, kFixCap);
+      for (int b0 = 0; b0 < m && !acc.stop; b0 += 64) {
+        const int i = b0 + lane;
+        const uint64_t k = i < m ? ck[i] : ~0ull;
+        const float al = i < m ? ca[i] : 0.0f;
         float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-        if (lane < m) {
-          const int64_t e = (int64_t)v * n + (uint32_t)k;
+        if (i < m) {
+          const int64_t e = vbase + (uint32_t)k;
           const float4 r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
           c0 = r1.z;
           c1 = r1.w;
           c2 = r2.x;
         }
-        for (int q = 0; q < m; ++q) {
+        const int cnt = min(64, m - b0);
+        for (int q = 0; q < cnt; ++q) {
           const uint64_t kq = __shfl(k, q, 64);
           if (!fix_blend(acc, __shfl(al, q, 64), __shfl(c0, q, 64), __shfl(c1, q, 64),
                          __shfl(c2, q, 64), ord2f((uint32_t)(kq >> 32)), o.tmin))
@@ -718,112 +768,9 @@ __global__ __launch_bounds__(64 * kFixWaves) void k_gs_blend_px_fix(
           last = kq;
           first = false;
         }
-      };
-      if (r <= 64) {
-        // bitonic sort across the wave's lanes, in registers
-        uint64_t k = lane < r ? rk[lane] : ~0ull;
-        float al = lane < r ? ra[lane] : 0.0f;
-        for (int kk = 2; kk <= 64; kk <<= 1)
-          for (int j = kk >> 1; j > 0; j >>= 1) {
-            const uint64_t ok = __shfl_xor(k, j, 64);
-            const float oa = __shfl_xor(al, j, 64);
-            const bool take_min = ((lane & j) == 0) == ((lane & kk) == 0);
-            if (take_min ? ok < k : ok > k) {
-              k = ok;
-              al = oa;
-            }
-          }
-        blend64(k, al, r);
-        return;
       }
-      int P = 64;
-      while (P < r) P <<= 1;
-      for (int i = r + lane; i < P; i += 64) rk[i] = ~0ull;
       wave_sync_lds();
-      for (int k = 2; k <= P; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-          for (int i = lane; i < (P >> 1); i += 64) {
-            const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1)), b = a + j;
-            const uint64_t x = rk[a], y = rk[b];
-            if ((x > y) == ((a & k) == 0)) {
-              rk[a] = y;
-              rk[b] = x;
-              const float t = ra[a];
-              ra[a] = ra[b];
-              ra[b] = t;
-            }
-          }
-          wave_sync_lds();
-        }
-      for (int b0 = 0; b0 < r && !acc.stop; b0 += 64) {
-        const int i = b0 + lane;
-        blend64(i < r ? rk[i] : ~0ull, i < r ? ra[i] : 0.0f, min(64, r - b0));
-      }
-    };
-    for (uint32_t c0 = rg.x; c0 < rg.y && !acc.stop; c0 += 64) {
-      const uint32_t j = c0 + lane;
-      uint64_t key = 0;
-      float al = 0.0f;
-      const bool ok = j < rg.y && eval(j, key, al);
-      const uint64_t m = __ballot(ok);
-      const int add = __builtin_popcountll(m);
-      if (np + add > kFixCap) {
-        overflow = true;
-        break;
-      }
-      if (ok) {
-        const int q = np + __builtin_popcountll(m & below);
-        pk[q] = key;
-        pa[q] = al;
-      }
-      np += add;
-      wave_sync_lds();
-      release(c0 + 64 < rg.y
-                  ? (uint32_t)(zs_word(tkey, ids, pcoef, (int64_t)v * n, rg.x, c0 + 64) >> 32)
-                  : 0xffffffffu);
-    }
-    if (!overflow && !acc.stop) release(0xffffffffu);
-    if (overflow) {
-      // What is blended so far is exact; continue by repeated selection of
-      // the least (key, index) above the last one.  A round's scan ends at
-      // the first chunk whose bound word passes the best key found so far.
-      while (true) {
-        uint64_t best = ~0ull;
-        float best_al = 0.0f;
-        for (uint32_t c0 = rg.x; c0 < rg.y; c0 += 64) {
-          const uint32_t j = c0 + lane;
-          uint64_t key;
-          float al;
-          if (j < rg.y && eval(j, key, al) && (first || key > last) && key < best) {
-            best = key;
-            best_al = al;
-          }
-          uint64_t mn = best;
-#pragma unroll
-          for (int sh = 32; sh > 0; sh >>= 1) {
-            const uint64_t y = __shfl_xor(mn, sh, 64);
-            mn = y < mn ? y : mn;
-          }
-          if (c0 + 64 < rg.y &&
-              (uint32_t)(zs_word(tkey, ids, pcoef, (int64_t)v * n, rg.x, c0 + 64) >> 32) >
-                  (uint32_t)(mn >> 32))
-            break;
-        }
-        uint64_t mn = best;
-#pragma unroll
-        for (int sh = 32; sh > 0; sh >>= 1) {
-          const uint64_t y = __shfl_xor(mn, sh, 64);
-          mn = y < mn ? y : mn;
-        }
-        if (mn == ~0ull) break;   // wave-uniform
-        const uint64_t holders = __ballot(best == mn);
-        const float al = __shfl(best_al, __builtin_ctzll(holders), 64);
-        const int64_t e = (int64_t)v * n + (uint32_t)mn;
-        const float4 r1 = rec[3 * e + 1], r2 = rec[3 * e + 2];
-        if (!fix_blend(acc, al, r1.z, r1.w, r2.x, ord2f((uint32_t)(mn >> 32)), o.tmin)) break;
-        last = mn;
-        first = false;
-      }
+      if (nc < kFixCap) break;   // the list is exhausted
     }
     if (lane == 0) {
       float* rgb = out_rgb + (int64_t)v * 3 * plane + off;
@@ -834,7 +781,6 @@ __global__ __launch_bounds__(64 * kFixWaves) void k_gs_blend_px_fix(
       out_t[(int64_t)v * plane + off] = acc.T;
       out_n[(int64_t)v * plane + off] = acc.cnt;
     }
-    wave_sync_lds();   // LDS reuse by the next pixel
   }
 }
 

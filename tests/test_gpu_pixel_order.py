@@ -44,11 +44,11 @@ def _ord_bits(x):
     return np.where(u & np.uint32(0x80000000), ~u, u | np.uint32(0x80000000))
 
 
-PREFIX = 2048   # records per tile list sorted by the per-tile bound
+PREFIX = 4096   # records per tile list sorted by the per-tile bound
 
 
 def check_tile_words(ws, g, cov, views, tile):
-    """The blend's tile lists: per tile, the sorted prefix (first 2048
+    """The blend's tile lists: per tile, the sorted prefix (first 4096
     positions) holds the binning's first records in another order with a
     non-decreasing bound, and the bound of every prefix position is at most
     the single-precision key (its operation order retyped in numpy float32)
@@ -123,7 +123,7 @@ def check_tile_words(ws, g, cov, views, tile):
     return longest
 
 
-@pytest.mark.parametrize("n", [3000, 5000])
+@pytest.mark.parametrize("n", [5000, 9000])
 def test_pixel_order_long_tile_lists(n):
     """Thousands of small Gaussians over a few tiles: lists far longer than
     the sorted prefix, so blending and the exact pass read past it (in the
