@@ -142,10 +142,10 @@ template <typename T>
 __device__ inline void store8(T* p, const float* v);
 template <>
 __device__ inline void store8<__bf16>(__bf16* p, const float* v) {
-  v8bf a;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) a[j] = (__bf16)v[j];
-  *reinterpret_cast<v8bf*>(p) = a;
+  // one vector conversion: four packed two-value conversions
+  typedef float v8f __attribute__((ext_vector_type(8)));
+  const v8f f = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+  *reinterpret_cast<v8bf*>(p) = __builtin_convertvector(f, v8bf);
 }
 template <>
 __device__ inline void store8<float>(float* p, const float* v) {
@@ -310,6 +310,11 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   const bool fast_py = d.C == 4 && (d.kn & 7) == 0 && (reinterpret_cast<uintptr_t>(pyr) & 15) == 0;
   const long long plane = (long long)d.W * d.H;
   const int n_up = NB * kgf, n_items = n_up + NPIX * (G - kgf);
+  // this crop's pyramid layer and periphery window (the origin read once)
+  const float* pyr_base = pyr + d.pyr_off[k];
+  const float* per_base = d.has_p ? periph + (long long)d.view[k] * 3 * plane +
+                                        (long long)dec_y0(d, k) * d.W + dec_x0(d, k)
+                                  : periph;
   // every halo pixel inside the layer: no zero selects
   const bool interior = oy >= 1 && ox >= 1 && oy + TH + 1 <= S && ox + 17 <= S;
   // upsampled item e = block * kgf + group (groups fastest, so that a wave's
@@ -376,11 +381,10 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
         const int c0 = g * 8;
         if (fast_py && c0 == d.kn) {
           // pyramid layer (4 channels, one 16-byte load) and periphery crop
-          const float4 pv = *reinterpret_cast<const float4*>(pyr + d.pyr_off[k] + ((long long)y * S + x) * 4);
+          const float4 pv = *reinterpret_cast<const float4*>(pyr_base + ((long long)y * S + x) * 4);
           v[0] = pv.x; v[1] = pv.y; v[2] = pv.z; v[3] = pv.w;
           if (d.has_p) {
-            const float* pp = periph + (long long)d.view[k] * 3 * plane +
-                              (long long)(dec_y0(d, k) + y) * d.W + (dec_x0(d, k) + x);
+            const float* pp = per_base + (long long)y * d.W + x;
             v[4] = pp[0];
             v[5] = pp[plane];
             v[6] = pp[2 * plane];
