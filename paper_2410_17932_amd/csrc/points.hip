@@ -453,8 +453,9 @@ struct PixHash {
 // fragments would otherwise be 64 scattered stores per instruction.
 constexpr uint32_t kSlotRef = 0x80000000u;   // tag | table place << kRankBits | rank
 constexpr int kEmitPlaces = 4096, kRankBits = 19;   // table at half load for ~2000 fragments
-constexpr int kEmitStage = 2048;
-__global__ __launch_bounds__(256) void k_pt_emit(
+constexpr int kEmitStage = 2048, kEmitBlock = 256;
+static_assert(kEmitPlaces % kEmitBlock == 0, "table entries per thread");
+__global__ __launch_bounds__(kEmitBlock) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const uint32_t* __restrict__ ckey,
     const uint32_t* __restrict__ cent, const uint32_t* __restrict__ live_p,
@@ -523,7 +524,8 @@ __global__ __launch_bounds__(256) void k_pt_emit(
               if (o >= max_frags) continue;   // only after a wrapped count (flagged)
               // a point reaches a pixel once, so a pixel's rank in the table
               // is below the number of survivors the workgroup handles
-              // (< 2^17 < 2^kRankBits: survivors < 2^30, at least 2^21 threads)
+              // (<= 2^18 < 2^kRankBits: the grid has at least 2^30 / 2^18
+              // workgroups whenever there can be 2^30 survivors)
               uint32_t r;
               const int hs = h.add(px, r);
               const uint32_t tag = hs >= 0 ? (kSlotRef | (uint32_t)hs << kRankBits | r)
@@ -548,8 +550,21 @@ __global__ __launch_bounds__(256) void k_pt_emit(
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < kEmitPlaces; q += blockDim.x)
-    if (h.key[q] != kPixEmpty) s_first[q] = atomicAdd(&pcnt[h.key[q]], h.cnt[q]);
+  {
+    // every entry's atomic issued before any result is awaited: device-scope
+    // atomics take about a microsecond each, so one wait per thread instead
+    // of one per entry
+    constexpr int kPer = kEmitPlaces / kEmitBlock;
+    uint32_t first[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int q = threadIdx.x + r * kEmitBlock;
+      const uint32_t key = h.key[q];
+      first[r] = key != kPixEmpty ? atomicAdd(&pcnt[key], h.cnt[q]) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) s_first[threadIdx.x + r * kEmitBlock] = first[r];
+  }
   __syncthreads();
   // the staged fragments out, coalesced, with their places
   {
@@ -812,8 +827,13 @@ vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* fea
   VRS_LAUNCH_CHECK();
   uint32_t* pcnt = at<uint32_t>(ws, L.pcnt);
   uint32_t* poff = at<uint32_t>(ws, L.poff);
-  hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)std::min<int64_t>(8192, div_up(vn, 256))),
-                     dim3(256), 0, st, pos, radius, np, kv, kc, a, at<uint32_t>(ws, L.ckey0),
+  // two resident workgroups per compute unit (the LDS table and stage
+  // allow two): survivors are counted on the device, and surplus
+  // workgroups would wait for LDS only to find no work; at most 2^18
+  // survivors per workgroup (the table's rank field)
+  const int64_t emit_blocks = std::min<int64_t>(
+      div_up(vn, kEmitBlock), std::max<int64_t>(2 * device_cus(), div_up(vn, int64_t(1) << 18)));
+  hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)emit_blocks), dim3(kEmitBlock), 0, st, pos, radius, np, kv, kc, a, at<uint32_t>(ws, L.ckey0),
                      at<uint32_t>(ws, L.cent), live, at<uint32_t>(ws, L.foffs), frag_count,
                      max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
                      at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot), pcnt, dev_status);

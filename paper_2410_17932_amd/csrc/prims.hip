@@ -435,6 +435,20 @@ hipError_t fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int v = 0;
+    cached[dev] = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) ==
+                          hipSuccess && v > 0
+                      ? v
+                      : 256;
+  }
+  return cached[dev];
+}
+
 size_t scan_tmp_bytes(int64_t n_max) {
   int64_t parts = (n_max + kScanTileMin - 1) / kScanTileMin;
   return 256 + (size_t)std::max<int64_t>(parts, 1) * 8;

@@ -100,6 +100,8 @@ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // cleared: an earlier kernel on the stream zeroed those bytes of tmp since
 // their last use, so the scan runs as one launch.
 size_t scan_tmp_bytes(int64_t n_max);
+// Compute units of the current device (queried once per device).
+int device_cus();
 hipError_t exclusive_scan_u32(const uint32_t* in, const uint32_t* idx, uint32_t* out,
                               uint32_t* total, const uint32_t* n_dev, int64_t n_max, void* tmp,
                               int32_t* status, hipStream_t st, bool cleared = false);

@@ -77,6 +77,16 @@ def test_points_stacked_crops():
     assert nf > 4 * 2048
 
 
+def test_points_many_survivors():
+    """About 300k survivors: more than the emission's resident workgroups
+    take in one round of 256, so workgroups handle several rounds (the
+    first staged in LDS, later ones written directly and fixed up)."""
+    sc = synth.small_scene(35, n_gauss=200, n_points=300000, width=512, height=384, f=300.0,
+                           crops=((256.0, 192.0, 256), (200.0, 150.0, 128)), radius="lognormal")
+    nf = _run(sc, cull=False)
+    assert nf > 2_000_000
+
+
 def test_points_with_opacity_and_levels():
     sc = synth.small_scene(32, n_points=4000, crops=((64.0, 64.0, 64), (20.0, 20.0, 32)))
     op = np.random.default_rng(0).uniform(0.2, 1.0, sc["points"]["n"]).astype(np.float32)
