@@ -28,6 +28,19 @@ __device__ inline uint64_t wave_uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// A lane flag as the wave's mask (bit l = lane l) and back: the mask lives
+// in scalar registers and every combination of flags is a scalar operation.
+__device__ inline uint64_t wave_mask(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+__device__ inline bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+// c + 1 in the lanes of mask m, c elsewhere: one vector add with m as its
+// carry-in (the compiler would select and add)
+__device__ inline int count_lanes(int c, uint64_t m) {
+  uint64_t carry_out;
+  asm("v_addc_co_u32_e64 %0, %1, 0, %0, %2" : "+v"(c), "=s"(carry_out) : "s"(m));
+  (void)carry_out;
+  return c;
+}
+
 // Lower bound of G(d) = ga dx^2 + gb dx dy + gc dy^2 (positive definite)
 // over the box dx in [X0, X1], dy in [Y0, Y1]: 0 if the box holds the
 // origin, else the least of the four edge minima (the minimiser of a convex
@@ -93,23 +106,25 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   // sub-tile of this wave and the lane's pixels
   const int sx0 = tx * TILE + (wave % NQ) * SUB, sy0 = ty * TILE + (wave / NQ) * SUB;
   const int px = sx0 + lane % SUB;
-  // ry[q] is the pixel row tested against record rectangles; a pixel outside
-  // the image gets kStopped, one that has stopped kStopped + the count of
-  // sub-tile-holding records it evaluated (both fail every rectangle test)
-  constexpr int kStopped = 1 << 30;
-  int py[PPT], ry[PPT];
+  // lm[q]: the wave's lanes whose pixel q is in the image and has not
+  // stopped (one bit per lane, in scalar registers: liveness costs no vector
+  // instructions); stopcov[q]: the count of sub-tile-holding records when
+  // the pixel stopped (statistics only)
+  int py[PPT];
+  uint64_t lm[PPT];
   float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
   int cnt[PPT];
-  uint32_t last[PPT], evals[PPT];
+  uint32_t last[PPT], evals[PPT], stopcov[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     py[q] = sy0 + lane / SUB + q * Cfg::ROWS;
-    ry[q] = px >= W || py[q] >= H ? kStopped : py[q];
+    lm[q] = wave_mask(px < W && py[q] < H);
     T[q] = 1.0f;
     C0[q] = C1[q] = C2[q] = D[q] = 0.0f;
     cnt[q] = 0;
     last[q] = 0;
     evals[q] = 0;
+    stopcov[q] = 0;
   }
   const uint2 rg = ranges[tglob];
   const uint32_t begin = rg.x, end = rg.y;
@@ -119,10 +134,13 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   float yc[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) yc[q] = (float)py[q] + 0.5f;
-  int all_ry = kStopped;   // bit 30 stays set only while every pixel has stopped
+  auto any_live = [&]() {
+    uint64_t a = 0;
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) all_ry &= ry[q];
-  bool alive = __ballot((all_ry & kStopped) == 0) != 0;   // wave-uniform
+    for (int q = 0; q < PPT; ++q) a |= lm[q];
+    return a != 0;   // wave-uniform
+  };
+  bool alive = any_live();
   // records whose rectangle holds the sub-tile, so far: every live pixel
   // evaluated each of them, so they are counted per wave, not per pixel
   uint32_t ncov = 0;
@@ -207,7 +225,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
             const uint32_t cspan = (uint32_t)((int)(chi >> 16) - cy0);
 #pragma unroll
             for (int q = 0; q < PPT; ++q)
-              evals[q] += (cin & ((uint32_t)(ry[q] - cy0) <= cspan)) ? 1u : 0u;
+              evals[q] += (lane_in(lm[q]) & cin & ((uint32_t)(py[q] - cy0) <= cspan)) ? 1u : 0u;
           }
         }
         if (!m) break;
@@ -219,56 +237,58 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
         const float dx = a.x - xc;
         // the exponent's per-column part (same operations as gs_exponent)
         const float P = (a.z * dx) * dx, R = a.w * dx;
-        // One record over the lane's pixels.  in_rect(q): the pixel is live
-        // and inside the record's rectangle (tested as unsigned range checks,
-        // combined with bitwise operators so that nothing branches; where the
-        // rectangle holds the sub-tile, liveness alone).
-        auto blend_record = [&](auto in_rect, auto cover_tag) {
-          constexpr bool kCover = decltype(cover_tag)::value;
-          if (STATS && kCover) ++ncov;
-          const int stopped = kStopped + (STATS ? (int)ncov : 0);
-          all_ry = kStopped;
+        // One record over the lane's pixels.  inr[q]: the pixel is live and
+        // inside the record's rectangle (where the rectangle holds the
+        // sub-tile, liveness alone).  The two cases differ in these masks
+        // only, so the blend state has a single update path.
+        const bool cov = (mcov >> bit) & 1ull;   // uniform
+        uint64_t inr[PPT];
+        if (cov) {
+          if constexpr (STATS) ++ncov;
 #pragma unroll
-          for (int q = 0; q < PPT; ++q) {
-#pragma clang fp contract(off)   // T - w0 rounded once, the same in test and update
-            const float dy = a.y - yc[q];
-            const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
-            const float e = __builtin_amdgcn_exp2f(qq);
-            const float al = fminf(b.y * e, aclamp);
-            const bool inr = in_rect(q);
-            // w0 = alpha T is the contribution's weight and T - w0 the new
-            // transmittance: every state update below is then in place
-            const float w0 = al * T[q];
-            const float Tn = T[q] - w0;
-            const bool ok0 = inr & (al >= amin);
-            const bool stop = ok0 & (Tn < tmin);
-            const bool ok = ok0 & !stop;
-            ry[q] = stop ? stopped : ry[q];
-            const float wgt = ok ? w0 : 0.0f;
-            C0[q] = fmaf(c.x, wgt, C0[q]);
-            C1[q] = fmaf(c.y, wgt, C1[q]);
-            C2[q] = fmaf(c.z, wgt, C2[q]);
-            D[q] = fmaf(c.w, wgt, D[q]);
-            T[q] -= wgt;
-            cnt[q] += ok ? 1 : 0;
-            if constexpr (STATS) {
-              last[q] = ok ? pos : last[q];
-              if (!kCover) evals[q] += inr ? 1u : 0u;
-            }
-            all_ry &= ry[q];
-          }
-        };
-        if ((mcov >> bit) & 1ull) {
-          blend_record([&](int q) { return ry[q] < kStopped; }, std::true_type{});
+          for (int q = 0; q < PPT; ++q) inr[q] = lm[q];
         } else {
           const uint32_t lo = __float_as_uint(b.z), hi = __float_as_uint(b.w);
           const int rx0 = (int)(lo & 0xffffu), ry0 = (int)(lo >> 16);
-          const bool inx = (uint32_t)(px - rx0) <= (uint32_t)((int)(hi & 0xffffu) - rx0);
+          const uint64_t inx =
+              wave_mask((uint32_t)(px - rx0) <= (uint32_t)((int)(hi & 0xffffu) - rx0));
           const uint32_t ry_span = (uint32_t)((int)(hi >> 16) - ry0);
-          blend_record([&](int q) { return inx & ((uint32_t)(ry[q] - ry0) <= ry_span); },
-                       std::false_type{});
+#pragma unroll
+          for (int q = 0; q < PPT; ++q)
+            inr[q] = lm[q] & inx & wave_mask((uint32_t)(py[q] - ry0) <= ry_span);
         }
-        if (__ballot((all_ry & kStopped) == 0) == 0) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+#pragma clang fp contract(off)   // T - w0 rounded once, the same in test and update
+          const float dy = a.y - yc[q];
+          const float qq = fmaf(dy, fmaf(b.x, dy, R), P);
+          const float e = __builtin_amdgcn_exp2f(qq);
+          const float al = fminf(b.y * e, aclamp);
+          // w0 = alpha T is the contribution's weight and T - w0 the new
+          // transmittance: every state update below is then in place
+          const float w0 = al * T[q];
+          const float Tn = T[q] - w0;
+          // the decisions as wave masks: each comparison is one vector
+          // instruction, their combinations scalar ones
+          const uint64_t ok0 = inr[q] & wave_mask(al >= amin);
+          const uint64_t stop = ok0 & wave_mask(Tn < tmin);
+          const uint64_t okm = ok0 & ~stop;
+          lm[q] &= ~stop;
+          const bool ok = lane_in(okm);
+          if constexpr (STATS) {
+            stopcov[q] = lane_in(stop) ? ncov : stopcov[q];
+            last[q] = ok ? pos : last[q];
+            if (!cov) evals[q] += lane_in(inr[q]) ? 1u : 0u;
+          }
+          const float wgt = ok ? w0 : 0.0f;
+          C0[q] = fmaf(c.x, wgt, C0[q]);
+          C1[q] = fmaf(c.y, wgt, C1[q]);
+          C2[q] = fmaf(c.z, wgt, C2[q]);
+          D[q] = fmaf(c.w, wgt, D[q]);
+          T[q] -= wgt;
+          cnt[q] = count_lanes(cnt[q], okm);
+        }
+        if (!any_live()) {
           alive = false;
           break;
         }
@@ -278,7 +298,7 @@ __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gs_blend(
   // sub-tile-holding records: up to its stop, or all of them
 #pragma unroll
   for (int q = 0; q < PPT; ++q)
-    if constexpr (STATS) evals[q] += ry[q] >= kStopped ? (uint32_t)(ry[q] - kStopped) : ncov;
+    if constexpr (STATS) evals[q] += lane_in(lm[q]) ? ncov : stopcov[q];
   const int64_t plane = (int64_t)W * H;
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
