@@ -15,11 +15,13 @@
 //                  projection, layer, crop footprints, then the depth cull;
 //                  survivors (depth key, entry, fragment offset) compacted in
 //                  the same pass, one 64-bit atomic per workgroup for the
-//                  survivor and fragment bases
-//   k_pt_emit      one thread per survivor writes its fragments (layer
-//                  pixel, weight | point index, depth key), counts them per
-//                  pixel and takes each one a free place in its pixel's
-//                  segment (the counting atomics' old values)
+//                  survivor and fragment bases, and the survivor that opens
+//                  each emission chunk
+//   k_pt_emit      one workgroup per chunk of 1024 consecutive fragments,
+//                  one thread per survivor of the chunk: writes its
+//                  fragments (layer pixel, weight | point index, depth key),
+//                  counts them per pixel and takes each one a free place in
+//                  its pixel's segment (the counting atomics' old values)
 //   scan           per-pixel counts -> segment offsets
 //   k_pt_scatter   each fragment's record (point index, depth key, weight,
 //                  pixel) to its segment place: no atomics
@@ -34,7 +36,8 @@
 namespace vrs {
 
 struct SplatWs {
-  size_t cent, ckey0, ctr, live, foffs, frag_count,
+  size_t surv, ctr, live, frag_count,   // survivors: (entry, depth key, fragment offset, 0)
+      chunk_first,                 // per emission chunk: the survivor holding its first fragment
       fkey0, fval0, fdep, fslot,   // fragments in emission order, place in segment
       seg,                         // (point index, depth key, weight, pixel) per segment place
       fkey1, fval1,                // fragments in blend order
@@ -45,6 +48,8 @@ struct SplatWs {
 };
 
 constexpr int kSelBlock = 256;
+// Fragments per emission workgroup (one chunk of the fragment range).
+constexpr int kEmitFrags = 1024;
 
 static int64_t pyramid_pixels(const vrs_crop* crops, int n_crops, int levels) {
   int64_t s = 0;
@@ -72,12 +77,11 @@ static bool splat_layout(int64_t np, int nv, int W, int H, const vrs_crop* crops
   const int64_t vn = std::max<int64_t>(L->vn, 1), mf = std::max<int64_t>(max_frags, 1);
   const int64_t pt = std::max<int64_t>(L->pix_total, 1);
   Carver c;
-  L->cent = c.take(vn * 4);
-  L->ckey0 = c.take(vn * 4);
+  L->surv = c.take(vn * 16);
   L->ctr = c.take(8);   // survivors in the low word, fragments in the high word
   L->live = L->ctr;
   L->frag_count = L->ctr + 4;
-  L->foffs = c.take(vn * 4);
+  L->chunk_first = c.take((mf / kEmitFrags + 2) * 4);
   L->fkey0 = c.take(mf * 4);
   L->fval0 = c.take(mf * 8);
   L->fdep = c.take(mf * 4);
@@ -251,8 +255,8 @@ constexpr int kSelRounds = 4, kSelPart = kSelBlock * kSelRounds;
 __global__ __launch_bounds__(kSelBlock) void k_pt_select(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
     KCrops crops, PtArgs a, const float* __restrict__ depth, const float* __restrict__ tfinal,
-    const uint32_t* __restrict__ grid, int gx, int gy, uint32_t* __restrict__ ckey,
-    uint32_t* __restrict__ cent, uint32_t* __restrict__ foffs, uint64_t* __restrict__ ctr,
+    const uint32_t* __restrict__ grid, int gx, int gy, uint4* __restrict__ surv,
+    uint64_t* __restrict__ ctr, uint32_t* __restrict__ chunk_first, int64_t max_frags,
     int32_t* status) {
   constexpr int NW = kSelBlock / 64;
   constexpr int NSLOT = kSelRounds * VRS_MAX_VIEWS * NW;   // (view, round, wave), view-major
@@ -397,19 +401,23 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
       const uint32_t below = __builtin_amdgcn_mbcnt_hi(
           (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       const uint32_t p = base + s_pre[slot] + below;
-      ckey[p] = __float_as_uint(s_zd[(j * nv + v) * kSelBlock + tid]);
-      cent[p] = (uint32_t)(v * np + i);
-      foffs[p] = fbase + s_fpre[slot] + fi - cnt;
+      const uint32_t fo = fbase + s_fpre[slot] + fi - cnt;
+      surv[p] = make_uint4((uint32_t)(v * np + i),
+                           __float_as_uint(s_zd[(j * nv + v) * kSelBlock + tid]), fo, 0u);
+      // the emission chunks whose first fragment is one of this survivor's
+      for (uint64_t c = ((uint64_t)fo + kEmitFrags - 1) / kEmitFrags;
+           c * kEmitFrags < (uint64_t)fo + cnt && c * kEmitFrags < (uint64_t)max_frags; ++c)
+        chunk_first[c] = p;
     }
   }
 }
 
 // ------------------------------------------------------------------ emit
 // Per-workgroup pixel table in LDS: open addressing with a short linear
-// probe.  Device-wide atomics to one address serialise and are slow on
-// their own, so fragment counts (and segment places) are gathered per
-// workgroup first and the table's entries go out as one atomic each; a
-// fragment whose probe finds no place falls back to its own atomic.
+// probe.  Device-scope atomics on one address serialise, so fragment counts
+// (and segment places) are gathered per workgroup first and the table's
+// entries go out as one atomic each; a fragment whose probe finds no place
+// falls back to its own atomic.
 constexpr int kPixProbe = 8;
 constexpr uint32_t kPixEmpty = 0xffffffffu;
 template <int N>   // places, a power of two
@@ -439,165 +447,147 @@ struct PixHash {
   }
 };
 
-// One thread per survivor (compaction order): its fragments at its offset,
-// each with its layer pixel, weight | point index and depth key, and its
-// place in the pixel's segment.  Places come from the pixel counters' old
-// values: the workgroup gathers its fragments per pixel in the LDS table,
-// each table entry adds its count with one atomic whose old value is the
-// entry's first place, and a fragment's place is that plus its rank in the
-// entry (held meanwhile as a tagged table reference).  A fragment whose
-// probe finds no table place takes its own with its own atomic.  The
-// workgroup's fragments are one contiguous range (its survivors are
-// consecutive), so the first kEmitStage of them are staged in LDS and go
-// out as coalesced stores once their places are known; a lane's own
-// fragments would otherwise be 64 scattered stores per instruction.
+// One workgroup per chunk of kEmitFrags consecutive fragments (the chunks'
+// first survivors are recorded by k_pt_select), one thread per survivor of
+// the chunk: its fragments that fall in the chunk, each with its layer
+// pixel, weight | point index, depth key and place in the pixel's segment.
+// Places come from the pixel counters' old values: the workgroup gathers
+// its fragments per pixel in the LDS table (at most half full: a chunk
+// holds kEmitFrags fragments), each table entry adds its count with one
+// atomic whose old value is the entry's first place, and a fragment's
+// place is that plus its rank in the entry.  The chunk is staged in LDS
+// and goes out as coalesced stores once the places are known.  Balanced by
+// construction: every workgroup emits one chunk, however the fragments
+// spread over survivors.
+constexpr int kEmitPlaces = 2 * kEmitFrags, kEmitBlock = 256;
 constexpr uint32_t kSlotRef = 0x80000000u;   // tag | table place << kRankBits | rank
-constexpr int kEmitPlaces = 4096, kRankBits = 19;   // table at half load for ~2000 fragments
-constexpr int kEmitStage = 2048, kEmitBlock = 256;
-static_assert(kEmitPlaces % kEmitBlock == 0, "table entries per thread");
+constexpr int kRankBits = 19;
+static_assert(kEmitPlaces <= (1 << (31 - kRankBits)) && kEmitFrags < (1 << kRankBits),
+              "table place and rank fit the tag");
+static_assert(kEmitPlaces % kEmitBlock == 0 && kEmitFrags % kEmitBlock == 0,
+              "table entries and staged fragments per thread");
 __global__ __launch_bounds__(kEmitBlock) void k_pt_emit(
     const float* __restrict__ pos, const float* __restrict__ radius, int64_t np, KViews views,
-    KCrops crops, PtArgs a, const uint32_t* __restrict__ ckey,
-    const uint32_t* __restrict__ cent, const uint32_t* __restrict__ live_p,
-    const uint32_t* __restrict__ foffs, const uint32_t* __restrict__ total_p, int64_t max_frags,
-    uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval, uint32_t* __restrict__ fdep,
-    uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt, int32_t* status) {
-  __shared__ PixHash<kEmitPlaces> h;   // a workgroup emits ~2000 fragments
-  __shared__ uint32_t s_first[kEmitPlaces];
-  // staged fragments: pixel, weight bits, place (or tag), owning thread;
-  // per thread its survivor's point index and depth key
-  __shared__ uint32_t s_spx[kEmitStage], s_sw[kEmitStage], s_stag[kEmitStage];
-  __shared__ uint8_t s_sown[kEmitStage];
-  __shared__ uint32_t s_pi[256], s_dz[256];
-  static_assert(kEmitPlaces <= (1 << (31 - kRankBits)), "table place fits the tag");
+    KCrops crops, PtArgs a, const uint4* __restrict__ surv, const uint32_t* __restrict__ live_p,
+    const uint32_t* __restrict__ chunk_first, const uint32_t* __restrict__ total_p,
+    int64_t max_frags, uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval,
+    uint32_t* __restrict__ fdep, uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt,
+    int32_t* status) {
+  __shared__ PixHash<kEmitPlaces> h;
+  // staged fragments: layer pixel, weight bits, place (or tag), owning
+  // survivor slot; per survivor slot its point index and depth key
+  __shared__ uint32_t s_spx[kEmitFrags], s_sw[kEmitFrags], s_stag[kEmitFrags];
+  __shared__ uint16_t s_sown[kEmitFrags];
+  __shared__ uint32_t s_pi[kEmitFrags + 1], s_dz[kEmitFrags + 1];
+  __shared__ int s_cx0[VRS_MAX_CROPS], s_cy0[VRS_MAX_CROPS];
+  // crop origins read once (from the device placement table when there is
+  // one): the crop loop below would otherwise wait on a load per crop
+  if (threadIdx.x < crops.n) {
+    s_cx0[threadIdx.x] = crop_x0(crops, threadIdx.x);
+    s_cy0[threadIdx.x] = crop_y0(crops, threadIdx.x);
+  }
+  __syncthreads();
   const int64_t live = *live_p;
   const int64_t total = *total_p;
   if (blockIdx.x == 0 && threadIdx.x == 0 && total > max_frags) set_status(status, VRS_ECAPACITY);
-  if (total > max_frags || (int64_t)blockIdx.x * blockDim.x >= live) return;   // uniform
-  const int64_t jb = (int64_t)blockIdx.x * blockDim.x;   // first survivor of the first pass
-  const int64_t wlo = foffs[jb];
-  h.clear();
-  __syncthreads();
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const bool first = j < jb + (int64_t)blockDim.x;
-    const uint32_t e = cent[j];
-    const uint32_t dz = ckey[j];
-    const int v = (int)(e / np);
-    const int64_t i = e - (int64_t)v * np;
-    if (first) {
-      s_pi[threadIdx.x] = (uint32_t)i;
-      s_dz[threadIdx.x] = dz;
-    }
-    const KView& cv = views.v[v];
-    PtGeom g;
-    // the depth cull already passed in k_pt_select; the same single-precision
-    // sequence gives identical geometry here
-    const float x = pos[i], y = pos[np + i], z = pos[2 * np + i];
-    if (!pt_geom32(cv, x, y, z, radius[i], a.levels, g)) continue;
-    float f = 0.0f;
-    if (g.two) f = log2f(g.s) - (float)g.l0;
-    FF ux, uy;   // the weights' position, compensated
-    pt_plane_ff(cv, x, y, z, ux, uy);
-    int64_t o = foffs[j];
-    for (int k = 0; k < crops.n; ++k) {
-      const KCrop& c = crops.c[k];
-      if (c.view != v) continue;
-      const int cx0 = crop_x0(crops, k), cy0 = crop_y0(crops, k);
-      int lb = c.pix_base;
-      int l = 0;
-      for (; l < g.l0; ++l) lb += (c.size >> l) * (c.size >> l);
-      for (int li = 0; li < (g.two ? 2 : 1); ++li, ++l) {
-        const int Sl = c.size >> l;
-        const float wl = g.two ? (li == 0 ? 1.0f - f : f) : 1.0f;
-        float xl, yl;
-        int ix, iy;
-        if (pt_layer32(g, cx0, cy0, l, Sl, xl, yl, ix, iy)) {
-          const float bx = pt_frac_ff(cv.fx, ux, cv.cx, cx0, l, ix);
-          const float by = pt_frac_ff(cv.fy, uy, cv.cy, cy0, l, iy);
-          for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-              const int xx = ix + dx, yy = iy + dy;
-              if (xx < 0 || xx >= Sl || yy < 0 || yy >= Sl) continue;
-              const float w = wl * (dx ? bx : 1.0f - bx) * (dy ? by : 1.0f - by);
-              const uint32_t px = (uint32_t)(lb + yy * Sl + xx);
-              if (o >= max_frags) continue;   // only after a wrapped count (flagged)
-              // a point reaches a pixel once, so a pixel's rank in the table
-              // is below the number of survivors the workgroup handles
-              // (<= 2^18 < 2^kRankBits: the grid has at least 2^30 / 2^18
-              // workgroups whenever there can be 2^30 survivors)
-              uint32_t r;
-              const int hs = h.add(px, r);
-              const uint32_t tag = hs >= 0 ? (kSlotRef | (uint32_t)hs << kRankBits | r)
-                                           : atomicAdd(&pcnt[px], 1u);
-              const int64_t local = o - wlo;
-              if (first && local < kEmitStage) {
-                s_spx[local] = px;
-                s_sw[local] = __float_as_uint(w);
-                s_stag[local] = tag;
-                s_sown[local] = (uint8_t)threadIdx.x;
-              } else {
-                fkey[o] = px;
-                fval[o] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)i;
-                fdep[o] = dz;
-                fslot[o] = tag;
+  if (total > max_frags) return;   // uniform
+  const int64_t nchunks = (total + kEmitFrags - 1) / kEmitFrags;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t f0 = ch * kEmitFrags, f1 = std::min<int64_t>(f0 + kEmitFrags, total);
+    const int64_t s0 = chunk_first[ch];
+    h.clear();
+    __syncthreads();
+    // survivors s0, s0 + 1, ... while their fragments start before f1 (at
+    // most kEmitFrags + 1 of them: each has at least one fragment)
+    for (int64_t j = s0 + threadIdx.x; j < live; j += kEmitBlock) {
+      const uint4 sv = surv[j];
+      const int64_t lo = sv.z;
+      if (lo >= f1) break;   // offsets ascend with j
+      const int slot = (int)(j - s0);
+      const uint32_t e = sv.x;
+      const int v = (int)(e / np);
+      const int64_t i = e - (int64_t)v * np;
+      s_pi[slot] = (uint32_t)i;
+      s_dz[slot] = sv.y;
+      const KView& cv = views.v[v];
+      PtGeom g;
+      // the depth cull already passed in k_pt_select; the same single-precision
+      // sequence gives identical geometry here
+      const float x = pos[i], y = pos[np + i], z = pos[2 * np + i];
+      if (!pt_geom32(cv, x, y, z, radius[i], a.levels, g)) continue;
+      float f = 0.0f;
+      if (g.two) f = log2f(g.s) - (float)g.l0;
+      FF ux, uy;   // the weights' position, compensated
+      pt_plane_ff(cv, x, y, z, ux, uy);
+      int64_t o = lo;
+      for (int k = 0; k < crops.n && o < f1; ++k) {
+        const KCrop& c = crops.c[k];
+        if (c.view != v) continue;
+        const int cx0 = s_cx0[k], cy0 = s_cy0[k];
+        int lb = c.pix_base;
+        int l = 0;
+        for (; l < g.l0; ++l) lb += (c.size >> l) * (c.size >> l);
+        for (int li = 0; li < (g.two ? 2 : 1); ++li, ++l) {
+          const int Sl = c.size >> l;
+          const float wl = g.two ? (li == 0 ? 1.0f - f : f) : 1.0f;
+          float xl, yl;
+          int ix, iy;
+          if (pt_layer32(g, cx0, cy0, l, Sl, xl, yl, ix, iy)) {
+            const float bx = pt_frac_ff(cv.fx, ux, cv.cx, cx0, l, ix);
+            const float by = pt_frac_ff(cv.fy, uy, cv.cy, cy0, l, iy);
+            for (int dy = 0; dy < 2; ++dy)
+              for (int dx = 0; dx < 2; ++dx) {
+                const int xx = ix + dx, yy = iy + dy;
+                if (xx < 0 || xx >= Sl || yy < 0 || yy >= Sl) continue;
+                if (o >= f0 && o < f1) {
+                  const int local = (int)(o - f0);
+                  const uint32_t px = (uint32_t)(lb + yy * Sl + xx);
+                  // a point reaches a pixel once, so a pixel's rank in the
+                  // table is below the chunk's fragment count
+                  uint32_t r;
+                  const int hs = h.add(px, r);
+                  s_spx[local] = px;
+                  s_sw[local] = __float_as_uint(wl * (dx ? bx : 1.0f - bx) * (dy ? by : 1.0f - by));
+                  s_stag[local] = hs >= 0 ? (kSlotRef | (uint32_t)hs << kRankBits | r)
+                                          : atomicAdd(&pcnt[px], 1u);
+                  s_sown[local] = (uint16_t)slot;
+                }
+                ++o;
               }
-              ++o;
-            }
+          }
+          lb += Sl * Sl;
         }
-        lb += Sl * Sl;
       }
     }
-  }
-  __syncthreads();
-  {
-    // every entry's atomic issued before any result is awaited: device-scope
-    // atomics take about a microsecond each, so one wait per thread instead
-    // of one per entry
-    constexpr int kPer = kEmitPlaces / kEmitBlock;
-    uint32_t first[kPer];
+    __syncthreads();
+    {
+      // every entry's atomic issued before any result is awaited (device-
+      // scope atomics take about a microsecond each); the old values
+      // replace the counts
+      constexpr int kPer = kEmitPlaces / kEmitBlock;
+      uint32_t first[kPer];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const int q = threadIdx.x + r * kEmitBlock;
-      const uint32_t key = h.key[q];
-      first[r] = key != kPixEmpty ? atomicAdd(&pcnt[key], h.cnt[q]) : 0u;
+      for (int r = 0; r < kPer; ++r) {
+        const int q = threadIdx.x + r * kEmitBlock;
+        const uint32_t key = h.key[q];
+        first[r] = key != kPixEmpty ? atomicAdd(&pcnt[key], h.cnt[q]) : 0u;
+      }
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) h.cnt[threadIdx.x + r * kEmitBlock] = first[r];
     }
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) s_first[threadIdx.x + r * kEmitBlock] = first[r];
-  }
-  __syncthreads();
-  // the staged fragments out, coalesced, with their places
-  {
-    const int64_t whi = std::min<int64_t>(jb + (int64_t)blockDim.x < live ? foffs[jb + blockDim.x] : total,
-                                          max_frags);
-    const int nst = (int)std::min<int64_t>(whi - wlo, kEmitStage);
-    for (int q = threadIdx.x; q < nst; q += blockDim.x) {
+    __syncthreads();
+    // the chunk out, coalesced, with its places
+    for (int q = threadIdx.x; q < (int)(f1 - f0); q += kEmitBlock) {
       const uint32_t t = s_stag[q];
       const int own = s_sown[q];
-      fkey[wlo + q] = s_spx[q];
-      fval[wlo + q] = ((uint64_t)s_sw[q] << 32) | (uint64_t)s_pi[own];
-      fdep[wlo + q] = s_dz[own];
-      fslot[wlo + q] = (t & kSlotRef)
-                           ? s_first[(t & ~kSlotRef) >> kRankBits] + (t & ((1u << kRankBits) - 1u))
-                           : t;
+      fkey[f0 + q] = s_spx[q];
+      fval[f0 + q] = ((uint64_t)s_sw[q] << 32) | (uint64_t)s_pi[own];
+      fdep[f0 + q] = s_dz[own];
+      fslot[f0 + q] = (t & kSlotRef)
+                          ? h.cnt[(t & ~kSlotRef) >> kRankBits] + (t & ((1u << kRankBits) - 1u))
+                          : t;
     }
-  }
-  // tagged places -> places for the rest: each thread revisits the
-  // fragments it wrote to memory
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < live;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const bool first = j < jb + (int64_t)blockDim.x;
-    const int64_t lo0 = foffs[j], hi = std::min<int64_t>(j + 1 < live ? foffs[j + 1] : total, max_frags);
-    const int64_t lo = first ? std::max<int64_t>(lo0, wlo + kEmitStage) : lo0;
-    for (int64_t o0 = lo; o0 < hi; o0 += 8) {   // eight loads in flight, then the stores
-      uint32_t t[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) t[q] = o0 + q < hi ? fslot[o0 + q] : 0u;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (t[q] & kSlotRef)
-          fslot[o0 + q] = s_first[(t[q] & ~kSlotRef) >> kRankBits] + (t[q] & ((1u << kRankBits) - 1u));
-    }
+    __syncthreads();   // the stage is reused by the next chunk
   }
 }
 
@@ -821,21 +811,19 @@ vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* fea
   }
   // survivors with their fragment offsets (compaction order), then emission
   hipLaunchKernelGGL(k_pt_select, dim3(sel_parts), dim3(kSelBlock), sel_lds, st, pos, radius, np, kv,
-                     kc, a, depth, t_final, grid, L.gx, L.gy, at<uint32_t>(ws, L.ckey0),
-                     at<uint32_t>(ws, L.cent), at<uint32_t>(ws, L.foffs), at<uint64_t>(ws, L.ctr),
+                     kc, a, depth, t_final, grid, L.gx, L.gy, at<uint4>(ws, L.surv),
+                     at<uint64_t>(ws, L.ctr), at<uint32_t>(ws, L.chunk_first), max_frags,
                      dev_status);
   VRS_LAUNCH_CHECK();
   uint32_t* pcnt = at<uint32_t>(ws, L.pcnt);
   uint32_t* poff = at<uint32_t>(ws, L.poff);
-  // two resident workgroups per compute unit (the LDS table and stage
-  // allow two): survivors are counted on the device, and surplus
-  // workgroups would wait for LDS only to find no work; at most 2^18
-  // survivors per workgroup (the table's rank field)
-  const int64_t emit_blocks = std::min<int64_t>(
-      div_up(vn, kEmitBlock), std::max<int64_t>(2 * device_cus(), div_up(vn, int64_t(1) << 18)));
-  hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)emit_blocks), dim3(kEmitBlock), 0, st, pos, radius, np, kv, kc, a, at<uint32_t>(ws, L.ckey0),
-                     at<uint32_t>(ws, L.cent), live, at<uint32_t>(ws, L.foffs), frag_count,
-                     max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
+  // one workgroup per chunk of the capacity's fragment range (grid-stride
+  // beyond 8192 chunks); workgroups past the counted chunks leave at once
+  const int64_t emit_blocks =
+      std::min<int64_t>(8192, std::max<int64_t>(1, div_up(max_frags, kEmitFrags)));
+  hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)emit_blocks), dim3(kEmitBlock), 0, st, pos, radius,
+                     np, kv, kc, a, at<uint4>(ws, L.surv), live, at<uint32_t>(ws, L.chunk_first),
+                     frag_count, max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
                      at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot), pcnt, dev_status);
   VRS_LAUNCH_CHECK();
   // per-pixel segments, then each fragment to its place in blend order

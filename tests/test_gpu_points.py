@@ -65,9 +65,9 @@ def test_points_multi_crop_stereo():
 
 
 def test_points_stacked_crops():
-    """Five crops around one gaze point: a survivor reaches every crop, so a
-    workgroup emits far more fragments than its LDS stage and pixel table
-    hold (the direct-store and per-fragment-atomic paths run too)."""
+    """Five crops around one gaze point: a survivor reaches every crop and
+    emits up to 40 fragments, so emission chunks hold few survivors and a
+    survivor's fragments often span two chunks."""
     crops = ((100.0, 80.0, 64), (101.0, 79.0, 64), (99.0, 81.0, 96), (100.0, 80.0, 96),
              (98.0, 82.0, 128))
     sc = synth.small_scene(33, n_gauss=500, n_points=20000, width=200, height=160, f=150.0,
@@ -78,9 +78,8 @@ def test_points_stacked_crops():
 
 
 def test_points_many_survivors():
-    """About 300k survivors: more than the emission's resident workgroups
-    take in one round of 256, so workgroups handle several rounds (the
-    first staged in LDS, later ones written directly and fixed up)."""
+    """About 300k survivors and 2.4M fragments: some 2,400 emission chunks,
+    each opened by the survivor the selection recorded for it."""
     sc = synth.small_scene(35, n_gauss=200, n_points=300000, width=512, height=384, f=300.0,
                            crops=((256.0, 192.0, 256), (200.0, 150.0, 128)), radius="lognormal")
     nf = _run(sc, cull=False)
