@@ -22,18 +22,24 @@ struct CompArgs {
 
 // Origin and gaze of crop k: the host values, or the device placement
 // table's (origins clamped into the view).
-__device__ inline int cx0(const CompArgs& a, int k) {
-  return a.place ? clamp_origin(a.place[k].x, a.W - a.S[k]) : a.x0[k];
+// Crop origin and gaze from the host table, or from the device placement
+// table `pl` (a.place, or a workgroup's copy of it in LDS).
+__device__ inline int cx0(const CompArgs& a, int k, const int4* pl) {
+  return pl ? clamp_origin(pl[k].x, a.W - a.S[k]) : a.x0[k];
 }
-__device__ inline int cy0(const CompArgs& a, int k) {
-  return a.place ? clamp_origin(a.place[k].y, a.H - a.S[k]) : a.y0[k];
+__device__ inline int cy0(const CompArgs& a, int k, const int4* pl) {
+  return pl ? clamp_origin(pl[k].y, a.H - a.S[k]) : a.y0[k];
 }
-__device__ inline float cgx(const CompArgs& a, int k) {
-  return a.place ? __int_as_float(a.place[k].z) : a.gx[k];
+__device__ inline float cgx(const CompArgs& a, int k, const int4* pl) {
+  return pl ? __int_as_float(pl[k].z) : a.gx[k];
 }
-__device__ inline float cgy(const CompArgs& a, int k) {
-  return a.place ? __int_as_float(a.place[k].w) : a.gy[k];
+__device__ inline float cgy(const CompArgs& a, int k, const int4* pl) {
+  return pl ? __int_as_float(pl[k].w) : a.gy[k];
 }
+__device__ inline int cx0(const CompArgs& a, int k) { return cx0(a, k, a.place); }
+__device__ inline int cy0(const CompArgs& a, int k) { return cy0(a, k, a.place); }
+__device__ inline float cgx(const CompArgs& a, int k) { return cgx(a, k, a.place); }
+__device__ inline float cgy(const CompArgs& a, int k) { return cgy(a, k, a.place); }
 
 __device__ inline float clamp01(float x) { return x < 0.0f ? 0.0f : (x > 1.0f ? 1.0f : x); }
 
@@ -60,9 +66,9 @@ __device__ inline float smootherstep_d(float x) { return 30.0f * x * x * (x - 1.
 // Blend mask c of crop k at crop pixel (lx, ly); u_out = argument of S2
 // (PAPER mode), fe_out = edge term.
 __device__ inline float blend_mask(const CompArgs& a, int k, const float* F, int lx, int ly,
-                                   float& u_out, float& gx, float& gy) {
-  const float dx = (float)(cx0(a, k) + lx) + 0.5f - cgx(a, k);
-  const float dy = (float)(cy0(a, k) + ly) + 0.5f - cgy(a, k);
+                                   float& u_out, float& gx, float& gy, const int4* pl) {
+  const float dx = (float)(cx0(a, k, pl) + lx) + 0.5f - cgx(a, k, pl);
+  const float dy = (float)(cy0(a, k, pl) + ly) + 0.5f - cgy(a, k, pl);
   const float r = sqrtf(dx * dx + dy * dy);
   const float df = 0.5f * (float)a.S[k];
   if (a.mode == VRS_BLEND_LINEAR) {
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* P,
       }
       const float* Fk = F + a.fbase[k];
       float u, gx, gy;
-      const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy);
+      const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy, a.place);
       const long long fp = (long long)S * S, fo = (long long)ly * S + lx;
       o0 = (1.0f - c) * o0 + c * Fk[fo];
       o1 = (1.0f - c) * o1 + c * Fk[fp + fo];
@@ -121,7 +127,7 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* P,
 // Four pixels (v, y, x..x+3) of a row: their crop chain from P into out
 // (which may be P: every read comes before the writes).
 __device__ inline void comp_quad(const CompArgs& a, const float* P, const float* __restrict__ F,
-                                 float* out, int v, int y, int x) {
+                                 float* out, int v, int y, int x, const int4* pl) {
   const long long plane = (long long)a.W * a.H;
   const long long base = (long long)v * 3 * plane + (long long)y * a.W + x;
   float4 c4[3] = {*reinterpret_cast<const float4*>(P + base),
@@ -134,23 +140,23 @@ __device__ inline void comp_quad(const CompArgs& a, const float* P, const float*
   }
   for (int k = 0; k < a.n_crops; ++k) {
     if (a.view[k] != v) continue;
-    const int S = a.S[k], ly = y - cy0(a, k);
-    if (ly < 0 || ly >= S || x + 3 < cx0(a, k) || x >= cx0(a, k) + S) continue;
+    const int S = a.S[k], ly = y - cy0(a, k, pl);
+    if (ly < 0 || ly >= S || x + 3 < cx0(a, k, pl) || x >= cx0(a, k, pl) + S) continue;
     const float* Fk = F + a.fbase[k];
     const long long fp = (long long)S * S;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int lx = x + j - cx0(a, k);
+      const int lx = x + j - cx0(a, k, pl);
       if (lx < 0 || lx >= S) continue;
       {
         // outside the crop's inscribed circle the mask is 0 in both modes
         // (the same operations as blend_mask): the pixel keeps its value
-        const float dx = (float)(cx0(a, k) + lx) + 0.5f - cgx(a, k);
-        const float dy = (float)(cy0(a, k) + ly) + 0.5f - cgy(a, k);
+        const float dx = (float)(cx0(a, k, pl) + lx) + 0.5f - cgx(a, k, pl);
+        const float dy = (float)(cy0(a, k, pl) + ly) + 0.5f - cgy(a, k, pl);
         if (!(sqrtf(dx * dx + dy * dy) < 0.5f * (float)S)) continue;
       }
       float u, gx, gy;
-      const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy);
+      const float c = blend_mask(a, k, Fk, lx, ly, u, gx, gy, pl);
       const long long fo = (long long)ly * S + lx;
       o[0][j] = (1.0f - c) * o[0][j] + c * Fk[fo];
       o[1][j] = (1.0f - c) * o[1][j] + c * Fk[fp + fo];
@@ -173,7 +179,7 @@ __global__ __launch_bounds__(256) void k_composite4(CompArgs a, const float* __r
     const int v = (int)(q / qplane);
     const long long pi = (q - v * qplane) * 4;
     const int y = (int)(pi / a.W), x = (int)(pi - (long long)y * a.W);
-    comp_quad(a, P, F, out, v, y, x);
+    comp_quad(a, P, F, out, v, y, x, a.place);
   }
 }
 
@@ -183,18 +189,27 @@ __global__ __launch_bounds__(256) void k_composite4(CompArgs a, const float* __r
 // with the whole crop chain.  Pixels under no crop are not touched.
 __global__ __launch_bounds__(256) void k_composite4_inplace(CompArgs a, float* io,
                                                             const float* __restrict__ F) {
+  // the device placement table read once per workgroup: every pixel walks
+  // the crop chain, which would otherwise wait on a load per crop
+  __shared__ int4 s_pl[VRS_MAX_CROPS];
+  const int4* pl = nullptr;
+  if (a.place) {   // uniform
+    if (threadIdx.x < a.n_crops) s_pl[threadIdx.x] = a.place[threadIdx.x];
+    __syncthreads();
+    pl = s_pl;
+  }
   const int kc = blockIdx.y;
   const int S = a.S[kc], v = a.view[kc];
-  const int gx0 = cx0(a, kc) >> 2, ng = ((cx0(a, kc) + S - 1) >> 2) - gx0 + 1;
+  const int gx0 = cx0(a, kc, pl) >> 2, ng = ((cx0(a, kc, pl) + S - 1) >> 2) - gx0 + 1;
   const long long i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= (long long)S * ng) return;
   const int ly = (int)(i / ng);
-  const int y = cy0(a, kc) + ly, x = (gx0 + (int)(i - (long long)ly * ng)) * 4;
+  const int y = cy0(a, kc, pl) + ly, x = (gx0 + (int)(i - (long long)ly * ng)) * 4;
   for (int k = 0; k < kc; ++k)
-    if (a.view[k] == v && y >= cy0(a, k) && y < cy0(a, k) + a.S[k] && x + 3 >= cx0(a, k) &&
-        x < cx0(a, k) + a.S[k])
+    if (a.view[k] == v && y >= cy0(a, k, pl) && y < cy0(a, k, pl) + a.S[k] &&
+        x + 3 >= cx0(a, k, pl) && x < cx0(a, k, pl) + a.S[k])
       return;   // an earlier crop's group
-  comp_quad(a, io, F, io, v, y, x);
+  comp_quad(a, io, F, io, v, y, x, pl);
 }
 
 // Adjoint.  Per pixel the crop chain is replayed forward to recover the
@@ -233,7 +248,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompArgs a, const float* 
         const int k = ks[j], S = a.S[k];
         const int lx = x - cx0(a, k), ly = y - cy0(a, k);
         const float* Fk = F + a.fbase[k];
-        cs[j] = blend_mask(a, k, Fk, lx, ly, us[j], gxs[j], gys[j]);
+        cs[j] = blend_mask(a, k, Fk, lx, ly, us[j], gxs[j], gys[j], a.place);
         const long long fp = (long long)S * S, fo = (long long)ly * S + lx;
         for (int ch = 0; ch < 3; ++ch)
           o[j + 1][ch] = (1.0f - cs[j]) * o[j][ch] + cs[j] * Fk[ch * fp + fo];

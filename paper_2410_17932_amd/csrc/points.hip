@@ -216,9 +216,10 @@ __device__ inline uint32_t pt_candidates(const KView& cv, int v, int n_crops,
 }
 
 // Footprint targets of a projected point over the candidate crops of view v
-// and the point's one or two pyramid layers.
+// and the point's one or two pyramid layers; ox, oy: the crops' origins.
 __device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, const KCrops& crops,
-                                           uint32_t cand, int levels) {
+                                           uint32_t cand, int levels, const int* ox,
+                                           const int* oy) {
   uint32_t cnt = 0;
   const float M = (float)(1 << levels);
   while (cand) {
@@ -226,7 +227,7 @@ __device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, const KCrops&
     cand &= cand - 1;
     const KCrop& c = crops.c[k];
     if (c.view != v) continue;
-    const int cx0 = crop_x0(crops, k), cy0 = crop_y0(crops, k);
+    const int cx0 = ox[k], cy0 = oy[k];
     const float ax = g.px - (float)cx0, ay = g.py - (float)cy0, lim = (float)c.size + M;
     if (!(ax >= -M && ax < lim && ay >= -M && ay < lim)) continue;
     for (int li = 0; li < (g.two ? 2 : 1); ++li) {
@@ -265,6 +266,9 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
   __shared__ uint64_t s_mask[NSLOT];
   __shared__ uint32_t s_pre[NSLOT], s_fsum[NSLOT], s_fpre[NSLOT];
   __shared__ uint32_t s_wsum[NW], s_wfsum[NW];
+  // crop origins read once (from the device placement table when there is
+  // one): a survivor's crop loop would otherwise wait on a load per crop
+  __shared__ int s_ox[VRS_MAX_CROPS], s_oy[VRS_MAX_CROPS];
   extern __shared__ __align__(16) char s_dyn[];
   const int nv = views.n;
   float* s_zd = reinterpret_cast<float*>(s_dyn);                               // [round][view][tid]
@@ -273,6 +277,10 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
   for (int e = tid; e < NSLOT; e += kSelBlock) {
     s_mask[e] = 0;
     s_fsum[e] = 0;
+  }
+  if (tid < crops.n) {
+    s_ox[tid] = crop_x0(crops, tid);
+    s_oy[tid] = crop_y0(crops, tid);
   }
   __syncthreads();
   const int64_t part = blockIdx.x;
@@ -323,7 +331,7 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
       if (ok[j] && !(cull[j] && pt_hidden(tz[j], tf[j], dp[j], a.cov_min, a.slack))) {
         PtGeom g;   // recomputed for the few points the cull keeps
         pt_geom32(cv, px[j], py[j], pz[j], pr[j], a.levels, g);
-        cnt = pt_targets_over(g, v, crops, cand[j], a.levels);
+        cnt = pt_targets_over(g, v, crops, cand[j], a.levels, s_ox, s_oy);
       }
       s_zd[(j * nv + v) * kSelBlock + tid] = tz[j];
       s_cnt[(j * nv + v) * kSelBlock + tid] = cnt;
