@@ -339,14 +339,16 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
       load8<float>(c00 + kn8, a01);
       load8<float>(c00 + CC * kn8, a10);
       load8<float>(c00 + (CC + 1) * kn8, a11);
-      // horizontal: left fine column (3/4 a_0 + 1/4 a_1), right (1/4, 3/4)
+      // horizontal: left fine column (3/4 a_0 + 1/4 a_1), right (1/4, 3/4),
+      // each pair from the difference: a_0 + d/4 and a_1 - d/4
       float tl[8], tr[8], bl[8], br[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        tl[j] = fmaf(0.25f, a01[j], 0.75f * a00[j]);
-        tr[j] = fmaf(0.75f, a01[j], 0.25f * a00[j]);
-        bl[j] = fmaf(0.25f, a11[j], 0.75f * a10[j]);
-        br[j] = fmaf(0.75f, a11[j], 0.25f * a10[j]);
+        const float dt = a01[j] - a00[j], db = a11[j] - a10[j];
+        tl[j] = fmaf(0.25f, dt, a00[j]);
+        tr[j] = fmaf(-0.25f, dt, a01[j]);
+        bl[j] = fmaf(0.25f, db, a10[j]);
+        br[j] = fmaf(-0.25f, db, a11[j]);
       }
       auto put = [&](auto inside_tag) {
 #pragma unroll
@@ -358,8 +360,10 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
           float v[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
+            // vertical likewise: top + e/4 (upper fine row), bot - e/4
             const float top = dx ? tr[j] : tl[j], bot = dx ? br[j] : bl[j];
-            const float val = dy ? fmaf(0.75f, bot, 0.25f * top) : fmaf(0.25f, bot, 0.75f * top);
+            const float e = bot - top;
+            const float val = dy ? fmaf(-0.25f, e, bot) : fmaf(0.25f, e, top);
             v[j] = in ? val : 0.0f;
           }
           store8<T>(&tile[(hy * 18 + hx) * cin8 + g * 8], v);
@@ -404,13 +408,17 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   store_chunk(0);
   __syncthreads();
   // ---- MFMA main loop over weight chunks
-  v4f acc[RPW][NT];
-#pragma unroll
-  for (int r = 0; r < RPW; ++r)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[r][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  // the accumulators start from the biases (lane (col, kq) holds channels
+  // 4 kq + i of each N-tile), so the epilogue adds nothing
   const int r0 = wave * RPW;
   const int col = lane & 15, kq = lane >> 4;
+  v4f acc[RPW][NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const float4 bj = *reinterpret_cast<const float4*>(&bp[j * 16 + 4 * kq]);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) acc[r][j] = v4f{bj.x, bj.y, bj.z, bj.w};
+  }
   const int rowbase = (r0 * 18 + col) * cin8;
   for (int c = 0; c < nchunks; ++c) {
     if (!ONE && c + 1 < nchunks) load_chunk(c + 1);
@@ -456,15 +464,13 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   // lane's four channels are contiguous in h and in the pre-activations.
   const bool write_h = hf.fovea == nullptr || pre != nullptr;
   const int x = ox + col;
-  // channel pairs outer, rows inner: biases and head weights are read once
+  // channel pairs outer, rows inner: head weights are read once
   // per pair; the head's partial products accumulate per row
   float part[RPW][3];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) part[r][0] = part[r][1] = part[r][2] = 0.0f;
 #pragma unroll
   for (int t = 0; t < NT / 2; ++t) {
-    const float4 bf = *reinterpret_cast<const float4*>(&bp[2 * t * 16 + 4 * kq]);
-    const float4 bg = *reinterpret_cast<const float4*>(&bp[(2 * t + 1) * 16 + 4 * kq]);
     float w[4][3];
     if (hf.fovea) {
 #pragma unroll
@@ -479,10 +485,10 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
       const int y = oy + r0 + r;
       if (y >= S) continue;   // uniform over the wave
       const long long p = (long long)y * S + x;
-      const float f[4] = {acc[r][2 * t][0] + bf.x, acc[r][2 * t][1] + bf.y,
-                          acc[r][2 * t][2] + bf.z, acc[r][2 * t][3] + bf.w};
-      const float g[4] = {acc[r][2 * t + 1][0] + bg.x, acc[r][2 * t + 1][1] + bg.y,
-                          acc[r][2 * t + 1][2] + bg.z, acc[r][2 * t + 1][3] + bg.w};
+      const float f[4] = {acc[r][2 * t][0], acc[r][2 * t][1], acc[r][2 * t][2],
+                          acc[r][2 * t][3]};
+      const float g[4] = {acc[r][2 * t + 1][0], acc[r][2 * t + 1][1], acc[r][2 * t + 1][2],
+                          acc[r][2 * t + 1][3]};
       float hv[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) hv[i] = elu_f(f[i]) * sigmoid_f(g[i]);
