@@ -205,6 +205,30 @@ __host__ __device__ inline size_t conv_smem_bytes(int cin8, int kn, int kpad) {
          (size_t)(kpad / Cfg::KSTEP) * 4 * sizeof(int);
 }
 
+// One 16-channel slice of the RGB head on the matrix cores: acc += A B with
+// A = the head weights (lane (col, kq): W_o[col][4 kq + i]) and B = the
+// gated values (lane (col, kq): channels 4 kq + i of pixel col).  BF16
+// operands with float accumulation (one 16x16x16 step), or float operands
+// (four 16x16x4 steps, the slice's k = 4 kq + i taken as k-index kq of
+// step i).
+template <typename T>
+__device__ inline v4f head_mfma(const float* wa, const float* hv, v4f acc) {
+  if constexpr (sizeof(T) == 2) {
+    typedef short v4s __attribute__((ext_vector_type(4)));
+    v4s a, b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = __builtin_bit_cast(short, (__bf16)wa[i]);
+      b[i] = __builtin_bit_cast(short, (__bf16)hv[i]);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[i], hv[i], acc, 0, 0, 0);
+    return acc;
+  }
+}
+
 // Register budget per N-tile count: the occupancy the accumulators allow
 // (4, 3, 2, 2 waves per SIMD for 2, 4, 6, 8 N-tiles; 8 N-tiles use 8-row
 // tiles).
@@ -464,20 +488,26 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   // lane's four channels are contiguous in h and in the pre-activations.
   const bool write_h = hf.fovea == nullptr || pre != nullptr;
   const int x = ox + col;
-  // channel pairs outer, rows inner: head weights are read once
-  // per pair; the head's partial products accumulate per row
-  float part[RPW][3];
+  // The fused RGB head F = W_o h + b_o is one small matrix product per row
+  // on the matrix cores: the gated values already sit in the layout of the
+  // B operand (lane (col, kq): channels 4 kq + i of pixel col), W_o (rows:
+  // colour channels, padded to 16) is the A operand, and the result's lanes
+  // kq = 0 hold the three colours of pixel col.  Channel pairs outer, rows
+  // inner: the head's A operand is built once per pair.
+  v4f head[RPW];
+  if (hf.fovea) {
+    const v4f hb0 = kq == 0 ? v4f{hf.bo[0], hf.bo[1], hf.bo[2], 0.0f} : v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) part[r][0] = part[r][1] = part[r][2] = 0.0f;
+    for (int r = 0; r < RPW; ++r) head[r] = hb0;
+  }
 #pragma unroll
   for (int t = 0; t < NT / 2; ++t) {
-    float w[4][3];
+    float wa[4];   // A operand: W_o[col][t 16 + 4 kq + i] (zero beyond 3 colours or the width)
     if (hf.fovea) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int ch = t * 16 + 4 * kq + i;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) w[i][c] = ch < d.width ? hf.wo[c * d.width + ch] : 0.0f;
+        wa[i] = col < 3 && ch < d.width ? hf.wo[col * d.width + ch] : 0.0f;
       }
     }
 #pragma unroll
@@ -492,12 +522,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
       float hv[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) hv[i] = elu_f(f[i]) * sigmoid_f(g[i]);
-      if (hf.fovea) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) part[r][c] = fmaf(w[i][c], hv[i], part[r][c]);
-      }
+      if (hf.fovea) head[r] = head_mfma<T>(wa, hv, head[r]);
       if (x < S) {
         if (write_h) {
           T* hp = hout + d.h_off[k] + p * d.kp + t * 16 + 4 * kq;
@@ -516,25 +541,16 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
       }
     }
   }
-  if (hf.fovea) {
-    // sum the head's partial products over the four lanes of each pixel
-    const float b0 = hf.bo[0], b1 = hf.bo[1], b2 = hf.bo[2];
+  if (hf.fovea && kq == 0 && x < S) {
     const long long opl = (long long)S * S;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
       const int y = oy + r0 + r;
-      if (y >= S) continue;   // uniform over the wave
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        part[r][c] += __shfl_xor(part[r][c], 16, 64);
-        part[r][c] += __shfl_xor(part[r][c], 32, 64);
-      }
-      if (kq == 0 && x < S) {
-        const long long p = (long long)y * S + x;
-        hf.fovea[hf.out_base[k] + p] = part[r][0] + b0;
-        hf.fovea[hf.out_base[k] + opl + p] = part[r][1] + b1;
-        hf.fovea[hf.out_base[k] + 2 * opl + p] = part[r][2] + b2;
-      }
+      if (y >= S) continue;
+      const long long p = (long long)y * S + x;
+      hf.fovea[hf.out_base[k] + p] = head[r][0];
+      hf.fovea[hf.out_base[k] + opl + p] = head[r][1];
+      hf.fovea[hf.out_base[k] + 2 * opl + p] = head[r][2];
     }
   }
 }
