@@ -585,9 +585,12 @@ __global__ __launch_bounds__(256) void k_gs_bin_scatter(
     const uint32_t* __restrict__ ucnt, const uint32_t* __restrict__ toff,
     const uint32_t* __restrict__ total_p, int64_t max_pairs, int64_t sxn, int64_t spv,
     int64_t tiles_x, int64_t tiles_y, uint32_t* __restrict__ ids) {
+  // the unit's pairs, staged per wave: a lane reads back only what it wrote
+  __shared__ uint64_t s_unit[4][kBinUnit];
   const int lane = threadIdx.x & 63;
   if ((int64_t)*total_p > max_pairs) return;
   const uint32_t nunits = *nunits_p;
+  uint64_t* su = s_unit[threadIdx.x >> 6];
   for (uint32_t u = blockIdx.x * 4u + (threadIdx.x >> 6); u < nunits; u += gridDim.x * 4u) {
     uint32_t lo, hi;
     const int64_t s = bin_unit(ubase, st_total, srange, u, &lo, &hi);
@@ -595,10 +598,22 @@ __global__ __launch_bounds__(256) void k_gs_bin_scatter(
     uint32_t cursor = 0;
     if (bin_tile(s, lane, sxn, spv, tiles_x, tiles_y, &t))
       cursor = toff[t] + ucnt[(int64_t)u * 64 + lane];
-    uint64_t cur = lo + lane < hi ? svals[lo + lane] : 0ull;
-    for (uint32_t i = lo; i < hi; i += 64) {
-      const uint32_t jn = i + 64 + lane;
-      const uint64_t nxt = jn < hi ? svals[jn] : 0ull;   // one round ahead
+    // Every load of the unit in flight at once, then parked in LDS.  A load
+    // issued inside the round loop would have to complete before the next
+    // round, and the loads and stores of one wave share a single in-order
+    // completion counter: that wait would drain the round's 64 stores too.
+    {
+      uint64_t r[kBinUnit / 64];
+#pragma unroll
+      for (int k = 0; k < kBinUnit / 64; ++k) {
+        const uint32_t j = lo + 64 * k + lane;
+        r[k] = j < hi ? svals[j] : 0ull;
+      }
+#pragma unroll
+      for (int k = 0; k < kBinUnit / 64; ++k) su[64 * k + lane] = r[k];
+    }
+    for (uint32_t i = lo, k = 0; i < hi; i += 64, ++k) {
+      const uint64_t cur = su[64 * k + lane];
       const uint32_t gi = (uint32_t)cur;
       uint64_t R[kSuper], X[kSuper];
       bool rp[kSuper], cp[kSuper];
@@ -613,7 +628,6 @@ __global__ __launch_bounds__(256) void k_gs_bin_scatter(
                                                __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u))] = gi;
       }
       cursor += bin_lane_count(R, X, lane);
-      cur = nxt;
     }
   }
 }
