@@ -15,7 +15,7 @@
 //                     order, and there are few of them (a Gaussian reaches
 //                     far fewer super-tiles than tiles)
 //   k_gs_runs         each super-tile's run [begin, end) in the sorted pairs
-//   k_gs_units        runs cut into work units of 512 pairs (a scan), and
+//   k_gs_units        runs cut into work units of 256 pairs (a scan), and
 //                     the exact tile pair total
 //   k_gs_bin_count    one wave per unit: per tile (tile = lane of an 8 x 8
 //                     super-tile) the unit's pairs reaching it, from row
@@ -227,16 +227,13 @@ __device__ inline uint32_t halfwave_lower_bound(const uint32_t* __restrict__ key
 
 // R[r] (X[c]): lanes whose rectangle reaches tile row r (column c); rp, cp:
 // the same per lane
-__device__ inline void bin_masks(uint32_t r12, bool ok, uint64_t* R, uint64_t* X, bool* rp,
-                                 bool* cp) {
+__device__ inline void bin_masks(uint32_t r12, bool ok, uint64_t* R, uint64_t* X) {
   const int lx0 = (int)(r12 & 7u), lx1 = (int)((r12 >> 3) & 7u);
   const int ly0 = (int)((r12 >> 6) & 7u), ly1 = (int)((r12 >> 9) & 7u);
 #pragma unroll
   for (int k = 0; k < kSuper; ++k) {
-    rp[k] = ok && ly0 <= k && k <= ly1;
-    cp[k] = ok && lx0 <= k && k <= lx1;
-    R[k] = __ballot(rp[k]);
-    X[k] = __ballot(cp[k]);
+    R[k] = __builtin_amdgcn_ballot_w64(ok && ly0 <= k && k <= ly1);
+    X[k] = __builtin_amdgcn_ballot_w64(ok && lx0 <= k && k <= lx1);
   }
 }
 
@@ -389,8 +386,7 @@ __global__ __launch_bounds__(256) void k_gs_bin_count(const uint64_t* __restrict
     for (int k = 0; k < kBinUnit / 64; ++k) {
       if (lo + 64 * k >= hi) break;   // uniform over the wave
       uint64_t R[kSuper], X[kSuper];
-      bool rp[kSuper], cp[kSuper];
-      bin_masks(r12[k], lo + 64 * k + lane < hi, R, X, rp, cp);
+      bin_masks(r12[k], lo + 64 * k + lane < hi, R, X);
       cnt += bin_lane_count(R, X, lane);
     }
     ucnt[(int64_t)u * 64 + lane] = cnt;
@@ -616,14 +612,14 @@ __global__ __launch_bounds__(256) void k_gs_bin_scatter(
       const uint64_t cur = su[64 * k + lane];
       const uint32_t gi = (uint32_t)cur;
       uint64_t R[kSuper], X[kSuper];
-      bool rp[kSuper], cp[kSuper];
-      bin_masks((uint32_t)(cur >> 32), i + lane < hi, R, X, rp, cp);
+      bin_masks((uint32_t)(cur >> 32), i + lane < hi, R, X);
 #pragma unroll
       for (int l = 0; l < 64; ++l) {
-        // the lanes reaching tile l are those of M: the rank is a bit count
+        // the lanes reaching tile l are those of M (a wave-uniform mask, the
+        // store's execution mask): the rank is a bit count
         const uint64_t M = R[l >> 3] & X[l & 7];
         const uint32_t at_l = (uint32_t)__builtin_amdgcn_readlane((int)cursor, l);
-        if (rp[l >> 3] && cp[l & 7])
+        if (__builtin_amdgcn_inverse_ballot_w64(M))
           ids[at_l + __builtin_amdgcn_mbcnt_hi((uint32_t)(M >> 32),
                                                __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u))] = gi;
       }

@@ -39,7 +39,7 @@ inline int bits_for(int64_t n) {
 
 // Binning work unit: up to kBinUnit consecutive pairs of one super-tile's
 // run (one wave, kBinUnit / 64 rounds of one pair per lane).
-constexpr int kBinUnit = 512;
+constexpr int kBinUnit = 256;
 inline int64_t bin_units_max(int64_t max_pairs, int64_t st_total) {
   return (std::max<int64_t>(max_pairs, 1) + kBinUnit - 1) / kBinUnit + st_total;
 }
