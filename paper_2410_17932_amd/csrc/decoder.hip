@@ -175,6 +175,13 @@ struct ConvCfg {
   static constexpr int TH = sizeof(T) == 2 && NT >= 8 ? 8 : DecTraits<T>::TH;
   static constexpr int KSTEP = DecTraits<T>::KSTEP;
   static constexpr int NPIX = (TH + 2) * 18;
+  // halo pixel stride: cin8 channels, plus 8 (16 bytes) in the BF16 levels
+  // of 4 or more N-tiles, whose LDS budget allows it: their 144-byte stride
+  // (nine 16-byte units) meets more LDS bank conflicts in the fill's 16-byte
+  // stores and the A-operand reads than 160 bytes (conflict cycles -34 % and
+  // -11 %, the levels ~3 % faster).  The finest level (two N-tiles) would
+  // lose its fourth workgroup per CU to it.
+  static constexpr int CPAD = sizeof(T) == 2 && NT >= 4 ? 8 : 0;
   static constexpr int CR = TH / 2 + 2, CC = 10;       // coarse rows / columns staged
   static constexpr int NOUT = NT * 16;
   static constexpr int NBUF = ONE ? 1 : 2;
@@ -201,7 +208,7 @@ __host__ __device__ inline int conv_region_bytes(int kn) {
 template <typename T, int NT, bool ONE>
 __host__ __device__ inline size_t conv_smem_bytes(int cin8, int kn, int kpad) {
   using Cfg = ConvCfg<T, NT, ONE>;
-  return (size_t)Cfg::NPIX * cin8 * sizeof(T) + conv_region_bytes<T, NT, ONE>(kn) +
+  return (size_t)Cfg::NPIX * (cin8 + Cfg::CPAD) * sizeof(T) + conv_region_bytes<T, NT, ONE>(kn) +
          (size_t)(kpad / Cfg::KSTEP) * 4 * sizeof(int);
 }
 
@@ -249,8 +256,9 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   constexpr int BROW = Cfg::BROW;
   extern __shared__ __align__(16) char smem[];
   const int cin8 = d.cin8, kn8 = (d.kn + 7) & ~7;
+  const int cs = cin8 + Cfg::CPAD;   // halo pixel stride (elements)
   T* tile = reinterpret_cast<T*>(smem);
-  char* region = smem + (size_t)NPIX * cin8 * sizeof(T);
+  char* region = smem + (size_t)NPIX * cs * sizeof(T);
   float* ctile = reinterpret_cast<float*>(region);
   T* sB = reinterpret_cast<T*>(region);   // after the fill
   int* s_aoff = reinterpret_cast<int*>(region + conv_region_bytes<T, NT, ONE>(d.kn));
@@ -319,7 +327,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
         cu = 0;
       }
       const int ty = tap / 3, tx = tap - 3 * ty;
-      s_aoff[i] = (ty * 18 + tx) * cin8 + cu * (sizeof(T) == 2 ? 8 : 1);
+      s_aoff[i] = (ty * 18 + tx) * cs + cu * (sizeof(T) == 2 ? 8 : 1);
     }
   }
   // ---- halo tile fill.  Upsampled channels: one work item per 2x2 block of
@@ -390,7 +398,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
             const float val = dy ? fmaf(-0.25f, e, bot) : fmaf(0.25f, e, top);
             v[j] = in ? val : 0.0f;
           }
-          store8<T>(&tile[(hy * 18 + hx) * cin8 + g * 8], v);
+          store8<T>(&tile[(hy * 18 + hx) * cs + g * 8], v);
         }
       };
       if (interior)
@@ -425,7 +433,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
           }
         }
       }
-      store8<T>(&tile[pix * cin8 + g * 8], v);
+      store8<T>(&tile[pix * cs + g * 8], v);
     }
   }
   __syncthreads();   // the coarse footprint is dead from here
@@ -443,7 +451,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
 #pragma unroll
     for (int r = 0; r < RPW; ++r) acc[r][j] = v4f{bj.x, bj.y, bj.z, bj.w};
   }
-  const int rowbase = (r0 * 18 + col) * cin8;
+  const int rowbase = (r0 * 18 + col) * cs;
   for (int c = 0; c < nchunks; ++c) {
     if (!ONE && c + 1 < nchunks) load_chunk(c + 1);
     const T* B = sB + (ONE ? 0 : (c & 1)) * NOUT * BROW;
@@ -456,7 +464,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
         v8bf a[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r)
-          a[r] = *reinterpret_cast<const v8bf*>(&tile[abase + r * 18 * cin8]);
+          a[r] = *reinterpret_cast<const v8bf*>(&tile[abase + r * 18 * cs]);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const v8bf b = *reinterpret_cast<const v8bf*>(&B[(j * 16 + col) * BROW + s * KSTEP + kq * 8]);
@@ -467,7 +475,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
       } else {
         float a[RPW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) a[r] = to_f(tile[abase + r * 18 * cin8]);
+        for (int r = 0; r < RPW; ++r) a[r] = to_f(tile[abase + r * 18 * cs]);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const float b = to_f(B[(j * 16 + col) * BROW + s * KSTEP + kq]);
