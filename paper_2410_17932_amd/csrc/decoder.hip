@@ -152,6 +152,14 @@ __device__ inline void store8<float>(float* p, const float* v) {
   *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
   *reinterpret_cast<float4*>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
 }
+// eight elements moved as they are
+template <typename T>
+__device__ inline void copy8(T* dst, const T* src) {
+  static_assert(sizeof(T) == 2 || sizeof(T) == 4, "BF16 or float");
+  *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+  if constexpr (sizeof(T) == 4)
+    *reinterpret_cast<uint4*>(dst + 4) = *reinterpret_cast<const uint4*>(src + 4);
+}
 
 // head: optional fused RGB head at the finest level (fovea != null):
 // F = W_o h_0 + b_o written straight to the packed foveal image; h_0 is
@@ -168,20 +176,20 @@ struct HeadFuse {
 // once, at the start, overlapping the halo fill; otherwise two chunks of CHS
 // k-steps are double-buffered: 8 KB, or 4 KB for two N-tiles, whose level
 // (the finest) is bound by the halo fill's latency, so four workgroups per
-// CU (38 KB each) beat whole weights at three.
+// CU (40 KB each) beat whole weights at three.
 template <typename T, int NT, bool ONE>
 struct ConvCfg {
   // 8-row tiles where the accumulators would leave one wave per SIMD
   static constexpr int TH = sizeof(T) == 2 && NT >= 8 ? 8 : DecTraits<T>::TH;
   static constexpr int KSTEP = DecTraits<T>::KSTEP;
   static constexpr int NPIX = (TH + 2) * 18;
-  // halo pixel stride: cin8 channels, plus 8 (16 bytes) in the BF16 levels
-  // of 4 or more N-tiles, whose LDS budget allows it: their 144-byte stride
-  // (nine 16-byte units) meets more LDS bank conflicts in the fill's 16-byte
-  // stores and the A-operand reads than 160 bytes (conflict cycles -34 % and
-  // -11 %, the levels ~3 % faster).  The finest level (two N-tiles) would
-  // lose its fourth workgroup per CU to it.
-  static constexpr int CPAD = sizeof(T) == 2 && NT >= 4 ? 8 : 0;
+  // halo pixel stride: cin8 channels, plus 8 (16 bytes) in the BF16 levels:
+  // their strides of an odd number of 16-byte units (80 and 144 bytes) meet
+  // more LDS bank conflicts in the fill's 16-byte stores and the A-operand
+  // reads than 96 and 160 bytes (conflict cycles -40 %, -34 % and -11 % for
+  // 2, 4 and 8 N-tiles).  The coarse footprint is then kept in BF16, so the
+  // finest level still fits four workgroups per CU.
+  static constexpr int CPAD = sizeof(T) == 2 ? 8 : 0;
   static constexpr int CR = TH / 2 + 2, CC = 10;       // coarse rows / columns staged
   static constexpr int NOUT = NT * 16;
   static constexpr int NBUF = ONE ? 1 : 2;
@@ -195,13 +203,14 @@ struct ConvCfg {
   static constexpr int PPT = (PIECES + 255) / 256;
 };
 
-// The weight chunks reuse the coarse footprint's LDS (float) once the halo
-// tile is filled; the per-k-step A offsets (int [k-steps][4]) follow.
+// The weight chunks reuse the coarse footprint's LDS (the coarser level's
+// output as stored, T) once the halo tile is filled; the per-k-step A
+// offsets (int [k-steps][4]) follow.
 template <typename T, int NT, bool ONE>
 __host__ __device__ inline int conv_region_bytes(int kn) {
   using Cfg = ConvCfg<T, NT, ONE>;
   const int kn8 = (kn + 7) & ~7;
-  const int coarse = Cfg::CR * Cfg::CC * kn8 * (int)sizeof(float);
+  const int coarse = Cfg::CR * Cfg::CC * kn8 * (int)sizeof(T);
   const int wchunks = Cfg::NBUF * Cfg::NOUT * Cfg::BROW * (int)sizeof(T);
   return coarse > wchunks ? coarse : wchunks;
 }
@@ -259,7 +268,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   const int cs = cin8 + Cfg::CPAD;   // halo pixel stride (elements)
   T* tile = reinterpret_cast<T*>(smem);
   char* region = smem + (size_t)NPIX * cs * sizeof(T);
-  float* ctile = reinterpret_cast<float*>(region);
+  T* ctile = reinterpret_cast<T*>(region);
   T* sB = reinterpret_cast<T*>(region);   // after the fill
   int* s_aoff = reinterpret_cast<int*>(region + conv_region_bytes<T, NT, ONE>(d.kn));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -300,7 +309,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   const int Sn = S >> 1;
   const int cy0 = (oy >> 1) - 1, cx0 = (ox >> 1) - 1;
   if (d.kn > 0) {
-    // converted to float once here: each value then feeds four 2x2 blocks
+    // copied as stored (8 channels = one 16-byte piece in BF16)
     const int kg = kn8 >> 3;
     for (int e = tid; e < CR * CC * kg; e += 256) {
       const int cp = e / kg, g = e - cp * kg;
@@ -308,9 +317,7 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
       int yy = cy0 + cyi, xx = cx0 + cxi;
       yy = yy < 0 ? 0 : (yy > Sn - 1 ? Sn - 1 : yy);
       xx = xx < 0 ? 0 : (xx > Sn - 1 ? Sn - 1 : xx);
-      float v[8];
-      load8<T>(hnext + d.hn_off[k] + ((long long)yy * Sn + xx) * d.kpn + g * 8, v);
-      store8<float>(&ctile[cp * kn8 + g * 8], v);
+      copy8<T>(&ctile[cp * kn8 + g * 8], hnext + d.hn_off[k] + ((long long)yy * Sn + xx) * d.kpn + g * 8);
     }
     __syncthreads();
   }
@@ -365,12 +372,12 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
     }
     if (e < n_up) {
       const int bi = blk / 9, bj = blk - bi * 9;
-      const float* c00 = &ctile[(bi * CC + bj) * kn8 + g * 8];
+      const T* c00 = &ctile[(bi * CC + bj) * kn8 + g * 8];
       float a00[8], a01[8], a10[8], a11[8];
-      load8<float>(c00, a00);
-      load8<float>(c00 + kn8, a01);
-      load8<float>(c00 + CC * kn8, a10);
-      load8<float>(c00 + (CC + 1) * kn8, a11);
+      load8<T>(c00, a00);
+      load8<T>(c00 + kn8, a01);
+      load8<T>(c00 + CC * kn8, a10);
+      load8<T>(c00 + (CC + 1) * kn8, a11);
       // horizontal: left fine column (3/4 a_0 + 1/4 a_1), right (1/4, 3/4),
       // each pair from the difference: a_0 + d/4 and a_1 - d/4
       float tl[8], tr[8], bl[8], br[8];
