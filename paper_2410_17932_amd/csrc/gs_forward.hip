@@ -41,9 +41,12 @@
 namespace vrs {
 
 // ------------------------------------------------------------ preprocess
+// The SH degree is a template parameter, so the coefficient reads have no
+// branches between them and are all in flight together.
+template <int DEG>
 __global__ __launch_bounds__(256) void k_gs_preprocess(
     const float* __restrict__ mean, const float* __restrict__ cov,
-    const float* __restrict__ opacity, const float* __restrict__ sh, int deg, int64_t n,
+    const float* __restrict__ opacity, const float* __restrict__ sh, int64_t n,
     KViews views, GsOpt o, float4* __restrict__ rec, uint32_t* __restrict__ dkey,
     uint32_t* __restrict__ dval, uint32_t* __restrict__ nsup, uint64_t* __restrict__ psum,
     uint32_t* __restrict__ scan_clear, int64_t clear_words) {
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
 #pragma unroll
     for (int k = 0; k < 6; ++k) S6[k] = cov[k * n + i];
     const float op = opacity[i];
-    const int K = (deg + 1) * (deg + 1);
+    constexpr int K = (DEG + 1) * (DEG + 1);
     float coef[16][3];
 #pragma unroll
     for (int k = 0; k < 16; ++k)
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
       const float rn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
       dx *= rn; dy *= rn; dz *= rn;
       float Y[16];
-      sh_eval(deg, dx, dy, dz, Y);
+      sh_eval(DEG, dx, dy, dz, Y);
       float col[3];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
@@ -721,11 +724,14 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
   bool s1 = false;
   if (vn > 0) {
     trace_begin(tr, VRS_TRACE_GS_PREPROCESS, st);
-    hipLaunchKernelGGL(k_gs_preprocess, dim3((unsigned)nps), dim3(256), 0, st, mean, cov,
-                       opacity, sh, sh_degree, n, kv, o, at<float4>(ws, L.rec),
-                       at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
-                       at<uint32_t>(ws, L.nsup), at<uint64_t>(ws, L.psum),
-                       at<uint32_t>(ws, L.scan_tmp),
+    auto pre = sh_degree == 0   ? k_gs_preprocess<0>
+               : sh_degree == 1 ? k_gs_preprocess<1>
+               : sh_degree == 2 ? k_gs_preprocess<2>
+                                : k_gs_preprocess<3>;
+    hipLaunchKernelGGL(pre, dim3((unsigned)nps), dim3(256), 0, st, mean, cov, opacity, sh, n, kv,
+                       o, at<float4>(ws, L.rec), at<uint32_t>(ws, L.dkey0),
+                       at<uint32_t>(ws, L.dval0), at<uint32_t>(ws, L.nsup),
+                       at<uint64_t>(ws, L.psum), at<uint32_t>(ws, L.scan_tmp),
                        (int64_t)((L.sched - L.scan_tmp) / 4 + kSchedDone + 1));
     VRS_LAUNCH_CHECK();
     if (o.order == VRS_ORDER_PIXEL) {
