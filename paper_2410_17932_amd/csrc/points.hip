@@ -216,22 +216,24 @@ __device__ inline uint32_t pt_candidates(const KView& cv, int v, int n_crops,
 }
 
 // Footprint targets of a projected point over the candidate crops of view v
-// and the point's one or two pyramid layers; ox, oy: the crops' origins.
-__device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, const KCrops& crops,
-                                           uint32_t cand, int levels, const int* ox,
+// and the point's one or two pyramid layers; cview, csize, ox, oy: the
+// crops' views, sizes and origins (a workgroup's copy in LDS: a lane's crop
+// index is its own, so a read from the kernel arguments would be a vector
+// load and a wait per crop).
+__device__ inline uint32_t pt_targets_over(const PtGeom& g, int v, uint32_t cand, int levels,
+                                           const int* cview, const int* csize, const int* ox,
                                            const int* oy) {
   uint32_t cnt = 0;
   const float M = (float)(1 << levels);
   while (cand) {
     const int k = __builtin_ctz(cand);
     cand &= cand - 1;
-    const KCrop& c = crops.c[k];
-    if (c.view != v) continue;
-    const int cx0 = ox[k], cy0 = oy[k];
-    const float ax = g.px - (float)cx0, ay = g.py - (float)cy0, lim = (float)c.size + M;
+    if (cview[k] != v) continue;
+    const int cx0 = ox[k], cy0 = oy[k], size = csize[k];
+    const float ax = g.px - (float)cx0, ay = g.py - (float)cy0, lim = (float)size + M;
     if (!(ax >= -M && ax < lim && ay >= -M && ay < lim)) continue;
     for (int li = 0; li < (g.two ? 2 : 1); ++li) {
-      const int l = g.l0 + li, Sl = c.size >> l;
+      const int l = g.l0 + li, Sl = size >> l;
       float xl, yl;
       int ix, iy;
       if (pt_layer32(g, cx0, cy0, l, Sl, xl, yl, ix, iy)) cnt += pt_targets(ix, iy, Sl);
@@ -266,9 +268,10 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
   __shared__ uint64_t s_mask[NSLOT];
   __shared__ uint32_t s_pre[NSLOT], s_fsum[NSLOT], s_fpre[NSLOT];
   __shared__ uint32_t s_wsum[NW], s_wfsum[NW];
-  // crop origins read once (from the device placement table when there is
-  // one): a survivor's crop loop would otherwise wait on a load per crop
-  __shared__ int s_ox[VRS_MAX_CROPS], s_oy[VRS_MAX_CROPS];
+  // crop origins (from the device placement table when there is one),
+  // views and sizes read once: a survivor's crop loop would otherwise wait
+  // on loads per crop
+  __shared__ int s_ox[VRS_MAX_CROPS], s_oy[VRS_MAX_CROPS], s_cv[VRS_MAX_CROPS], s_cs[VRS_MAX_CROPS];
   extern __shared__ __align__(16) char s_dyn[];
   const int nv = views.n;
   float* s_zd = reinterpret_cast<float*>(s_dyn);                               // [round][view][tid]
@@ -281,6 +284,8 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
   if (tid < crops.n) {
     s_ox[tid] = crop_x0(crops, tid);
     s_oy[tid] = crop_y0(crops, tid);
+    s_cv[tid] = crops.c[tid].view;
+    s_cs[tid] = crops.c[tid].size;
   }
   __syncthreads();
   const int64_t part = blockIdx.x;
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(kSelBlock) void k_pt_select(
       if (ok[j] && !(cull[j] && pt_hidden(tz[j], tf[j], dp[j], a.cov_min, a.slack))) {
         PtGeom g;   // recomputed for the few points the cull keeps
         pt_geom32(cv, px[j], py[j], pz[j], pr[j], a.levels, g);
-        cnt = pt_targets_over(g, v, crops, cand[j], a.levels, s_ox, s_oy);
+        cnt = pt_targets_over(g, v, cand[j], a.levels, s_cv, s_cs, s_ox, s_oy);
       }
       s_zd[(j * nv + v) * kSelBlock + tid] = tz[j];
       s_cnt[(j * nv + v) * kSelBlock + tid] = cnt;
