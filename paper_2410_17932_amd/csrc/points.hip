@@ -652,13 +652,30 @@ __global__ __launch_bounds__(256) void k_pt_rank(const uint4* __restrict__ seg,
     const uint32_t start = poff[rec.w], n = poff[rec.w + 1] - start;
     uint32_t rank = 0;
     if (ids) {
+      // keys in groups of kRankBatch, every group's loads in flight before
+      // the comparisons; equal depth keys (rare) are settled after the
+      // group by the original indices, so no index load sits between the
+      // key loads and their use
       const uint32_t own_id = ids[rec.x];
-#pragma unroll 8
-      for (uint32_t j = 0; j < n; ++j) {
-        const uint64_t kj = key[2 * (int64_t)(start + j)];
-        bool before = (uint32_t)(kj >> 32) < rec.y;
-        if ((uint32_t)(kj >> 32) == rec.y && kj != own) before = ids[(uint32_t)kj] < own_id;
-        rank += before ? 1u : 0u;
+      constexpr int kRankBatch = 8;
+      for (uint32_t j0 = 0; j0 < n; j0 += kRankBatch) {
+        uint64_t kk[kRankBatch];
+#pragma unroll
+        for (int q = 0; q < kRankBatch; ++q)
+          kk[q] = j0 + q < n ? key[2 * (int64_t)(start + j0 + q)] : 0ull;
+        uint32_t ties = 0;
+#pragma unroll
+        for (int q = 0; q < kRankBatch; ++q) {
+          if (j0 + q >= n) continue;
+          const uint32_t kd = (uint32_t)(kk[q] >> 32);
+          rank += kd < rec.y ? 1u : 0u;
+          if (kd == rec.y && kk[q] != own) ties |= 1u << q;
+        }
+        while (ties) {
+          const int q = __builtin_ctz(ties);
+          ties &= ties - 1;
+          rank += ids[(uint32_t)kk[q]] < own_id ? 1u : 0u;
+        }
       }
     } else {
 #pragma unroll 8
