@@ -311,13 +311,32 @@ void k_dec_conv(DecLevel d, const float* __restrict__ pyr,
   if (d.kn > 0) {
     // copied as stored (8 channels = one 16-byte piece in BF16)
     const int kg = kn8 >> 3;
-    for (int e = tid; e < CR * CC * kg; e += 256) {
+    const int nco = CR * CC * kg;
+    auto csrc = [&](int e) {
       const int cp = e / kg, g = e - cp * kg;
       const int cyi = cp / CC, cxi = cp - cyi * CC;
       int yy = cy0 + cyi, xx = cx0 + cxi;
       yy = yy < 0 ? 0 : (yy > Sn - 1 ? Sn - 1 : yy);
       xx = xx < 0 ? 0 : (xx > Sn - 1 ? Sn - 1 : xx);
-      copy8<T>(&ctile[cp * kn8 + g * 8], hnext + d.hn_off[k] + ((long long)yy * Sn + xx) * d.kpn + g * 8);
+      return hnext + d.hn_off[k] + ((long long)yy * Sn + xx) * d.kpn + g * 8;
+    };
+    // two items per thread and round, both loads in flight before the stores
+    for (int e0 = tid; e0 < nco; e0 += 512) {
+      const int e1 = e0 + 256;
+      uint4 r0[sizeof(T) / 2], r1[sizeof(T) / 2];
+      const T* p0 = csrc(e0);
+#pragma unroll
+      for (int h = 0; h < (int)sizeof(T) / 2; ++h) r0[h] = reinterpret_cast<const uint4*>(p0)[h];
+      if (e1 < nco) {
+        const T* p1 = csrc(e1);
+#pragma unroll
+        for (int h = 0; h < (int)sizeof(T) / 2; ++h) r1[h] = reinterpret_cast<const uint4*>(p1)[h];
+      }
+#pragma unroll
+      for (int h = 0; h < (int)sizeof(T) / 2; ++h) reinterpret_cast<uint4*>(&ctile[e0 * 8])[h] = r0[h];
+      if (e1 < nco)
+#pragma unroll
+        for (int h = 0; h < (int)sizeof(T) / 2; ++h) reinterpret_cast<uint4*>(&ctile[e1 * 8])[h] = r1[h];
     }
     __syncthreads();
   }
