@@ -126,8 +126,9 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a, const float* P,
 // per four pixels.
 // Four pixels (v, y, x..x+3) of a row: their crop chain from P into out
 // (which may be P: every read comes before the writes).
+// cand: the crops that may cover the quad (bit k), walked in crop order.
 __device__ inline void comp_quad(const CompArgs& a, const float* P, const float* __restrict__ F,
-                                 float* out, int v, int y, int x, const int4* pl) {
+                                 float* out, int v, int y, int x, const int4* pl, uint32_t cand) {
   const long long plane = (long long)a.W * a.H;
   const long long base = (long long)v * 3 * plane + (long long)y * a.W + x;
   float4 c4[3] = {*reinterpret_cast<const float4*>(P + base),
@@ -138,7 +139,9 @@ __device__ inline void comp_quad(const CompArgs& a, const float* P, const float*
   for (int ch = 0; ch < 3; ++ch) {
     o[ch][0] = c4[ch].x; o[ch][1] = c4[ch].y; o[ch][2] = c4[ch].z; o[ch][3] = c4[ch].w;
   }
-  for (int k = 0; k < a.n_crops; ++k) {
+  while (cand) {
+    const int k = __builtin_ctz(cand);
+    cand &= cand - 1;
     if (a.view[k] != v) continue;
     const int S = a.S[k], ly = y - cy0(a, k, pl);
     if (ly < 0 || ly >= S || x + 3 < cx0(a, k, pl) || x >= cx0(a, k, pl) + S) continue;
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(256) void k_composite4(CompArgs a, const float* __r
     const int v = (int)(q / qplane);
     const long long pi = (q - v * qplane) * 4;
     const int y = (int)(pi / a.W), x = (int)(pi - (long long)y * a.W);
-    comp_quad(a, P, F, out, v, y, x, a.place);
+    comp_quad(a, P, F, out, v, y, x, a.place, a.n_crops >= 32 ? ~0u : (1u << a.n_crops) - 1u);
   }
 }
 
@@ -192,6 +195,7 @@ __global__ __launch_bounds__(256) void k_composite4_inplace(CompArgs a, float* i
   // the device placement table read once per workgroup: every pixel walks
   // the crop chain, which would otherwise wait on a load per crop
   __shared__ int4 s_pl[VRS_MAX_CROPS];
+  __shared__ uint32_t s_near;
   const int4* pl = nullptr;
   if (a.place) {   // uniform
     if (threadIdx.x < a.n_crops) s_pl[threadIdx.x] = a.place[threadIdx.x];
@@ -201,15 +205,32 @@ __global__ __launch_bounds__(256) void k_composite4_inplace(CompArgs a, float* i
   const int kc = blockIdx.y;
   const int S = a.S[kc], v = a.view[kc];
   const int gx0 = cx0(a, kc, pl) >> 2, ng = ((cx0(a, kc, pl) + S - 1) >> 2) - gx0 + 1;
+  // the crops whose square meets this crop's four-pixel groups: the only
+  // ones any of the workgroup's groups can lie under (crop kc among them)
+  if (threadIdx.x < 64) {
+    const int k = threadIdx.x;
+    bool near = false;
+    if (k < a.n_crops && a.view[k] == v) {
+      const int kx = cx0(a, k, pl), ky = cy0(a, k, pl), ks = a.S[k];
+      const int ky0 = cy0(a, kc, pl);
+      near = kx < (gx0 + ng) * 4 && kx + ks > gx0 * 4 && ky < ky0 + S && ky + ks > ky0;
+    }
+    const uint64_t m = __ballot(near);
+    if (threadIdx.x == 0) s_near = (uint32_t)m;
+  }
+  __syncthreads();
+  const uint32_t near = s_near;
   const long long i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= (long long)S * ng) return;
   const int ly = (int)(i / ng);
   const int y = cy0(a, kc, pl) + ly, x = (gx0 + (int)(i - (long long)ly * ng)) * 4;
-  for (int k = 0; k < kc; ++k)
+  for (uint32_t e = near & ((1u << kc) - 1u); e; e &= e - 1) {
+    const int k = __builtin_ctz(e);
     if (a.view[k] == v && y >= cy0(a, k, pl) && y < cy0(a, k, pl) + a.S[k] &&
         x + 3 >= cx0(a, k, pl) && x < cx0(a, k, pl) + a.S[k])
       return;   // an earlier crop's group
-  comp_quad(a, io, F, io, v, y, x, pl);
+  }
+  comp_quad(a, io, F, io, v, y, x, pl, near);
 }
 
 // Adjoint.  Per pixel the crop chain is replayed forward to recover the
