@@ -485,19 +485,23 @@ __global__ __launch_bounds__(kEmitBlock) void k_pt_emit(
     const uint32_t* __restrict__ chunk_first, const uint32_t* __restrict__ total_p,
     int64_t max_frags, uint32_t* __restrict__ fkey, uint64_t* __restrict__ fval,
     uint32_t* __restrict__ fdep, uint32_t* __restrict__ fslot, uint32_t* __restrict__ pcnt,
-    int32_t* status) {
+    const uint32_t* __restrict__ grid, int gx, int gy, int32_t* status) {
   __shared__ PixHash<kEmitPlaces> h;
   // staged fragments: layer pixel, weight bits, place (or tag), owning
   // survivor slot; per survivor slot its point index and depth key
   __shared__ uint32_t s_spx[kEmitFrags], s_sw[kEmitFrags], s_stag[kEmitFrags];
   __shared__ uint16_t s_sown[kEmitFrags];
   __shared__ uint32_t s_pi[kEmitFrags + 1], s_dz[kEmitFrags + 1];
-  __shared__ int s_cx0[VRS_MAX_CROPS], s_cy0[VRS_MAX_CROPS];
-  // crop origins read once (from the device placement table when there is
-  // one): the crop loop below would otherwise wait on a load per crop
+  __shared__ int s_cx0[VRS_MAX_CROPS], s_cy0[VRS_MAX_CROPS], s_cs[VRS_MAX_CROPS],
+      s_pb[VRS_MAX_CROPS];
+  // crop origins (from the device placement table when there is one), sizes
+  // and pyramid bases read once: the crop loop below would otherwise wait on
+  // loads per crop
   if (threadIdx.x < crops.n) {
     s_cx0[threadIdx.x] = crop_x0(crops, threadIdx.x);
     s_cy0[threadIdx.x] = crop_y0(crops, threadIdx.x);
+    s_cs[threadIdx.x] = crops.c[threadIdx.x].size;
+    s_pb[threadIdx.x] = crops.c[threadIdx.x].pix_base;
   }
   __syncthreads();
   const int64_t live = *live_p;
@@ -533,15 +537,17 @@ __global__ __launch_bounds__(kEmitBlock) void k_pt_emit(
       FF ux, uy;   // the weights' position, compensated
       pt_plane_ff(cv, x, y, z, ux, uy);
       int64_t o = lo;
-      for (int k = 0; k < crops.n && o < f1; ++k) {
-        const KCrop& c = crops.c[k];
-        if (c.view != v) continue;
-        const int cx0 = s_cx0[k], cy0 = s_cy0[k];
-        int lb = c.pix_base;
+      // the crops the selection counted this point's fragments over (its
+      // crop-grid candidates: the other crops give it none), in crop order
+      for (uint32_t cand = pt_candidates(cv, v, crops.n, grid, gx, gy, x, y, z); cand && o < f1;
+           cand &= cand - 1) {
+        const int k = __builtin_ctz(cand);
+        const int cx0 = s_cx0[k], cy0 = s_cy0[k], size = s_cs[k];
+        int lb = s_pb[k];
         int l = 0;
-        for (; l < g.l0; ++l) lb += (c.size >> l) * (c.size >> l);
+        for (; l < g.l0; ++l) lb += (size >> l) * (size >> l);
         for (int li = 0; li < (g.two ? 2 : 1); ++li, ++l) {
-          const int Sl = c.size >> l;
+          const int Sl = size >> l;
           const float wl = g.two ? (li == 0 ? 1.0f - f : f) : 1.0f;
           float xl, yl;
           int ix, iy;
@@ -854,7 +860,8 @@ vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* fea
   hipLaunchKernelGGL(k_pt_emit, dim3((unsigned)emit_blocks), dim3(kEmitBlock), 0, st, pos, radius,
                      np, kv, kc, a, at<uint4>(ws, L.surv), live, at<uint32_t>(ws, L.chunk_first),
                      frag_count, max_frags, at<uint32_t>(ws, L.fkey0), at<uint64_t>(ws, L.fval0),
-                     at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot), pcnt, dev_status);
+                     at<uint32_t>(ws, L.fdep), at<uint32_t>(ws, L.fslot), pcnt, grid, L.gx, L.gy,
+                     dev_status);
   VRS_LAUNCH_CHECK();
   // per-pixel segments, then each fragment to its place in blend order
   VRS_HIP_CHECK(exclusive_scan_u32(pcnt, nullptr, poff, poff + L.pix_total, nullptr, L.pix_total,
