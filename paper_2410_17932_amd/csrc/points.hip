@@ -151,8 +151,10 @@ struct PtArgs {
 // listed in every cell that meets [x0 - 2^levels - 2, x0 + size + 2^levels + 2)
 // (likewise y); border cells extend to infinity so that lookups of pixels
 // outside the view clamp to them.
+// ox, oy: the crops' origins (a workgroup's copy in LDS).
 __device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx, int gy,
-                                        int64_t idx, uint32_t* __restrict__ grid) {
+                                        int64_t idx, const int* ox, const int* oy,
+                                        uint32_t* __restrict__ grid) {
   const int v = (int)(idx / ((int64_t)gx * gy));
   const int cell = (int)(idx - (int64_t)v * gx * gy);
   const int cy = cell / gx, cx = cell - cy * gx;
@@ -165,7 +167,7 @@ __device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx,
   for (int k = 0; k < crops.n; ++k) {
     const KCrop& c = crops.c[k];
     if (c.view != v) continue;
-    const int cx0 = crop_x0(crops, k), cy0 = crop_y0(crops, k);
+    const int cx0 = ox[k], cy0 = oy[k];
     const int64_t x0 = (int64_t)cx0 - M, x1 = (int64_t)cx0 + c.size + M;
     const int64_t y0 = (int64_t)cy0 - M, y1 = (int64_t)cy0 + c.size + M;
     if (x0 < hi_x && x1 > lo_x && y0 < hi_y && y1 > lo_y) mask |= 1u << k;
@@ -181,14 +183,25 @@ __global__ void k_pt_prep(uint32_t* __restrict__ pcnt, int64_t pix_total,
                           int64_t scan_words, KCrops crops, int nv, int levels, int gx, int gy,
                           uint32_t* __restrict__ grid) {
   const int64_t cells = (int64_t)nv * gx * gy;
-  const int64_t n = std::max(std::max(pix_total, scan_words), std::max<int64_t>(cells, 1));
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (i < pix_total) pcnt[i] = 0u;
-    if (i < scan_words) scan_tmp[i] = 0u;
-    if (i == 0) *ctr = 0ull;
-    if (i < cells) pt_cropgrid_cell(crops, levels, gx, gy, i, grid);
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // crop origins read once per workgroup (from the device placement table
+  // when there is one): a cell's crop loop would otherwise wait on each
+  __shared__ int s_ox[VRS_MAX_CROPS], s_oy[VRS_MAX_CROPS];
+  if (threadIdx.x < crops.n) {
+    s_ox[threadIdx.x] = crop_x0(crops, threadIdx.x);
+    s_oy[threadIdx.x] = crop_y0(crops, threadIdx.x);
   }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // the counters in 16-byte stores (the workspace's sub-buffers are 256-byte
+  // aligned), the tail word by word
+  uint4* p4 = reinterpret_cast<uint4*>(pcnt);
+  for (int64_t q = gt; q < pix_total / 4; q += stride) p4[q] = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t i = (pix_total & ~int64_t(3)) + gt; i < pix_total; i += stride) pcnt[i] = 0u;
+  for (int64_t i = gt; i < scan_words; i += stride) scan_tmp[i] = 0u;
+  if (gt == 0) *ctr = 0ull;
+  for (int64_t i = gt; i < cells; i += stride)
+    pt_cropgrid_cell(crops, levels, gx, gy, i, s_ox, s_oy, grid);
 }
 
 // Candidate crops of one point in view v: the crop-lookup grid cell of a
