@@ -47,7 +47,8 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_gs_preprocess(
     const float* __restrict__ mean, const float* __restrict__ cov,
     const float* __restrict__ opacity, const float* __restrict__ sh, int64_t n,
-    KViews views, GsOpt o, float4* __restrict__ rec, uint32_t* __restrict__ dkey,
+    KViews views, GsOpt o, float4* __restrict__ rec, uint2* __restrict__ rect,
+    uint32_t* __restrict__ dkey,
     uint32_t* __restrict__ dval, uint32_t* __restrict__ nsup, uint64_t* __restrict__ psum,
     uint32_t* __restrict__ scan_clear, int64_t clear_words) {
   __shared__ uint64_t s_p[4];
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
         rec[3 * e + 0] = make_float4(0, 0, 0, 0);
         rec[3 * e + 1] = make_float4(0, 0, 0, 0);
         rec[3 * e + 2] = make_float4(0, 0, __uint_as_float(0xffffffffu), 0);
+        rect[e] = make_uint2(0xffffffffu, 0u);
         continue;
       }
       const float inv = 1.0f / g.det;
@@ -109,6 +111,7 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
       rec[3 * e + 1] = make_float4(C, op, col[0], col[1]);
       rec[3 * e + 2] = make_float4(col[2], g.t[2], __uint_as_float(pack_xy(g.x0, g.y0)),
                                    __uint_as_float(pack_xy(g.x1, g.y1)));
+      rect[e] = make_uint2(pack_xy(g.x0, g.y0), pack_xy(g.x1, g.y1));
     }
   }
 #pragma unroll
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
 constexpr int kEmitBlock = 256;
 __global__ __launch_bounds__(kEmitBlock) void k_gs_emit_super(
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ sorted_e,
-    const float4* __restrict__ rec, const uint32_t* __restrict__ total_p, int64_t vn,
+    const uint2* __restrict__ rect, const uint32_t* __restrict__ total_p, int64_t vn,
     int64_t n, int64_t max_pairs, int tile, int64_t sxn, int64_t spv,
     uint32_t* __restrict__ skey, uint64_t* __restrict__ sval, int64_t st_total,
     uint2* __restrict__ srange, int32_t* status) {
@@ -153,8 +156,10 @@ __global__ __launch_bounds__(kEmitBlock) void k_gs_emit_super(
     s_off[tid] = offs[j];
     const uint32_t e = sorted_e[j];
     const int64_t v = e / n, gi = e - v * n;
-    const float4 r2 = rec[3 * (int64_t)e + 2];
-    const uint32_t lo_xy = __float_as_uint(r2.z), hi_xy = __float_as_uint(r2.w);
+    // the entry's rectangle from its own 8-byte array: a gather from the
+    // 48-byte records would fetch a record line for 8 bytes
+    const uint2 r = rect[e];
+    const uint32_t lo_xy = r.x, hi_xy = r.y;
     const int tx0 = (int)(lo_xy & 0xffffu) / tile, ty0 = (int)(lo_xy >> 16) / tile;
     const int tx1 = (int)(hi_xy & 0xffffu) / tile, ty1 = (int)(hi_xy >> 16) / tile;
     s_base[tid] = (uint32_t)(v * spv + (int64_t)(ty0 / kSuper) * sxn + tx0 / kSuper);
@@ -729,7 +734,7 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
                : sh_degree == 2 ? k_gs_preprocess<2>
                                 : k_gs_preprocess<3>;
     hipLaunchKernelGGL(pre, dim3((unsigned)nps), dim3(256), 0, st, mean, cov, opacity, sh, n, kv,
-                       o, at<float4>(ws, L.rec), at<uint32_t>(ws, L.dkey0),
+                       o, at<float4>(ws, L.rec), at<uint2>(ws, L.rect), at<uint32_t>(ws, L.dkey0),
                        at<uint32_t>(ws, L.dval0), at<uint32_t>(ws, L.nsup),
                        at<uint64_t>(ws, L.psum), at<uint32_t>(ws, L.scan_tmp),
                        (int64_t)((L.sched - L.scan_tmp) / 4 + kSchedDone + 1));
@@ -753,7 +758,7 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
     trace_end(tr, VRS_TRACE_GS_DEPTH_SORT, st);
     trace_begin(tr, VRS_TRACE_GS_EMIT, st);
     hipLaunchKernelGGL(k_gs_emit_super, dim3(div_up(vn, kEmitBlock)), dim3(kEmitBlock), 0, st,
-                       at<uint32_t>(ws, L.soffs), sorted_e, at<float4>(ws, L.rec), super_count,
+                       at<uint32_t>(ws, L.soffs), sorted_e, at<uint2>(ws, L.rect), super_count,
                        vn, n, max_pairs, o.tile, L.sxn, L.spv, at<uint32_t>(ws, L.skey0),
                        at<uint64_t>(ws, L.sval0), L.st_total, at<uint2>(ws, L.srange),
                        dev_status);

@@ -14,7 +14,7 @@ constexpr int kSuper = 8;
 constexpr int kSchedHist = 0, kSchedDone = 256, kSchedCursor = 320, kSchedWords = 576;
 
 struct RenderWs {
-  size_t rec, dkey0, dval0, dkey1, dval1, nsup, nsorted, soffs, psum, pair_count, super_count,
+  size_t rec, rect, dkey0, dval0, dkey1, dval1, nsup, nsorted, soffs, psum, pair_count, super_count,
       skey0, sval0, skey1, sval1,   // (super-tile, Gaussian) pairs
       srange, ubase, nunits,        // per super-tile run and first work unit
       ucnt, tcnt, toff,             // per (unit, tile) and per tile counts, tile offsets
@@ -69,6 +69,7 @@ inline bool render_layout(int64_t n, int nv, const vrs_view* views, int tile, in
   const int64_t mp = std::max<int64_t>(max_pairs, 1);
   Carver c;
   L->rec = c.take((size_t)vn * 48);
+  L->rect = c.take((size_t)vn * 8);   // per (view, Gaussian): its rectangle alone (record word 2.zw)
   L->dkey0 = c.take(vn * 4);
   L->dval0 = c.take(vn * 4);
   L->dkey1 = c.take(vn * 4);
