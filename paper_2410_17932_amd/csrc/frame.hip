@@ -119,18 +119,15 @@ extern "C" vrs_status vrs_render_frame(const vrs_plan* plan, const vrs_scene* sc
                                   d.max_pairs, b->status_render, stream,
                                   (flags & VRS_FRAME_STATS) ? vrs::kRenderStats : 0, tr);
   if (r != VRS_OK || !fovea) return r;
-  // the gaze is read here, after the periphery
-  const vrs_crop_place* place = nullptr;
-  if (gaze) {
-    r = vrs_place_crops(gaze, d.views, d.n_views, d.crops, d.n_crops, b->place, stream);
-    if (r != VRS_OK) return r;
-    place = b->place;
-  }
+  // the gaze is read here, after the periphery: the splat's set-up launch
+  // places the crops (as vrs_place_crops would) and writes b->place, which
+  // every later stage reads
+  const vrs_crop_place* place = gaze ? b->place : nullptr;
   r = vrs::splat_impl(scene->pos, scene->radius, scene->feat, scene->point_opacity, d.n_points,
                       d.point_channels, d.levels, d.views, d.n_views, d.crops, d.n_crops, place,
                       d.depth_cull ? b->depth : nullptr, d.depth_cull ? b->t_final : nullptr,
                       d.cov_min, d.slack, scene->point_ids, b->pyramid, b->ws_splat,
-                      plan->ws[VRS_WS_SPLAT], d.max_frags, b->status_splat, stream, tr);
+                      plan->ws[VRS_WS_SPLAT], d.max_frags, b->status_splat, stream, tr, gaze);
   if (r != VRS_OK) return r;
   r = vrs::decode_impl_entry(b->pyramid, d.levels, b->rgb, d.views, d.n_views, d.crops,
                              d.n_crops, place, scene->decoder_weights, &d.decoder, b->fovea_rgb,

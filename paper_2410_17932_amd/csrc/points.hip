@@ -175,21 +175,53 @@ __device__ inline void pt_cropgrid_cell(const KCrops& crops, int levels, int gx,
   grid[idx] = mask;
 }
 
+// Crop k placed on its gaze point g: the crop of size S centred on the gaze,
+// x0 = clamp(rint(g.x - S/2), 0, W - S) (ties to even), y0 likewise; the
+// gaze itself in the last two words.
+__device__ inline int4 place_crop(const KCrops& kc, int k, float2 g) {
+  const float h = 0.5f * (float)kc.c[k].size;
+  const float fx = rintf(g.x - h), fy = rintf(g.y - h);
+  // clamp in float first: a non-finite or huge gaze gives a valid origin
+  const float cx = fminf(fmaxf(fx, 0.0f), (float)kc.c[k].mx0);
+  const float cy = fminf(fmaxf(fy, 0.0f), (float)kc.c[k].my0);
+  return make_int4(cx == cx ? (int)cx : 0, cy == cy ? (int)cy : 0, __float_as_int(g.x),
+                   __float_as_int(g.y));
+}
+
+// Crop origins from gaze points on the device (Sec. 4 "Inference": the eye
+// tracker is read after the periphery is rendered), one thread per crop.
+__global__ void k_place_crops(const float2* __restrict__ gaze, KCrops kc, int4* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= kc.n) return;
+  out[k] = place_crop(kc, k, gaze[k]);
+}
+
 // Per-call set-up in one launch: the per-pixel fragment counters, the
 // survivor and fragment counts and the pixel scan's temporary zeroed, and
 // the crop-lookup grid.
+// With gaze, the crops are placed here as well (what the placement entry
+// point computes): every workgroup places them for its own cells, the first
+// one writes the placement table that the later kernels read.
 __global__ void k_pt_prep(uint32_t* __restrict__ pcnt, int64_t pix_total,
                           uint64_t* __restrict__ ctr, uint32_t* __restrict__ scan_tmp,
                           int64_t scan_words, KCrops crops, int nv, int levels, int gx, int gy,
-                          uint32_t* __restrict__ grid) {
+                          uint32_t* __restrict__ grid, const float2* __restrict__ gaze,
+                          int4* __restrict__ place_out) {
   const int64_t cells = (int64_t)nv * gx * gy;
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   // crop origins read once per workgroup (from the device placement table
   // when there is one): a cell's crop loop would otherwise wait on each
   __shared__ int s_ox[VRS_MAX_CROPS], s_oy[VRS_MAX_CROPS];
   if (threadIdx.x < crops.n) {
-    s_ox[threadIdx.x] = crop_x0(crops, threadIdx.x);
-    s_oy[threadIdx.x] = crop_y0(crops, threadIdx.x);
+    if (gaze) {
+      const int4 pl = place_crop(crops, threadIdx.x, gaze[threadIdx.x]);
+      s_ox[threadIdx.x] = pl.x;
+      s_oy[threadIdx.x] = pl.y;
+      if (blockIdx.x == 0) place_out[threadIdx.x] = pl;
+    } else {
+      s_ox[threadIdx.x] = crop_x0(crops, threadIdx.x);
+      s_oy[threadIdx.x] = crop_y0(crops, threadIdx.x);
+    }
   }
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -809,10 +841,11 @@ vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* fea
                       const vrs_crop_place* place, const float* depth, const float* t_final,
                       float cov_min, float slack, const uint32_t* point_ids, float* pyramid,
                       void* ws, size_t ws_bytes, int64_t max_frags, int32_t* dev_status,
-                      void* stream, const Trace* tr) {
+                      void* stream, const Trace* tr, const float* gaze) {
   KViews kv;
   KCrops kc;
   SplatWs L;
+  if (gaze && !place) return VRS_EINVAL;
   if (channels != 4) return channels > 0 ? VRS_EUNSUPPORTED : VRS_EINVAL;
   if (!check_views(views, n_views, &kv) || !make_crops(crops, n_crops, levels, kv, &kc, place))
     return VRS_EINVAL;
@@ -834,6 +867,12 @@ vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* fea
   uint32_t* frag_count = at<uint32_t>(ws, L.frag_count);
   trace_begin(tr, VRS_TRACE_SPLAT, st);
   if (vn == 0 || n_crops == 0) {
+    if (gaze && n_crops > 0) {   // the crops are still placed for the later stages
+      hipLaunchKernelGGL(k_place_crops, dim3(1), dim3(64), 0, st,
+                         reinterpret_cast<const float2*>(gaze), kc,
+                         reinterpret_cast<int4*>(const_cast<vrs_crop_place*>(place)));
+      VRS_LAUNCH_CHECK();
+    }
     if (L.pix_total > 0) {
       const int blocks = (int)std::min<int64_t>(4096, div_up(L.pix_total, 256));
       hipLaunchKernelGGL(k_zero4, dim3(blocks), dim3(256), 0, st,
@@ -855,7 +894,8 @@ vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* fea
     hipLaunchKernelGGL(k_pt_prep, dim3((unsigned)std::min<int64_t>(4096, div_up(most, 256))),
                        dim3(256), 0, st, at<uint32_t>(ws, L.pcnt), L.pix_total,
                        at<uint64_t>(ws, L.ctr), at<uint32_t>(ws, L.scan_tmp), scan_words, kc,
-                       n_views, levels, L.gx, L.gy, grid);
+                       n_views, levels, L.gx, L.gy, grid, reinterpret_cast<const float2*>(gaze),
+                       reinterpret_cast<int4*>(const_cast<vrs_crop_place*>(place)));
     VRS_LAUNCH_CHECK();
   }
   // survivors with their fragment offsets (compaction order), then emission
@@ -1080,26 +1120,6 @@ extern "C" vrs_status vrs_splat_points_backward(const float* pos, const float* r
 }
 
 // ------------------------------------------------------- crop placement
-namespace vrs {
-
-// Crop origins from gaze points on the device (Sec. 4 "Inference": the eye
-// tracker is read after the periphery is rendered): the crop of size S
-// centred on the gaze, x0 = clamp(rint(gaze_x - S/2), 0, W - S) (ties to
-// even), y0 likewise.
-__global__ void k_place_crops(const float2* __restrict__ gaze, KCrops kc, int4* __restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= kc.n) return;
-  const float2 g = gaze[k];
-  const float h = 0.5f * (float)kc.c[k].size;
-  const float fx = rintf(g.x - h), fy = rintf(g.y - h);
-  // clamp in float first: a non-finite or huge gaze gives a valid origin
-  const float cx = fminf(fmaxf(fx, 0.0f), (float)kc.c[k].mx0);
-  const float cy = fminf(fmaxf(fy, 0.0f), (float)kc.c[k].my0);
-  out[k] = make_int4(cx == cx ? (int)cx : 0, cy == cy ? (int)cy : 0, __float_as_int(g.x),
-                     __float_as_int(g.y));
-}
-
-}  // namespace vrs
 
 extern "C" vrs_status vrs_place_crops(const float* gaze, const vrs_view* views, int n_views,
                                       const vrs_crop* crops, int n_crops, vrs_crop_place* place,

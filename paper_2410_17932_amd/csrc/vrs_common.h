@@ -159,7 +159,7 @@ vrs_status splat_impl(const float* pos, const float* radius, const uint16_t* fea
                       const vrs_crop_place* place, const float* depth, const float* t_final,
                       float cov_min, float slack, const uint32_t* point_ids, float* pyramid,
                       void* ws, size_t ws_bytes, int64_t max_frags, int32_t* dev_status,
-                      void* stream, const Trace* tr);
+                      void* stream, const Trace* tr, const float* gaze = nullptr);
 vrs_status decode_impl_entry(const float* pyramid, int levels, const float* rgb_periphery,
                              const vrs_view* views, int n_views, const vrs_crop* crops,
                              int n_crops, const vrs_crop_place* place, const float* weights,
