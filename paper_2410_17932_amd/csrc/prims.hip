@@ -36,11 +36,11 @@ __global__ void k_fill(uint32_t* p, uint32_t v, int64_t n) {
 }
 
 // ------------------------------------------------------------------ scan
-// Partition shapes: direct reads take 16K-item partitions (1024 threads x
-// 16 items: fewer partitions, so fewer ticket atomics and look-back rounds);
-// gathered reads (in[idx[i]]) take 4K-item partitions (512 x 8), where more
-// workgroups keep more gathers in flight.  Temporaries are sized for the
-// smaller one.
+// Partition shapes: direct reads of 2M items or more take 16K-item
+// partitions (1024 threads x 16 items: fewer partitions, so fewer ticket
+// atomics and look-back rounds); gathered reads (in[idx[i]]) and smaller
+// scans take 4K-item partitions (512 x 8), where more workgroups keep more
+// reads in flight.  Temporaries are sized for the smaller one.
 constexpr int kScanTileMin = 4096;
 
 // Clears the partition counter, the look-back flags the scan will use and
@@ -463,14 +463,17 @@ static hipError_t scan_impl(const uint32_t* in, const uint32_t* idx, uint32_t* o
   }
   uint32_t* counter = static_cast<uint32_t*>(tmp);
   uint64_t* flags = reinterpret_cast<uint64_t*>(static_cast<char*>(tmp) + 256);
-  const int64_t tile = idx ? 512 * 8 : 1024 * 16;
+  // 4K-item partitions for gathers and below 2M items (more workgroups in
+  // flight: a 1M-item scan has only 62 partitions of 16K), 16K above
+  const bool small = idx || n_max < (int64_t(2) << 20);
+  const int64_t tile = small ? 512 * 8 : 1024 * 16;
   const int64_t parts = (n_max + tile - 1) / tile;
   if (!cleared) {
     const int cb = (int)std::min<int64_t>(1024, (parts + 255) / 256 + 1);
     hipLaunchKernelGGL(k_scan_clear, dim3(cb), dim3(256), 0, st, counter, flags, total, n_dev,
                        n_max);
   }
-  if (idx)
+  if (small)
     hipLaunchKernelGGL((k_scan<512, 8>), dim3((unsigned)parts), dim3(512), 0, st, in, idx, out,
                        total, n_dev, n_max, counter, flags, status);
   else
