@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
     const float* __restrict__ opacity, const float* __restrict__ sh, int64_t n,
     KViews views, GsOpt o, float4* __restrict__ rec, uint2* __restrict__ rect,
     uint32_t* __restrict__ dkey,
-    uint32_t* __restrict__ dval, uint32_t* __restrict__ nsup, uint64_t* __restrict__ psum,
+    uint32_t* __restrict__ nsup, uint64_t* __restrict__ psum,
     uint32_t* __restrict__ scan_clear, int64_t clear_words) {
   __shared__ uint64_t s_p[4];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -74,7 +74,6 @@ __global__ __launch_bounds__(256) void k_gs_preprocess(
       const int64_t e = v * n + i;
       Geom g;
       const bool ok = gs_geom32(cv, mx, my, mz, S6, o.lowpass, o.extent, g);
-      dval[e] = (uint32_t)e;
       if (!ok) {
         dkey[e] = 0xffffffffu;
         nsup[e] = 0;
@@ -735,7 +734,7 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
                                 : k_gs_preprocess<3>;
     hipLaunchKernelGGL(pre, dim3((unsigned)nps), dim3(256), 0, st, mean, cov, opacity, sh, n, kv,
                        o, at<float4>(ws, L.rec), at<uint2>(ws, L.rect), at<uint32_t>(ws, L.dkey0),
-                       at<uint32_t>(ws, L.dval0), at<uint32_t>(ws, L.nsup),
+                       at<uint32_t>(ws, L.nsup),
                        at<uint64_t>(ws, L.psum), at<uint32_t>(ws, L.scan_tmp),
                        (int64_t)((L.sched - L.scan_tmp) / 4 + kSchedDone + 1));
     VRS_LAUNCH_CHECK();
@@ -750,7 +749,7 @@ vrs_status render_impl(const float* mean, const float* cov, const float* opacity
     VRS_HIP_CHECK(radix_sort_u32(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0),
                                  at<uint32_t>(ws, L.dkey1), at<uint32_t>(ws, L.dval1), nullptr, vn,
                                  32, L.radix, at<void>(ws, L.sort_tmp), dev_status, st, &d1,
-                                 at<uint32_t>(ws, L.nsup), at<uint32_t>(ws, L.nsorted)));
+                                 at<uint32_t>(ws, L.nsup), at<uint32_t>(ws, L.nsorted), true));
     const uint32_t* sorted_e = at<uint32_t>(ws, d1 ? L.dval1 : L.dval0);
     VRS_HIP_CHECK(exclusive_scan_u32(at<uint32_t>(ws, L.nsorted), nullptr,
                                      at<uint32_t>(ws, L.soffs), super_count, nullptr, vn,

@@ -299,7 +299,8 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
       const int64_t i = wbase + j * 64 + lane;
       const bool ok = i < n;
       key[j] = ok ? kin[i] : 0xffffffffu;
-      val[j] = ok ? vin[i] : V(0);
+      // no input values: each item's value is its input position
+      val[j] = ok ? (vin ? vin[i] : (V)i) : V(0);
     }
     // stable rank within the wave: match lanes with equal digit by ballots
     volatile uint32_t* wh = s_wh[wave];
@@ -379,7 +380,8 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(
 template <typename V, int R>
 hipError_t radix_sort_r(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t* n_dev,
                         int64_t n_max, int key_bits, void* tmp, hipStream_t st,
-                        bool* result_in_1, const uint32_t* gather_src, uint32_t* gather_dst) {
+                        bool* result_in_1, const uint32_t* gather_src, uint32_t* gather_dst,
+                        bool iota) {
   constexpr int NB = 1 << R;
   const int passes = key_bits <= 0 ? 0 : (key_bits + R - 1) / R;
   *result_in_1 = (passes & 1) != 0;
@@ -397,7 +399,8 @@ hipError_t radix_sort_r(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t
                        totals);
     const bool last = p == passes - 1;
     hipLaunchKernelGGL((k_sort_scatter<V, R>), dim3(grid), dim3(kSortBlock), 0, st,
-                       kb[p & 1], vb[p & 1], kb[(p + 1) & 1], vb[(p + 1) & 1], n_dev, n_max,
+                       kb[p & 1], (p == 0 && iota) ? nullptr : vb[p & 1], kb[(p + 1) & 1],
+                       vb[(p + 1) & 1], n_dev, n_max,
                        R * p, parts, counts, totals, last ? gather_src : nullptr,
                        last ? gather_dst : nullptr);
   }
@@ -408,21 +411,21 @@ template <typename V>
 hipError_t radix_sort_impl(uint32_t* k0, V* v0, uint32_t* k1, V* v1, const uint32_t* n_dev,
                            int64_t n_max, int key_bits, int radix_bits, void* tmp,
                            int32_t* status, hipStream_t st, bool* result_in_1,
-                           const uint32_t* gather_src, uint32_t* gather_dst) {
+                           const uint32_t* gather_src, uint32_t* gather_dst, bool iota) {
   (void)status;   // nothing in the sort waits on another workgroup
   switch (radix_bits) {
     case 4:
       return radix_sort_r<V, 4>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
-                                gather_src, gather_dst);
+                                gather_src, gather_dst, iota);
     case 6:
       return radix_sort_r<V, 6>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
-                                gather_src, gather_dst);
+                                gather_src, gather_dst, iota);
     case 11:
       return radix_sort_r<V, 11>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
-                                 gather_src, gather_dst);
+                                 gather_src, gather_dst, iota);
     default:
       return radix_sort_r<V, 8>(k0, v0, k1, v1, n_dev, n_max, key_bits, tmp, st, result_in_1,
-                                gather_src, gather_dst);
+                                gather_src, gather_dst, iota);
   }
 }
 
@@ -506,16 +509,16 @@ size_t sort_tmp_bytes(int64_t n_max, int key_bits, int radix_bits) {
 hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, int radix_bits,
                           void* tmp, int32_t* status, hipStream_t st, bool* result_in_1,
-                          const uint32_t* gather_src, uint32_t* gather_dst) {
+                          const uint32_t* gather_src, uint32_t* gather_dst, bool iota) {
   return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, radix_bits, tmp,
-                                   status, st, result_in_1, gather_src, gather_dst);
+                                   status, st, result_in_1, gather_src, gather_dst, iota);
 }
 
 hipError_t radix_sort_u64(uint32_t* k0, uint64_t* v0, uint32_t* k1, uint64_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, int radix_bits,
                           void* tmp, int32_t* status, hipStream_t st, bool* result_in_1) {
   return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n_dev, n_max, key_bits, radix_bits, tmp,
-                                   status, st, result_in_1, nullptr, nullptr);
+                                   status, st, result_in_1, nullptr, nullptr, false);
 }
 
 }  // namespace vrs

@@ -117,11 +117,14 @@ bool radix_bits_ok(int radix_bits);
 size_t sort_tmp_bytes(int64_t n_max, int key_bits, int radix_bits);
 // gather_src/gather_dst (both or neither): the last pass also writes
 // gather_dst[i] = gather_src[value i] in sorted order (a per-value word
-// carried into the sorted order without a pass of its own).
+// carried into the sorted order without a pass of its own).  iota: the
+// values are the items' input positions, not read from v0 (v0 is still the
+// buffer of the even passes' output).
 hipError_t radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, int radix_bits,
                           void* tmp, int32_t* status, hipStream_t st, bool* result_in_1,
-                          const uint32_t* gather_src = nullptr, uint32_t* gather_dst = nullptr);
+                          const uint32_t* gather_src = nullptr, uint32_t* gather_dst = nullptr,
+                          bool iota = false);
 hipError_t radix_sort_u64(uint32_t* k0, uint64_t* v0, uint32_t* k1, uint64_t* v1,
                           const uint32_t* n_dev, int64_t n_max, int key_bits, int radix_bits,
                           void* tmp, int32_t* status, hipStream_t st, bool* result_in_1);
